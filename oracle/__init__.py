@@ -1,0 +1,175 @@
+"""CPU oracle for the MAPA allocation query -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The GPU product path never loads it and
+shares no code with it.
+
+Two independent implementations live here:
+
+* ``mapa_oracle.c`` (built to ``liboracle.so`` with gcc): plain recursive brute
+  force over every injective tuple in lexicographic order, Eq. 1 and Eq. 3
+  evaluated literally, Alg. 1's strict-improvement scan.
+* ``brute.py``: the same definition with ``itertools.permutations``; slow,
+  used to cross-check the C file exhaustively on tiny graphs.
+
+``run_batch_semantics`` adds the batch-level state update (Sec. 3.6): each
+query is evaluated against the busy masks at batch entry; afterwards, in array
+order, the first query of a server that asked to commit marks its chosen
+vertices busy, and any later committing query of the same server is refused
+(status CONFLICT).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+SRC_PATH = os.path.join(HERE, "mapa_oracle.c")
+
+RING, A2A, TREE = 0, 1, 2
+MODE_ALL, MODE_LINKED = 0, 1
+OK, NOFIT, CONFLICT = 0, 1, 2
+EINVAL, EUNSUP = -1, -2
+
+
+class OrResult(ctypes.Structure):
+    _fields_ = [
+        ("count", ctypes.c_int64),
+        ("status", ctypes.c_int32),
+        ("key", ctypes.c_int32),
+        ("agg", ctypes.c_int32),
+        ("pres", ctypes.c_int32),
+        ("vertex_mask", ctypes.c_uint32),
+        ("mapping", ctypes.c_uint8 * 8),
+    ]
+
+
+RESULT_DTYPE = np.dtype([
+    ("count", np.int64), ("status", np.int32), ("key", np.int32), ("agg", np.int32),
+    ("pres", np.int32), ("vertex_mask", np.uint32), ("mapping", np.uint8, 8),
+], align=True)
+
+
+def build(force: bool = False) -> str:
+    """Compile the C oracle with gcc (plain -O2, no vectorisation pragmas)."""
+    if force or not os.path.exists(LIB_PATH) or \
+            os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC_PATH):
+        tmp = LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-pthread",
+                               "-o", tmp, SRC_PATH])
+        os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = ctypes.CDLL(LIB_PATH)
+        L.or_query.restype = ctypes.c_int
+        L.or_query.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int,
+                               ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                               ctypes.POINTER(OrResult)]
+        L.or_batch.restype = ctypes.c_int
+        L.or_batch.argtypes = [ctypes.c_int] + [ctypes.c_void_p] * 10 + [ctypes.c_int]
+        L.or_pattern_edges.restype = ctypes.c_int
+        L.or_pattern_edges.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+        L.or_aut_count.restype = ctypes.c_int
+        L.or_aut_count.argtypes = [ctypes.c_int, ctypes.c_int]
+        L.or_result_size.restype = ctypes.c_int
+        assert L.or_result_size() == RESULT_DTYPE.itemsize == ctypes.sizeof(OrResult)
+        _lib = L
+    return _lib
+
+
+def query(W, busy, kind, k, mode=MODE_ALL, a=1, b=1) -> dict:
+    """One query on an n x n weight matrix.  Returns a dict of the result."""
+    W = np.ascontiguousarray(np.asarray(W, dtype=np.uint8))
+    n = W.shape[0]
+    r = OrResult()
+    lib().or_query(n, W.ctypes.data, int(busy), int(kind), int(k), int(mode), int(a), int(b),
+                   ctypes.byref(r))
+    return {
+        "count": r.count, "status": r.status, "key": r.key, "agg": r.agg, "pres": r.pres,
+        "vertex_mask": r.vertex_mask,
+        "mapping": tuple(r.mapping[i] for i in range(k) if r.status == OK) if 1 <= k <= 8 else (),
+    }
+
+
+def pattern_edges(kind, k):
+    buf = (ctypes.c_int * 56)()
+    ne = lib().or_pattern_edges(int(kind), int(k), buf)
+    if ne < 0:
+        raise ValueError("bad pattern")
+    return [(buf[2 * i], buf[2 * i + 1]) for i in range(ne)]
+
+
+def aut_count(kind, k) -> int:
+    return int(lib().or_aut_count(int(kind), int(k)))
+
+
+def pad_topologies(topologies):
+    T = len(topologies)
+    tn = np.array([t.shape[0] for t in topologies], dtype=np.int32)
+    tw = np.zeros((T, 16, 16), dtype=np.uint8)
+    for i, t in enumerate(topologies):
+        n = t.shape[0]
+        tw[i, :n, :n] = t
+    return tn, tw
+
+
+def batch(topologies, q_topo, q_busy, kind, k, mode, a, b, nthreads: int | None = None):
+    """Evaluate queries independently.  Returns a structured numpy array."""
+    tn, tw = pad_topologies(topologies)
+    nq = len(q_topo)
+    cols = [np.ascontiguousarray(np.asarray(x, dtype=dt)) for x, dt in (
+        (q_topo, np.int32), (q_busy, np.uint32), (kind, np.uint8), (k, np.uint8),
+        (mode, np.uint8), (a, np.int16), (b, np.int16))]
+    out = np.zeros(nq, dtype=RESULT_DTYPE)
+    if nthreads is None:
+        nthreads = os.cpu_count() or 1
+    lib().or_batch(nq, tn.ctypes.data, tw.ctypes.data, *[c.ctypes.data for c in cols],
+                   out.ctypes.data, int(nthreads))
+    return out
+
+
+def run_workload(wl, nthreads: int | None = None):
+    """Evaluate every query of a synth.Workload against its entry busy masks."""
+    q = wl.queries
+    srv = q["server"]
+    return batch(wl.topologies, wl.server_topo[srv], wl.busy[srv], q["kind"], q["k"],
+                 q["mode"], q["a"], q["b"], nthreads)
+
+
+def run_batch_semantics(wl, nthreads: int | None = None):
+    """Evaluate a batch, then apply commits (see module docstring).
+
+    Returns (results, handles int64 [nq], busy_after uint32 [S])."""
+    res = run_workload(wl, nthreads)
+    q = wl.queries
+    busy = wl.busy.copy()
+    handles = np.full(wl.nq, -1, dtype=np.int64)
+    seen = set()
+    for i in range(wl.nq):
+        if not q["commit"][i]:
+            continue
+        s = int(q["server"][i])
+        first = s not in seen
+        seen.add(s)
+        if res["status"][i] != OK:
+            continue
+        if not first:
+            res["status"][i] = CONFLICT
+            continue
+        m = int(res["vertex_mask"][i])
+        busy[s] |= np.uint32(m)
+        handles[i] = (s << 32) | m
+    return res, handles, busy

@@ -1,0 +1,319 @@
+/*
+ * MAPA allocation oracle -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain, slow, obviously correct CPU brute force of one allocation query of
+ * "MAPA: Multi-Accelerator Pattern Allocation Policy for Multi-Tenant GPU
+ * Servers" (SC'21).  Only the test-suite, the smoke check and the benchmark's
+ * CPU-baseline leg may load this library; the product path never does.  It
+ * shares no code, header, table or helper with the GPU library.
+ *
+ * What one query computes (every step cites the passage it follows):
+ *   - Hardware graph G: n accelerators, symmetric weight matrix W, W[v][v]=0,
+ *     edge label = highest link bandwidth (Sec. 3.2).  Busy vertices are
+ *     removed from G by state management (Sec. 3.6); R = the free vertices.
+ *   - Pattern graph P on k vertices: ring, all-to-all or binary tree (Sec. 3.1,
+ *     Fig. "Example application topology").  Canonical numbering, see
+ *     or_pattern_edges().
+ *   - Matches (Sec. 3.3): one-to-one maps phi from V(P) into R such that
+ *     adjacent pattern vertices land on adjacent accelerators.  Because the
+ *     paper assumes G fully connected (Sec. 3.2, every pair reachable through
+ *     the host), mode ALL accepts every injective map; mode LINKED accepts
+ *     only maps whose pattern edges land on pairs with W > 0.
+ *   - AggBW (Eq. 1): sum of w(e) over the pattern edges mapped into G.
+ *   - PreservedBW (Eq. 3): sum of w(e) over the subgraph induced by the free
+ *     vertices that the match leaves unallocated, i.e. over pairs u<v of
+ *     R \ phi(V(P)).
+ *   - Selection (Alg. 1): scan every match, keep the one with the largest
+ *     key; key = a*AggBW + b*PreservedBW with integer a, b >= 0 ((1,0) is the
+ *     Greedy policy of Sec. 4, (0,1) the bandwidth-insensitive branch of
+ *     Alg. 1).  Matches are scanned in lexicographic order of
+ *     (phi(0), ..., phi(k-1)) and a later match replaces the kept one only
+ *     on a strictly larger key, so ties go to the lexicographically smallest
+ *     mapping.
+ *   - The result: number of matches (int64), the kept mapping, its key, AggBW
+ *     and PreservedBW.
+ *
+ * PreservedBW depends only on the chosen vertex set; its literal double loop
+ * is memoised per vertex set (same loop, evaluated at most once per set).
+ * Parity of this file is pinned by the "not gpu" test-suite: closed-form
+ * counts, hand-derived counts and argmaxes, the paper's worked AggBW example,
+ * automorphism counts, textbook special cases and exhaustive agreement with an
+ * independent Python brute force.
+ */
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_MAX_N 16
+#define OR_MAX_K 8
+#define OR_MAX_AB 1024
+
+enum { OR_RING = 0, OR_A2A = 1, OR_TREE = 2 };
+enum { OR_MODE_ALL = 0, OR_MODE_LINKED = 1 };
+enum { OR_OK = 0, OR_NOFIT = 1 };
+enum { OR_EINVAL = -1, OR_EUNSUP = -2, OR_ENOMEM = -3 };
+
+typedef struct {
+  int64_t count;
+  int32_t status;
+  int32_t key, agg, pres;
+  uint32_t vertex_mask;
+  uint8_t mapping[8];
+} or_result;
+
+/* Canonical pattern graphs (Sec. 3.1).  Pattern vertex i is tuple position i.
+ *   ring, k=1: no edge; k=2: the single edge (0,1); k>=3: (i, i+1 mod k).
+ *   all-to-all: every pair i<j.
+ *   binary tree: heap numbering, vertex i>0 hangs under (i-1)/2.
+ * Each edge appears once.  Returns the number of edges; ep holds pairs. */
+int or_pattern_edges(int kind, int k, int *ep) {
+  int ne = 0;
+  if (k < 1 || k > OR_MAX_K) return OR_EINVAL;
+  if (kind == OR_RING) {
+    if (k == 2) {
+      ep[0] = 0; ep[1] = 1; ne = 1;
+    } else if (k >= 3) {
+      for (int i = 0; i < k; ++i) { ep[2 * ne] = i; ep[2 * ne + 1] = (i + 1) % k; ++ne; }
+    }
+  } else if (kind == OR_A2A) {
+    for (int i = 0; i < k; ++i)
+      for (int j = i + 1; j < k; ++j) { ep[2 * ne] = i; ep[2 * ne + 1] = j; ++ne; }
+  } else if (kind == OR_TREE) {
+    for (int i = 1; i < k; ++i) { ep[2 * ne] = (i - 1) / 2; ep[2 * ne + 1] = i; ++ne; }
+  } else {
+    return OR_EINVAL;
+  }
+  return ne;
+}
+
+/* |Aut(P)| by brute force over all k! permutations sigma of V(P): sigma is an
+ * automorphism iff it maps the edge set onto itself. */
+int or_aut_count(int kind, int k) {
+  int ep[2 * 28];
+  int ne = or_pattern_edges(kind, k, ep);
+  if (ne < 0) return ne;
+  int adj[OR_MAX_K][OR_MAX_K];
+  memset(adj, 0, sizeof adj);
+  for (int e = 0; e < ne; ++e) adj[ep[2 * e]][ep[2 * e + 1]] = adj[ep[2 * e + 1]][ep[2 * e]] = 1;
+  int sigma[OR_MAX_K], used[OR_MAX_K] = {0};
+  int count = 0, depth = 0;
+  /* iterative permutation walk */
+  int next[OR_MAX_K + 1];
+  next[0] = 0;
+  while (depth >= 0) {
+    if (depth == k) {
+      int ok = 1;
+      for (int e = 0; e < ne && ok; ++e)
+        if (!adj[sigma[ep[2 * e]]][sigma[ep[2 * e + 1]]]) ok = 0;
+      count += ok;
+      --depth;
+      if (depth >= 0) used[sigma[depth]] = 0;
+      continue;
+    }
+    int c = next[depth];
+    while (c < k && used[c]) ++c;
+    if (c >= k) {
+      --depth;
+      if (depth >= 0) used[sigma[depth]] = 0;
+      continue;
+    }
+    sigma[depth] = c;
+    used[c] = 1;
+    next[depth] = c + 1;
+    ++depth;
+    next[depth] = 0;
+  }
+  return count;
+}
+
+typedef struct {
+  int n, k, ne, mode;
+  int64_t a, b;
+  const uint8_t *W; /* n*n row-major */
+  int ep[2 * 28];
+  int R[OR_MAX_N], F;
+  uint32_t Rmask;
+  int32_t *memo; /* 1<<n entries; -1 = not yet evaluated */
+  int phi[OR_MAX_K];
+  int used[OR_MAX_N];
+  int64_t count;
+  int have;
+  int64_t bkey, bagg, bpres;
+  int bphi[OR_MAX_K];
+} or_state;
+
+/* Eq. 3: PreservedBW of the vertex set S = sum of W[u][v] over pairs u<v of
+ * free vertices not in S (the subgraph induced by R \ S). */
+static int64_t preserved_bw(or_state *s, uint32_t S) {
+  if (s->memo[S] >= 0) return s->memo[S];
+  int64_t p = 0;
+  for (int u = 0; u < s->n; ++u) {
+    if (!((s->Rmask >> u) & 1u) || ((S >> u) & 1u)) continue;
+    for (int v = u + 1; v < s->n; ++v) {
+      if (!((s->Rmask >> v) & 1u) || ((S >> v) & 1u)) continue;
+      p += s->W[u * s->n + v];
+    }
+  }
+  s->memo[S] = (int32_t)p;
+  return p;
+}
+
+static void visit_match(or_state *s) {
+  const int n = s->n;
+  /* Sec. 3.3, mode LINKED: adjacent pattern vertices must be adjacent in G */
+  if (s->mode == OR_MODE_LINKED)
+    for (int e = 0; e < s->ne; ++e)
+      if (s->W[s->phi[s->ep[2 * e]] * n + s->phi[s->ep[2 * e + 1]]] == 0) return;
+  s->count += 1;
+  /* Eq. 1: AggBW = sum over the mapped pattern edges */
+  int64_t agg = 0;
+  for (int e = 0; e < s->ne; ++e) agg += s->W[s->phi[s->ep[2 * e]] * n + s->phi[s->ep[2 * e + 1]]];
+  uint32_t S = 0;
+  for (int i = 0; i < s->k; ++i) S |= 1u << s->phi[i];
+  int64_t pres = preserved_bw(s, S);
+  int64_t key = s->a * agg + s->b * pres;
+  /* Alg. 1: replace on a strictly larger score only */
+  if (!s->have || key > s->bkey) {
+    s->have = 1;
+    s->bkey = key;
+    s->bagg = agg;
+    s->bpres = pres;
+    memcpy(s->bphi, s->phi, sizeof s->phi);
+  }
+}
+
+/* all injective tuples, candidates ascending at every position, so tuples
+ * come out in lexicographic order */
+static void extend(or_state *s, int pos) {
+  if (pos == s->k) {
+    visit_match(s);
+    return;
+  }
+  for (int i = 0; i < s->F; ++i) {
+    int v = s->R[i];
+    if (s->used[v]) continue;
+    s->used[v] = 1;
+    s->phi[pos] = v;
+    extend(s, pos + 1);
+    s->used[v] = 0;
+  }
+}
+
+static int validate_topology(int n, const uint8_t *W) {
+  if (n < 1) return OR_EINVAL;
+  if (n > OR_MAX_N) return OR_EUNSUP;
+  for (int u = 0; u < n; ++u) {
+    if (W[u * n + u] != 0) return OR_EINVAL;
+    for (int v = 0; v < n; ++v)
+      if (W[u * n + v] != W[v * n + u]) return OR_EINVAL;
+  }
+  return OR_OK;
+}
+
+/* One query against one hardware graph.  memo must hold 1<<n int32. */
+static int query_with_memo(int n, const uint8_t *W, uint32_t busy, int kind, int k, int mode,
+                           int a, int b, or_result *out, int32_t *memo) {
+  memset(out, 0, sizeof *out);
+  memset(out->mapping, 0xFF, sizeof out->mapping);
+  out->key = INT32_MIN;
+  int rc = validate_topology(n, W);
+  if (rc) return out->status = rc;
+  if (k > OR_MAX_K) return out->status = OR_EUNSUP;
+  if (k < 1 || kind < 0 || kind > 2 || mode < 0 || mode > 1 || a < 0 || b < 0 ||
+      a > OR_MAX_AB || b > OR_MAX_AB || (n < 32 && (busy >> n) != 0))
+    return out->status = OR_EINVAL;
+
+  or_state *s = (or_state *)calloc(1, sizeof(or_state));
+  if (!s) return out->status = OR_ENOMEM;
+  s->n = n; s->k = k; s->mode = mode; s->a = a; s->b = b; s->W = W; s->memo = memo;
+  s->ne = or_pattern_edges(kind, k, s->ep);
+  for (int v = 0; v < n; ++v)
+    if (!((busy >> v) & 1u)) { s->R[s->F++] = v; s->Rmask |= 1u << v; }
+  for (uint32_t m = 0; m < (1u << n); ++m) memo[m] = -1;
+
+  if (k <= s->F) extend(s, 0);
+
+  out->count = s->count;
+  if (s->have) {
+    out->status = OR_OK;
+    out->key = (int32_t)s->bkey;
+    out->agg = (int32_t)s->bagg;
+    out->pres = (int32_t)s->bpres;
+    for (int i = 0; i < k; ++i) {
+      out->mapping[i] = (uint8_t)s->bphi[i];
+      out->vertex_mask |= 1u << s->bphi[i];
+    }
+  } else {
+    out->status = OR_NOFIT;
+  }
+  free(s);
+  return OR_OK;
+}
+
+int or_query(int n, const uint8_t *W, uint32_t busy, int kind, int k, int mode, int a, int b,
+             or_result *out) {
+  int nn = (n >= 1 && n <= OR_MAX_N) ? n : 1;
+  int32_t *memo = (int32_t *)malloc(sizeof(int32_t) << nn);
+  if (!memo) return OR_ENOMEM;
+  int rc = query_with_memo(n, W, busy, kind, k, mode, a, b, out, memo);
+  free(memo);
+  return rc;
+}
+
+/* ---------------- batch driver: static split of queries over threads ------ */
+
+typedef struct {
+  int tid, nthreads, nq;
+  const int32_t *topo_n;
+  const uint8_t *topo_W; /* per topology 16*16 row-major, row stride 16 */
+  const int32_t *q_topo;
+  const uint32_t *q_busy;
+  const uint8_t *q_kind, *q_k, *q_mode;
+  const int16_t *q_a, *q_b;
+  or_result *out;
+} or_job;
+
+static void *batch_worker(void *arg) {
+  or_job *j = (or_job *)arg;
+  int32_t *memo = (int32_t *)malloc(sizeof(int32_t) << OR_MAX_N);
+  uint8_t W[OR_MAX_N * OR_MAX_N];
+  for (int q = j->tid; q < j->nq; q += j->nthreads) {
+    int t = j->q_topo[q];
+    int n = j->topo_n[t];
+    if (n < 1 || n > OR_MAX_N || !memo) {
+      memset(&j->out[q], 0, sizeof(or_result));
+      j->out[q].status = memo ? OR_EINVAL : OR_ENOMEM;
+      continue;
+    }
+    for (int u = 0; u < n; ++u)
+      for (int v = 0; v < n; ++v) W[u * n + v] = j->topo_W[(size_t)t * 256 + u * 16 + v];
+    query_with_memo(n, W, j->q_busy[q], j->q_kind[q], j->q_k[q], j->q_mode[q], j->q_a[q],
+                    j->q_b[q], &j->out[q], memo);
+  }
+  free(memo);
+  return NULL;
+}
+
+int or_batch(int nq, const int32_t *topo_n, const uint8_t *topo_W, const int32_t *q_topo,
+             const uint32_t *q_busy, const uint8_t *q_kind, const uint8_t *q_k,
+             const uint8_t *q_mode, const int16_t *q_a, const int16_t *q_b, or_result *out,
+             int nthreads) {
+  if (nthreads < 1) nthreads = 1;
+  if (nthreads > 256) nthreads = 256;
+  pthread_t th[256];
+  or_job jobs[256];
+  for (int t = 0; t < nthreads; ++t) {
+    jobs[t] = (or_job){t, nthreads, nq, topo_n, topo_W, q_topo, q_busy, q_kind, q_k, q_mode,
+                       q_a, q_b, out};
+    if (pthread_create(&th[t], NULL, batch_worker, &jobs[t]) != 0) {
+      batch_worker(&jobs[t]);
+      th[t] = 0;
+    }
+  }
+  for (int t = 0; t < nthreads; ++t)
+    if (th[t]) pthread_join(th[t], NULL);
+  return OR_OK;
+}
+
+int or_result_size(void) { return (int)sizeof(or_result); }

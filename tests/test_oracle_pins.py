@@ -1,0 +1,527 @@
+"""Pins for the CPU oracle: values fixed by the paper and by mathematics, not
+by the oracle itself.
+
+Each pin is chosen so that a plausible slip in the oracle fails at least one
+of them: a dropped pattern edge (ring closure, a tree edge), a wrong sign or a
+wrong vertex set in PreservedBW, busy vertices leaking into a score, a wrong
+tie-break, an off-by-one in the candidate set.  ``test_pins_catch_planted_
+mistakes`` plants such slips into a copy of the Python brute force (on the CPU)
+and checks the pins reject every one of them.
+"""
+import itertools
+import math
+import os
+import random
+
+import numpy as np
+import pytest
+
+from oracle import brute
+
+RING, A2A, TREE = 0, 1, 2
+ALL, LINKED = 0, 1
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- host graphs
+
+def graph(n, edges, w=1):
+    W = np.zeros((n, n), dtype=np.uint8)
+    for e in edges:
+        u, v = e[0], e[1]
+        W[u, v] = W[v, u] = e[2] if len(e) > 2 else w
+    return W
+
+
+def cube_mesh(w=1):
+    e = list(itertools.combinations(range(4), 2))
+    e += [(u + 4, v + 4) for u, v in itertools.combinations(range(4), 2)]
+    e += [(i, i + 4) for i in range(4)]
+    return graph(8, e, w)
+
+
+def hypercube(dim):
+    n = 1 << dim
+    return graph(n, [(u, u ^ (1 << b)) for u in range(n) for b in range(dim) if u < u ^ (1 << b)])
+
+
+def random_sym(rng, n, wmax, p_edge=1.0):
+    W = np.zeros((n, n), dtype=np.uint8)
+    for u in range(n):
+        for v in range(u + 1, n):
+            if rng.random() < p_edge:
+                W[u, v] = W[v, u] = rng.integers(0, wmax + 1)
+    return W
+
+
+def load_dgx1v():
+    rows, facts, mode = [], {}, None
+    with open(os.path.join(GOLDEN, "dgx1v_worked_example.txt")) as f:
+        for line in f:
+            line = line.split("#")[0].strip()
+            if not line:
+                continue
+            if line == "nvlink_counts":
+                mode = "m"
+                continue
+            if line == "end":
+                mode = None
+                continue
+            if mode == "m":
+                rows.append([int(x) for x in line.split()])
+                continue
+            tok = line.split()
+            if tok[0] == "gbps":
+                facts.setdefault("gbps", {})[int(tok[1])] = int(tok[2])
+            elif tok[0] == "aggbw_of":
+                facts["aggbw_of"] = (tuple(int(x) for x in tok[1:4]), int(tok[5]))
+            elif tok[0] == "best_mapping":
+                facts["best_mapping"] = tuple(int(x) for x in tok[1:])
+            else:
+                facts[tok[0]] = int(tok[1])
+    return np.array(rows, dtype=np.uint8), facts
+
+
+# ------------------------------------------------- theoretical automorphisms
+# |Aut| of the canonical patterns, from combinatorics: the cycle C_k has the
+# dihedral group (2k elements, k>=3); K_k has k!; the heap-numbered binary
+# trees are, for k = 1..8: a point, an edge, a path of 3, a path of 4, a
+# spider with legs 1,1,2, a "double cherry" minus a leaf, the complete binary
+# tree of 7 (8 automorphisms), and that tree with one extra grandchild.
+AUT = {
+    RING: [1, 2, 6, 8, 10, 12, 14, 16],
+    A2A: [math.factorial(k) for k in range(1, 9)],
+    TREE: [1, 2, 2, 2, 2, 2, 8, 2],
+}
+
+
+def test_automorphism_counts_match_theory(orc):
+    for kind in (RING, A2A, TREE):
+        for k in range(1, 9):
+            assert orc.aut_count(kind, k) == AUT[kind][k - 1], (kind, k)
+
+
+def test_pattern_edge_counts(orc):
+    # |E| of C_k (k>=3), K_k, and a tree on k vertices
+    for k in range(1, 9):
+        assert len(orc.pattern_edges(RING, k)) == (0 if k == 1 else 1 if k == 2 else k)
+        assert len(orc.pattern_edges(A2A, k)) == k * (k - 1) // 2
+        assert len(orc.pattern_edges(TREE, k)) == k - 1
+
+
+# ------------------------------------------------------------------- P1 / P2
+
+@pytest.mark.parametrize("n", [1, 2, 5, 8, 11, 16])
+def test_all_mode_count_closed_form(orc, n):
+    """Sec. 3.2 fully connected G: every injective map is a match, so the
+    count is F!/(F-k)! for k <= F and the result is NOFIT for k > F."""
+    rng = np.random.default_rng(1000 + n)
+    W = random_sym(rng, n, 3)
+    for _ in range(12):
+        busy = int(rng.integers(0, 1 << n))
+        F = n - bin(busy).count("1")
+        for kind in (RING, A2A, TREE):
+            for k in range(1, 9):
+                if math.perm(F, k) > 600_000:
+                    continue
+                r = orc.query(W, busy, kind, k, ALL, 1, 1)
+                if k > F:
+                    assert r["status"] == 1 and r["count"] == 0
+                else:
+                    assert r["status"] == 0 and r["count"] == math.perm(F, k)
+
+
+def test_linked_equals_all_on_positive_complete_graph(orc):
+    rng = np.random.default_rng(7)
+    for n in (4, 6, 8):
+        W = random_sym(rng, n, 4)
+        W[W == 0] = 1
+        np.fill_diagonal(W, 0)
+        for kind in (RING, A2A, TREE):
+            for k in range(1, min(n, 6) + 1):
+                for ab in ((1, 1), (1, 0), (0, 1)):
+                    assert orc.query(W, 0, kind, k, ALL, *ab) == orc.query(W, 0, kind, k, LINKED, *ab)
+
+
+# ------------------------------------------------------------------ P3 / P4
+
+def test_pattern_into_itself_counts_automorphisms(orc):
+    """Embeddings of P into a host graph equal to P are exactly Aut(P).  The
+    host graphs are written here from the shapes' definitions."""
+    hosts = {
+        RING: lambda k: [] if k == 1 else [(0, 1)] if k == 2 else [(i, (i + 1) % k) for i in range(k)],
+        A2A: lambda k: list(itertools.combinations(range(k), 2)),
+        TREE: lambda k: [(i, c) for i in range(k) for c in (2 * i + 1, 2 * i + 2) if c < k],
+    }
+    for kind in (RING, A2A, TREE):
+        for k in range(1, 9):
+            W = graph(k, hosts[kind](k))
+            assert orc.query(W, 0, kind, k, LINKED)["count"] == AUT[kind][k - 1], (kind, k)
+
+
+def test_cube_mesh_hand_counts(orc):
+    """Hand-derived LINKED counts on the 8-vertex cube-mesh (K4 + K4 + rungs;
+    every vertex has degree 4).  Ordered embeddings = copies x |Aut|:
+      edges 16 -> ring k=2: 32;  triangles 4 per K4 (rungs close none) -> 48;
+      4-cycles: 3 per K4 + 6 rung squares {i,j,j+4,i+4} -> 12 x 8 = 96;
+      K4 copies 2 -> 48;  no K5;  tree k=3 (2-paths): sum deg(deg-1) = 96;
+      tree k=4 (3-paths): sum over ordered edges of (deg-1)^2 - common
+      neighbours = 24*(9-2) + 8*9 = 240."""
+    W = cube_mesh()
+    expect = {(RING, 2): 32, (RING, 3): 48, (RING, 4): 96, (A2A, 3): 48, (A2A, 4): 48,
+              (A2A, 5): 0, (A2A, 8): 0, (TREE, 2): 32, (TREE, 3): 96, (TREE, 4): 240}
+    for (kind, k), c in expect.items():
+        assert orc.query(W, 0, kind, k, LINKED)["count"] == c, (kind, k)
+
+
+def test_hypercube_hand_counts(orc):
+    """Q4: 32 edges, degree 4, bipartite (no odd cycle), every 4-cycle is a
+    2-face: C(4,2) * 2^2 = 24 faces -> 24 x 8 = 192; 2-paths 16*4*3 = 192."""
+    W = hypercube(4)
+    assert orc.query(W, 0, RING, 2, LINKED)["count"] == 64
+    assert orc.query(W, 0, RING, 4, LINKED)["count"] == 192
+    assert orc.query(W, 0, TREE, 3, LINKED)["count"] == 192
+    for k in (3, 5):
+        assert orc.query(W, 0, RING, k, LINKED)["count"] == 0
+    assert orc.query(W, 0, A2A, 3, LINKED)["count"] == 0
+
+
+def test_linked_counts_divisible_by_automorphisms(orc):
+    rng = np.random.default_rng(11)
+    for _ in range(6):
+        W = random_sym(rng, 8, 2, p_edge=0.6)
+        busy = int(rng.integers(0, 4))
+        for kind in (RING, A2A, TREE):
+            for k in range(2, 7):
+                c = orc.query(W, busy, kind, k, LINKED)["count"]
+                assert c % AUT[kind][k - 1] == 0, (kind, k, c)
+
+
+# ---------------------------------------------------------------------- P6
+
+def test_cube_mesh_all_ones_argmax(orc):
+    """Unit weights, ring k=4, nothing busy: AggBW <= 4 (four edges) and
+    PreservedBW <= 6 (the 4 vertices left over span at most a K4); both are
+    reached only when the chosen quad is one K4 (so the rest is the other).
+    Every vertex order of {0,1,2,3} is a 4-cycle of K4, so the lexicographic
+    first best mapping is (0,1,2,3) under all three keys."""
+    W = cube_mesh()
+    for (a, b), key, agg, pres in (((1, 1), 10, 4, 6), ((1, 0), 4, 4, 6), ((0, 1), 6, 4, 6)):
+        r = orc.query(W, 0, RING, 4, ALL, a, b)
+        assert (r["key"], r["mapping"], r["count"]) == (key, (0, 1, 2, 3), 1680)
+        assert (r["agg"], r["pres"]) == (agg, pres)
+
+
+# ---------------------------------------------------------------------- P7
+
+def test_paper_worked_aggbw_example(orc):
+    counts, facts = load_dgx1v()
+    assert (counts == counts.T).all() and (counts.sum(1) == 6).all()
+    gb = np.vectorize(lambda c: facts["gbps"][int(c)])(counts).astype(np.uint8)
+    np.fill_diagonal(gb, 0)
+    (u, v, w), agg = facts["aggbw_of"]
+    # only {u,v,w} free, K3 pattern: every match is that triple
+    busy = 0xFF & ~((1 << u) | (1 << v) | (1 << w))
+    r = orc.query(gb, busy, RING, 3, ALL, 1, 0)
+    assert r["agg"] == agg and r["key"] == agg and r["count"] == 6
+    assert r["mapping"] == (u, v, w)
+    r = orc.query(gb, 0, RING, 3, ALL, 1, 0)
+    assert r["key"] == facts["best_key"] and r["agg"] == facts["best_key"]
+    assert r["mapping"] == facts["best_mapping"]
+    assert r["count"] == facts["count"]
+
+
+# ---------------------------------------------------------------------- P8
+
+def pres_identity(W, R, S):
+    """W(R \\ S) = W(R) - sum_{v in S} d_R(v) + W(S)  (inclusion-exclusion)."""
+    def wsum(X):
+        return sum(int(W[u][v]) for u, v in itertools.combinations(sorted(X), 2))
+    dR = {v: sum(int(W[v][u]) for u in R) for v in S}
+    return wsum(R) - sum(dR.values()) + wsum(S)
+
+
+def test_preserved_identity_and_self_consistency(orc):
+    """P8 + P12: recompute AggBW with test-side edge lists and PreservedBW by
+    inclusion-exclusion from the returned mapping."""
+    rng = np.random.default_rng(3)
+    test_edges = {
+        RING: lambda k: [] if k == 1 else [(0, 1)] if k == 2 else [(i, (i + 1) % k) for i in range(k)],
+        A2A: lambda k: list(itertools.combinations(range(k), 2)),
+        TREE: lambda k: [(i, c) for i in range(k) for c in (2 * i + 1, 2 * i + 2) if c < k],
+    }
+    for it in range(300):
+        n = int(rng.integers(2, 11))
+        W = random_sym(rng, n, 7, p_edge=0.8)
+        busy = int(rng.integers(0, 1 << n)) & int(rng.integers(0, 1 << n))
+        kind = int(rng.integers(0, 3))
+        k = int(rng.integers(1, 6))
+        mode = int(rng.integers(0, 2))
+        a, b = int(rng.integers(0, 5)), int(rng.integers(0, 5))
+        r = orc.query(W, busy, kind, k, mode, a, b)
+        if r["status"] != 0:
+            continue
+        phi = r["mapping"]
+        R = [v for v in range(n) if not busy >> v & 1]
+        assert len(set(phi)) == k and set(phi) <= set(R)
+        E = test_edges[kind](k)
+        if mode == LINKED:
+            assert all(W[phi[p]][phi[q]] > 0 for p, q in E)
+        agg = sum(int(W[phi[p]][phi[q]]) for p, q in E)
+        assert r["agg"] == agg
+        assert r["pres"] == pres_identity(W, R, set(phi))
+        assert r["key"] == a * agg + b * r["pres"]
+        assert r["vertex_mask"] == sum(1 << v for v in phi)
+
+
+# ---------------------------------------------------------------------- P9
+
+def test_single_vertex_pattern(orc):
+    """k=1: AggBW = 0, PreservedBW(v) = W(R) - d_R(v); the best vertex is the
+    free vertex of least free-degree, ties to the smaller id."""
+    rng = np.random.default_rng(5)
+    for _ in range(50):
+        n = int(rng.integers(1, 17))
+        W = random_sym(rng, n, 5)
+        busy = int(rng.integers(0, 1 << n)) & int(rng.integers(0, 1 << n))
+        R = [v for v in range(n) if not busy >> v & 1]
+        for kind in (RING, A2A, TREE):
+            r = orc.query(W, busy, kind, 1, ALL, 1, 1)
+            if not R:
+                assert r["status"] == 1
+                continue
+            d = {v: sum(int(W[v][u]) for u in R) for v in R}
+            best = min(R, key=lambda v: (d[v], v))
+            wr = sum(int(W[u][v]) for u, v in itertools.combinations(R, 2))
+            assert r["mapping"] == (best,) and r["key"] == wr - d[best] and r["count"] == len(R)
+
+
+def held_karp_max_cycle(W, verts):
+    """Textbook Held-Karp DP for the heaviest Hamiltonian cycle on verts."""
+    m = len(verts)
+    if m == 1:
+        return 0
+    if m == 2:
+        return int(W[verts[0]][verts[1]])
+    NEG = -10 ** 9
+    dp = [[NEG] * m for _ in range(1 << m)]
+    dp[1][0] = 0
+    for mask in range(1 << m):
+        if not mask & 1:
+            continue
+        for j in range(m):
+            if dp[mask][j] == NEG:
+                continue
+            for t in range(m):
+                if mask >> t & 1:
+                    continue
+                val = dp[mask][j] + int(W[verts[j]][verts[t]])
+                if val > dp[mask | 1 << t][t]:
+                    dp[mask | 1 << t][t] = val
+    full = (1 << m) - 1
+    return max(dp[full][j] + int(W[verts[j]][verts[0]]) for j in range(1, m))
+
+
+def test_greedy_full_ring_is_max_hamiltonian_cycle(orc):
+    rng = np.random.default_rng(9)
+    for _ in range(40):
+        n = int(rng.integers(3, 9))
+        W = random_sym(rng, n, 9)
+        busy = int(rng.integers(0, 1 << n)) & int(rng.integers(0, 1 << n))
+        R = [v for v in range(n) if not busy >> v & 1]
+        if len(R) < 3:
+            continue
+        r = orc.query(W, busy, RING, len(R), ALL, 1, 0)
+        assert r["key"] == held_karp_max_cycle(W, R)
+        assert r["pres"] == 0
+
+
+def test_a2a_greedy_is_heaviest_induced_subset(orc):
+    rng = np.random.default_rng(13)
+    for _ in range(40):
+        n = int(rng.integers(3, 10))
+        W = random_sym(rng, n, 6)
+        busy = int(rng.integers(0, 1 << n)) & int(rng.integers(0, 1 << n))
+        R = [v for v in range(n) if not busy >> v & 1]
+        for k in range(2, min(len(R), 5) + 1):
+            best = max(combo_w(W, c) for c in itertools.combinations(R, k))
+            first = min(c for c in itertools.combinations(R, k) if combo_w(W, c) == best)
+            r = orc.query(W, busy, A2A, k, ALL, 1, 0)
+            assert r["key"] == best
+            # a2a AggBW is order-free, so the first sorted best subset wins
+            assert r["mapping"] == first
+
+
+def combo_w(W, c):
+    return sum(int(W[u][v]) for u, v in itertools.combinations(c, 2))
+
+
+def test_two_vertex_patterns_coincide(orc):
+    rng = np.random.default_rng(17)
+    for _ in range(30):
+        n = int(rng.integers(2, 12))
+        W = random_sym(rng, n, 4, p_edge=0.7)
+        busy = int(rng.integers(0, 1 << n)) & int(rng.integers(0, 1 << n))
+        for mode in (ALL, LINKED):
+            rs = [orc.query(W, busy, kind, 2, mode, 2, 3) for kind in (RING, A2A, TREE)]
+            assert rs[0] == rs[1] == rs[2]
+
+
+# --------------------------------------------------------------------- P10
+
+def test_relabeling_invariance(orc):
+    rng = np.random.default_rng(21)
+    for _ in range(40):
+        n = int(rng.integers(3, 10))
+        W = random_sym(rng, n, 3, p_edge=0.7)
+        busy = int(rng.integers(0, 1 << n)) & int(rng.integers(0, 1 << n))
+        pi = rng.permutation(n)
+        Wp = np.zeros_like(W)
+        for u in range(n):
+            for v in range(n):
+                Wp[pi[u], pi[v]] = W[u, v]
+        busyp = sum(1 << int(pi[v]) for v in range(n) if busy >> v & 1)
+        kind, k = int(rng.integers(0, 3)), int(rng.integers(1, 6))
+        mode, a, b = int(rng.integers(0, 2)), int(rng.integers(0, 3)), int(rng.integers(0, 3))
+        r = orc.query(W, busy, kind, k, mode, a, b)
+        rp = orc.query(Wp, busyp, kind, k, mode, a, b)
+        assert (r["count"], r["status"], r["key"]) == (rp["count"], rp["status"], rp["key"])
+
+
+# --------------------------------------------------------------------- P11
+
+def as_tuple(r):
+    if r["status"] != 0:
+        return (r["count"], r["status"])
+    return (r["count"], r["status"], r["key"], r["agg"], r["pres"], tuple(r["mapping"]),
+            r["vertex_mask"])
+
+
+def test_exhaustive_agreement_with_python_brute_force(orc):
+    """Every n <= 4 case with weights in {0..3} drawn per graph, every busy
+    mask, kind, k <= n, both modes and four key weightings; plus sampled
+    n = 5 and n = 6 graphs."""
+    rng = np.random.default_rng(23)
+    cases = 0
+    for n in range(1, 7):
+        graphs = 3 if n <= 4 else 2
+        for _ in range(graphs):
+            W = random_sym(rng, n, 3)
+            Wl = W.tolist()
+            masks = range(1 << n) if n <= 5 else rng.integers(0, 1 << n, size=6)
+            for busy in masks:
+                busy = int(busy)
+                for kind in (RING, A2A, TREE):
+                    for k in range(1, n + 1):
+                        for mode in (ALL, LINKED):
+                            for a, b in ((1, 0), (0, 1), (1, 1), (3, 2)):
+                                assert as_tuple(orc.query(W, busy, kind, k, mode, a, b)) == \
+                                    as_tuple(brute.query(Wl, busy, kind, k, mode, a, b)), \
+                                    (n, busy, kind, k, mode, a, b)
+                                cases += 1
+    assert cases > 5000
+
+
+# ---------------------------------------------------------- edges and limits
+
+def test_input_validation(orc):
+    W = cube_mesh()
+    assert orc.query(W, 0, RING, 0)["status"] == orc.EINVAL
+    assert orc.query(W, 0, RING, 9)["status"] == orc.EUNSUP
+    assert orc.query(W, 0, 3, 2)["status"] == orc.EINVAL
+    assert orc.query(W, 0, RING, 2, 2)["status"] == orc.EINVAL
+    assert orc.query(W, 1 << 8, RING, 2)["status"] == orc.EINVAL
+    assert orc.query(W, 0, RING, 2, ALL, 1025, 0)["status"] == orc.EINVAL
+    bad = W.copy()
+    bad[0, 1] = 7
+    assert orc.query(bad, 0, RING, 2)["status"] == orc.EINVAL
+    bad = W.copy()
+    bad[2, 2] = 1
+    assert orc.query(bad, 0, RING, 2)["status"] == orc.EINVAL
+    assert orc.query(np.zeros((17, 17), np.uint8), 0, RING, 2)["status"] == orc.EUNSUP
+
+
+def test_extreme_weights_and_keys_fit_int32(orc):
+    """W = 255 everywhere, a = b = 1024: key = 1024 * (AggBW + PreservedBW)."""
+    n = 16
+    W = np.full((n, n), 255, np.uint8)
+    np.fill_diagonal(W, 0)
+    r = orc.query(W, 0, A2A, 3, ALL, 1024, 1024)
+    agg = 3 * 255
+    pres = math.comb(13, 2) * 255
+    assert r["key"] == 1024 * (agg + pres) and r["mapping"] == (0, 1, 2)
+
+
+# ------------------------------------------- planted mistakes must be caught
+
+def _pins_hold(q):
+    """A compact subset of the pins above, run against a brute-force variant."""
+    W = cube_mesh()
+    r = q(W.tolist(), 0, RING, 4, 0, 1, 1)
+    if (r.get("key"), r.get("mapping"), r["count"]) != (10, (0, 1, 2, 3), 1680):
+        return False
+    counts, facts = load_dgx1v()
+    gb = np.vectorize(lambda c: facts["gbps"][int(c)])(counts).astype(np.uint8)
+    np.fill_diagonal(gb, 0)
+    r = q(gb.tolist(), 0, RING, 3, 0, 1, 0)
+    if (r.get("key"), r.get("mapping")) != (facts["best_key"], facts["best_mapping"]):
+        return False
+    r = q(W.tolist(), 0, TREE, 4, 1, 1, 1)
+    if r["count"] != 240:
+        return False
+    rng = random.Random(1)
+    for _ in range(20):
+        n = rng.randint(3, 6)
+        Wr = [[0] * n for _ in range(n)]
+        for u in range(n):
+            for v in range(u + 1, n):
+                Wr[u][v] = Wr[v][u] = rng.randint(0, 4)
+        busy = rng.randint(0, (1 << n) - 1) & rng.randint(0, (1 << n) - 1)
+        R = [v for v in range(n) if not busy >> v & 1]
+        r = q(Wr, busy, RING, 1, 0, 1, 1)
+        if R:
+            d = {v: sum(Wr[v][u] for u in R) for v in R}
+            best = min(R, key=lambda v: (d[v], v))
+            if r.get("mapping") != (best,):
+                return False
+        if len(R) >= 3:
+            r = q(Wr, busy, RING, len(R), 0, 1, 0)
+            if r.get("key") != held_karp_max_cycle(np.array(Wr), R):
+                return False
+    return True
+
+
+def test_pins_catch_planted_mistakes(monkeypatch):
+    assert _pins_hold(brute.query)
+
+    def variant(edges=None, pres_over=None, tie_last=False):
+        def q(W, busy, kind, k, mode=0, a=1, b=1):
+            n = len(W)
+            free = [v for v in range(n) if not (busy >> v) & 1]
+            E = (edges or brute.edges)(kind, k)
+            count, best = 0, None
+            for phi in itertools.permutations(free, k):
+                if mode == 1 and any(W[phi[p]][phi[q_]] == 0 for p, q_ in E):
+                    continue
+                count += 1
+                agg = sum(W[phi[p]][phi[q_]] for p, q_ in E)
+                left = (pres_over or (lambda fr, ph, nn: [v for v in fr if v not in ph]))(free, phi, n)
+                pres = sum(W[u][v] for u, v in itertools.combinations(left, 2))
+                key = a * agg + b * pres
+                if best is None or key > best[0] or (tie_last and key == best[0]):
+                    best = (key, tuple(phi))
+            if best is None:
+                return {"count": 0}
+            return {"count": count, "key": best[0], "mapping": best[1]}
+        return q
+
+    open_ring = lambda kind, k: [(i, i + 1) for i in range(k - 1)] if kind == RING else brute.edges(kind, k)
+    bad_tree = lambda kind, k: [(i // 2, i) for i in range(1, k)] if kind == TREE else brute.edges(kind, k)
+    with_busy = lambda fr, ph, n: [v for v in range(n) if v not in ph]
+    keep_chosen = lambda fr, ph, n: list(fr)
+    for name, v in (("open ring", variant(edges=open_ring)),
+                    ("tree parent i//2", variant(edges=bad_tree)),
+                    ("busy vertices preserved", variant(pres_over=with_busy)),
+                    ("chosen vertices preserved", variant(pres_over=keep_chosen)),
+                    ("last maximum wins", variant(tie_last=True))):
+        assert not _pins_hold(v), name
