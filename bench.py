@@ -1,0 +1,244 @@
+#!/usr/bin/env python3
+"""Benchmark of the MAPA allocation hot path on one MI355X.
+
+A step is one pass of the whole hot path over one batch: every query of the
+workload is answered (free sets and key constants, pattern tables, every
+embedding enumerated and scored, best selected with the fixed tie-break),
+every successful query commits its allocation, and every committed
+allocation is released again, so each step starts from the same busy state.
+Queries, results and busy masks stay in HBM; nothing crosses PCIe inside the
+timed region.
+
+Default workload: the batched config (65,536 server states over three 8- and
+6-vertex topologies, 0-6 busy vertices, ring / all-to-all / tree patterns with
+k in 2..8).  ``--config 3`` runs the large 16-vertex enumeration and
+``--config 1`` the tiny one.
+
+Prints ONE JSON line (rank 0):  value = embeddings scored per second, plus
+queries/s, per-batch p50/p99 latency, the roofline of the enumeration kernel
+(integer ALU bound) and the CPU oracle timed on the host on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "pattern embeddings scored/sec + allocation queries/sec, p50/p99 latency"
+# MI355X: 256 CUs x 4 SIMD x 16 lanes = 64 int32 lane-ops per clock per CU
+# (one wave64 VALU op every 4 clocks on each of 4 SIMDs), 2.4 GHz peak clock.
+CU, LANES_PER_CLK, CLK = 256, 64, 2.4e9
+ALU_PEAK = CU * LANES_PER_CLK * CLK  # 39.32e12 int ops/s
+
+WORKLOAD_TEXT = {
+    1: "tiny: 1,000 states of one 8-vertex cube-mesh (weights 1-2), 0-4 busy, ring k=4",
+    2: ("batched: 65,536 server states over three topologies (cube-mesh all-1, cube-mesh half "
+        "weight-2, 6-vertex two-socket), 0-6 busy, ring/all-to-all/tree with k in 2..8"),
+    3: ("large: 256 16-vertex hypercube+chord topologies (weights 1-3), all free, ring and "
+        "all-to-all with k in 6..8 (1,536 queries, 2.98e11 embeddings)"),
+}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def nb_count(kind: int, k: int, p: int) -> int:
+    """Pattern neighbours of position p that precede it (ring/a2a/tree)."""
+    if p == 0:
+        return 0
+    if kind == 1:
+        return p
+    if kind == 0:
+        return 2 if (p == k - 1 and k >= 3) else 1
+    return 1
+
+
+def algorithmic_ops(wl) -> tuple[int, int]:
+    """(embeddings, algorithmic int ops) of one pass over the workload.
+
+    Every vertex placement of the shared-prefix search (a node at depth p+1,
+    of which there are F!/(F-p-1)! in ALL mode) costs 8 + 3B + |Nb(p)| integer
+    operations: candidate test, incremental AggBW adds over the |Nb(p)|
+    earlier pattern neighbours, B masked bit-plane popcounts with their
+    shift-adds for the PreservedBW term, the key update and the best-so-far
+    compare/select.  B = bits of the largest weight of the topology."""
+    q = wl.queries
+    bits = [max(1, int(W.max()).bit_length()) for W in wl.topologies]
+    n_of = [W.shape[0] for W in wl.topologies]
+    emb = ops = 0
+    cache = {}
+    for s, kind, k in zip(q["server"], q["kind"], q["k"]):
+        t = int(wl.server_topo[s])
+        F = n_of[t] - bin(int(wl.busy[s])).count("1")
+        key = (F, int(kind), int(k), bits[t])
+        if key not in cache:
+            if k > F:
+                cache[key] = (0, 0)
+            else:
+                e = math.perm(F, int(k))
+                o = sum(math.perm(F, p + 1) * (8 + 3 * bits[t] + nb_count(int(kind), int(k), p))
+                        for p in range(int(k)))
+                cache[key] = (e, o)
+        e, o = cache[key]
+        emb += e
+        ops += o
+    return emb, ops
+
+
+def cpu_baseline(wl, seconds: float = 8.0):
+    """The oracle (test infrastructure) timed on the host on a bounded sample."""
+    import oracle
+    oracle.build()
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    cores = max(1, min(16, cores))
+    # bounded sample: whole queries, at most ~5e8 embeddings per pass
+    sel, total = [], 0
+    emb_q = []
+    q = wl.queries
+    for i in range(wl.nq):
+        t = int(wl.server_topo[q["server"][i]])
+        F = wl.topologies[t].shape[0] - bin(int(wl.busy[q["server"][i]])).count("1")
+        e = math.perm(F, int(q["k"][i])) if q["k"][i] <= F else 0
+        emb_q.append(e)
+    order = np.argsort(np.arange(wl.nq) * 2654435761 % (1 << 32), kind="stable")
+    for i in order:
+        if total + emb_q[i] > 5e8 and sel:
+            continue
+        sel.append(int(i))
+        total += emb_q[i]
+    sub = wl.subset(np.sort(np.array(sel)))
+    done = passes = 0
+    t0 = time.perf_counter()
+    while True:
+        res = oracle.run_workload(sub, nthreads=cores)
+        done += int(res["count"].sum())
+        passes += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": "embeddings/s", "cores": cores, "kind": "oracle",
+            "sample": f"{len(sel)} of {wl.nq} queries ({total:.3g} embeddings) x {passes} "
+                      f"passes in {dt:.1f} s, static split by query over {cores} threads"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=0, help="timed steps (default: per config)")
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", type=int, default=2, choices=(1, 2, 3))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true", help="no HIP-event timing of the kernel")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "single-GPU build: every multi-GPU server exists only as a "
+                                   "topology graph in the input; run with --gpus 1"}))
+        sys.exit(2)
+
+    import torch
+    from paper_2110_03214_amd import binding as B
+    from paper_2110_03214_amd import synth
+
+    if not torch.cuda.is_available():
+        log("no GPU visible")
+        sys.exit(1)
+    steps = args.steps or {1: 200, 2: 200, 3: 3}[args.config]
+    wl = {1: synth.config1, 2: synth.config2, 3: synth.config3}[args.config]()
+    emb, ops = algorithmic_ops(wl)
+    log(f"[bench] config {args.config}: {wl.nq} queries, {emb:.4g} embeddings/step, "
+        f"{ops:.4g} algorithmic ops/step")
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    ctx = B.Context(0)
+    qh, ids = B.load_workload(ctx, wl)
+    qh["commit"] = 1
+    dq = torch.from_numpy(qh.view(np.uint8).copy()).to(dev)
+    dr = torch.zeros(wl.nq * B.RESULT_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+    handles = dr.view(torch.int64)[5:]  # alloc_handle: byte 40 of each 48-byte result
+
+    def step():
+        ctx.query_batch(dq, dr, stream=stream)
+        ctx.release(handles, stride=48, count=wl.nq, stream=stream)
+
+    for i in range(args.warmup):
+        step()
+        if i == 0:
+            torch.cuda.synchronize()
+            log("[bench] first step done")
+    torch.cuda.synchronize()
+    res = dr.cpu().numpy().view(B.RESULT_DTYPE)
+    assert int(res["count"].sum()) == emb, (int(res["count"].sum()), emb)
+    busy0 = ctx.get_busy(ids)
+    assert np.array_equal(busy0, wl.busy), "release did not restore the entry state"
+
+    if not args.no_profile:
+        ctx.profile(True)
+    ctx.reset_stats()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(steps):
+        ev[s][0].record(stream)
+        step()
+        ev[s][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lat = np.array([a.elapsed_time(b) for a, b in ev])
+    st = ctx.stats()
+    ctx.profile(False)
+    log(f"[bench] {steps} steps in {wall:.3f} s; enumerate {st['enum_ms'] / max(1, st['enum_launches']):.3f} ms avg")
+
+    ms_per_step = wall * 1e3 / steps
+    value = emb * steps / wall
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "embeddings/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic (seeded generator)",
+        "config": {"workload": WORKLOAD_TEXT[args.config], "config_id": args.config,
+                   "queries": wl.nq, "embeddings_per_step": emb,
+                   "topologies": len(wl.topologies), "parallelism": "single GPU"},
+        "queries_per_s": wl.nq * steps / wall,
+        "p50_ms": float(np.percentile(lat, 50)),
+        "p99_ms": float(np.percentile(lat, 99)),
+        "latency_scope": "per batch (every query of a batch completes together)",
+    }
+    if not args.no_profile and st["enum_launches"]:
+        avg_s = st["enum_ms"] / st["enum_launches"] / 1e3
+        achieved = ops / avg_s
+        out["roofline"] = {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_PEAK / 1e12,
+                           "unit": "Tops/s", "frac": achieved / ALU_PEAK, "traffic": None,
+                           "kernel": "k_enumerate", "kernel_ms": avg_s * 1e3,
+                           "ops_per_launch": ops}
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle")
+        out["cpu_baseline"] = cpu_baseline(wl)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

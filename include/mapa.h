@@ -1,0 +1,244 @@
+/*
+ * mapa.h -- C ABI of the MI355X-native MAPA allocation hot path.
+ *
+ * MAPA (Multi-Accelerator Pattern Allocation, SC'21) places a job's
+ * communication pattern on the free accelerators of a multi-GPU server:
+ *   - the server is a weighted hardware graph G whose vertices are
+ *     accelerators and whose edge label is the highest link bandwidth
+ *     between two of them (Sec. 3.2);
+ *   - the job is a small pattern graph P: a ring, an all-to-all or a binary
+ *     tree on k accelerators (Sec. 3.1);
+ *   - a match is a one-to-one map of V(P) into the free vertices of G
+ *     (Sec. 3.3, subgraph isomorphism);
+ *   - every match is scored with AggBW (Eq. 1) and PreservedBW (Eq. 3), and the
+ *     best one is selected (Alg. 1; the Greedy policy of Sec. 4 uses AggBW);
+ *   - allocation and release remove and add back vertices of G (Sec. 3.6).
+ *
+ * This library enumerates every match on the GPU, scores every match with
+ * exact integer arithmetic, and returns the match count, the best key and the
+ * chosen vertex set with a fixed tie-break.  All compute runs in hand-written
+ * HIP kernels for gfx950; there is no CPU fallback: without a GPU every
+ * compute entry point returns MAPA_ERR_NO_DEVICE after validating its
+ * arguments.
+ *
+ * Conventions
+ *   - Every function returns int32_t status: MAPA_OK (0) or a negative
+ *     MAPA_ERR_* code.  Nothing aborts.  mapa_last_error() gives a
+ *     human-readable message for the last error raised on the calling thread.
+ *   - On error, no device state changes and no output is written, except
+ *     where a function states otherwise.
+ *   - A context is used by one host thread at a time.  Calls on one context
+ *     are executed on the device in the order they are issued, whatever
+ *     streams they name.
+ *   - "Host pointer": ordinary CPU memory.  "Device pointer": memory from
+ *     hipMalloc (for example a torch tensor on a ROCm device), on the
+ *     context's device.
+ */
+#ifndef MAPA_H
+#define MAPA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- limits -------------------------------------------------------------- */
+#define MAPA_MAX_N 16     /* accelerators per server (hardware-graph vertices)  */
+#define MAPA_MAX_K 8      /* accelerators per job (pattern vertices)            */
+#define MAPA_MAX_AB 1024  /* largest key weight a, b                             */
+
+/* ---- status codes -------------------------------------------------------- */
+#define MAPA_OK 0
+#define MAPA_ERR_INVALID_ARG (-1)    /* malformed argument (see each function)  */
+#define MAPA_ERR_UNSUPPORTED (-2)    /* n > 16 or k > 8                         */
+#define MAPA_ERR_OOM (-3)            /* device or host allocation failed       */
+#define MAPA_ERR_DEVICE (-4)         /* a HIP call failed                      */
+#define MAPA_ERR_NOT_BUSY (-5)       /* release of a vertex that is not busy   */
+#define MAPA_ERR_UNKNOWN_SERVER (-6) /* server id not created                  */
+#define MAPA_ERR_ADMISSION (-7)      /* batch does not fit the enumeration buffer */
+#define MAPA_ERR_NO_DEVICE (-8)      /* context was created without a device   */
+#define MAPA_ERR_STATE (-9)          /* call not allowed in the current state  */
+
+/* ---- pattern kinds (Sec. 3.1) ----------------------------------------------
+ * Pattern vertex i is position i of the mapping tuple.
+ *   MAPA_RING:       k=1 no edge; k=2 the edge (0,1); k>=3 edges (i, i+1 mod k)
+ *   MAPA_ALL_TO_ALL: every pair i<j
+ *   MAPA_TREE:       binary heap, vertex i>0 joined to (i-1)/2                */
+#define MAPA_RING 0
+#define MAPA_ALL_TO_ALL 1
+#define MAPA_TREE 2
+
+/* ---- match modes (Sec. 3.2 / 3.3) -------------------------------------------
+ * MAPA_ALL_INJECTIVE: the hardware graph is taken as fully connected (every
+ *   pair of accelerators can talk through the host), so every injective map
+ *   of the pattern into the free vertices is a match.  A pair with weight 0
+ *   contributes 0 bandwidth.
+ * MAPA_LINKED: a match must map every pattern edge onto a pair with weight > 0
+ *   (subgraph isomorphism over the direct links; induced-ness not required). */
+#define MAPA_ALL_INJECTIVE 0
+#define MAPA_LINKED 1
+
+/* ---- per-query result status ------------------------------------------------ */
+#define MAPA_RES_OK 0        /* at least one match; best fields are valid         */
+#define MAPA_RES_NOFIT 1     /* no match (k > free vertices, or none linked)      */
+#define MAPA_RES_CONFLICT 2  /* asked to commit, but an earlier query of the same
+                                batch already owns this server's commit; result
+                                fields are valid, nothing was committed           */
+#define MAPA_RES_INVALID 3   /* malformed query (device-pointer batches only;
+                                host-pointer batches are rejected up front)       */
+
+/* ---- flags ------------------------------------------------------------------ */
+#define MAPA_DEVICE_PTRS 1u  /* array arguments are device pointers; the call is
+                                asynchronous on the given stream                 */
+
+typedef struct mapa_ctx mapa_ctx; /* opaque; owns all device memory it uses */
+
+/* One allocation query: place pattern (kind, k) on server `server`.
+ * 16 bytes, no padding. */
+typedef struct {
+  int32_t server;   /* server id from mapa_create_topology                      */
+  uint8_t kind;     /* MAPA_RING / MAPA_ALL_TO_ALL / MAPA_TREE                   */
+  uint8_t k;        /* pattern vertices, 1..8                                   */
+  uint8_t mode;     /* MAPA_ALL_INJECTIVE or MAPA_LINKED                        */
+  uint8_t commit;   /* 1: on MAPA_RES_OK mark the chosen vertices busy          */
+  int16_t a;        /* key = a*AggBW + b*PreservedBW, 0 <= a, b <= 1024.        */
+  int16_t b;        /*   (1,0): Greedy; (0,1): Alg. 1 insensitive branch;
+                         (1,1): both terms                                      */
+  int32_t reserved; /* must be 0                                                */
+} mapa_query;
+
+/* Result of one query.  48 bytes. */
+typedef struct {
+  int64_t count;        /* number of matches (every one was scored)              */
+  int32_t status;       /* MAPA_RES_*                                            */
+  int32_t key;          /* key of the chosen match; INT32_MIN if none            */
+  int32_t agg;          /* AggBW of the chosen match (Eq. 1)                     */
+  int32_t pres;         /* PreservedBW of the chosen match (Eq. 3)               */
+  uint32_t vertex_mask; /* bit v set iff accelerator v is chosen; 0 if none     */
+  uint8_t mapping[8];   /* mapping[i] = accelerator of pattern vertex i;
+                           0xFF beyond k or if none                              */
+  int32_t reserved;     /* 0                                                     */
+  int64_t alloc_handle; /* (server << 32) | vertex_mask if committed, else -1    */
+} mapa_result;
+
+/* Selection rule (Alg. 1, strict improvement): the chosen match has the
+ * largest key; among equal keys, the lexicographically smallest mapping tuple
+ * (mapping[0], ..., mapping[k-1]) wins.  PreservedBW of a match M is the total
+ * weight of pairs u<v of free vertices that M leaves unused (Eq. 3); busy
+ * vertices never contribute.  AggBW is the total weight of the pattern edges
+ * under the mapping (Eq. 1). */
+
+/* Message for the last error raised on the calling thread ("" if none). */
+const char *mapa_last_error(void);
+
+/* Create a context on HIP device `device` (>= 0), or a validation-only
+ * context with device = -1 (argument checks run; compute calls then return
+ * MAPA_ERR_NO_DEVICE).  enum_buffer_bytes sizes the prefix work-list of one
+ * in-flight batch (0 = default 256 MiB); a batch of nq queries needs at least
+ * 8 * (nq + 17408) bytes of it, else MAPA_ERR_ADMISSION.  *out receives the
+ * context. */
+int32_t mapa_ctx_create(int32_t device, size_t enum_buffer_bytes, mapa_ctx **out);
+
+/* Wait for outstanding work, free every device and host resource.  NULL-safe. */
+int32_t mapa_ctx_destroy(mapa_ctx *ctx);
+
+/* Register a hardware graph (Sec. 3.2) and create num_servers servers of it,
+ * all free.
+ *   n:  1..16 accelerators (n > 16: MAPA_ERR_UNSUPPORTED)
+ *   W:  host pointer, n*n uint8 row-major, W[i][j] = link weight of the pair,
+ *       symmetric, W[i][i] = 0, 0 = no direct link.  Copied; caller keeps it.
+ *   num_servers: >= 0.
+ * Outputs (host pointers, may be NULL): *topo_id = the topology index,
+ * *first_server = id of the first new server; the new servers are
+ * first_server .. first_server + num_servers - 1. */
+int32_t mapa_create_topology(mapa_ctx *ctx, int32_t n, const uint8_t *W, int32_t num_servers,
+                             int32_t *topo_id, int32_t *first_server);
+
+/* Overwrite the busy masks of `count` servers (bit v set = accelerator v is
+ * allocated; Sec. 3.6).  server_ids / busy_masks: host pointers (synchronous
+ * call, fully validated: unknown server -> MAPA_ERR_UNKNOWN_SERVER, a bit >= n
+ * -> MAPA_ERR_INVALID_ARG), or device pointers with MAPA_DEVICE_PTRS
+ * (asynchronous on hip_stream; entries with an unknown server are skipped and
+ * bits >= n are cleared). */
+int32_t mapa_set_busy(mapa_ctx *ctx, int32_t count, const int32_t *server_ids,
+                      const uint32_t *busy_masks, uint32_t flags, void *hip_stream);
+
+/* Read the busy masks of `count` servers into busy_out (host pointers;
+ * synchronous). */
+int32_t mapa_get_busy(mapa_ctx *ctx, int32_t count, const int32_t *server_ids,
+                      uint32_t *busy_out);
+
+/* Run nq allocation queries (Sec. 3.3-3.5) as one batch.
+ *   q:   nq queries; res: nq results (same index).
+ *   Host pointers (flags = 0): the batch is validated first (bad field ->
+ *     MAPA_ERR_INVALID_ARG, k > 8 -> MAPA_ERR_UNSUPPORTED, unknown server ->
+ *     MAPA_ERR_UNKNOWN_SERVER; nothing runs on error), then the call blocks
+ *     until res is filled.
+ *   MAPA_DEVICE_PTRS: q and res are device pointers; the call returns once
+ *     the work is queued on hip_stream (a hipStream_t, NULL = the default
+ *     stream); malformed queries get status MAPA_RES_INVALID.
+ * Semantics: every query is evaluated against the busy masks as they are when
+ * the batch starts.  Then commits are applied: for each server, only the first
+ * query of the batch (in array order) with commit = 1 may commit, and does so
+ * if its status is MAPA_RES_OK; later committing queries of that server get
+ * MAPA_RES_CONFLICT.  The caller owns q and res. */
+int32_t mapa_query_batch(mapa_ctx *ctx, const mapa_query *q, int32_t nq, mapa_result *res,
+                         uint32_t flags, void *hip_stream);
+
+/* Release committed allocations (Sec. 3.6: add the vertices back).
+ * Handles equal to -1 are ignored.
+ *   Host pointers: synchronous and all-or-nothing: if any handle names an
+ *     unknown server (MAPA_ERR_UNKNOWN_SERVER), a vertex that is not busy or
+ *     two handles overlap (MAPA_ERR_NOT_BUSY), nothing is released.
+ *   MAPA_DEVICE_PTRS: handles is a device array whose entries may be read at
+ *     any int64 stride: entry i is at byte offset i * stride_bytes
+ *     (stride_bytes = 8 for a plain array, 48 to release the alloc_handle
+ *     fields of a mapa_result array in place).  Asynchronous on hip_stream;
+ *     each handle is applied on its own: its vertices become free. */
+int32_t mapa_release(mapa_ctx *ctx, int32_t count, const int64_t *handles, int32_t stride_bytes,
+                     uint32_t flags, void *hip_stream);
+
+/* ---- tuning and measurement ---------------------------------------------- */
+
+typedef struct {
+  int32_t min_leaves_per_item;  /* smallest prefix-item size considered (64)     */
+  int32_t items_per_lane;       /* target items per resident GPU lane (4)        */
+  int32_t blocks_per_cu;        /* persistent enumeration blocks per CU (0=auto) */
+  int32_t threads_per_block;    /* 64..1024, multiple of 64 (256)                */
+} mapa_tuning;
+
+/* Read or replace the context's tuning knobs (NULL out/in allowed).  Results
+ * never depend on tuning; only speed does. */
+int32_t mapa_get_tuning(mapa_ctx *ctx, mapa_tuning *out);
+int32_t mapa_set_tuning(mapa_ctx *ctx, const mapa_tuning *in);
+
+typedef struct {
+  int64_t batches;         /* query batches run                                */
+  int64_t enum_launches;   /* enumeration-kernel launches timed                */
+  double enum_ms;          /* summed enumeration-kernel time (HIP events)      */
+  int64_t last_items;      /* prefix items of the last batch (0 if unknown)    */
+  int32_t last_split;      /* index of the split size chosen for the last batch */
+  int64_t self_check_failures; /* results whose key disagreed with the AggBW and
+                                  PreservedBW recomputed from the chosen mapping
+                                  (always 0 unless something is broken)        */
+  int32_t cu_count;        /* compute units of the device                      */
+  int32_t num_servers;
+  int32_t num_topologies;
+} mapa_stats;
+
+/* Enable (1) or disable (0) HIP-event timing of the enumeration kernel on the
+ * stream it is launched on.  mapa_get_stats synchronises the context and
+ * fills *out; mapa_reset_stats zeroes the counters. */
+int32_t mapa_profile(mapa_ctx *ctx, int32_t enable);
+int32_t mapa_get_stats(mapa_ctx *ctx, mapa_stats *out);
+int32_t mapa_reset_stats(mapa_ctx *ctx);
+
+/* Block until all work issued on the context has finished. */
+int32_t mapa_sync(mapa_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MAPA_H */

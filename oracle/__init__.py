@@ -161,6 +161,8 @@ def run_batch_semantics(wl, nthreads: int | None = None):
     for i in range(wl.nq):
         if not q["commit"][i]:
             continue
+        if res["status"][i] < 0:      # malformed query: never claims a server
+            continue
         s = int(q["server"][i])
         first = s not in seen
         seen.add(s)

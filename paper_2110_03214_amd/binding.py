@@ -1,0 +1,253 @@
+"""ctypes binding of ``libmapa.so`` (C ABI in ``include/mapa.h``).
+
+Argument marshalling only: every step of the allocation path runs in the HIP
+library.  There is no fallback; if the library is missing, loading raises.
+
+The raw functions keep the C names (``mapa_create_topology``,
+``mapa_set_busy``, ``mapa_query_batch``, ``mapa_release`` ...).  ``Context``
+wraps them for numpy host arrays and for device tensors (anything exposing
+``data_ptr()``, e.g. torch tensors on a ROCm device).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmapa.so")
+
+MAPA_OK = 0
+ERRORS = {
+    -1: "MAPA_ERR_INVALID_ARG", -2: "MAPA_ERR_UNSUPPORTED", -3: "MAPA_ERR_OOM",
+    -4: "MAPA_ERR_DEVICE", -5: "MAPA_ERR_NOT_BUSY", -6: "MAPA_ERR_UNKNOWN_SERVER",
+    -7: "MAPA_ERR_ADMISSION", -8: "MAPA_ERR_NO_DEVICE", -9: "MAPA_ERR_STATE",
+}
+ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_OOM, ERR_DEVICE, ERR_NOT_BUSY = -1, -2, -3, -4, -5
+ERR_UNKNOWN_SERVER, ERR_ADMISSION, ERR_NO_DEVICE, ERR_STATE = -6, -7, -8, -9
+RING, ALL_TO_ALL, TREE = 0, 1, 2
+ALL_INJECTIVE, LINKED = 0, 1
+RES_OK, RES_NOFIT, RES_CONFLICT, RES_INVALID = 0, 1, 2, 3
+DEVICE_PTRS = 1
+
+QUERY_DTYPE = np.dtype([("server", np.int32), ("kind", np.uint8), ("k", np.uint8),
+                        ("mode", np.uint8), ("commit", np.uint8), ("a", np.int16),
+                        ("b", np.int16), ("reserved", np.int32)])
+RESULT_DTYPE = np.dtype([("count", np.int64), ("status", np.int32), ("key", np.int32),
+                         ("agg", np.int32), ("pres", np.int32), ("vertex_mask", np.uint32),
+                         ("mapping", np.uint8, 8), ("reserved", np.int32),
+                         ("alloc_handle", np.int64)])
+assert QUERY_DTYPE.itemsize == 16 and RESULT_DTYPE.itemsize == 48
+assert RESULT_DTYPE.fields["alloc_handle"][1] == 40
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("min_leaves_per_item", ctypes.c_int32), ("items_per_lane", ctypes.c_int32),
+                ("blocks_per_cu", ctypes.c_int32), ("threads_per_block", ctypes.c_int32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("batches", ctypes.c_int64), ("enum_launches", ctypes.c_int64),
+                ("enum_ms", ctypes.c_double), ("last_items", ctypes.c_int64),
+                ("last_split", ctypes.c_int32), ("self_check_failures", ctypes.c_int64),
+                ("cu_count", ctypes.c_int32), ("num_servers", ctypes.c_int32),
+                ("num_topologies", ctypes.c_int32)]
+
+
+# every symbol include/mapa.h declares, with its ctypes signature
+_P, _I32, _U32, _SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_size_t
+SIGNATURES = {
+    "mapa_last_error": (ctypes.c_char_p, []),
+    "mapa_ctx_create": (_I32, [_I32, _SZ, ctypes.POINTER(_P)]),
+    "mapa_ctx_destroy": (_I32, [_P]),
+    "mapa_create_topology": (_I32, [_P, _I32, _P, _I32, _P, _P]),
+    "mapa_set_busy": (_I32, [_P, _I32, _P, _P, _U32, _P]),
+    "mapa_get_busy": (_I32, [_P, _I32, _P, _P]),
+    "mapa_query_batch": (_I32, [_P, _P, _I32, _P, _U32, _P]),
+    "mapa_release": (_I32, [_P, _I32, _P, _I32, _U32, _P]),
+    "mapa_get_tuning": (_I32, [_P, ctypes.POINTER(Tuning)]),
+    "mapa_set_tuning": (_I32, [_P, ctypes.POINTER(Tuning)]),
+    "mapa_profile": (_I32, [_P, _I32]),
+    "mapa_get_stats": (_I32, [_P, ctypes.POINTER(Stats)]),
+    "mapa_reset_stats": (_I32, [_P]),
+    "mapa_sync": (_I32, [_P]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libmapa.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2110_03214_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+class MapaError(RuntimeError):
+    def __init__(self, code, where):
+        msg = lib().mapa_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def check(code, where):
+    if code != MAPA_OK:
+        raise MapaError(code, where)
+    return code
+
+
+def _ptr(x):
+    """Device pointer of a tensor-like, or host pointer of a numpy array."""
+    if x is None:
+        return None
+    if hasattr(x, "data_ptr"):
+        return ctypes.c_void_p(x.data_ptr())
+    return ctypes.c_void_p(x.ctypes.data)
+
+
+def pack_queries(server, kind, k, mode=ALL_INJECTIVE, commit=0, a=1, b=1) -> np.ndarray:
+    q = np.zeros(len(server), dtype=QUERY_DTYPE)
+    q["server"], q["kind"], q["k"], q["mode"] = server, kind, k, mode
+    q["commit"], q["a"], q["b"] = commit, a, b
+    return q
+
+
+class Context:
+    """One device context: topologies, device-resident server busy masks,
+    batch workspace and enumeration buffer."""
+
+    def __init__(self, device: int = 0, enum_buffer_bytes: int = 0):
+        h = ctypes.c_void_p()
+        check(lib().mapa_ctx_create(int(device), int(enum_buffer_bytes), ctypes.byref(h)),
+              "mapa_ctx_create")
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if self.h:
+            lib().mapa_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- state ---------------------------------------------------------------
+    def create_topology(self, W, num_servers: int):
+        W = np.ascontiguousarray(np.asarray(W, dtype=np.uint8))
+        n = W.shape[0]
+        tid, first = ctypes.c_int32(), ctypes.c_int32()
+        check(lib().mapa_create_topology(self.h, n, W.ctypes.data, int(num_servers),
+                                         ctypes.byref(tid), ctypes.byref(first)),
+              "mapa_create_topology")
+        return tid.value, first.value
+
+    def load_servers(self, topologies, server_topo) -> np.ndarray:
+        """Create one server per entry of server_topo; returns the library's
+        server id of each (servers are created grouped by topology)."""
+        server_topo = np.asarray(server_topo)
+        ids = np.empty(len(server_topo), dtype=np.int32)
+        for t, W in enumerate(topologies):
+            idx = np.nonzero(server_topo == t)[0]
+            _, first = self.create_topology(W, len(idx))
+            ids[idx] = first + np.arange(len(idx), dtype=np.int32)
+        return ids
+
+    def set_busy(self, server_ids, masks, stream=None):
+        if hasattr(server_ids, "data_ptr"):
+            check(lib().mapa_set_busy(self.h, int(server_ids.numel()), _ptr(server_ids),
+                                      _ptr(masks), DEVICE_PTRS, _stream(stream)), "mapa_set_busy")
+            return
+        ids = np.ascontiguousarray(server_ids, dtype=np.int32)
+        m = np.ascontiguousarray(masks, dtype=np.uint32)
+        check(lib().mapa_set_busy(self.h, len(ids), _ptr(ids), _ptr(m), 0, None), "mapa_set_busy")
+
+    def get_busy(self, server_ids) -> np.ndarray:
+        ids = np.ascontiguousarray(server_ids, dtype=np.int32)
+        out = np.zeros(len(ids), dtype=np.uint32)
+        check(lib().mapa_get_busy(self.h, len(ids), _ptr(ids), _ptr(out)), "mapa_get_busy")
+        return out
+
+    # -- queries -------------------------------------------------------------
+    def query_batch(self, queries, results=None, stream=None):
+        """Host numpy QUERY_DTYPE array -> numpy RESULT_DTYPE array (blocking),
+        or device byte tensors (nq*16 and nq*48 bytes) -> asynchronous."""
+        if hasattr(queries, "data_ptr"):
+            nq = queries.numel() * queries.element_size() // QUERY_DTYPE.itemsize
+            check(lib().mapa_query_batch(self.h, _ptr(queries), int(nq), _ptr(results),
+                                         DEVICE_PTRS, _stream(stream)), "mapa_query_batch")
+            return results
+        q = np.ascontiguousarray(queries, dtype=QUERY_DTYPE)
+        res = np.zeros(len(q), dtype=RESULT_DTYPE) if results is None else results
+        check(lib().mapa_query_batch(self.h, _ptr(q), len(q), _ptr(res), 0, None),
+              "mapa_query_batch")
+        return res
+
+    def release(self, handles, stride: int = 8, count: int | None = None, stream=None):
+        if hasattr(handles, "data_ptr"):
+            n = count if count is not None else handles.numel() * handles.element_size() // stride
+            check(lib().mapa_release(self.h, int(n), _ptr(handles), int(stride), DEVICE_PTRS,
+                                     _stream(stream)), "mapa_release")
+            return
+        h = np.ascontiguousarray(handles, dtype=np.int64)
+        check(lib().mapa_release(self.h, len(h), _ptr(h), 8, 0, None), "mapa_release")
+
+    # -- tuning / stats ----------------------------------------------------------
+    def tuning(self) -> Tuning:
+        t = Tuning()
+        check(lib().mapa_get_tuning(self.h, ctypes.byref(t)), "mapa_get_tuning")
+        return t
+
+    def set_tuning(self, **kw):
+        t = self.tuning()
+        for key, v in kw.items():
+            setattr(t, key, int(v))
+        check(lib().mapa_set_tuning(self.h, ctypes.byref(t)), "mapa_set_tuning")
+
+    def profile(self, on: bool = True):
+        check(lib().mapa_profile(self.h, 1 if on else 0), "mapa_profile")
+
+    def stats(self) -> dict:
+        s = Stats()
+        check(lib().mapa_get_stats(self.h, ctypes.byref(s)), "mapa_get_stats")
+        return {name: getattr(s, name) for name, _ in Stats._fields_}
+
+    def reset_stats(self):
+        check(lib().mapa_reset_stats(self.h), "mapa_reset_stats")
+
+    def sync(self):
+        check(lib().mapa_sync(self.h), "mapa_sync")
+
+
+def _stream(stream):
+    if stream is None:
+        return None
+    if hasattr(stream, "cuda_stream"):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+def load_workload(ctx: Context, wl):
+    """Create a synth.Workload's servers in ctx, set their busy masks and
+    return its queries translated to library server ids."""
+    ids = ctx.load_servers(wl.topologies, wl.server_topo)
+    ctx.set_busy(ids, wl.busy)
+    q = wl.queries
+    return pack_queries(ids[q["server"]], q["kind"], q["k"], q["mode"], q["commit"], q["a"], q["b"]), ids

@@ -1,0 +1,731 @@
+// Host core of the MAPA allocation library: context, topology registry,
+// device-resident server state, argument validation and the batch driver.
+// Every compute step runs in kernels.hip; this file only checks arguments,
+// manages memory and enqueues work.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "mapa.h"
+#include "mapa_internal.h"
+
+using namespace mapa;
+
+namespace {
+
+thread_local std::string g_err;
+
+int32_t fail(int32_t code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess) return fail(MAPA_ERR_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr size_t kDefaultEnumBytes = 256ull << 20;
+
+// Canonical pattern graphs (Sec. 3.1), as back-neighbour position masks:
+// nb[kind][k][p] = { j < p : (j, p) is a pattern edge }.
+Tables build_tables() {
+  Tables t;
+  std::memset(&t, 0, sizeof t);
+  for (int k = 1; k <= kMaxK; ++k) {
+    for (int p = 1; p < k; ++p) {
+      // ring: consecutive positions, closed when k >= 3; k = 2 is one edge
+      uint8_t ring = (uint8_t)(1u << (p - 1));
+      if (p == k - 1 && k >= 3) ring |= 1u;
+      t.nb[MAPA_RING][k][p] = ring;
+      t.nb[MAPA_ALL_TO_ALL][k][p] = (uint8_t)((1u << p) - 1u);
+      t.nb[MAPA_TREE][k][p] = (uint8_t)(1u << ((p - 1) / 2));
+    }
+  }
+  // buckets laid out largest items first (longest-processing-time order)
+  std::vector<std::pair<double, int>> order;
+  for (int b = 0; b < kNumBuckets; ++b) {
+    const int Fp = b % kFp, L = (b / kFp) % kMaxK + 1;
+    double leaves = 0;
+    if (Fp >= L) {
+      leaves = 1;
+      for (int i = 0; i < L; ++i) leaves *= (Fp - i);
+    }
+    order.push_back({-leaves, b});
+  }
+  std::sort(order.begin(), order.end());
+  for (int r = 0; r < kNumBuckets; ++r) t.rank_bucket[r] = (uint16_t)order[r].second;
+  return t;
+}
+
+int weight_class(const uint8_t *W, int n) {
+  int mx = 0;
+  for (int i = 0; i < n * n; ++i) mx = std::max(mx, (int)W[i]);
+  return mx <= 3 ? 1 : mx <= 15 ? 2 : 4;
+}
+
+template <class T>
+hipError_t dev_alloc(T **p, size_t count) {
+  *p = nullptr;
+  if (count == 0) return hipSuccess;
+  return hipMalloc((void **)p, count * sizeof(T));
+}
+
+template <class T>
+void dev_free(T *&p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+struct ProfEvents {
+  hipEvent_t start, stop;
+};
+
+}  // namespace
+
+struct mapa_ctx {
+  int device = -1;
+  bool has_device = false;
+  int cu_count = 0;
+  hipStream_t internal = nullptr;
+  hipEvent_t last = nullptr;  // completion of the last issued call
+
+  // topologies (host copy is authoritative; device copies are derived)
+  std::vector<int32_t> topo_n;
+  std::vector<std::array<uint8_t, 256>> topo_W;  // 16x16 padded
+  int wpr = 1;
+  int32_t *d_topo_n = nullptr;
+  uint8_t *d_topo_W = nullptr;
+  uint32_t *d_rows = nullptr;
+  size_t cap_topos = 0;
+
+  // servers
+  std::vector<int32_t> server_topo;  // host mirror, immutable per server
+  int32_t *d_server_topo = nullptr;
+  uint32_t *d_busy = nullptr;
+  unsigned long long *d_commit_slot = nullptr;
+  size_t cap_servers = 0;
+  uint32_t gen = 0;
+
+  // batch workspace
+  size_t cap_q = 0;
+  Plan *d_plan = nullptr;
+  unsigned long long *d_acc_count = nullptr, *d_acc_best = nullptr;
+  mapa_query *d_q = nullptr;
+  mapa_result *d_res = nullptr;
+  uint2 *d_items = nullptr;
+  unsigned long long cap_items = 0;
+  Counters *d_ctr = nullptr;
+  // small scratch for host-pointer state calls
+  int32_t *d_ids = nullptr;
+  uint32_t *d_masks = nullptr;
+  int64_t *d_handles = nullptr;
+  uint32_t *d_flag = nullptr;
+  size_t cap_small = 0;
+
+  mapa_tuning tuning{64, 4, 0, 256};
+  bool profile = false;
+  std::vector<ProfEvents> prof;
+  double prof_ms = 0;
+  int64_t prof_launches = 0;
+  int64_t batches = 0;
+};
+
+namespace {
+
+hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Order this call after every earlier call of the context.
+hipError_t begin_call(mapa_ctx *c, hipStream_t s) { return hipStreamWaitEvent(s, c->last, 0); }
+hipError_t end_call(mapa_ctx *c, hipStream_t s) { return hipEventRecord(c->last, s); }
+
+int32_t sync_ctx(mapa_ctx *c) {
+  if (!c->has_device) return MAPA_OK;
+  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(hipEventSynchronize(c->last));
+  return MAPA_OK;
+}
+
+void build_rows(const uint8_t *W16, int n, int wpr, uint32_t *out /* 16*wpr */) {
+  for (int v = 0; v < 16; ++v)
+    for (int w = 0; w < wpr; ++w) {
+      uint32_t lo = 0, hi = 0;
+      if (v < n)
+        for (int u = 0; u < n; ++u) {
+          const uint8_t x = W16[v * 16 + u];
+          lo |= ((x >> (2 * w)) & 1u) << u;
+          hi |= ((x >> (2 * w + 1)) & 1u) << u;
+        }
+      out[v * wpr + w] = lo | (hi << 16);
+    }
+}
+
+// Re-upload every device copy of the topology tables (after growth or a
+// weight-class change).  Caller has synchronised the context.
+int32_t upload_topologies(mapa_ctx *c) {
+  const size_t T = c->topo_n.size();
+  if (T > c->cap_topos) {
+    size_t cap = std::max<size_t>(16, c->cap_topos);
+    while (cap < T) cap *= 2;
+    dev_free(c->d_topo_n);
+    dev_free(c->d_topo_W);
+    dev_free(c->d_rows);
+    c->cap_topos = 0;
+    if (dev_alloc(&c->d_topo_n, cap) != hipSuccess || dev_alloc(&c->d_topo_W, cap * 256) != hipSuccess ||
+        dev_alloc(&c->d_rows, cap * 16 * 4) != hipSuccess)
+      return fail(MAPA_ERR_OOM, "topology tables: device allocation failed");
+    c->cap_topos = cap;
+  }
+  std::vector<uint8_t> W(T * 256);
+  std::vector<uint32_t> rows(T * 16 * c->wpr);
+  for (size_t t = 0; t < T; ++t) {
+    std::memcpy(&W[t * 256], c->topo_W[t].data(), 256);
+    build_rows(c->topo_W[t].data(), c->topo_n[t], c->wpr, &rows[t * 16 * c->wpr]);
+  }
+  HIPCHK(hipMemcpy(c->d_topo_n, c->topo_n.data(), T * sizeof(int32_t), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(c->d_topo_W, W.data(), W.size(), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(c->d_rows, rows.data(), rows.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+  return MAPA_OK;
+}
+
+int32_t grow_servers(mapa_ctx *c, size_t need) {
+  if (need <= c->cap_servers) return MAPA_OK;
+  size_t cap = std::max<size_t>(1024, c->cap_servers);
+  while (cap < need) cap *= 2;
+  int32_t *st = nullptr;
+  uint32_t *busy = nullptr;
+  unsigned long long *slot = nullptr;
+  if (dev_alloc(&st, cap) != hipSuccess || dev_alloc(&busy, cap) != hipSuccess ||
+      dev_alloc(&slot, cap) != hipSuccess) {
+    dev_free(st);
+    dev_free(busy);
+    dev_free(slot);
+    return fail(MAPA_ERR_OOM, "server tables: device allocation failed");
+  }
+  HIPCHK(hipMemset(busy, 0, cap * sizeof(uint32_t)));
+  HIPCHK(hipMemset(st, 0, cap * sizeof(int32_t)));
+  HIPCHK(hipMemset(slot, 0xFF, cap * sizeof(unsigned long long)));
+  if (c->cap_servers) {
+    HIPCHK(hipMemcpy(st, c->d_server_topo, c->cap_servers * sizeof(int32_t), hipMemcpyDeviceToDevice));
+    HIPCHK(hipMemcpy(busy, c->d_busy, c->cap_servers * sizeof(uint32_t), hipMemcpyDeviceToDevice));
+    HIPCHK(hipMemcpy(slot, c->d_commit_slot, c->cap_servers * sizeof(unsigned long long),
+                     hipMemcpyDeviceToDevice));
+  }
+  dev_free(c->d_server_topo);
+  dev_free(c->d_busy);
+  dev_free(c->d_commit_slot);
+  c->d_server_topo = st;
+  c->d_busy = busy;
+  c->d_commit_slot = slot;
+  c->cap_servers = cap;
+  return MAPA_OK;
+}
+
+int32_t ensure_batch_capacity(mapa_ctx *c, size_t nq) {
+  if (nq <= c->cap_q) return MAPA_OK;
+  int32_t rc = sync_ctx(c);
+  if (rc) return rc;
+  size_t cap = std::max<size_t>(1024, c->cap_q);
+  while (cap < nq) cap *= 2;
+  dev_free(c->d_plan);
+  dev_free(c->d_acc_count);
+  dev_free(c->d_acc_best);
+  dev_free(c->d_q);
+  dev_free(c->d_res);
+  c->cap_q = 0;
+  if (dev_alloc(&c->d_plan, cap) != hipSuccess || dev_alloc(&c->d_acc_count, cap) != hipSuccess ||
+      dev_alloc(&c->d_acc_best, cap) != hipSuccess || dev_alloc(&c->d_q, cap) != hipSuccess ||
+      dev_alloc(&c->d_res, cap) != hipSuccess)
+    return fail(MAPA_ERR_OOM, "batch workspace for %zu queries: device allocation failed", nq);
+  c->cap_q = cap;
+  return MAPA_OK;
+}
+
+int32_t ensure_small(mapa_ctx *c, size_t n) {
+  if (n <= c->cap_small) return MAPA_OK;
+  int32_t rc = sync_ctx(c);
+  if (rc) return rc;
+  size_t cap = std::max<size_t>(1024, c->cap_small);
+  while (cap < n) cap *= 2;
+  dev_free(c->d_ids);
+  dev_free(c->d_masks);
+  dev_free(c->d_handles);
+  c->cap_small = 0;
+  if (dev_alloc(&c->d_ids, cap) != hipSuccess || dev_alloc(&c->d_masks, cap) != hipSuccess ||
+      dev_alloc(&c->d_handles, cap) != hipSuccess)
+    return fail(MAPA_ERR_OOM, "state scratch: device allocation failed");
+  c->cap_small = cap;
+  return MAPA_OK;
+}
+
+int32_t validate_query(const mapa_ctx *c, const mapa_query &q, int32_t i) {
+  if (q.server < 0 || (size_t)q.server >= c->server_topo.size())
+    return fail(MAPA_ERR_UNKNOWN_SERVER, "query %d: unknown server %d", i, q.server);
+  if (q.k > kMaxK) return fail(MAPA_ERR_UNSUPPORTED, "query %d: k=%d > %d", i, q.k, kMaxK);
+  if (q.k < 1) return fail(MAPA_ERR_INVALID_ARG, "query %d: k=%d < 1", i, q.k);
+  if (q.kind > 2) return fail(MAPA_ERR_INVALID_ARG, "query %d: kind=%d", i, q.kind);
+  if (q.mode > 1) return fail(MAPA_ERR_INVALID_ARG, "query %d: mode=%d", i, q.mode);
+  if (q.commit > 1) return fail(MAPA_ERR_INVALID_ARG, "query %d: commit=%d", i, q.commit);
+  if (q.a < 0 || q.a > MAPA_MAX_AB || q.b < 0 || q.b > MAPA_MAX_AB)
+    return fail(MAPA_ERR_INVALID_ARG, "query %d: key weights (%d,%d) outside 0..%d", i, q.a, q.b,
+                MAPA_MAX_AB);
+  if (q.reserved != 0) return fail(MAPA_ERR_INVALID_ARG, "query %d: reserved != 0", i);
+  return MAPA_OK;
+}
+
+void fill_args(mapa_ctx *c, BatchArgs &a) {
+  a.plan = c->d_plan;
+  a.acc_count = c->d_acc_count;
+  a.acc_best = c->d_acc_best;
+  a.items = c->d_items;
+  a.cap_items = c->cap_items;
+  a.ctr = c->d_ctr;
+  a.server_topo = c->d_server_topo;
+  a.busy = c->d_busy;
+  a.commit_slot = c->d_commit_slot;
+  a.nservers = (int32_t)c->server_topo.size();
+  a.topo_n = c->d_topo_n;
+  a.topo_W = c->d_topo_W;
+  a.rows = c->d_rows;
+  a.ntopo = (int32_t)c->topo_n.size();
+  a.wpr = c->wpr;
+  a.gen = c->gen;
+  a.min_leaves = std::max(1, c->tuning.min_leaves_per_item);
+  const int threads = c->tuning.threads_per_block;
+  const size_t lds_bytes = (size_t)a.ntopo * 16 * c->wpr * sizeof(uint32_t);
+  a.rows_in_lds = lds_bytes <= 48 * 1024 ? 1 : 0;
+  int per_cu = c->tuning.blocks_per_cu;
+  if (per_cu <= 0) per_cu = enumerate_occupancy(c->wpr, a.rows_in_lds, threads, lds_bytes);
+  if (per_cu <= 0) per_cu = 4;
+  a.enum_blocks = std::max(1, c->cu_count) * per_cu;
+  a.enum_threads = threads;
+  const unsigned long long lanes = (unsigned long long)std::max(1, c->cu_count) * per_cu * threads;
+  a.target_items = std::max<unsigned long long>(1, lanes * (unsigned long long)std::max(1, c->tuning.items_per_lane));
+}
+
+}  // namespace
+
+// =================================================================== ABI
+
+extern "C" {
+
+const char *mapa_last_error(void) { return g_err.c_str(); }
+
+int32_t mapa_ctx_create(int32_t device, size_t enum_buffer_bytes, mapa_ctx **out) {
+  if (!out) return fail(MAPA_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  mapa_ctx *c = new (std::nothrow) mapa_ctx();
+  if (!c) return fail(MAPA_ERR_OOM, "context allocation failed");
+  if (device < 0) {  // validation-only context
+    *out = c;
+    return MAPA_OK;
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device >= ndev) {
+    delete c;
+    return fail(MAPA_ERR_NO_DEVICE, "HIP device %d not available (%d devices)", device, ndev);
+  }
+  c->device = device;
+  c->has_device = true;
+  auto bail = [&](int32_t rc) {
+    mapa_ctx_destroy(c);
+    return rc;
+  };
+  if (hipSetDevice(device) != hipSuccess) return bail(fail(MAPA_ERR_DEVICE, "hipSetDevice failed"));
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess)
+    return bail(fail(MAPA_ERR_DEVICE, "hipGetDeviceProperties failed"));
+  c->cu_count = prop.multiProcessorCount;
+  if (hipStreamCreateWithFlags(&c->internal, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->last, hipEventDisableTiming) != hipSuccess)
+    return bail(fail(MAPA_ERR_DEVICE, "stream/event creation failed"));
+  if (hipEventRecord(c->last, c->internal) != hipSuccess)
+    return bail(fail(MAPA_ERR_DEVICE, "hipEventRecord failed"));
+  const Tables t = build_tables();
+  if (upload_tables(t) != hipSuccess) return bail(fail(MAPA_ERR_DEVICE, "table upload failed"));
+  size_t bytes = enum_buffer_bytes ? enum_buffer_bytes : kDefaultEnumBytes;
+  unsigned long long items = bytes / sizeof(uint2);
+  items = std::min<unsigned long long>(items, 1ull << 31);
+  if (items < (unsigned long long)kPadReserve + 1024)
+    return bail(fail(MAPA_ERR_INVALID_ARG, "enum_buffer_bytes %zu too small (need >= %llu)", bytes,
+                     (unsigned long long)(kPadReserve + 1024) * sizeof(uint2)));
+  if (dev_alloc(&c->d_items, items) != hipSuccess || dev_alloc(&c->d_ctr, 1) != hipSuccess ||
+      dev_alloc(&c->d_flag, 1) != hipSuccess)
+    return bail(fail(MAPA_ERR_OOM, "enumeration buffer of %zu bytes: allocation failed", bytes));
+  c->cap_items = items;
+  if (hipMemset(c->d_ctr, 0, sizeof(Counters)) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
+    return bail(fail(MAPA_ERR_DEVICE, "counter init failed"));
+  *out = c;
+  return MAPA_OK;
+}
+
+int32_t mapa_ctx_destroy(mapa_ctx *c) {
+  if (!c) return MAPA_OK;
+  if (c->has_device) {
+    (void)hipSetDevice(c->device);
+    if (c->last) (void)hipEventSynchronize(c->last);
+    (void)hipDeviceSynchronize();
+    for (auto &e : c->prof) {
+      (void)hipEventDestroy(e.start);
+      (void)hipEventDestroy(e.stop);
+    }
+    dev_free(c->d_topo_n);
+    dev_free(c->d_topo_W);
+    dev_free(c->d_rows);
+    dev_free(c->d_server_topo);
+    dev_free(c->d_busy);
+    dev_free(c->d_commit_slot);
+    dev_free(c->d_plan);
+    dev_free(c->d_acc_count);
+    dev_free(c->d_acc_best);
+    dev_free(c->d_q);
+    dev_free(c->d_res);
+    dev_free(c->d_items);
+    dev_free(c->d_ctr);
+    dev_free(c->d_ids);
+    dev_free(c->d_masks);
+    dev_free(c->d_handles);
+    dev_free(c->d_flag);
+    if (c->last) (void)hipEventDestroy(c->last);
+    if (c->internal) (void)hipStreamDestroy(c->internal);
+  }
+  delete c;
+  return MAPA_OK;
+}
+
+int32_t mapa_create_topology(mapa_ctx *c, int32_t n, const uint8_t *W, int32_t num_servers,
+                             int32_t *topo_id, int32_t *first_server) {
+  if (!c) return fail(MAPA_ERR_INVALID_ARG, "ctx is NULL");
+  if (n < 1) return fail(MAPA_ERR_INVALID_ARG, "n=%d < 1", n);
+  if (n > kMaxN) return fail(MAPA_ERR_UNSUPPORTED, "n=%d > %d", n, kMaxN);
+  if (!W) return fail(MAPA_ERR_INVALID_ARG, "W is NULL");
+  if (num_servers < 0) return fail(MAPA_ERR_INVALID_ARG, "num_servers=%d < 0", num_servers);
+  for (int i = 0; i < n; ++i) {
+    if (W[i * n + i] != 0) return fail(MAPA_ERR_INVALID_ARG, "W[%d][%d] != 0", i, i);
+    for (int j = 0; j < n; ++j)
+      if (W[i * n + j] != W[j * n + i])
+        return fail(MAPA_ERR_INVALID_ARG, "W not symmetric at (%d,%d)", i, j);
+  }
+  if (c->topo_n.size() >= 65535) return fail(MAPA_ERR_UNSUPPORTED, "too many topologies");
+  if (c->server_topo.size() + (size_t)num_servers > (size_t)INT32_MAX)
+    return fail(MAPA_ERR_UNSUPPORTED, "too many servers");
+  std::array<uint8_t, 256> w16{};
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) w16[i * 16 + j] = W[i * n + j];
+  const int32_t tid = (int32_t)c->topo_n.size();
+  const int32_t first = (int32_t)c->server_topo.size();
+  if (c->has_device) {
+    int32_t rc = sync_ctx(c);
+    if (rc) return rc;
+    HIPCHK(hipSetDevice(c->device));
+    c->topo_n.push_back(n);
+    c->topo_W.push_back(w16);
+    c->wpr = std::max(c->wpr, weight_class(W, n));
+    rc = upload_topologies(c);
+    if (!rc) rc = grow_servers(c, first + (size_t)num_servers);
+    if (rc) {
+      c->topo_n.pop_back();
+      c->topo_W.pop_back();
+      return rc;
+    }
+    if (num_servers > 0) {
+      std::vector<int32_t> ids(num_servers, tid);
+      HIPCHK(hipMemcpy(c->d_server_topo + first, ids.data(), num_servers * sizeof(int32_t),
+                       hipMemcpyHostToDevice));
+      HIPCHK(hipMemset(c->d_busy + first, 0, num_servers * sizeof(uint32_t)));
+    }
+  } else {
+    c->topo_n.push_back(n);
+    c->topo_W.push_back(w16);
+  }
+  c->server_topo.insert(c->server_topo.end(), (size_t)num_servers, tid);
+  if (topo_id) *topo_id = tid;
+  if (first_server) *first_server = first;
+  return MAPA_OK;
+}
+
+int32_t mapa_set_busy(mapa_ctx *c, int32_t count, const int32_t *ids, const uint32_t *masks,
+                      uint32_t flags, void *stream) {
+  if (!c) return fail(MAPA_ERR_INVALID_ARG, "ctx is NULL");
+  if (count < 0) return fail(MAPA_ERR_INVALID_ARG, "count < 0");
+  if (count == 0) return MAPA_OK;
+  if (!ids || !masks) return fail(MAPA_ERR_INVALID_ARG, "NULL array");
+  const bool dev = flags & MAPA_DEVICE_PTRS;
+  if (!dev) {
+    for (int32_t i = 0; i < count; ++i) {
+      const int32_t s = ids[i];
+      if (s < 0 || (size_t)s >= c->server_topo.size())
+        return fail(MAPA_ERR_UNKNOWN_SERVER, "entry %d: unknown server %d", i, s);
+      const int n = c->topo_n[c->server_topo[s]];
+      if (n < 32 && (masks[i] >> n) != 0)
+        return fail(MAPA_ERR_INVALID_ARG, "entry %d: busy bit >= n=%d", i, n);
+    }
+  }
+  if (!c->has_device) return fail(MAPA_ERR_NO_DEVICE, "context has no device");
+  HIPCHK(hipSetDevice(c->device));
+  hipStream_t s = as_stream(stream);
+  const int32_t *d_ids = ids;
+  const uint32_t *d_masks = masks;
+  if (!dev) {
+    int32_t rc = ensure_small(c, count);
+    if (rc) return rc;
+    HIPCHK(begin_call(c, s));
+    HIPCHK(hipMemcpyAsync(c->d_ids, ids, count * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c->d_masks, masks, count * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+    d_ids = c->d_ids;
+    d_masks = c->d_masks;
+  } else {
+    HIPCHK(begin_call(c, s));
+  }
+  HIPCHK(launch_set_busy(d_ids, d_masks, count, (int32_t)c->server_topo.size(), c->d_server_topo,
+                         c->d_topo_n, c->d_busy, s));
+  HIPCHK(end_call(c, s));
+  if (!dev) HIPCHK(hipStreamSynchronize(s));
+  return MAPA_OK;
+}
+
+int32_t mapa_get_busy(mapa_ctx *c, int32_t count, const int32_t *ids, uint32_t *out) {
+  if (!c) return fail(MAPA_ERR_INVALID_ARG, "ctx is NULL");
+  if (count < 0) return fail(MAPA_ERR_INVALID_ARG, "count < 0");
+  if (count == 0) return MAPA_OK;
+  if (!ids || !out) return fail(MAPA_ERR_INVALID_ARG, "NULL array");
+  for (int32_t i = 0; i < count; ++i)
+    if (ids[i] < 0 || (size_t)ids[i] >= c->server_topo.size())
+      return fail(MAPA_ERR_UNKNOWN_SERVER, "entry %d: unknown server %d", i, ids[i]);
+  if (!c->has_device) return fail(MAPA_ERR_NO_DEVICE, "context has no device");
+  HIPCHK(hipSetDevice(c->device));
+  int32_t rc = ensure_small(c, count);
+  if (rc) return rc;
+  hipStream_t s = c->internal;
+  HIPCHK(begin_call(c, s));
+  HIPCHK(hipMemcpyAsync(c->d_ids, ids, count * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  HIPCHK(launch_get_busy(c->d_ids, count, c->d_busy, c->d_masks, s));
+  HIPCHK(hipMemcpyAsync(out, c->d_masks, count * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(end_call(c, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return MAPA_OK;
+}
+
+int32_t mapa_query_batch(mapa_ctx *c, const mapa_query *q, int32_t nq, mapa_result *res,
+                         uint32_t flags, void *stream) {
+  if (!c) return fail(MAPA_ERR_INVALID_ARG, "ctx is NULL");
+  if (nq < 0) return fail(MAPA_ERR_INVALID_ARG, "nq < 0");
+  if (nq == 0) return MAPA_OK;
+  if (!q || !res) return fail(MAPA_ERR_INVALID_ARG, "NULL array");
+  const bool dev = flags & MAPA_DEVICE_PTRS;
+  if (!dev)
+    for (int32_t i = 0; i < nq; ++i) {
+      int32_t rc = validate_query(c, q[i], i);
+      if (rc) return rc;
+    }
+  if (!c->has_device) return fail(MAPA_ERR_NO_DEVICE, "context has no device");
+  if ((unsigned long long)nq + kPadReserve > c->cap_items)
+    return fail(MAPA_ERR_ADMISSION, "batch of %d queries exceeds the enumeration buffer (%llu items)",
+                nq, c->cap_items);
+  if (c->server_topo.empty()) return fail(MAPA_ERR_UNKNOWN_SERVER, "no servers created");
+  HIPCHK(hipSetDevice(c->device));
+  int32_t rc = ensure_batch_capacity(c, nq);
+  if (rc) return rc;
+  hipStream_t s = as_stream(stream);
+  if (++c->gen == 0) {  // commit tags wrapped: reset every claim
+    HIPCHK(hipEventSynchronize(c->last));
+    HIPCHK(hipMemset(c->d_commit_slot, 0xFF, c->cap_servers * sizeof(unsigned long long)));
+    HIPCHK(hipDeviceSynchronize());
+    c->gen = 1;
+  }
+  BatchArgs a;
+  std::memset(&a, 0, sizeof a);
+  fill_args(c, a);
+  a.nq = nq;
+  HIPCHK(begin_call(c, s));
+  if (!dev) {
+    HIPCHK(hipMemcpyAsync(c->d_q, q, nq * sizeof(mapa_query), hipMemcpyHostToDevice, s));
+    a.q = c->d_q;
+    a.res = c->d_res;
+  } else {
+    a.q = q;
+    a.res = res;
+  }
+  HIPCHK(launch_batch_front(a, s));
+  ProfEvents ev{};
+  if (c->profile) {
+    HIPCHK(hipEventCreate(&ev.start));
+    HIPCHK(hipEventCreate(&ev.stop));
+    HIPCHK(hipEventRecord(ev.start, s));
+  }
+  HIPCHK(launch_enumerate(a, s));
+  if (c->profile) {
+    HIPCHK(hipEventRecord(ev.stop, s));
+    c->prof.push_back(ev);
+  }
+  HIPCHK(launch_finalize(a, s));
+  if (!dev) HIPCHK(hipMemcpyAsync(res, c->d_res, nq * sizeof(mapa_result), hipMemcpyDeviceToHost, s));
+  HIPCHK(end_call(c, s));
+  ++c->batches;
+  if (!dev) HIPCHK(hipStreamSynchronize(s));
+  return MAPA_OK;
+}
+
+int32_t mapa_release(mapa_ctx *c, int32_t count, const int64_t *handles, int32_t stride,
+                     uint32_t flags, void *stream) {
+  if (!c) return fail(MAPA_ERR_INVALID_ARG, "ctx is NULL");
+  if (count < 0) return fail(MAPA_ERR_INVALID_ARG, "count < 0");
+  if (count == 0) return MAPA_OK;
+  if (!handles) return fail(MAPA_ERR_INVALID_ARG, "handles is NULL");
+  const bool dev = flags & MAPA_DEVICE_PTRS;
+  if (stride == 0) stride = sizeof(int64_t);
+  if (stride < (int32_t)sizeof(int64_t) || stride % (int32_t)sizeof(int64_t) != 0)
+    return fail(MAPA_ERR_INVALID_ARG, "stride %d is not a positive multiple of 8", stride);
+  std::vector<int64_t> h;
+  if (!dev) {
+    // host handles: full validation, all-or-nothing
+    std::vector<std::pair<int32_t, uint32_t>> seen;
+    for (int32_t i = 0; i < count; ++i) {
+      const int64_t x = *(const int64_t *)((const char *)handles + (size_t)i * stride);
+      if (x == -1) continue;
+      const int32_t s = (int32_t)(x >> 32);
+      const uint32_t m = (uint32_t)x;
+      if (x < 0 || s < 0 || (size_t)s >= c->server_topo.size())
+        return fail(MAPA_ERR_UNKNOWN_SERVER, "handle %d: unknown server %d", i, s);
+      const int n = c->topo_n[c->server_topo[s]];
+      if (m == 0 || (n < 32 && (m >> n) != 0))
+        return fail(MAPA_ERR_INVALID_ARG, "handle %d: vertex mask 0x%x invalid for n=%d", i, m, n);
+      seen.push_back({s, m});
+      h.push_back(x);
+    }
+    std::sort(seen.begin(), seen.end());
+    for (size_t i = 1; i < seen.size(); ++i)
+      if (seen[i].first == seen[i - 1].first) {
+        uint32_t acc = 0;
+        size_t j = i - 1;
+        while (j > 0 && seen[j - 1].first == seen[i].first) --j;
+        for (; j < i; ++j) acc |= seen[j].second;
+        if (acc & seen[i].second)
+          return fail(MAPA_ERR_NOT_BUSY, "two handles release the same vertex of server %d",
+                      seen[i].first);
+      }
+  }
+  if (!dev && h.empty()) return MAPA_OK;
+  if (!c->has_device) return fail(MAPA_ERR_NO_DEVICE, "context has no device");
+  HIPCHK(hipSetDevice(c->device));
+  if (dev) {
+    hipStream_t s = as_stream(stream);
+    HIPCHK(begin_call(c, s));
+    HIPCHK(launch_release_apply(handles, stride, count, (int32_t)c->server_topo.size(), c->d_busy, s));
+    HIPCHK(end_call(c, s));
+    return MAPA_OK;
+  }
+  int32_t rc = ensure_small(c, h.size());
+  if (rc) return rc;
+  hipStream_t s = c->internal;
+  uint32_t flag = 0;
+  HIPCHK(begin_call(c, s));
+  HIPCHK(hipMemcpyAsync(c->d_handles, h.data(), h.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemsetAsync(c->d_flag, 0, sizeof(uint32_t), s));
+  HIPCHK(launch_release_check(c->d_handles, 8, (int32_t)h.size(), c->d_busy, c->d_flag, s));
+  HIPCHK(hipMemcpyAsync(&flag, c->d_flag, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (flag) {
+    HIPCHK(end_call(c, s));
+    return fail(MAPA_ERR_NOT_BUSY, "a released vertex is not busy; nothing released");
+  }
+  HIPCHK(launch_release_apply(c->d_handles, 8, (int32_t)h.size(), (int32_t)c->server_topo.size(),
+                              c->d_busy, s));
+  HIPCHK(end_call(c, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return MAPA_OK;
+}
+
+int32_t mapa_get_tuning(mapa_ctx *c, mapa_tuning *out) {
+  if (!c) return fail(MAPA_ERR_INVALID_ARG, "ctx is NULL");
+  if (out) *out = c->tuning;
+  return MAPA_OK;
+}
+
+int32_t mapa_set_tuning(mapa_ctx *c, const mapa_tuning *in) {
+  if (!c) return fail(MAPA_ERR_INVALID_ARG, "ctx is NULL");
+  if (!in) return MAPA_OK;
+  if (in->min_leaves_per_item < 1 || in->min_leaves_per_item > (1 << 20))
+    return fail(MAPA_ERR_INVALID_ARG, "min_leaves_per_item outside 1..2^20");
+  if (in->items_per_lane < 1 || in->items_per_lane > 4096)
+    return fail(MAPA_ERR_INVALID_ARG, "items_per_lane outside 1..4096");
+  if (in->blocks_per_cu < 0 || in->blocks_per_cu > 64)
+    return fail(MAPA_ERR_INVALID_ARG, "blocks_per_cu outside 0..64");
+  if (in->threads_per_block < 64 || in->threads_per_block > 256 || in->threads_per_block % 64)
+    return fail(MAPA_ERR_INVALID_ARG, "threads_per_block must be 64, 128, 192 or 256");
+  c->tuning = *in;
+  return MAPA_OK;
+}
+
+int32_t mapa_profile(mapa_ctx *c, int32_t enable) {
+  if (!c) return fail(MAPA_ERR_INVALID_ARG, "ctx is NULL");
+  c->profile = enable != 0;
+  return MAPA_OK;
+}
+
+int32_t mapa_get_stats(mapa_ctx *c, mapa_stats *out) {
+  if (!c) return fail(MAPA_ERR_INVALID_ARG, "ctx is NULL");
+  if (!out) return fail(MAPA_ERR_INVALID_ARG, "out is NULL");
+  std::memset(out, 0, sizeof *out);
+  out->num_servers = (int32_t)c->server_topo.size();
+  out->num_topologies = (int32_t)c->topo_n.size();
+  out->batches = c->batches;
+  out->cu_count = c->cu_count;
+  if (c->has_device) {
+    int32_t rc = sync_ctx(c);
+    if (rc) return rc;
+    for (auto &e : c->prof) {
+      float ms = 0;
+      HIPCHK(hipEventElapsedTime(&ms, e.start, e.stop));
+      c->prof_ms += ms;
+      ++c->prof_launches;
+      (void)hipEventDestroy(e.start);
+      (void)hipEventDestroy(e.stop);
+    }
+    c->prof.clear();
+    Counters h;
+    HIPCHK(hipMemcpy(&h, c->d_ctr, sizeof h, hipMemcpyDeviceToHost));
+    out->last_items = (int64_t)h.last_total_items;
+    out->last_split = (int32_t)h.chosen_split;
+    out->self_check_failures = h.self_check_failures;
+  }
+  out->enum_launches = c->prof_launches;
+  out->enum_ms = c->prof_ms;
+  return MAPA_OK;
+}
+
+int32_t mapa_reset_stats(mapa_ctx *c) {
+  if (!c) return fail(MAPA_ERR_INVALID_ARG, "ctx is NULL");
+  int32_t rc = sync_ctx(c);
+  if (rc) return rc;
+  for (auto &e : c->prof) {
+    (void)hipEventDestroy(e.start);
+    (void)hipEventDestroy(e.stop);
+  }
+  c->prof.clear();
+  c->prof_ms = 0;
+  c->prof_launches = 0;
+  c->batches = 0;
+  return MAPA_OK;
+}
+
+int32_t mapa_sync(mapa_ctx *c) {
+  if (!c) return fail(MAPA_ERR_INVALID_ARG, "ctx is NULL");
+  return sync_ctx(c);
+}
+
+}  // extern "C"

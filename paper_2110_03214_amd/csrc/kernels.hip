@@ -1,0 +1,655 @@
+// HIP kernels of the MAPA allocation hot path, written for gfx950 (CDNA4,
+// wave64).  Integer-only: every match is enumerated and scored exactly.
+//
+// Batch pipeline (one launch each, all on the caller's stream):
+//   k_prepare    per query: validate, free set R, constant key term b*W(R),
+//                per-split prefix depths and item totals, commit claim.
+//   k_bucketize  choose one split for the batch; per query: prefix depth d,
+//                shape bucket, offset inside the bucket.
+//   k_scan       lay buckets out (largest items first), pad each to whole
+//                64-item chunks, reset the per-batch counters.
+//   k_expand     one wave per query writes its prefix items (query, prefix).
+//   k_enumerate  persistent: each wave takes a 64-item chunk; each lane
+//                expands its prefix depth-first over the remaining pattern
+//                positions, scoring every match incrementally, and keeps a
+//                count and its best (key, mapping).  Lanes of one chunk share
+//                the subtree shape, so their loops run in lock step.
+//   k_finalize   per query: decode the best mapping, recompute AggBW and
+//                PreservedBW from it, apply the batch's commits.
+//
+// Scoring (Eq. 1 and Eq. 3).  For a mapping phi with vertex set S inside the
+// free set R:
+//   key = a*AggBW + b*PreservedBW
+//       = b*W(R) + sum_p [ a*sum_{j in Nb(p)} W[phi_j][phi_p]
+//                          - b*sum_{u in R \ {phi_0..phi_{p-1}}} W[phi_p][u] ]
+// where Nb(p) are the pattern neighbours of position p that precede it and
+// W(X) is the total weight inside X.  The second form removes the chosen
+// vertices from R one at a time (each removal drops the weight from that
+// vertex to what is still left), so every tree node adds one term and a leaf
+// costs two masked weighted popcounts.
+//
+// Weighted popcounts use bit-planes: row v of a topology holds, for each
+// weight bit t, the mask of neighbours u with bit t of W[v][u] set; two planes
+// share one 32-bit word (plane 2w in the low half, 2w+1 in the high half), so
+// sum_{u in X} W[v][u] = sum_w 4^w * (popc(row_w & X2) + popc((row_w & X2) >> 16))
+// with X2 = X | X << 16.
+#include "mapa_internal.h"
+
+namespace mapa {
+
+__constant__ Tables c_tab;
+
+hipError_t upload_tables(const Tables &t) {
+  return hipMemcpyToSymbol(HIP_SYMBOL(c_tab), &t, sizeof(Tables));
+}
+
+// ----------------------------------------------------------------- helpers
+
+__device__ __forceinline__ unsigned long long perm64(int F, int k) {
+  unsigned long long p = 1;
+  for (int i = 0; i < k; ++i) p *= (unsigned long long)(F - i);
+  return p;
+}
+
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    unsigned long long o = __shfl_xor(v, off, 64);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+
+__device__ __forceinline__ unsigned long long commit_tag(uint32_t gen, uint32_t qi) {
+  return ((unsigned long long)(~gen) << 32) | qi;
+}
+
+// ----------------------------------------------------------------- prepare
+
+__global__ __launch_bounds__(256) void k_prepare(BatchArgs a) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long leaves = 0;
+  unsigned long long items[kNumSplits];
+#pragma unroll
+  for (int j = 0; j < kNumSplits; ++j) items[j] = 0;
+
+  if (i < a.nq) {
+    const mapa_query q = a.q[i];
+    Plan p = {};
+    p.server = q.server;
+    p.kind = q.kind;
+    p.k = q.k;
+    p.mode = q.mode;
+    p.a = q.a;
+    p.b = q.b;
+    p.commit = q.commit;
+    const bool ok = q.server >= 0 && q.server < a.nservers && q.kind <= 2 && q.k >= 1 &&
+                    q.k <= kMaxK && q.mode <= 1 && q.commit <= 1 && q.a >= 0 &&
+                    q.a <= MAPA_MAX_AB && q.b >= 0 && q.b <= MAPA_MAX_AB && q.reserved == 0;
+    if (!ok) {
+      p.status = kPlanInvalid;
+    } else {
+      const int t = a.server_topo[q.server];
+      const int n = a.topo_n[t];
+      const uint32_t R = ~a.busy[q.server] & ((1u << n) - 1u);
+      const int F = __popc(R);
+      p.topo = (uint16_t)t;
+      p.n = (uint8_t)n;
+      p.R = R;
+      p.F = (uint8_t)F;
+      const uint8_t *W = a.topo_W + (size_t)t * 256;
+      int wr = 0;
+      for (uint32_t m = R; m; m &= m - 1) {
+        const int u = __ffs(m) - 1;
+        for (uint32_t m2 = m & (m - 1); m2; m2 &= m2 - 1) wr += W[u * 16 + __ffs(m2) - 1];
+      }
+      p.kp0 = (int32_t)q.b * wr;
+      if (q.k > F) {
+        p.status = kPlanNofit;
+      } else {
+        p.status = kPlanOk;
+        leaves = perm64(F, q.k);
+        unsigned long long ds = 0;
+        for (int j = 0; j < kNumSplits; ++j) {
+          int d = 0;
+          if (j < kSplitWhole) {
+            const unsigned long long T = (unsigned long long)a.min_leaves << (2 * j);
+            while (d < q.k - 1 && perm64(F - d, q.k - d) > T) ++d;
+          }
+          ds |= (unsigned long long)d << (4 * j);
+          items[j] = perm64(F, d);
+        }
+        p.dsplit = ds;
+      }
+      if (q.commit) atomicMin(&a.commit_slot[q.server], commit_tag(a.gen, (uint32_t)i));
+    }
+    a.plan[i] = p;
+    a.acc_count[i] = 0;
+    a.acc_best[i] = 0;
+  }
+  // one atomic per wave and counter
+  leaves = wave_sum_u64(leaves);
+#pragma unroll
+  for (int j = 0; j < kNumSplits; ++j) items[j] = wave_sum_u64(items[j]);
+  if ((threadIdx.x & 63) == 0) {
+    if (leaves) atomicAdd(&a.ctr->total_leaves, leaves);
+#pragma unroll
+    for (int j = 0; j < kNumSplits; ++j)
+      if (items[j]) atomicAdd(&a.ctr->total_items[j], items[j]);
+  }
+}
+
+// --------------------------------------------------------------- bucketize
+
+__global__ __launch_bounds__(256) void k_bucketize(BatchArgs a) {
+  __shared__ int s_split;
+  __shared__ uint32_t s_cnt[kNumBuckets];
+  __shared__ uint32_t s_base[kNumBuckets];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  for (int b = threadIdx.x; b < kNumBuckets; b += blockDim.x) s_cnt[b] = 0;
+  if (threadIdx.x == 0) {
+    // The split is a pure function of batch totals, so every block picks the
+    // same one: the smallest items that still give >= target_items items
+    // overall ... and fit the buffer; else whole queries.
+    const unsigned long long total = a.ctr->total_leaves;
+    const unsigned long long target = (total + a.target_items - 1) / a.target_items;
+    int j = kSplitWhole;
+    for (int c = 0; c < kSplitWhole; ++c) {
+      const unsigned long long T = (unsigned long long)a.min_leaves << (2 * c);
+      if (T >= target && a.ctr->total_items[c] + kPadReserve <= a.cap_items) {
+        j = c;
+        break;
+      }
+    }
+    s_split = j;
+    if (blockIdx.x == 0) {
+      a.ctr->chosen_split = (uint32_t)j;
+      a.ctr->last_total_items = a.ctr->total_items[j];
+    }
+  }
+  __syncthreads();
+  const int j = s_split;
+  int b = -1;
+  uint32_t nitems = 0, local = 0;
+  Plan p;
+  if (i < a.nq) {
+    p = a.plan[i];
+    if (p.status == kPlanOk) {
+      const int d = (int)((p.dsplit >> (4 * j)) & 15ull);
+      nitems = (uint32_t)perm64(p.F, d);
+      b = bucket_id(p.mode, p.k - d, p.F - d);
+      p.d = (uint8_t)d;
+      p.bucket = (uint16_t)b;
+      p.nitems = nitems;
+      local = atomicAdd(&s_cnt[b], nitems);
+    }
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < kNumBuckets; c += blockDim.x)
+    s_base[c] = s_cnt[c] ? atomicAdd(&a.ctr->bucket_items[c], s_cnt[c]) : 0u;
+  __syncthreads();
+  if (b >= 0) {
+    p.item_off = s_base[b] + local;
+    a.plan[i] = p;
+  }
+}
+
+// -------------------------------------------------------------------- scan
+
+__global__ __launch_bounds__(512) void k_scan(BatchArgs a) {
+  __shared__ uint32_t s_pad[kNumBuckets];
+  __shared__ uint32_t s_start[kNumBuckets];
+  const int t = threadIdx.x;
+  for (int r = t; r < kNumBuckets; r += blockDim.x) {
+    const uint32_t cnt = a.ctr->bucket_items[c_tab.rank_bucket[r]];
+    s_pad[r] = (cnt + (kChunk - 1)) & ~(uint32_t)(kChunk - 1);
+  }
+  __syncthreads();
+  if (t == 0) {
+    uint32_t acc = 0;
+    for (int r = 0; r < kNumBuckets; ++r) {
+      s_start[r] = acc;
+      acc += s_pad[r];
+    }
+    a.ctr->total_chunks = acc / kChunk;
+  }
+  __syncthreads();
+  for (int r = t; r < kNumBuckets; r += blockDim.x) {
+    const int b = c_tab.rank_bucket[r];
+    const uint32_t cnt = a.ctr->bucket_items[b];
+    a.ctr->bucket_start[b] = s_start[r];
+    for (uint32_t x = cnt; x < s_pad[r]; ++x) a.items[s_start[r] + x] = make_uint2(kInvalidItem, 0u);
+  }
+  __syncthreads();
+  for (int r = t; r < kNumBuckets; r += blockDim.x) a.ctr->bucket_items[r] = 0;
+  if (t == 0) {
+    a.ctr->total_leaves = 0;
+    for (int j = 0; j < kNumSplits; ++j) a.ctr->total_items[j] = 0;
+    a.ctr->chunk_ctr = 0;
+  }
+}
+
+// ------------------------------------------------------------------ expand
+
+// Prefix item x of a query (0 <= x < F!/(F-d)!) is the x-th injective
+// d-tuple of free vertices in lexicographic order: digit t of x in the mixed
+// radix (F, F-1, ..., F-d+1) picks the digit-th smallest still-unused vertex.
+__global__ __launch_bounds__(256) void k_expand(BatchArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int nwaves = (gridDim.x * blockDim.x) >> 6;
+  for (int i = wave; i < a.nq; i += nwaves) {
+    const Plan p = a.plan[i];
+    if (p.status != kPlanOk) continue;
+    const uint32_t base = a.ctr->bucket_start[p.bucket] + p.item_off;
+    const int d = p.d, F = p.F;
+    uint32_t div0 = 1;
+    for (int t = 1; t < d; ++t) div0 *= (uint32_t)(F - t);
+    for (uint32_t x = lane; x < p.nitems; x += 64) {
+      uint32_t rem = x, div = div0, avail = p.R, code = 0;
+      for (int t = 0; t < d; ++t) {
+        uint32_t r = rem / div;
+        rem -= r * div;
+        if (t + 1 < d) div /= (uint32_t)(F - 1 - t);
+        uint32_t m = avail;
+        for (; r; --r) m &= m - 1;
+        const int v = __ffs(m) - 1;
+        avail &= ~(1u << v);
+        code |= (uint32_t)v << (4 * t);
+      }
+      a.items[base + x] = make_uint2((uint32_t)i, code);
+    }
+  }
+}
+
+// --------------------------------------------------------------- enumerate
+
+struct LaneState {
+  const uint32_t *trow;  // this lane's topology rows [16][WPR]
+  uint32_t R;            // free set
+  int a, b;
+  int kind, k;
+  int linked;
+  uint32_t count;        // matches seen
+  int bkey;              // best key so far (-1: none)
+  uint32_t bcode;        // its mapping, vertex of position p at bits 4p..4p+3
+};
+
+template <int WPR>
+__device__ __forceinline__ int wsum(const uint32_t *r, uint32_t m2) {
+  int s = 0;
+#pragma unroll
+  for (int w = WPR - 1; w >= 0; --w) {
+    const uint32_t x = r[w] & m2;
+    s = s * 4 + __popc(x) + __popc(x >> 16);
+  }
+  return s;
+}
+
+template <int WPR>
+__device__ __forceinline__ uint32_t adjacency(const uint32_t *r) {
+  uint32_t x = 0;
+#pragma unroll
+  for (int w = 0; w < WPR; ++w) x |= r[w] | (r[w] >> 16);
+  return x & 0xFFFFu;
+}
+
+// Vertices at the pattern neighbours of position p that precede it, and the
+// candidate set for position p (LINKED: must touch each of them).
+template <int WPR>
+__device__ __forceinline__ void node_masks(const LaneState &s, uint32_t rest, uint32_t code,
+                                           int p, uint32_t &nbm, uint32_t &cand) {
+  const uint32_t nbpos = c_tab.nb[s.kind][s.k][p];
+  cand = rest;
+  if (!s.linked && nbpos == ((1u << p) - 1u)) {
+    nbm = s.R & ~rest;  // every earlier position: the chosen set itself
+    return;
+  }
+  nbm = 0;
+  for (uint32_t m = nbpos; m; m &= m - 1) {
+    const int j = __ffs(m) - 1;
+    const int v = (code >> (4 * j)) & 15;
+    nbm |= 1u << v;
+    if (s.linked) cand &= adjacency<WPR>(s.trow + v * WPR);
+  }
+}
+
+template <int L, int WPR>
+__device__ __forceinline__ void level(LaneState &s, uint32_t rest, uint32_t code, int kp, int p) {
+  uint32_t nbm, cand;
+  node_masks<WPR>(s, rest, code, p, nbm, cand);
+  const uint32_t nb2 = nbm | (nbm << 16);
+  const uint32_t rest2 = rest | (rest << 16);
+  if constexpr (L == 1) {
+    s.count += __popc(cand);
+    const int sh = 4 * p;
+    while (cand) {
+      const int c = __ffs(cand) - 1;
+      cand &= cand - 1;
+      const uint32_t *rc = s.trow + c * WPR;
+      const int key = kp + __mul24(s.a, wsum<WPR>(rc, nb2)) - __mul24(s.b, wsum<WPR>(rc, rest2));
+      if (key > s.bkey) {
+        s.bkey = key;
+        s.bcode = code | ((uint32_t)c << sh);
+      }
+    }
+  } else {
+    while (cand) {
+      const int c = __ffs(cand) - 1;
+      cand &= cand - 1;
+      const uint32_t *rc = s.trow + c * WPR;
+      const int kp2 = kp + __mul24(s.a, wsum<WPR>(rc, nb2)) - __mul24(s.b, wsum<WPR>(rc, rest2));
+      level<L - 1, WPR>(s, rest & ~(1u << c), code | ((uint32_t)c << (4 * p)), kp2, p + 1);
+    }
+  }
+}
+
+template <int WPR>
+__device__ __forceinline__ void run_item(const BatchArgs &a, const uint32_t *rows, uint2 it) {
+  const int lane = threadIdx.x & 63;
+  const bool valid = it.x != kInvalidItem;
+  LaneState s;
+  s.count = 0;
+  s.bkey = -1;
+  s.bcode = 0;
+  s.k = 0;
+  uint32_t rest = 0, code = 0;
+  int kp = 0, L = 0, d = 0;
+  if (valid) {
+    const Plan &p = a.plan[it.x];
+    s.trow = rows + (uint32_t)p.topo * (16 * WPR);
+    s.R = p.R;
+    s.a = p.a;
+    s.b = p.b;
+    s.kind = p.kind;
+    s.k = p.k;
+    s.linked = p.mode;
+    d = p.d;
+    rest = p.R;
+    kp = p.kp0;
+    bool ok = true;
+    for (int pos = 0; pos < d; ++pos) {
+      const int v = (it.y >> (4 * pos)) & 15;
+      uint32_t nbm, cand;
+      node_masks<WPR>(s, rest, code, pos, nbm, cand);
+      ok = ok && ((cand >> v) & 1u);
+      const uint32_t *rv = s.trow + v * WPR;
+      kp += __mul24(s.a, wsum<WPR>(rv, nbm | (nbm << 16))) -
+            __mul24(s.b, wsum<WPR>(rv, rest | (rest << 16)));
+      rest &= ~(1u << v);
+      code |= (uint32_t)v << (4 * pos);
+    }
+    L = ok ? (int)p.k - d : 0;
+  }
+  switch (L) {
+    case 1: level<1, WPR>(s, rest, code, kp, d); break;
+    case 2: level<2, WPR>(s, rest, code, kp, d); break;
+    case 3: level<3, WPR>(s, rest, code, kp, d); break;
+    case 4: level<4, WPR>(s, rest, code, kp, d); break;
+    case 5: level<5, WPR>(s, rest, code, kp, d); break;
+    case 6: level<6, WPR>(s, rest, code, kp, d); break;
+    case 7: level<7, WPR>(s, rest, code, kp, d); break;
+    case 8: level<8, WPR>(s, rest, code, kp, d); break;
+    default: break;
+  }
+
+  // best as one u64: key high, inverted lexicographic mapping code low, so
+  // max() takes the largest key and then the smallest mapping.
+  unsigned long long best = 0;
+  if (s.bkey >= 0) {
+    uint32_t lex = 0;
+    for (int i = 0; i < s.k; ++i) lex = (lex << 4) | ((s.bcode >> (4 * i)) & 15u);
+    best = ((unsigned long long)(uint32_t)s.bkey << 32) | (0xFFFFFFFFu - lex);
+  }
+  unsigned long long cnt = s.count;
+  const int qi = valid ? (int)it.x : -1;
+  const int q0 = __builtin_amdgcn_readfirstlane(qi);
+  const bool same = __ballot(valid && qi != q0) == 0ull;
+  if (same) {
+    cnt = wave_sum_u64(cnt);
+    best = wave_max_u64(best);
+    if (lane == 0 && q0 >= 0) {
+      atomicAdd(&a.acc_count[q0], cnt);
+      if (best) atomicMax(&a.acc_best[q0], best);
+    }
+  } else if (valid) {
+    if (cnt) atomicAdd(&a.acc_count[qi], cnt);
+    if (best) atomicMax(&a.acc_best[qi], best);
+  }
+}
+
+template <int WPR>
+__device__ __forceinline__ void chunk_loop(const BatchArgs &a, const uint32_t *rows) {
+  const int lane = threadIdx.x & 63;
+  const uint32_t nchunks = *(volatile const uint32_t *)&a.ctr->total_chunks;
+  for (;;) {
+    uint32_t c = 0;
+    if (lane == 0) c = atomicAdd(&a.ctr->chunk_ctr, 1u);
+    c = __shfl(c, 0, 64);
+    if (c >= nchunks) break;
+    const uint2 it = a.items[(size_t)c * kChunk + lane];
+    run_item<WPR>(a, rows, it);
+  }
+}
+
+template <int WPR, bool ROWS_LDS>
+__global__ __launch_bounds__(256) void k_enumerate(BatchArgs a) {
+  if constexpr (ROWS_LDS) {
+    extern __shared__ uint32_t s_rows[];
+    const int words = a.ntopo * 16 * WPR;
+    for (int i = threadIdx.x; i < words; i += blockDim.x) s_rows[i] = a.rows[i];
+    __syncthreads();
+    chunk_loop<WPR>(a, s_rows);
+  } else {
+    chunk_loop<WPR>(a, a.rows);
+  }
+}
+
+// ---------------------------------------------------------------- finalize
+
+__global__ __launch_bounds__(256) void k_finalize(BatchArgs a) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.nq) return;
+  const Plan p = a.plan[i];
+  mapa_result r;
+  r.count = 0;
+  r.status = MAPA_RES_NOFIT;
+  r.key = INT32_MIN;
+  r.agg = 0;
+  r.pres = 0;
+  r.vertex_mask = 0;
+  for (int t = 0; t < 8; ++t) r.mapping[t] = 0xFF;
+  r.reserved = 0;
+  r.alloc_handle = -1;
+  if (p.status == kPlanInvalid) {
+    r.status = MAPA_RES_INVALID;
+  } else if (p.status == kPlanOk) {
+    const unsigned long long cnt = a.acc_count[i];
+    const unsigned long long best = a.acc_best[i];
+    r.count = (int64_t)cnt;
+    if (cnt > 0) {
+      const int k = p.k;
+      const uint32_t lex = 0xFFFFFFFFu - (uint32_t)best;
+      uint32_t S = 0;
+      for (int t = 0; t < k; ++t) {
+        const uint32_t v = (lex >> (4 * (k - 1 - t))) & 15u;
+        r.mapping[t] = (uint8_t)v;
+        S |= 1u << v;
+      }
+      const uint8_t *W = a.topo_W + (size_t)p.topo * 256;
+      int agg = 0;
+      for (int t = 1; t < k; ++t) {
+        const uint32_t vt = (lex >> (4 * (k - 1 - t))) & 15u;
+        for (uint32_t m = c_tab.nb[p.kind][k][t]; m; m &= m - 1) {
+          const int j = __ffs(m) - 1;
+          const uint32_t vj = (lex >> (4 * (k - 1 - j))) & 15u;
+          agg += W[vj * 16 + vt];
+        }
+      }
+      int pres = 0;
+      const uint32_t X = p.R & ~S;
+      for (uint32_t m = X; m; m &= m - 1) {
+        const int u = __ffs(m) - 1;
+        for (uint32_t m2 = m & (m - 1); m2; m2 &= m2 - 1) pres += W[u * 16 + __ffs(m2) - 1];
+      }
+      r.key = (int32_t)(best >> 32);
+      r.agg = agg;
+      r.pres = pres;
+      r.vertex_mask = S;
+      r.status = MAPA_RES_OK;
+      if ((int32_t)p.a * agg + (int32_t)p.b * pres != r.key)
+        atomicAdd(&a.ctr->self_check_failures, 1u);
+      if (p.commit) {
+        if (a.commit_slot[p.server] == commit_tag(a.gen, (uint32_t)i)) {
+          atomicOr(&a.busy[p.server], S);
+          r.alloc_handle = ((int64_t)p.server << 32) | (int64_t)S;
+        } else {
+          r.status = MAPA_RES_CONFLICT;
+        }
+      }
+    }
+  }
+  a.res[i] = r;
+}
+
+// ------------------------------------------------------------- state kernels
+
+__global__ void k_set_busy(const int32_t *ids, const uint32_t *masks, int32_t count,
+                           int32_t nservers, const int32_t *server_topo, const int32_t *topo_n,
+                           uint32_t *busy) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const int s = ids[i];
+  if (s < 0 || s >= nservers) return;
+  const int n = topo_n[server_topo[s]];
+  busy[s] = masks[i] & ((1u << n) - 1u);
+}
+
+__global__ void k_get_busy(const int32_t *ids, int32_t count, const uint32_t *busy,
+                           uint32_t *out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) out[i] = busy[ids[i]];
+}
+
+__device__ __forceinline__ int64_t load_handle(const int64_t *h, int32_t stride, int i) {
+  return *(const int64_t *)((const char *)h + (size_t)i * stride);
+}
+
+__global__ void k_release_check(const int64_t *h, int32_t stride, int32_t count,
+                                const uint32_t *busy, uint32_t *flag) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const int64_t x = load_handle(h, stride, i);
+  if (x == -1) return;
+  const uint32_t m = (uint32_t)x;
+  if ((busy[(int32_t)(x >> 32)] & m) != m) atomicOr(flag, 1u);
+}
+
+__global__ void k_release_apply(const int64_t *h, int32_t stride, int32_t count,
+                                int32_t nservers, uint32_t *busy) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const int64_t x = load_handle(h, stride, i);
+  if (x == -1) return;
+  const int32_t s = (int32_t)(x >> 32);
+  if (s < 0 || s >= nservers) return;
+  atomicAnd(&busy[s], ~(uint32_t)x);
+}
+
+// ---------------------------------------------------------------- launchers
+
+static inline unsigned blocks_for(long long n, int threads) {
+  return (unsigned)((n + threads - 1) / threads);
+}
+
+hipError_t launch_batch_front(const BatchArgs &a, hipStream_t s) {
+  const unsigned g = blocks_for(a.nq, 256);
+  hipLaunchKernelGGL(k_prepare, dim3(g), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_bucketize, dim3(g), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(512), 0, s, a);
+  unsigned ge = blocks_for((long long)a.nq * 64, 256);
+  if (ge > (1u << 20)) ge = 1u << 20;
+  hipLaunchKernelGGL(k_expand, dim3(ge), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int WPR, bool LDS>
+static hipError_t launch_enum_t(const BatchArgs &a, hipStream_t s) {
+  const size_t lds = LDS ? (size_t)a.ntopo * 16 * WPR * sizeof(uint32_t) : 0;
+  hipLaunchKernelGGL((k_enumerate<WPR, LDS>), dim3(a.enum_blocks), dim3(a.enum_threads), lds, s,
+                     a);
+  return hipGetLastError();
+}
+
+hipError_t launch_enumerate(const BatchArgs &a, hipStream_t s) {
+  const bool lds = a.rows_in_lds != 0;
+  switch (a.wpr) {
+    case 1: return lds ? launch_enum_t<1, true>(a, s) : launch_enum_t<1, false>(a, s);
+    case 2: return lds ? launch_enum_t<2, true>(a, s) : launch_enum_t<2, false>(a, s);
+    default: return lds ? launch_enum_t<4, true>(a, s) : launch_enum_t<4, false>(a, s);
+  }
+}
+
+template <int WPR, bool LDS>
+static int occ_t(int threads, size_t lds) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_enumerate<WPR, LDS>, threads, lds) !=
+      hipSuccess)
+    return 0;
+  return nb;
+}
+
+int enumerate_occupancy(int wpr, int rows_in_lds, int threads, size_t lds_bytes) {
+  const bool l = rows_in_lds != 0;
+  switch (wpr) {
+    case 1: return l ? occ_t<1, true>(threads, lds_bytes) : occ_t<1, false>(threads, 0);
+    case 2: return l ? occ_t<2, true>(threads, lds_bytes) : occ_t<2, false>(threads, 0);
+    default: return l ? occ_t<4, true>(threads, lds_bytes) : occ_t<4, false>(threads, 0);
+  }
+}
+
+hipError_t launch_finalize(const BatchArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(blocks_for(a.nq, 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_busy(const int32_t *ids, const uint32_t *masks, int32_t count,
+                           int32_t nservers, const int32_t *server_topo, const int32_t *topo_n,
+                           uint32_t *busy, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_set_busy, dim3(blocks_for(count, 256)), dim3(256), 0, s, ids, masks,
+                     count, nservers, server_topo, topo_n, busy);
+  return hipGetLastError();
+}
+
+hipError_t launch_get_busy(const int32_t *ids, int32_t count, const uint32_t *busy,
+                           uint32_t *out, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_get_busy, dim3(blocks_for(count, 256)), dim3(256), 0, s, ids, count,
+                     busy, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_release_check(const int64_t *h, int32_t stride, int32_t count,
+                                const uint32_t *busy, uint32_t *flag, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_release_check, dim3(blocks_for(count, 256)), dim3(256), 0, s, h, stride,
+                     count, busy, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_release_apply(const int64_t *h, int32_t stride, int32_t count,
+                                int32_t nservers, uint32_t *busy, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_release_apply, dim3(blocks_for(count, 256)), dim3(256), 0, s, h, stride,
+                     count, nservers, busy);
+  return hipGetLastError();
+}
+
+}  // namespace mapa

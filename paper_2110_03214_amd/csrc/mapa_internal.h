@@ -1,0 +1,119 @@
+// Internal layout shared by the host core (host.cpp) and the kernels
+// (kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mapa.h"
+
+namespace mapa {
+
+constexpr int kMaxN = MAPA_MAX_N;
+constexpr int kMaxK = MAPA_MAX_K;
+
+// Prefix-split candidates.  Split j < kSplitWhole aims at items of at most
+// min_leaves * 4^j embeddings; split kSplitWhole keeps every query whole.
+constexpr int kNumSplits = 9;
+constexpr int kSplitWhole = kNumSplits - 1;
+
+// Shape buckets: (mode, L = levels left below the prefix, F' = free vertices
+// left below the prefix).  In ALL mode every item of one bucket expands the
+// same-shaped subtree, so the 64 lanes of a wave stay in lock step.
+constexpr int kFp = kMaxN + 1;                 // F' in 0..16
+constexpr int kNumBuckets = 2 * kMaxK * kFp;   // 272
+constexpr int kChunk = 64;                     // items per wave-chunk (one per lane)
+constexpr int kPadReserve = (kChunk - 1) * kNumBuckets;
+constexpr uint32_t kInvalidItem = 0xFFFFFFFFu;
+
+__host__ __device__ inline int bucket_id(int mode, int L, int Fp) {
+  return mode * (kMaxK * kFp) + (L - 1) * kFp + Fp;
+}
+
+// Per-query plan, written by the prepare/bucketize kernels.
+struct Plan {
+  uint32_t R;          // free vertex mask at batch start
+  int32_t kp0;         // b * W(R): the key's constant term
+  int32_t server;
+  uint16_t topo;
+  uint8_t n, k;
+  uint8_t kind, mode, F, status;  // status: kPlanOk / kPlanNofit / kPlanInvalid
+  int16_t a, b;
+  uint8_t d;           // chosen prefix depth
+  uint8_t commit;
+  uint16_t bucket;
+  uint32_t nitems;     // prefix items of the chosen split
+  uint32_t item_off;   // offset of the first item inside its bucket
+  uint64_t dsplit;     // 4 bits per split j: prefix depth d_j
+};
+static_assert(sizeof(Plan) == 48, "Plan layout");
+
+constexpr uint8_t kPlanOk = 0, kPlanNofit = 1, kPlanInvalid = 3;
+
+// Per-batch counters (device).  Zeroed at allocation; the scan kernel
+// re-zeroes what it consumed so the next batch starts clean.
+struct Counters {
+  unsigned long long total_leaves;
+  unsigned long long total_items[kNumSplits];
+  uint32_t bucket_items[kNumBuckets];
+  uint32_t bucket_start[kNumBuckets];
+  uint32_t total_chunks;
+  uint32_t chunk_ctr;
+  uint32_t chosen_split;
+  uint32_t self_check_failures;
+  unsigned long long last_total_items;
+};
+
+struct Tables {          // uploaded once per device into __constant__ memory
+  uint8_t nb[3][kMaxK + 1][kMaxK];   // back-neighbour position masks
+  uint16_t rank_bucket[kNumBuckets]; // bucket laid out at rank r (largest items first)
+};
+
+// kernels.hip
+hipError_t upload_tables(const Tables &t);
+
+struct BatchArgs {
+  const mapa_query *q;
+  mapa_result *res;
+  int32_t nq;
+  Plan *plan;
+  unsigned long long *acc_count;
+  unsigned long long *acc_best;
+  uint2 *items;
+  unsigned long long cap_items;
+  Counters *ctr;
+  // context state
+  const int32_t *server_topo;
+  uint32_t *busy;
+  unsigned long long *commit_slot;
+  int32_t nservers;
+  const int32_t *topo_n;
+  const uint8_t *topo_W;  // [T][16][16]
+  const uint32_t *rows;   // [T][16][wpr]
+  int32_t ntopo;
+  int32_t wpr;
+  uint32_t gen;
+  // tuning
+  int32_t min_leaves;
+  unsigned long long target_items;
+  int32_t enum_blocks;
+  int32_t enum_threads;
+  int32_t rows_in_lds;
+};
+
+hipError_t launch_batch_front(const BatchArgs &a, hipStream_t s);   // prepare .. expand
+hipError_t launch_enumerate(const BatchArgs &a, hipStream_t s);
+hipError_t launch_finalize(const BatchArgs &a, hipStream_t s);
+int enumerate_occupancy(int wpr, int rows_in_lds, int threads, size_t lds_bytes);
+
+hipError_t launch_set_busy(const int32_t *ids, const uint32_t *masks, int32_t count,
+                           int32_t nservers, const int32_t *server_topo, const int32_t *topo_n,
+                           uint32_t *busy, hipStream_t s);
+hipError_t launch_get_busy(const int32_t *ids, int32_t count, const uint32_t *busy,
+                           uint32_t *out, hipStream_t s);
+hipError_t launch_release_check(const int64_t *handles, int32_t stride, int32_t count,
+                                const uint32_t *busy, uint32_t *flag, hipStream_t s);
+hipError_t launch_release_apply(const int64_t *handles, int32_t stride, int32_t count,
+                                int32_t nservers, uint32_t *busy, hipStream_t s);
+
+}  // namespace mapa

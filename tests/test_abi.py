@@ -1,0 +1,148 @@
+"""C ABI on the CPU: the library loads, exports every symbol the header
+declares, and rejects malformed arguments with the documented status codes
+(validation-only context: no GPU compute is attempted)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2110_03214_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mapa.h")
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mapa_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = B.lib()
+    declared = header_functions()
+    assert len(declared) >= 14
+    for name in declared:
+        assert hasattr(L, name), name
+    assert set(declared) == set(B.SIGNATURES)
+
+
+def test_struct_sizes_match_header():
+    text = open(HEADER).read()
+    assert "16 bytes" in text and "48 bytes" in text
+    assert B.QUERY_DTYPE.itemsize == 16 and B.RESULT_DTYPE.itemsize == 48
+
+
+@pytest.fixture
+def vctx():
+    c = B.Context(device=-1)
+    yield c
+    c.close()
+
+
+def cube_mesh():
+    W = np.zeros((8, 8), np.uint8)
+    for u in range(8):
+        for v in range(8):
+            if u != v and (u // 4 == v // 4 or abs(u - v) == 4):
+                W[u, v] = 1
+    return W
+
+
+def code_of(fn):
+    with pytest.raises(B.MapaError) as e:
+        fn()
+    return e.value.code
+
+
+def test_device_context_without_gpu_reports_no_device():
+    h = ctypes.c_void_p()
+    rc = B.lib().mapa_ctx_create(0, 0, ctypes.byref(h))
+    try:
+        import torch
+        has_gpu = torch.cuda.is_available()
+    except Exception:
+        has_gpu = False
+    if has_gpu:
+        assert rc == B.MAPA_OK
+        B.lib().mapa_ctx_destroy(h)
+    else:
+        assert rc == B.ERR_NO_DEVICE and not h.value
+
+
+def test_topology_validation(vctx):
+    W = cube_mesh()
+    assert vctx.create_topology(W, 3) == (0, 0)
+    assert vctx.create_topology(W, 2) == (1, 3)
+    assert code_of(lambda: vctx.create_topology(np.zeros((17, 17), np.uint8), 1)) == B.ERR_UNSUPPORTED
+    asym = W.copy()
+    asym[0, 1] = 2
+    assert code_of(lambda: vctx.create_topology(asym, 1)) == B.ERR_INVALID_ARG
+    diag = W.copy()
+    diag[3, 3] = 1
+    assert code_of(lambda: vctx.create_topology(diag, 1)) == B.ERR_INVALID_ARG
+    assert code_of(lambda: vctx.create_topology(W, -1)) == B.ERR_INVALID_ARG
+    h = ctypes.c_void_p()
+    t = ctypes.c_int32()
+    assert B.lib().mapa_create_topology(vctx.h, 0, W.ctypes.data, 1, ctypes.byref(t), None) == B.ERR_INVALID_ARG
+    assert B.lib().mapa_create_topology(vctx.h, 8, None, 1, None, None) == B.ERR_INVALID_ARG
+    assert "NULL" in B.lib().mapa_last_error().decode()
+
+
+def test_busy_validation(vctx):
+    vctx.create_topology(cube_mesh(), 4)
+    assert code_of(lambda: vctx.set_busy([4], [1])) == B.ERR_UNKNOWN_SERVER
+    assert code_of(lambda: vctx.set_busy([0], [1 << 8])) == B.ERR_INVALID_ARG
+    assert code_of(lambda: vctx.set_busy([0, 1], [3, 5])) == B.ERR_NO_DEVICE
+    assert code_of(lambda: vctx.get_busy([9])) == B.ERR_UNKNOWN_SERVER
+
+
+def test_query_validation(vctx):
+    vctx.create_topology(cube_mesh(), 4)
+    good = B.pack_queries([0, 1, 2], [0, 1, 2], [4, 3, 8])
+
+    def with_field(name, value, idx=1):
+        q = good.copy()
+        q[name][idx] = value
+        return lambda: vctx.query_batch(q)
+
+    assert code_of(with_field("server", 4)) == B.ERR_UNKNOWN_SERVER
+    assert code_of(with_field("server", -1)) == B.ERR_UNKNOWN_SERVER
+    assert code_of(with_field("kind", 3)) == B.ERR_INVALID_ARG
+    assert code_of(with_field("k", 0)) == B.ERR_INVALID_ARG
+    assert code_of(with_field("k", 9)) == B.ERR_UNSUPPORTED
+    assert code_of(with_field("mode", 2)) == B.ERR_INVALID_ARG
+    assert code_of(with_field("commit", 2)) == B.ERR_INVALID_ARG
+    assert code_of(with_field("a", 1025)) == B.ERR_INVALID_ARG
+    assert code_of(with_field("b", -1)) == B.ERR_INVALID_ARG
+    assert code_of(with_field("reserved", 7)) == B.ERR_INVALID_ARG
+    assert "query 1" in B.lib().mapa_last_error().decode()
+    # a valid batch passes validation and then needs a device
+    assert code_of(lambda: vctx.query_batch(good)) == B.ERR_NO_DEVICE
+
+
+def test_release_validation(vctx):
+    vctx.create_topology(cube_mesh(), 2)
+    assert code_of(lambda: vctx.release([(5 << 32) | 1])) == B.ERR_UNKNOWN_SERVER
+    assert code_of(lambda: vctx.release([(0 << 32) | (1 << 9)])) == B.ERR_INVALID_ARG
+    assert code_of(lambda: vctx.release([(0 << 32) | 3, (0 << 32) | 6])) == B.ERR_NOT_BUSY
+    assert code_of(lambda: vctx.release([(0 << 32) | 3, (1 << 32) | 3])) == B.ERR_NO_DEVICE
+    vctx.release([-1, -1])  # nothing to release: fine without a device
+
+
+def test_tuning_validation(vctx):
+    t = vctx.tuning()
+    assert t.min_leaves_per_item >= 1 and t.threads_per_block == 256
+    assert code_of(lambda: vctx.set_tuning(threads_per_block=100)) == B.ERR_INVALID_ARG
+    assert code_of(lambda: vctx.set_tuning(min_leaves_per_item=0)) == B.ERR_INVALID_ARG
+    vctx.set_tuning(min_leaves_per_item=256, items_per_lane=2)
+    assert vctx.tuning().min_leaves_per_item == 256
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    monkeypatch.setattr(B, "_lib", None)
+    monkeypatch.setattr(B, "LIB_PATH", str(tmp_path / "nope.so"))
+    with pytest.raises(RuntimeError, match="missing"):
+        B.lib()

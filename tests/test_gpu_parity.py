@@ -1,0 +1,277 @@
+"""GPU parity: the HIP path against the CPU oracle, bit for bit.
+
+Every comparison covers the match count, the result status, the integer key,
+AggBW, PreservedBW, the chosen mapping and its vertex set.  Inputs are the
+seeded workloads (full batched config in the launch configuration the
+benchmark times, the tiny config under four keys and both modes, sampled and
+stored results of the large config) plus edge cases: empty and full servers,
+k > free vertices, n = 1 and n = 16, k = 8, the widest weights and key
+factors, LINKED with no match, ragged batches, and batch commit semantics.
+"""
+import os
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2110_03214_amd import binding as B
+from paper_2110_03214_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+NTHREADS = min(16, os.cpu_count() or 1)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.fail("GPU test run without a visible GPU")
+    return t
+
+
+@pytest.fixture
+def ctx(torch):
+    c = B.Context(0)
+    yield c
+    c.close()
+
+
+def assert_same(gpu, ref, k, label=""):
+    """Compare result arrays field by field (mapping only up to k)."""
+    k = np.asarray(k)
+    assert len(gpu) == len(ref)
+    for f in ("count", "status"):
+        bad = np.nonzero(gpu[f] != ref[f])[0]
+        assert bad.size == 0, f"{label} {f} differs at {bad[:5]}: gpu {gpu[f][bad[:5]]} ref {ref[f][bad[:5]]}"
+    ok = ref["status"] == 0
+    for f in ("key", "agg", "pres", "vertex_mask"):
+        bad = np.nonzero(ok & (gpu[f] != ref[f]))[0]
+        assert bad.size == 0, f"{label} {f} differs at {bad[:5]}: gpu {gpu[f][bad[:5]]} ref {ref[f][bad[:5]]}"
+    for kk in np.unique(k):
+        sel = ok & (k == kk)
+        assert np.array_equal(gpu["mapping"][sel, :kk], ref["mapping"][sel, :kk]), f"{label} mapping k={kk}"
+        assert (gpu["mapping"][sel, kk:] == 0xFF).all()
+
+
+def run_gpu(ctx, wl):
+    q, _ = B.load_workload(ctx, wl)
+    return ctx.query_batch(q)
+
+
+def test_tiny_config_all_keys_and_modes(ctx):
+    base = synth.config1()
+    q, ids = B.load_workload(ctx, base)
+    for a, b, mode in ((1, 1, 0), (1, 0, 0), (0, 1, 0), (3, 2, 0), (1, 1, 1), (1, 0, 1)):
+        wl = base.with_keys(a, b, mode)
+        qq = q.copy()
+        qq["a"], qq["b"], qq["mode"] = a, b, mode
+        got = ctx.query_batch(qq)
+        ref = oracle.run_workload(wl, NTHREADS)
+        assert_same(got, ref, wl.queries["k"], f"C1 a={a} b={b} mode={mode}")
+    assert ctx.stats()["self_check_failures"] == 0
+
+
+def test_batched_config_full_size_device_pointers(ctx, torch):
+    """All 65,536 queries of the batched config, device-resident queries and
+    results, one launch sequence: exactly what the benchmark times."""
+    wl = synth.config2()
+    q, _ = B.load_workload(ctx, wl)
+    dq = torch.from_numpy(q.view(np.uint8)).to("cuda")
+    dr = torch.zeros(wl.nq * 48, dtype=torch.uint8, device="cuda")
+    ctx.query_batch(dq, dr, stream=torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    got = dr.cpu().numpy().view(B.RESULT_DTYPE)
+    ref = oracle.run_workload(wl, NTHREADS)
+    assert_same(got, ref, wl.queries["k"], "C2")
+    assert int(got["count"].sum()) == int(ref["count"].sum())
+    assert abs((got["status"] == 1).mean() - 0.517) < 0.01
+
+
+def test_batched_config_tuning_does_not_change_results(ctx):
+    wl = synth.config2(8192)
+    q, _ = B.load_workload(ctx, wl)
+    ref = ctx.query_batch(q)
+    for kw in (dict(min_leaves_per_item=1, items_per_lane=64),
+               dict(min_leaves_per_item=4096, items_per_lane=1),
+               dict(min_leaves_per_item=16, items_per_lane=8, blocks_per_cu=1, threads_per_block=64)):
+        ctx.set_tuning(**kw)
+        got = ctx.query_batch(q)
+        assert np.array_equal(got, ref), kw
+    assert_same(ref, oracle.run_workload(wl, NTHREADS), wl.queries["k"], "C2[8192]")
+
+
+def test_large_config_closed_form_counts_and_sampled_parity(ctx):
+    wl = synth.config3()
+    q, _ = B.load_workload(ctx, wl)
+    got = ctx.query_batch(q)
+    k = wl.queries["k"].astype(int)
+    assert (got["count"] == np.array([math.perm(16, int(x)) for x in k])).all()
+    assert (got["status"] == 0).all()
+    # the oracle recomputes every k = 6 query (5.8e6 embeddings each)
+    sel = np.nonzero(k == 6)[0]
+    ref = oracle.run_workload(wl.subset(sel), NTHREADS)
+    assert_same(got[sel], ref, k[sel], "C3 k=6")
+    assert ctx.stats()["self_check_failures"] == 0
+
+
+def load_stored_c3():
+    path = os.path.join(GOLDEN, "c3_expected.txt")
+    if not os.path.exists(path):
+        return None
+    rows = [line.split() for line in open(path) if not line.startswith("#")]
+    out = np.zeros(len(rows), dtype=oracle.RESULT_DTYPE)
+    for i, r in enumerate(rows):
+        k = int(r[3])
+        out[i]["count"], out[i]["status"] = int(r[4]), int(r[5])
+        out[i]["key"], out[i]["agg"], out[i]["pres"] = int(r[6]), int(r[7]), int(r[8])
+        out[i]["vertex_mask"] = int(r[9])
+        m = np.full(8, 255, np.uint8)
+        m[:k] = [int(x) for x in r[10:10 + k]]
+        out[i]["mapping"] = m
+    return out
+
+
+def test_large_config_full_against_stored_oracle_results(ctx):
+    ref = load_stored_c3()
+    if ref is None:
+        pytest.skip("tests/golden/c3_expected.txt not generated")
+    wl = synth.config3()
+    got = run_gpu(ctx, wl)
+    assert_same(got, ref, wl.queries["k"], "C3 full")
+
+
+def random_topology(rng, n, wmax, p_edge):
+    W = np.zeros((n, n), np.uint8)
+    for u in range(n):
+        for v in range(u + 1, n):
+            if rng.random() < p_edge:
+                W[u, v] = W[v, u] = rng.integers(1, wmax + 1)
+    return W
+
+
+@pytest.mark.parametrize("wmax", [3, 15, 255])
+def test_random_small_graphs_every_shape(ctx, wmax):
+    """Ragged mix: n = 1..9, every kind, k = 1..8, both modes, several keys,
+    random busy masks; weights up to 3, 15 or 255 (the three row formats)."""
+    rng = np.random.default_rng(77 + wmax)
+    topos, st, busy, cols = [], [], [], {key: [] for key in ("server", "kind", "k", "mode", "a", "b")}
+    s = 0
+    for _rep in range(1):
+        for n in range(1, 10):
+            for _ in range(2):
+                topos.append(random_topology(rng, n, wmax, 0.6))
+                for _ in range(6):
+                    st.append(len(topos) - 1)
+                    busy.append(int(rng.integers(0, 1 << n)) & int(rng.integers(0, 1 << n)))
+                    for kind in range(3):
+                        for k in range(1, 9):
+                            for mode in (0, 1):
+                                a, b = [(1, 1), (1, 0), (0, 1), (1024, 7)][int(rng.integers(0, 4))]
+                                for key, v in zip(cols, (s, kind, k, mode, a, b)):
+                                    cols[key].append(v)
+                    s += 1
+    q = synth.make_queries(cols["server"], cols["kind"], cols["k"], cols["mode"], 0, cols["a"], cols["b"])
+    wl = synth.Workload("random", topos, np.array(st, np.int32), np.array(busy, np.uint32), q)
+    got = run_gpu(ctx, wl)
+    ref = oracle.run_workload(wl, NTHREADS)
+    assert_same(got, ref, wl.queries["k"], "random")
+    assert ctx.stats()["self_check_failures"] == 0
+
+
+def test_edge_cases(ctx):
+    W16 = np.full((16, 16), 255, np.uint8)
+    np.fill_diagonal(W16, 0)
+    one = np.zeros((1, 1), np.uint8)
+    cm = synth.config2_topologies()[1]
+    topos = [W16, one, cm, np.zeros((8, 8), np.uint8)]
+    st = np.array([0, 0, 1, 1, 2, 2, 3], np.int32)
+    busy = np.array([0, 0xFF00, 0, 1, 0xFF, 0, 0], np.uint32)
+    rows = [
+        (0, 1, 3, 0, 1024, 1024),   # widest weights and key factors
+        (1, 0, 8, 0, 1024, 1024),   # n=16, half busy, k=8 = F
+        (1, 1, 8, 1, 1, 1),         # LINKED on K8 of weight 255
+        (2, 0, 1, 0, 1, 1),         # n=1, k=1
+        (3, 0, 1, 0, 1, 1),         # n=1, everything busy -> NOFIT
+        (3, 2, 2, 0, 1, 1),         # k > F -> NOFIT
+        (4, 0, 8, 0, 1, 1),         # all busy on 8 -> NOFIT
+        (5, 1, 5, 1, 1, 1),         # LINKED a2a k=5 on cube-mesh: no K5 -> NOFIT
+        (5, 0, 8, 1, 1, 0),         # LINKED Hamiltonian ring on cube-mesh
+        (6, 2, 4, 1, 1, 1),         # LINKED on an edgeless graph -> NOFIT
+        (6, 2, 4, 0, 1, 1),         # ALL on an edgeless graph: every key 0
+    ]
+    cols = list(zip(*rows))
+    q = synth.make_queries(cols[0], cols[1], cols[2], cols[3], 0, cols[4], cols[5])
+    wl = synth.Workload("edges", topos, st, busy, q)
+    got = run_gpu(ctx, wl)
+    ref = oracle.run_workload(wl, NTHREADS)
+    assert_same(got, ref, wl.queries["k"], "edges")
+    assert list(got["status"]) == [0, 0, 0, 0, 1, 1, 1, 1, 0, 1, 0]
+    assert list(got["count"][[1, 2, 3, 10]]) == [40320, 40320, 1, 1680]
+
+
+def test_commit_conflict_release_semantics(ctx):
+    rng = np.random.default_rng(5)
+    base = synth.config2(512)
+    # duplicate some servers and ask everything to commit
+    srv = base.queries["server"].copy()
+    srv[100:200] = srv[0:100]
+    q = synth.make_queries(srv, base.queries["kind"], base.queries["k"], 0, 1, 1, 1)
+    q["commit"][rng.integers(0, 512, size=50)] = 0
+    wl = synth.Workload("commit", base.topologies, base.server_topo, base.busy, q)
+    qq, ids = B.load_workload(ctx, wl)
+    got = ctx.query_batch(qq)
+    ref, handles, busy_after = oracle.run_batch_semantics(wl, NTHREADS)
+    assert_same(got, ref, wl.queries["k"], "commit")
+    exp_handles = np.full(len(handles), -1, np.int64)
+    live = handles >= 0
+    exp_handles[live] = (ids[handles[live] >> 32].astype(np.int64) << 32) | (handles[live] & 0xFFFFFFFF)
+    assert np.array_equal(got["alloc_handle"], exp_handles)
+    assert np.array_equal(ctx.get_busy(ids), busy_after)
+    assert (got["status"] == 2).sum() > 0
+    # release everything that was committed: back to the entry state
+    ctx.release(got["alloc_handle"])
+    assert np.array_equal(ctx.get_busy(ids), wl.busy)
+    # releasing again is refused and changes nothing
+    live = got["alloc_handle"][got["alloc_handle"] >= 0]
+    with pytest.raises(B.MapaError) as e:
+        ctx.release(live[:3])
+    assert e.value.code == B.ERR_NOT_BUSY
+    assert np.array_equal(ctx.get_busy(ids), wl.busy)
+
+
+def test_device_pointer_release_and_invalid_queries(ctx, torch):
+    wl = synth.config2(2048)
+    q, ids = B.load_workload(ctx, wl)
+    q["commit"] = 1
+    q["k"][7] = 0          # malformed: answered with RES_INVALID on device
+    q["reserved"][9] = 3
+    dq = torch.from_numpy(q.view(np.uint8)).to("cuda")
+    dr = torch.zeros(len(q) * 48, dtype=torch.uint8, device="cuda")
+    ctx.query_batch(dq, dr, stream=torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    got = dr.cpu().numpy().view(B.RESULT_DTYPE)
+    assert got["status"][7] == B.RES_INVALID and got["status"][9] == B.RES_INVALID
+    assert got["alloc_handle"][7] == -1
+    ok = got["status"] == 0
+    busy = ctx.get_busy(ids)
+    assert (busy[np.nonzero(ok)[0]] == (wl.busy[np.nonzero(ok)[0]] | got["vertex_mask"][ok])).all()
+    # release through the result array in place (stride 48)
+    dh = dr.view(torch.int64)[5:]  # alloc_handle is at byte 40 of each 48-byte result
+    ctx.release(dh, stride=48, count=len(q), stream=torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    assert np.array_equal(ctx.get_busy(ids), wl.busy)
+
+
+def test_set_busy_device_pointers(ctx, torch):
+    wl = synth.config2(1024)
+    q, ids = B.load_workload(ctx, wl)
+    new = (wl.busy ^ 0x5).astype(np.uint32)
+    d_ids = torch.from_numpy(ids).to("cuda")
+    d_m = torch.from_numpy(new.view(np.int32)).to("cuda")
+    ctx.set_busy(d_ids, d_m, stream=torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    n = np.array([wl.topologies[t].shape[0] for t in wl.server_topo])
+    assert np.array_equal(ctx.get_busy(ids), new & ((1 << n) - 1).astype(np.uint32))
