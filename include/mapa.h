@@ -92,6 +92,13 @@ extern "C" {
 /* ---- flags ------------------------------------------------------------------ */
 #define MAPA_DEVICE_PTRS 1u  /* array arguments are device pointers; the call is
                                 asynchronous on the given stream                 */
+#define MAPA_USE_GRAPH 2u    /* with MAPA_DEVICE_PTRS: capture the batch's launch
+                                sequence into a HIP graph on first use for this
+                                (queries, results, nq, stream) and replay it on
+                                later calls with the same arguments; the graph is
+                                rebuilt after topologies, servers, tuning or
+                                capacity change.  Results are identical.  Ignored
+                                while kernel timing (mapa_profile) is on.        */
 
 typedef struct mapa_ctx mapa_ctx; /* opaque; owns all device memory it uses */
 

@@ -29,6 +29,7 @@ RING, ALL_TO_ALL, TREE = 0, 1, 2
 ALL_INJECTIVE, LINKED = 0, 1
 RES_OK, RES_NOFIT, RES_CONFLICT, RES_INVALID = 0, 1, 2, 3
 DEVICE_PTRS = 1
+USE_GRAPH = 2
 
 QUERY_DTYPE = np.dtype([("server", np.int32), ("kind", np.uint8), ("k", np.uint8),
                         ("mode", np.uint8), ("commit", np.uint8), ("a", np.int16),
@@ -186,13 +187,15 @@ class Context:
         return out
 
     # -- queries -------------------------------------------------------------
-    def query_batch(self, queries, results=None, stream=None):
+    def query_batch(self, queries, results=None, stream=None, graph: bool = False):
         """Host numpy QUERY_DTYPE array -> numpy RESULT_DTYPE array (blocking),
-        or device byte tensors (nq*16 and nq*48 bytes) -> asynchronous."""
+        or device byte tensors (nq*16 and nq*48 bytes) -> asynchronous
+        (``graph=True``: replay a captured HIP graph of the batch)."""
         if hasattr(queries, "data_ptr"):
             nq = queries.numel() * queries.element_size() // QUERY_DTYPE.itemsize
+            flags = DEVICE_PTRS | (USE_GRAPH if graph else 0)
             check(lib().mapa_query_batch(self.h, _ptr(queries), int(nq), _ptr(results),
-                                         DEVICE_PTRS, _stream(stream)), "mapa_query_batch")
+                                         flags, _stream(stream)), "mapa_query_batch")
             return results
         q = np.ascontiguousarray(queries, dtype=QUERY_DTYPE)
         res = np.zeros(len(q), dtype=RESULT_DTYPE) if results is None else results

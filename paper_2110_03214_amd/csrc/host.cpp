@@ -119,7 +119,7 @@ struct mapa_ctx {
   uint32_t *d_busy = nullptr;
   unsigned long long *d_commit_slot = nullptr;
   size_t cap_servers = 0;
-  uint32_t gen = 0;
+  uint64_t batches_since_slot_reset = 0;
 
   // batch workspace
   size_t cap_q = 0;
@@ -136,6 +136,18 @@ struct mapa_ctx {
   int64_t *d_handles = nullptr;
   uint32_t *d_flag = nullptr;
   size_t cap_small = 0;
+
+  // captured batch graphs (device-pointer batches with MAPA_USE_GRAPH)
+  struct Graph {
+    const void *q;
+    void *res;
+    int32_t nq;
+    hipStream_t stream;
+    uint64_t version;
+    hipGraphExec_t exec;
+  };
+  std::vector<Graph> graphs;
+  uint64_t version = 1;  // bumped whenever a value baked into a launch changes
 
   mapa_tuning tuning{64, 4, 0, 256};
   bool profile = false;
@@ -235,10 +247,17 @@ int32_t grow_servers(mapa_ctx *c, size_t need) {
   return MAPA_OK;
 }
 
+void drop_graphs(mapa_ctx *c) {
+  for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.exec);
+  c->graphs.clear();
+  ++c->version;
+}
+
 int32_t ensure_batch_capacity(mapa_ctx *c, size_t nq) {
   if (nq <= c->cap_q) return MAPA_OK;
   int32_t rc = sync_ctx(c);
   if (rc) return rc;
+  drop_graphs(c);
   size_t cap = std::max<size_t>(1024, c->cap_q);
   while (cap < nq) cap *= 2;
   dev_free(c->d_plan);
@@ -303,7 +322,6 @@ void fill_args(mapa_ctx *c, BatchArgs &a) {
   a.rows = c->d_rows;
   a.ntopo = (int32_t)c->topo_n.size();
   a.wpr = c->wpr;
-  a.gen = c->gen;
   a.min_leaves = std::max(1, c->tuning.min_leaves_per_item);
   const int threads = c->tuning.threads_per_block;
   const size_t lds_bytes = (size_t)a.ntopo * 16 * c->wpr * sizeof(uint32_t);
@@ -367,8 +385,14 @@ int32_t mapa_ctx_create(int32_t device, size_t enum_buffer_bytes, mapa_ctx **out
       dev_alloc(&c->d_flag, 1) != hipSuccess)
     return bail(fail(MAPA_ERR_OOM, "enumeration buffer of %zu bytes: allocation failed", bytes));
   c->cap_items = items;
-  if (hipMemset(c->d_ctr, 0, sizeof(Counters)) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
-    return bail(fail(MAPA_ERR_DEVICE, "counter init failed"));
+  {
+    Counters z;
+    std::memset(&z, 0, sizeof z);
+    z.gen = 1;
+    if (hipMemcpy(c->d_ctr, &z, sizeof z, hipMemcpyHostToDevice) != hipSuccess ||
+        hipDeviceSynchronize() != hipSuccess)
+      return bail(fail(MAPA_ERR_DEVICE, "counter init failed"));
+  }
   *out = c;
   return MAPA_OK;
 }
@@ -383,6 +407,7 @@ int32_t mapa_ctx_destroy(mapa_ctx *c) {
       (void)hipEventDestroy(e.start);
       (void)hipEventDestroy(e.stop);
     }
+    for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.exec);
     dev_free(c->d_topo_n);
     dev_free(c->d_topo_W);
     dev_free(c->d_rows);
@@ -432,6 +457,7 @@ int32_t mapa_create_topology(mapa_ctx *c, int32_t n, const uint8_t *W, int32_t n
     int32_t rc = sync_ctx(c);
     if (rc) return rc;
     HIPCHK(hipSetDevice(c->device));
+    drop_graphs(c);
     c->topo_n.push_back(n);
     c->topo_W.push_back(w16);
     c->wpr = std::max(c->wpr, weight_class(W, n));
@@ -541,16 +567,52 @@ int32_t mapa_query_batch(mapa_ctx *c, const mapa_query *q, int32_t nq, mapa_resu
   int32_t rc = ensure_batch_capacity(c, nq);
   if (rc) return rc;
   hipStream_t s = as_stream(stream);
-  if (++c->gen == 0) {  // commit tags wrapped: reset every claim
+  if (++c->batches_since_slot_reset >= (1ull << 31)) {
+    // commit generations would wrap: clear every claim and restart at 1
     HIPCHK(hipEventSynchronize(c->last));
     HIPCHK(hipMemset(c->d_commit_slot, 0xFF, c->cap_servers * sizeof(unsigned long long)));
+    const uint32_t one = 1;
+    HIPCHK(hipMemcpy(&c->d_ctr->gen, &one, sizeof one, hipMemcpyHostToDevice));
     HIPCHK(hipDeviceSynchronize());
-    c->gen = 1;
+    c->batches_since_slot_reset = 1;
   }
   BatchArgs a;
   std::memset(&a, 0, sizeof a);
   fill_args(c, a);
   a.nq = nq;
+  const bool use_graph = dev && (flags & MAPA_USE_GRAPH) && !c->profile;
+  if (use_graph) {
+    a.q = q;
+    a.res = res;
+    mapa_ctx::Graph *g = nullptr;
+    for (auto &e : c->graphs)
+      if (e.q == q && e.res == res && e.nq == nq && e.stream == s && e.version == c->version) g = &e;
+    if (!g) {
+      if (c->graphs.size() >= 16) drop_graphs(c);
+      hipGraph_t graph = nullptr;
+      hipGraphExec_t exec = nullptr;
+      HIPCHK(hipStreamBeginCapture(c->internal, hipStreamCaptureModeRelaxed));
+      hipError_t e1 = launch_batch_front(a, c->internal);
+      hipError_t e2 = e1 == hipSuccess ? launch_enumerate(a, c->internal) : e1;
+      hipError_t e3 = e2 == hipSuccess ? launch_finalize(a, c->internal) : e2;
+      hipError_t ec = hipStreamEndCapture(c->internal, &graph);
+      if (e3 != hipSuccess || ec != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return fail(MAPA_ERR_DEVICE, "graph capture failed: %s",
+                    hipGetErrorString(e3 != hipSuccess ? e3 : ec));
+      }
+      hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (ei != hipSuccess) return fail(MAPA_ERR_DEVICE, "graph instantiate: %s", hipGetErrorString(ei));
+      c->graphs.push_back({q, res, nq, s, c->version, exec});
+      g = &c->graphs.back();
+    }
+    HIPCHK(begin_call(c, s));
+    HIPCHK(hipGraphLaunch(g->exec, s));
+    HIPCHK(end_call(c, s));
+    ++c->batches;
+    return MAPA_OK;
+  }
   HIPCHK(begin_call(c, s));
   if (!dev) {
     HIPCHK(hipMemcpyAsync(c->d_q, q, nq * sizeof(mapa_query), hipMemcpyHostToDevice, s));
@@ -667,6 +729,11 @@ int32_t mapa_set_tuning(mapa_ctx *c, const mapa_tuning *in) {
     return fail(MAPA_ERR_INVALID_ARG, "blocks_per_cu outside 0..64");
   if (in->threads_per_block < 64 || in->threads_per_block > 256 || in->threads_per_block % 64)
     return fail(MAPA_ERR_INVALID_ARG, "threads_per_block must be 64, 128, 192 or 256");
+  if (c->has_device) {
+    int32_t rc = sync_ctx(c);
+    if (rc) return rc;
+    drop_graphs(c);
+  }
   c->tuning = *in;
   return MAPA_OK;
 }

@@ -127,7 +127,7 @@ __global__ __launch_bounds__(256) void k_prepare(BatchArgs a) {
         }
         p.dsplit = ds;
       }
-      if (q.commit) atomicMin(&a.commit_slot[q.server], commit_tag(a.gen, (uint32_t)i));
+      if (q.commit) atomicMin(&a.commit_slot[q.server], commit_tag(a.ctr->gen, (uint32_t)i));
     }
     a.plan[i] = p;
     a.acc_count[i] = 0;
@@ -232,6 +232,7 @@ __global__ __launch_bounds__(512) void k_scan(BatchArgs a) {
     a.ctr->total_leaves = 0;
     for (int j = 0; j < kNumSplits; ++j) a.ctr->total_items[j] = 0;
     a.ctr->chunk_ctr = 0;
+    a.ctr->gen += 1u;  // finalize of this batch uses gen - 1
   }
 }
 
@@ -506,7 +507,7 @@ __global__ __launch_bounds__(256) void k_finalize(BatchArgs a) {
       if ((int32_t)p.a * agg + (int32_t)p.b * pres != r.key)
         atomicAdd(&a.ctr->self_check_failures, 1u);
       if (p.commit) {
-        if (a.commit_slot[p.server] == commit_tag(a.gen, (uint32_t)i)) {
+        if (a.commit_slot[p.server] == commit_tag(a.ctr->gen - 1u, (uint32_t)i)) {
           atomicOr(&a.busy[p.server], S);
           r.alloc_handle = ((int64_t)p.server << 32) | (int64_t)S;
         } else {

@@ -62,6 +62,10 @@ struct Counters {
   uint32_t chosen_split;
   uint32_t self_check_failures;
   unsigned long long last_total_items;
+  // Commit generation: read by k_prepare, advanced by k_scan, so k_finalize
+  // of the same batch sees gen + 1.  Lives in device memory so that a
+  // captured batch graph stays correct on every replay.
+  uint32_t gen;
 };
 
 struct Tables {          // uploaded once per device into __constant__ memory
@@ -92,7 +96,6 @@ struct BatchArgs {
   const uint32_t *rows;   // [T][16][wpr]
   int32_t ntopo;
   int32_t wpr;
-  uint32_t gen;
   // tuning
   int32_t min_leaves;
   unsigned long long target_items;

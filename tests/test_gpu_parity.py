@@ -275,3 +275,37 @@ def test_set_busy_device_pointers(ctx, torch):
     torch.cuda.synchronize()
     n = np.array([wl.topologies[t].shape[0] for t in wl.server_topo])
     assert np.array_equal(ctx.get_busy(ids), new & ((1 << n) - 1).astype(np.uint32))
+
+
+def test_graph_replay_matches_eager(ctx, torch):
+    """A captured batch graph, replayed several times with eager batches and
+    synchronisations in between, gives the eager result on every replay
+    (including commits and their handles; everything is released in between)."""
+    wl = synth.config2(4096)
+    q, ids = B.load_workload(ctx, wl)
+    q["commit"] = 1
+    stream = torch.cuda.current_stream()
+    dq = torch.from_numpy(q.view(np.uint8)).to("cuda")
+    d_eager = torch.zeros(len(q) * 48, dtype=torch.uint8, device="cuda")
+    d_graph = torch.zeros(len(q) * 48, dtype=torch.uint8, device="cuda")
+
+    def release(buf):
+        ctx.release(buf.view(torch.int64)[5:], stride=48, count=len(q), stream=stream)
+
+    ctx.query_batch(dq, d_eager, stream=stream)
+    torch.cuda.synchronize()
+    eager = d_eager.cpu().numpy().view(B.RESULT_DTYPE).copy()
+    release(d_eager)
+    for rep in range(4):
+        d_graph.zero_()
+        ctx.query_batch(dq, d_graph, stream=stream, graph=True)
+        torch.cuda.synchronize()
+        got = d_graph.cpu().numpy().view(B.RESULT_DTYPE)
+        assert np.array_equal(got, eager), f"replay {rep}"
+        release(d_graph)
+        ctx.query_batch(dq, d_eager, stream=stream)   # eager work between replays
+        torch.cuda.synchronize()
+        assert np.array_equal(d_eager.cpu().numpy().view(B.RESULT_DTYPE), eager)
+        release(d_eager)
+        torch.cuda.synchronize()
+        assert np.array_equal(ctx.get_busy(ids), wl.busy)
