@@ -119,7 +119,6 @@ struct mapa_ctx {
   uint32_t *d_busy = nullptr;
   unsigned long long *d_commit_slot = nullptr;
   size_t cap_servers = 0;
-  uint64_t batches_since_slot_reset = 0;
 
   // batch workspace
   size_t cap_q = 0;
@@ -385,14 +384,8 @@ int32_t mapa_ctx_create(int32_t device, size_t enum_buffer_bytes, mapa_ctx **out
       dev_alloc(&c->d_flag, 1) != hipSuccess)
     return bail(fail(MAPA_ERR_OOM, "enumeration buffer of %zu bytes: allocation failed", bytes));
   c->cap_items = items;
-  {
-    Counters z;
-    std::memset(&z, 0, sizeof z);
-    z.gen = 1;
-    if (hipMemcpy(c->d_ctr, &z, sizeof z, hipMemcpyHostToDevice) != hipSuccess ||
-        hipDeviceSynchronize() != hipSuccess)
-      return bail(fail(MAPA_ERR_DEVICE, "counter init failed"));
-  }
+  if (hipMemset(c->d_ctr, 0, sizeof(Counters)) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
+    return bail(fail(MAPA_ERR_DEVICE, "counter init failed"));
   *out = c;
   return MAPA_OK;
 }
@@ -567,15 +560,6 @@ int32_t mapa_query_batch(mapa_ctx *c, const mapa_query *q, int32_t nq, mapa_resu
   int32_t rc = ensure_batch_capacity(c, nq);
   if (rc) return rc;
   hipStream_t s = as_stream(stream);
-  if (++c->batches_since_slot_reset >= (1ull << 31)) {
-    // commit generations would wrap: clear every claim and restart at 1
-    HIPCHK(hipEventSynchronize(c->last));
-    HIPCHK(hipMemset(c->d_commit_slot, 0xFF, c->cap_servers * sizeof(unsigned long long)));
-    const uint32_t one = 1;
-    HIPCHK(hipMemcpy(&c->d_ctr->gen, &one, sizeof one, hipMemcpyHostToDevice));
-    HIPCHK(hipDeviceSynchronize());
-    c->batches_since_slot_reset = 1;
-  }
   BatchArgs a;
   std::memset(&a, 0, sizeof a);
   fill_args(c, a);

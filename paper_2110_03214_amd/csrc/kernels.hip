@@ -66,9 +66,12 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
   return v;
 }
 
-__device__ __forceinline__ unsigned long long commit_tag(uint32_t gen, uint32_t qi) {
-  return ((unsigned long long)(~gen) << 32) | qi;
-}
+// Commit arbitration: every committing query of a batch claims its server's
+// slot with atomicMin(query index); the holder of the minimum (the first
+// committing query in array order) is the only one allowed to commit, and it
+// resets the slot to "free" (all ones) in k_finalize, so slots are free
+// between batches and concurrent batches on disjoint servers never interact.
+constexpr unsigned long long kSlotFree = ~0ull;
 
 // ----------------------------------------------------------------- prepare
 
@@ -127,7 +130,7 @@ __global__ __launch_bounds__(256) void k_prepare(BatchArgs a) {
         }
         p.dsplit = ds;
       }
-      if (q.commit) atomicMin(&a.commit_slot[q.server], commit_tag(a.ctr->gen, (uint32_t)i));
+      if (q.commit) atomicMin(&a.commit_slot[q.server], (unsigned long long)i);
     }
     a.plan[i] = p;
     a.acc_count[i] = 0;
@@ -232,7 +235,6 @@ __global__ __launch_bounds__(512) void k_scan(BatchArgs a) {
     a.ctr->total_leaves = 0;
     for (int j = 0; j < kNumSplits; ++j) a.ctr->total_items[j] = 0;
     a.ctr->chunk_ctr = 0;
-    a.ctr->gen += 1u;  // finalize of this batch uses gen - 1
   }
 }
 
@@ -506,14 +508,17 @@ __global__ __launch_bounds__(256) void k_finalize(BatchArgs a) {
       r.status = MAPA_RES_OK;
       if ((int32_t)p.a * agg + (int32_t)p.b * pres != r.key)
         atomicAdd(&a.ctr->self_check_failures, 1u);
-      if (p.commit) {
-        if (a.commit_slot[p.server] == commit_tag(a.ctr->gen - 1u, (uint32_t)i)) {
-          atomicOr(&a.busy[p.server], S);
-          r.alloc_handle = ((int64_t)p.server << 32) | (int64_t)S;
-        } else {
-          r.status = MAPA_RES_CONFLICT;
-        }
+    }
+  }
+  if (p.status != kPlanInvalid && p.commit) {
+    if (a.commit_slot[p.server] == (unsigned long long)i) {
+      if (r.status == MAPA_RES_OK) {
+        atomicOr(&a.busy[p.server], r.vertex_mask);
+        r.alloc_handle = ((int64_t)p.server << 32) | (int64_t)r.vertex_mask;
       }
+      a.commit_slot[p.server] = kSlotFree;
+    } else if (r.status == MAPA_RES_OK) {
+      r.status = MAPA_RES_CONFLICT;
     }
   }
   a.res[i] = r;

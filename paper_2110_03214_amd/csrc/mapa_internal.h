@@ -62,10 +62,6 @@ struct Counters {
   uint32_t chosen_split;
   uint32_t self_check_failures;
   unsigned long long last_total_items;
-  // Commit generation: read by k_prepare, advanced by k_scan, so k_finalize
-  // of the same batch sees gen + 1.  Lives in device memory so that a
-  // captured batch graph stays correct on every replay.
-  uint32_t gen;
 };
 
 struct Tables {          // uploaded once per device into __constant__ memory
