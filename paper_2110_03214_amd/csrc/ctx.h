@@ -1,0 +1,132 @@
+// Context and workspace layout shared by the host core (host.cpp) and the
+// serving loop (serve.cpp).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <array>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "mapa.h"
+#include "mapa_internal.h"
+
+namespace mapa {
+
+int32_t fail(int32_t code, const char *fmt, ...);
+
+#define MAPA_HIPCHK(expr)                                                                 \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return ::mapa::fail(MAPA_ERR_DEVICE, "%s: %s", #expr, hipGetErrorString(e_));       \
+  } while (0)
+
+template <class T>
+hipError_t dev_alloc(T **p, size_t count) {
+  *p = nullptr;
+  if (count == 0) return hipSuccess;
+  return hipMalloc((void **)p, count * sizeof(T));
+}
+
+template <class T>
+void dev_free(T *&p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+// Everything one in-flight batch needs on the device: per-query plans and
+// accumulators, staging for host-pointer calls, the prefix work-list and the
+// per-batch counters.  Two batches in flight need two workspaces.
+struct Workspace {
+  size_t cap_q = 0;
+  Plan *d_plan = nullptr;
+  unsigned long long *d_acc_count = nullptr, *d_acc_best = nullptr;
+  mapa_query *d_q = nullptr;
+  mapa_result *d_res = nullptr;
+  uint2 *d_items = nullptr;
+  unsigned long long cap_items = 0;
+  Counters *d_ctr = nullptr;
+};
+
+int32_t ws_create(Workspace &w, size_t enum_bytes);
+int32_t ws_ensure_q(Workspace &w, size_t nq);  // no work may be in flight on w
+void ws_destroy(Workspace &w);
+
+struct ProfEvents {
+  hipEvent_t start, stop;
+};
+
+struct ServeState;  // serve.cpp
+
+}  // namespace mapa
+
+struct mapa_ctx {
+  int device = -1;
+  bool has_device = false;
+  int cu_count = 0;
+  hipStream_t internal = nullptr;
+  hipEvent_t last = nullptr;  // completion of the last issued call
+  size_t enum_bytes = 0;
+
+  // topologies (host copy is authoritative; device copies are derived)
+  std::vector<int32_t> topo_n;
+  std::vector<std::array<uint8_t, 256>> topo_W;  // 16x16 padded
+  int wpr = 1;
+  int32_t *d_topo_n = nullptr;
+  uint8_t *d_topo_W = nullptr;
+  uint32_t *d_rows = nullptr;
+  size_t cap_topos = 0;
+
+  // servers
+  std::vector<int32_t> server_topo;  // host mirror, immutable per server
+  int32_t *d_server_topo = nullptr;
+  uint32_t *d_busy = nullptr;
+  unsigned long long *d_commit_slot = nullptr;
+  size_t cap_servers = 0;
+
+  // the API calls' batch workspace
+  mapa::Workspace ws;
+  // small scratch for host-pointer state calls
+  int32_t *d_ids = nullptr;
+  uint32_t *d_masks = nullptr;
+  int64_t *d_handles = nullptr;
+  uint32_t *d_flag = nullptr;
+  size_t cap_small = 0;
+
+  // captured batch graphs (device-pointer batches with MAPA_USE_GRAPH)
+  struct Graph {
+    const void *q;
+    void *res;
+    int32_t nq;
+    hipStream_t stream;
+    uint64_t version;
+    hipGraphExec_t exec;
+  };
+  std::vector<Graph> graphs;
+  uint64_t version = 1;  // bumped whenever a value baked into a launch changes
+
+  mapa_tuning tuning{64, 4, 0, 256};
+  bool profile = false;
+  std::vector<mapa::ProfEvents> prof;
+  double prof_ms = 0;
+  int64_t prof_launches = 0;
+  int64_t batches = 0;
+
+  mapa::ServeState *serve = nullptr;  // non-null while the serving loop runs
+};
+
+namespace mapa {
+
+int32_t sync_ctx(mapa_ctx *c);
+void fill_args(mapa_ctx *c, const Workspace &w, BatchArgs &a);
+
+// Enqueue the whole batch pipeline (prepare .. finalize) for nq queries that
+// are already in device memory, writing nq results to d_res, on stream s.
+int32_t enqueue_batch(mapa_ctx *c, const Workspace &w, const mapa_query *d_q,
+                      mapa_result *d_res, int32_t nq, hipStream_t s);
+
+void serve_teardown(mapa_ctx *c);  // stop and free a running serving loop
+
+}  // namespace mapa

@@ -5,23 +5,21 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <array>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
 #include <new>
-#include <string>
 #include <utility>
-#include <vector>
 
-#include "mapa.h"
-#include "mapa_internal.h"
+#include "ctx.h"
 
 using namespace mapa;
 
-namespace {
+namespace mapa {
 
+namespace {
 thread_local std::string g_err;
+}
 
 int32_t fail(int32_t code, const char *fmt, ...) {
   char buf[512];
@@ -33,11 +31,111 @@ int32_t fail(int32_t code, const char *fmt, ...) {
   return code;
 }
 
-#define HIPCHK(expr)                                                                     \
-  do {                                                                                   \
-    hipError_t e_ = (expr);                                                              \
-    if (e_ != hipSuccess) return fail(MAPA_ERR_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
-  } while (0)
+const char *last_error() { return g_err.c_str(); }
+
+// ------------------------------------------------------------- workspace
+
+int32_t ws_create(Workspace &w, size_t enum_bytes) {
+  unsigned long long items = enum_bytes / sizeof(uint2);
+  items = std::min<unsigned long long>(items, 1ull << 31);
+  if (items < (unsigned long long)kPadReserve + 1024)
+    return fail(MAPA_ERR_INVALID_ARG, "enumeration buffer of %zu bytes too small (need >= %llu)",
+                enum_bytes, (unsigned long long)(kPadReserve + 1024) * sizeof(uint2));
+  if (dev_alloc(&w.d_items, items) != hipSuccess || dev_alloc(&w.d_ctr, 1) != hipSuccess) {
+    ws_destroy(w);
+    return fail(MAPA_ERR_OOM, "enumeration buffer of %zu bytes: allocation failed", enum_bytes);
+  }
+  w.cap_items = items;
+  MAPA_HIPCHK(hipMemset(w.d_ctr, 0, sizeof(Counters)));
+  return MAPA_OK;
+}
+
+int32_t ws_ensure_q(Workspace &w, size_t nq) {
+  if (nq <= w.cap_q) return MAPA_OK;
+  size_t cap = std::max<size_t>(1024, w.cap_q);
+  while (cap < nq) cap *= 2;
+  dev_free(w.d_plan);
+  dev_free(w.d_acc_count);
+  dev_free(w.d_acc_best);
+  dev_free(w.d_q);
+  dev_free(w.d_res);
+  w.cap_q = 0;
+  if (dev_alloc(&w.d_plan, cap) != hipSuccess || dev_alloc(&w.d_acc_count, cap) != hipSuccess ||
+      dev_alloc(&w.d_acc_best, cap) != hipSuccess || dev_alloc(&w.d_q, cap) != hipSuccess ||
+      dev_alloc(&w.d_res, cap) != hipSuccess)
+    return fail(MAPA_ERR_OOM, "batch workspace for %zu queries: device allocation failed", nq);
+  w.cap_q = cap;
+  return MAPA_OK;
+}
+
+void ws_destroy(Workspace &w) {
+  dev_free(w.d_plan);
+  dev_free(w.d_acc_count);
+  dev_free(w.d_acc_best);
+  dev_free(w.d_q);
+  dev_free(w.d_res);
+  dev_free(w.d_items);
+  dev_free(w.d_ctr);
+  w.cap_q = 0;
+  w.cap_items = 0;
+}
+
+// ------------------------------------------------------------- helpers
+
+int32_t sync_ctx(mapa_ctx *c) {
+  if (!c->has_device) return MAPA_OK;
+  MAPA_HIPCHK(hipSetDevice(c->device));
+  MAPA_HIPCHK(hipEventSynchronize(c->last));
+  return MAPA_OK;
+}
+
+void fill_args(mapa_ctx *c, const Workspace &w, BatchArgs &a) {
+  a.plan = w.d_plan;
+  a.acc_count = w.d_acc_count;
+  a.acc_best = w.d_acc_best;
+  a.items = w.d_items;
+  a.cap_items = w.cap_items;
+  a.ctr = w.d_ctr;
+  a.server_topo = c->d_server_topo;
+  a.busy = c->d_busy;
+  a.commit_slot = c->d_commit_slot;
+  a.nservers = (int32_t)c->server_topo.size();
+  a.topo_n = c->d_topo_n;
+  a.topo_W = c->d_topo_W;
+  a.rows = c->d_rows;
+  a.ntopo = (int32_t)c->topo_n.size();
+  a.wpr = c->wpr;
+  a.min_leaves = std::max(1, c->tuning.min_leaves_per_item);
+  const int threads = c->tuning.threads_per_block;
+  const size_t lds_bytes = (size_t)a.ntopo * 16 * c->wpr * sizeof(uint32_t);
+  a.rows_in_lds = lds_bytes <= 48 * 1024 ? 1 : 0;
+  int per_cu = c->tuning.blocks_per_cu;
+  if (per_cu <= 0) per_cu = enumerate_occupancy(c->wpr, a.rows_in_lds, threads, lds_bytes);
+  if (per_cu <= 0) per_cu = 4;
+  a.enum_blocks = std::max(1, c->cu_count) * per_cu;
+  a.enum_threads = threads;
+  const unsigned long long lanes = (unsigned long long)std::max(1, c->cu_count) * per_cu * threads;
+  a.target_items =
+      std::max<unsigned long long>(1, lanes * (unsigned long long)std::max(1, c->tuning.items_per_lane));
+}
+
+int32_t enqueue_batch(mapa_ctx *c, const Workspace &w, const mapa_query *d_q, mapa_result *d_res,
+                      int32_t nq, hipStream_t s) {
+  BatchArgs a;
+  std::memset(&a, 0, sizeof a);
+  fill_args(c, w, a);
+  a.nq = nq;
+  a.q = d_q;
+  a.res = d_res;
+  MAPA_HIPCHK(launch_batch_front(a, s));
+  MAPA_HIPCHK(launch_enumerate(a, s));
+  MAPA_HIPCHK(launch_finalize(a, s));
+  return MAPA_OK;
+}
+
+}  // namespace mapa
+
+namespace {
 
 constexpr size_t kDefaultEnumBytes = 256ull << 20;
 
@@ -78,96 +176,14 @@ int weight_class(const uint8_t *W, int n) {
   return mx <= 3 ? 1 : mx <= 15 ? 2 : 4;
 }
 
-template <class T>
-hipError_t dev_alloc(T **p, size_t count) {
-  *p = nullptr;
-  if (count == 0) return hipSuccess;
-  return hipMalloc((void **)p, count * sizeof(T));
-}
-
-template <class T>
-void dev_free(T *&p) {
-  if (p) (void)hipFree(p);
-  p = nullptr;
-}
-
-struct ProfEvents {
-  hipEvent_t start, stop;
-};
-
-}  // namespace
-
-struct mapa_ctx {
-  int device = -1;
-  bool has_device = false;
-  int cu_count = 0;
-  hipStream_t internal = nullptr;
-  hipEvent_t last = nullptr;  // completion of the last issued call
-
-  // topologies (host copy is authoritative; device copies are derived)
-  std::vector<int32_t> topo_n;
-  std::vector<std::array<uint8_t, 256>> topo_W;  // 16x16 padded
-  int wpr = 1;
-  int32_t *d_topo_n = nullptr;
-  uint8_t *d_topo_W = nullptr;
-  uint32_t *d_rows = nullptr;
-  size_t cap_topos = 0;
-
-  // servers
-  std::vector<int32_t> server_topo;  // host mirror, immutable per server
-  int32_t *d_server_topo = nullptr;
-  uint32_t *d_busy = nullptr;
-  unsigned long long *d_commit_slot = nullptr;
-  size_t cap_servers = 0;
-
-  // batch workspace
-  size_t cap_q = 0;
-  Plan *d_plan = nullptr;
-  unsigned long long *d_acc_count = nullptr, *d_acc_best = nullptr;
-  mapa_query *d_q = nullptr;
-  mapa_result *d_res = nullptr;
-  uint2 *d_items = nullptr;
-  unsigned long long cap_items = 0;
-  Counters *d_ctr = nullptr;
-  // small scratch for host-pointer state calls
-  int32_t *d_ids = nullptr;
-  uint32_t *d_masks = nullptr;
-  int64_t *d_handles = nullptr;
-  uint32_t *d_flag = nullptr;
-  size_t cap_small = 0;
-
-  // captured batch graphs (device-pointer batches with MAPA_USE_GRAPH)
-  struct Graph {
-    const void *q;
-    void *res;
-    int32_t nq;
-    hipStream_t stream;
-    uint64_t version;
-    hipGraphExec_t exec;
-  };
-  std::vector<Graph> graphs;
-  uint64_t version = 1;  // bumped whenever a value baked into a launch changes
-
-  mapa_tuning tuning{64, 4, 0, 256};
-  bool profile = false;
-  std::vector<ProfEvents> prof;
-  double prof_ms = 0;
-  int64_t prof_launches = 0;
-  int64_t batches = 0;
-};
-
-namespace {
-
 hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
 // Order this call after every earlier call of the context.
 hipError_t begin_call(mapa_ctx *c, hipStream_t s) { return hipStreamWaitEvent(s, c->last, 0); }
 hipError_t end_call(mapa_ctx *c, hipStream_t s) { return hipEventRecord(c->last, s); }
 
-int32_t sync_ctx(mapa_ctx *c) {
-  if (!c->has_device) return MAPA_OK;
-  HIPCHK(hipSetDevice(c->device));
-  HIPCHK(hipEventSynchronize(c->last));
+int32_t not_while_serving(mapa_ctx *c, const char *fn) {
+  if (c->serve) return fail(MAPA_ERR_STATE, "%s: the serving loop owns the context", fn);
   return MAPA_OK;
 }
 
@@ -207,9 +223,9 @@ int32_t upload_topologies(mapa_ctx *c) {
     std::memcpy(&W[t * 256], c->topo_W[t].data(), 256);
     build_rows(c->topo_W[t].data(), c->topo_n[t], c->wpr, &rows[t * 16 * c->wpr]);
   }
-  HIPCHK(hipMemcpy(c->d_topo_n, c->topo_n.data(), T * sizeof(int32_t), hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(c->d_topo_W, W.data(), W.size(), hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(c->d_rows, rows.data(), rows.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+  MAPA_HIPCHK(hipMemcpy(c->d_topo_n, c->topo_n.data(), T * sizeof(int32_t), hipMemcpyHostToDevice));
+  MAPA_HIPCHK(hipMemcpy(c->d_topo_W, W.data(), W.size(), hipMemcpyHostToDevice));
+  MAPA_HIPCHK(hipMemcpy(c->d_rows, rows.data(), rows.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
   return MAPA_OK;
 }
 
@@ -227,14 +243,14 @@ int32_t grow_servers(mapa_ctx *c, size_t need) {
     dev_free(slot);
     return fail(MAPA_ERR_OOM, "server tables: device allocation failed");
   }
-  HIPCHK(hipMemset(busy, 0, cap * sizeof(uint32_t)));
-  HIPCHK(hipMemset(st, 0, cap * sizeof(int32_t)));
-  HIPCHK(hipMemset(slot, 0xFF, cap * sizeof(unsigned long long)));
+  MAPA_HIPCHK(hipMemset(busy, 0, cap * sizeof(uint32_t)));
+  MAPA_HIPCHK(hipMemset(st, 0, cap * sizeof(int32_t)));
+  MAPA_HIPCHK(hipMemset(slot, 0xFF, cap * sizeof(unsigned long long)));
   if (c->cap_servers) {
-    HIPCHK(hipMemcpy(st, c->d_server_topo, c->cap_servers * sizeof(int32_t), hipMemcpyDeviceToDevice));
-    HIPCHK(hipMemcpy(busy, c->d_busy, c->cap_servers * sizeof(uint32_t), hipMemcpyDeviceToDevice));
-    HIPCHK(hipMemcpy(slot, c->d_commit_slot, c->cap_servers * sizeof(unsigned long long),
-                     hipMemcpyDeviceToDevice));
+    MAPA_HIPCHK(hipMemcpy(st, c->d_server_topo, c->cap_servers * sizeof(int32_t), hipMemcpyDeviceToDevice));
+    MAPA_HIPCHK(hipMemcpy(busy, c->d_busy, c->cap_servers * sizeof(uint32_t), hipMemcpyDeviceToDevice));
+    MAPA_HIPCHK(hipMemcpy(slot, c->d_commit_slot, c->cap_servers * sizeof(unsigned long long),
+                          hipMemcpyDeviceToDevice));
   }
   dev_free(c->d_server_topo);
   dev_free(c->d_busy);
@@ -253,24 +269,11 @@ void drop_graphs(mapa_ctx *c) {
 }
 
 int32_t ensure_batch_capacity(mapa_ctx *c, size_t nq) {
-  if (nq <= c->cap_q) return MAPA_OK;
+  if (nq <= c->ws.cap_q) return MAPA_OK;
   int32_t rc = sync_ctx(c);
   if (rc) return rc;
   drop_graphs(c);
-  size_t cap = std::max<size_t>(1024, c->cap_q);
-  while (cap < nq) cap *= 2;
-  dev_free(c->d_plan);
-  dev_free(c->d_acc_count);
-  dev_free(c->d_acc_best);
-  dev_free(c->d_q);
-  dev_free(c->d_res);
-  c->cap_q = 0;
-  if (dev_alloc(&c->d_plan, cap) != hipSuccess || dev_alloc(&c->d_acc_count, cap) != hipSuccess ||
-      dev_alloc(&c->d_acc_best, cap) != hipSuccess || dev_alloc(&c->d_q, cap) != hipSuccess ||
-      dev_alloc(&c->d_res, cap) != hipSuccess)
-    return fail(MAPA_ERR_OOM, "batch workspace for %zu queries: device allocation failed", nq);
-  c->cap_q = cap;
-  return MAPA_OK;
+  return ws_ensure_q(c->ws, nq);
 }
 
 int32_t ensure_small(mapa_ctx *c, size_t n) {
@@ -305,48 +308,20 @@ int32_t validate_query(const mapa_ctx *c, const mapa_query &q, int32_t i) {
   return MAPA_OK;
 }
 
-void fill_args(mapa_ctx *c, BatchArgs &a) {
-  a.plan = c->d_plan;
-  a.acc_count = c->d_acc_count;
-  a.acc_best = c->d_acc_best;
-  a.items = c->d_items;
-  a.cap_items = c->cap_items;
-  a.ctr = c->d_ctr;
-  a.server_topo = c->d_server_topo;
-  a.busy = c->d_busy;
-  a.commit_slot = c->d_commit_slot;
-  a.nservers = (int32_t)c->server_topo.size();
-  a.topo_n = c->d_topo_n;
-  a.topo_W = c->d_topo_W;
-  a.rows = c->d_rows;
-  a.ntopo = (int32_t)c->topo_n.size();
-  a.wpr = c->wpr;
-  a.min_leaves = std::max(1, c->tuning.min_leaves_per_item);
-  const int threads = c->tuning.threads_per_block;
-  const size_t lds_bytes = (size_t)a.ntopo * 16 * c->wpr * sizeof(uint32_t);
-  a.rows_in_lds = lds_bytes <= 48 * 1024 ? 1 : 0;
-  int per_cu = c->tuning.blocks_per_cu;
-  if (per_cu <= 0) per_cu = enumerate_occupancy(c->wpr, a.rows_in_lds, threads, lds_bytes);
-  if (per_cu <= 0) per_cu = 4;
-  a.enum_blocks = std::max(1, c->cu_count) * per_cu;
-  a.enum_threads = threads;
-  const unsigned long long lanes = (unsigned long long)std::max(1, c->cu_count) * per_cu * threads;
-  a.target_items = std::max<unsigned long long>(1, lanes * (unsigned long long)std::max(1, c->tuning.items_per_lane));
-}
-
 }  // namespace
 
 // =================================================================== ABI
 
 extern "C" {
 
-const char *mapa_last_error(void) { return g_err.c_str(); }
+const char *mapa_last_error(void) { return mapa::last_error(); }
 
 int32_t mapa_ctx_create(int32_t device, size_t enum_buffer_bytes, mapa_ctx **out) {
   if (!out) return fail(MAPA_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
   mapa_ctx *c = new (std::nothrow) mapa_ctx();
   if (!c) return fail(MAPA_ERR_OOM, "context allocation failed");
+  c->enum_bytes = enum_buffer_bytes ? enum_buffer_bytes : kDefaultEnumBytes;
   if (device < 0) {  // validation-only context
     *out = c;
     return MAPA_OK;
@@ -374,24 +349,17 @@ int32_t mapa_ctx_create(int32_t device, size_t enum_buffer_bytes, mapa_ctx **out
     return bail(fail(MAPA_ERR_DEVICE, "hipEventRecord failed"));
   const Tables t = build_tables();
   if (upload_tables(t) != hipSuccess) return bail(fail(MAPA_ERR_DEVICE, "table upload failed"));
-  size_t bytes = enum_buffer_bytes ? enum_buffer_bytes : kDefaultEnumBytes;
-  unsigned long long items = bytes / sizeof(uint2);
-  items = std::min<unsigned long long>(items, 1ull << 31);
-  if (items < (unsigned long long)kPadReserve + 1024)
-    return bail(fail(MAPA_ERR_INVALID_ARG, "enum_buffer_bytes %zu too small (need >= %llu)", bytes,
-                     (unsigned long long)(kPadReserve + 1024) * sizeof(uint2)));
-  if (dev_alloc(&c->d_items, items) != hipSuccess || dev_alloc(&c->d_ctr, 1) != hipSuccess ||
-      dev_alloc(&c->d_flag, 1) != hipSuccess)
-    return bail(fail(MAPA_ERR_OOM, "enumeration buffer of %zu bytes: allocation failed", bytes));
-  c->cap_items = items;
-  if (hipMemset(c->d_ctr, 0, sizeof(Counters)) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
-    return bail(fail(MAPA_ERR_DEVICE, "counter init failed"));
+  int32_t rc = ws_create(c->ws, c->enum_bytes);
+  if (rc) return bail(rc);
+  if (dev_alloc(&c->d_flag, 1) != hipSuccess) return bail(fail(MAPA_ERR_OOM, "flag allocation failed"));
+  if (hipDeviceSynchronize() != hipSuccess) return bail(fail(MAPA_ERR_DEVICE, "device init failed"));
   *out = c;
   return MAPA_OK;
 }
 
 int32_t mapa_ctx_destroy(mapa_ctx *c) {
   if (!c) return MAPA_OK;
+  serve_teardown(c);
   if (c->has_device) {
     (void)hipSetDevice(c->device);
     if (c->last) (void)hipEventSynchronize(c->last);
@@ -407,13 +375,7 @@ int32_t mapa_ctx_destroy(mapa_ctx *c) {
     dev_free(c->d_server_topo);
     dev_free(c->d_busy);
     dev_free(c->d_commit_slot);
-    dev_free(c->d_plan);
-    dev_free(c->d_acc_count);
-    dev_free(c->d_acc_best);
-    dev_free(c->d_q);
-    dev_free(c->d_res);
-    dev_free(c->d_items);
-    dev_free(c->d_ctr);
+    ws_destroy(c->ws);
     dev_free(c->d_ids);
     dev_free(c->d_masks);
     dev_free(c->d_handles);
@@ -428,6 +390,7 @@ int32_t mapa_ctx_destroy(mapa_ctx *c) {
 int32_t mapa_create_topology(mapa_ctx *c, int32_t n, const uint8_t *W, int32_t num_servers,
                              int32_t *topo_id, int32_t *first_server) {
   if (!c) return fail(MAPA_ERR_INVALID_ARG, "ctx is NULL");
+  if (int32_t rc = not_while_serving(c, "mapa_create_topology")) return rc;
   if (n < 1) return fail(MAPA_ERR_INVALID_ARG, "n=%d < 1", n);
   if (n > kMaxN) return fail(MAPA_ERR_UNSUPPORTED, "n=%d > %d", n, kMaxN);
   if (!W) return fail(MAPA_ERR_INVALID_ARG, "W is NULL");
@@ -449,8 +412,8 @@ int32_t mapa_create_topology(mapa_ctx *c, int32_t n, const uint8_t *W, int32_t n
   if (c->has_device) {
     int32_t rc = sync_ctx(c);
     if (rc) return rc;
-    HIPCHK(hipSetDevice(c->device));
     drop_graphs(c);
+    const int old_wpr = c->wpr;
     c->topo_n.push_back(n);
     c->topo_W.push_back(w16);
     c->wpr = std::max(c->wpr, weight_class(W, n));
@@ -459,13 +422,14 @@ int32_t mapa_create_topology(mapa_ctx *c, int32_t n, const uint8_t *W, int32_t n
     if (rc) {
       c->topo_n.pop_back();
       c->topo_W.pop_back();
+      c->wpr = old_wpr;
       return rc;
     }
     if (num_servers > 0) {
       std::vector<int32_t> ids(num_servers, tid);
-      HIPCHK(hipMemcpy(c->d_server_topo + first, ids.data(), num_servers * sizeof(int32_t),
-                       hipMemcpyHostToDevice));
-      HIPCHK(hipMemset(c->d_busy + first, 0, num_servers * sizeof(uint32_t)));
+      MAPA_HIPCHK(hipMemcpy(c->d_server_topo + first, ids.data(), num_servers * sizeof(int32_t),
+                            hipMemcpyHostToDevice));
+      MAPA_HIPCHK(hipMemset(c->d_busy + first, 0, num_servers * sizeof(uint32_t)));
     }
   } else {
     c->topo_n.push_back(n);
@@ -480,6 +444,7 @@ int32_t mapa_create_topology(mapa_ctx *c, int32_t n, const uint8_t *W, int32_t n
 int32_t mapa_set_busy(mapa_ctx *c, int32_t count, const int32_t *ids, const uint32_t *masks,
                       uint32_t flags, void *stream) {
   if (!c) return fail(MAPA_ERR_INVALID_ARG, "ctx is NULL");
+  if (int32_t rc = not_while_serving(c, "mapa_set_busy")) return rc;
   if (count < 0) return fail(MAPA_ERR_INVALID_ARG, "count < 0");
   if (count == 0) return MAPA_OK;
   if (!ids || !masks) return fail(MAPA_ERR_INVALID_ARG, "NULL array");
@@ -495,30 +460,31 @@ int32_t mapa_set_busy(mapa_ctx *c, int32_t count, const int32_t *ids, const uint
     }
   }
   if (!c->has_device) return fail(MAPA_ERR_NO_DEVICE, "context has no device");
-  HIPCHK(hipSetDevice(c->device));
+  MAPA_HIPCHK(hipSetDevice(c->device));
   hipStream_t s = as_stream(stream);
   const int32_t *d_ids = ids;
   const uint32_t *d_masks = masks;
   if (!dev) {
     int32_t rc = ensure_small(c, count);
     if (rc) return rc;
-    HIPCHK(begin_call(c, s));
-    HIPCHK(hipMemcpyAsync(c->d_ids, ids, count * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(c->d_masks, masks, count * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+    MAPA_HIPCHK(begin_call(c, s));
+    MAPA_HIPCHK(hipMemcpyAsync(c->d_ids, ids, count * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    MAPA_HIPCHK(hipMemcpyAsync(c->d_masks, masks, count * sizeof(uint32_t), hipMemcpyHostToDevice, s));
     d_ids = c->d_ids;
     d_masks = c->d_masks;
   } else {
-    HIPCHK(begin_call(c, s));
+    MAPA_HIPCHK(begin_call(c, s));
   }
-  HIPCHK(launch_set_busy(d_ids, d_masks, count, (int32_t)c->server_topo.size(), c->d_server_topo,
-                         c->d_topo_n, c->d_busy, s));
-  HIPCHK(end_call(c, s));
-  if (!dev) HIPCHK(hipStreamSynchronize(s));
+  MAPA_HIPCHK(launch_set_busy(d_ids, d_masks, count, (int32_t)c->server_topo.size(),
+                              c->d_server_topo, c->d_topo_n, c->d_busy, s));
+  MAPA_HIPCHK(end_call(c, s));
+  if (!dev) MAPA_HIPCHK(hipStreamSynchronize(s));
   return MAPA_OK;
 }
 
 int32_t mapa_get_busy(mapa_ctx *c, int32_t count, const int32_t *ids, uint32_t *out) {
   if (!c) return fail(MAPA_ERR_INVALID_ARG, "ctx is NULL");
+  if (int32_t rc = not_while_serving(c, "mapa_get_busy")) return rc;
   if (count < 0) return fail(MAPA_ERR_INVALID_ARG, "count < 0");
   if (count == 0) return MAPA_OK;
   if (!ids || !out) return fail(MAPA_ERR_INVALID_ARG, "NULL array");
@@ -526,22 +492,23 @@ int32_t mapa_get_busy(mapa_ctx *c, int32_t count, const int32_t *ids, uint32_t *
     if (ids[i] < 0 || (size_t)ids[i] >= c->server_topo.size())
       return fail(MAPA_ERR_UNKNOWN_SERVER, "entry %d: unknown server %d", i, ids[i]);
   if (!c->has_device) return fail(MAPA_ERR_NO_DEVICE, "context has no device");
-  HIPCHK(hipSetDevice(c->device));
+  MAPA_HIPCHK(hipSetDevice(c->device));
   int32_t rc = ensure_small(c, count);
   if (rc) return rc;
   hipStream_t s = c->internal;
-  HIPCHK(begin_call(c, s));
-  HIPCHK(hipMemcpyAsync(c->d_ids, ids, count * sizeof(int32_t), hipMemcpyHostToDevice, s));
-  HIPCHK(launch_get_busy(c->d_ids, count, c->d_busy, c->d_masks, s));
-  HIPCHK(hipMemcpyAsync(out, c->d_masks, count * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-  HIPCHK(end_call(c, s));
-  HIPCHK(hipStreamSynchronize(s));
+  MAPA_HIPCHK(begin_call(c, s));
+  MAPA_HIPCHK(hipMemcpyAsync(c->d_ids, ids, count * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  MAPA_HIPCHK(launch_get_busy(c->d_ids, count, c->d_busy, c->d_masks, s));
+  MAPA_HIPCHK(hipMemcpyAsync(out, c->d_masks, count * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  MAPA_HIPCHK(end_call(c, s));
+  MAPA_HIPCHK(hipStreamSynchronize(s));
   return MAPA_OK;
 }
 
 int32_t mapa_query_batch(mapa_ctx *c, const mapa_query *q, int32_t nq, mapa_result *res,
                          uint32_t flags, void *stream) {
   if (!c) return fail(MAPA_ERR_INVALID_ARG, "ctx is NULL");
+  if (int32_t rc = not_while_serving(c, "mapa_query_batch")) return rc;
   if (nq < 0) return fail(MAPA_ERR_INVALID_ARG, "nq < 0");
   if (nq == 0) return MAPA_OK;
   if (!q || !res) return fail(MAPA_ERR_INVALID_ARG, "NULL array");
@@ -552,22 +519,16 @@ int32_t mapa_query_batch(mapa_ctx *c, const mapa_query *q, int32_t nq, mapa_resu
       if (rc) return rc;
     }
   if (!c->has_device) return fail(MAPA_ERR_NO_DEVICE, "context has no device");
-  if ((unsigned long long)nq + kPadReserve > c->cap_items)
+  if ((unsigned long long)nq + kPadReserve > c->ws.cap_items)
     return fail(MAPA_ERR_ADMISSION, "batch of %d queries exceeds the enumeration buffer (%llu items)",
-                nq, c->cap_items);
+                nq, c->ws.cap_items);
   if (c->server_topo.empty()) return fail(MAPA_ERR_UNKNOWN_SERVER, "no servers created");
-  HIPCHK(hipSetDevice(c->device));
+  MAPA_HIPCHK(hipSetDevice(c->device));
   int32_t rc = ensure_batch_capacity(c, nq);
   if (rc) return rc;
   hipStream_t s = as_stream(stream);
-  BatchArgs a;
-  std::memset(&a, 0, sizeof a);
-  fill_args(c, a);
-  a.nq = nq;
   const bool use_graph = dev && (flags & MAPA_USE_GRAPH) && !c->profile;
   if (use_graph) {
-    a.q = q;
-    a.res = res;
     mapa_ctx::Graph *g = nullptr;
     for (auto &e : c->graphs)
       if (e.q == q && e.res == res && e.nq == nq && e.stream == s && e.version == c->version) g = &e;
@@ -575,60 +536,64 @@ int32_t mapa_query_batch(mapa_ctx *c, const mapa_query *q, int32_t nq, mapa_resu
       if (c->graphs.size() >= 16) drop_graphs(c);
       hipGraph_t graph = nullptr;
       hipGraphExec_t exec = nullptr;
-      HIPCHK(hipStreamBeginCapture(c->internal, hipStreamCaptureModeRelaxed));
-      hipError_t e1 = launch_batch_front(a, c->internal);
-      hipError_t e2 = e1 == hipSuccess ? launch_enumerate(a, c->internal) : e1;
-      hipError_t e3 = e2 == hipSuccess ? launch_finalize(a, c->internal) : e2;
-      hipError_t ec = hipStreamEndCapture(c->internal, &graph);
-      if (e3 != hipSuccess || ec != hipSuccess) {
+      MAPA_HIPCHK(hipStreamBeginCapture(c->internal, hipStreamCaptureModeRelaxed));
+      const int32_t ecap = enqueue_batch(c, c->ws, q, res, nq, c->internal);
+      const hipError_t eend = hipStreamEndCapture(c->internal, &graph);
+      if (ecap != MAPA_OK || eend != hipSuccess) {
         if (graph) (void)hipGraphDestroy(graph);
-        return fail(MAPA_ERR_DEVICE, "graph capture failed: %s",
-                    hipGetErrorString(e3 != hipSuccess ? e3 : ec));
+        return ecap != MAPA_OK ? ecap
+                               : fail(MAPA_ERR_DEVICE, "graph capture: %s", hipGetErrorString(eend));
       }
-      hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
       (void)hipGraphDestroy(graph);
       if (ei != hipSuccess) return fail(MAPA_ERR_DEVICE, "graph instantiate: %s", hipGetErrorString(ei));
       c->graphs.push_back({q, res, nq, s, c->version, exec});
       g = &c->graphs.back();
     }
-    HIPCHK(begin_call(c, s));
-    HIPCHK(hipGraphLaunch(g->exec, s));
-    HIPCHK(end_call(c, s));
+    MAPA_HIPCHK(begin_call(c, s));
+    MAPA_HIPCHK(hipGraphLaunch(g->exec, s));
+    MAPA_HIPCHK(end_call(c, s));
     ++c->batches;
     return MAPA_OK;
   }
-  HIPCHK(begin_call(c, s));
+  MAPA_HIPCHK(begin_call(c, s));
+  const mapa_query *dq = q;
+  mapa_result *dr = res;
   if (!dev) {
-    HIPCHK(hipMemcpyAsync(c->d_q, q, nq * sizeof(mapa_query), hipMemcpyHostToDevice, s));
-    a.q = c->d_q;
-    a.res = c->d_res;
-  } else {
-    a.q = q;
-    a.res = res;
+    MAPA_HIPCHK(hipMemcpyAsync(c->ws.d_q, q, nq * sizeof(mapa_query), hipMemcpyHostToDevice, s));
+    dq = c->ws.d_q;
+    dr = c->ws.d_res;
   }
-  HIPCHK(launch_batch_front(a, s));
+  BatchArgs a;
+  std::memset(&a, 0, sizeof a);
+  fill_args(c, c->ws, a);
+  a.nq = nq;
+  a.q = dq;
+  a.res = dr;
+  MAPA_HIPCHK(launch_batch_front(a, s));
   ProfEvents ev{};
   if (c->profile) {
-    HIPCHK(hipEventCreate(&ev.start));
-    HIPCHK(hipEventCreate(&ev.stop));
-    HIPCHK(hipEventRecord(ev.start, s));
+    MAPA_HIPCHK(hipEventCreate(&ev.start));
+    MAPA_HIPCHK(hipEventCreate(&ev.stop));
+    MAPA_HIPCHK(hipEventRecord(ev.start, s));
   }
-  HIPCHK(launch_enumerate(a, s));
+  MAPA_HIPCHK(launch_enumerate(a, s));
   if (c->profile) {
-    HIPCHK(hipEventRecord(ev.stop, s));
+    MAPA_HIPCHK(hipEventRecord(ev.stop, s));
     c->prof.push_back(ev);
   }
-  HIPCHK(launch_finalize(a, s));
-  if (!dev) HIPCHK(hipMemcpyAsync(res, c->d_res, nq * sizeof(mapa_result), hipMemcpyDeviceToHost, s));
-  HIPCHK(end_call(c, s));
+  MAPA_HIPCHK(launch_finalize(a, s));
+  if (!dev) MAPA_HIPCHK(hipMemcpyAsync(res, c->ws.d_res, nq * sizeof(mapa_result), hipMemcpyDeviceToHost, s));
+  MAPA_HIPCHK(end_call(c, s));
   ++c->batches;
-  if (!dev) HIPCHK(hipStreamSynchronize(s));
+  if (!dev) MAPA_HIPCHK(hipStreamSynchronize(s));
   return MAPA_OK;
 }
 
 int32_t mapa_release(mapa_ctx *c, int32_t count, const int64_t *handles, int32_t stride,
                      uint32_t flags, void *stream) {
   if (!c) return fail(MAPA_ERR_INVALID_ARG, "ctx is NULL");
+  if (int32_t rc = not_while_serving(c, "mapa_release")) return rc;
   if (count < 0) return fail(MAPA_ERR_INVALID_ARG, "count < 0");
   if (count == 0) return MAPA_OK;
   if (!handles) return fail(MAPA_ERR_INVALID_ARG, "handles is NULL");
@@ -667,32 +632,33 @@ int32_t mapa_release(mapa_ctx *c, int32_t count, const int64_t *handles, int32_t
   }
   if (!dev && h.empty()) return MAPA_OK;
   if (!c->has_device) return fail(MAPA_ERR_NO_DEVICE, "context has no device");
-  HIPCHK(hipSetDevice(c->device));
+  MAPA_HIPCHK(hipSetDevice(c->device));
   if (dev) {
     hipStream_t s = as_stream(stream);
-    HIPCHK(begin_call(c, s));
-    HIPCHK(launch_release_apply(handles, stride, count, (int32_t)c->server_topo.size(), c->d_busy, s));
-    HIPCHK(end_call(c, s));
+    MAPA_HIPCHK(begin_call(c, s));
+    MAPA_HIPCHK(launch_release_apply(handles, stride, count, (int32_t)c->server_topo.size(),
+                                     c->d_busy, s));
+    MAPA_HIPCHK(end_call(c, s));
     return MAPA_OK;
   }
   int32_t rc = ensure_small(c, h.size());
   if (rc) return rc;
   hipStream_t s = c->internal;
   uint32_t flag = 0;
-  HIPCHK(begin_call(c, s));
-  HIPCHK(hipMemcpyAsync(c->d_handles, h.data(), h.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
-  HIPCHK(hipMemsetAsync(c->d_flag, 0, sizeof(uint32_t), s));
-  HIPCHK(launch_release_check(c->d_handles, 8, (int32_t)h.size(), c->d_busy, c->d_flag, s));
-  HIPCHK(hipMemcpyAsync(&flag, c->d_flag, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
+  MAPA_HIPCHK(begin_call(c, s));
+  MAPA_HIPCHK(hipMemcpyAsync(c->d_handles, h.data(), h.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
+  MAPA_HIPCHK(hipMemsetAsync(c->d_flag, 0, sizeof(uint32_t), s));
+  MAPA_HIPCHK(launch_release_check(c->d_handles, 8, (int32_t)h.size(), c->d_busy, c->d_flag, s));
+  MAPA_HIPCHK(hipMemcpyAsync(&flag, c->d_flag, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  MAPA_HIPCHK(hipStreamSynchronize(s));
   if (flag) {
-    HIPCHK(end_call(c, s));
+    MAPA_HIPCHK(end_call(c, s));
     return fail(MAPA_ERR_NOT_BUSY, "a released vertex is not busy; nothing released");
   }
-  HIPCHK(launch_release_apply(c->d_handles, 8, (int32_t)h.size(), (int32_t)c->server_topo.size(),
-                              c->d_busy, s));
-  HIPCHK(end_call(c, s));
-  HIPCHK(hipStreamSynchronize(s));
+  MAPA_HIPCHK(launch_release_apply(c->d_handles, 8, (int32_t)h.size(), (int32_t)c->server_topo.size(),
+                                   c->d_busy, s));
+  MAPA_HIPCHK(end_call(c, s));
+  MAPA_HIPCHK(hipStreamSynchronize(s));
   return MAPA_OK;
 }
 
@@ -704,6 +670,7 @@ int32_t mapa_get_tuning(mapa_ctx *c, mapa_tuning *out) {
 
 int32_t mapa_set_tuning(mapa_ctx *c, const mapa_tuning *in) {
   if (!c) return fail(MAPA_ERR_INVALID_ARG, "ctx is NULL");
+  if (int32_t rc = not_while_serving(c, "mapa_set_tuning")) return rc;
   if (!in) return MAPA_OK;
   if (in->min_leaves_per_item < 1 || in->min_leaves_per_item > (1 << 20))
     return fail(MAPA_ERR_INVALID_ARG, "min_leaves_per_item outside 1..2^20");
@@ -731,6 +698,7 @@ int32_t mapa_profile(mapa_ctx *c, int32_t enable) {
 int32_t mapa_get_stats(mapa_ctx *c, mapa_stats *out) {
   if (!c) return fail(MAPA_ERR_INVALID_ARG, "ctx is NULL");
   if (!out) return fail(MAPA_ERR_INVALID_ARG, "out is NULL");
+  if (int32_t rc = not_while_serving(c, "mapa_get_stats")) return rc;
   std::memset(out, 0, sizeof *out);
   out->num_servers = (int32_t)c->server_topo.size();
   out->num_topologies = (int32_t)c->topo_n.size();
@@ -741,7 +709,7 @@ int32_t mapa_get_stats(mapa_ctx *c, mapa_stats *out) {
     if (rc) return rc;
     for (auto &e : c->prof) {
       float ms = 0;
-      HIPCHK(hipEventElapsedTime(&ms, e.start, e.stop));
+      MAPA_HIPCHK(hipEventElapsedTime(&ms, e.start, e.stop));
       c->prof_ms += ms;
       ++c->prof_launches;
       (void)hipEventDestroy(e.start);
@@ -749,7 +717,7 @@ int32_t mapa_get_stats(mapa_ctx *c, mapa_stats *out) {
     }
     c->prof.clear();
     Counters h;
-    HIPCHK(hipMemcpy(&h, c->d_ctr, sizeof h, hipMemcpyDeviceToHost));
+    MAPA_HIPCHK(hipMemcpy(&h, c->ws.d_ctr, sizeof h, hipMemcpyDeviceToHost));
     out->last_items = (int64_t)h.last_total_items;
     out->last_split = (int32_t)h.chosen_split;
     out->self_check_failures = h.self_check_failures;
@@ -761,6 +729,7 @@ int32_t mapa_get_stats(mapa_ctx *c, mapa_stats *out) {
 
 int32_t mapa_reset_stats(mapa_ctx *c) {
   if (!c) return fail(MAPA_ERR_INVALID_ARG, "ctx is NULL");
+  if (int32_t rc = not_while_serving(c, "mapa_reset_stats")) return rc;
   int32_t rc = sync_ctx(c);
   if (rc) return rc;
   for (auto &e : c->prof) {
@@ -776,6 +745,7 @@ int32_t mapa_reset_stats(mapa_ctx *c) {
 
 int32_t mapa_sync(mapa_ctx *c) {
   if (!c) return fail(MAPA_ERR_INVALID_ARG, "ctx is NULL");
+  if (int32_t rc = not_while_serving(c, "mapa_sync")) return rc;
   return sync_ctx(c);
 }
 
