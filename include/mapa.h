@@ -245,6 +245,89 @@ int32_t mapa_reset_stats(mapa_ctx *ctx);
 /* Block until all work issued on the context has finished. */
 int32_t mapa_sync(mapa_ctx *ctx);
 
+/* ---- serving loop (continuous batching) -------------------------------------
+ * A context can run one serving loop: a host thread owned by the context that
+ * takes allocation requests as they arrive, answers each one against the
+ * device-resident busy masks of its server (Sec. 3.3-3.5), marks granted
+ * accelerators busy, holds them for the requested time and then adds them
+ * back (Sec. 3.6).  While the loop runs it owns the context: every other call
+ * except mapa_serve_* and mapa_last_error returns MAPA_ERR_STATE.
+ *
+ * Scheduling.  Requests of one server are answered one at a time in arrival
+ * order (first in, first out per server), each against the busy mask left by
+ * every earlier request and release of that server.  Requests of different
+ * servers are batched together.  Up to `inflight` device batches run at once,
+ * each on its own stream and workspace, so requests that arrive while a batch
+ * is on the GPU join the next one as soon as a slot frees up.  A request joins
+ * a batch only while the batch's prefix work-list estimate fits the admission
+ * budget; otherwise it waits for the next batch (at the head of the line).  A
+ * request asking for more accelerators than its server has free is answered
+ * MAPA_RES_NOFIT on the host at once.  Every completion reports the busy mask
+ * it was evaluated against, so each answer can be reproduced alone. */
+
+typedef struct {
+  int32_t max_batch;       /* queries per device batch, 1..65536 (0: 4096)            */
+  int32_t inflight;        /* device batches in flight, 1 or 2 (0: 2)                  */
+  double time_unit_us;     /* wall-clock microseconds per trace time unit; 0: every
+                              request is due when it is submitted                      */
+  int64_t admission_items; /* prefix-item budget of one batch (0: the work-list buffer) */
+  int32_t item_leaves;     /* embeddings per prefix item assumed by admission (0: 4096) */
+  int32_t reserved;        /* must be 0                                                 */
+} mapa_serve_opts;
+
+typedef struct {           /* 40 bytes */
+  int64_t id;              /* caller's request id, echoed in the completion            */
+  double t_arrival;        /* arrival time in trace units, non-decreasing              */
+  double hold;             /* a granted allocation is released `hold` trace units after
+                              it is granted; < 0: held until mapa_serve_stop          */
+  int32_t server;
+  uint8_t kind, k, mode;   /* as in mapa_query                                         */
+  uint8_t reserved0;       /* must be 0                                                */
+  int16_t a, b;            /* key weights, as in mapa_query                            */
+  int32_t reserved1;       /* must be 0                                                */
+} mapa_request;
+
+typedef struct {           /* 72 bytes */
+  int64_t id;
+  int64_t count;           /* matches scored                                           */
+  int64_t alloc_handle;    /* (server << 32) | vertex_mask if granted, else -1         */
+  double latency_us;       /* completion time minus scheduled arrival time             */
+  int32_t status;          /* MAPA_RES_OK or MAPA_RES_NOFIT                            */
+  int32_t key, agg, pres;
+  uint32_t vertex_mask;
+  uint32_t busy_before;    /* the server's busy mask this request was answered against */
+  int32_t batch;           /* device batch index; -1 if answered on the host           */
+  int32_t server;
+  uint8_t mapping[8];
+} mapa_completion;
+
+typedef struct {
+  int64_t requests, completed, granted, nofit;
+  int64_t host_nofit;      /* answered on the host without a device batch              */
+  int64_t batches, releases, embeddings, admission_waits;
+  double wall_s;           /* from start to the last completion                        */
+  double requests_per_s, embeddings_per_s;
+  double p50_us, p99_us, p999_us, max_us;  /* request latency percentiles            */
+  double mean_batch;       /* mean queries per device batch                            */
+} mapa_serve_stats;
+
+/* Start the loop.  opts may be NULL (defaults).  MAPA_ERR_STATE if a loop is
+ * already running; MAPA_ERR_NO_DEVICE without a device. */
+int32_t mapa_serve_start(mapa_ctx *ctx, const mapa_serve_opts *opts);
+
+/* Queue n requests (host array, copied).  All-or-nothing validation: unknown
+ * server -> MAPA_ERR_UNKNOWN_SERVER, malformed field or an arrival earlier
+ * than the previous one -> MAPA_ERR_INVALID_ARG, k > 8 -> MAPA_ERR_UNSUPPORTED. */
+int32_t mapa_serve_submit(mapa_ctx *ctx, const mapa_request *reqs, int32_t n);
+
+/* Move up to cap finished requests into out (host array); *n_out = how many. */
+int32_t mapa_serve_poll(mapa_ctx *ctx, mapa_completion *out, int32_t cap, int32_t *n_out);
+
+/* Answer every submitted request, release every allocation still held, stop
+ * the loop and fill *out (may be NULL).  Completions not yet polled are
+ * dropped.  The context is usable by the other calls again afterwards. */
+int32_t mapa_serve_stop(mapa_ctx *ctx, mapa_serve_stats *out);
+
 #ifdef __cplusplus
 }
 #endif
