@@ -55,6 +55,32 @@ class Stats(ctypes.Structure):
                 ("num_topologies", ctypes.c_int32)]
 
 
+class ServeOpts(ctypes.Structure):
+    _fields_ = [("max_batch", ctypes.c_int32), ("inflight", ctypes.c_int32),
+                ("time_unit_us", ctypes.c_double), ("admission_items", ctypes.c_int64),
+                ("item_leaves", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class ServeStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in (
+        "requests", "completed", "granted", "nofit", "host_nofit", "batches", "releases",
+        "embeddings", "admission_waits")] + [(n, ctypes.c_double) for n in (
+            "wall_s", "requests_per_s", "embeddings_per_s", "p50_us", "p99_us", "p999_us",
+            "max_us", "mean_batch")]
+
+
+REQUEST_DTYPE = np.dtype([("id", np.int64), ("t_arrival", np.float64), ("hold", np.float64),
+                          ("server", np.int32), ("kind", np.uint8), ("k", np.uint8),
+                          ("mode", np.uint8), ("reserved0", np.uint8), ("a", np.int16),
+                          ("b", np.int16), ("reserved1", np.int32)])
+COMPLETION_DTYPE = np.dtype([("id", np.int64), ("count", np.int64), ("alloc_handle", np.int64),
+                             ("latency_us", np.float64), ("status", np.int32), ("key", np.int32),
+                             ("agg", np.int32), ("pres", np.int32), ("vertex_mask", np.uint32),
+                             ("busy_before", np.uint32), ("batch", np.int32),
+                             ("server", np.int32), ("mapping", np.uint8, 8)])
+assert REQUEST_DTYPE.itemsize == 40 and COMPLETION_DTYPE.itemsize == 72
+
+
 # every symbol include/mapa.h declares, with its ctypes signature
 _P, _I32, _U32, _SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_size_t
 SIGNATURES = {
@@ -72,6 +98,10 @@ SIGNATURES = {
     "mapa_get_stats": (_I32, [_P, ctypes.POINTER(Stats)]),
     "mapa_reset_stats": (_I32, [_P]),
     "mapa_sync": (_I32, [_P]),
+    "mapa_serve_start": (_I32, [_P, ctypes.POINTER(ServeOpts)]),
+    "mapa_serve_submit": (_I32, [_P, _P, _I32]),
+    "mapa_serve_poll": (_I32, [_P, _P, _I32, ctypes.POINTER(_I32)]),
+    "mapa_serve_stop": (_I32, [_P, ctypes.POINTER(ServeStats)]),
 }
 
 _lib = None
@@ -237,6 +267,28 @@ class Context:
 
     def sync(self):
         check(lib().mapa_sync(self.h), "mapa_sync")
+
+    # -- serving loop ----------------------------------------------------------
+    def serve_start(self, max_batch=0, inflight=0, time_unit_us=0.0, admission_items=0,
+                    item_leaves=0):
+        o = ServeOpts(int(max_batch), int(inflight), float(time_unit_us), int(admission_items),
+                      int(item_leaves), 0)
+        check(lib().mapa_serve_start(self.h, ctypes.byref(o)), "mapa_serve_start")
+
+    def serve_submit(self, reqs):
+        r = np.ascontiguousarray(reqs, dtype=REQUEST_DTYPE)
+        check(lib().mapa_serve_submit(self.h, _ptr(r), len(r)), "mapa_serve_submit")
+
+    def serve_poll(self, cap: int = 65536) -> np.ndarray:
+        out = np.zeros(cap, dtype=COMPLETION_DTYPE)
+        n = ctypes.c_int32()
+        check(lib().mapa_serve_poll(self.h, _ptr(out), cap, ctypes.byref(n)), "mapa_serve_poll")
+        return out[:n.value]
+
+    def serve_stop(self) -> dict:
+        st = ServeStats()
+        check(lib().mapa_serve_stop(self.h, ctypes.byref(st)), "mapa_serve_stop")
+        return {name: getattr(st, name) for name, _ in ServeStats._fields_}
 
 
 def _stream(stream):

@@ -146,3 +146,16 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(B, "LIB_PATH", str(tmp_path / "nope.so"))
     with pytest.raises(RuntimeError, match="missing"):
         B.lib()
+
+
+def test_serving_api_validation(vctx):
+    vctx.create_topology(cube_mesh(), 2)
+    # no loop running: submit/poll/stop refuse with MAPA_ERR_STATE
+    r = np.zeros(1, dtype=B.REQUEST_DTYPE)
+    r["k"] = 2
+    assert code_of(lambda: vctx.serve_submit(r)) == B.ERR_STATE
+    assert code_of(lambda: vctx.serve_poll()) == B.ERR_STATE
+    assert code_of(lambda: vctx.serve_stop()) == B.ERR_STATE
+    assert code_of(lambda: vctx.serve_start(max_batch=-1)) == B.ERR_INVALID_ARG
+    assert code_of(lambda: vctx.serve_start(inflight=3)) == B.ERR_INVALID_ARG
+    assert code_of(lambda: vctx.serve_start()) == B.ERR_NO_DEVICE
