@@ -277,8 +277,9 @@ struct LaneState {
   const uint32_t *trow;  // this lane's topology rows [16][WPR]
   uint32_t R;            // free set
   int a, b;
-  int kind, k;
+  int k;
   int linked;
+  unsigned long long nbtab;  // byte p: pattern neighbours of position p that precede it
   uint32_t count;        // matches seen
   int bkey;              // best key so far (-1: none)
   uint32_t bcode;        // its mapping, vertex of position p at bits 4p..4p+3
@@ -305,12 +306,12 @@ __device__ __forceinline__ uint32_t adjacency(const uint32_t *r) {
 
 // Vertices at the pattern neighbours of position p that precede it, and the
 // candidate set for position p (LINKED: must touch each of them).
-template <int WPR>
+template <int WPR, bool LINKED>
 __device__ __forceinline__ void node_masks(const LaneState &s, uint32_t rest, uint32_t code,
                                            int p, uint32_t &nbm, uint32_t &cand) {
-  const uint32_t nbpos = c_tab.nb[s.kind][s.k][p];
+  const uint32_t nbpos = (uint32_t)(s.nbtab >> (8 * p)) & 0xFFu;
   cand = rest;
-  if (!s.linked && nbpos == ((1u << p) - 1u)) {
+  if (!LINKED && nbpos == ((1u << p) - 1u)) {
     nbm = s.R & ~rest;  // every earlier position: the chosen set itself
     return;
   }
@@ -319,37 +320,72 @@ __device__ __forceinline__ void node_masks(const LaneState &s, uint32_t rest, ui
     const int j = __ffs(m) - 1;
     const int v = (code >> (4 * j)) & 15;
     nbm |= 1u << v;
-    if (s.linked) cand &= adjacency<WPR>(s.trow + v * WPR);
+    if constexpr (LINKED) cand &= adjacency<WPR>(s.trow + v * WPR);
   }
 }
 
-template <int L, int WPR>
+// One pattern position: expand every candidate vertex c, scoring it with
+//   a * (weight from c to the vertices at its earlier pattern neighbours)
+//   - b * (weight from c to the free vertices not yet chosen)
+// and recurse; at the last position keep the node's best leaf.
+//
+// In ALL mode every lane of a wave holds an item of the same bucket, so all
+// lanes have the same number of candidates at every node: the loops are
+// counted on the scalar unit.  The leaf loop keeps the node's best as one u32,
+// ((key + 1) << 4) | (15 - c), so a single max() picks the largest key and,
+// among equal keys, the smallest vertex; the node's best then replaces the
+// lane's best only if strictly larger (leaves arrive in lexicographic order).
+template <int L, int WPR, bool LINKED>
 __device__ __forceinline__ void level(LaneState &s, uint32_t rest, uint32_t code, int kp, int p) {
   uint32_t nbm, cand;
-  node_masks<WPR>(s, rest, code, p, nbm, cand);
+  node_masks<WPR, LINKED>(s, rest, code, p, nbm, cand);
   const uint32_t nb2 = nbm | (nbm << 16);
   const uint32_t rest2 = rest | (rest << 16);
+  int m = __popc(cand);
+  if constexpr (!LINKED) m = __builtin_amdgcn_readfirstlane(m);
   if constexpr (L == 1) {
-    s.count += __popc(cand);
-    const int sh = 4 * p;
-    while (cand) {
-      const int c = __ffs(cand) - 1;
+    s.count += (uint32_t)m;
+    // ((key + 1) << 4) | (15 - c)  ==  16*(kp + 1) + 15 + 16a*nb - 16b*dr - c
+    const int base = 16 * kp + 31;
+    const int a16 = 16 * s.a, b16 = 16 * s.b;
+    uint32_t pb = 0;
+    for (int t = 0; t < m; ++t) {
+      const int c = __builtin_ctz(cand);
       cand &= cand - 1;
       const uint32_t *rc = s.trow + c * WPR;
-      const int key = kp + __mul24(s.a, wsum<WPR>(rc, nb2)) - __mul24(s.b, wsum<WPR>(rc, rest2));
-      if (key > s.bkey) {
-        s.bkey = key;
-        s.bcode = code | ((uint32_t)c << sh);
-      }
+      const uint32_t pk = (uint32_t)(base + __mul24(a16, wsum<WPR>(rc, nb2)) -
+                                     __mul24(b16, wsum<WPR>(rc, rest2)) - c);
+      pb = pk > pb ? pk : pb;
+    }
+    const int key = (int)(pb >> 4) - 1;
+    if (key > s.bkey) {
+      s.bkey = key;
+      s.bcode = code | ((15u - (pb & 15u)) << (4 * p));
     }
   } else {
-    while (cand) {
-      const int c = __ffs(cand) - 1;
+    for (int t = 0; t < m; ++t) {
+      const int c = __builtin_ctz(cand);
       cand &= cand - 1;
       const uint32_t *rc = s.trow + c * WPR;
       const int kp2 = kp + __mul24(s.a, wsum<WPR>(rc, nb2)) - __mul24(s.b, wsum<WPR>(rc, rest2));
-      level<L - 1, WPR>(s, rest & ~(1u << c), code | ((uint32_t)c << (4 * p)), kp2, p + 1);
+      level<L - 1, WPR, LINKED>(s, rest & ~(1u << c), code | ((uint32_t)c << (4 * p)), kp2, p + 1);
     }
+  }
+}
+
+template <int WPR, bool LINKED>
+__device__ __forceinline__ void expand(LaneState &s, int L, uint32_t rest, uint32_t code, int kp,
+                                       int d) {
+  switch (L) {
+    case 1: level<1, WPR, LINKED>(s, rest, code, kp, d); break;
+    case 2: level<2, WPR, LINKED>(s, rest, code, kp, d); break;
+    case 3: level<3, WPR, LINKED>(s, rest, code, kp, d); break;
+    case 4: level<4, WPR, LINKED>(s, rest, code, kp, d); break;
+    case 5: level<5, WPR, LINKED>(s, rest, code, kp, d); break;
+    case 6: level<6, WPR, LINKED>(s, rest, code, kp, d); break;
+    case 7: level<7, WPR, LINKED>(s, rest, code, kp, d); break;
+    case 8: level<8, WPR, LINKED>(s, rest, code, kp, d); break;
+    default: break;
   }
 }
 
@@ -362,6 +398,7 @@ __device__ __forceinline__ void run_item(const BatchArgs &a, const uint32_t *row
   s.bkey = -1;
   s.bcode = 0;
   s.k = 0;
+  s.linked = 0;
   uint32_t rest = 0, code = 0;
   int kp = 0, L = 0, d = 0;
   if (valid) {
@@ -370,9 +407,12 @@ __device__ __forceinline__ void run_item(const BatchArgs &a, const uint32_t *row
     s.R = p.R;
     s.a = p.a;
     s.b = p.b;
-    s.kind = p.kind;
     s.k = p.k;
     s.linked = p.mode;
+    unsigned long long nbtab = 0;
+    for (int q = 0; q < (int)p.k; ++q)
+      nbtab |= (unsigned long long)c_tab.nb[p.kind][p.k][q] << (8 * q);
+    s.nbtab = nbtab;
     d = p.d;
     rest = p.R;
     kp = p.kp0;
@@ -380,7 +420,10 @@ __device__ __forceinline__ void run_item(const BatchArgs &a, const uint32_t *row
     for (int pos = 0; pos < d; ++pos) {
       const int v = (it.y >> (4 * pos)) & 15;
       uint32_t nbm, cand;
-      node_masks<WPR>(s, rest, code, pos, nbm, cand);
+      if (s.linked)
+        node_masks<WPR, true>(s, rest, code, pos, nbm, cand);
+      else
+        node_masks<WPR, false>(s, rest, code, pos, nbm, cand);
       ok = ok && ((cand >> v) & 1u);
       const uint32_t *rv = s.trow + v * WPR;
       kp += __mul24(s.a, wsum<WPR>(rv, nbm | (nbm << 16))) -
@@ -390,17 +433,12 @@ __device__ __forceinline__ void run_item(const BatchArgs &a, const uint32_t *row
     }
     L = ok ? (int)p.k - d : 0;
   }
-  switch (L) {
-    case 1: level<1, WPR>(s, rest, code, kp, d); break;
-    case 2: level<2, WPR>(s, rest, code, kp, d); break;
-    case 3: level<3, WPR>(s, rest, code, kp, d); break;
-    case 4: level<4, WPR>(s, rest, code, kp, d); break;
-    case 5: level<5, WPR>(s, rest, code, kp, d); break;
-    case 6: level<6, WPR>(s, rest, code, kp, d); break;
-    case 7: level<7, WPR>(s, rest, code, kp, d); break;
-    case 8: level<8, WPR>(s, rest, code, kp, d); break;
-    default: break;
-  }
+  // Items of one chunk share a bucket, so the match mode is wave-uniform
+  // (lane 0 holds a real item whenever any lane does).
+  if (__builtin_amdgcn_readfirstlane(s.linked))
+    expand<WPR, true>(s, L, rest, code, kp, d);
+  else
+    expand<WPR, false>(s, L, rest, code, kp, d);
 
   // best as one u64: key high, inverted lexicographic mapping code low, so
   // max() takes the largest key and then the smallest mapping.
