@@ -62,15 +62,27 @@ def nb_count(kind: int, k: int, p: int) -> int:
     return 1
 
 
+def placement_ops(B: int, nb: int) -> int:
+    """Integer ops to place one vertex at a position with nb earlier pattern
+    neighbours, for weights of B bits: the cheaper of the two incremental
+    formulations of the score.
+      (i)  per-neighbour adds: candidate test, nb AggBW adds, B masked
+           bit-plane popcounts with their shift-adds for the PreservedBW term
+           (3B), key update (2), best-so-far compare/select (3):  8 + 3B + nb;
+      (ii) both terms as masked weighted popcounts over ceil(B/2) words of two
+           bit-planes each (and, two popcounts, align: 4 per word and term):
+           candidate select/clear (2), 8*ceil(B/2), key update (3), best (2):
+           7 + 8*ceil(B/2)."""
+    return min(8 + 3 * B + nb, 7 + 8 * ((B + 1) // 2))
+
+
 def algorithmic_ops(wl) -> tuple[int, int]:
     """(embeddings, algorithmic int ops) of one pass over the workload.
 
-    Every vertex placement of the shared-prefix search (a node at depth p+1,
-    of which there are F!/(F-p-1)! in ALL mode) costs 8 + 3B + |Nb(p)| integer
-    operations: candidate test, incremental AggBW adds over the |Nb(p)|
-    earlier pattern neighbours, B masked bit-plane popcounts with their
-    shift-adds for the PreservedBW term, the key update and the best-so-far
-    compare/select.  B = bits of the largest weight of the topology."""
+    Every vertex placement of the shared-prefix search is charged
+    placement_ops(B, |Nb(p)|): a node at depth p+1 of the search tree, of
+    which there are F!/(F-p-1)! in ALL mode (the leaves are the embeddings).
+    B = bits of the topology's largest weight."""
     q = wl.queries
     bits = [max(1, int(W.max()).bit_length()) for W in wl.topologies]
     n_of = [W.shape[0] for W in wl.topologies]
@@ -85,7 +97,7 @@ def algorithmic_ops(wl) -> tuple[int, int]:
                 cache[key] = (0, 0)
             else:
                 e = math.perm(F, int(k))
-                o = sum(math.perm(F, p + 1) * (8 + 3 * bits[t] + nb_count(int(kind), int(k), p))
+                o = sum(math.perm(F, p + 1) * placement_ops(bits[t], nb_count(int(kind), int(k), p))
                         for p in range(int(k)))
                 cache[key] = (e, o)
         e, o = cache[key]

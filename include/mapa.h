@@ -183,9 +183,10 @@ int32_t mapa_get_busy(mapa_ctx *ctx, int32_t count, const int32_t *server_ids,
  *     MAPA_ERR_INVALID_ARG, k > 8 -> MAPA_ERR_UNSUPPORTED, unknown server ->
  *     MAPA_ERR_UNKNOWN_SERVER; nothing runs on error), then the call blocks
  *     until res is filled.
- *   MAPA_DEVICE_PTRS: q and res are device pointers; the call returns once
- *     the work is queued on hip_stream (a hipStream_t, NULL = the default
- *     stream); malformed queries get status MAPA_RES_INVALID.
+ *   MAPA_DEVICE_PTRS: q and res are device pointers (16-byte aligned); the
+ *     call returns once the work is queued on hip_stream (a hipStream_t,
+ *     NULL = the default stream); malformed queries get status
+ *     MAPA_RES_INVALID.
  * Semantics: every query is evaluated against the busy masks as they are when
  * the batch starts.  Then commits are applied: for each server, only the first
  * query of the batch (in array order) with commit = 1 may commit, and does so

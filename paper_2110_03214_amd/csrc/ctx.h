@@ -94,6 +94,7 @@ struct mapa_ctx {
   int64_t *d_handles = nullptr;
   uint32_t *d_flag = nullptr;
   size_t cap_small = 0;
+  uint8_t *d_split = nullptr;  // prefix depth per (F, k, split), from the tuning
 
   // captured batch graphs (device-pointer batches with MAPA_USE_GRAPH)
   struct Graph {

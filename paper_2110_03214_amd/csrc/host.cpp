@@ -105,6 +105,7 @@ void fill_args(mapa_ctx *c, const Workspace &w, BatchArgs &a) {
   a.rows = c->d_rows;
   a.ntopo = (int32_t)c->topo_n.size();
   a.wpr = c->wpr;
+  a.split_d = c->d_split;
   a.min_leaves = std::max(1, c->tuning.min_leaves_per_item);
   const int threads = c->tuning.threads_per_block;
   const size_t lds_bytes = (size_t)a.ntopo * 16 * c->wpr * sizeof(uint32_t);
@@ -154,6 +155,18 @@ Tables build_tables() {
       t.nb[MAPA_TREE][k][p] = (uint8_t)(1u << ((p - 1) / 2));
     }
   }
+  for (int kind = 0; kind < 3; ++kind)
+    for (int k = 1; k <= kMaxK; ++k) {
+      unsigned long long tab = 0;
+      for (int p = 0; p < k; ++p) tab |= (unsigned long long)t.nb[kind][k][p] << (8 * p);
+      t.nbtab[kind][k] = tab;
+    }
+  for (int F = 0; F <= kMaxN; ++F)
+    for (int d = 0; d <= kMaxK; ++d) {
+      unsigned long long v = 1;
+      for (int i = 0; i < d; ++i) v *= (unsigned long long)std::max(0, F - i);
+      t.perm[F][d] = v;
+    }
   // buckets laid out largest items first (longest-processing-time order)
   std::vector<std::pair<double, int>> order;
   for (int b = 0; b < kNumBuckets; ++b) {
@@ -168,6 +181,26 @@ Tables build_tables() {
   std::sort(order.begin(), order.end());
   for (int r = 0; r < kNumBuckets; ++r) t.rank_bucket[r] = (uint16_t)order[r].second;
   return t;
+}
+
+// Prefix depth per (F, k, split): the smallest d <= k-1 whose items hold at
+// most min_leaves * 4^j embeddings; 0 (whole query) for the last split.
+std::vector<uint8_t> build_split_table(int min_leaves) {
+  std::vector<uint8_t> tab(kSplitTable, 0);
+  auto perm = [](int F, int k) {
+    unsigned long long v = 1;
+    for (int i = 0; i < k; ++i) v *= (unsigned long long)std::max(0, F - i);
+    return v;
+  };
+  for (int F = 0; F <= kMaxN; ++F)
+    for (int k = 1; k <= kMaxK; ++k)
+      for (int j = 0; j < kSplitWhole; ++j) {
+        const unsigned long long T = (unsigned long long)min_leaves << (2 * j);
+        int d = 0;
+        while (d < k - 1 && perm(F - d, k - d) > T) ++d;
+        tab[((size_t)F * (kMaxK + 1) + k) * kNumSplits + j] = (uint8_t)d;
+      }
+  return tab;
 }
 
 int weight_class(const uint8_t *W, int n) {
@@ -268,6 +301,14 @@ void drop_graphs(mapa_ctx *c) {
   ++c->version;
 }
 
+int32_t upload_split_table(mapa_ctx *c) {
+  const std::vector<uint8_t> tab = build_split_table(std::max(1, c->tuning.min_leaves_per_item));
+  if (!c->d_split && dev_alloc(&c->d_split, kSplitTable) != hipSuccess)
+    return fail(MAPA_ERR_OOM, "split table: device allocation failed");
+  MAPA_HIPCHK(hipMemcpy(c->d_split, tab.data(), tab.size(), hipMemcpyHostToDevice));
+  return MAPA_OK;
+}
+
 int32_t ensure_batch_capacity(mapa_ctx *c, size_t nq) {
   if (nq <= c->ws.cap_q) return MAPA_OK;
   int32_t rc = sync_ctx(c);
@@ -351,6 +392,8 @@ int32_t mapa_ctx_create(int32_t device, size_t enum_buffer_bytes, mapa_ctx **out
   if (upload_tables(t) != hipSuccess) return bail(fail(MAPA_ERR_DEVICE, "table upload failed"));
   int32_t rc = ws_create(c->ws, c->enum_bytes);
   if (rc) return bail(rc);
+  rc = upload_split_table(c);
+  if (rc) return bail(rc);
   if (dev_alloc(&c->d_flag, 1) != hipSuccess) return bail(fail(MAPA_ERR_OOM, "flag allocation failed"));
   if (hipDeviceSynchronize() != hipSuccess) return bail(fail(MAPA_ERR_DEVICE, "device init failed"));
   *out = c;
@@ -380,6 +423,7 @@ int32_t mapa_ctx_destroy(mapa_ctx *c) {
     dev_free(c->d_masks);
     dev_free(c->d_handles);
     dev_free(c->d_flag);
+    dev_free(c->d_split);
     if (c->last) (void)hipEventDestroy(c->last);
     if (c->internal) (void)hipStreamDestroy(c->internal);
   }
@@ -680,12 +724,14 @@ int32_t mapa_set_tuning(mapa_ctx *c, const mapa_tuning *in) {
     return fail(MAPA_ERR_INVALID_ARG, "blocks_per_cu outside 0..64");
   if (in->threads_per_block < 64 || in->threads_per_block > 256 || in->threads_per_block % 64)
     return fail(MAPA_ERR_INVALID_ARG, "threads_per_block must be 64, 128, 192 or 256");
+  c->tuning = *in;
   if (c->has_device) {
     int32_t rc = sync_ctx(c);
     if (rc) return rc;
     drop_graphs(c);
+    rc = upload_split_table(c);
+    if (rc) return rc;
   }
-  c->tuning = *in;
   return MAPA_OK;
 }
 

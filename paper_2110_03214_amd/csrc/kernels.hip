@@ -5,10 +5,11 @@
 //   k_prepare    per query: validate, free set R, constant key term b*W(R),
 //                per-split prefix depths and item totals, commit claim.
 //   k_bucketize  choose one split for the batch; per query: prefix depth d,
-//                shape bucket, offset inside the bucket.
-//   k_scan       lay buckets out (largest items first), pad each to whole
-//                64-item chunks, reset the per-batch counters.
-//   k_expand     one wave per query writes its prefix items (query, prefix).
+//                shape bucket, offset inside the bucket; the last block lays
+//                the buckets out (largest items first), pads each to whole
+//                64-item chunks and resets the per-batch counters.
+//   k_expand     writes every query's prefix items (query, prefix): small
+//                queries one thread each, larger ones a whole block each.
 //   k_enumerate  persistent: each wave takes a 64-item chunk; each lane
 //                expands its prefix depth-first over the remaining pattern
 //                positions, scoring every match incrementally, and keeps a
@@ -73,6 +74,25 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
 // between batches and concurrent batches on disjoint servers never interact.
 constexpr unsigned long long kSlotFree = ~0ull;
 
+// Weighted popcount over a bit-plane row with a runtime number of words:
+// sum_{u in X} W[v][u] for row r of vertex v and X2 = X | X << 16.
+__device__ __forceinline__ int wsum_rt(const uint32_t *r, int wpr, uint32_t m2) {
+  int s = 0;
+  for (int w = wpr - 1; w >= 0; --w) {
+    const uint32_t x = r[w] & m2;
+    s = s * 4 + __popc(x) + __popc(x >> 16);
+  }
+  return s;
+}
+
+// W(X): total weight of the pairs inside X (each pair seen from both ends).
+__device__ __forceinline__ int set_weight(const uint32_t *trow, int wpr, uint32_t X) {
+  const uint32_t X2 = X | (X << 16);
+  int s = 0;
+  for (uint32_t m = X; m; m &= m - 1) s += wsum_rt(trow + (__builtin_ctz(m)) * wpr, wpr, X2);
+  return s >> 1;
+}
+
 // ----------------------------------------------------------------- prepare
 
 __global__ __launch_bounds__(256) void k_prepare(BatchArgs a) {
@@ -106,29 +126,16 @@ __global__ __launch_bounds__(256) void k_prepare(BatchArgs a) {
       p.n = (uint8_t)n;
       p.R = R;
       p.F = (uint8_t)F;
-      const uint8_t *W = a.topo_W + (size_t)t * 256;
-      int wr = 0;
-      for (uint32_t m = R; m; m &= m - 1) {
-        const int u = __ffs(m) - 1;
-        for (uint32_t m2 = m & (m - 1); m2; m2 &= m2 - 1) wr += W[u * 16 + __ffs(m2) - 1];
-      }
-      p.kp0 = (int32_t)q.b * wr;
+      p.kp0 = (int32_t)q.b * set_weight(a.rows + (size_t)t * 16 * a.wpr, a.wpr, R);
+      p.nbtab = c_tab.nbtab[q.kind][q.k];
       if (q.k > F) {
         p.status = kPlanNofit;
       } else {
         p.status = kPlanOk;
-        leaves = perm64(F, q.k);
-        unsigned long long ds = 0;
-        for (int j = 0; j < kNumSplits; ++j) {
-          int d = 0;
-          if (j < kSplitWhole) {
-            const unsigned long long T = (unsigned long long)a.min_leaves << (2 * j);
-            while (d < q.k - 1 && perm64(F - d, q.k - d) > T) ++d;
-          }
-          ds |= (unsigned long long)d << (4 * j);
-          items[j] = perm64(F, d);
-        }
-        p.dsplit = ds;
+        leaves = c_tab.perm[F][q.k];
+        const uint8_t *sd = a.split_d + ((size_t)F * (kMaxK + 1) + q.k) * kNumSplits;
+#pragma unroll
+        for (int j = 0; j < kNumSplits; ++j) items[j] = c_tab.perm[F][sd[j]];
       }
       if (q.commit) atomicMin(&a.commit_slot[q.server], (unsigned long long)i);
     }
@@ -150,16 +157,56 @@ __global__ __launch_bounds__(256) void k_prepare(BatchArgs a) {
 
 // --------------------------------------------------------------- bucketize
 
+// Lay the buckets out (largest items first), pad each to whole 64-item
+// chunks with invalid items, and reset the per-batch counters.  Run by the
+// last block of k_bucketize, once every block's bucket counts are in.
+__device__ void layout_buckets(const BatchArgs &a) {
+  __shared__ uint32_t s_pad[kNumBuckets];
+  __shared__ uint32_t s_cnt[kNumBuckets];
+  __shared__ uint32_t s_start[kNumBuckets];
+  const int t = threadIdx.x;
+  for (int r = t; r < kNumBuckets; r += blockDim.x) {
+    const int b = c_tab.rank_bucket[r];
+    const uint32_t cnt = __hip_atomic_load(&a.ctr->bucket_items[b], __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+    s_cnt[r] = cnt;
+    s_pad[r] = (cnt + (kChunk - 1)) & ~(uint32_t)(kChunk - 1);
+  }
+  __syncthreads();
+  if (t == 0) {
+    uint32_t acc = 0;
+    for (int r = 0; r < kNumBuckets; ++r) {
+      s_start[r] = acc;
+      acc += s_pad[r];
+    }
+    a.ctr->total_chunks = acc / kChunk;
+  }
+  __syncthreads();
+  for (int r = t; r < kNumBuckets; r += blockDim.x) {
+    const int b = c_tab.rank_bucket[r];
+    a.ctr->bucket_start[b] = s_start[r];
+    for (uint32_t x = s_cnt[r]; x < s_pad[r]; ++x) a.items[s_start[r] + x] = make_uint2(kInvalidItem, 0u);
+    a.ctr->bucket_items[b] = 0;
+  }
+  if (t == 0) {
+    a.ctr->total_leaves = 0;
+    for (int j = 0; j < kNumSplits; ++j) a.ctr->total_items[j] = 0;
+    a.ctr->chunk_ctr = 0;
+    a.ctr->blocks_done = 0;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_bucketize(BatchArgs a) {
   __shared__ int s_split;
+  __shared__ bool s_last;
   __shared__ uint32_t s_cnt[kNumBuckets];
   __shared__ uint32_t s_base[kNumBuckets];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   for (int b = threadIdx.x; b < kNumBuckets; b += blockDim.x) s_cnt[b] = 0;
   if (threadIdx.x == 0) {
     // The split is a pure function of batch totals, so every block picks the
-    // same one: the smallest items that still give >= target_items items
-    // overall ... and fit the buffer; else whole queries.
+    // same one: the smallest item size that still gives at least
+    // target_items items in total and fits the work-list; else whole queries.
     const unsigned long long total = a.ctr->total_leaves;
     const unsigned long long target = (total + a.target_items - 1) / a.target_items;
     int j = kSplitWhole;
@@ -179,13 +226,13 @@ __global__ __launch_bounds__(256) void k_bucketize(BatchArgs a) {
   __syncthreads();
   const int j = s_split;
   int b = -1;
-  uint32_t nitems = 0, local = 0;
+  uint32_t local = 0;
   Plan p;
   if (i < a.nq) {
     p = a.plan[i];
     if (p.status == kPlanOk) {
-      const int d = (int)((p.dsplit >> (4 * j)) & 15ull);
-      nitems = (uint32_t)perm64(p.F, d);
+      const int d = a.split_d[((size_t)p.F * (kMaxK + 1) + p.k) * kNumSplits + j];
+      const uint32_t nitems = (uint32_t)c_tab.perm[p.F][d];
       b = bucket_id(p.mode, p.k - d, p.F - d);
       p.d = (uint8_t)d;
       p.bucket = (uint16_t)b;
@@ -201,40 +248,13 @@ __global__ __launch_bounds__(256) void k_bucketize(BatchArgs a) {
     p.item_off = s_base[b] + local;
     a.plan[i] = p;
   }
-}
-
-// -------------------------------------------------------------------- scan
-
-__global__ __launch_bounds__(512) void k_scan(BatchArgs a) {
-  __shared__ uint32_t s_pad[kNumBuckets];
-  __shared__ uint32_t s_start[kNumBuckets];
-  const int t = threadIdx.x;
-  for (int r = t; r < kNumBuckets; r += blockDim.x) {
-    const uint32_t cnt = a.ctr->bucket_items[c_tab.rank_bucket[r]];
-    s_pad[r] = (cnt + (kChunk - 1)) & ~(uint32_t)(kChunk - 1);
-  }
+  // the last block to finish lays the buckets out
+  __threadfence();
+  if (threadIdx.x == 0) s_last = atomicAdd(&a.ctr->blocks_done, 1u) == gridDim.x - 1;
   __syncthreads();
-  if (t == 0) {
-    uint32_t acc = 0;
-    for (int r = 0; r < kNumBuckets; ++r) {
-      s_start[r] = acc;
-      acc += s_pad[r];
-    }
-    a.ctr->total_chunks = acc / kChunk;
-  }
-  __syncthreads();
-  for (int r = t; r < kNumBuckets; r += blockDim.x) {
-    const int b = c_tab.rank_bucket[r];
-    const uint32_t cnt = a.ctr->bucket_items[b];
-    a.ctr->bucket_start[b] = s_start[r];
-    for (uint32_t x = cnt; x < s_pad[r]; ++x) a.items[s_start[r] + x] = make_uint2(kInvalidItem, 0u);
-  }
-  __syncthreads();
-  for (int r = t; r < kNumBuckets; r += blockDim.x) a.ctr->bucket_items[r] = 0;
-  if (t == 0) {
-    a.ctr->total_leaves = 0;
-    for (int j = 0; j < kNumSplits; ++j) a.ctr->total_items[j] = 0;
-    a.ctr->chunk_ctr = 0;
+  if (s_last) {
+    __threadfence();
+    layout_buckets(a);
   }
 }
 
@@ -243,31 +263,58 @@ __global__ __launch_bounds__(512) void k_scan(BatchArgs a) {
 // Prefix item x of a query (0 <= x < F!/(F-d)!) is the x-th injective
 // d-tuple of free vertices in lexicographic order: digit t of x in the mixed
 // radix (F, F-1, ..., F-d+1) picks the digit-th smallest still-unused vertex.
-__global__ __launch_bounds__(256) void k_expand(BatchArgs a) {
-  const int lane = threadIdx.x & 63;
-  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const int nwaves = (gridDim.x * blockDim.x) >> 6;
-  for (int i = wave; i < a.nq; i += nwaves) {
-    const Plan p = a.plan[i];
+__device__ __forceinline__ uint32_t unrank_prefix(uint32_t x, int d, int F, uint32_t R,
+                                                  uint32_t div0) {
+  uint32_t rem = x, div = div0, avail = R, code = 0;
+  for (int t = 0; t < d; ++t) {
+    uint32_t r = rem / div;
+    rem -= r * div;
+    if (t + 1 < d) div /= (uint32_t)(F - 1 - t);
+    uint32_t m = avail;
+    for (; r; --r) m &= m - 1;
+    const int v = __builtin_ctz(m);
+    avail &= ~(1u << v);
+    code |= (uint32_t)v << (4 * t);
+  }
+  return code;
+}
+
+constexpr uint32_t kExpandSmall = 8;  // a thread writes up to this many items itself
+
+// Each block owns a contiguous range of queries: a thread writes the items of
+// a query with few items, and the whole block writes those of larger ones.
+__global__ __launch_bounds__(256) void k_expand(BatchArgs a, int qpb) {
+  __shared__ int s_big[256];
+  __shared__ int s_nbig;
+  const int q0 = blockIdx.x * qpb;
+  const int q1 = min(a.nq, q0 + qpb);
+  if (threadIdx.x == 0) s_nbig = 0;
+  __syncthreads();
+  for (int i = q0 + threadIdx.x; i < q1; i += blockDim.x) {
+    const Plan &p = a.plan[i];
     if (p.status != kPlanOk) continue;
+    if (p.nitems > kExpandSmall) {
+      s_big[atomicAdd(&s_nbig, 1)] = i;
+      continue;
+    }
     const uint32_t base = a.ctr->bucket_start[p.bucket] + p.item_off;
     const int d = p.d, F = p.F;
     uint32_t div0 = 1;
     for (int t = 1; t < d; ++t) div0 *= (uint32_t)(F - t);
-    for (uint32_t x = lane; x < p.nitems; x += 64) {
-      uint32_t rem = x, div = div0, avail = p.R, code = 0;
-      for (int t = 0; t < d; ++t) {
-        uint32_t r = rem / div;
-        rem -= r * div;
-        if (t + 1 < d) div /= (uint32_t)(F - 1 - t);
-        uint32_t m = avail;
-        for (; r; --r) m &= m - 1;
-        const int v = __ffs(m) - 1;
-        avail &= ~(1u << v);
-        code |= (uint32_t)v << (4 * t);
-      }
-      a.items[base + x] = make_uint2((uint32_t)i, code);
-    }
+    for (uint32_t x = 0; x < p.nitems; ++x)
+      a.items[base + x] = make_uint2((uint32_t)i, unrank_prefix(x, d, F, p.R, div0));
+  }
+  __syncthreads();
+  const int nbig = s_nbig;
+  for (int bi = 0; bi < nbig; ++bi) {
+    const int i = s_big[bi];
+    const Plan &p = a.plan[i];
+    const uint32_t base = a.ctr->bucket_start[p.bucket] + p.item_off;
+    const int d = p.d, F = p.F;
+    uint32_t div0 = 1;
+    for (int t = 1; t < d; ++t) div0 *= (uint32_t)(F - t);
+    for (uint32_t x = threadIdx.x; x < p.nitems; x += blockDim.x)
+      a.items[base + x] = make_uint2((uint32_t)i, unrank_prefix(x, d, F, p.R, div0));
   }
 }
 
@@ -409,10 +456,7 @@ __device__ __forceinline__ void run_item(const BatchArgs &a, const uint32_t *row
     s.b = p.b;
     s.k = p.k;
     s.linked = p.mode;
-    unsigned long long nbtab = 0;
-    for (int q = 0; q < (int)p.k; ++q)
-      nbtab |= (unsigned long long)c_tab.nb[p.kind][p.k][q] << (8 * q);
-    s.nbtab = nbtab;
+    s.nbtab = p.nbtab;
     d = p.d;
     rest = p.R;
     kp = p.kp0;
@@ -498,68 +542,58 @@ __global__ __launch_bounds__(256) void k_finalize(BatchArgs a) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.nq) return;
   const Plan p = a.plan[i];
-  mapa_result r;
-  r.count = 0;
-  r.status = MAPA_RES_NOFIT;
-  r.key = INT32_MIN;
-  r.agg = 0;
-  r.pres = 0;
-  r.vertex_mask = 0;
-  for (int t = 0; t < 8; ++t) r.mapping[t] = 0xFF;
-  r.reserved = 0;
-  r.alloc_handle = -1;
+  int64_t count = 0;
+  int32_t status = MAPA_RES_NOFIT, key = INT32_MIN, agg = 0, pres = 0;
+  uint32_t S = 0, map_lo = 0xFFFFFFFFu, map_hi = 0xFFFFFFFFu;
+  int64_t handle = -1;
   if (p.status == kPlanInvalid) {
-    r.status = MAPA_RES_INVALID;
+    status = MAPA_RES_INVALID;
   } else if (p.status == kPlanOk) {
     const unsigned long long cnt = a.acc_count[i];
     const unsigned long long best = a.acc_best[i];
-    r.count = (int64_t)cnt;
+    count = (int64_t)cnt;
     if (cnt > 0) {
       const int k = p.k;
       const uint32_t lex = 0xFFFFFFFFu - (uint32_t)best;
-      uint32_t S = 0;
+      const uint32_t *trow = a.rows + (size_t)p.topo * 16 * a.wpr;
+      uint32_t phi_code = 0;  // vertex of position t at bits 4t..4t+3
       for (int t = 0; t < k; ++t) {
         const uint32_t v = (lex >> (4 * (k - 1 - t))) & 15u;
-        r.mapping[t] = (uint8_t)v;
+        phi_code |= v << (4 * t);
         S |= 1u << v;
+        if (t < 4) map_lo = (map_lo & ~(0xFFu << (8 * t))) | (v << (8 * t));
+        else map_hi = (map_hi & ~(0xFFu << (8 * (t - 4)))) | (v << (8 * (t - 4)));
       }
-      const uint8_t *W = a.topo_W + (size_t)p.topo * 256;
-      int agg = 0;
+      // AggBW (Eq. 1) from the mapping: each position against its earlier
+      // pattern neighbours; PreservedBW (Eq. 3): weight left inside R \ S
       for (int t = 1; t < k; ++t) {
-        const uint32_t vt = (lex >> (4 * (k - 1 - t))) & 15u;
-        for (uint32_t m = c_tab.nb[p.kind][k][t]; m; m &= m - 1) {
-          const int j = __ffs(m) - 1;
-          const uint32_t vj = (lex >> (4 * (k - 1 - j))) & 15u;
-          agg += W[vj * 16 + vt];
-        }
+        uint32_t nbm = 0;
+        for (uint32_t m = (uint32_t)(p.nbtab >> (8 * t)) & 0xFFu; m; m &= m - 1)
+          nbm |= 1u << ((phi_code >> (4 * __builtin_ctz(m))) & 15u);
+        agg += wsum_rt(trow + ((phi_code >> (4 * t)) & 15u) * a.wpr, a.wpr, nbm | (nbm << 16));
       }
-      int pres = 0;
-      const uint32_t X = p.R & ~S;
-      for (uint32_t m = X; m; m &= m - 1) {
-        const int u = __ffs(m) - 1;
-        for (uint32_t m2 = m & (m - 1); m2; m2 &= m2 - 1) pres += W[u * 16 + __ffs(m2) - 1];
-      }
-      r.key = (int32_t)(best >> 32);
-      r.agg = agg;
-      r.pres = pres;
-      r.vertex_mask = S;
-      r.status = MAPA_RES_OK;
-      if ((int32_t)p.a * agg + (int32_t)p.b * pres != r.key)
-        atomicAdd(&a.ctr->self_check_failures, 1u);
+      pres = set_weight(trow, a.wpr, p.R & ~S);
+      key = (int32_t)(best >> 32);
+      status = MAPA_RES_OK;
+      if ((int32_t)p.a * agg + (int32_t)p.b * pres != key) atomicAdd(&a.ctr->self_check_failures, 1u);
     }
   }
   if (p.status != kPlanInvalid && p.commit) {
     if (a.commit_slot[p.server] == (unsigned long long)i) {
-      if (r.status == MAPA_RES_OK) {
-        atomicOr(&a.busy[p.server], r.vertex_mask);
-        r.alloc_handle = ((int64_t)p.server << 32) | (int64_t)r.vertex_mask;
+      if (status == MAPA_RES_OK) {
+        atomicOr(&a.busy[p.server], S);
+        handle = ((int64_t)p.server << 32) | (int64_t)S;
       }
       a.commit_slot[p.server] = kSlotFree;
-    } else if (r.status == MAPA_RES_OK) {
-      r.status = MAPA_RES_CONFLICT;
+    } else if (status == MAPA_RES_OK) {
+      status = MAPA_RES_CONFLICT;
     }
   }
-  a.res[i] = r;
+  // 48-byte result as three 16-byte stores
+  int4 *dst = reinterpret_cast<int4 *>(a.res + i);
+  dst[0] = make_int4((int32_t)(uint32_t)count, (int32_t)(count >> 32), status, key);
+  dst[1] = make_int4(agg, pres, (int32_t)S, (int32_t)map_lo);
+  dst[2] = make_int4((int32_t)map_hi, 0, (int32_t)(uint32_t)handle, (int32_t)(handle >> 32));
 }
 
 // ------------------------------------------------------------- state kernels
@@ -616,10 +650,11 @@ hipError_t launch_batch_front(const BatchArgs &a, hipStream_t s) {
   const unsigned g = blocks_for(a.nq, 256);
   hipLaunchKernelGGL(k_prepare, dim3(g), dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_bucketize, dim3(g), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(512), 0, s, a);
-  unsigned ge = blocks_for((long long)a.nq * 64, 256);
-  if (ge > (1u << 20)) ge = 1u << 20;
-  hipLaunchKernelGGL(k_expand, dim3(ge), dim3(256), 0, s, a);
+  // at most 64 queries per expansion block, and at least ~1024 blocks
+  int qpb = 64;
+  if (blocks_for(a.nq, qpb) < 1024) qpb = (int)((a.nq + 1023) / 1024);
+  if (qpb < 1) qpb = 1;
+  hipLaunchKernelGGL(k_expand, dim3(blocks_for(a.nq, qpb)), dim3(256), 0, s, a, qpb);
   return hipGetLastError();
 }
 

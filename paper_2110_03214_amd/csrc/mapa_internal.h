@@ -44,7 +44,7 @@ struct Plan {
   uint16_t bucket;
   uint32_t nitems;     // prefix items of the chosen split
   uint32_t item_off;   // offset of the first item inside its bucket
-  uint64_t dsplit;     // 4 bits per split j: prefix depth d_j
+  uint64_t nbtab;      // byte p: pattern neighbours of position p that precede it
 };
 static_assert(sizeof(Plan) == 48, "Plan layout");
 
@@ -53,6 +53,8 @@ constexpr uint8_t kPlanOk = 0, kPlanNofit = 1, kPlanInvalid = 3;
 // Per-batch counters (device).  Zeroed at allocation; the scan kernel
 // re-zeroes what it consumed so the next batch starts clean.
 struct Counters {
+  uint32_t blocks_done;   // k_bucketize blocks finished (the last one lays buckets out)
+  uint32_t pad0;
   unsigned long long total_leaves;
   unsigned long long total_items[kNumSplits];
   uint32_t bucket_items[kNumBuckets];
@@ -65,9 +67,17 @@ struct Counters {
 };
 
 struct Tables {          // uploaded once per device into __constant__ memory
-  uint8_t nb[3][kMaxK + 1][kMaxK];   // back-neighbour position masks
-  uint16_t rank_bucket[kNumBuckets]; // bucket laid out at rank r (largest items first)
+  unsigned long long perm[kMaxN + 1][kMaxK + 1];  // F!/(F-d)!
+  unsigned long long nbtab[3][kMaxK + 1];  // byte p: back-neighbour position mask of p
+  uint8_t nb[3][kMaxK + 1][kMaxK];         // the same masks, one per entry
+  uint16_t rank_bucket[kNumBuckets];       // bucket laid out at rank r (largest items first)
 };
+
+// Prefix depth of split j for a query with F free vertices and k pattern
+// positions: the smallest d <= k-1 with (F-d)!/(F-k)! <= min_leaves * 4^j
+// (j < kSplitWhole), and d = 0 for j = kSplitWhole.  Built on the host per
+// context (it depends on the tuning), indexed [F][k][j].
+constexpr int kSplitTable = (kMaxN + 1) * (kMaxK + 1) * kNumSplits;
 
 // kernels.hip
 hipError_t upload_tables(const Tables &t);
@@ -92,6 +102,7 @@ struct BatchArgs {
   const uint32_t *rows;   // [T][16][wpr]
   int32_t ntopo;
   int32_t wpr;
+  const uint8_t *split_d;  // [F][k][j], see kSplitTable
   // tuning
   int32_t min_leaves;
   unsigned long long target_items;
