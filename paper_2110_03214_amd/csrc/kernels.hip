@@ -89,6 +89,19 @@ __device__ __forceinline__ int wsum_rt(const uint32_t *r, int wpr, uint32_t m2) 
 __device__ __forceinline__ int set_weight(const uint32_t *trow, int wpr, uint32_t X) {
   const uint32_t X2 = X | (X << 16);
   int s = 0;
+  if (wpr == 1) {
+    // the 16 rows as four 16-byte loads issued together
+    const uint4 *r4 = reinterpret_cast<const uint4 *>(trow);
+    const uint4 q0 = r4[0], q1 = r4[1], q2 = r4[2], q3 = r4[3];
+    const uint32_t row[16] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w,
+                              q2.x, q2.y, q2.z, q2.w, q3.x, q3.y, q3.z, q3.w};
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const uint32_t x = row[v] & X2;
+      s += ((X >> v) & 1u) ? (int)(__popc(x) + __popc(x >> 16)) : 0;
+    }
+    return s >> 1;
+  }
   for (uint32_t m = X; m; m &= m - 1) s += wsum_rt(trow + (__builtin_ctz(m)) * wpr, wpr, X2);
   return s >> 1;
 }
@@ -143,15 +156,24 @@ __global__ __launch_bounds__(256) void k_prepare(BatchArgs a) {
     a.acc_count[i] = 0;
     a.acc_best[i] = 0;
   }
-  // one atomic per wave and counter
+  // wave sums -> block sums in LDS -> one global atomic per block and counter
+  __shared__ unsigned long long s_tot[kNumSplits + 1];
+  if (threadIdx.x <= kNumSplits) s_tot[threadIdx.x] = 0;
+  __syncthreads();
   leaves = wave_sum_u64(leaves);
 #pragma unroll
   for (int j = 0; j < kNumSplits; ++j) items[j] = wave_sum_u64(items[j]);
   if ((threadIdx.x & 63) == 0) {
-    if (leaves) atomicAdd(&a.ctr->total_leaves, leaves);
+    if (leaves) atomicAdd(&s_tot[kNumSplits], leaves);
 #pragma unroll
     for (int j = 0; j < kNumSplits; ++j)
-      if (items[j]) atomicAdd(&a.ctr->total_items[j], items[j]);
+      if (items[j]) atomicAdd(&s_tot[j], items[j]);
+  }
+  __syncthreads();
+  if (threadIdx.x < kNumSplits) {
+    if (s_tot[threadIdx.x]) atomicAdd(&a.ctr->total_items[threadIdx.x][0], s_tot[threadIdx.x]);
+  } else if (threadIdx.x == kNumSplits) {
+    if (s_tot[kNumSplits]) atomicAdd(&a.ctr->total_leaves[0], s_tot[kNumSplits]);
   }
 }
 
@@ -167,7 +189,7 @@ __device__ void layout_buckets(const BatchArgs &a) {
   const int t = threadIdx.x;
   for (int r = t; r < kNumBuckets; r += blockDim.x) {
     const int b = c_tab.rank_bucket[r];
-    const uint32_t cnt = __hip_atomic_load(&a.ctr->bucket_items[b], __ATOMIC_RELAXED,
+    const uint32_t cnt = __hip_atomic_load(&a.ctr->bucket_items[b][0], __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_AGENT);
     s_cnt[r] = cnt;
     s_pad[r] = (cnt + (kChunk - 1)) & ~(uint32_t)(kChunk - 1);
@@ -186,13 +208,13 @@ __device__ void layout_buckets(const BatchArgs &a) {
     const int b = c_tab.rank_bucket[r];
     a.ctr->bucket_start[b] = s_start[r];
     for (uint32_t x = s_cnt[r]; x < s_pad[r]; ++x) a.items[s_start[r] + x] = make_uint2(kInvalidItem, 0u);
-    a.ctr->bucket_items[b] = 0;
+    a.ctr->bucket_items[b][0] = 0;
   }
   if (t == 0) {
-    a.ctr->total_leaves = 0;
-    for (int j = 0; j < kNumSplits; ++j) a.ctr->total_items[j] = 0;
-    a.ctr->chunk_ctr = 0;
-    a.ctr->blocks_done = 0;
+    a.ctr->total_leaves[0] = 0;
+    for (int j = 0; j < kNumSplits; ++j) a.ctr->total_items[j][0] = 0;
+    a.ctr->chunk_ctr[0] = 0;
+    a.ctr->blocks_done[0] = 0;
   }
 }
 
@@ -207,12 +229,12 @@ __global__ __launch_bounds__(256) void k_bucketize(BatchArgs a) {
     // The split is a pure function of batch totals, so every block picks the
     // same one: the smallest item size that still gives at least
     // target_items items in total and fits the work-list; else whole queries.
-    const unsigned long long total = a.ctr->total_leaves;
+    const unsigned long long total = a.ctr->total_leaves[0];
     const unsigned long long target = (total + a.target_items - 1) / a.target_items;
     int j = kSplitWhole;
     for (int c = 0; c < kSplitWhole; ++c) {
       const unsigned long long T = (unsigned long long)a.min_leaves << (2 * c);
-      if (T >= target && a.ctr->total_items[c] + kPadReserve <= a.cap_items) {
+      if (T >= target && a.ctr->total_items[c][0] + kPadReserve <= a.cap_items) {
         j = c;
         break;
       }
@@ -220,7 +242,7 @@ __global__ __launch_bounds__(256) void k_bucketize(BatchArgs a) {
     s_split = j;
     if (blockIdx.x == 0) {
       a.ctr->chosen_split = (uint32_t)j;
-      a.ctr->last_total_items = a.ctr->total_items[j];
+      a.ctr->last_total_items = a.ctr->total_items[j][0];
     }
   }
   __syncthreads();
@@ -242,7 +264,7 @@ __global__ __launch_bounds__(256) void k_bucketize(BatchArgs a) {
   }
   __syncthreads();
   for (int c = threadIdx.x; c < kNumBuckets; c += blockDim.x)
-    s_base[c] = s_cnt[c] ? atomicAdd(&a.ctr->bucket_items[c], s_cnt[c]) : 0u;
+    s_base[c] = s_cnt[c] ? atomicAdd(&a.ctr->bucket_items[c][0], s_cnt[c]) : 0u;
   __syncthreads();
   if (b >= 0) {
     p.item_off = s_base[b] + local;
@@ -250,7 +272,7 @@ __global__ __launch_bounds__(256) void k_bucketize(BatchArgs a) {
   }
   // the last block to finish lays the buckets out
   __threadfence();
-  if (threadIdx.x == 0) s_last = atomicAdd(&a.ctr->blocks_done, 1u) == gridDim.x - 1;
+  if (threadIdx.x == 0) s_last = atomicAdd(&a.ctr->blocks_done[0], 1u) == gridDim.x - 1;
   __syncthreads();
   if (s_last) {
     __threadfence();
@@ -283,8 +305,8 @@ constexpr uint32_t kExpandSmall = 8;  // a thread writes up to this many items i
 
 // Each block owns a contiguous range of queries: a thread writes the items of
 // a query with few items, and the whole block writes those of larger ones.
-__global__ __launch_bounds__(256) void k_expand(BatchArgs a, int qpb) {
-  __shared__ int s_big[256];
+__global__ __launch_bounds__(64) void k_expand(BatchArgs a, int qpb) {
+  __shared__ int s_big[64];
   __shared__ int s_nbig;
   const int q0 = blockIdx.x * qpb;
   const int q1 = min(a.nq, q0 + qpb);
@@ -515,7 +537,7 @@ __device__ __forceinline__ void chunk_loop(const BatchArgs &a, const uint32_t *r
   const uint32_t nchunks = *(volatile const uint32_t *)&a.ctr->total_chunks;
   for (;;) {
     uint32_t c = 0;
-    if (lane == 0) c = atomicAdd(&a.ctr->chunk_ctr, 1u);
+    if (lane == 0) c = atomicAdd(&a.ctr->chunk_ctr[0], 1u);
     c = __shfl(c, 0, 64);
     if (c >= nchunks) break;
     const uint2 it = a.items[(size_t)c * kChunk + lane];
@@ -650,11 +672,11 @@ hipError_t launch_batch_front(const BatchArgs &a, hipStream_t s) {
   const unsigned g = blocks_for(a.nq, 256);
   hipLaunchKernelGGL(k_prepare, dim3(g), dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_bucketize, dim3(g), dim3(256), 0, s, a);
-  // at most 64 queries per expansion block, and at least ~1024 blocks
+  // one-wave blocks of at most 64 queries, and at least ~2048 blocks
   int qpb = 64;
-  if (blocks_for(a.nq, qpb) < 1024) qpb = (int)((a.nq + 1023) / 1024);
+  if (blocks_for(a.nq, qpb) < 2048) qpb = (int)((a.nq + 2047) / 2048);
   if (qpb < 1) qpb = 1;
-  hipLaunchKernelGGL(k_expand, dim3(blocks_for(a.nq, qpb)), dim3(256), 0, s, a, qpb);
+  hipLaunchKernelGGL(k_expand, dim3(blocks_for(a.nq, qpb)), dim3(64), 0, s, a, qpb);
   return hipGetLastError();
 }
 

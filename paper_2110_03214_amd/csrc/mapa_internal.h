@@ -50,19 +50,22 @@ static_assert(sizeof(Plan) == 48, "Plan layout");
 
 constexpr uint8_t kPlanOk = 0, kPlanNofit = 1, kPlanInvalid = 3;
 
-// Per-batch counters (device).  Zeroed at allocation; the scan kernel
-// re-zeroes what it consumed so the next batch starts clean.
+// Per-batch counters (device).  Zeroed at allocation; the last k_bucketize
+// block re-zeroes what the batch consumed so the next batch starts clean.
+// Counters hit by atomics from many blocks each own a 128-byte line, so their
+// atomics spread over L2 channels instead of queueing on one.
+constexpr int kLine = 32;  // u32 per 128-byte line
 struct Counters {
-  uint32_t blocks_done;   // k_bucketize blocks finished (the last one lays buckets out)
-  uint32_t pad0;
-  unsigned long long total_leaves;
-  unsigned long long total_items[kNumSplits];
-  uint32_t bucket_items[kNumBuckets];
+  unsigned long long total_leaves[kLine / 2];
+  unsigned long long total_items[kNumSplits][kLine / 2];  // [j][0] used
+  uint32_t bucket_items[kNumBuckets][kLine];              // [b][0] used
+  uint32_t blocks_done[kLine];                            // k_bucketize blocks finished
+  uint32_t chunk_ctr[kLine];                              // next chunk to expand
   uint32_t bucket_start[kNumBuckets];
   uint32_t total_chunks;
-  uint32_t chunk_ctr;
   uint32_t chosen_split;
   uint32_t self_check_failures;
+  uint32_t pad;
   unsigned long long last_total_items;
 };
 
