@@ -8,8 +8,8 @@
 //                shape bucket, offset inside the bucket; the last block lays
 //                the buckets out (largest items first), pads each to whole
 //                64-item chunks and resets the per-batch counters.
-//   k_expand     writes every query's prefix items (query, prefix): small
-//                queries one thread each, larger ones a whole block each.
+//   k_expand     fills every query's work-list slots with (query, item index);
+//                k_enumerate turns the index into the prefix tuple.
 //   k_enumerate  persistent: each wave takes a 64-item chunk; each lane
 //                expands its prefix depth-first over the remaining pattern
 //                positions, scoring every match incrementally, and keeps a
@@ -34,6 +34,8 @@
 // share one 32-bit word (plane 2w in the low half, 2w+1 in the high half), so
 // sum_{u in X} W[v][u] = sum_w 4^w * (popc(row_w & X2) + popc((row_w & X2) >> 16))
 // with X2 = X | X << 16.
+#include <algorithm>
+
 #include "mapa_internal.h"
 
 namespace mapa {
@@ -218,12 +220,14 @@ __device__ void layout_buckets(const BatchArgs &a) {
   }
 }
 
-__global__ __launch_bounds__(256) void k_bucketize(BatchArgs a) {
+// Few, fat blocks: each block histograms many queries in LDS and then adds
+// one total per bucket to the global counters, so every global counter sees
+// only a handful of atomics.
+__global__ __launch_bounds__(1024) void k_bucketize(BatchArgs a) {
   __shared__ int s_split;
   __shared__ bool s_last;
   __shared__ uint32_t s_cnt[kNumBuckets];
   __shared__ uint32_t s_base[kNumBuckets];
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
   for (int b = threadIdx.x; b < kNumBuckets; b += blockDim.x) s_cnt[b] = 0;
   if (threadIdx.x == 0) {
     // The split is a pure function of batch totals, so every block picks the
@@ -247,28 +251,39 @@ __global__ __launch_bounds__(256) void k_bucketize(BatchArgs a) {
   }
   __syncthreads();
   const int j = s_split;
-  int b = -1;
-  uint32_t local = 0;
-  Plan p;
-  if (i < a.nq) {
-    p = a.plan[i];
-    if (p.status == kPlanOk) {
-      const int d = a.split_d[((size_t)p.F * (kMaxK + 1) + p.k) * kNumSplits + j];
-      const uint32_t nitems = (uint32_t)c_tab.perm[p.F][d];
-      b = bucket_id(p.mode, p.k - d, p.F - d);
-      p.d = (uint8_t)d;
-      p.bucket = (uint16_t)b;
-      p.nitems = nitems;
-      local = atomicAdd(&s_cnt[b], nitems);
+  const int per_block = (a.nq + gridDim.x - 1) / gridDim.x;
+  const int q0 = blockIdx.x * per_block;
+  const int q1 = min(a.nq, q0 + per_block);
+  constexpr int kMaxPerThread = 16;
+  uint32_t local[kMaxPerThread];
+  int bk[kMaxPerThread];
+#pragma unroll
+  for (int r = 0; r < kMaxPerThread; ++r) {
+    const int i = q0 + threadIdx.x + r * (int)blockDim.x;
+    bk[r] = -1;
+    local[r] = 0;
+    if (i < q1) {
+      const Plan &p = a.plan[i];
+      if (p.status == kPlanOk) {
+        const int d = a.split_d[((size_t)p.F * (kMaxK + 1) + p.k) * kNumSplits + j];
+        const uint32_t nitems = (uint32_t)c_tab.perm[p.F][d];
+        const int b = bucket_id(p.mode, p.k - d, p.F - d);
+        a.plan[i].d = (uint8_t)d;
+        a.plan[i].bucket = (uint16_t)b;
+        a.plan[i].nitems = nitems;
+        bk[r] = b;
+        local[r] = atomicAdd(&s_cnt[b], nitems);
+      }
     }
   }
   __syncthreads();
   for (int c = threadIdx.x; c < kNumBuckets; c += blockDim.x)
     s_base[c] = s_cnt[c] ? atomicAdd(&a.ctr->bucket_items[c][0], s_cnt[c]) : 0u;
   __syncthreads();
-  if (b >= 0) {
-    p.item_off = s_base[b] + local;
-    a.plan[i] = p;
+#pragma unroll
+  for (int r = 0; r < kMaxPerThread; ++r) {
+    const int i = q0 + threadIdx.x + r * (int)blockDim.x;
+    if (bk[r] >= 0) a.plan[i].item_off = s_base[bk[r]] + local[r];
   }
   // the last block to finish lays the buckets out
   __threadfence();
@@ -285,9 +300,11 @@ __global__ __launch_bounds__(256) void k_bucketize(BatchArgs a) {
 // Prefix item x of a query (0 <= x < F!/(F-d)!) is the x-th injective
 // d-tuple of free vertices in lexicographic order: digit t of x in the mixed
 // radix (F, F-1, ..., F-d+1) picks the digit-th smallest still-unused vertex.
-__device__ __forceinline__ uint32_t unrank_prefix(uint32_t x, int d, int F, uint32_t R,
-                                                  uint32_t div0) {
-  uint32_t rem = x, div = div0, avail = R, code = 0;
+// Returns the tuple with the vertex of position t at bits 4t..4t+3.
+__device__ __forceinline__ uint32_t unrank_prefix(uint32_t x, int d, int F, uint32_t R) {
+  uint32_t div = 1;
+  for (int t = 1; t < d; ++t) div *= (uint32_t)(F - t);
+  uint32_t rem = x, avail = R, code = 0;
   for (int t = 0; t < d; ++t) {
     uint32_t r = rem / div;
     rem -= r * div;
@@ -301,10 +318,11 @@ __device__ __forceinline__ uint32_t unrank_prefix(uint32_t x, int d, int F, uint
   return code;
 }
 
-constexpr uint32_t kExpandSmall = 8;  // a thread writes up to this many items itself
+constexpr uint32_t kExpandSmall = 16;  // a lane writes up to this many items itself
 
-// Each block owns a contiguous range of queries: a thread writes the items of
-// a query with few items, and the whole block writes those of larger ones.
+// Work-list fill: item slot base+x of a query holds (query, x).  One-wave
+// blocks own a range of queries; a lane fills a small query's items, the
+// whole wave a large one's.
 __global__ __launch_bounds__(64) void k_expand(BatchArgs a, int qpb) {
   __shared__ int s_big[64];
   __shared__ int s_nbig;
@@ -319,24 +337,16 @@ __global__ __launch_bounds__(64) void k_expand(BatchArgs a, int qpb) {
       s_big[atomicAdd(&s_nbig, 1)] = i;
       continue;
     }
-    const uint32_t base = a.ctr->bucket_start[p.bucket] + p.item_off;
-    const int d = p.d, F = p.F;
-    uint32_t div0 = 1;
-    for (int t = 1; t < d; ++t) div0 *= (uint32_t)(F - t);
-    for (uint32_t x = 0; x < p.nitems; ++x)
-      a.items[base + x] = make_uint2((uint32_t)i, unrank_prefix(x, d, F, p.R, div0));
+    uint2 *dst = a.items + a.ctr->bucket_start[p.bucket] + p.item_off;
+    for (uint32_t x = 0; x < p.nitems; ++x) dst[x] = make_uint2((uint32_t)i, x);
   }
   __syncthreads();
   const int nbig = s_nbig;
   for (int bi = 0; bi < nbig; ++bi) {
     const int i = s_big[bi];
     const Plan &p = a.plan[i];
-    const uint32_t base = a.ctr->bucket_start[p.bucket] + p.item_off;
-    const int d = p.d, F = p.F;
-    uint32_t div0 = 1;
-    for (int t = 1; t < d; ++t) div0 *= (uint32_t)(F - t);
-    for (uint32_t x = threadIdx.x; x < p.nitems; x += blockDim.x)
-      a.items[base + x] = make_uint2((uint32_t)i, unrank_prefix(x, d, F, p.R, div0));
+    uint2 *dst = a.items + a.ctr->bucket_start[p.bucket] + p.item_off;
+    for (uint32_t x = threadIdx.x; x < p.nitems; x += blockDim.x) dst[x] = make_uint2((uint32_t)i, x);
   }
 }
 
@@ -483,8 +493,9 @@ __device__ __forceinline__ void run_item(const BatchArgs &a, const uint32_t *row
     rest = p.R;
     kp = p.kp0;
     bool ok = true;
+    const uint32_t prefix = unrank_prefix(it.y, d, p.F, p.R);
     for (int pos = 0; pos < d; ++pos) {
-      const int v = (it.y >> (4 * pos)) & 15;
+      const int v = (prefix >> (4 * pos)) & 15;
       uint32_t nbm, cand;
       if (s.linked)
         node_masks<WPR, true>(s, rest, code, pos, nbm, cand);
@@ -671,7 +682,11 @@ static inline unsigned blocks_for(long long n, int threads) {
 hipError_t launch_batch_front(const BatchArgs &a, hipStream_t s) {
   const unsigned g = blocks_for(a.nq, 256);
   hipLaunchKernelGGL(k_prepare, dim3(g), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(k_bucketize, dim3(g), dim3(256), 0, s, a);
+  // 1024-thread blocks, up to 16 queries per thread, at most 64 blocks
+  unsigned gb = blocks_for(a.nq, 1024 * 16);
+  if (gb < 64) gb = std::min<unsigned>(64, blocks_for(a.nq, 1024));
+  if (gb < 1) gb = 1;
+  hipLaunchKernelGGL(k_bucketize, dim3(gb), dim3(1024), 0, s, a);
   // one-wave blocks of at most 64 queries, and at least ~2048 blocks
   int qpb = 64;
   if (blocks_for(a.nq, qpb) < 2048) qpb = (int)((a.nq + 2047) / 2048);
