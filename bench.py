@@ -153,6 +153,9 @@ def main():
     ap.add_argument("--config", type=int, default=2, choices=(1, 2, 3))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="no HIP-event timing of the kernel")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run one plain device-to-device copy of this many MiB first, to scale "
+                         "hardware memory counters (FETCH_SIZE / WRITE_SIZE) against known bytes")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -175,6 +178,14 @@ def main():
 
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
+    if args.copy_calibration_mib:
+        src = torch.empty(args.copy_calibration_mib << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        src.fill_(1)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     ctx = B.Context(0)
     qh, ids = B.load_workload(ctx, wl)
     qh["commit"] = 1

@@ -197,13 +197,30 @@ __device__ void layout_buckets(const BatchArgs &a) {
     s_pad[r] = (cnt + (kChunk - 1)) & ~(uint32_t)(kChunk - 1);
   }
   __syncthreads();
-  if (t == 0) {
-    uint32_t acc = 0;
-    for (int r = 0; r < kNumBuckets; ++r) {
-      s_start[r] = acc;
-      acc += s_pad[r];
+  if (t < 64) {
+    // exclusive scan of the padded sizes in rank order by one wave: each lane
+    // owns 5 consecutive ranks (64 x 5 >= 272)
+    constexpr int kPer = (kNumBuckets + 63) / 64;
+    uint32_t sum = 0;
+    for (int e = 0; e < kPer; ++e) {
+      const int r = t * kPer + e;
+      if (r < kNumBuckets) sum += s_pad[r];
     }
-    a.ctr->total_chunks = acc / kChunk;
+    uint32_t incl = sum;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint32_t o = __shfl_up(incl, off, 64);
+      if (t >= off) incl += o;
+    }
+    uint32_t run = incl - sum;
+    for (int e = 0; e < kPer; ++e) {
+      const int r = t * kPer + e;
+      if (r < kNumBuckets) {
+        s_start[r] = run;
+        run += s_pad[r];
+      }
+    }
+    if (t == 63) a.ctr->total_chunks = incl / kChunk;
   }
   __syncthreads();
   for (int r = t; r < kNumBuckets; r += blockDim.x) {
