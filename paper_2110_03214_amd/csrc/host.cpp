@@ -170,7 +170,7 @@ Tables build_tables() {
   // buckets laid out largest items first (longest-processing-time order)
   std::vector<std::pair<double, int>> order;
   for (int b = 0; b < kNumBuckets; ++b) {
-    const int Fp = b % kFp, L = (b / kFp) % kMaxK + 1;
+    const int Fp = b % kFp, L = (b / kFp) % kMaxK + 1;  // see bucket_id
     double leaves = 0;
     if (Fp >= L) {
       leaves = 1;

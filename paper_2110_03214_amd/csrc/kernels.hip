@@ -284,7 +284,7 @@ __global__ __launch_bounds__(1024) void k_bucketize(BatchArgs a) {
       if (p.status == kPlanOk) {
         const int d = a.split_d[((size_t)p.F * (kMaxK + 1) + p.k) * kNumSplits + j];
         const uint32_t nitems = (uint32_t)c_tab.perm[p.F][d];
-        const int b = bucket_id(p.mode, p.k - d, p.F - d);
+        const int b = bucket_id(p.mode, p.kind, p.k - d, p.F - d);
         a.plan[i].d = (uint8_t)d;
         a.plan[i].bucket = (uint16_t)b;
         a.plan[i].nitems = nitems;
@@ -377,8 +377,10 @@ struct LaneState {
   int linked;
   unsigned long long nbtab;  // byte p: pattern neighbours of position p that precede it
   uint32_t count;        // matches seen
-  int bkey;              // best key so far (-1: none)
-  uint32_t bcode;        // its mapping, vertex of position p at bits 4p..4p+3
+  // best leaf so far: bpk = ((key + 1) << 4) | (15 - last vertex) of the best
+  // leaf-parent node (0: none), bcode = that node's mapping of positions < k-1
+  uint32_t bpk;
+  uint32_t bcode;
 };
 
 template <int WPR>
@@ -401,22 +403,35 @@ __device__ __forceinline__ uint32_t adjacency(const uint32_t *r) {
 }
 
 // Vertices at the pattern neighbours of position p that precede it, and the
-// candidate set for position p (LINKED: must touch each of them).
-template <int WPR, bool LINKED>
-__device__ __forceinline__ void node_masks(const LaneState &s, uint32_t rest, uint32_t code,
-                                           int p, uint32_t &nbm, uint32_t &cand) {
-  const uint32_t nbpos = (uint32_t)(s.nbtab >> (8 * p)) & 0xFFu;
+// candidate set for position p.
+//   ALL mode: computed per pattern kind (wave-uniform): ring -> the previous
+//   vertex, plus vertex 0 at the closing position; tree -> the parent
+//   (heap numbering); all-to-all -> every chosen vertex.  Candidates: every
+//   free vertex not chosen yet.
+//   LINKED mode: from the back-neighbour table; candidates must also be
+//   adjacent to each of those vertices.
+template <int WPR, bool LINKED, bool LAST>
+__device__ __forceinline__ void node_masks(const LaneState &s, int kind, uint32_t rest,
+                                           uint32_t code, int p, uint32_t prev, uint32_t &nbm,
+                                           uint32_t &cand) {
   cand = rest;
-  if (!LINKED && nbpos == ((1u << p) - 1u)) {
-    nbm = s.R & ~rest;  // every earlier position: the chosen set itself
-    return;
-  }
-  nbm = 0;
-  for (uint32_t m = nbpos; m; m &= m - 1) {
-    const int j = __ffs(m) - 1;
-    const int v = (code >> (4 * j)) & 15;
-    nbm |= 1u << v;
-    if constexpr (LINKED) cand &= adjacency<WPR>(s.trow + v * WPR);
+  if constexpr (!LINKED) {
+    if (kind == MAPA_ALL_TO_ALL) {
+      nbm = s.R & ~rest;
+    } else if (kind == MAPA_RING) {
+      nbm = p > 0 ? (1u << prev) : 0u;
+      if (LAST && s.k >= 3) nbm |= 1u << (code & 15u);
+    } else {
+      nbm = p > 0 ? (1u << ((code >> (4 * ((p - 1) >> 1))) & 15u)) : 0u;
+    }
+  } else {
+    const uint32_t nbpos = (uint32_t)(s.nbtab >> (8 * p)) & 0xFFu;
+    nbm = 0;
+    for (uint32_t m = nbpos; m; m &= m - 1) {
+      const int v = (code >> (4 * __builtin_ctz(m))) & 15;
+      nbm |= 1u << v;
+      cand &= adjacency<WPR>(s.trow + v * WPR);
+    }
   }
 }
 
@@ -426,19 +441,19 @@ __device__ __forceinline__ void node_masks(const LaneState &s, uint32_t rest, ui
 // and recurse; at the last position keep the node's best leaf.
 //
 // In ALL mode every lane of a wave holds an item of the same bucket, so all
-// lanes have the same number of candidates at every node: the loops are
-// counted on the scalar unit.  The leaf loop keeps the node's best as one u32,
-// ((key + 1) << 4) | (15 - c), so a single max() picks the largest key and,
-// among equal keys, the smallest vertex; the node's best then replaces the
-// lane's best only if strictly larger (leaves arrive in lexicographic order).
+// lanes have the same number of candidates mu at every node and the loops
+// are counted on the scalar unit.  The leaf loop keeps the node's best as one
+// u32, ((key + 1) << 4) | (15 - c), so one max() picks the largest key and,
+// among equal keys, the smallest vertex; the node then replaces the lane's
+// best only on a strictly larger key (leaves arrive in lexicographic order).
 template <int L, int WPR, bool LINKED>
-__device__ __forceinline__ void level(LaneState &s, uint32_t rest, uint32_t code, int kp, int p) {
+__device__ __forceinline__ void level(LaneState &s, int kind, uint32_t rest, uint32_t code,
+                                      int kp, int p, uint32_t prev, int mu) {
   uint32_t nbm, cand;
-  node_masks<WPR, LINKED>(s, rest, code, p, nbm, cand);
+  node_masks<WPR, LINKED, L == 1>(s, kind, rest, code, p, prev, nbm, cand);
   const uint32_t nb2 = nbm | (nbm << 16);
   const uint32_t rest2 = rest | (rest << 16);
-  int m = __popc(cand);
-  if constexpr (!LINKED) m = __builtin_amdgcn_readfirstlane(m);
+  const int m = LINKED ? __popc(cand) : mu;
   if constexpr (L == 1) {
     s.count += (uint32_t)m;
     // ((key + 1) << 4) | (15 - c)  ==  16*(kp + 1) + 15 + 16a*nb - 16b*dr - c
@@ -453,34 +468,35 @@ __device__ __forceinline__ void level(LaneState &s, uint32_t rest, uint32_t code
                                      __mul24(b16, wsum<WPR>(rc, rest2)) - c);
       pb = pk > pb ? pk : pb;
     }
-    const int key = (int)(pb >> 4) - 1;
-    if (key > s.bkey) {
-      s.bkey = key;
-      s.bcode = code | ((15u - (pb & 15u)) << (4 * p));
-    }
+    // strictly larger key <=> pb > (bpk | 15)
+    const bool better = pb > (s.bpk | 15u);
+    s.bpk = better ? pb : s.bpk;
+    s.bcode = better ? code : s.bcode;
   } else {
+    const int sh = 4 * p;
     for (int t = 0; t < m; ++t) {
       const int c = __builtin_ctz(cand);
       cand &= cand - 1;
       const uint32_t *rc = s.trow + c * WPR;
       const int kp2 = kp + __mul24(s.a, wsum<WPR>(rc, nb2)) - __mul24(s.b, wsum<WPR>(rc, rest2));
-      level<L - 1, WPR, LINKED>(s, rest & ~(1u << c), code | ((uint32_t)c << (4 * p)), kp2, p + 1);
+      level<L - 1, WPR, LINKED>(s, kind, rest & ~(1u << c), code | ((uint32_t)c << sh), kp2, p + 1,
+                                (uint32_t)c, mu - 1);
     }
   }
 }
 
 template <int WPR, bool LINKED>
-__device__ __forceinline__ void expand(LaneState &s, int L, uint32_t rest, uint32_t code, int kp,
-                                       int d) {
+__device__ __forceinline__ void expand(LaneState &s, int kind, int L, uint32_t rest,
+                                       uint32_t code, int kp, int d, uint32_t prev, int mu) {
   switch (L) {
-    case 1: level<1, WPR, LINKED>(s, rest, code, kp, d); break;
-    case 2: level<2, WPR, LINKED>(s, rest, code, kp, d); break;
-    case 3: level<3, WPR, LINKED>(s, rest, code, kp, d); break;
-    case 4: level<4, WPR, LINKED>(s, rest, code, kp, d); break;
-    case 5: level<5, WPR, LINKED>(s, rest, code, kp, d); break;
-    case 6: level<6, WPR, LINKED>(s, rest, code, kp, d); break;
-    case 7: level<7, WPR, LINKED>(s, rest, code, kp, d); break;
-    case 8: level<8, WPR, LINKED>(s, rest, code, kp, d); break;
+    case 1: level<1, WPR, LINKED>(s, kind, rest, code, kp, d, prev, mu); break;
+    case 2: level<2, WPR, LINKED>(s, kind, rest, code, kp, d, prev, mu); break;
+    case 3: level<3, WPR, LINKED>(s, kind, rest, code, kp, d, prev, mu); break;
+    case 4: level<4, WPR, LINKED>(s, kind, rest, code, kp, d, prev, mu); break;
+    case 5: level<5, WPR, LINKED>(s, kind, rest, code, kp, d, prev, mu); break;
+    case 6: level<6, WPR, LINKED>(s, kind, rest, code, kp, d, prev, mu); break;
+    case 7: level<7, WPR, LINKED>(s, kind, rest, code, kp, d, prev, mu); break;
+    case 8: level<8, WPR, LINKED>(s, kind, rest, code, kp, d, prev, mu); break;
     default: break;
   }
 }
@@ -491,12 +507,12 @@ __device__ __forceinline__ void run_item(const BatchArgs &a, const uint32_t *row
   const bool valid = it.x != kInvalidItem;
   LaneState s;
   s.count = 0;
-  s.bkey = -1;
+  s.bpk = 0;
   s.bcode = 0;
   s.k = 0;
   s.linked = 0;
-  uint32_t rest = 0, code = 0;
-  int kp = 0, L = 0, d = 0;
+  uint32_t rest = 0, code = 0, prev = 0;
+  int kp = 0, L = 0, d = 0, kind = 0, fp = 0;
   if (valid) {
     const Plan &p = a.plan[it.x];
     s.trow = rows + (uint32_t)p.topo * (16 * WPR);
@@ -506,7 +522,9 @@ __device__ __forceinline__ void run_item(const BatchArgs &a, const uint32_t *row
     s.k = p.k;
     s.linked = p.mode;
     s.nbtab = p.nbtab;
+    kind = p.kind;
     d = p.d;
+    fp = p.F - d;
     rest = p.R;
     kp = p.kp0;
     bool ok = true;
@@ -515,32 +533,44 @@ __device__ __forceinline__ void run_item(const BatchArgs &a, const uint32_t *row
       const int v = (prefix >> (4 * pos)) & 15;
       uint32_t nbm, cand;
       if (s.linked)
-        node_masks<WPR, true>(s, rest, code, pos, nbm, cand);
+        node_masks<WPR, true, false>(s, kind, rest, code, pos, prev, nbm, cand);
+      else if (pos == s.k - 1)
+        node_masks<WPR, false, true>(s, kind, rest, code, pos, prev, nbm, cand);
       else
-        node_masks<WPR, false>(s, rest, code, pos, nbm, cand);
+        node_masks<WPR, false, false>(s, kind, rest, code, pos, prev, nbm, cand);
       ok = ok && ((cand >> v) & 1u);
       const uint32_t *rv = s.trow + v * WPR;
       kp += __mul24(s.a, wsum<WPR>(rv, nbm | (nbm << 16))) -
             __mul24(s.b, wsum<WPR>(rv, rest | (rest << 16)));
       rest &= ~(1u << v);
       code |= (uint32_t)v << (4 * pos);
+      prev = (uint32_t)v;
     }
     L = ok ? (int)p.k - d : 0;
   }
-  // Items of one chunk share a bucket, so the match mode is wave-uniform
+  // Items of one chunk share a bucket: the mode, the pattern kind and (ALL
+  // mode) the number of free vertices below the prefix are wave-uniform
   // (lane 0 holds a real item whenever any lane does).
+  const int kind_w = __builtin_amdgcn_readfirstlane(kind);
+  const int fp_w = __builtin_amdgcn_readfirstlane(fp);
   if (__builtin_amdgcn_readfirstlane(s.linked))
-    expand<WPR, true>(s, L, rest, code, kp, d);
+    expand<WPR, true>(s, kind_w, L, rest, code, kp, d, prev, 0);
   else
-    expand<WPR, false>(s, L, rest, code, kp, d);
+    expand<WPR, false>(s, kind_w, L, rest, code, kp, d, prev, fp_w);
 
+  int bkey = -1;
+  uint32_t bcode = 0;
+  if (s.bpk) {
+    bkey = (int)(s.bpk >> 4) - 1;
+    bcode = s.bcode | ((15u - (s.bpk & 15u)) << (4 * (s.k - 1)));
+  }
   // best as one u64: key high, inverted lexicographic mapping code low, so
   // max() takes the largest key and then the smallest mapping.
   unsigned long long best = 0;
-  if (s.bkey >= 0) {
+  if (bkey >= 0) {
     uint32_t lex = 0;
-    for (int i = 0; i < s.k; ++i) lex = (lex << 4) | ((s.bcode >> (4 * i)) & 15u);
-    best = ((unsigned long long)(uint32_t)s.bkey << 32) | (0xFFFFFFFFu - lex);
+    for (int i = 0; i < s.k; ++i) lex = (lex << 4) | ((bcode >> (4 * i)) & 15u);
+    best = ((unsigned long long)(uint32_t)bkey << 32) | (0xFFFFFFFFu - lex);
   }
   unsigned long long cnt = s.count;
   const int qi = valid ? (int)it.x : -1;

@@ -17,17 +17,18 @@ constexpr int kMaxK = MAPA_MAX_K;
 constexpr int kNumSplits = 9;
 constexpr int kSplitWhole = kNumSplits - 1;
 
-// Shape buckets: (mode, L = levels left below the prefix, F' = free vertices
-// left below the prefix).  In ALL mode every item of one bucket expands the
-// same-shaped subtree, so the 64 lanes of a wave stay in lock step.
-constexpr int kFp = kMaxN + 1;                 // F' in 0..16
-constexpr int kNumBuckets = 2 * kMaxK * kFp;   // 272
-constexpr int kChunk = 64;                     // items per wave-chunk (one per lane)
+// Shape buckets: (mode, pattern kind, L = positions left below the prefix,
+// F' = free vertices left below the prefix).  Every item of one bucket
+// expands a subtree of the same pattern kind, and in ALL mode of the same
+// shape, so the 64 lanes of a wave run the same code in lock step.
+constexpr int kFp = kMaxN + 1;                      // F' in 0..16
+constexpr int kNumBuckets = 2 * 3 * kMaxK * kFp;    // 816
+constexpr int kChunk = 64;                          // items per wave-chunk (one per lane)
 constexpr int kPadReserve = (kChunk - 1) * kNumBuckets;
 constexpr uint32_t kInvalidItem = 0xFFFFFFFFu;
 
-__host__ __device__ inline int bucket_id(int mode, int L, int Fp) {
-  return mode * (kMaxK * kFp) + (L - 1) * kFp + Fp;
+__host__ __device__ inline int bucket_id(int mode, int kind, int L, int Fp) {
+  return ((mode * 3 + kind) * kMaxK + (L - 1)) * kFp + Fp;
 }
 
 // Per-query plan, written by the prepare/bucketize kernels.
