@@ -145,6 +145,68 @@ def cpu_baseline(wl, seconds: float = 8.0):
                       f"passes in {dt:.1f} s, static split by query over {cores} threads"}
 
 
+def run_plain(ctx, B, qh, limit: int = 4096):
+    """Plain form: one query per call, host pointers, synchronous (launch +
+    copy back + sync per query).  Returns queries/s and per-query latency."""
+    n = min(limit, len(qh))
+    q = qh[:n].copy()
+    q["commit"] = 0
+    lat = np.empty(n)
+    for i in range(min(64, n)):  # warm
+        ctx.query_batch(q[i:i + 1])
+    t0 = time.perf_counter()
+    for i in range(n):
+        t = time.perf_counter()
+        ctx.query_batch(q[i:i + 1])
+        lat[i] = time.perf_counter() - t
+    wall = time.perf_counter() - t0
+    return {"queries": n, "queries_per_s": n / wall, "p50_ms": float(np.percentile(lat, 50) * 1e3),
+            "p99_ms": float(np.percentile(lat, 99) * 1e3)}
+
+
+def run_serving(B, cfg: int, nreq: int, loads=(0.5, 0.8, 1.0, 1.2)):
+    """Serving form: a request trace through the continuous-batching loop.
+    First replays it as fast as possible to measure capacity, then at offered
+    loads that are fractions of that capacity (time unit scaled)."""
+    from paper_2110_03214_amd import synth
+    tr = synth.config4(nreq) if cfg == 4 else synth.config5(nreq)
+    rate_per_unit = nreq / tr.t_arrival[-1]
+    out = {"workload": ("serving: Poisson requests over 4,096 servers of the batched config's "
+                        "three topologies" if cfg == 4 else
+                        "mixed serving: bursty requests over 1,024 cube-mesh and 1,024 16-vertex "
+                        "servers"), "requests": nreq, "runs": []}
+    ctx = B.Context(0)
+    ids = ctx.load_servers(tr.topologies, tr.server_topo)
+    r = np.zeros(tr.n, dtype=B.REQUEST_DTYPE)
+    r["id"] = np.arange(tr.n)
+    r["t_arrival"], r["hold"], r["server"] = tr.t_arrival, tr.hold, ids[tr.server]
+    r["kind"], r["k"], r["a"], r["b"] = tr.kind, tr.k, 1, 1
+
+    def one(unit_us):
+        ctx.serve_start(max_batch=4096, inflight=2, time_unit_us=unit_us)
+        ctx.serve_submit(r)
+        got = 0
+        while got < tr.n:
+            got += len(ctx.serve_poll())
+            time.sleep(0.001)
+        return ctx.serve_stop()
+
+    cap = one(0.0)
+    capacity = cap["requests_per_s"]
+    out["capacity_requests_per_s"] = capacity
+    for f in loads:
+        unit = rate_per_unit / (f * capacity) * 1e6  # us per trace time unit
+        st = one(unit)
+        out["runs"].append({"offered_fraction": f, "offered_requests_per_s": f * capacity,
+                            "requests_per_s": st["requests_per_s"], "p50_us": st["p50_us"],
+                            "p99_us": st["p99_us"], "p999_us": st["p999_us"],
+                            "mean_batch": st["mean_batch"], "batches": st["batches"],
+                            "granted": st["granted"], "nofit": st["nofit"],
+                            "embeddings_per_s": st["embeddings_per_s"]})
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -153,6 +215,10 @@ def main():
     ap.add_argument("--config", type=int, default=2, choices=(1, 2, 3))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="no HIP-event timing of the kernel")
+    ap.add_argument("--plain", type=int, default=4096,
+                    help="queries timed in the plain one-query-per-launch form (0: skip)")
+    ap.add_argument("--serving", type=int, default=100000,
+                    help="requests of the serving trace timed through the serving loop (0: skip)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device-to-device copy of this many MiB first, to scale "
                          "hardware memory counters (FETCH_SIZE / WRITE_SIZE) against known bytes")
@@ -256,10 +322,16 @@ def main():
                            "unit": "Tops/s", "frac": achieved / ALU_PEAK, "traffic": None,
                            "kernel": "k_enumerate", "kernel_ms": avg_s * 1e3,
                            "ops_per_launch": ops}
+    if args.plain:
+        log("[bench] plain form: one query per launch")
+        out["plain_one_query_per_launch"] = run_plain(ctx, B, qh, args.plain)
+    ctx.close()
+    if args.serving and args.config == 2:
+        log("[bench] serving form")
+        out["serving"] = run_serving(B, 4, args.serving)
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(wl)
-    ctx.close()
     print(json.dumps(out), flush=True)
 
 
