@@ -460,6 +460,7 @@ __device__ __forceinline__ void level(LaneState &s, int kind, uint32_t rest, uin
     const int base = 16 * kp + 31;
     const int a16 = 16 * s.a, b16 = 16 * s.b;
     uint32_t pb = 0;
+#pragma unroll 2
     for (int t = 0; t < m; ++t) {
       const int c = __builtin_ctz(cand);
       cand &= cand - 1;
