@@ -246,6 +246,12 @@ int32_t mapa_reset_stats(mapa_ctx *ctx);
 /* Block until all work issued on the context has finished. */
 int32_t mapa_sync(mapa_ctx *ctx);
 
+/* Measure the device's integer vector-ALU throughput: a probe kernel of
+ * independent integer chains (the enumeration kernel's instruction mix) runs
+ * on every compute unit.  *ops_per_s receives 32-bit lane operations per
+ * second (host pointer).  Synchronous; changes no context state. */
+int32_t mapa_measure_alu_peak(mapa_ctx *ctx, double *ops_per_s);
+
 /* ---- serving loop (continuous batching) -------------------------------------
  * A context can run one serving loop: a host thread owned by the context that
  * takes allocation requests as they arrive, answers each one against the

@@ -98,6 +98,7 @@ SIGNATURES = {
     "mapa_get_stats": (_I32, [_P, ctypes.POINTER(Stats)]),
     "mapa_reset_stats": (_I32, [_P]),
     "mapa_sync": (_I32, [_P]),
+    "mapa_measure_alu_peak": (_I32, [_P, ctypes.POINTER(ctypes.c_double)]),
     "mapa_serve_start": (_I32, [_P, ctypes.POINTER(ServeOpts)]),
     "mapa_serve_submit": (_I32, [_P, _P, _I32]),
     "mapa_serve_poll": (_I32, [_P, _P, _I32, ctypes.POINTER(_I32)]),
@@ -267,6 +268,11 @@ class Context:
 
     def sync(self):
         check(lib().mapa_sync(self.h), "mapa_sync")
+
+    def measure_alu_peak(self) -> float:
+        v = ctypes.c_double()
+        check(lib().mapa_measure_alu_peak(self.h, ctypes.byref(v)), "mapa_measure_alu_peak")
+        return v.value
 
     # -- serving loop ----------------------------------------------------------
     def serve_start(self, max_batch=0, inflight=0, time_unit_us=0.0, admission_items=0,

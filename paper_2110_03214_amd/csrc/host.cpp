@@ -789,6 +789,35 @@ int32_t mapa_reset_stats(mapa_ctx *c) {
   return MAPA_OK;
 }
 
+int32_t mapa_measure_alu_peak(mapa_ctx *c, double *ops_per_s) {
+  if (!c || !ops_per_s) return fail(MAPA_ERR_INVALID_ARG, "NULL argument");
+  if (int32_t rc = not_while_serving(c, "mapa_measure_alu_peak")) return rc;
+  if (!c->has_device) return fail(MAPA_ERR_NO_DEVICE, "context has no device");
+  int32_t rc = sync_ctx(c);
+  if (rc) return rc;
+  const int blocks = std::max(1, c->cu_count) * 16;  // 16 waves per CU
+  const int iters = 4096;
+  uint32_t *d_out = nullptr;
+  if (dev_alloc(&d_out, blocks) != hipSuccess) return fail(MAPA_ERR_OOM, "probe buffer");
+  hipEvent_t e0, e1;
+  MAPA_HIPCHK(hipEventCreate(&e0));
+  MAPA_HIPCHK(hipEventCreate(&e1));
+  MAPA_HIPCHK(launch_valu_probe(d_out, blocks, iters, c->internal));  // warm-up
+  MAPA_HIPCHK(hipEventRecord(e0, c->internal));
+  MAPA_HIPCHK(launch_valu_probe(d_out, blocks, iters, c->internal));
+  MAPA_HIPCHK(hipEventRecord(e1, c->internal));
+  MAPA_HIPCHK(hipEventSynchronize(e1));
+  float ms = 0;
+  MAPA_HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  dev_free(d_out);
+  MAPA_HIPCHK(hipEventRecord(c->last, c->internal));
+  const double lane_ops = (double)blocks * 256.0 * iters * valu_probe_ops_per_iter();
+  *ops_per_s = ms > 0 ? lane_ops / (ms * 1e-3) : 0.0;
+  return MAPA_OK;
+}
+
 int32_t mapa_sync(mapa_ctx *c) {
   if (!c) return fail(MAPA_ERR_INVALID_ARG, "ctx is NULL");
   if (int32_t rc = not_while_serving(c, "mapa_sync")) return rc;

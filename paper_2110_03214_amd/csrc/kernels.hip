@@ -721,6 +721,48 @@ __global__ void k_release_apply(const int64_t *h, int32_t stride, int32_t count,
   atomicAnd(&busy[s], ~(uint32_t)x);
 }
 
+// ---------------------------------------------------------- ALU peak probe
+
+// Integer VALU throughput probe: eight independent chains per lane, each
+// step applying the enumeration kernel's instruction mix (and, popcount with
+// accumulate, shift, 24-bit multiply-add, max, add) to all eight chains in
+// turn, so consecutive instructions never depend on each other and issue,
+// not latency, limits the rate.  Written as inline VALU instructions so that
+// every iteration is exactly kProbeOpsPerIter ops per lane.
+constexpr int kProbeOpsPerIter = 8 * 6;
+
+#define MAPA_PROBE_STEP(OP)                                                     \
+  _Pragma("unroll") for (int c = 0; c < 8; ++c) asm volatile(OP : "+v"(x[c]) : "v"(m), "v"(k));
+
+__global__ __launch_bounds__(256) void k_valu_probe(uint32_t *out, int iters, uint32_t seed) {
+  uint32_t x[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) x[c] = seed * (threadIdx.x + 7u * c + 1u) + blockIdx.x;
+  const uint32_t m = seed | 0x00FF00FFu;
+  const uint32_t k = seed >> 7;
+  for (int i = 0; i < iters; ++i) {
+    MAPA_PROBE_STEP("v_and_b32 %0, %0, %1")
+    MAPA_PROBE_STEP("v_bcnt_u32_b32 %0, %0, %2")
+    MAPA_PROBE_STEP("v_lshrrev_b32 %0, 3, %0")
+    MAPA_PROBE_STEP("v_mad_u32_u24 %0, %0, 3, %2")
+    MAPA_PROBE_STEP("v_max_u32 %0, %0, %2")
+    MAPA_PROBE_STEP("v_add_u32 %0, %0, %1")
+  }
+  uint32_t r = 0;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) r ^= x[c];
+  if (r == 0x12345678u) out[blockIdx.x] = r;  // keeps the chains alive
+}
+
+#undef MAPA_PROBE_STEP
+
+hipError_t launch_valu_probe(uint32_t *out, int blocks, int iters, hipStream_t s) {
+  hipLaunchKernelGGL(k_valu_probe, dim3(blocks), dim3(256), 0, s, out, iters, 0x2545F491u);
+  return hipGetLastError();
+}
+
+int valu_probe_ops_per_iter() { return kProbeOpsPerIter; }
+
 // ---------------------------------------------------------------- launchers
 
 static inline unsigned blocks_for(long long n, int threads) {

@@ -120,6 +120,9 @@ hipError_t launch_enumerate(const BatchArgs &a, hipStream_t s);
 hipError_t launch_finalize(const BatchArgs &a, hipStream_t s);
 int enumerate_occupancy(int wpr, int rows_in_lds, int threads, size_t lds_bytes);
 
+hipError_t launch_valu_probe(uint32_t *out, int blocks, int iters, hipStream_t s);
+int valu_probe_ops_per_iter();
+
 hipError_t launch_set_busy(const int32_t *ids, const uint32_t *masks, int32_t count,
                            int32_t nservers, const int32_t *server_topo, const int32_t *topo_n,
                            uint32_t *busy, hipStream_t s);
