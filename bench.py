@@ -269,10 +269,6 @@ def main():
             torch.cuda.synchronize()
             log("[bench] first step done")
     torch.cuda.synchronize()
-    res = dr.cpu().numpy().view(B.RESULT_DTYPE)
-    assert int(res["count"].sum()) == emb, (int(res["count"].sum()), emb)
-    busy0 = ctx.get_busy(ids)
-    assert np.array_equal(busy0, wl.busy), "release did not restore the entry state"
 
     if not args.no_profile:
         ctx.profile(True)
@@ -289,6 +285,11 @@ def main():
     wall = time.perf_counter() - t0
     lat = np.array([a.elapsed_time(b) for a, b in ev])
     st = ctx.stats()
+    # every step scored every embedding and handed every allocation back
+    res = dr.cpu().numpy().view(B.RESULT_DTYPE)
+    assert int(res["count"].sum()) == emb, (int(res["count"].sum()), emb)
+    assert np.array_equal(ctx.get_busy(ids), wl.busy), "release did not restore the entry state"
+    assert st["self_check_failures"] == 0
     ctx.profile(False)
     log(f"[bench] {steps} steps in {wall:.3f} s; enumerate {st['enum_ms'] / max(1, st['enum_launches']):.3f} ms avg")
 

@@ -234,11 +234,13 @@ void build_rows(const uint8_t *W16, int n, int wpr, uint32_t *out /* 16*wpr */) 
     }
 }
 
-// Re-upload every device copy of the topology tables (after growth or a
-// weight-class change).  Caller has synchronised the context.
-int32_t upload_topologies(mapa_ctx *c) {
+// Upload the device copies of the topology tables: all of them after growth
+// or a change of row format, else only topology `first` onwards.  Caller has
+// synchronised the context.
+int32_t upload_topologies(mapa_ctx *c, size_t first, bool all) {
   const size_t T = c->topo_n.size();
   if (T > c->cap_topos) {
+    all = true;
     size_t cap = std::max<size_t>(16, c->cap_topos);
     while (cap < T) cap *= 2;
     dev_free(c->d_topo_n);
@@ -250,15 +252,20 @@ int32_t upload_topologies(mapa_ctx *c) {
       return fail(MAPA_ERR_OOM, "topology tables: device allocation failed");
     c->cap_topos = cap;
   }
-  std::vector<uint8_t> W(T * 256);
-  std::vector<uint32_t> rows(T * 16 * c->wpr);
-  for (size_t t = 0; t < T; ++t) {
-    std::memcpy(&W[t * 256], c->topo_W[t].data(), 256);
-    build_rows(c->topo_W[t].data(), c->topo_n[t], c->wpr, &rows[t * 16 * c->wpr]);
+  const size_t t0 = all ? 0 : first;
+  if (t0 >= T) return MAPA_OK;
+  const size_t nt = T - t0;
+  std::vector<uint8_t> W(nt * 256);
+  std::vector<uint32_t> rows(nt * 16 * c->wpr);
+  for (size_t t = t0; t < T; ++t) {
+    std::memcpy(&W[(t - t0) * 256], c->topo_W[t].data(), 256);
+    build_rows(c->topo_W[t].data(), c->topo_n[t], c->wpr, &rows[(t - t0) * 16 * c->wpr]);
   }
-  MAPA_HIPCHK(hipMemcpy(c->d_topo_n, c->topo_n.data(), T * sizeof(int32_t), hipMemcpyHostToDevice));
-  MAPA_HIPCHK(hipMemcpy(c->d_topo_W, W.data(), W.size(), hipMemcpyHostToDevice));
-  MAPA_HIPCHK(hipMemcpy(c->d_rows, rows.data(), rows.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+  MAPA_HIPCHK(hipMemcpy(c->d_topo_n + t0, c->topo_n.data() + t0, nt * sizeof(int32_t),
+                        hipMemcpyHostToDevice));
+  MAPA_HIPCHK(hipMemcpy(c->d_topo_W + t0 * 256, W.data(), W.size(), hipMemcpyHostToDevice));
+  MAPA_HIPCHK(hipMemcpy(c->d_rows + t0 * 16 * c->wpr, rows.data(), rows.size() * sizeof(uint32_t),
+                        hipMemcpyHostToDevice));
   return MAPA_OK;
 }
 
@@ -461,7 +468,7 @@ int32_t mapa_create_topology(mapa_ctx *c, int32_t n, const uint8_t *W, int32_t n
     c->topo_n.push_back(n);
     c->topo_W.push_back(w16);
     c->wpr = std::max(c->wpr, weight_class(W, n));
-    rc = upload_topologies(c);
+    rc = upload_topologies(c, (size_t)tid, c->wpr != old_wpr);
     if (!rc) rc = grow_servers(c, first + (size_t)num_servers);
     if (rc) {
       c->topo_n.pop_back();
