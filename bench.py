@@ -33,10 +33,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "pattern embeddings scored/sec + allocation queries/sec, p50/p99 latency"
-# MI355X: 256 CUs x 4 SIMD x 16 lanes = 64 int32 lane-ops per clock per CU
-# (one wave64 VALU op every 4 clocks on each of 4 SIMDs), 2.4 GHz peak clock.
-CU, LANES_PER_CLK, CLK = 256, 64, 2.4e9
-ALU_PEAK = CU * LANES_PER_CLK * CLK  # 39.32e12 int ops/s
+# MI355X vector-ALU ceiling for 32-bit lane operations: the published fp32
+# vector rate, 157.3 TFLOP/s, is 256 CUs x 2.4 GHz x 128 lanes x 2 flops per
+# FMA, so the vector ALUs retire at most 256 x 128 x 2.4e9 = 78.6e12 32-bit
+# lane-ops/s.  (A 4 SIMD x 16 lane model, 39.3e12, is exceeded in
+# measurement: the enumeration kernel itself sustains ~75 int32 lane-ops per
+# clock per CU.)
+CU, LANES_PER_CLK, CLK = 256, 128, 2.4e9
+ALU_PEAK = CU * LANES_PER_CLK * CLK  # 78.64e12 int32 lane-ops/s
 
 WORKLOAD_TEXT = {
     1: "tiny: 1,000 states of one 8-vertex cube-mesh (weights 1-2), 0-4 busy, ring k=4",
@@ -319,10 +323,12 @@ def main():
     if not args.no_profile and st["enum_launches"]:
         avg_s = st["enum_ms"] / st["enum_launches"] / 1e3
         achieved = ops / avg_s
+        probe = ctx.measure_alu_peak()
         out["roofline"] = {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_PEAK / 1e12,
                            "unit": "Tops/s", "frac": achieved / ALU_PEAK, "traffic": None,
                            "kernel": "k_enumerate", "kernel_ms": avg_s * 1e3,
-                           "ops_per_launch": ops}
+                           "ops_per_launch": ops,
+                           "measured_peak": probe / 1e12, "frac_of_measured_peak": achieved / probe}
     if args.plain:
         log("[bench] plain form: one query per launch")
         out["plain_one_query_per_launch"] = run_plain(ctx, B, qh, args.plain)

@@ -211,8 +211,12 @@ int32_t mapa_release(mapa_ctx *ctx, int32_t count, const int64_t *handles, int32
 /* ---- tuning and measurement ---------------------------------------------- */
 
 typedef struct {
-  int32_t min_leaves_per_item;  /* smallest prefix-item size considered (64)     */
-  int32_t items_per_lane;       /* target items per resident GPU lane (4)        */
+  int32_t min_leaves_per_item;  /* smallest prefix-item size considered (64);
+                                   sizes min_leaves_per_item * 2^j, j < 16,
+                                   and whole queries are the candidates      */
+  int32_t items_per_lane;       /* the batch takes the largest item size that
+                                   still gives every resident GPU lane this
+                                   many items (2)                            */
   int32_t blocks_per_cu;        /* persistent enumeration blocks per CU (0=auto) */
   int32_t threads_per_block;    /* 64..1024, multiple of 64 (256)                */
 } mapa_tuning;
@@ -275,8 +279,9 @@ int32_t mapa_measure_alu_peak(mapa_ctx *ctx, double *ops_per_s);
 typedef struct {
   int32_t max_batch;       /* queries per device batch, 1..65536 (0: 4096)            */
   int32_t inflight;        /* device batches in flight, 1 or 2 (0: 2)                  */
-  double time_unit_us;     /* wall-clock microseconds per trace time unit; 0: every
-                              request is due when it is submitted                      */
+  double time_unit_us;     /* wall-clock microseconds per trace time unit; trace time 0
+                              is when the run's first mapa_serve_submit returns.  0:
+                              every request is due when it is submitted               */
   int64_t admission_items; /* prefix-item budget of one batch (0: the work-list buffer) */
   int32_t item_leaves;     /* embeddings per prefix item assumed by admission (0: 4096) */
   int32_t reserved;        /* must be 0                                                 */
@@ -312,10 +317,11 @@ typedef struct {
   int64_t requests, completed, granted, nofit;
   int64_t host_nofit;      /* answered on the host without a device batch              */
   int64_t batches, releases, embeddings, admission_waits;
-  double wall_s;           /* from start to the last completion                        */
+  double wall_s;           /* from the first submission to the last completion         */
   double requests_per_s, embeddings_per_s;
   double p50_us, p99_us, p999_us, max_us;  /* request latency percentiles            */
   double mean_batch;       /* mean queries per device batch                            */
+  double mean_batch_us;    /* mean time from a batch's dispatch to its results on the host */
 } mapa_serve_stats;
 
 /* Start the loop.  opts may be NULL (defaults).  MAPA_ERR_STATE if a loop is

@@ -66,7 +66,7 @@ class ServeStats(ctypes.Structure):
         "requests", "completed", "granted", "nofit", "host_nofit", "batches", "releases",
         "embeddings", "admission_waits")] + [(n, ctypes.c_double) for n in (
             "wall_s", "requests_per_s", "embeddings_per_s", "p50_us", "p99_us", "p999_us",
-            "max_us", "mean_batch")]
+            "max_us", "mean_batch", "mean_batch_us")]
 
 
 REQUEST_DTYPE = np.dtype([("id", np.int64), ("t_arrival", np.float64), ("hold", np.float64),

@@ -108,7 +108,9 @@ struct mapa_ctx {
   std::vector<Graph> graphs;
   uint64_t version = 1;  // bumped whenever a value baked into a launch changes
 
-  mapa_tuning tuning{64, 4, 0, 256};
+  mapa_tuning tuning{64, 2, 0, 256};
+  uint64_t occ_shape = ~0ull;  // launch shape whose occupancy occ_blocks holds
+  int occ_blocks = 0;
   bool profile = false;
   std::vector<mapa::ProfEvents> prof;
   double prof_ms = 0;

@@ -106,12 +106,20 @@ void fill_args(mapa_ctx *c, const Workspace &w, BatchArgs &a) {
   a.ntopo = (int32_t)c->topo_n.size();
   a.wpr = c->wpr;
   a.split_d = c->d_split;
-  a.min_leaves = std::max(1, c->tuning.min_leaves_per_item);
   const int threads = c->tuning.threads_per_block;
   const size_t lds_bytes = (size_t)a.ntopo * 16 * c->wpr * sizeof(uint32_t);
   a.rows_in_lds = lds_bytes <= 48 * 1024 ? 1 : 0;
   int per_cu = c->tuning.blocks_per_cu;
-  if (per_cu <= 0) per_cu = enumerate_occupancy(c->wpr, a.rows_in_lds, threads, lds_bytes);
+  if (per_cu <= 0) {
+    // the occupancy query costs microseconds: ask once per launch shape
+    const uint64_t shape = ((uint64_t)lds_bytes << 24) | ((uint64_t)threads << 8) |
+                           ((uint64_t)c->wpr << 1) | (uint64_t)a.rows_in_lds;
+    if (shape != c->occ_shape) {
+      c->occ_blocks = enumerate_occupancy(c->wpr, a.rows_in_lds, threads, lds_bytes);
+      c->occ_shape = shape;
+    }
+    per_cu = c->occ_blocks;
+  }
   if (per_cu <= 0) per_cu = 4;
   a.enum_blocks = std::max(1, c->cu_count) * per_cu;
   a.enum_threads = threads;
@@ -184,7 +192,7 @@ Tables build_tables() {
 }
 
 // Prefix depth per (F, k, split): the smallest d <= k-1 whose items hold at
-// most min_leaves * 4^j embeddings; 0 (whole query) for the last split.
+// most min_leaves * 2^j embeddings; 0 (whole query) for the last split.
 std::vector<uint8_t> build_split_table(int min_leaves) {
   std::vector<uint8_t> tab(kSplitTable, 0);
   auto perm = [](int F, int k) {
@@ -195,7 +203,7 @@ std::vector<uint8_t> build_split_table(int min_leaves) {
   for (int F = 0; F <= kMaxN; ++F)
     for (int k = 1; k <= kMaxK; ++k)
       for (int j = 0; j < kSplitWhole; ++j) {
-        const unsigned long long T = (unsigned long long)min_leaves << (2 * j);
+        const unsigned long long T = (unsigned long long)min_leaves << j;
         int d = 0;
         while (d < k - 1 && perm(F - d, k - d) > T) ++d;
         tab[((size_t)F * (kMaxK + 1) + k) * kNumSplits + j] = (uint8_t)d;

@@ -112,7 +112,6 @@ __device__ __forceinline__ int set_weight(const uint32_t *trow, int wpr, uint32_
 
 __global__ __launch_bounds__(256) void k_prepare(BatchArgs a) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  unsigned long long leaves = 0;
   unsigned long long items[kNumSplits];
 #pragma unroll
   for (int j = 0; j < kNumSplits; ++j) items[j] = 0;
@@ -147,7 +146,6 @@ __global__ __launch_bounds__(256) void k_prepare(BatchArgs a) {
         p.status = kPlanNofit;
       } else {
         p.status = kPlanOk;
-        leaves = c_tab.perm[F][q.k];
         const uint8_t *sd = a.split_d + ((size_t)F * (kMaxK + 1) + q.k) * kNumSplits;
 #pragma unroll
         for (int j = 0; j < kNumSplits; ++j) items[j] = c_tab.perm[F][sd[j]];
@@ -159,24 +157,19 @@ __global__ __launch_bounds__(256) void k_prepare(BatchArgs a) {
     a.acc_best[i] = 0;
   }
   // wave sums -> block sums in LDS -> one global atomic per block and counter
-  __shared__ unsigned long long s_tot[kNumSplits + 1];
-  if (threadIdx.x <= kNumSplits) s_tot[threadIdx.x] = 0;
+  __shared__ unsigned long long s_tot[kNumSplits];
+  if (threadIdx.x < kNumSplits) s_tot[threadIdx.x] = 0;
   __syncthreads();
-  leaves = wave_sum_u64(leaves);
 #pragma unroll
   for (int j = 0; j < kNumSplits; ++j) items[j] = wave_sum_u64(items[j]);
   if ((threadIdx.x & 63) == 0) {
-    if (leaves) atomicAdd(&s_tot[kNumSplits], leaves);
 #pragma unroll
     for (int j = 0; j < kNumSplits; ++j)
       if (items[j]) atomicAdd(&s_tot[j], items[j]);
   }
   __syncthreads();
-  if (threadIdx.x < kNumSplits) {
-    if (s_tot[threadIdx.x]) atomicAdd(&a.ctr->total_items[threadIdx.x][0], s_tot[threadIdx.x]);
-  } else if (threadIdx.x == kNumSplits) {
-    if (s_tot[kNumSplits]) atomicAdd(&a.ctr->total_leaves[0], s_tot[kNumSplits]);
-  }
+  if (threadIdx.x < kNumSplits && s_tot[threadIdx.x])
+    atomicAdd(&a.ctr->total_items[threadIdx.x][0], s_tot[threadIdx.x]);
 }
 
 // --------------------------------------------------------------- bucketize
@@ -230,7 +223,6 @@ __device__ void layout_buckets(const BatchArgs &a) {
     a.ctr->bucket_items[b][0] = 0;
   }
   if (t == 0) {
-    a.ctr->total_leaves[0] = 0;
     for (int j = 0; j < kNumSplits; ++j) a.ctr->total_items[j][0] = 0;
     a.ctr->chunk_ctr[0] = 0;
     a.ctr->blocks_done[0] = 0;
@@ -248,18 +240,23 @@ __global__ __launch_bounds__(1024) void k_bucketize(BatchArgs a) {
   for (int b = threadIdx.x; b < kNumBuckets; b += blockDim.x) s_cnt[b] = 0;
   if (threadIdx.x == 0) {
     // The split is a pure function of batch totals, so every block picks the
-    // same one: the smallest item size that still gives at least
-    // target_items items in total and fits the work-list; else whole queries.
-    const unsigned long long total = a.ctr->total_leaves[0];
-    const unsigned long long target = (total + a.target_items - 1) / a.target_items;
+    // same one.  Item counts fall as j grows.  Take the fewest, largest items
+    // that still give every resident lane target_items / lanes of them;
+    // if no split does, the most items that fit the work-list.  Whole
+    // queries (one item each) always fit.
     int j = kSplitWhole;
-    for (int c = 0; c < kSplitWhole; ++c) {
-      const unsigned long long T = (unsigned long long)a.min_leaves << (2 * c);
-      if (T >= target && a.ctr->total_items[c][0] + kPadReserve <= a.cap_items) {
+    int most = kSplitWhole;
+    for (int c = kSplitWhole; c >= 0; --c) {
+      const unsigned long long n = a.ctr->total_items[c][0];
+      if (n + kPadReserve > a.cap_items) break;
+      most = c;
+      if (n >= a.target_items) {
         j = c;
         break;
       }
+      j = -1;
     }
+    if (j < 0) j = most;
     s_split = j;
     if (blockIdx.x == 0) {
       a.ctr->chosen_split = (uint32_t)j;

@@ -13,8 +13,8 @@ constexpr int kMaxN = MAPA_MAX_N;
 constexpr int kMaxK = MAPA_MAX_K;
 
 // Prefix-split candidates.  Split j < kSplitWhole aims at items of at most
-// min_leaves * 4^j embeddings; split kSplitWhole keeps every query whole.
-constexpr int kNumSplits = 9;
+// min_leaves * 2^j embeddings; split kSplitWhole keeps every query whole.
+constexpr int kNumSplits = 17;
 constexpr int kSplitWhole = kNumSplits - 1;
 
 // Shape buckets: (mode, pattern kind, L = positions left below the prefix,
@@ -57,7 +57,6 @@ constexpr uint8_t kPlanOk = 0, kPlanNofit = 1, kPlanInvalid = 3;
 // atomics spread over L2 channels instead of queueing on one.
 constexpr int kLine = 32;  // u32 per 128-byte line
 struct Counters {
-  unsigned long long total_leaves[kLine / 2];
   unsigned long long total_items[kNumSplits][kLine / 2];  // [j][0] used
   uint32_t bucket_items[kNumBuckets][kLine];              // [b][0] used
   uint32_t blocks_done[kLine];                            // k_bucketize blocks finished
@@ -78,7 +77,7 @@ struct Tables {          // uploaded once per device into __constant__ memory
 };
 
 // Prefix depth of split j for a query with F free vertices and k pattern
-// positions: the smallest d <= k-1 with (F-d)!/(F-k)! <= min_leaves * 4^j
+// positions: the smallest d <= k-1 with (F-d)!/(F-k)! <= min_leaves * 2^j
 // (j < kSplitWhole), and d = 0 for j = kSplitWhole.  Built on the host per
 // context (it depends on the tuning), indexed [F][k][j].
 constexpr int kSplitTable = (kMaxN + 1) * (kMaxK + 1) * kNumSplits;
@@ -108,7 +107,6 @@ struct BatchArgs {
   int32_t wpr;
   const uint8_t *split_d;  // [F][k][j], see kSplitTable
   // tuning
-  int32_t min_leaves;
   unsigned long long target_items;
   int32_t enum_blocks;
   int32_t enum_threads;

@@ -52,6 +52,7 @@ struct Slot {
   size_t cap_rel = 0;
   bool active = false;
   int32_t batch_id = -1;
+  double t_dispatch = 0;
   std::vector<Req> reqs;
   std::vector<uint32_t> busy_before;
 };
@@ -82,6 +83,7 @@ struct ServeState {
   bool stopping = false;               // guarded by mu
   double last_arrival = -1e300;        // caller side, guarded by mu
   int64_t submitted = 0;               // guarded by mu
+  double origin_us = -1;               // trace time 0 (first submission), guarded by mu
   int32_t error = MAPA_OK;
   std::string error_msg;
   Clock::time_point t0;
@@ -101,6 +103,7 @@ struct ServeState {
   mapa_serve_stats st{};
   int64_t completed = 0;
   int64_t batched_queries = 0;
+  double batch_us_sum = 0;
   double last_done_us = 0;
   hipEvent_t rel_event = nullptr;
   bool rel_event_valid = false;
@@ -184,6 +187,7 @@ int32_t harvest(ServeState *S, bool *did) {
       push_completion(S, cpl, now);
       make_ready(S, s);
     }
+    S->batch_us_sum += now - sl.t_dispatch;
     sl.active = false;
     sl.reqs.clear();
     *did = true;
@@ -331,6 +335,7 @@ int32_t dispatch(ServeState *S, Slot &sl, bool final_release, bool *did) {
     SERVE_CHK(hipMemcpyAsync(sl.h_res, sl.ws.d_res, nq * sizeof(mapa_result), hipMemcpyDeviceToHost,
                              sl.stream));
     sl.batch_id = S->next_batch++;
+    sl.t_dispatch = now;
     ++S->st.batches;
     S->batched_queries += nq;
   }
@@ -522,11 +527,18 @@ int32_t mapa_serve_submit(mapa_ctx *c, const mapa_request *reqs, int32_t n) {
     last = r.t_arrival;
   }
   S->last_arrival = last;
+  // the loop sees nothing of this call before the lock is released, so trace
+  // time 0 is taken at the end of the first submission
   const double now = S->now_us();
+  if (S->origin_us < 0) S->origin_us = now;
+  const size_t first = S->incoming.size();
   for (int32_t i = 0; i < n; ++i) {
-    const double due = S->opts.time_unit_us > 0 ? reqs[i].t_arrival * S->opts.time_unit_us : now;
+    const double due =
+        S->opts.time_unit_us > 0 ? reqs[i].t_arrival * S->opts.time_unit_us : 0.0;
     S->incoming.push_back({reqs[i], due});
   }
+  const double base = S->opts.time_unit_us > 0 ? S->origin_us : S->now_us();
+  for (size_t i = first; i < S->incoming.size(); ++i) S->incoming[i].due_us += base;
   S->submitted += n;
   S->cv.notify_all();
   return MAPA_OK;
@@ -561,7 +573,7 @@ int32_t mapa_serve_stop(mapa_ctx *c, mapa_serve_stats *out) {
   mapa_serve_stats st = S->st;
   st.requests = S->submitted;
   st.completed = S->completed;
-  st.wall_s = S->last_done_us * 1e-6;
+  st.wall_s = S->origin_us >= 0 ? std::max(0.0, S->last_done_us - S->origin_us) * 1e-6 : 0.0;
   st.requests_per_s = st.wall_s > 0 ? (double)st.completed / st.wall_s : 0;
   st.embeddings_per_s = st.wall_s > 0 ? (double)st.embeddings / st.wall_s : 0;
   st.p50_us = percentile(S->lat, 0.50);
@@ -569,6 +581,7 @@ int32_t mapa_serve_stop(mapa_ctx *c, mapa_serve_stats *out) {
   st.p999_us = percentile(S->lat, 0.999);
   st.max_us = S->lat.empty() ? 0 : *std::max_element(S->lat.begin(), S->lat.end());
   st.mean_batch = st.batches ? (double)S->batched_queries / (double)st.batches : 0;
+  st.mean_batch_us = st.batches ? S->batch_us_sum / (double)st.batches : 0;
   const int32_t err = S->error;
   const std::string msg = S->error_msg;
   c->serve = nullptr;
