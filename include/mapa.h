@@ -92,6 +92,8 @@ extern "C" {
 /* ---- flags ------------------------------------------------------------------ */
 #define MAPA_DEVICE_PTRS 1u  /* array arguments are device pointers; the call is
                                 asynchronous on the given stream                 */
+#define MAPA_PIPELINE 4u     /* host pointers: always run the multi-kernel batch
+                                pipeline, never the fused small-batch launch     */
 #define MAPA_USE_GRAPH 2u    /* with MAPA_DEVICE_PTRS: capture the batch's launch
                                 sequence into a HIP graph on first use for this
                                 (queries, results, nq, stream) and replay it on
@@ -182,7 +184,11 @@ int32_t mapa_get_busy(mapa_ctx *ctx, int32_t count, const int32_t *server_ids,
  *   Host pointers (flags = 0): the batch is validated first (bad field ->
  *     MAPA_ERR_INVALID_ARG, k > 8 -> MAPA_ERR_UNSUPPORTED, unknown server ->
  *     MAPA_ERR_UNKNOWN_SERVER; nothing runs on error), then the call blocks
- *     until res is filled.
+ *     until res is filled.  A small batch (at most 4096 queries, each on a
+ *     different server, at most 2^20 embeddings per query and 2^24 in all,
+ *     counted on the whole topology) runs as one fused launch that reads and
+ *     writes pinned staging memory; MAPA_PIPELINE forces the pipeline.
+ *     Results are identical either way.
  *   MAPA_DEVICE_PTRS: q and res are device pointers (16-byte aligned); the
  *     call returns once the work is queued on hip_stream (a hipStream_t,
  *     NULL = the default stream); malformed queries get status
@@ -214,9 +220,11 @@ typedef struct {
   int32_t min_leaves_per_item;  /* smallest prefix-item size considered (64);
                                    sizes min_leaves_per_item * 2^j, j < 16,
                                    and whole queries are the candidates      */
-  int32_t items_per_lane;       /* the batch takes the largest item size that
-                                   still gives every resident GPU lane this
-                                   many items (2)                            */
+  int32_t mean_item_leaves;     /* the batch takes the finest split whose
+                                   items still average this many embeddings
+                                   and give every resident GPU lane one
+                                   (128); a batch too small to fill the lanes
+                                   takes the finest split that fits          */
   int32_t blocks_per_cu;        /* persistent enumeration blocks per CU (0=auto) */
   int32_t threads_per_block;    /* 64..1024, multiple of 64 (256)                */
 } mapa_tuning;
@@ -322,6 +330,7 @@ typedef struct {
   double p50_us, p99_us, p999_us, max_us;  /* request latency percentiles            */
   double mean_batch;       /* mean queries per device batch                            */
   double mean_batch_us;    /* mean time from a batch's dispatch to its results on the host */
+  int64_t fused_batches;   /* batches run as one fused launch (small batches)    */
 } mapa_serve_stats;
 
 /* Start the loop.  opts may be NULL (defaults).  MAPA_ERR_STATE if a loop is

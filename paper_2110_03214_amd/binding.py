@@ -30,6 +30,7 @@ ALL_INJECTIVE, LINKED = 0, 1
 RES_OK, RES_NOFIT, RES_CONFLICT, RES_INVALID = 0, 1, 2, 3
 DEVICE_PTRS = 1
 USE_GRAPH = 2
+PIPELINE = 4
 
 QUERY_DTYPE = np.dtype([("server", np.int32), ("kind", np.uint8), ("k", np.uint8),
                         ("mode", np.uint8), ("commit", np.uint8), ("a", np.int16),
@@ -43,7 +44,7 @@ assert RESULT_DTYPE.fields["alloc_handle"][1] == 40
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [("min_leaves_per_item", ctypes.c_int32), ("items_per_lane", ctypes.c_int32),
+    _fields_ = [("min_leaves_per_item", ctypes.c_int32), ("mean_item_leaves", ctypes.c_int32),
                 ("blocks_per_cu", ctypes.c_int32), ("threads_per_block", ctypes.c_int32)]
 
 
@@ -66,7 +67,7 @@ class ServeStats(ctypes.Structure):
         "requests", "completed", "granted", "nofit", "host_nofit", "batches", "releases",
         "embeddings", "admission_waits")] + [(n, ctypes.c_double) for n in (
             "wall_s", "requests_per_s", "embeddings_per_s", "p50_us", "p99_us", "p999_us",
-            "max_us", "mean_batch", "mean_batch_us")]
+            "max_us", "mean_batch", "mean_batch_us")] + [("fused_batches", ctypes.c_int64)]
 
 
 REQUEST_DTYPE = np.dtype([("id", np.int64), ("t_arrival", np.float64), ("hold", np.float64),
@@ -218,10 +219,12 @@ class Context:
         return out
 
     # -- queries -------------------------------------------------------------
-    def query_batch(self, queries, results=None, stream=None, graph: bool = False):
-        """Host numpy QUERY_DTYPE array -> numpy RESULT_DTYPE array (blocking),
-        or device byte tensors (nq*16 and nq*48 bytes) -> asynchronous
-        (``graph=True``: replay a captured HIP graph of the batch)."""
+    def query_batch(self, queries, results=None, stream=None, graph: bool = False,
+                    pipeline: bool = False):
+        """Host numpy QUERY_DTYPE array -> numpy RESULT_DTYPE array (blocking;
+        ``pipeline=True``: never the fused small-batch launch), or device byte
+        tensors (nq*16 and nq*48 bytes) -> asynchronous (``graph=True``:
+        replay a captured HIP graph of the batch)."""
         if hasattr(queries, "data_ptr"):
             nq = queries.numel() * queries.element_size() // QUERY_DTYPE.itemsize
             flags = DEVICE_PTRS | (USE_GRAPH if graph else 0)
@@ -230,8 +233,8 @@ class Context:
             return results
         q = np.ascontiguousarray(queries, dtype=QUERY_DTYPE)
         res = np.zeros(len(q), dtype=RESULT_DTYPE) if results is None else results
-        check(lib().mapa_query_batch(self.h, _ptr(q), len(q), _ptr(res), 0, None),
-              "mapa_query_batch")
+        check(lib().mapa_query_batch(self.h, _ptr(q), len(q), _ptr(res),
+                                     PIPELINE if pipeline else 0, None), "mapa_query_batch")
         return res
 
     def release(self, handles, stride: int = 8, count: int | None = None, stream=None):

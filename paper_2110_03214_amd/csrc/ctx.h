@@ -42,7 +42,8 @@ void dev_free(T *&p) {
 struct Workspace {
   size_t cap_q = 0;
   Plan *d_plan = nullptr;
-  unsigned long long *d_acc_count = nullptr, *d_acc_best = nullptr;
+  unsigned long long *d_acc_count = nullptr, *d_acc_best = nullptr;  // zero between batches
+  uint32_t *d_done = nullptr;  // fused launch: blocks finished per query, zero between batches
   mapa_query *d_q = nullptr;
   mapa_result *d_res = nullptr;
   uint2 *d_items = nullptr;
@@ -95,6 +96,11 @@ struct mapa_ctx {
   uint32_t *d_flag = nullptr;
   size_t cap_small = 0;
   uint8_t *d_split = nullptr;  // prefix depth per (F, k, split), from the tuning
+  // pinned staging of the fused small-batch path (kFusedMaxQueries each)
+  mapa_query *h_fq = nullptr;
+  mapa_result *h_fres = nullptr;
+  std::vector<uint32_t> srv_stamp;  // per server: last batch stamp (distinct-server test)
+  uint32_t stamp = 0;
 
   // captured batch graphs (device-pointer batches with MAPA_USE_GRAPH)
   struct Graph {
@@ -108,7 +114,7 @@ struct mapa_ctx {
   std::vector<Graph> graphs;
   uint64_t version = 1;  // bumped whenever a value baked into a launch changes
 
-  mapa_tuning tuning{64, 2, 0, 256};
+  mapa_tuning tuning{64, 128, 0, 256};
   uint64_t occ_shape = ~0ull;  // launch shape whose occupancy occ_blocks holds
   int occ_blocks = 0;
   bool profile = false;
@@ -123,6 +129,17 @@ struct mapa_ctx {
 namespace mapa {
 
 int32_t sync_ctx(mapa_ctx *c);
+
+// F!/(F-k)!: embeddings of a k-position pattern into F free vertices (0 if k > F).
+unsigned long long perm_leaves(int F, int k);
+
+// True when the nq queries name nq different servers (servers must be valid).
+bool distinct_servers(mapa_ctx *c, const mapa_query *q, int32_t nq);
+// Enqueue the fused small-batch launch for nq queries at q (device or pinned
+// host memory), results to res, on stream s, counting self-check failures
+// in workspace w.
+int32_t enqueue_fused(mapa_ctx *c, const Workspace &w, const mapa_query *q, mapa_result *res,
+                      int32_t nq, hipStream_t s);
 void fill_args(mapa_ctx *c, const Workspace &w, BatchArgs &a);
 
 // Enqueue the whole batch pipeline (prepare .. finalize) for nq queries that

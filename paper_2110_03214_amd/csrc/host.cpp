@@ -57,13 +57,19 @@ int32_t ws_ensure_q(Workspace &w, size_t nq) {
   dev_free(w.d_plan);
   dev_free(w.d_acc_count);
   dev_free(w.d_acc_best);
+  dev_free(w.d_done);
   dev_free(w.d_q);
   dev_free(w.d_res);
   w.cap_q = 0;
   if (dev_alloc(&w.d_plan, cap) != hipSuccess || dev_alloc(&w.d_acc_count, cap) != hipSuccess ||
-      dev_alloc(&w.d_acc_best, cap) != hipSuccess || dev_alloc(&w.d_q, cap) != hipSuccess ||
-      dev_alloc(&w.d_res, cap) != hipSuccess)
+      dev_alloc(&w.d_acc_best, cap) != hipSuccess || dev_alloc(&w.d_done, cap) != hipSuccess ||
+      dev_alloc(&w.d_q, cap) != hipSuccess || dev_alloc(&w.d_res, cap) != hipSuccess)
     return fail(MAPA_ERR_OOM, "batch workspace for %zu queries: device allocation failed", nq);
+  // accumulators and block counters start at zero; every batch leaves them so
+  MAPA_HIPCHK(hipMemset(w.d_acc_count, 0, cap * sizeof(unsigned long long)));
+  MAPA_HIPCHK(hipMemset(w.d_acc_best, 0, cap * sizeof(unsigned long long)));
+  MAPA_HIPCHK(hipMemset(w.d_done, 0, cap * sizeof(uint32_t)));
+  MAPA_HIPCHK(hipDeviceSynchronize());
   w.cap_q = cap;
   return MAPA_OK;
 }
@@ -72,6 +78,7 @@ void ws_destroy(Workspace &w) {
   dev_free(w.d_plan);
   dev_free(w.d_acc_count);
   dev_free(w.d_acc_best);
+  dev_free(w.d_done);
   dev_free(w.d_q);
   dev_free(w.d_res);
   dev_free(w.d_items);
@@ -124,8 +131,53 @@ void fill_args(mapa_ctx *c, const Workspace &w, BatchArgs &a) {
   a.enum_blocks = std::max(1, c->cu_count) * per_cu;
   a.enum_threads = threads;
   const unsigned long long lanes = (unsigned long long)std::max(1, c->cu_count) * per_cu * threads;
-  a.target_items =
-      std::max<unsigned long long>(1, lanes * (unsigned long long)std::max(1, c->tuning.items_per_lane));
+  a.lanes = std::max<unsigned long long>(1, lanes);
+  a.mean_leaves = (uint32_t)std::max(1, c->tuning.mean_item_leaves);
+}
+
+unsigned long long perm_leaves(int F, int k) {
+  if (k > F) return 0;
+  unsigned long long p = 1;
+  for (int i = 0; i < k; ++i) p *= (unsigned long long)(F - i);
+  return p;
+}
+
+bool distinct_servers(mapa_ctx *c, const mapa_query *q, int32_t nq) {
+  if (c->srv_stamp.size() < c->server_topo.size()) c->srv_stamp.resize(c->server_topo.size(), 0);
+  if (++c->stamp == 0) {  // wrapped: clear the old stamps
+    std::fill(c->srv_stamp.begin(), c->srv_stamp.end(), 0u);
+    c->stamp = 1;
+  }
+  for (int32_t i = 0; i < nq; ++i) {
+    uint32_t &m = c->srv_stamp[(size_t)q[i].server];
+    if (m == c->stamp) return false;
+    m = c->stamp;
+  }
+  return true;
+}
+
+int32_t enqueue_fused(mapa_ctx *c, const Workspace &w, const mapa_query *q, mapa_result *res,
+                      int32_t nq, hipStream_t s) {
+  FusedArgs f;
+  std::memset(&f, 0, sizeof f);
+  f.q = q;
+  f.res = res;
+  f.nq = nq;
+  f.server_topo = c->d_server_topo;
+  f.busy = c->d_busy;
+  f.nservers = (int32_t)c->server_topo.size();
+  f.topo_n = c->d_topo_n;
+  f.rows = c->d_rows;
+  f.wpr = c->wpr;
+  f.self_check_failures = &w.d_ctr->self_check_failures;
+  f.acc_count = w.d_acc_count;
+  f.acc_best = w.d_acc_best;
+  f.done = w.d_done;
+  // spread small batches over several blocks per query, up to ~4 per CU
+  const int target = std::max(1, c->cu_count) * 4;
+  f.bpq = std::max(1, std::min(kFusedMaxBlocksPerQuery, target / std::max(1, nq)));
+  MAPA_HIPCHK(launch_fused(f, s));
+  return MAPA_OK;
 }
 
 int32_t enqueue_batch(mapa_ctx *c, const Workspace &w, const mapa_query *d_q, mapa_result *d_res,
@@ -169,6 +221,8 @@ Tables build_tables() {
       for (int p = 0; p < k; ++p) tab |= (unsigned long long)t.nb[kind][k][p] << (8 * p);
       t.nbtab[kind][k] = tab;
     }
+  for (int m = 2; m <= kMaxN; ++m)
+    t.inv[m] = (uint32_t)(((1ull << 32) + (unsigned long long)m - 1) / (unsigned long long)m);
   for (int F = 0; F <= kMaxN; ++F)
     for (int d = 0; d <= kMaxK; ++d) {
       unsigned long long v = 1;
@@ -439,6 +493,8 @@ int32_t mapa_ctx_destroy(mapa_ctx *c) {
     dev_free(c->d_handles);
     dev_free(c->d_flag);
     dev_free(c->d_split);
+    if (c->h_fq) (void)hipHostFree(c->h_fq);
+    if (c->h_fres) (void)hipHostFree(c->h_fres);
     if (c->last) (void)hipEventDestroy(c->last);
     if (c->internal) (void)hipStreamDestroy(c->internal);
   }
@@ -615,6 +671,32 @@ int32_t mapa_query_batch(mapa_ctx *c, const mapa_query *q, int32_t nq, mapa_resu
     ++c->batches;
     return MAPA_OK;
   }
+  if (!dev && !(flags & MAPA_PIPELINE) && nq <= kFusedMaxQueries) {
+    // small batch, one query per server: one fused launch on pinned staging
+    unsigned long long total = 0;
+    bool small = true;
+    for (int32_t i = 0; i < nq && small; ++i) {
+      const unsigned long long e = perm_leaves(c->topo_n[c->server_topo[q[i].server]], q[i].k);
+      small = e <= kFusedMaxQueryLeaves;
+      total += e;
+    }
+    if (small && total <= kFusedMaxLeaves && distinct_servers(c, q, nq)) {
+      if (!c->h_fq) {
+        MAPA_HIPCHK(hipHostMalloc((void **)&c->h_fq, kFusedMaxQueries * sizeof(mapa_query),
+                                  hipHostMallocDefault));
+        MAPA_HIPCHK(hipHostMalloc((void **)&c->h_fres, kFusedMaxQueries * sizeof(mapa_result),
+                                  hipHostMallocDefault));
+      }
+      std::memcpy(c->h_fq, q, nq * sizeof(mapa_query));
+      MAPA_HIPCHK(begin_call(c, s));
+      if (int32_t rc2 = enqueue_fused(c, c->ws, c->h_fq, c->h_fres, nq, s)) return rc2;
+      MAPA_HIPCHK(end_call(c, s));
+      ++c->batches;
+      MAPA_HIPCHK(hipStreamSynchronize(s));
+      std::memcpy(res, c->h_fres, nq * sizeof(mapa_result));
+      return MAPA_OK;
+    }
+  }
   MAPA_HIPCHK(begin_call(c, s));
   const mapa_query *dq = q;
   mapa_result *dr = res;
@@ -733,8 +815,8 @@ int32_t mapa_set_tuning(mapa_ctx *c, const mapa_tuning *in) {
   if (!in) return MAPA_OK;
   if (in->min_leaves_per_item < 1 || in->min_leaves_per_item > (1 << 20))
     return fail(MAPA_ERR_INVALID_ARG, "min_leaves_per_item outside 1..2^20");
-  if (in->items_per_lane < 1 || in->items_per_lane > 4096)
-    return fail(MAPA_ERR_INVALID_ARG, "items_per_lane outside 1..4096");
+  if (in->mean_item_leaves < 1 || in->mean_item_leaves > (1 << 30))
+    return fail(MAPA_ERR_INVALID_ARG, "mean_item_leaves outside 1..2^30");
   if (in->blocks_per_cu < 0 || in->blocks_per_cu > 64)
     return fail(MAPA_ERR_INVALID_ARG, "blocks_per_cu outside 0..64");
   if (in->threads_per_block < 64 || in->threads_per_block > 256 || in->threads_per_block % 64)

@@ -110,66 +110,81 @@ __device__ __forceinline__ int set_weight(const uint32_t *trow, int wpr, uint32_
 
 // ----------------------------------------------------------------- prepare
 
+// Plan of one query against the busy mask now in memory: validation, free
+// set R, the key's constant term b*W(R), the pattern's back-neighbour table.
+__device__ __forceinline__ Plan make_plan(const mapa_query &q, int32_t nservers,
+                                          const int32_t *server_topo, const int32_t *topo_n,
+                                          const uint32_t *busy, const uint32_t *rows, int wpr) {
+  Plan p = {};
+  p.server = q.server;
+  p.kind = q.kind;
+  p.k = q.k;
+  p.mode = q.mode;
+  p.a = q.a;
+  p.b = q.b;
+  p.commit = q.commit;
+  const bool ok = q.server >= 0 && q.server < nservers && q.kind <= 2 && q.k >= 1 &&
+                  q.k <= kMaxK && q.mode <= 1 && q.commit <= 1 && q.a >= 0 &&
+                  q.a <= MAPA_MAX_AB && q.b >= 0 && q.b <= MAPA_MAX_AB && q.reserved == 0;
+  if (!ok) {
+    p.status = kPlanInvalid;
+    return p;
+  }
+  const int t = server_topo[q.server];
+  const int n = topo_n[t];
+  const uint32_t R = ~busy[q.server] & ((1u << n) - 1u);
+  const int F = __popc(R);
+  p.topo = (uint16_t)t;
+  p.n = (uint8_t)n;
+  p.R = R;
+  p.F = (uint8_t)F;
+  p.kp0 = (int32_t)q.b * set_weight(rows + (size_t)t * 16 * wpr, wpr, R);
+  p.nbtab = c_tab.nbtab[q.kind][q.k];
+  p.status = q.k > F ? kPlanNofit : kPlanOk;
+  return p;
+}
+
 __global__ __launch_bounds__(256) void k_prepare(BatchArgs a) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long leaves = 0;
   unsigned long long items[kNumSplits];
 #pragma unroll
   for (int j = 0; j < kNumSplits; ++j) items[j] = 0;
 
   if (i < a.nq) {
     const mapa_query q = a.q[i];
-    Plan p = {};
-    p.server = q.server;
-    p.kind = q.kind;
-    p.k = q.k;
-    p.mode = q.mode;
-    p.a = q.a;
-    p.b = q.b;
-    p.commit = q.commit;
-    const bool ok = q.server >= 0 && q.server < a.nservers && q.kind <= 2 && q.k >= 1 &&
-                    q.k <= kMaxK && q.mode <= 1 && q.commit <= 1 && q.a >= 0 &&
-                    q.a <= MAPA_MAX_AB && q.b >= 0 && q.b <= MAPA_MAX_AB && q.reserved == 0;
-    if (!ok) {
-      p.status = kPlanInvalid;
-    } else {
-      const int t = a.server_topo[q.server];
-      const int n = a.topo_n[t];
-      const uint32_t R = ~a.busy[q.server] & ((1u << n) - 1u);
-      const int F = __popc(R);
-      p.topo = (uint16_t)t;
-      p.n = (uint8_t)n;
-      p.R = R;
-      p.F = (uint8_t)F;
-      p.kp0 = (int32_t)q.b * set_weight(a.rows + (size_t)t * 16 * a.wpr, a.wpr, R);
-      p.nbtab = c_tab.nbtab[q.kind][q.k];
-      if (q.k > F) {
-        p.status = kPlanNofit;
-      } else {
-        p.status = kPlanOk;
-        const uint8_t *sd = a.split_d + ((size_t)F * (kMaxK + 1) + q.k) * kNumSplits;
+    const Plan p = make_plan(q, a.nservers, a.server_topo, a.topo_n, a.busy, a.rows, a.wpr);
+    if (p.status == kPlanOk) {
+      leaves = c_tab.perm[p.F][p.k];
+      const uint8_t *sd = a.split_d + ((size_t)p.F * (kMaxK + 1) + p.k) * kNumSplits;
 #pragma unroll
-        for (int j = 0; j < kNumSplits; ++j) items[j] = c_tab.perm[F][sd[j]];
-      }
-      if (q.commit) atomicMin(&a.commit_slot[q.server], (unsigned long long)i);
+      for (int j = 0; j < kNumSplits; ++j) items[j] = c_tab.perm[p.F][sd[j]];
     }
+    if (p.status != kPlanInvalid && p.commit)
+      atomicMin(&a.commit_slot[p.server], (unsigned long long)i);
     a.plan[i] = p;
     a.acc_count[i] = 0;
     a.acc_best[i] = 0;
   }
   // wave sums -> block sums in LDS -> one global atomic per block and counter
-  __shared__ unsigned long long s_tot[kNumSplits];
-  if (threadIdx.x < kNumSplits) s_tot[threadIdx.x] = 0;
+  __shared__ unsigned long long s_tot[kNumSplits + 1];
+  if (threadIdx.x <= kNumSplits) s_tot[threadIdx.x] = 0;
   __syncthreads();
+  leaves = wave_sum_u64(leaves);
 #pragma unroll
   for (int j = 0; j < kNumSplits; ++j) items[j] = wave_sum_u64(items[j]);
   if ((threadIdx.x & 63) == 0) {
+    if (leaves) atomicAdd(&s_tot[kNumSplits], leaves);
 #pragma unroll
     for (int j = 0; j < kNumSplits; ++j)
       if (items[j]) atomicAdd(&s_tot[j], items[j]);
   }
   __syncthreads();
-  if (threadIdx.x < kNumSplits && s_tot[threadIdx.x])
-    atomicAdd(&a.ctr->total_items[threadIdx.x][0], s_tot[threadIdx.x]);
+  if (threadIdx.x < kNumSplits) {
+    if (s_tot[threadIdx.x]) atomicAdd(&a.ctr->total_items[threadIdx.x][0], s_tot[threadIdx.x]);
+  } else if (threadIdx.x == kNumSplits) {
+    if (s_tot[kNumSplits]) atomicAdd(&a.ctr->total_leaves[0], s_tot[kNumSplits]);
+  }
 }
 
 // --------------------------------------------------------------- bucketize
@@ -222,9 +237,10 @@ __device__ void layout_buckets(const BatchArgs &a) {
     for (uint32_t x = s_cnt[r]; x < s_pad[r]; ++x) a.items[s_start[r] + x] = make_uint2(kInvalidItem, 0u);
     a.ctr->bucket_items[b][0] = 0;
   }
+  if (t < kQueues) a.ctr->queue_ctr[t][0] = 0;
   if (t == 0) {
+    a.ctr->total_leaves[0] = 0;
     for (int j = 0; j < kNumSplits; ++j) a.ctr->total_items[j][0] = 0;
-    a.ctr->chunk_ctr[0] = 0;
     a.ctr->blocks_done[0] = 0;
   }
 }
@@ -240,23 +256,25 @@ __global__ __launch_bounds__(1024) void k_bucketize(BatchArgs a) {
   for (int b = threadIdx.x; b < kNumBuckets; b += blockDim.x) s_cnt[b] = 0;
   if (threadIdx.x == 0) {
     // The split is a pure function of batch totals, so every block picks the
-    // same one.  Item counts fall as j grows.  Take the fewest, largest items
-    // that still give every resident lane target_items / lanes of them;
-    // if no split does, the most items that fit the work-list.  Whole
+    // same one.  Items get finer (more, smaller) as j falls.  Finer items
+    // balance the lanes better but each costs a fixed setup, so take the
+    // finest split that fits the work-list, gives every resident lane an
+    // item and keeps the mean item at mean_leaves embeddings or more.
+    // Failing that: the coarsest split that still gives every lane an item;
+    // for a batch too small for that, the finest split that fits.  Whole
     // queries (one item each) always fit.
-    int j = kSplitWhole;
-    int most = kSplitWhole;
+    const unsigned long long leaves = a.ctr->total_leaves[0];
+    int best = -1, busy = -1, finest = kSplitWhole;
     for (int c = kSplitWhole; c >= 0; --c) {
       const unsigned long long n = a.ctr->total_items[c][0];
       if (n + kPadReserve > a.cap_items) break;
-      most = c;
-      if (n >= a.target_items) {
-        j = c;
-        break;
+      finest = c;
+      if (n >= a.lanes) {
+        if (busy < 0) busy = c;
+        if (leaves >= n * (unsigned long long)a.mean_leaves) best = c;
       }
-      j = -1;
     }
-    if (j < 0) j = most;
+    const int j = best >= 0 ? best : busy >= 0 ? busy : finest;
     s_split = j;
     if (blockIdx.x == 0) {
       a.ctr->chosen_split = (uint32_t)j;
@@ -315,17 +333,45 @@ __global__ __launch_bounds__(1024) void k_bucketize(BatchArgs a) {
 // d-tuple of free vertices in lexicographic order: digit t of x in the mixed
 // radix (F, F-1, ..., F-d+1) picks the digit-th smallest still-unused vertex.
 // Returns the tuple with the vertex of position t at bits 4t..4t+3.
+// Position of the r-th (from 0) set bit of a 16-bit mask that has more than
+// r set bits: a branch-free binary search on popcounts.
+__device__ __forceinline__ int select_bit(uint32_t m, uint32_t r) {
+  int pos = 0;
+  uint32_t c = __popc(m & 0xFFu);
+  bool up = r >= c;
+  r -= up ? c : 0u;
+  pos += up ? 8 : 0;
+  c = __popc((m >> pos) & 0xFu);
+  up = r >= c;
+  r -= up ? c : 0u;
+  pos += up ? 4 : 0;
+  c = __popc((m >> pos) & 0x3u);
+  up = r >= c;
+  r -= up ? c : 0u;
+  pos += up ? 2 : 0;
+  c = (m >> pos) & 1u;
+  pos += r >= c ? 1 : 0;
+  return pos;
+}
+
+// Prefix x of depth d: x is a mixed-radix number whose digit t (radix F - t,
+// most significant first) picks the position-t vertex among the free
+// vertices not yet chosen, in increasing order, so consecutive x are
+// consecutive prefixes in lexicographic order.  Digits come off the least
+// significant end by multiply-high division (x < 2^28); the vertices then
+// follow in order.  Returns the prefix's mapping code (vertex of position t
+// at bits 4t..4t+3).
 __device__ __forceinline__ uint32_t unrank_prefix(uint32_t x, int d, int F, uint32_t R) {
-  uint32_t div = 1;
-  for (int t = 1; t < d; ++t) div *= (uint32_t)(F - t);
-  uint32_t rem = x, avail = R, code = 0;
+  uint32_t digits = 0;
+  for (int t = d - 1; t >= 0; --t) {
+    const uint32_t m = (uint32_t)(F - t);
+    const uint32_t q = m > 1 ? __umulhi(x, c_tab.inv[m]) : x;
+    digits |= (x - q * m) << (4 * t);
+    x = q;
+  }
+  uint32_t avail = R, code = 0;
   for (int t = 0; t < d; ++t) {
-    uint32_t r = rem / div;
-    rem -= r * div;
-    if (t + 1 < d) div /= (uint32_t)(F - 1 - t);
-    uint32_t m = avail;
-    for (; r; --r) m &= m - 1;
-    const int v = __builtin_ctz(m);
+    const int v = select_bit(avail, (digits >> (4 * t)) & 15u);
     avail &= ~(1u << v);
     code |= (uint32_t)v << (4 * t);
   }
@@ -499,10 +545,16 @@ __device__ __forceinline__ void expand(LaneState &s, int kind, int L, uint32_t r
   }
 }
 
+// One prefix item: prefix x (of depth p.d) of query plan *pp, expanded over
+// the remaining positions.  pp == nullptr: the lane holds no item.  Returns
+// the item's match count and its best as one u64 (key high, inverted
+// lexicographic mapping code low, so max() takes the largest key and then
+// the smallest mapping; 0: no match).  trow: the topology's rows.
 template <int WPR>
-__device__ __forceinline__ void run_item(const BatchArgs &a, const uint32_t *rows, uint2 it) {
-  const int lane = threadIdx.x & 63;
-  const bool valid = it.x != kInvalidItem;
+__device__ __forceinline__ void item_search(const Plan *pp, const uint32_t *trow, uint32_t x,
+                                            unsigned long long &cnt_out,
+                                            unsigned long long &best_out) {
+  const bool valid = pp != nullptr;
   LaneState s;
   s.count = 0;
   s.bpk = 0;
@@ -512,8 +564,8 @@ __device__ __forceinline__ void run_item(const BatchArgs &a, const uint32_t *row
   uint32_t rest = 0, code = 0, prev = 0;
   int kp = 0, L = 0, d = 0, kind = 0, fp = 0;
   if (valid) {
-    const Plan &p = a.plan[it.x];
-    s.trow = rows + (uint32_t)p.topo * (16 * WPR);
+    const Plan &p = *pp;
+    s.trow = trow;
     s.R = p.R;
     s.a = p.a;
     s.b = p.b;
@@ -526,7 +578,7 @@ __device__ __forceinline__ void run_item(const BatchArgs &a, const uint32_t *row
     rest = p.R;
     kp = p.kp0;
     bool ok = true;
-    const uint32_t prefix = unrank_prefix(it.y, d, p.F, p.R);
+    const uint32_t prefix = unrank_prefix(x, d, p.F, p.R);
     for (int pos = 0; pos < d; ++pos) {
       const int v = (prefix >> (4 * pos)) & 15;
       uint32_t nbm, cand;
@@ -562,15 +614,24 @@ __device__ __forceinline__ void run_item(const BatchArgs &a, const uint32_t *row
     bkey = (int)(s.bpk >> 4) - 1;
     bcode = s.bcode | ((15u - (s.bpk & 15u)) << (4 * (s.k - 1)));
   }
-  // best as one u64: key high, inverted lexicographic mapping code low, so
-  // max() takes the largest key and then the smallest mapping.
   unsigned long long best = 0;
   if (bkey >= 0) {
     uint32_t lex = 0;
     for (int i = 0; i < s.k; ++i) lex = (lex << 4) | ((bcode >> (4 * i)) & 15u);
     best = ((unsigned long long)(uint32_t)bkey << 32) | (0xFFFFFFFFu - lex);
   }
-  unsigned long long cnt = s.count;
+  cnt_out = s.count;
+  best_out = best;
+}
+
+template <int WPR>
+__device__ __forceinline__ void run_item(const BatchArgs &a, const uint32_t *rows, uint2 it) {
+  const int lane = threadIdx.x & 63;
+  const bool valid = it.x != kInvalidItem;
+  const Plan *pp = valid ? &a.plan[it.x] : nullptr;
+  const uint32_t *trow = valid ? rows + (uint32_t)pp->topo * (16 * WPR) : rows;
+  unsigned long long cnt, best;
+  item_search<WPR>(pp, trow, it.y, cnt, best);
   const int qi = valid ? (int)it.x : -1;
   const int q0 = __builtin_amdgcn_readfirstlane(qi);
   const bool same = __ballot(valid && qi != q0) == 0ull;
@@ -591,11 +652,30 @@ template <int WPR>
 __device__ __forceinline__ void chunk_loop(const BatchArgs &a, const uint32_t *rows) {
   const int lane = threadIdx.x & 63;
   const uint32_t nchunks = *(volatile const uint32_t *)&a.ctr->total_chunks;
+  // Home queue: consecutive blocks land on different XCDs, so the waves of
+  // one queue mostly share an XCD.  A wave whose queue runs dry looks at
+  // every queue's counter at once (one lane each) and moves to the next one,
+  // counting from its home, that still holds chunks.
+  const uint32_t home = blockIdx.x % kQueues;
+  uint32_t qu = home;
   for (;;) {
     uint32_t c = 0;
-    if (lane == 0) c = atomicAdd(&a.ctr->chunk_ctr[0], 1u);
+    if (lane == 0) c = qu + atomicAdd(&a.ctr->queue_ctr[qu][0], 1u) * (uint32_t)kQueues;
     c = __shfl(c, 0, 64);
-    if (c >= nchunks) break;
+    if (c >= nchunks) {
+      bool left = false;
+      if (lane < kQueues) {
+        const uint32_t pos = __hip_atomic_load(&a.ctr->queue_ctr[lane][0], __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+        left = (unsigned long long)lane + (unsigned long long)pos * kQueues < nchunks;
+      }
+      const unsigned long long m = __ballot(left);
+      if (!m) break;
+      // first queue with chunks left at or after home, cyclically
+      const unsigned long long hi = m & (~0ull << home);
+      qu = (uint32_t)__builtin_ctzll(hi ? hi : m);
+      continue;
+    }
     const uint2 it = a.items[(size_t)c * kChunk + lane];
     run_item<WPR>(a, rows, it);
   }
@@ -616,24 +696,36 @@ __global__ __launch_bounds__(256) void k_enumerate(BatchArgs a) {
 
 // ---------------------------------------------------------------- finalize
 
-__global__ __launch_bounds__(256) void k_finalize(BatchArgs a) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= a.nq) return;
-  const Plan p = a.plan[i];
-  int64_t count = 0;
-  int32_t status = MAPA_RES_NOFIT, key = INT32_MIN, agg = 0, pres = 0;
-  uint32_t S = 0, map_lo = 0xFFFFFFFFu, map_hi = 0xFFFFFFFFu;
-  int64_t handle = -1;
+// A query's result from its plan, match count and best u64: the mapping,
+// AggBW (Eq. 1) and PreservedBW (Eq. 3) recomputed from the mapping, checked
+// against the key the search kept.  No commit yet (handle -1).
+struct Outcome {
+  int64_t count;
+  int32_t status, key, agg, pres;
+  uint32_t S, map_lo, map_hi;
+  int64_t handle;
+};
+
+__device__ __forceinline__ Outcome decode_best(const Plan &p, unsigned long long cnt,
+                                               unsigned long long best, const uint32_t *trow,
+                                               int wpr, uint32_t *self_check_failures) {
+  Outcome o;
+  o.count = 0;
+  o.status = MAPA_RES_NOFIT;
+  o.key = INT32_MIN;
+  o.agg = o.pres = 0;
+  o.S = 0;
+  o.map_lo = o.map_hi = 0xFFFFFFFFu;
+  o.handle = -1;
+  int32_t &status = o.status, &agg = o.agg, &pres = o.pres;
+  uint32_t &S = o.S, &map_lo = o.map_lo, &map_hi = o.map_hi;
   if (p.status == kPlanInvalid) {
     status = MAPA_RES_INVALID;
   } else if (p.status == kPlanOk) {
-    const unsigned long long cnt = a.acc_count[i];
-    const unsigned long long best = a.acc_best[i];
-    count = (int64_t)cnt;
+    o.count = (int64_t)cnt;
     if (cnt > 0) {
       const int k = p.k;
       const uint32_t lex = 0xFFFFFFFFu - (uint32_t)best;
-      const uint32_t *trow = a.rows + (size_t)p.topo * 16 * a.wpr;
       uint32_t phi_code = 0;  // vertex of position t at bits 4t..4t+3
       for (int t = 0; t < k; ++t) {
         const uint32_t v = (lex >> (4 * (k - 1 - t))) & 15u;
@@ -648,30 +740,129 @@ __global__ __launch_bounds__(256) void k_finalize(BatchArgs a) {
         uint32_t nbm = 0;
         for (uint32_t m = (uint32_t)(p.nbtab >> (8 * t)) & 0xFFu; m; m &= m - 1)
           nbm |= 1u << ((phi_code >> (4 * __builtin_ctz(m))) & 15u);
-        agg += wsum_rt(trow + ((phi_code >> (4 * t)) & 15u) * a.wpr, a.wpr, nbm | (nbm << 16));
+        agg += wsum_rt(trow + ((phi_code >> (4 * t)) & 15u) * wpr, wpr, nbm | (nbm << 16));
       }
-      pres = set_weight(trow, a.wpr, p.R & ~S);
-      key = (int32_t)(best >> 32);
+      pres = set_weight(trow, wpr, p.R & ~S);
+      o.key = (int32_t)(best >> 32);
       status = MAPA_RES_OK;
-      if ((int32_t)p.a * agg + (int32_t)p.b * pres != key) atomicAdd(&a.ctr->self_check_failures, 1u);
+      if ((int32_t)p.a * agg + (int32_t)p.b * pres != o.key) atomicAdd(self_check_failures, 1u);
     }
   }
+  return o;
+}
+
+// 48-byte result as three 16-byte stores
+__device__ __forceinline__ void store_result(mapa_result *res, const Outcome &o) {
+  int4 *dst = reinterpret_cast<int4 *>(res);
+  dst[0] = make_int4((int32_t)(uint32_t)o.count, (int32_t)(o.count >> 32), o.status, o.key);
+  dst[1] = make_int4(o.agg, o.pres, (int32_t)o.S, (int32_t)o.map_lo);
+  dst[2] = make_int4((int32_t)o.map_hi, 0, (int32_t)(uint32_t)o.handle, (int32_t)(o.handle >> 32));
+}
+
+__global__ __launch_bounds__(256) void k_finalize(BatchArgs a) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.nq) return;
+  const Plan p = a.plan[i];
+  Outcome o = decode_best(p, a.acc_count[i], a.acc_best[i], a.rows + (size_t)p.topo * 16 * a.wpr,
+                          a.wpr, &a.ctr->self_check_failures);
+  a.acc_count[i] = 0;  // leave the accumulators clean for the next batch
+  a.acc_best[i] = 0;
   if (p.status != kPlanInvalid && p.commit) {
     if (a.commit_slot[p.server] == (unsigned long long)i) {
-      if (status == MAPA_RES_OK) {
-        atomicOr(&a.busy[p.server], S);
-        handle = ((int64_t)p.server << 32) | (int64_t)S;
+      if (o.status == MAPA_RES_OK) {
+        atomicOr(&a.busy[p.server], o.S);
+        o.handle = ((int64_t)p.server << 32) | (int64_t)o.S;
       }
       a.commit_slot[p.server] = kSlotFree;
-    } else if (status == MAPA_RES_OK) {
-      status = MAPA_RES_CONFLICT;
+    } else if (o.status == MAPA_RES_OK) {
+      o.status = MAPA_RES_CONFLICT;
     }
   }
-  // 48-byte result as three 16-byte stores
-  int4 *dst = reinterpret_cast<int4 *>(a.res + i);
-  dst[0] = make_int4((int32_t)(uint32_t)count, (int32_t)(count >> 32), status, key);
-  dst[1] = make_int4(agg, pres, (int32_t)S, (int32_t)map_lo);
-  dst[2] = make_int4((int32_t)map_hi, 0, (int32_t)(uint32_t)handle, (int32_t)(handle >> 32));
+  store_result(a.res + i, o);
+}
+
+// ------------------------------------------------------------ fused batch
+
+// Small batches whose queries all name different servers, in one launch:
+// bpq blocks per query each build the query's plan, take every bpq-th group
+// of prefix items (enough items for every thread of the query's blocks),
+// expand them and add their count and best to the query's accumulators; the
+// last block of a query to finish decodes the result, commits directly (no
+// other query of the batch can claim the server) and clears the
+// accumulators.  Queries and results may live in pinned host memory.
+template <int WPR>
+__global__ __launch_bounds__(256) void k_fused(FusedArgs f) {
+  __shared__ Plan s_plan;
+  __shared__ uint32_t s_rows[16 * WPR];
+  __shared__ unsigned long long s_cnt[4], s_best[4];
+  __shared__ bool s_last;
+  const int i = blockIdx.x / f.bpq;
+  const int j = blockIdx.x % f.bpq;
+  const int tid = threadIdx.x;
+  const uint32_t span = (uint32_t)f.bpq * blockDim.x;
+  if (tid == 0) {
+    const mapa_query q = f.q[i];
+    Plan p = make_plan(q, f.nservers, f.server_topo, f.topo_n, f.busy, f.rows, WPR);
+    if (p.status == kPlanOk) {
+      int d = 0;
+      while (d < p.k - 1 && c_tab.perm[p.F][d] < (unsigned long long)span) ++d;
+      p.d = (uint8_t)d;
+      p.nitems = (uint32_t)c_tab.perm[p.F][d];
+    }
+    s_plan = p;
+  }
+  __syncthreads();
+  const int status = s_plan.status;
+  const uint32_t nitems = status == kPlanOk ? s_plan.nitems : 0u;
+  if (status != kPlanInvalid && tid < 16 * WPR) s_rows[tid] = f.rows[(size_t)s_plan.topo * 16 * WPR + tid];
+  __syncthreads();
+  unsigned long long cnt = 0, best = 0;
+  for (uint32_t base = (uint32_t)j * blockDim.x; base < nitems; base += span) {
+    const uint32_t x = base + (uint32_t)tid;
+    unsigned long long c1, b1;
+    item_search<WPR>(x < nitems ? &s_plan : nullptr, s_rows, x, c1, b1);
+    cnt += c1;
+    best = b1 > best ? b1 : best;
+  }
+  cnt = wave_sum_u64(cnt);
+  best = wave_max_u64(best);
+  if ((tid & 63) == 0) {
+    s_cnt[tid >> 6] = cnt;
+    s_best[tid >> 6] = best;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
+      cnt += s_cnt[w];
+      best = s_best[w] > best ? s_best[w] : best;
+    }
+    bool last = true;
+    if (f.bpq > 1) {
+      if (cnt) atomicAdd(&f.acc_count[i], cnt);
+      if (best) atomicMax(&f.acc_best[i], best);
+      __threadfence();
+      last = atomicAdd(&f.done[i], 1u) == (uint32_t)f.bpq - 1;
+      if (last) {
+        __threadfence();
+        cnt = __hip_atomic_load(&f.acc_count[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        best = __hip_atomic_load(&f.acc_best[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        f.acc_count[i] = 0;
+        f.acc_best[i] = 0;
+        f.done[i] = 0;
+      }
+    }
+    s_last = last;
+  }
+  __syncthreads();
+  if (tid == 0 && s_last) {
+    const Plan p = s_plan;
+    Outcome o = decode_best(p, cnt, best, s_rows, WPR, f.self_check_failures);
+    if (p.status != kPlanInvalid && p.commit && o.status == MAPA_RES_OK) {
+      atomicOr(&f.busy[p.server], o.S);
+      o.handle = ((int64_t)p.server << 32) | (int64_t)o.S;
+    }
+    store_result(f.res + i, o);
+  }
 }
 
 // ------------------------------------------------------------- state kernels
@@ -815,6 +1006,17 @@ int enumerate_occupancy(int wpr, int rows_in_lds, int threads, size_t lds_bytes)
     case 2: return l ? occ_t<2, true>(threads, lds_bytes) : occ_t<2, false>(threads, 0);
     default: return l ? occ_t<4, true>(threads, lds_bytes) : occ_t<4, false>(threads, 0);
   }
+}
+
+hipError_t launch_fused(const FusedArgs &f, hipStream_t s) {
+  if (f.nq <= 0) return hipSuccess;
+  if (f.bpq < 1 || f.bpq > kFusedMaxBlocksPerQuery) return hipErrorInvalidValue;
+  switch (f.wpr) {
+    case 1: hipLaunchKernelGGL(k_fused<1>, dim3(f.nq * f.bpq), dim3(kFusedThreads), 0, s, f); break;
+    case 2: hipLaunchKernelGGL(k_fused<2>, dim3(f.nq * f.bpq), dim3(kFusedThreads), 0, s, f); break;
+    default: hipLaunchKernelGGL(k_fused<4>, dim3(f.nq * f.bpq), dim3(kFusedThreads), 0, s, f); break;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_finalize(const BatchArgs &a, hipStream_t s) {

@@ -56,11 +56,16 @@ constexpr uint8_t kPlanOk = 0, kPlanNofit = 1, kPlanInvalid = 3;
 // Counters hit by atomics from many blocks each own a 128-byte line, so their
 // atomics spread over L2 channels instead of queueing on one.
 constexpr int kLine = 32;  // u32 per 128-byte line
+// The chunk list is dealt round-robin into kQueues queues (chunk c goes to
+// queue c % kQueues), each with its own claim counter, so the claims of the
+// persistent waves spread over many addresses instead of serializing on one.
+constexpr int kQueues = 32;
 struct Counters {
   unsigned long long total_items[kNumSplits][kLine / 2];  // [j][0] used
+  unsigned long long total_leaves[kLine / 2];             // [0] used
   uint32_t bucket_items[kNumBuckets][kLine];              // [b][0] used
   uint32_t blocks_done[kLine];                            // k_bucketize blocks finished
-  uint32_t chunk_ctr[kLine];                              // next chunk to expand
+  uint32_t queue_ctr[kQueues][kLine];                     // next chunk of each queue
   uint32_t bucket_start[kNumBuckets];
   uint32_t total_chunks;
   uint32_t chosen_split;
@@ -74,6 +79,8 @@ struct Tables {          // uploaded once per device into __constant__ memory
   unsigned long long nbtab[3][kMaxK + 1];  // byte p: back-neighbour position mask of p
   uint8_t nb[3][kMaxK + 1][kMaxK];         // the same masks, one per entry
   uint16_t rank_bucket[kNumBuckets];       // bucket laid out at rank r (largest items first)
+  uint32_t inv[kMaxN + 1];                 // ceil(2^32 / m), m >= 2: x / m = umulhi(x, inv[m])
+                                           // for every x < 2^28
 };
 
 // Prefix depth of split j for a query with F free vertices and k pattern
@@ -107,12 +114,37 @@ struct BatchArgs {
   int32_t wpr;
   const uint8_t *split_d;  // [F][k][j], see kSplitTable
   // tuning
-  unsigned long long target_items;
+  unsigned long long lanes;  // resident enumeration lanes
+  uint32_t mean_leaves;      // smallest mean item size the split may take
   int32_t enum_blocks;
   int32_t enum_threads;
   int32_t rows_in_lds;
 };
 
+// Fused path for small batches with one query per server (k_fused).
+constexpr int kFusedThreads = 256;
+constexpr int kFusedMaxBlocksPerQuery = 16;
+constexpr int32_t kFusedMaxQueries = 4096;
+constexpr unsigned long long kFusedMaxQueryLeaves = 1ull << 20;  // per query
+constexpr unsigned long long kFusedMaxLeaves = 1ull << 24;       // per batch
+
+struct FusedArgs {
+  const mapa_query *q;  // device or pinned host memory
+  mapa_result *res;     // device or pinned host memory
+  int32_t nq;
+  const int32_t *server_topo;
+  uint32_t *busy;
+  int32_t nservers;
+  const int32_t *topo_n;
+  const uint32_t *rows;
+  int32_t wpr;
+  uint32_t *self_check_failures;
+  unsigned long long *acc_count, *acc_best;  // per query, zero on entry and exit
+  uint32_t *done;                            // per query, zero on entry and exit
+  int32_t bpq;                               // blocks per query
+};
+
+hipError_t launch_fused(const FusedArgs &f, hipStream_t s);
 hipError_t launch_batch_front(const BatchArgs &a, hipStream_t s);   // prepare .. expand
 hipError_t launch_enumerate(const BatchArgs &a, hipStream_t s);
 hipError_t launch_finalize(const BatchArgs &a, hipStream_t s);

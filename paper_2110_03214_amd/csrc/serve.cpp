@@ -47,8 +47,7 @@ struct Slot {
   hipEvent_t done = nullptr;
   mapa_query *h_q = nullptr;     // pinned
   mapa_result *h_res = nullptr;  // pinned
-  int64_t *h_rel = nullptr;      // pinned
-  int64_t *d_rel = nullptr;
+  int64_t *h_rel = nullptr;      // pinned, read by the release kernel in place
   size_t cap_rel = 0;
   bool active = false;
   int32_t batch_id = -1;
@@ -57,17 +56,11 @@ struct Slot {
   std::vector<uint32_t> busy_before;
 };
 
-unsigned long long perm_u64(int F, int k) {
-  unsigned long long p = 1;
-  for (int i = 0; i < k; ++i) p *= (unsigned long long)(F - i);
-  return p;
-}
-
 // prefix items a request would need with items of at most `leaves` embeddings
 unsigned long long estimate_items(int F, int k, int leaves) {
   int d = 0;
-  while (d < k - 1 && perm_u64(F - d, k - d) > (unsigned long long)leaves) ++d;
-  return perm_u64(F, d);
+  while (d < k - 1 && perm_leaves(F - d, k - d) > (unsigned long long)leaves) ++d;
+  return perm_leaves(F, d);
 }
 
 }  // namespace
@@ -78,7 +71,7 @@ struct ServeState {
   std::thread th;
   std::mutex mu;
   std::condition_variable cv;
-  std::vector<Req> incoming;           // guarded by mu
+  std::vector<std::vector<Req>> incoming;  // one vector per submission, guarded by mu
   std::deque<mapa_completion> done_q;  // guarded by mu
   bool stopping = false;               // guarded by mu
   double last_arrival = -1e300;        // caller side, guarded by mu
@@ -95,7 +88,20 @@ struct ServeState {
   std::vector<uint8_t> in_flight, in_ready;
   std::vector<std::deque<Req>> fifo;
   std::deque<int32_t> ready;
-  std::deque<Req> pending;  // submitted, not yet due
+  // submitted, not yet due: whole submissions in arrival order, consumed
+  // from the front (pend_pos indexes the front one), so taking over a large
+  // submission costs nothing per request
+  std::deque<std::vector<Req>> pending;
+  size_t pend_pos = 0;
+
+  bool pending_empty() {
+    while (!pending.empty() && pend_pos >= pending.front().size()) {
+      pending.pop_front();
+      pend_pos = 0;
+    }
+    return pending.empty();
+  }
+  const Req &pending_front() const { return pending.front()[pend_pos]; }
   std::priority_queue<Held, std::vector<Held>, HeldLater> held;
   std::vector<Held> deferred;  // due releases whose server has a request in flight
   std::vector<int64_t> held_forever;
@@ -103,6 +109,7 @@ struct ServeState {
   mapa_serve_stats st{};
   int64_t completed = 0;
   int64_t batched_queries = 0;
+  int64_t fused_batches = 0;
   double batch_us_sum = 0;
   double last_done_us = 0;
   hipEvent_t rel_event = nullptr;
@@ -293,18 +300,14 @@ int32_t dispatch(ServeState *S, Slot &sl, bool final_release, bool *did) {
     if (rel.size() > sl.cap_rel) {
       SERVE_CHK(hipStreamSynchronize(sl.stream));
       if (sl.h_rel) (void)hipHostFree(sl.h_rel);
-      dev_free(sl.d_rel);
       sl.h_rel = nullptr;
       sl.cap_rel = 0;
       size_t cap = std::max<size_t>(4096, rel.size() * 2);
       SERVE_CHK(hipHostMalloc((void **)&sl.h_rel, cap * sizeof(int64_t), hipHostMallocDefault));
-      SERVE_CHK(dev_alloc(&sl.d_rel, cap));
       sl.cap_rel = cap;
     }
     std::memcpy(sl.h_rel, rel.data(), rel.size() * sizeof(int64_t));
-    SERVE_CHK(hipMemcpyAsync(sl.d_rel, sl.h_rel, rel.size() * sizeof(int64_t), hipMemcpyHostToDevice,
-                             sl.stream));
-    SERVE_CHK(launch_release_apply(sl.d_rel, 8, (int32_t)rel.size(), (int32_t)c->server_topo.size(),
+    SERVE_CHK(launch_release_apply(sl.h_rel, 8, (int32_t)rel.size(), (int32_t)c->server_topo.size(),
                                    c->d_busy, sl.stream));
     SERVE_CHK(hipEventRecord(S->rel_event, sl.stream));
     S->rel_event_valid = true;
@@ -324,16 +327,34 @@ int32_t dispatch(ServeState *S, Slot &sl, bool final_release, bool *did) {
       q.b = r.b;
       q.reserved = 0;
     }
-    SERVE_CHK(hipMemcpyAsync(sl.ws.d_q, sl.h_q, nq * sizeof(mapa_query), hipMemcpyHostToDevice,
-                             sl.stream));
-    const int32_t rc = enqueue_batch(c, sl.ws, sl.ws.d_q, sl.ws.d_res, nq, sl.stream);
+    // one request per server: small batches take the fused launch, which
+    // reads the requests from and writes the results to the pinned buffers
+    unsigned long long total = 0;
+    bool small = nq <= kFusedMaxQueries;
+    for (int32_t i = 0; i < nq && small; ++i) {
+      const int32_t s = sl.reqs[i].r.server;
+      const unsigned long long e =
+          perm_leaves(S->nvert[s] - __builtin_popcount(sl.busy_before[i]), sl.reqs[i].r.k);
+      small = e <= kFusedMaxQueryLeaves;
+      total += e;
+    }
+    int32_t rc;
+    if (small && total <= kFusedMaxLeaves) {
+      rc = enqueue_fused(c, sl.ws, sl.h_q, sl.h_res, nq, sl.stream);
+      ++S->fused_batches;
+    } else {
+      SERVE_CHK(hipMemcpyAsync(sl.ws.d_q, sl.h_q, nq * sizeof(mapa_query), hipMemcpyHostToDevice,
+                               sl.stream));
+      rc = enqueue_batch(c, sl.ws, sl.ws.d_q, sl.ws.d_res, nq, sl.stream);
+      if (!rc)
+        SERVE_CHK(hipMemcpyAsync(sl.h_res, sl.ws.d_res, nq * sizeof(mapa_result),
+                                 hipMemcpyDeviceToHost, sl.stream));
+    }
     if (rc) {
       S->error = rc;
       S->error_msg = "batch enqueue failed";
       return rc;
     }
-    SERVE_CHK(hipMemcpyAsync(sl.h_res, sl.ws.d_res, nq * sizeof(mapa_result), hipMemcpyDeviceToHost,
-                             sl.stream));
     sl.batch_id = S->next_batch++;
     sl.t_dispatch = now;
     ++S->st.batches;
@@ -356,16 +377,16 @@ void loop_main(ServeState *S) {
     bool stopping;
     {
       std::lock_guard<std::mutex> lk(S->mu);
-      for (auto &r : S->incoming) S->pending.push_back(r);
+      for (auto &v : S->incoming) S->pending.push_back(std::move(v));
       S->incoming.clear();
       stopping = S->stopping;
     }
     if (harvest(S, &did)) break;
     // due arrivals join their server's queue
     const double now = S->now_us();
-    while (!S->pending.empty() && S->pending.front().due_us <= now) {
-      const Req r = S->pending.front();
-      S->pending.pop_front();
+    while (!S->pending_empty() && S->pending_front().due_us <= now) {
+      const Req r = S->pending_front();
+      ++S->pend_pos;
       S->fifo[r.r.server].push_back(r);
       make_ready(S, r.r.server);
       did = true;
@@ -398,7 +419,7 @@ void loop_main(ServeState *S) {
     }
     // idle: sleep until the next arrival, release or submission
     double next = 1e300;
-    if (!S->pending.empty()) next = S->pending.front().due_us;
+    if (!S->pending_empty()) next = S->pending_front().due_us;
     if (!S->held.empty()) next = std::min(next, S->held.top().t_us);
     if (!S->deferred.empty()) next = std::min(next, S->now_us());
     const double wait_us = std::max(0.0, std::min(next - S->now_us(), 2000.0));
@@ -415,7 +436,6 @@ void free_state(ServeState *S) {
     if (sl.h_q) (void)hipHostFree(sl.h_q);
     if (sl.h_res) (void)hipHostFree(sl.h_res);
     if (sl.h_rel) (void)hipHostFree(sl.h_rel);
-    dev_free(sl.d_rel);
     if (sl.done) (void)hipEventDestroy(sl.done);
     if (sl.stream) (void)hipStreamDestroy(sl.stream);
   }
@@ -512,9 +532,8 @@ int32_t mapa_serve_submit(mapa_ctx *c, const mapa_request *reqs, int32_t n) {
   if (n < 0) return fail(MAPA_ERR_INVALID_ARG, "n < 0");
   if (n == 0) return MAPA_OK;
   if (!reqs) return fail(MAPA_ERR_INVALID_ARG, "reqs is NULL");
-  std::lock_guard<std::mutex> lk(S->mu);
-  if (S->stopping) return fail(MAPA_ERR_STATE, "the serving loop is stopping");
-  double last = S->last_arrival;
+  // validate and copy outside the lock; due times are relative until then
+  std::vector<Req> batch((size_t)n);
   for (int32_t i = 0; i < n; ++i) {
     const mapa_request &r = reqs[i];
     if (r.server < 0 || (size_t)r.server >= c->server_topo.size())
@@ -523,22 +542,22 @@ int32_t mapa_serve_submit(mapa_ctx *c, const mapa_request *reqs, int32_t n) {
     if (r.k < 1 || r.kind > 2 || r.mode > 1 || r.a < 0 || r.a > MAPA_MAX_AB || r.b < 0 ||
         r.b > MAPA_MAX_AB || r.reserved0 != 0 || r.reserved1 != 0)
       return fail(MAPA_ERR_INVALID_ARG, "request %d: malformed field", i);
-    if (!(r.t_arrival >= last)) return fail(MAPA_ERR_INVALID_ARG, "request %d: arrival goes back in time", i);
-    last = r.t_arrival;
+    if (i > 0 && !(r.t_arrival >= reqs[i - 1].t_arrival))
+      return fail(MAPA_ERR_INVALID_ARG, "request %d: arrival goes back in time", i);
+    batch[i] = {r, S->opts.time_unit_us > 0 ? r.t_arrival * S->opts.time_unit_us : 0.0};
   }
-  S->last_arrival = last;
+  std::lock_guard<std::mutex> lk(S->mu);
+  if (S->stopping) return fail(MAPA_ERR_STATE, "the serving loop is stopping");
+  if (!(reqs[0].t_arrival >= S->last_arrival))
+    return fail(MAPA_ERR_INVALID_ARG, "request 0: arrival goes back in time");
+  S->last_arrival = reqs[n - 1].t_arrival;
   // the loop sees nothing of this call before the lock is released, so trace
   // time 0 is taken at the end of the first submission
   const double now = S->now_us();
   if (S->origin_us < 0) S->origin_us = now;
-  const size_t first = S->incoming.size();
-  for (int32_t i = 0; i < n; ++i) {
-    const double due =
-        S->opts.time_unit_us > 0 ? reqs[i].t_arrival * S->opts.time_unit_us : 0.0;
-    S->incoming.push_back({reqs[i], due});
-  }
-  const double base = S->opts.time_unit_us > 0 ? S->origin_us : S->now_us();
-  for (size_t i = first; i < S->incoming.size(); ++i) S->incoming[i].due_us += base;
+  const double base = S->opts.time_unit_us > 0 ? S->origin_us : now;
+  for (auto &r : batch) r.due_us += base;
+  S->incoming.push_back(std::move(batch));
   S->submitted += n;
   S->cv.notify_all();
   return MAPA_OK;
@@ -582,6 +601,7 @@ int32_t mapa_serve_stop(mapa_ctx *c, mapa_serve_stats *out) {
   st.max_us = S->lat.empty() ? 0 : *std::max_element(S->lat.begin(), S->lat.end());
   st.mean_batch = st.batches ? (double)S->batched_queries / (double)st.batches : 0;
   st.mean_batch_us = st.batches ? S->batch_us_sum / (double)st.batches : 0;
+  st.fused_batches = S->fused_batches;
   const int32_t err = S->error;
   const std::string msg = S->error_msg;
   c->serve = nullptr;

@@ -137,7 +137,7 @@ def test_tuning_validation(vctx):
     assert t.min_leaves_per_item >= 1 and t.threads_per_block == 256
     assert code_of(lambda: vctx.set_tuning(threads_per_block=100)) == B.ERR_INVALID_ARG
     assert code_of(lambda: vctx.set_tuning(min_leaves_per_item=0)) == B.ERR_INVALID_ARG
-    vctx.set_tuning(min_leaves_per_item=256, items_per_lane=2)
+    vctx.set_tuning(min_leaves_per_item=256, mean_item_leaves=64)
     assert vctx.tuning().min_leaves_per_item == 256
 
 

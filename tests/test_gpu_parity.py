@@ -61,17 +61,31 @@ def run_gpu(ctx, wl):
     return ctx.query_batch(q)
 
 
-def test_tiny_config_all_keys_and_modes(ctx):
+@pytest.mark.parametrize("pipeline", [False, True], ids=["fused", "pipeline"])
+def test_tiny_config_all_keys_and_modes(ctx, pipeline):
+    """1,000 states of one cube-mesh, one query per server: the fused
+    small-batch launch by default, the multi-kernel pipeline when forced."""
     base = synth.config1()
     q, ids = B.load_workload(ctx, base)
     for a, b, mode in ((1, 1, 0), (1, 0, 0), (0, 1, 0), (3, 2, 0), (1, 1, 1), (1, 0, 1)):
         wl = base.with_keys(a, b, mode)
         qq = q.copy()
         qq["a"], qq["b"], qq["mode"] = a, b, mode
-        got = ctx.query_batch(qq)
+        got = ctx.query_batch(qq, pipeline=pipeline)
         ref = oracle.run_workload(wl, NTHREADS)
         assert_same(got, ref, wl.queries["k"], f"C1 a={a} b={b} mode={mode}")
     assert ctx.stats()["self_check_failures"] == 0
+
+
+def distinct_server_batches(servers):
+    """Index batches in which every server appears at most once: the j-th
+    query of each server goes to batch j."""
+    occ = {}
+    batch_of = np.empty(len(servers), np.int64)
+    for i, s in enumerate(servers):
+        batch_of[i] = occ.get(int(s), 0)
+        occ[int(s)] = batch_of[i] + 1
+    return [np.nonzero(batch_of == j)[0] for j in range(int(batch_of.max()) + 1)]
 
 
 def test_batched_config_full_size_device_pointers(ctx, torch):
@@ -94,9 +108,9 @@ def test_batched_config_tuning_does_not_change_results(ctx):
     wl = synth.config2(8192)
     q, _ = B.load_workload(ctx, wl)
     ref = ctx.query_batch(q)
-    for kw in (dict(min_leaves_per_item=1, items_per_lane=64),
-               dict(min_leaves_per_item=4096, items_per_lane=1),
-               dict(min_leaves_per_item=16, items_per_lane=8, blocks_per_cu=1, threads_per_block=64)):
+    for kw in (dict(min_leaves_per_item=1, mean_item_leaves=1),
+               dict(min_leaves_per_item=4096, mean_item_leaves=1 << 20),
+               dict(min_leaves_per_item=16, mean_item_leaves=8, blocks_per_cu=1, threads_per_block=64)):
         ctx.set_tuning(**kw)
         got = ctx.query_batch(q)
         assert np.array_equal(got, ref), kw
@@ -175,9 +189,17 @@ def test_random_small_graphs_every_shape(ctx, wmax):
                     s += 1
     q = synth.make_queries(cols["server"], cols["kind"], cols["k"], cols["mode"], 0, cols["a"], cols["b"])
     wl = synth.Workload("random", topos, np.array(st, np.int32), np.array(busy, np.uint32), q)
-    got = run_gpu(ctx, wl)
+    qh, _ = B.load_workload(ctx, wl)
+    got = ctx.query_batch(qh)
     ref = oracle.run_workload(wl, NTHREADS)
     assert_same(got, ref, wl.queries["k"], "random")
+    # the same queries as fused launches (one query per server per batch)
+    # and through the forced pipeline, batch by batch
+    for sel in distinct_server_batches(qh["server"]):
+        fused = ctx.query_batch(qh[sel])
+        piped = ctx.query_batch(qh[sel], pipeline=True)
+        assert np.array_equal(fused, piped)
+        assert_same(fused, ref[sel], wl.queries["k"][sel], "random fused")
     assert ctx.stats()["self_check_failures"] == 0
 
 
@@ -210,6 +232,27 @@ def test_edge_cases(ctx):
     assert_same(got, ref, wl.queries["k"], "edges")
     assert list(got["status"]) == [0, 0, 0, 0, 1, 1, 1, 1, 0, 1, 0]
     assert list(got["count"][[1, 2, 3, 10]]) == [40320, 40320, 1, 1680]
+
+
+def test_fused_commit_and_release(ctx):
+    """A committing batch with one query per server (the fused launch):
+    the same results, handles and busy masks as the oracle's batch
+    semantics, and releasing the handles restores the entry state."""
+    base = synth.config2(2048)
+    q = synth.make_queries(base.queries["server"], base.queries["kind"], base.queries["k"], 0, 1, 1, 1)
+    wl = synth.Workload("commit1", base.topologies, base.server_topo, base.busy, q)
+    qq, ids = B.load_workload(ctx, wl)
+    assert len(np.unique(qq["server"])) == len(qq)
+    got = ctx.query_batch(qq)
+    ref, handles, busy_after = oracle.run_batch_semantics(wl, NTHREADS)
+    assert_same(got, ref, wl.queries["k"], "fused commit")
+    exp_handles = np.full(len(handles), -1, np.int64)
+    live = handles >= 0
+    exp_handles[live] = (ids[handles[live] >> 32].astype(np.int64) << 32) | (handles[live] & 0xFFFFFFFF)
+    assert np.array_equal(got["alloc_handle"], exp_handles)
+    assert np.array_equal(ctx.get_busy(ids), busy_after)
+    ctx.release(got["alloc_handle"])
+    assert np.array_equal(ctx.get_busy(ids), wl.busy)
 
 
 def test_commit_conflict_release_semantics(ctx):
