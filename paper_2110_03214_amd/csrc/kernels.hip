@@ -5,9 +5,9 @@
 //   k_prepare    per query: validate, free set R, constant key term b*W(R),
 //                per-split prefix depths and item totals, commit claim.
 //   k_bucketize  choose one split for the batch; per query: prefix depth d,
-//                shape bucket, offset inside the bucket; the last block lays
-//                the buckets out (largest items first), pads each to whole
-//                64-item chunks and resets the per-batch counters.
+//                shape bucket, offset inside the bucket.
+//   k_layout     one block: lays the buckets out (largest items first), pads
+//                each to whole 64-item chunks, resets the per-batch counters.
 //   k_expand     fills every query's work-list slots with (query, item index);
 //                k_enumerate turns the index into the prefix tuple.
 //   k_enumerate  persistent: each wave takes a 64-item chunk; each lane
@@ -180,18 +180,15 @@ __global__ __launch_bounds__(256) void k_prepare(BatchArgs a) {
       if (items[j]) atomicAdd(&s_tot[j], items[j]);
   }
   __syncthreads();
-  if (threadIdx.x < kNumSplits) {
-    if (s_tot[threadIdx.x]) atomicAdd(&a.ctr->total_items[threadIdx.x][0], s_tot[threadIdx.x]);
-  } else if (threadIdx.x == kNumSplits) {
-    if (s_tot[kNumSplits]) atomicAdd(&a.ctr->total_leaves[0], s_tot[kNumSplits]);
-  }
+  if (threadIdx.x <= kNumSplits && s_tot[threadIdx.x])
+    atomicAdd(&a.ctr->totals[blockIdx.x % kTotCopies][threadIdx.x][0], s_tot[threadIdx.x]);
 }
 
 // --------------------------------------------------------------- bucketize
 
 // Lay the buckets out (largest items first), pad each to whole 64-item
 // chunks with invalid items, and reset the per-batch counters.  Run by the
-// last block of k_bucketize, once every block's bucket counts are in.
+// one block of k_layout, once every k_bucketize block's counts are in.
 __device__ void layout_buckets(const BatchArgs &a) {
   __shared__ uint32_t s_pad[kNumBuckets];
   __shared__ uint32_t s_cnt[kNumBuckets];
@@ -238,22 +235,35 @@ __device__ void layout_buckets(const BatchArgs &a) {
     a.ctr->bucket_items[b][0] = 0;
   }
   if (t < kQueues) a.ctr->queue_ctr[t][0] = 0;
-  if (t == 0) {
-    a.ctr->total_leaves[0] = 0;
-    for (int j = 0; j < kNumSplits; ++j) a.ctr->total_items[j][0] = 0;
-    a.ctr->blocks_done[0] = 0;
-  }
+  for (int e = t; e < kTotCopies * (kNumSplits + 1); e += blockDim.x)
+    a.ctr->totals[e / (kNumSplits + 1)][e % (kNumSplits + 1)][0] = 0;
 }
+
+// One block, after k_bucketize: the bucket layout (the counts it needs are
+// final only once every k_bucketize block has added its own).
+__global__ __launch_bounds__(1024) void k_layout(BatchArgs a) { layout_buckets(a); }
 
 // Few, fat blocks: each block histograms many queries in LDS and then adds
 // one total per bucket to the global counters, so every global counter sees
 // only a handful of atomics.
 __global__ __launch_bounds__(1024) void k_bucketize(BatchArgs a) {
   __shared__ int s_split;
-  __shared__ bool s_last;
   __shared__ uint32_t s_cnt[kNumBuckets];
   __shared__ uint32_t s_base[kNumBuckets];
+  __shared__ unsigned long long s_part[kTotCopies * (kNumSplits + 1)];
+  __shared__ unsigned long long s_tot[kNumSplits + 1];
   for (int b = threadIdx.x; b < kNumBuckets; b += blockDim.x) s_cnt[b] = 0;
+  // the batch totals: every copy loaded at once (one load per thread), then summed
+  if (threadIdx.x < kTotCopies * (kNumSplits + 1))
+    s_part[threadIdx.x] =
+        a.ctr->totals[threadIdx.x / (kNumSplits + 1)][threadIdx.x % (kNumSplits + 1)][0];
+  __syncthreads();
+  if (threadIdx.x <= kNumSplits) {
+    unsigned long long v = 0;
+    for (int c = 0; c < kTotCopies; ++c) v += s_part[c * (kNumSplits + 1) + threadIdx.x];
+    s_tot[threadIdx.x] = v;
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
     // The split is a pure function of batch totals, so every block picks the
     // same one.  Items get finer (more, smaller) as j falls.  Finer items
@@ -263,10 +273,10 @@ __global__ __launch_bounds__(1024) void k_bucketize(BatchArgs a) {
     // Failing that: the coarsest split that still gives every lane an item;
     // for a batch too small for that, the finest split that fits.  Whole
     // queries (one item each) always fit.
-    const unsigned long long leaves = a.ctr->total_leaves[0];
+    const unsigned long long leaves = s_tot[kNumSplits];
     int best = -1, busy = -1, finest = kSplitWhole;
     for (int c = kSplitWhole; c >= 0; --c) {
-      const unsigned long long n = a.ctr->total_items[c][0];
+      const unsigned long long n = s_tot[c];
       if (n + kPadReserve > a.cap_items) break;
       finest = c;
       if (n >= a.lanes) {
@@ -278,7 +288,7 @@ __global__ __launch_bounds__(1024) void k_bucketize(BatchArgs a) {
     s_split = j;
     if (blockIdx.x == 0) {
       a.ctr->chosen_split = (uint32_t)j;
-      a.ctr->last_total_items = a.ctr->total_items[j][0];
+      a.ctr->last_total_items = s_tot[j];
     }
   }
   __syncthreads();
@@ -316,14 +326,6 @@ __global__ __launch_bounds__(1024) void k_bucketize(BatchArgs a) {
   for (int r = 0; r < kMaxPerThread; ++r) {
     const int i = q0 + threadIdx.x + r * (int)blockDim.x;
     if (bk[r] >= 0) a.plan[i].item_off = s_base[bk[r]] + local[r];
-  }
-  // the last block to finish lays the buckets out
-  __threadfence();
-  if (threadIdx.x == 0) s_last = atomicAdd(&a.ctr->blocks_done[0], 1u) == gridDim.x - 1;
-  __syncthreads();
-  if (s_last) {
-    __threadfence();
-    layout_buckets(a);
   }
 }
 
@@ -453,15 +455,18 @@ __device__ __forceinline__ uint32_t adjacency(const uint32_t *r) {
 //   free vertex not chosen yet.
 //   LINKED mode: from the back-neighbour table; candidates must also be
 //   adjacent to each of those vertices.
-template <int WPR, bool LINKED, bool LAST>
+//   KIND >= 0 fixes the pattern kind at compile time (ALL mode inside the
+//   search, where it is wave-uniform); KIND < 0 reads it from `kind`.
+template <int WPR, bool LINKED, bool LAST, int KIND = -1>
 __device__ __forceinline__ void node_masks(const LaneState &s, int kind, uint32_t rest,
                                            uint32_t code, int p, uint32_t prev, uint32_t &nbm,
                                            uint32_t &cand) {
   cand = rest;
   if constexpr (!LINKED) {
-    if (kind == MAPA_ALL_TO_ALL) {
+    const int kd = KIND >= 0 ? KIND : kind;
+    if (kd == MAPA_ALL_TO_ALL) {
       nbm = s.R & ~rest;
-    } else if (kind == MAPA_RING) {
+    } else if (kd == MAPA_RING) {
       nbm = p > 0 ? (1u << prev) : 0u;
       if (LAST && s.k >= 3) nbm |= 1u << (code & 15u);
     } else {
@@ -489,11 +494,11 @@ __device__ __forceinline__ void node_masks(const LaneState &s, int kind, uint32_
 // u32, ((key + 1) << 4) | (15 - c), so one max() picks the largest key and,
 // among equal keys, the smallest vertex; the node then replaces the lane's
 // best only on a strictly larger key (leaves arrive in lexicographic order).
-template <int L, int WPR, bool LINKED>
+template <int L, int WPR, bool LINKED, int KIND>
 __device__ __forceinline__ void level(LaneState &s, int kind, uint32_t rest, uint32_t code,
                                       int kp, int p, uint32_t prev, int mu) {
   uint32_t nbm, cand;
-  node_masks<WPR, LINKED, L == 1>(s, kind, rest, code, p, prev, nbm, cand);
+  node_masks<WPR, LINKED, L == 1, KIND>(s, kind, rest, code, p, prev, nbm, cand);
   const uint32_t nb2 = nbm | (nbm << 16);
   const uint32_t rest2 = rest | (rest << 16);
   const int m = LINKED ? __popc(cand) : mu;
@@ -523,24 +528,24 @@ __device__ __forceinline__ void level(LaneState &s, int kind, uint32_t rest, uin
       cand &= cand - 1;
       const uint32_t *rc = s.trow + c * WPR;
       const int kp2 = kp + __mul24(s.a, wsum<WPR>(rc, nb2)) - __mul24(s.b, wsum<WPR>(rc, rest2));
-      level<L - 1, WPR, LINKED>(s, kind, rest & ~(1u << c), code | ((uint32_t)c << sh), kp2, p + 1,
+      level<L - 1, WPR, LINKED, KIND>(s, kind, rest & ~(1u << c), code | ((uint32_t)c << sh), kp2, p + 1,
                                 (uint32_t)c, mu - 1);
     }
   }
 }
 
-template <int WPR, bool LINKED>
+template <int WPR, bool LINKED, int KIND>
 __device__ __forceinline__ void expand(LaneState &s, int kind, int L, uint32_t rest,
                                        uint32_t code, int kp, int d, uint32_t prev, int mu) {
   switch (L) {
-    case 1: level<1, WPR, LINKED>(s, kind, rest, code, kp, d, prev, mu); break;
-    case 2: level<2, WPR, LINKED>(s, kind, rest, code, kp, d, prev, mu); break;
-    case 3: level<3, WPR, LINKED>(s, kind, rest, code, kp, d, prev, mu); break;
-    case 4: level<4, WPR, LINKED>(s, kind, rest, code, kp, d, prev, mu); break;
-    case 5: level<5, WPR, LINKED>(s, kind, rest, code, kp, d, prev, mu); break;
-    case 6: level<6, WPR, LINKED>(s, kind, rest, code, kp, d, prev, mu); break;
-    case 7: level<7, WPR, LINKED>(s, kind, rest, code, kp, d, prev, mu); break;
-    case 8: level<8, WPR, LINKED>(s, kind, rest, code, kp, d, prev, mu); break;
+    case 1: level<1, WPR, LINKED, KIND>(s, kind, rest, code, kp, d, prev, mu); break;
+    case 2: level<2, WPR, LINKED, KIND>(s, kind, rest, code, kp, d, prev, mu); break;
+    case 3: level<3, WPR, LINKED, KIND>(s, kind, rest, code, kp, d, prev, mu); break;
+    case 4: level<4, WPR, LINKED, KIND>(s, kind, rest, code, kp, d, prev, mu); break;
+    case 5: level<5, WPR, LINKED, KIND>(s, kind, rest, code, kp, d, prev, mu); break;
+    case 6: level<6, WPR, LINKED, KIND>(s, kind, rest, code, kp, d, prev, mu); break;
+    case 7: level<7, WPR, LINKED, KIND>(s, kind, rest, code, kp, d, prev, mu); break;
+    case 8: level<8, WPR, LINKED, KIND>(s, kind, rest, code, kp, d, prev, mu); break;
     default: break;
   }
 }
@@ -604,9 +609,13 @@ __device__ __forceinline__ void item_search(const Plan *pp, const uint32_t *trow
   const int kind_w = __builtin_amdgcn_readfirstlane(kind);
   const int fp_w = __builtin_amdgcn_readfirstlane(fp);
   if (__builtin_amdgcn_readfirstlane(s.linked))
-    expand<WPR, true>(s, kind_w, L, rest, code, kp, d, prev, 0);
+    expand<WPR, true, -1>(s, kind_w, L, rest, code, kp, d, prev, 0);
+  else if (kind_w == MAPA_RING)
+    expand<WPR, false, MAPA_RING>(s, kind_w, L, rest, code, kp, d, prev, fp_w);
+  else if (kind_w == MAPA_ALL_TO_ALL)
+    expand<WPR, false, MAPA_ALL_TO_ALL>(s, kind_w, L, rest, code, kp, d, prev, fp_w);
   else
-    expand<WPR, false>(s, kind_w, L, rest, code, kp, d, prev, fp_w);
+    expand<WPR, false, MAPA_TREE>(s, kind_w, L, rest, code, kp, d, prev, fp_w);
 
   int bkey = -1;
   uint32_t bcode = 0;
@@ -965,6 +974,7 @@ hipError_t launch_batch_front(const BatchArgs &a, hipStream_t s) {
   if (gb < 64) gb = std::min<unsigned>(64, blocks_for(a.nq, 1024));
   if (gb < 1) gb = 1;
   hipLaunchKernelGGL(k_bucketize, dim3(gb), dim3(1024), 0, s, a);
+  hipLaunchKernelGGL(k_layout, dim3(1), dim3(1024), 0, s, a);
   // one-wave blocks of at most 64 queries, and at least ~2048 blocks
   int qpb = 64;
   if (blocks_for(a.nq, qpb) < 2048) qpb = (int)((a.nq + 2047) / 2048);

@@ -51,8 +51,8 @@ static_assert(sizeof(Plan) == 48, "Plan layout");
 
 constexpr uint8_t kPlanOk = 0, kPlanNofit = 1, kPlanInvalid = 3;
 
-// Per-batch counters (device).  Zeroed at allocation; the last k_bucketize
-// block re-zeroes what the batch consumed so the next batch starts clean.
+// Per-batch counters (device).  Zeroed at allocation; k_layout re-zeroes what
+// the batch consumed so the next batch starts clean.
 // Counters hit by atomics from many blocks each own a 128-byte line, so their
 // atomics spread over L2 channels instead of queueing on one.
 constexpr int kLine = 32;  // u32 per 128-byte line
@@ -60,11 +60,13 @@ constexpr int kLine = 32;  // u32 per 128-byte line
 // queue c % kQueues), each with its own claim counter, so the claims of the
 // persistent waves spread over many addresses instead of serializing on one.
 constexpr int kQueues = 32;
+constexpr int kTotCopies = 16;
 struct Counters {
-  unsigned long long total_items[kNumSplits][kLine / 2];  // [j][0] used
-  unsigned long long total_leaves[kLine / 2];             // [0] used
+  // item total of each split j (and, at j = kNumSplits, the embedding total),
+  // spread over kTotCopies copies: block b of k_prepare adds to copy
+  // b % kTotCopies, so no counter queues more than a few atomics
+  unsigned long long totals[kTotCopies][kNumSplits + 1][kLine / 2];  // [c][j][0] used
   uint32_t bucket_items[kNumBuckets][kLine];              // [b][0] used
-  uint32_t blocks_done[kLine];                            // k_bucketize blocks finished
   uint32_t queue_ctr[kQueues][kLine];                     // next chunk of each queue
   uint32_t bucket_start[kNumBuckets];
   uint32_t total_chunks;
