@@ -229,16 +229,25 @@ Tables build_tables() {
       for (int i = 0; i < d; ++i) v *= (unsigned long long)std::max(0, F - i);
       t.perm[F][d] = v;
     }
-  // buckets laid out largest items first (longest-processing-time order)
+  // Buckets laid out costliest items first (longest-processing-time order),
+  // so the last chunks the persistent waves pick up are the cheapest.  An
+  // item's cost in VALU instructions, roughly: its setup, every interior
+  // node of its subtree (the node's own score terms and its children's
+  // bookkeeping) and every leaf.
+  constexpr double kItemCost = 300, kNodeCost = 30, kLeafCost = 20;
   std::vector<std::pair<double, int>> order;
   for (int b = 0; b < kNumBuckets; ++b) {
     const int Fp = b % kFp, L = (b / kFp) % kMaxK + 1;  // see bucket_id
-    double leaves = 0;
+    double cost = 0;
     if (Fp >= L) {
-      leaves = 1;
-      for (int i = 0; i < L; ++i) leaves *= (Fp - i);
+      double nodes = 1;  // subtree nodes at depth i below the prefix
+      cost = kItemCost;
+      for (int i = 1; i <= L; ++i) {
+        nodes *= (Fp - i + 1);
+        cost += nodes * (i < L ? kNodeCost : kLeafCost);
+      }
     }
-    order.push_back({-leaves, b});
+    order.push_back({-cost, b});
   }
   std::sort(order.begin(), order.end());
   for (int r = 0; r < kNumBuckets; ++r) t.rank_bucket[r] = (uint16_t)order[r].second;
