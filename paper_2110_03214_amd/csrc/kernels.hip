@@ -651,9 +651,25 @@ __device__ __forceinline__ void run_item(const BatchArgs &a, const uint32_t *row
       atomicAdd(&a.acc_count[q0], cnt);
       if (best) atomicMax(&a.acc_best[q0], best);
     }
-  } else if (valid) {
-    if (cnt) atomicAdd(&a.acc_count[qi], cnt);
-    if (best) atomicMax(&a.acc_best[qi], best);
+  } else {
+    // The items of one query sit in consecutive lanes of a chunk: fold each
+    // run of equal query ids onto its first lane, which alone issues the
+    // atomics (one per query and chunk instead of one per item).
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int oq = __shfl_down(qi, off, 64);
+      const unsigned long long oc = __shfl_down(cnt, off, 64);
+      const unsigned long long ob = __shfl_down(best, off, 64);
+      if (lane + off < 64 && oq == qi) {
+        cnt += oc;
+        best = ob > best ? ob : best;
+      }
+    }
+    const int pq = __shfl_up(qi, 1, 64);
+    if (valid && (lane == 0 || pq != qi)) {
+      if (cnt) atomicAdd(&a.acc_count[qi], cnt);
+      if (best) atomicMax(&a.acc_best[qi], best);
+    }
   }
 }
 
