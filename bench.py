@@ -21,6 +21,7 @@ queries/s, per-batch p50/p99 latency, the roofline of the enumeration kernel
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -41,6 +42,12 @@ METRIC = "pattern embeddings scored/sec + allocation queries/sec, p50/p99 latenc
 # clock per CU.)
 CU, LANES_PER_CLK, CLK = 256, 128, 2.4e9
 ALU_PEAK = CU * LANES_PER_CLK * CLK  # 78.64e12 int32 lane-ops/s
+
+# Counter profiles (rocprofv3 FETCH_SIZE / WRITE_SIZE) of the enumeration
+# kernel, committed under profiles/; their HBM byte count is reported only
+# while the kernel sources still hash to the value the profile was taken on.
+KERNEL_SOURCES = ("paper_2110_03214_amd/csrc/kernels.hip", "paper_2110_03214_amd/csrc/mapa_internal.h")
+PMC_PROFILE = {2: "k_enumerate_batched_65536q_pmc.txt", 3: "k_enumerate_large_1536q_pmc.txt"}
 
 WORKLOAD_TEXT = {
     1: "tiny: 1,000 states of one 8-vertex cube-mesh (weights 1-2), 0-4 busy, ring k=4",
@@ -108,6 +115,35 @@ def algorithmic_ops(wl) -> tuple[int, int]:
         emb += e
         ops += o
     return emb, ops
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def profiled_traffic(cfg: int):
+    """(HBM bytes per enumeration launch, profile path) from the committed
+    counter profile of this workload, or (None, reason) when there is none or
+    the kernel has changed since it was taken."""
+    name = PMC_PROFILE.get(cfg)
+    if not name:
+        return None, "no counter profile for this workload"
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None, f"profiles/{name} missing"
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith(" "):
+                key, _, val = line.partition(":")
+                fields[key.strip()] = val.strip()
+    if fields.get("kernel_source_sha256") != kernel_source_hash():
+        return None, f"profiles/{name} was taken on other kernel sources"
+    return int(fields["traffic_bytes_per_launch"]), f"profiles/{name}"
 
 
 def cpu_baseline(wl, seconds: float = 8.0):
@@ -324,10 +360,12 @@ def main():
         avg_s = st["enum_ms"] / st["enum_launches"] / 1e3
         achieved = ops / avg_s
         probe = ctx.measure_alu_peak()
+        traffic, source = profiled_traffic(args.config)
         out["roofline"] = {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_PEAK / 1e12,
-                           "unit": "Tops/s", "frac": achieved / ALU_PEAK, "traffic": None,
+                           "unit": "Tops/s", "frac": achieved / ALU_PEAK, "traffic": traffic,
+                           "traffic_unit": "HBM bytes per launch", "traffic_source": source,
                            "kernel": "k_enumerate", "kernel_ms": avg_s * 1e3,
-                           "ops_per_launch": ops,
+                           "ops_per_launch": ops, "items_per_launch": st["last_items"],
                            "measured_peak": probe / 1e12, "frac_of_measured_peak": achieved / probe}
     if args.plain:
         log("[bench] plain form: one query per launch")
