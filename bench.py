@@ -143,6 +143,8 @@ def profiled_traffic(cfg: int):
                 fields[key.strip()] = val.strip()
     if fields.get("kernel_source_sha256") != kernel_source_hash():
         return None, f"profiles/{name} was taken on other kernel sources"
+    if "traffic_bytes_per_launch" not in fields:
+        return None, f"profiles/{name} holds no memory counters"
     return int(fields["traffic_bytes_per_launch"]), f"profiles/{name}"
 
 
