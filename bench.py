@@ -243,6 +243,7 @@ def run_serving(B, cfg: int, nreq: int, loads=(0.5, 0.8, 1.0, 1.2)):
                             "requests_per_s": st["requests_per_s"], "p50_us": st["p50_us"],
                             "p99_us": st["p99_us"], "p999_us": st["p999_us"],
                             "mean_batch": st["mean_batch"], "batches": st["batches"],
+                            "mean_batch_us": st["mean_batch_us"], "fused_batches": st["fused_batches"],
                             "granted": st["granted"], "nofit": st["nofit"],
                             "embeddings_per_s": st["embeddings_per_s"]})
     ctx.close()
@@ -259,6 +260,9 @@ def main():
     ap.add_argument("--no-profile", action="store_true", help="no HIP-event timing of the kernel")
     ap.add_argument("--plain", type=int, default=4096,
                     help="queries timed in the plain one-query-per-launch form (0: skip)")
+    ap.add_argument("--serving-trace", type=int, default=4, choices=(4, 5),
+                    help="serving trace: 4 = Poisson requests over the batched config's topologies, "
+                         "5 = bursty requests over cube-mesh and 16-vertex servers")
     ap.add_argument("--serving", type=int, default=100000,
                     help="requests of the serving trace timed through the serving loop (0: skip)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -374,8 +378,8 @@ def main():
         out["plain_one_query_per_launch"] = run_plain(ctx, B, qh, args.plain)
     ctx.close()
     if args.serving and args.config == 2:
-        log("[bench] serving form")
-        out["serving"] = run_serving(B, 4, args.serving)
+        log(f"[bench] serving form, trace {args.serving_trace}")
+        out["serving"] = run_serving(B, args.serving_trace, args.serving)
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(wl)
