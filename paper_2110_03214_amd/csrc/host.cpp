@@ -114,15 +114,19 @@ void fill_args(mapa_ctx *c, const Workspace &w, BatchArgs &a) {
   a.wpr = c->wpr;
   a.split_d = c->d_split;
   const int threads = c->tuning.threads_per_block;
-  const size_t lds_bytes = (size_t)a.ntopo * 16 * c->wpr * sizeof(uint32_t);
+  const size_t lds_bytes = (size_t)a.ntopo * kTopoWords * c->wpr * sizeof(uint32_t);
   a.rows_in_lds = lds_bytes <= 48 * 1024 ? 1 : 0;
+  // the pair_level variant pays for its registers only when the last two
+  // positions have many candidates: topologies of 10 or more vertices
+  const int max_n = c->topo_n.empty() ? 0 : *std::max_element(c->topo_n.begin(), c->topo_n.end());
+  a.pair = (c->wpr == 1 && max_n >= 10) ? 1 : 0;
   int per_cu = c->tuning.blocks_per_cu;
   if (per_cu <= 0) {
     // the occupancy query costs microseconds: ask once per launch shape
     const uint64_t shape = ((uint64_t)lds_bytes << 24) | ((uint64_t)threads << 8) |
-                           ((uint64_t)c->wpr << 1) | (uint64_t)a.rows_in_lds;
+                           ((uint64_t)a.pair << 5) | ((uint64_t)c->wpr << 1) | (uint64_t)a.rows_in_lds;
     if (shape != c->occ_shape) {
-      c->occ_blocks = enumerate_occupancy(c->wpr, a.rows_in_lds, threads, lds_bytes);
+      c->occ_blocks = enumerate_occupancy(c->wpr, a.rows_in_lds, a.pair, threads, lds_bytes);
       c->occ_shape = shape;
     }
     per_cu = c->occ_blocks;
@@ -291,7 +295,7 @@ int32_t not_while_serving(mapa_ctx *c, const char *fn) {
   return MAPA_OK;
 }
 
-void build_rows(const uint8_t *W16, int n, int wpr, uint32_t *out /* 16*wpr */) {
+void build_rows(const uint8_t *W16, int n, int wpr, uint32_t *out /* kTopoWords * wpr */) {
   for (int v = 0; v < 16; ++v)
     for (int w = 0; w < wpr; ++w) {
       uint32_t lo = 0, hi = 0;
@@ -302,6 +306,18 @@ void build_rows(const uint8_t *W16, int n, int wpr, uint32_t *out /* 16*wpr */) 
           hi |= ((x >> (2 * w + 1)) & 1u) << u;
         }
       out[v * wpr + w] = lo | (hi << 16);
+    }
+  // packed weights: field width 2 * wpr bits, 16 / wpr fields per word
+  const int bits = 2 * wpr, per = 16 / wpr;
+  uint32_t *pk = out + 16 * wpr;
+  for (int v = 0; v < 16; ++v)
+    for (int w = 0; w < wpr; ++w) {
+      uint32_t word = 0;
+      for (int f = 0; f < per; ++f) {
+        const int u = w * per + f;
+        if (v < n && u < n) word |= (uint32_t)W16[v * 16 + u] << (bits * f);
+      }
+      pk[v * wpr + w] = word;
     }
 }
 
@@ -319,7 +335,7 @@ int32_t upload_topologies(mapa_ctx *c, size_t first, bool all) {
     dev_free(c->d_rows);
     c->cap_topos = 0;
     if (dev_alloc(&c->d_topo_n, cap) != hipSuccess || dev_alloc(&c->d_topo_W, cap * 256) != hipSuccess ||
-        dev_alloc(&c->d_rows, cap * 16 * 4) != hipSuccess)
+        dev_alloc(&c->d_rows, cap * kTopoWords * 4) != hipSuccess)
       return fail(MAPA_ERR_OOM, "topology tables: device allocation failed");
     c->cap_topos = cap;
   }
@@ -327,15 +343,15 @@ int32_t upload_topologies(mapa_ctx *c, size_t first, bool all) {
   if (t0 >= T) return MAPA_OK;
   const size_t nt = T - t0;
   std::vector<uint8_t> W(nt * 256);
-  std::vector<uint32_t> rows(nt * 16 * c->wpr);
+  std::vector<uint32_t> rows(nt * kTopoWords * c->wpr);
   for (size_t t = t0; t < T; ++t) {
     std::memcpy(&W[(t - t0) * 256], c->topo_W[t].data(), 256);
-    build_rows(c->topo_W[t].data(), c->topo_n[t], c->wpr, &rows[(t - t0) * 16 * c->wpr]);
+    build_rows(c->topo_W[t].data(), c->topo_n[t], c->wpr, &rows[(t - t0) * kTopoWords * c->wpr]);
   }
   MAPA_HIPCHK(hipMemcpy(c->d_topo_n + t0, c->topo_n.data() + t0, nt * sizeof(int32_t),
                         hipMemcpyHostToDevice));
   MAPA_HIPCHK(hipMemcpy(c->d_topo_W + t0 * 256, W.data(), W.size(), hipMemcpyHostToDevice));
-  MAPA_HIPCHK(hipMemcpy(c->d_rows + t0 * 16 * c->wpr, rows.data(), rows.size() * sizeof(uint32_t),
+  MAPA_HIPCHK(hipMemcpy(c->d_rows + t0 * kTopoWords * c->wpr, rows.data(), rows.size() * sizeof(uint32_t),
                         hipMemcpyHostToDevice));
   return MAPA_OK;
 }

@@ -138,7 +138,7 @@ __device__ __forceinline__ Plan make_plan(const mapa_query &q, int32_t nservers,
   p.n = (uint8_t)n;
   p.R = R;
   p.F = (uint8_t)F;
-  p.kp0 = (int32_t)q.b * set_weight(rows + (size_t)t * 16 * wpr, wpr, R);
+  p.kp0 = (int32_t)q.b * set_weight(rows + (size_t)t * kTopoWords * wpr, wpr, R);
   p.nbtab = c_tab.nbtab[q.kind][q.k];
   p.status = q.k > F ? kPlanNofit : kPlanOk;
   return p;
@@ -483,20 +483,123 @@ __device__ __forceinline__ void node_masks(const LaneState &s, int kind, uint32_
   }
 }
 
+// The last two pattern positions in ALL mode, with the N = M + 1 free
+// vertices left (c_0 < ... < c_M) and M wave-uniform: every ordered pair
+// (c_i at position p = k-2, c_j at position k-1) is a match.  With
+//   D_j = w(c_j, rest)               weight to every vertex still free,
+//   X_j = w(c_j, fixed neighbours of position k-1, i.e. those other than c_i),
+//   Y_i = w(c_i, neighbours of position p),
+// the leaf key of (c_i, c_j) is
+//   kp + a*Y_i - b*D_i + a*(X_j + alpha*W[c_j][c_i]) - b*(D_j - W[c_j][c_i])
+// where alpha says whether position p neighbours position k-1.  Per node the
+// N values P_j = 16a*X_j - 16b*D_j - c_j are computed once; a leaf is then
+// one packed-weight field, one multiply-add and a max.  The inner loop is
+// unrolled over N, so the per-candidate values stay in registers.  Leaves
+// come in lexicographic order (c_i, then c_j, ascending) as in level().
+// Rows of one word (weights up to 3): the packed weight of u is 2 bits at 2u.
+template <int M, int KIND>
+__device__ __forceinline__ void pair_level(LaneState &s, uint32_t rest, uint32_t code, int kp,
+                                           int p, uint32_t prev) {
+  constexpr int N = M + 1;
+  uint32_t nbm, cand;
+  node_masks<1, false, false, KIND>(s, KIND, rest, code, p, prev, nbm, cand);
+  // fixed neighbours of position k-1 and whether position p is one of them
+  uint32_t fixm = 0;
+  bool alpha = true;
+  if constexpr (KIND == MAPA_ALL_TO_ALL) {
+    fixm = s.R & ~rest;
+  } else if constexpr (KIND == MAPA_RING) {
+    if (s.k >= 3) fixm = 1u << (code & 15u);
+  } else {
+    const int parent = (s.k - 2) >> 1;  // heap parent of position k-1
+    alpha = parent == p;
+    if (!alpha) fixm = 1u << ((code >> (4 * parent)) & 15u);
+  }
+  const uint32_t nb2 = nbm | (nbm << 16), rest2 = rest | (rest << 16), fix2 = fixm | (fixm << 16);
+  const uint32_t *prow = s.trow + 16;  // packed-weight rows
+  uint32_t sh2[N];                     // 2 * c_j: bit offset of c_j's packed weight
+  int P[N];
+  uint32_t r = rest;
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    const uint32_t c = (uint32_t)__builtin_ctz(r);
+    r &= r - 1;
+    sh2[j] = 2 * c;
+    const uint32_t *row = s.trow + c;
+    P[j] = __mul24(16 * s.a, wsum<1>(row, fix2)) - __mul24(16 * s.b, wsum<1>(row, rest2)) - (int)c;
+  }
+  const int gamma = (alpha ? 16 * s.a : 0) + 16 * s.b;
+  s.count += (uint32_t)(N * M);
+  const int sh = 4 * p;
+  uint32_t ri = rest;
+  for (int i = 0; i < N; ++i) {
+    const uint32_t ci = (uint32_t)__builtin_ctz(ri);
+    ri &= ri - 1;
+    const uint32_t *row = s.trow + ci;
+    const int kp2 = kp + __mul24(s.a, wsum<1>(row, nb2)) - __mul24(s.b, wsum<1>(row, rest2));
+    const int base = 16 * kp2 + 31;
+    const uint32_t wp = prow[ci];
+    const uint32_t si = 2 * ci;
+    uint32_t pb = 0;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const int w = (int)((wp >> sh2[j]) & 3u);
+      const uint32_t pk = (uint32_t)(base + P[j] + __mul24(gamma, w));
+      pb = (pk > pb && sh2[j] != si) ? pk : pb;  // c_j = c_i is no match
+    }
+    const bool better = pb > (s.bpk | 15u);
+    s.bpk = better ? pb : s.bpk;
+    s.bcode = better ? (code | (ci << sh)) : s.bcode;
+  }
+}
+
+// pair_level for N = 2 .. 12 free vertices at the last two positions (rows of
+// one word); other shapes take the general per-level loops.
+template <int KIND>
+__device__ __forceinline__ bool pair_dispatch(LaneState &s, uint32_t rest, uint32_t code, int kp,
+                                              int p, uint32_t prev, int mu) {
+  switch (mu) {
+    case 2: pair_level<1, KIND>(s, rest, code, kp, p, prev); return true;
+    case 3: pair_level<2, KIND>(s, rest, code, kp, p, prev); return true;
+    case 4: pair_level<3, KIND>(s, rest, code, kp, p, prev); return true;
+    case 5: pair_level<4, KIND>(s, rest, code, kp, p, prev); return true;
+    case 6: pair_level<5, KIND>(s, rest, code, kp, p, prev); return true;
+    case 7: pair_level<6, KIND>(s, rest, code, kp, p, prev); return true;
+    case 8: pair_level<7, KIND>(s, rest, code, kp, p, prev); return true;
+    case 9: pair_level<8, KIND>(s, rest, code, kp, p, prev); return true;
+    case 10: pair_level<9, KIND>(s, rest, code, kp, p, prev); return true;
+    case 11: pair_level<10, KIND>(s, rest, code, kp, p, prev); return true;
+    case 12: pair_level<11, KIND>(s, rest, code, kp, p, prev); return true;
+    default: return false;
+  }
+}
+
 // One pattern position: expand every candidate vertex c, scoring it with
 //   a * (weight from c to the vertices at its earlier pattern neighbours)
 //   - b * (weight from c to the free vertices not yet chosen)
 // and recurse; at the last position keep the node's best leaf.
 //
-// In ALL mode every lane of a wave holds an item of the same bucket, so all
-// lanes have the same number of candidates mu at every node and the loops
-// are counted on the scalar unit.  The leaf loop keeps the node's best as one
-// u32, ((key + 1) << 4) | (15 - c), so one max() picks the largest key and,
-// among equal keys, the smallest vertex; the node then replaces the lane's
-// best only on a strictly larger key (leaves arrive in lexicographic order).
-template <int L, int WPR, bool LINKED, int KIND>
+// The chain is entered at its top for every item: a level above the item's
+// run of positions (Lrun) passes straight through, so each level exists once
+// per instantiation.  In ALL mode every lane of a wave holds an item of the
+// same bucket, so all lanes have the same number of candidates mu at every
+// node and the loops are counted on the scalar unit; the last two positions
+// go to pair_level.  The leaf loop keeps the node's best as one u32,
+// ((key + 1) << 4) | (15 - c), so one max() picks the largest key and, among
+// equal keys, the smallest vertex; the node then replaces the lane's best only
+// on a strictly larger key (leaves arrive in lexicographic order).
+template <int L, int WPR, bool LINKED, int KIND, bool PAIR>
 __device__ __forceinline__ void level(LaneState &s, int kind, uint32_t rest, uint32_t code,
-                                      int kp, int p, uint32_t prev, int mu) {
+                                      int kp, int p, uint32_t prev, int mu, int Lrun) {
+  if constexpr (L > 1) {
+    if (Lrun < L) {
+      level<L - 1, WPR, LINKED, KIND, PAIR>(s, kind, rest, code, kp, p, prev, mu, Lrun);
+      return;
+    }
+  }
+  if constexpr (PAIR && L == 2 && !LINKED && KIND >= 0 && WPR == 1) {
+    if (pair_dispatch<KIND>(s, rest, code, kp, p, prev, mu)) return;
+  }
   uint32_t nbm, cand;
   node_masks<WPR, LINKED, L == 1, KIND>(s, kind, rest, code, p, prev, nbm, cand);
   const uint32_t nb2 = nbm | (nbm << 16);
@@ -528,26 +631,16 @@ __device__ __forceinline__ void level(LaneState &s, int kind, uint32_t rest, uin
       cand &= cand - 1;
       const uint32_t *rc = s.trow + c * WPR;
       const int kp2 = kp + __mul24(s.a, wsum<WPR>(rc, nb2)) - __mul24(s.b, wsum<WPR>(rc, rest2));
-      level<L - 1, WPR, LINKED, KIND>(s, kind, rest & ~(1u << c), code | ((uint32_t)c << sh), kp2, p + 1,
-                                (uint32_t)c, mu - 1);
+      level<L - 1, WPR, LINKED, KIND, PAIR>(s, kind, rest & ~(1u << c), code | ((uint32_t)c << sh),
+                                            kp2, p + 1, (uint32_t)c, mu - 1, L - 1);
     }
   }
 }
 
-template <int WPR, bool LINKED, int KIND>
+template <int WPR, bool LINKED, int KIND, bool PAIR>
 __device__ __forceinline__ void expand(LaneState &s, int kind, int L, uint32_t rest,
                                        uint32_t code, int kp, int d, uint32_t prev, int mu) {
-  switch (L) {
-    case 1: level<1, WPR, LINKED, KIND>(s, kind, rest, code, kp, d, prev, mu); break;
-    case 2: level<2, WPR, LINKED, KIND>(s, kind, rest, code, kp, d, prev, mu); break;
-    case 3: level<3, WPR, LINKED, KIND>(s, kind, rest, code, kp, d, prev, mu); break;
-    case 4: level<4, WPR, LINKED, KIND>(s, kind, rest, code, kp, d, prev, mu); break;
-    case 5: level<5, WPR, LINKED, KIND>(s, kind, rest, code, kp, d, prev, mu); break;
-    case 6: level<6, WPR, LINKED, KIND>(s, kind, rest, code, kp, d, prev, mu); break;
-    case 7: level<7, WPR, LINKED, KIND>(s, kind, rest, code, kp, d, prev, mu); break;
-    case 8: level<8, WPR, LINKED, KIND>(s, kind, rest, code, kp, d, prev, mu); break;
-    default: break;
-  }
+  if (L > 0) level<kMaxK, WPR, LINKED, KIND, PAIR>(s, kind, rest, code, kp, d, prev, mu, L);
 }
 
 // One prefix item: prefix x (of depth p.d) of query plan *pp, expanded over
@@ -555,7 +648,7 @@ __device__ __forceinline__ void expand(LaneState &s, int kind, int L, uint32_t r
 // the item's match count and its best as one u64 (key high, inverted
 // lexicographic mapping code low, so max() takes the largest key and then
 // the smallest mapping; 0: no match).  trow: the topology's rows.
-template <int WPR>
+template <int WPR, bool PAIR>
 __device__ __forceinline__ void item_search(const Plan *pp, const uint32_t *trow, uint32_t x,
                                             unsigned long long &cnt_out,
                                             unsigned long long &best_out) {
@@ -609,13 +702,13 @@ __device__ __forceinline__ void item_search(const Plan *pp, const uint32_t *trow
   const int kind_w = __builtin_amdgcn_readfirstlane(kind);
   const int fp_w = __builtin_amdgcn_readfirstlane(fp);
   if (__builtin_amdgcn_readfirstlane(s.linked))
-    expand<WPR, true, -1>(s, kind_w, L, rest, code, kp, d, prev, 0);
+    expand<WPR, true, -1, PAIR>(s, kind_w, L, rest, code, kp, d, prev, 0);
   else if (kind_w == MAPA_RING)
-    expand<WPR, false, MAPA_RING>(s, kind_w, L, rest, code, kp, d, prev, fp_w);
+    expand<WPR, false, MAPA_RING, PAIR>(s, kind_w, L, rest, code, kp, d, prev, fp_w);
   else if (kind_w == MAPA_ALL_TO_ALL)
-    expand<WPR, false, MAPA_ALL_TO_ALL>(s, kind_w, L, rest, code, kp, d, prev, fp_w);
+    expand<WPR, false, MAPA_ALL_TO_ALL, PAIR>(s, kind_w, L, rest, code, kp, d, prev, fp_w);
   else
-    expand<WPR, false, MAPA_TREE>(s, kind_w, L, rest, code, kp, d, prev, fp_w);
+    expand<WPR, false, MAPA_TREE, PAIR>(s, kind_w, L, rest, code, kp, d, prev, fp_w);
 
   int bkey = -1;
   uint32_t bcode = 0;
@@ -633,14 +726,14 @@ __device__ __forceinline__ void item_search(const Plan *pp, const uint32_t *trow
   best_out = best;
 }
 
-template <int WPR>
+template <int WPR, bool PAIR>
 __device__ __forceinline__ void run_item(const BatchArgs &a, const uint32_t *rows, uint2 it) {
   const int lane = threadIdx.x & 63;
   const bool valid = it.x != kInvalidItem;
   const Plan *pp = valid ? &a.plan[it.x] : nullptr;
-  const uint32_t *trow = valid ? rows + (uint32_t)pp->topo * (16 * WPR) : rows;
+  const uint32_t *trow = valid ? rows + (uint32_t)pp->topo * (kTopoWords * WPR) : rows;
   unsigned long long cnt, best;
-  item_search<WPR>(pp, trow, it.y, cnt, best);
+  item_search<WPR, PAIR>(pp, trow, it.y, cnt, best);
   const int qi = valid ? (int)it.x : -1;
   const int q0 = __builtin_amdgcn_readfirstlane(qi);
   const bool same = __ballot(valid && qi != q0) == 0ull;
@@ -673,7 +766,7 @@ __device__ __forceinline__ void run_item(const BatchArgs &a, const uint32_t *row
   }
 }
 
-template <int WPR>
+template <int WPR, bool PAIR>
 __device__ __forceinline__ void chunk_loop(const BatchArgs &a, const uint32_t *rows) {
   const int lane = threadIdx.x & 63;
   const uint32_t nchunks = *(volatile const uint32_t *)&a.ctr->total_chunks;
@@ -702,20 +795,23 @@ __device__ __forceinline__ void chunk_loop(const BatchArgs &a, const uint32_t *r
       continue;
     }
     const uint2 it = a.items[(size_t)c * kChunk + lane];
-    run_item<WPR>(a, rows, it);
+    run_item<WPR, PAIR>(a, rows, it);
   }
 }
 
-template <int WPR, bool ROWS_LDS>
+// PAIR: the last two positions of one-word-row topologies go through
+// pair_level (faster per match, more registers, so fewer waves per SIMD);
+// taken for contexts with topologies of 10 or more vertices.
+template <int WPR, bool ROWS_LDS, bool PAIR>
 __global__ __launch_bounds__(256) void k_enumerate(BatchArgs a) {
   if constexpr (ROWS_LDS) {
     extern __shared__ uint32_t s_rows[];
-    const int words = a.ntopo * 16 * WPR;
+    const int words = a.ntopo * kTopoWords * WPR;
     for (int i = threadIdx.x; i < words; i += blockDim.x) s_rows[i] = a.rows[i];
     __syncthreads();
-    chunk_loop<WPR>(a, s_rows);
+    chunk_loop<WPR, PAIR>(a, s_rows);
   } else {
-    chunk_loop<WPR>(a, a.rows);
+    chunk_loop<WPR, PAIR>(a, a.rows);
   }
 }
 
@@ -788,7 +884,7 @@ __global__ __launch_bounds__(256) void k_finalize(BatchArgs a) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.nq) return;
   const Plan p = a.plan[i];
-  Outcome o = decode_best(p, a.acc_count[i], a.acc_best[i], a.rows + (size_t)p.topo * 16 * a.wpr,
+  Outcome o = decode_best(p, a.acc_count[i], a.acc_best[i], a.rows + (size_t)p.topo * kTopoWords * a.wpr,
                           a.wpr, &a.ctr->self_check_failures);
   a.acc_count[i] = 0;  // leave the accumulators clean for the next batch
   a.acc_best[i] = 0;
@@ -818,7 +914,7 @@ __global__ __launch_bounds__(256) void k_finalize(BatchArgs a) {
 template <int WPR>
 __global__ __launch_bounds__(256) void k_fused(FusedArgs f) {
   __shared__ Plan s_plan;
-  __shared__ uint32_t s_rows[16 * WPR];
+  __shared__ uint32_t s_rows[kTopoWords * WPR];
   __shared__ unsigned long long s_cnt[4], s_best[4];
   __shared__ bool s_last;
   const int i = blockIdx.x / f.bpq;
@@ -839,13 +935,14 @@ __global__ __launch_bounds__(256) void k_fused(FusedArgs f) {
   __syncthreads();
   const int status = s_plan.status;
   const uint32_t nitems = status == kPlanOk ? s_plan.nitems : 0u;
-  if (status != kPlanInvalid && tid < 16 * WPR) s_rows[tid] = f.rows[(size_t)s_plan.topo * 16 * WPR + tid];
+  if (status != kPlanInvalid && tid < kTopoWords * WPR)
+    s_rows[tid] = f.rows[(size_t)s_plan.topo * kTopoWords * WPR + tid];
   __syncthreads();
   unsigned long long cnt = 0, best = 0;
   for (uint32_t base = (uint32_t)j * blockDim.x; base < nitems; base += span) {
     const uint32_t x = base + (uint32_t)tid;
     unsigned long long c1, b1;
-    item_search<WPR>(x < nitems ? &s_plan : nullptr, s_rows, x, c1, b1);
+    item_search<WPR, false>(x < nitems ? &s_plan : nullptr, s_rows, x, c1, b1);
     cnt += c1;
     best = b1 > best ? b1 : best;
   }
@@ -999,10 +1096,10 @@ hipError_t launch_batch_front(const BatchArgs &a, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int WPR, bool LDS>
+template <int WPR, bool LDS, bool PAIR>
 static hipError_t launch_enum_t(const BatchArgs &a, hipStream_t s) {
-  const size_t lds = LDS ? (size_t)a.ntopo * 16 * WPR * sizeof(uint32_t) : 0;
-  hipLaunchKernelGGL((k_enumerate<WPR, LDS>), dim3(a.enum_blocks), dim3(a.enum_threads), lds, s,
+  const size_t lds = LDS ? (size_t)a.ntopo * kTopoWords * WPR * sizeof(uint32_t) : 0;
+  hipLaunchKernelGGL((k_enumerate<WPR, LDS, PAIR>), dim3(a.enum_blocks), dim3(a.enum_threads), lds, s,
                      a);
   return hipGetLastError();
 }
@@ -1010,27 +1107,31 @@ static hipError_t launch_enum_t(const BatchArgs &a, hipStream_t s) {
 hipError_t launch_enumerate(const BatchArgs &a, hipStream_t s) {
   const bool lds = a.rows_in_lds != 0;
   switch (a.wpr) {
-    case 1: return lds ? launch_enum_t<1, true>(a, s) : launch_enum_t<1, false>(a, s);
-    case 2: return lds ? launch_enum_t<2, true>(a, s) : launch_enum_t<2, false>(a, s);
-    default: return lds ? launch_enum_t<4, true>(a, s) : launch_enum_t<4, false>(a, s);
+    case 1:
+      if (a.pair) return lds ? launch_enum_t<1, true, true>(a, s) : launch_enum_t<1, false, true>(a, s);
+      return lds ? launch_enum_t<1, true, false>(a, s) : launch_enum_t<1, false, false>(a, s);
+    case 2: return lds ? launch_enum_t<2, true, false>(a, s) : launch_enum_t<2, false, false>(a, s);
+    default: return lds ? launch_enum_t<4, true, false>(a, s) : launch_enum_t<4, false, false>(a, s);
   }
 }
 
-template <int WPR, bool LDS>
+template <int WPR, bool LDS, bool PAIR>
 static int occ_t(int threads, size_t lds) {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_enumerate<WPR, LDS>, threads, lds) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_enumerate<WPR, LDS, PAIR>, threads, lds) !=
       hipSuccess)
     return 0;
   return nb;
 }
 
-int enumerate_occupancy(int wpr, int rows_in_lds, int threads, size_t lds_bytes) {
+int enumerate_occupancy(int wpr, int rows_in_lds, int pair, int threads, size_t lds_bytes) {
   const bool l = rows_in_lds != 0;
   switch (wpr) {
-    case 1: return l ? occ_t<1, true>(threads, lds_bytes) : occ_t<1, false>(threads, 0);
-    case 2: return l ? occ_t<2, true>(threads, lds_bytes) : occ_t<2, false>(threads, 0);
-    default: return l ? occ_t<4, true>(threads, lds_bytes) : occ_t<4, false>(threads, 0);
+    case 1:
+      if (pair) return l ? occ_t<1, true, true>(threads, lds_bytes) : occ_t<1, false, true>(threads, 0);
+      return l ? occ_t<1, true, false>(threads, lds_bytes) : occ_t<1, false, false>(threads, 0);
+    case 2: return l ? occ_t<2, true, false>(threads, lds_bytes) : occ_t<2, false, false>(threads, 0);
+    default: return l ? occ_t<4, true, false>(threads, lds_bytes) : occ_t<4, false, false>(threads, 0);
   }
 }
 

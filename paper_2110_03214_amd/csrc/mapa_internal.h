@@ -56,6 +56,13 @@ constexpr uint8_t kPlanOk = 0, kPlanNofit = 1, kPlanInvalid = 3;
 // Counters hit by atomics from many blocks each own a 128-byte line, so their
 // atomics spread over L2 channels instead of queueing on one.
 constexpr int kLine = 32;  // u32 per 128-byte line
+
+// A topology's device block, per word of row format (wpr words per row):
+// 16 bit-plane rows (vertex v: for each weight bit t, the mask of neighbours
+// u with bit t of W[v][u] set; planes 2w and 2w+1 share word w, low and high
+// half) followed by 16 packed-weight rows (vertex v: W[v][u] in field u, 2,
+// 4 or 8 bits wide for wpr = 1, 2, 4).  kTopoWords * wpr u32 per topology.
+constexpr int kTopoWords = 32;
 // The chunk list is dealt round-robin into kQueues queues (chunk c goes to
 // queue c % kQueues), each with its own claim counter, so the claims of the
 // persistent waves spread over many addresses instead of serializing on one.
@@ -111,7 +118,7 @@ struct BatchArgs {
   int32_t nservers;
   const int32_t *topo_n;
   const uint8_t *topo_W;  // [T][16][16]
-  const uint32_t *rows;   // [T][16][wpr]
+  const uint32_t *rows;   // [T][kTopoWords][wpr], see kTopoWords
   int32_t ntopo;
   int32_t wpr;
   const uint8_t *split_d;  // [F][k][j], see kSplitTable
@@ -121,6 +128,7 @@ struct BatchArgs {
   int32_t enum_blocks;
   int32_t enum_threads;
   int32_t rows_in_lds;
+  int32_t pair;  // use the k_enumerate variant with pair_level
 };
 
 // Fused path for small batches with one query per server (k_fused).
@@ -150,7 +158,7 @@ hipError_t launch_fused(const FusedArgs &f, hipStream_t s);
 hipError_t launch_batch_front(const BatchArgs &a, hipStream_t s);   // prepare .. expand
 hipError_t launch_enumerate(const BatchArgs &a, hipStream_t s);
 hipError_t launch_finalize(const BatchArgs &a, hipStream_t s);
-int enumerate_occupancy(int wpr, int rows_in_lds, int threads, size_t lds_bytes);
+int enumerate_occupancy(int wpr, int rows_in_lds, int pair, int threads, size_t lds_bytes);
 
 hipError_t launch_valu_probe(uint32_t *out, int blocks, int iters, hipStream_t s);
 int valu_probe_ops_per_iter();

@@ -203,6 +203,39 @@ def test_random_small_graphs_every_shape(ctx, wmax):
     assert ctx.stats()["self_check_failures"] == 0
 
 
+def test_sixteen_vertex_topologies_every_pair_width(ctx):
+    """Contexts with 16-vertex topologies of weights <= 3 run the search
+    variant whose last two positions are scored from per-candidate tables.
+    Busy masks leave 2..13 free vertices, so the last two positions see every
+    candidate count from 2 to 12 (and beyond, for k = 2 on 14-16 free),
+    under all kinds, both modes and several keys."""
+    rng = np.random.default_rng(1616)
+    topos = [random_topology(rng, 16, 3, 0.7) for _ in range(4)]
+    st, busy, cols = [], [], {key: [] for key in ("server", "kind", "k", "mode", "a", "b")}
+    s = 0
+    for F in list(range(2, 14)) + [14, 16]:
+        for rep in range(3):
+            t = int(rng.integers(0, len(topos)))
+            free = rng.choice(16, size=F, replace=False)
+            st.append(t)
+            busy.append(int(0xFFFF & ~int(np.bitwise_or.reduce(1 << free))))
+            for kind in range(3):
+                for k in range(2, 9):
+                    if k > F or math.perm(F, k) > 2_000_000:
+                        continue
+                    for mode in (0, 1):
+                        a, b = [(1, 1), (1, 0), (0, 1), (7, 1024)][int(rng.integers(0, 4))]
+                        for key, v in zip(cols, (s, kind, k, mode, a, b)):
+                            cols[key].append(v)
+            s += 1
+    q = synth.make_queries(cols["server"], cols["kind"], cols["k"], cols["mode"], 0, cols["a"], cols["b"])
+    wl = synth.Workload("sixteen", topos, np.array(st, np.int32), np.array(busy, np.uint32), q)
+    got = run_gpu(ctx, wl)
+    ref = oracle.run_workload(wl, NTHREADS)
+    assert_same(got, ref, wl.queries["k"], "sixteen")
+    assert ctx.stats()["self_check_failures"] == 0
+
+
 def test_edge_cases(ctx):
     W16 = np.full((16, 16), 255, np.uint8)
     np.fill_diagonal(W16, 0)
