@@ -116,10 +116,11 @@ void fill_args(mapa_ctx *c, const Workspace &w, BatchArgs &a) {
   const int threads = c->tuning.threads_per_block;
   const size_t lds_bytes = (size_t)a.ntopo * kTopoWords * c->wpr * sizeof(uint32_t);
   a.rows_in_lds = lds_bytes <= 48 * 1024 ? 1 : 0;
-  // the pair_level variant pays for its registers only when the last two
-  // positions have many candidates: topologies of 10 or more vertices
+  // widest pair_level of the k_enumerate variant: the wider, the more
+  // registers (fewer waves per SIMD), so up to 12 free vertices only where
+  // topologies have 10 or more vertices (measured: 8 is best below that)
   const int max_n = c->topo_n.empty() ? 0 : *std::max_element(c->topo_n.begin(), c->topo_n.end());
-  a.pair = (c->wpr == 1 && max_n >= 10) ? 1 : 0;
+  a.pair = c->wpr != 1 ? 0 : max_n >= 10 ? 12 : 8;
   int per_cu = c->tuning.blocks_per_cu;
   if (per_cu <= 0) {
     // the occupancy query costs microseconds: ask once per launch shape

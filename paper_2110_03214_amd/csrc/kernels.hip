@@ -553,23 +553,78 @@ __device__ __forceinline__ void pair_level(LaneState &s, uint32_t rest, uint32_t
   }
 }
 
-// pair_level for N = 2 .. 12 free vertices at the last two positions (rows of
-// one word); other shapes take the general per-level loops.
-template <int KIND>
+// pair_level for N = 2 .. PAIRN free vertices at the last two positions (rows
+// of one word); other shapes take the general per-level loops.
+template <int KIND, int PAIRN>
 __device__ __forceinline__ bool pair_dispatch(LaneState &s, uint32_t rest, uint32_t code, int kp,
                                               int p, uint32_t prev, int mu) {
   switch (mu) {
-    case 2: pair_level<1, KIND>(s, rest, code, kp, p, prev); return true;
-    case 3: pair_level<2, KIND>(s, rest, code, kp, p, prev); return true;
-    case 4: pair_level<3, KIND>(s, rest, code, kp, p, prev); return true;
-    case 5: pair_level<4, KIND>(s, rest, code, kp, p, prev); return true;
-    case 6: pair_level<5, KIND>(s, rest, code, kp, p, prev); return true;
-    case 7: pair_level<6, KIND>(s, rest, code, kp, p, prev); return true;
-    case 8: pair_level<7, KIND>(s, rest, code, kp, p, prev); return true;
-    case 9: pair_level<8, KIND>(s, rest, code, kp, p, prev); return true;
-    case 10: pair_level<9, KIND>(s, rest, code, kp, p, prev); return true;
-    case 11: pair_level<10, KIND>(s, rest, code, kp, p, prev); return true;
-    case 12: pair_level<11, KIND>(s, rest, code, kp, p, prev); return true;
+    case 2:
+      if constexpr (PAIRN >= 2) {
+        pair_level<1, KIND>(s, rest, code, kp, p, prev);
+        return true;
+      }
+      return false;
+    case 3:
+      if constexpr (PAIRN >= 3) {
+        pair_level<2, KIND>(s, rest, code, kp, p, prev);
+        return true;
+      }
+      return false;
+    case 4:
+      if constexpr (PAIRN >= 4) {
+        pair_level<3, KIND>(s, rest, code, kp, p, prev);
+        return true;
+      }
+      return false;
+    case 5:
+      if constexpr (PAIRN >= 5) {
+        pair_level<4, KIND>(s, rest, code, kp, p, prev);
+        return true;
+      }
+      return false;
+    case 6:
+      if constexpr (PAIRN >= 6) {
+        pair_level<5, KIND>(s, rest, code, kp, p, prev);
+        return true;
+      }
+      return false;
+    case 7:
+      if constexpr (PAIRN >= 7) {
+        pair_level<6, KIND>(s, rest, code, kp, p, prev);
+        return true;
+      }
+      return false;
+    case 8:
+      if constexpr (PAIRN >= 8) {
+        pair_level<7, KIND>(s, rest, code, kp, p, prev);
+        return true;
+      }
+      return false;
+    case 9:
+      if constexpr (PAIRN >= 9) {
+        pair_level<8, KIND>(s, rest, code, kp, p, prev);
+        return true;
+      }
+      return false;
+    case 10:
+      if constexpr (PAIRN >= 10) {
+        pair_level<9, KIND>(s, rest, code, kp, p, prev);
+        return true;
+      }
+      return false;
+    case 11:
+      if constexpr (PAIRN >= 11) {
+        pair_level<10, KIND>(s, rest, code, kp, p, prev);
+        return true;
+      }
+      return false;
+    case 12:
+      if constexpr (PAIRN >= 12) {
+        pair_level<11, KIND>(s, rest, code, kp, p, prev);
+        return true;
+      }
+      return false;
     default: return false;
   }
 }
@@ -588,7 +643,7 @@ __device__ __forceinline__ bool pair_dispatch(LaneState &s, uint32_t rest, uint3
 // ((key + 1) << 4) | (15 - c), so one max() picks the largest key and, among
 // equal keys, the smallest vertex; the node then replaces the lane's best only
 // on a strictly larger key (leaves arrive in lexicographic order).
-template <int L, int WPR, bool LINKED, int KIND, bool PAIR>
+template <int L, int WPR, bool LINKED, int KIND, int PAIR>
 __device__ __forceinline__ void level(LaneState &s, int kind, uint32_t rest, uint32_t code,
                                       int kp, int p, uint32_t prev, int mu, int Lrun) {
   if constexpr (L > 1) {
@@ -597,8 +652,8 @@ __device__ __forceinline__ void level(LaneState &s, int kind, uint32_t rest, uin
       return;
     }
   }
-  if constexpr (PAIR && L == 2 && !LINKED && KIND >= 0 && WPR == 1) {
-    if (pair_dispatch<KIND>(s, rest, code, kp, p, prev, mu)) return;
+  if constexpr (PAIR > 0 && L == 2 && !LINKED && KIND >= 0 && WPR == 1) {
+    if (pair_dispatch<KIND, PAIR>(s, rest, code, kp, p, prev, mu)) return;
   }
   uint32_t nbm, cand;
   node_masks<WPR, LINKED, L == 1, KIND>(s, kind, rest, code, p, prev, nbm, cand);
@@ -637,7 +692,7 @@ __device__ __forceinline__ void level(LaneState &s, int kind, uint32_t rest, uin
   }
 }
 
-template <int WPR, bool LINKED, int KIND, bool PAIR>
+template <int WPR, bool LINKED, int KIND, int PAIR>
 __device__ __forceinline__ void expand(LaneState &s, int kind, int L, uint32_t rest,
                                        uint32_t code, int kp, int d, uint32_t prev, int mu) {
   if (L > 0) level<kMaxK, WPR, LINKED, KIND, PAIR>(s, kind, rest, code, kp, d, prev, mu, L);
@@ -648,7 +703,7 @@ __device__ __forceinline__ void expand(LaneState &s, int kind, int L, uint32_t r
 // the item's match count and its best as one u64 (key high, inverted
 // lexicographic mapping code low, so max() takes the largest key and then
 // the smallest mapping; 0: no match).  trow: the topology's rows.
-template <int WPR, bool PAIR>
+template <int WPR, int PAIR>
 __device__ __forceinline__ void item_search(const Plan *pp, const uint32_t *trow, uint32_t x,
                                             unsigned long long &cnt_out,
                                             unsigned long long &best_out) {
@@ -726,7 +781,7 @@ __device__ __forceinline__ void item_search(const Plan *pp, const uint32_t *trow
   best_out = best;
 }
 
-template <int WPR, bool PAIR>
+template <int WPR, int PAIR>
 __device__ __forceinline__ void run_item(const BatchArgs &a, const uint32_t *rows, uint2 it) {
   const int lane = threadIdx.x & 63;
   const bool valid = it.x != kInvalidItem;
@@ -766,7 +821,7 @@ __device__ __forceinline__ void run_item(const BatchArgs &a, const uint32_t *row
   }
 }
 
-template <int WPR, bool PAIR>
+template <int WPR, int PAIR>
 __device__ __forceinline__ void chunk_loop(const BatchArgs &a, const uint32_t *rows) {
   const int lane = threadIdx.x & 63;
   const uint32_t nchunks = *(volatile const uint32_t *)&a.ctr->total_chunks;
@@ -799,10 +854,10 @@ __device__ __forceinline__ void chunk_loop(const BatchArgs &a, const uint32_t *r
   }
 }
 
-// PAIR: the last two positions of one-word-row topologies go through
-// pair_level (faster per match, more registers, so fewer waves per SIMD);
-// taken for contexts with topologies of 10 or more vertices.
-template <int WPR, bool ROWS_LDS, bool PAIR>
+// PAIR > 0: the last two positions of one-word-row topologies with up to PAIR
+// free vertices go through pair_level (faster per match, more registers, so
+// fewer waves per SIMD).
+template <int WPR, bool ROWS_LDS, int PAIR>
 __global__ __launch_bounds__(256) void k_enumerate(BatchArgs a) {
   if constexpr (ROWS_LDS) {
     extern __shared__ uint32_t s_rows[];
@@ -942,7 +997,7 @@ __global__ __launch_bounds__(256) void k_fused(FusedArgs f) {
   for (uint32_t base = (uint32_t)j * blockDim.x; base < nitems; base += span) {
     const uint32_t x = base + (uint32_t)tid;
     unsigned long long c1, b1;
-    item_search<WPR, false>(x < nitems ? &s_plan : nullptr, s_rows, x, c1, b1);
+    item_search<WPR, 0>(x < nitems ? &s_plan : nullptr, s_rows, x, c1, b1);
     cnt += c1;
     best = b1 > best ? b1 : best;
   }
@@ -1096,7 +1151,7 @@ hipError_t launch_batch_front(const BatchArgs &a, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int WPR, bool LDS, bool PAIR>
+template <int WPR, bool LDS, int PAIR>
 static hipError_t launch_enum_t(const BatchArgs &a, hipStream_t s) {
   const size_t lds = LDS ? (size_t)a.ntopo * kTopoWords * WPR * sizeof(uint32_t) : 0;
   hipLaunchKernelGGL((k_enumerate<WPR, LDS, PAIR>), dim3(a.enum_blocks), dim3(a.enum_threads), lds, s,
@@ -1108,14 +1163,15 @@ hipError_t launch_enumerate(const BatchArgs &a, hipStream_t s) {
   const bool lds = a.rows_in_lds != 0;
   switch (a.wpr) {
     case 1:
-      if (a.pair) return lds ? launch_enum_t<1, true, true>(a, s) : launch_enum_t<1, false, true>(a, s);
-      return lds ? launch_enum_t<1, true, false>(a, s) : launch_enum_t<1, false, false>(a, s);
-    case 2: return lds ? launch_enum_t<2, true, false>(a, s) : launch_enum_t<2, false, false>(a, s);
-    default: return lds ? launch_enum_t<4, true, false>(a, s) : launch_enum_t<4, false, false>(a, s);
+      if (a.pair >= 12) return lds ? launch_enum_t<1, true, 12>(a, s) : launch_enum_t<1, false, 12>(a, s);
+      if (a.pair >= 8) return lds ? launch_enum_t<1, true, 8>(a, s) : launch_enum_t<1, false, 8>(a, s);
+      return lds ? launch_enum_t<1, true, 0>(a, s) : launch_enum_t<1, false, 0>(a, s);
+    case 2: return lds ? launch_enum_t<2, true, 0>(a, s) : launch_enum_t<2, false, 0>(a, s);
+    default: return lds ? launch_enum_t<4, true, 0>(a, s) : launch_enum_t<4, false, 0>(a, s);
   }
 }
 
-template <int WPR, bool LDS, bool PAIR>
+template <int WPR, bool LDS, int PAIR>
 static int occ_t(int threads, size_t lds) {
   int nb = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_enumerate<WPR, LDS, PAIR>, threads, lds) !=
@@ -1128,10 +1184,11 @@ int enumerate_occupancy(int wpr, int rows_in_lds, int pair, int threads, size_t 
   const bool l = rows_in_lds != 0;
   switch (wpr) {
     case 1:
-      if (pair) return l ? occ_t<1, true, true>(threads, lds_bytes) : occ_t<1, false, true>(threads, 0);
-      return l ? occ_t<1, true, false>(threads, lds_bytes) : occ_t<1, false, false>(threads, 0);
-    case 2: return l ? occ_t<2, true, false>(threads, lds_bytes) : occ_t<2, false, false>(threads, 0);
-    default: return l ? occ_t<4, true, false>(threads, lds_bytes) : occ_t<4, false, false>(threads, 0);
+      if (pair >= 12) return l ? occ_t<1, true, 12>(threads, lds_bytes) : occ_t<1, false, 12>(threads, 0);
+      if (pair >= 8) return l ? occ_t<1, true, 8>(threads, lds_bytes) : occ_t<1, false, 8>(threads, 0);
+      return l ? occ_t<1, true, 0>(threads, lds_bytes) : occ_t<1, false, 0>(threads, 0);
+    case 2: return l ? occ_t<2, true, 0>(threads, lds_bytes) : occ_t<2, false, 0>(threads, 0);
+    default: return l ? occ_t<4, true, 0>(threads, lds_bytes) : occ_t<4, false, 0>(threads, 0);
   }
 }
 

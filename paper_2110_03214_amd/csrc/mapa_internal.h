@@ -128,7 +128,7 @@ struct BatchArgs {
   int32_t enum_blocks;
   int32_t enum_threads;
   int32_t rows_in_lds;
-  int32_t pair;  // use the k_enumerate variant with pair_level
+  int32_t pair;  // k_enumerate variant: widest pair_level (0: none)
 };
 
 // Fused path for small batches with one query per server (k_fused).
