@@ -858,7 +858,9 @@ __device__ __forceinline__ void chunk_loop(const BatchArgs &a, const uint32_t *r
 // free vertices go through pair_level (faster per match, more registers, so
 // fewer waves per SIMD).
 template <int WPR, bool ROWS_LDS, int PAIR>
-__global__ __launch_bounds__(256) void k_enumerate(BatchArgs a) {
+// At most 128 VGPRs, so four waves share each SIMD: the values this forces
+// to scratch belong to the outer levels of the search, which run rarely.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_enumerate(BatchArgs a) {
   if constexpr (ROWS_LDS) {
     extern __shared__ uint32_t s_rows[];
     const int words = a.ntopo * kTopoWords * WPR;
