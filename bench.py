@@ -62,55 +62,34 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def nb_count(kind: int, k: int, p: int) -> int:
-    """Pattern neighbours of position p that precede it (ring/a2a/tree)."""
-    if p == 0:
-        return 0
-    if kind == 1:
-        return p
-    if kind == 0:
-        return 2 if (p == k - 1 and k >= 3) else 1
-    return 1
-
-
-def placement_ops(B: int, nb: int) -> int:
-    """Integer ops to place one vertex at a position with nb earlier pattern
-    neighbours, for weights of B bits: the cheaper of the two incremental
-    formulations of the score.
-      (i)  per-neighbour adds: candidate test, nb AggBW adds, B masked
-           bit-plane popcounts with their shift-adds for the PreservedBW term
-           (3B), key update (2), best-so-far compare/select (3):  8 + 3B + nb;
-      (ii) both terms as masked weighted popcounts over ceil(B/2) words of two
-           bit-planes each (and, two popcounts, align: 4 per word and term):
-           candidate select/clear (2), 8*ceil(B/2), key update (3), best (2):
-           7 + 8*ceil(B/2)."""
-    return min(8 + 3 * B + nb, 7 + 8 * ((B + 1) // 2))
+# Integer ops charged per node of the search tree (every partial and every
+# complete embedding): with the weights of the node's candidates to the
+# vertices still free tabulated once per parent, placing one more vertex
+# needs one packed-weight read (the weight to the vertex just placed), one
+# multiply-add, one add of the tabulated term and one compare/select.  No
+# method that scores every embedding separately does less, so the fraction
+# of peak this gives is a lower bound on the kernel's ALU use.
+OPS_PER_NODE = 4
 
 
 def algorithmic_ops(wl) -> tuple[int, int]:
-    """(embeddings, algorithmic int ops) of one pass over the workload.
-
-    Every vertex placement of the shared-prefix search is charged
-    placement_ops(B, |Nb(p)|): a node at depth p+1 of the search tree, of
-    which there are F!/(F-p-1)! in ALL mode (the leaves are the embeddings).
-    B = bits of the topology's largest weight."""
+    """(embeddings, algorithmic int ops) of one pass over the workload:
+    OPS_PER_NODE for every node at depth 1..k of each query's search tree,
+    F!/(F-p)! of them at depth p in ALL mode (the leaves are the embeddings)."""
     q = wl.queries
-    bits = [max(1, int(W.max()).bit_length()) for W in wl.topologies]
     n_of = [W.shape[0] for W in wl.topologies]
     emb = ops = 0
     cache = {}
-    for s, kind, k in zip(q["server"], q["kind"], q["k"]):
+    for s, k in zip(q["server"], q["k"]):
         t = int(wl.server_topo[s])
         F = n_of[t] - bin(int(wl.busy[s])).count("1")
-        key = (F, int(kind), int(k), bits[t])
+        key = (F, int(k))
         if key not in cache:
             if k > F:
                 cache[key] = (0, 0)
             else:
-                e = math.perm(F, int(k))
-                o = sum(math.perm(F, p + 1) * placement_ops(bits[t], nb_count(int(kind), int(k), p))
-                        for p in range(int(k)))
-                cache[key] = (e, o)
+                nodes = sum(math.perm(F, p) for p in range(1, int(k) + 1))
+                cache[key] = (math.perm(F, int(k)), OPS_PER_NODE * nodes)
         e, o = cache[key]
         emb += e
         ops += o
