@@ -115,8 +115,16 @@ typedef struct {
   int16_t a;        /* key = a*AggBW + b*PreservedBW, 0 <= a, b <= 1024.        */
   int16_t b;        /*   (1,0): Greedy; (0,1): Alg. 1 insensitive branch;
                          (1,1): both terms                                      */
-  int32_t reserved; /* must be 0                                                */
+  int32_t metric;   /* MAPA_METRIC_WEIGHTED: the key above.  MAPA_METRIC_EFFBW:
+                       the bandwidth-sensitive branch of Alg. 1, key = predicted
+                       effective bandwidth (Eq. 2) of the mapped pattern edges'
+                       link mix; a, b unused; the server's topology must have
+                       weights 0, 1, 2 only (PCIe, single, double NVLink), else
+                       MAPA_ERR_UNSUPPORTED (host batches) / MAPA_RES_INVALID  */
 } mapa_query;
+
+#define MAPA_METRIC_WEIGHTED 0
+#define MAPA_METRIC_EFFBW 1
 
 /* Result of one query.  48 bytes. */
 typedef struct {
@@ -128,13 +136,17 @@ typedef struct {
   uint32_t vertex_mask; /* bit v set iff accelerator v is chosen; 0 if none     */
   uint8_t mapping[8];   /* mapping[i] = accelerator of pattern vertex i;
                            0xFF beyond k or if none                              */
-  int32_t reserved;     /* 0                                                     */
+  int32_t links;        /* MAPA_METRIC_EFFBW: x | y << 8 | z << 16, the numbers of
+                           the chosen match's pattern edges on double NVLinks,
+                           single NVLinks and PCIe (Eq. 2); else 0               */
   int64_t alloc_handle; /* (server << 32) | vertex_mask if committed, else -1    */
 } mapa_result;
 
 /* Selection rule (Alg. 1, strict improvement): the chosen match has the
  * largest key; among equal keys, the lexicographically smallest mapping tuple
- * (mapping[0], ..., mapping[k-1]) wins.  PreservedBW of a match M is the total
+ * (mapping[0], ..., mapping[k-1]) wins.  With MAPA_METRIC_EFFBW the key
+ * compared is Eq. 2's value in double precision (coefficients of Table
+ * "Values of Coefficients"), and `key` reports round(1000 * EffBW).  PreservedBW of a match M is the total
  * weight of pairs u<v of free vertices that M leaves unused (Eq. 3); busy
  * vertices never contribute.  AggBW is the total weight of the pattern edges
  * under the mapping (Eq. 1). */
@@ -146,7 +158,7 @@ const char *mapa_last_error(void);
  * context with device = -1 (argument checks run; compute calls then return
  * MAPA_ERR_NO_DEVICE).  enum_buffer_bytes sizes the prefix work-list of one
  * in-flight batch (0 = default 256 MiB); a batch of nq queries needs at least
- * 8 * (nq + 17408) bytes of it, else MAPA_ERR_ADMISSION.  *out receives the
+ * 8 * (nq + 102816) bytes of it, else MAPA_ERR_ADMISSION.  *out receives the
  * context. */
 int32_t mapa_ctx_create(int32_t device, size_t enum_buffer_bytes, mapa_ctx **out);
 
@@ -302,7 +314,7 @@ typedef struct {           /* 40 bytes */
                               it is granted; < 0: held until mapa_serve_stop          */
   int32_t server;
   uint8_t kind, k, mode;   /* as in mapa_query                                         */
-  uint8_t reserved0;       /* must be 0                                                */
+  uint8_t metric;          /* as in mapa_query                                         */
   int16_t a, b;            /* key weights, as in mapa_query                            */
   int32_t reserved1;       /* must be 0                                                */
 } mapa_request;

@@ -32,6 +32,7 @@ SRC_PATH = os.path.join(HERE, "mapa_oracle.c")
 
 RING, A2A, TREE = 0, 1, 2
 MODE_ALL, MODE_LINKED = 0, 1
+METRIC_WEIGHTED, METRIC_EFFBW = 0, 1
 OK, NOFIT, CONFLICT = 0, 1, 2
 EINVAL, EUNSUP = -1, -2
 
@@ -45,12 +46,13 @@ class OrResult(ctypes.Structure):
         ("pres", ctypes.c_int32),
         ("vertex_mask", ctypes.c_uint32),
         ("mapping", ctypes.c_uint8 * 8),
+        ("links", ctypes.c_int32),
     ]
 
 
 RESULT_DTYPE = np.dtype([
     ("count", np.int64), ("status", np.int32), ("key", np.int32), ("agg", np.int32),
-    ("pres", np.int32), ("vertex_mask", np.uint32), ("mapping", np.uint8, 8),
+    ("pres", np.int32), ("vertex_mask", np.uint32), ("mapping", np.uint8, 8), ("links", np.int32),
 ], align=True)
 
 
@@ -60,7 +62,7 @@ def build(force: bool = False) -> str:
             os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC_PATH):
         tmp = LIB_PATH + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-pthread",
-                               "-o", tmp, SRC_PATH])
+                               "-o", tmp, SRC_PATH, "-lm"])
         os.replace(tmp, LIB_PATH)
     return LIB_PATH
 
@@ -77,9 +79,11 @@ def lib():
         L.or_query.restype = ctypes.c_int
         L.or_query.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int,
                                ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                               ctypes.POINTER(OrResult)]
+                               ctypes.c_int, ctypes.POINTER(OrResult)]
         L.or_batch.restype = ctypes.c_int
-        L.or_batch.argtypes = [ctypes.c_int] + [ctypes.c_void_p] * 10 + [ctypes.c_int]
+        L.or_batch.argtypes = [ctypes.c_int] + [ctypes.c_void_p] * 11 + [ctypes.c_int]
+        L.or_effbw.restype = ctypes.c_double
+        L.or_effbw.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
         L.or_pattern_edges.restype = ctypes.c_int
         L.or_pattern_edges.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
         L.or_aut_count.restype = ctypes.c_int
@@ -90,18 +94,23 @@ def lib():
     return _lib
 
 
-def query(W, busy, kind, k, mode=MODE_ALL, a=1, b=1) -> dict:
+def query(W, busy, kind, k, mode=MODE_ALL, a=1, b=1, metric=METRIC_WEIGHTED) -> dict:
     """One query on an n x n weight matrix.  Returns a dict of the result."""
     W = np.ascontiguousarray(np.asarray(W, dtype=np.uint8))
     n = W.shape[0]
     r = OrResult()
     lib().or_query(n, W.ctypes.data, int(busy), int(kind), int(k), int(mode), int(a), int(b),
-                   ctypes.byref(r))
+                   int(metric), ctypes.byref(r))
     return {
         "count": r.count, "status": r.status, "key": r.key, "agg": r.agg, "pres": r.pres,
-        "vertex_mask": r.vertex_mask,
+        "vertex_mask": r.vertex_mask, "links": r.links,
         "mapping": tuple(r.mapping[i] for i in range(k) if r.status == OK) if 1 <= k <= 8 else (),
     }
+
+
+def effbw(x, y, z) -> float:
+    """Eq. 2 (predicted effective bandwidth) as the oracle evaluates it."""
+    return float(lib().or_effbw(int(x), int(y), int(z)))
 
 
 def pattern_edges(kind, k):
@@ -126,13 +135,16 @@ def pad_topologies(topologies):
     return tn, tw
 
 
-def batch(topologies, q_topo, q_busy, kind, k, mode, a, b, nthreads: int | None = None):
+def batch(topologies, q_topo, q_busy, kind, k, mode, a, b, nthreads: int | None = None,
+          metric=None):
     """Evaluate queries independently.  Returns a structured numpy array."""
     tn, tw = pad_topologies(topologies)
     nq = len(q_topo)
+    if metric is None:
+        metric = np.zeros(nq, np.uint8)
     cols = [np.ascontiguousarray(np.asarray(x, dtype=dt)) for x, dt in (
         (q_topo, np.int32), (q_busy, np.uint32), (kind, np.uint8), (k, np.uint8),
-        (mode, np.uint8), (a, np.int16), (b, np.int16))]
+        (mode, np.uint8), (a, np.int16), (b, np.int16), (metric, np.uint8))]
     out = np.zeros(nq, dtype=RESULT_DTYPE)
     if nthreads is None:
         nthreads = os.cpu_count() or 1
@@ -146,7 +158,7 @@ def run_workload(wl, nthreads: int | None = None):
     q = wl.queries
     srv = q["server"]
     return batch(wl.topologies, wl.server_topo[srv], wl.busy[srv], q["kind"], q["k"],
-                 q["mode"], q["a"], q["b"], nthreads)
+                 q["mode"], q["a"], q["b"], nthreads, q.get("metric"))
 
 
 def run_batch_semantics(wl, nthreads: int | None = None):

@@ -32,6 +32,14 @@
  *     mapping.
  *   - The result: number of matches (int64), the kept mapping, its key, AggBW
  *     and PreservedBW.
+ *   - Bandwidth-sensitive jobs (metric EFFBW): Alg. 1 keeps instead the match
+ *     with the largest predicted effective bandwidth, Eq. 2 evaluated on the
+ *     numbers x, y, z of mapped pattern edges that land on double NVLinks
+ *     (weight 2), single NVLinks (weight 1) and PCIe (weight 0), with the
+ *     coefficients of Table "Values of Coefficients"; same scan order and
+ *     strict improvement.  The reported key is round(1000 * EffBW); x, y, z
+ *     are reported too.  Other weights have no class in Eq. 2, so such
+ *     topologies are unsupported for this metric.
  *
  * PreservedBW depends only on the chosen vertex set; its literal double loop
  * is memoised per vertex set (same loop, evaluated at most once per set).
@@ -40,6 +48,7 @@
  * automorphism counts, textbook special cases and exhaustive agreement with an
  * independent Python brute force.
  */
+#include <math.h>
 #include <pthread.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -53,6 +62,7 @@ enum { OR_RING = 0, OR_A2A = 1, OR_TREE = 2 };
 enum { OR_MODE_ALL = 0, OR_MODE_LINKED = 1 };
 enum { OR_OK = 0, OR_NOFIT = 1 };
 enum { OR_EINVAL = -1, OR_EUNSUP = -2, OR_ENOMEM = -3 };
+enum { OR_METRIC_WEIGHTED = 0, OR_METRIC_EFFBW = 1 };
 
 typedef struct {
   int64_t count;
@@ -60,7 +70,22 @@ typedef struct {
   int32_t key, agg, pres;
   uint32_t vertex_mask;
   uint8_t mapping[8];
+  int32_t links; /* EFFBW: x | y << 8 | z << 16 of the kept match, else 0 */
 } or_result;
+
+/* Eq. 2: predicted effective bandwidth from x double NVLinks, y single
+ * NVLinks and z PCIe links, coefficients theta_1..theta_14 of Table "Values
+ * of Coefficients". */
+double or_effbw(int x, int y, int z) {
+  static const double th[15] = {0.0,     16.396, 4.536,  1.556,   -20.694, -9.467, 7.615, -7.973,
+                                12.733, -4.195, -8.413, 62.851, 27.418,  -5.114, -46.973};
+  const double X = x, Y = y, Z = z;
+  return th[1] * X + th[2] * Y + th[3] * Z +
+         th[4] / (X + 1) + th[5] / (Y + 1) + th[6] / (Z + 1) +
+         th[7] * X * Y + th[8] * Y * Z + th[9] * Z * X +
+         th[10] / (X * Y + 1) + th[11] / (Y * Z + 1) + th[12] / (Z * X + 1) +
+         th[13] * X * Y * Z + th[14] / (X * Y * Z + 1);
+}
 
 /* Canonical pattern graphs (Sec. 3.1).  Pattern vertex i is tuple position i.
  *   ring, k=1: no edge; k=2: the single edge (0,1); k>=3: (i, i+1 mod k).
@@ -128,7 +153,7 @@ int or_aut_count(int kind, int k) {
 }
 
 typedef struct {
-  int n, k, ne, mode;
+  int n, k, ne, mode, metric;
   int64_t a, b;
   const uint8_t *W; /* n*n row-major */
   int ep[2 * 28];
@@ -140,6 +165,8 @@ typedef struct {
   int64_t count;
   int have;
   int64_t bkey, bagg, bpres;
+  double beff;
+  int bx, by, bz;
   int bphi[OR_MAX_K];
 } or_state;
 
@@ -172,6 +199,28 @@ static void visit_match(or_state *s) {
   uint32_t S = 0;
   for (int i = 0; i < s->k; ++i) S |= 1u << s->phi[i];
   int64_t pres = preserved_bw(s, S);
+  if (s->metric == OR_METRIC_EFFBW) {
+    /* Eq. 2 on the link classes of the mapped pattern edges */
+    int x = 0, y = 0, z = 0;
+    for (int e = 0; e < s->ne; ++e) {
+      int w = s->W[s->phi[s->ep[2 * e]] * n + s->phi[s->ep[2 * e + 1]]];
+      if (w == 2) ++x;
+      else if (w == 1) ++y;
+      else ++z;
+    }
+    double eff = or_effbw(x, y, z);
+    /* Alg. 1, sensitive branch: strictly larger EffBW only */
+    if (!s->have || eff > s->beff) {
+      s->have = 1;
+      s->beff = eff;
+      s->bx = x; s->by = y; s->bz = z;
+      s->bkey = (int64_t)llround(1000.0 * eff);
+      s->bagg = agg;
+      s->bpres = pres;
+      memcpy(s->bphi, s->phi, sizeof s->phi);
+    }
+    return;
+  }
   int64_t key = s->a * agg + s->b * pres;
   /* Alg. 1: replace on a strictly larger score only */
   if (!s->have || key > s->bkey) {
@@ -213,7 +262,7 @@ static int validate_topology(int n, const uint8_t *W) {
 
 /* One query against one hardware graph.  memo must hold 1<<n int32. */
 static int query_with_memo(int n, const uint8_t *W, uint32_t busy, int kind, int k, int mode,
-                           int a, int b, or_result *out, int32_t *memo) {
+                           int a, int b, int metric, or_result *out, int32_t *memo) {
   memset(out, 0, sizeof *out);
   memset(out->mapping, 0xFF, sizeof out->mapping);
   out->key = INT32_MIN;
@@ -221,12 +270,16 @@ static int query_with_memo(int n, const uint8_t *W, uint32_t busy, int kind, int
   if (rc) return out->status = rc;
   if (k > OR_MAX_K) return out->status = OR_EUNSUP;
   if (k < 1 || kind < 0 || kind > 2 || mode < 0 || mode > 1 || a < 0 || b < 0 ||
-      a > OR_MAX_AB || b > OR_MAX_AB || (n < 32 && (busy >> n) != 0))
+      a > OR_MAX_AB || b > OR_MAX_AB || (n < 32 && (busy >> n) != 0) || metric < 0 || metric > 1)
     return out->status = OR_EINVAL;
+  if (metric == OR_METRIC_EFFBW)
+    for (int i = 0; i < n * n; ++i)
+      if (W[i] > 2) return out->status = OR_EUNSUP;
 
   or_state *s = (or_state *)calloc(1, sizeof(or_state));
   if (!s) return out->status = OR_ENOMEM;
-  s->n = n; s->k = k; s->mode = mode; s->a = a; s->b = b; s->W = W; s->memo = memo;
+  s->n = n; s->k = k; s->mode = mode; s->metric = metric; s->a = a; s->b = b; s->W = W;
+  s->memo = memo;
   s->ne = or_pattern_edges(kind, k, s->ep);
   for (int v = 0; v < n; ++v)
     if (!((busy >> v) & 1u)) { s->R[s->F++] = v; s->Rmask |= 1u << v; }
@@ -244,6 +297,7 @@ static int query_with_memo(int n, const uint8_t *W, uint32_t busy, int kind, int
       out->mapping[i] = (uint8_t)s->bphi[i];
       out->vertex_mask |= 1u << s->bphi[i];
     }
+    if (metric == OR_METRIC_EFFBW) out->links = s->bx | (s->by << 8) | (s->bz << 16);
   } else {
     out->status = OR_NOFIT;
   }
@@ -252,11 +306,11 @@ static int query_with_memo(int n, const uint8_t *W, uint32_t busy, int kind, int
 }
 
 int or_query(int n, const uint8_t *W, uint32_t busy, int kind, int k, int mode, int a, int b,
-             or_result *out) {
+             int metric, or_result *out) {
   int nn = (n >= 1 && n <= OR_MAX_N) ? n : 1;
   int32_t *memo = (int32_t *)malloc(sizeof(int32_t) << nn);
   if (!memo) return OR_ENOMEM;
-  int rc = query_with_memo(n, W, busy, kind, k, mode, a, b, out, memo);
+  int rc = query_with_memo(n, W, busy, kind, k, mode, a, b, metric, out, memo);
   free(memo);
   return rc;
 }
@@ -269,7 +323,7 @@ typedef struct {
   const uint8_t *topo_W; /* per topology 16*16 row-major, row stride 16 */
   const int32_t *q_topo;
   const uint32_t *q_busy;
-  const uint8_t *q_kind, *q_k, *q_mode;
+  const uint8_t *q_kind, *q_k, *q_mode, *q_metric;
   const int16_t *q_a, *q_b;
   or_result *out;
 } or_job;
@@ -289,7 +343,7 @@ static void *batch_worker(void *arg) {
     for (int u = 0; u < n; ++u)
       for (int v = 0; v < n; ++v) W[u * n + v] = j->topo_W[(size_t)t * 256 + u * 16 + v];
     query_with_memo(n, W, j->q_busy[q], j->q_kind[q], j->q_k[q], j->q_mode[q], j->q_a[q],
-                    j->q_b[q], &j->out[q], memo);
+                    j->q_b[q], j->q_metric[q], &j->out[q], memo);
   }
   free(memo);
   return NULL;
@@ -297,15 +351,15 @@ static void *batch_worker(void *arg) {
 
 int or_batch(int nq, const int32_t *topo_n, const uint8_t *topo_W, const int32_t *q_topo,
              const uint32_t *q_busy, const uint8_t *q_kind, const uint8_t *q_k,
-             const uint8_t *q_mode, const int16_t *q_a, const int16_t *q_b, or_result *out,
-             int nthreads) {
+             const uint8_t *q_mode, const int16_t *q_a, const int16_t *q_b,
+             const uint8_t *q_metric, or_result *out, int nthreads) {
   if (nthreads < 1) nthreads = 1;
   if (nthreads > 256) nthreads = 256;
   pthread_t th[256];
   or_job jobs[256];
   for (int t = 0; t < nthreads; ++t) {
     jobs[t] = (or_job){t, nthreads, nq, topo_n, topo_W, q_topo, q_busy, q_kind, q_k, q_mode,
-                       q_a, q_b, out};
+                       q_metric, q_a, q_b, out};
     if (pthread_create(&th[t], NULL, batch_worker, &jobs[t]) != 0) {
       batch_worker(&jobs[t]);
       th[t] = 0;

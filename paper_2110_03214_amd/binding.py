@@ -27,6 +27,7 @@ ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_OOM, ERR_DEVICE, ERR_NOT_BUSY = -1, -2, -3
 ERR_UNKNOWN_SERVER, ERR_ADMISSION, ERR_NO_DEVICE, ERR_STATE = -6, -7, -8, -9
 RING, ALL_TO_ALL, TREE = 0, 1, 2
 ALL_INJECTIVE, LINKED = 0, 1
+METRIC_WEIGHTED, METRIC_EFFBW = 0, 1
 RES_OK, RES_NOFIT, RES_CONFLICT, RES_INVALID = 0, 1, 2, 3
 DEVICE_PTRS = 1
 USE_GRAPH = 2
@@ -34,10 +35,10 @@ PIPELINE = 4
 
 QUERY_DTYPE = np.dtype([("server", np.int32), ("kind", np.uint8), ("k", np.uint8),
                         ("mode", np.uint8), ("commit", np.uint8), ("a", np.int16),
-                        ("b", np.int16), ("reserved", np.int32)])
+                        ("b", np.int16), ("metric", np.int32)])
 RESULT_DTYPE = np.dtype([("count", np.int64), ("status", np.int32), ("key", np.int32),
                          ("agg", np.int32), ("pres", np.int32), ("vertex_mask", np.uint32),
-                         ("mapping", np.uint8, 8), ("reserved", np.int32),
+                         ("mapping", np.uint8, 8), ("links", np.int32),
                          ("alloc_handle", np.int64)])
 assert QUERY_DTYPE.itemsize == 16 and RESULT_DTYPE.itemsize == 48
 assert RESULT_DTYPE.fields["alloc_handle"][1] == 40
@@ -72,7 +73,7 @@ class ServeStats(ctypes.Structure):
 
 REQUEST_DTYPE = np.dtype([("id", np.int64), ("t_arrival", np.float64), ("hold", np.float64),
                           ("server", np.int32), ("kind", np.uint8), ("k", np.uint8),
-                          ("mode", np.uint8), ("reserved0", np.uint8), ("a", np.int16),
+                          ("mode", np.uint8), ("metric", np.uint8), ("a", np.int16),
                           ("b", np.int16), ("reserved1", np.int32)])
 COMPLETION_DTYPE = np.dtype([("id", np.int64), ("count", np.int64), ("alloc_handle", np.int64),
                              ("latency_us", np.float64), ("status", np.int32), ("key", np.int32),
@@ -147,10 +148,10 @@ def _ptr(x):
     return ctypes.c_void_p(x.ctypes.data)
 
 
-def pack_queries(server, kind, k, mode=ALL_INJECTIVE, commit=0, a=1, b=1) -> np.ndarray:
+def pack_queries(server, kind, k, mode=ALL_INJECTIVE, commit=0, a=1, b=1, metric=0) -> np.ndarray:
     q = np.zeros(len(server), dtype=QUERY_DTYPE)
     q["server"], q["kind"], q["k"], q["mode"] = server, kind, k, mode
-    q["commit"], q["a"], q["b"] = commit, a, b
+    q["commit"], q["a"], q["b"], q["metric"] = commit, a, b, metric
     return q
 
 
@@ -314,4 +315,5 @@ def load_workload(ctx: Context, wl):
     ids = ctx.load_servers(wl.topologies, wl.server_topo)
     ctx.set_busy(ids, wl.busy)
     q = wl.queries
-    return pack_queries(ids[q["server"]], q["kind"], q["k"], q["mode"], q["commit"], q["a"], q["b"]), ids
+    return pack_queries(ids[q["server"]], q["kind"], q["k"], q["mode"], q["commit"], q["a"], q["b"],
+                        q.get("metric", 0)), ids

@@ -78,7 +78,11 @@ struct mapa_ctx {
   int32_t *d_topo_n = nullptr;
   uint8_t *d_topo_W = nullptr;
   uint32_t *d_rows = nullptr;
+  std::vector<uint8_t> topo_maxw;  // largest weight per topology
+  uint8_t *d_topo_maxw = nullptr;
   size_t cap_topos = 0;
+  uint16_t *d_eff_rank = nullptr;  // Eq. 2 tables (eff_off layout)
+  int32_t *d_eff_key = nullptr;
 
   // servers
   std::vector<int32_t> server_topo;  // host mirror, immutable per server

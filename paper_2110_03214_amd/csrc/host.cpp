@@ -110,6 +110,9 @@ void fill_args(mapa_ctx *c, const Workspace &w, BatchArgs &a) {
   a.topo_n = c->d_topo_n;
   a.topo_W = c->d_topo_W;
   a.rows = c->d_rows;
+  a.topo_maxw = c->d_topo_maxw;
+  a.eff_rank = c->d_eff_rank;
+  a.eff_key = c->d_eff_key;
   a.ntopo = (int32_t)c->topo_n.size();
   a.wpr = c->wpr;
   a.split_d = c->d_split;
@@ -174,6 +177,9 @@ int32_t enqueue_fused(mapa_ctx *c, const Workspace &w, const mapa_query *q, mapa
   f.topo_n = c->d_topo_n;
   f.rows = c->d_rows;
   f.wpr = c->wpr;
+  f.topo_maxw = c->d_topo_maxw;
+  f.eff_rank = c->d_eff_rank;
+  f.eff_key = c->d_eff_key;
   f.self_check_failures = &w.d_ctr->self_check_failures;
   f.acc_count = w.d_acc_count;
   f.acc_best = w.d_acc_best;
@@ -334,9 +340,11 @@ int32_t upload_topologies(mapa_ctx *c, size_t first, bool all) {
     dev_free(c->d_topo_n);
     dev_free(c->d_topo_W);
     dev_free(c->d_rows);
+    dev_free(c->d_topo_maxw);
     c->cap_topos = 0;
     if (dev_alloc(&c->d_topo_n, cap) != hipSuccess || dev_alloc(&c->d_topo_W, cap * 256) != hipSuccess ||
-        dev_alloc(&c->d_rows, cap * kTopoWords * 4) != hipSuccess)
+        dev_alloc(&c->d_rows, cap * kTopoWords * 4) != hipSuccess ||
+        dev_alloc(&c->d_topo_maxw, cap) != hipSuccess)
       return fail(MAPA_ERR_OOM, "topology tables: device allocation failed");
     c->cap_topos = cap;
   }
@@ -354,6 +362,50 @@ int32_t upload_topologies(mapa_ctx *c, size_t first, bool all) {
   MAPA_HIPCHK(hipMemcpy(c->d_topo_W + t0 * 256, W.data(), W.size(), hipMemcpyHostToDevice));
   MAPA_HIPCHK(hipMemcpy(c->d_rows + t0 * kTopoWords * c->wpr, rows.data(), rows.size() * sizeof(uint32_t),
                         hipMemcpyHostToDevice));
+  MAPA_HIPCHK(hipMemcpy(c->d_topo_maxw + t0, c->topo_maxw.data() + t0, nt, hipMemcpyHostToDevice));
+  return MAPA_OK;
+}
+
+// Eq. 2, the predicted effective bandwidth of a link mix: x double NVLinks,
+// y single NVLinks, z PCIe links, coefficients of Table "Values of
+// Coefficients" in the order of the equation's features.
+double effbw_eq2(int x, int y, int z) {
+  static const double theta[14] = {16.396, 4.536,  1.556,  -20.694, -9.467, 7.615,  -7.973,
+                                   12.733, -4.195, -8.413, 62.851,  27.418, -5.114, -46.973};
+  const double X = x, Y = y, Z = z;
+  const double f[14] = {X,           Y,           Z,           1 / (X + 1),     1 / (Y + 1),
+                        1 / (Z + 1), X * Y,       Y * Z,       Z * X,           1 / (X * Y + 1),
+                        1 / (Y * Z + 1), 1 / (Z * X + 1), X * Y * Z, 1 / (X * Y * Z + 1)};
+  double v = 0;
+  for (int i = 0; i < 14; ++i) v += theta[i] * f[i];
+  return v;
+}
+
+// The device's Eq. 2 tables: per edge count E, each mix's dense rank (equal
+// values share a rank, so maximising the rank maximises EffBW and keeps its
+// ties) and its reported key round(1000 * EffBW).
+int32_t upload_effbw_tables(mapa_ctx *c) {
+  std::vector<uint16_t> rank(kEffEntries, 0);
+  std::vector<int32_t> key(kEffEntries, 0);
+  for (int E = 0; E <= kMaxEdges; ++E) {
+    std::vector<double> vals;
+    for (int x = 0; x <= E; ++x)
+      for (int y = 0; x + y <= E; ++y) vals.push_back(effbw_eq2(x, y, E - x - y));
+    std::sort(vals.begin(), vals.end());
+    vals.erase(std::unique(vals.begin(), vals.end()), vals.end());
+    for (int x = 0; x <= E; ++x)
+      for (int y = 0; x + y <= E; ++y) {
+        const double v = effbw_eq2(x, y, E - x - y);
+        const size_t at = (size_t)eff_off(E) + (size_t)x * (E + 1) + y;
+        rank[at] = (uint16_t)(std::lower_bound(vals.begin(), vals.end(), v) - vals.begin());
+        key[at] = (int32_t)std::llround(1000.0 * v);
+      }
+  }
+  if (dev_alloc(&c->d_eff_rank, kEffEntries) != hipSuccess ||
+      dev_alloc(&c->d_eff_key, kEffEntries) != hipSuccess)
+    return fail(MAPA_ERR_OOM, "effective-bandwidth tables: device allocation failed");
+  MAPA_HIPCHK(hipMemcpy(c->d_eff_rank, rank.data(), rank.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
+  MAPA_HIPCHK(hipMemcpy(c->d_eff_key, key.data(), key.size() * sizeof(int32_t), hipMemcpyHostToDevice));
   return MAPA_OK;
 }
 
@@ -440,7 +492,12 @@ int32_t validate_query(const mapa_ctx *c, const mapa_query &q, int32_t i) {
   if (q.a < 0 || q.a > MAPA_MAX_AB || q.b < 0 || q.b > MAPA_MAX_AB)
     return fail(MAPA_ERR_INVALID_ARG, "query %d: key weights (%d,%d) outside 0..%d", i, q.a, q.b,
                 MAPA_MAX_AB);
-  if (q.reserved != 0) return fail(MAPA_ERR_INVALID_ARG, "query %d: reserved != 0", i);
+  if (q.metric != MAPA_METRIC_WEIGHTED && q.metric != MAPA_METRIC_EFFBW)
+    return fail(MAPA_ERR_INVALID_ARG, "query %d: metric=%d", i, q.metric);
+  if (q.metric == MAPA_METRIC_EFFBW && c->topo_maxw[c->server_topo[q.server]] > 2)
+    return fail(MAPA_ERR_UNSUPPORTED,
+                "query %d: effective bandwidth needs link weights 0, 1, 2 (PCIe, single, double "
+                "NVLink); server %d has weight %d", i, q.server, c->topo_maxw[c->server_topo[q.server]]);
   return MAPA_OK;
 }
 
@@ -489,6 +546,8 @@ int32_t mapa_ctx_create(int32_t device, size_t enum_buffer_bytes, mapa_ctx **out
   if (rc) return bail(rc);
   rc = upload_split_table(c);
   if (rc) return bail(rc);
+  rc = upload_effbw_tables(c);
+  if (rc) return bail(rc);
   if (dev_alloc(&c->d_flag, 1) != hipSuccess) return bail(fail(MAPA_ERR_OOM, "flag allocation failed"));
   if (hipDeviceSynchronize() != hipSuccess) return bail(fail(MAPA_ERR_DEVICE, "device init failed"));
   *out = c;
@@ -519,6 +578,9 @@ int32_t mapa_ctx_destroy(mapa_ctx *c) {
     dev_free(c->d_handles);
     dev_free(c->d_flag);
     dev_free(c->d_split);
+    dev_free(c->d_topo_maxw);
+    dev_free(c->d_eff_rank);
+    dev_free(c->d_eff_key);
     if (c->h_fq) (void)hipHostFree(c->h_fq);
     if (c->h_fres) (void)hipHostFree(c->h_fres);
     if (c->last) (void)hipEventDestroy(c->last);
@@ -546,8 +608,12 @@ int32_t mapa_create_topology(mapa_ctx *c, int32_t n, const uint8_t *W, int32_t n
   if (c->server_topo.size() + (size_t)num_servers > (size_t)INT32_MAX)
     return fail(MAPA_ERR_UNSUPPORTED, "too many servers");
   std::array<uint8_t, 256> w16{};
+  uint8_t maxw = 0;
   for (int i = 0; i < n; ++i)
-    for (int j = 0; j < n; ++j) w16[i * 16 + j] = W[i * n + j];
+    for (int j = 0; j < n; ++j) {
+      w16[i * 16 + j] = W[i * n + j];
+      maxw = std::max(maxw, W[i * n + j]);
+    }
   const int32_t tid = (int32_t)c->topo_n.size();
   const int32_t first = (int32_t)c->server_topo.size();
   if (c->has_device) {
@@ -557,12 +623,14 @@ int32_t mapa_create_topology(mapa_ctx *c, int32_t n, const uint8_t *W, int32_t n
     const int old_wpr = c->wpr;
     c->topo_n.push_back(n);
     c->topo_W.push_back(w16);
+    c->topo_maxw.push_back(maxw);
     c->wpr = std::max(c->wpr, weight_class(W, n));
     rc = upload_topologies(c, (size_t)tid, c->wpr != old_wpr);
     if (!rc) rc = grow_servers(c, first + (size_t)num_servers);
     if (rc) {
       c->topo_n.pop_back();
       c->topo_W.pop_back();
+      c->topo_maxw.pop_back();
       c->wpr = old_wpr;
       return rc;
     }
@@ -575,6 +643,7 @@ int32_t mapa_create_topology(mapa_ctx *c, int32_t n, const uint8_t *W, int32_t n
   } else {
     c->topo_n.push_back(n);
     c->topo_W.push_back(w16);
+    c->topo_maxw.push_back(maxw);
   }
   c->server_topo.insert(c->server_topo.end(), (size_t)num_servers, tid);
   if (topo_id) *topo_id = tid;

@@ -114,7 +114,8 @@ __device__ __forceinline__ int set_weight(const uint32_t *trow, int wpr, uint32_
 // set R, the key's constant term b*W(R), the pattern's back-neighbour table.
 __device__ __forceinline__ Plan make_plan(const mapa_query &q, int32_t nservers,
                                           const int32_t *server_topo, const int32_t *topo_n,
-                                          const uint32_t *busy, const uint32_t *rows, int wpr) {
+                                          const uint8_t *topo_maxw, const uint32_t *busy,
+                                          const uint32_t *rows, int wpr) {
   Plan p = {};
   p.server = q.server;
   p.kind = q.kind;
@@ -125,12 +126,18 @@ __device__ __forceinline__ Plan make_plan(const mapa_query &q, int32_t nservers,
   p.commit = q.commit;
   const bool ok = q.server >= 0 && q.server < nservers && q.kind <= 2 && q.k >= 1 &&
                   q.k <= kMaxK && q.mode <= 1 && q.commit <= 1 && q.a >= 0 &&
-                  q.a <= MAPA_MAX_AB && q.b >= 0 && q.b <= MAPA_MAX_AB && q.reserved == 0;
+                  q.a <= MAPA_MAX_AB && q.b >= 0 && q.b <= MAPA_MAX_AB &&
+                  (q.metric == MAPA_METRIC_WEIGHTED || q.metric == MAPA_METRIC_EFFBW);
   if (!ok) {
     p.status = kPlanInvalid;
     return p;
   }
   const int t = server_topo[q.server];
+  p.metric = (uint8_t)q.metric;
+  if (q.metric == MAPA_METRIC_EFFBW && topo_maxw[t] > 2) {  // no link class in Eq. 2
+    p.status = kPlanInvalid;
+    return p;
+  }
   const int n = topo_n[t];
   const uint32_t R = ~busy[q.server] & ((1u << n) - 1u);
   const int F = __popc(R);
@@ -138,7 +145,10 @@ __device__ __forceinline__ Plan make_plan(const mapa_query &q, int32_t nservers,
   p.n = (uint8_t)n;
   p.R = R;
   p.F = (uint8_t)F;
-  p.kp0 = (int32_t)q.b * set_weight(rows + (size_t)t * kTopoWords * wpr, wpr, R);
+  // the search's running score starts from b * W(R); for Eq. 2 it is the
+  // link mix of the edges placed so far, which starts empty
+  p.kp0 = q.metric == MAPA_METRIC_EFFBW ? 0
+                                        : (int32_t)q.b * set_weight(rows + (size_t)t * kTopoWords * wpr, wpr, R);
   p.nbtab = c_tab.nbtab[q.kind][q.k];
   p.status = q.k > F ? kPlanNofit : kPlanOk;
   return p;
@@ -153,7 +163,8 @@ __global__ __launch_bounds__(256) void k_prepare(BatchArgs a) {
 
   if (i < a.nq) {
     const mapa_query q = a.q[i];
-    const Plan p = make_plan(q, a.nservers, a.server_topo, a.topo_n, a.busy, a.rows, a.wpr);
+    const Plan p = make_plan(q, a.nservers, a.server_topo, a.topo_n, a.topo_maxw, a.busy, a.rows,
+                             a.wpr);
     if (p.status == kPlanOk) {
       leaves = c_tab.perm[p.F][p.k];
       const uint8_t *sd = a.split_d + ((size_t)p.F * (kMaxK + 1) + p.k) * kNumSplits;
@@ -309,7 +320,7 @@ __global__ __launch_bounds__(1024) void k_bucketize(BatchArgs a) {
       if (p.status == kPlanOk) {
         const int d = a.split_d[((size_t)p.F * (kMaxK + 1) + p.k) * kNumSplits + j];
         const uint32_t nitems = (uint32_t)c_tab.perm[p.F][d];
-        const int b = bucket_id(p.mode, p.kind, p.k - d, p.F - d);
+        const int b = bucket_id(p.metric, p.mode, p.kind, p.k - d, p.F - d);
         a.plan[i].d = (uint8_t)d;
         a.plan[i].bucket = (uint16_t)b;
         a.plan[i].nitems = nitems;
@@ -426,6 +437,9 @@ struct LaneState {
   // leaf-parent node (0: none), bcode = that node's mapping of positions < k-1
   uint32_t bpk;
   uint32_t bcode;
+  // Eq. 2 (bandwidth-sensitive queries): rank table and this pattern's block
+  const uint16_t *erank;
+  int eoff, e1;
 };
 
 template <int WPR>
@@ -698,6 +712,58 @@ __device__ __forceinline__ void expand(LaneState &s, int kind, int L, uint32_t r
   if (L > 0) level<kMaxK, WPR, LINKED, KIND, PAIR>(s, kind, rest, code, kp, d, prev, mu, L);
 }
 
+// Bandwidth-sensitive queries (Eq. 2, sensitive branch of Alg. 1).  The
+// search carries the link mix of the pattern edges placed so far, packed as
+// x << 8 | y (x double NVLinks, y single NVLinks; z follows from the edge
+// count), and a leaf's key is the rank of its mix's predicted effective
+// bandwidth.  The mix added by placing c: among the vertices at the
+// position's earlier pattern neighbours, those joined to c by weight 2 (high
+// bit-plane only) and by weight 1 (low bit-plane only); such topologies have
+// no higher planes.
+template <int WPR>
+__device__ __forceinline__ uint32_t link_mix(const uint32_t *rc, uint32_t nbm) {
+  const uint32_t lo = rc[0] & 0xFFFFu, hi = rc[0] >> 16;
+  return ((uint32_t)__popc(hi & ~lo & nbm) << 8) + (uint32_t)__popc(lo & ~hi & nbm);
+}
+
+template <int L, int WPR, bool LINKED>
+__device__ __forceinline__ void level_eff(LaneState &s, int kind, uint32_t rest, uint32_t code,
+                                          uint32_t mix, int p, uint32_t prev, int mu, int Lrun) {
+  if constexpr (L > 1) {
+    if (Lrun < L) {
+      level_eff<L - 1, WPR, LINKED>(s, kind, rest, code, mix, p, prev, mu, Lrun);
+      return;
+    }
+  }
+  uint32_t nbm, cand;
+  node_masks<WPR, LINKED, L == 1>(s, kind, rest, code, p, prev, nbm, cand);
+  const int m = LINKED ? __popc(cand) : mu;
+  if constexpr (L == 1) {
+    s.count += (uint32_t)m;
+    uint32_t pb = 0;
+    for (int t = 0; t < m; ++t) {
+      const int c = __builtin_ctz(cand);
+      cand &= cand - 1;
+      const uint32_t mx = mix + link_mix<WPR>(s.trow + c * WPR, nbm);
+      const uint32_t rank = s.erank[s.eoff + (int)(mx >> 8) * s.e1 + (int)(mx & 255u)];
+      const uint32_t pk = 16 * rank + 31 - (uint32_t)c;  // ((rank + 1) << 4) | (15 - c)
+      pb = pk > pb ? pk : pb;
+    }
+    const bool better = pb > (s.bpk | 15u);
+    s.bpk = better ? pb : s.bpk;
+    s.bcode = better ? code : s.bcode;
+  } else {
+    const int sh = 4 * p;
+    for (int t = 0; t < m; ++t) {
+      const int c = __builtin_ctz(cand);
+      cand &= cand - 1;
+      level_eff<L - 1, WPR, LINKED>(s, kind, rest & ~(1u << c), code | ((uint32_t)c << sh),
+                                    mix + link_mix<WPR>(s.trow + c * WPR, nbm), p + 1,
+                                    (uint32_t)c, mu - 1, L - 1);
+    }
+  }
+}
+
 // One prefix item: prefix x (of depth p.d) of query plan *pp, expanded over
 // the remaining positions.  pp == nullptr: the lane holds no item.  Returns
 // the item's match count and its best as one u64 (key high, inverted
@@ -705,7 +771,7 @@ __device__ __forceinline__ void expand(LaneState &s, int kind, int L, uint32_t r
 // the smallest mapping; 0: no match).  trow: the topology's rows.
 template <int WPR, int PAIR>
 __device__ __forceinline__ void item_search(const Plan *pp, const uint32_t *trow, uint32_t x,
-                                            unsigned long long &cnt_out,
+                                            const uint16_t *erank, unsigned long long &cnt_out,
                                             unsigned long long &best_out) {
   const bool valid = pp != nullptr;
   LaneState s;
@@ -714,8 +780,11 @@ __device__ __forceinline__ void item_search(const Plan *pp, const uint32_t *trow
   s.bcode = 0;
   s.k = 0;
   s.linked = 0;
+  s.erank = erank;
+  s.eoff = 0;
+  s.e1 = 1;
   uint32_t rest = 0, code = 0, prev = 0;
-  int kp = 0, L = 0, d = 0, kind = 0, fp = 0;
+  int kp = 0, L = 0, d = 0, kind = 0, fp = 0, metric = 0;
   if (valid) {
     const Plan &p = *pp;
     s.trow = trow;
@@ -725,6 +794,12 @@ __device__ __forceinline__ void item_search(const Plan *pp, const uint32_t *trow
     s.k = p.k;
     s.linked = p.mode;
     s.nbtab = p.nbtab;
+    metric = p.metric;
+    if (metric) {
+      const int E = __popcll(p.nbtab);  // pattern edges: one back-neighbour bit each
+      s.eoff = eff_off(E);
+      s.e1 = E + 1;
+    }
     kind = p.kind;
     d = p.d;
     fp = p.F - d;
@@ -743,8 +818,11 @@ __device__ __forceinline__ void item_search(const Plan *pp, const uint32_t *trow
         node_masks<WPR, false, false>(s, kind, rest, code, pos, prev, nbm, cand);
       ok = ok && ((cand >> v) & 1u);
       const uint32_t *rv = s.trow + v * WPR;
-      kp += __mul24(s.a, wsum<WPR>(rv, nbm | (nbm << 16))) -
-            __mul24(s.b, wsum<WPR>(rv, rest | (rest << 16)));
+      if (metric)
+        kp += (int)link_mix<WPR>(rv, nbm);
+      else
+        kp += __mul24(s.a, wsum<WPR>(rv, nbm | (nbm << 16))) -
+              __mul24(s.b, wsum<WPR>(rv, rest | (rest << 16)));
       rest &= ~(1u << v);
       code |= (uint32_t)v << (4 * pos);
       prev = (uint32_t)v;
@@ -756,7 +834,14 @@ __device__ __forceinline__ void item_search(const Plan *pp, const uint32_t *trow
   // (lane 0 holds a real item whenever any lane does).
   const int kind_w = __builtin_amdgcn_readfirstlane(kind);
   const int fp_w = __builtin_amdgcn_readfirstlane(fp);
-  if (__builtin_amdgcn_readfirstlane(s.linked))
+  if (__builtin_amdgcn_readfirstlane(metric)) {
+    if (L > 0) {
+      if (__builtin_amdgcn_readfirstlane(s.linked))
+        level_eff<kMaxK, WPR, true>(s, kind_w, rest, code, (uint32_t)kp, d, prev, 0, L);
+      else
+        level_eff<kMaxK, WPR, false>(s, kind_w, rest, code, (uint32_t)kp, d, prev, fp_w, L);
+    }
+  } else if (__builtin_amdgcn_readfirstlane(s.linked))
     expand<WPR, true, -1, PAIR>(s, kind_w, L, rest, code, kp, d, prev, 0);
   else if (kind_w == MAPA_RING)
     expand<WPR, false, MAPA_RING, PAIR>(s, kind_w, L, rest, code, kp, d, prev, fp_w);
@@ -788,7 +873,7 @@ __device__ __forceinline__ void run_item(const BatchArgs &a, const uint32_t *row
   const Plan *pp = valid ? &a.plan[it.x] : nullptr;
   const uint32_t *trow = valid ? rows + (uint32_t)pp->topo * (kTopoWords * WPR) : rows;
   unsigned long long cnt, best;
-  item_search<WPR, PAIR>(pp, trow, it.y, cnt, best);
+  item_search<WPR, PAIR>(pp, trow, it.y, a.eff_rank, cnt, best);
   const int qi = valid ? (int)it.x : -1;
   const int q0 = __builtin_amdgcn_readfirstlane(qi);
   const bool same = __ballot(valid && qi != q0) == 0ull;
@@ -881,12 +966,15 @@ struct Outcome {
   int64_t count;
   int32_t status, key, agg, pres;
   uint32_t S, map_lo, map_hi;
+  int32_t links;  // Eq. 2 queries: x | y << 8 | z << 16 of the chosen match
   int64_t handle;
 };
 
 __device__ __forceinline__ Outcome decode_best(const Plan &p, unsigned long long cnt,
                                                unsigned long long best, const uint32_t *trow,
-                                               int wpr, uint32_t *self_check_failures) {
+                                               int wpr, const uint16_t *eff_rank,
+                                               const int32_t *eff_key,
+                                               uint32_t *self_check_failures) {
   Outcome o;
   o.count = 0;
   o.status = MAPA_RES_NOFIT;
@@ -894,6 +982,7 @@ __device__ __forceinline__ Outcome decode_best(const Plan &p, unsigned long long
   o.agg = o.pres = 0;
   o.S = 0;
   o.map_lo = o.map_hi = 0xFFFFFFFFu;
+  o.links = 0;
   o.handle = -1;
   int32_t &status = o.status, &agg = o.agg, &pres = o.pres;
   uint32_t &S = o.S, &map_lo = o.map_lo, &map_hi = o.map_hi;
@@ -914,16 +1003,32 @@ __device__ __forceinline__ Outcome decode_best(const Plan &p, unsigned long long
       }
       // AggBW (Eq. 1) from the mapping: each position against its earlier
       // pattern neighbours; PreservedBW (Eq. 3): weight left inside R \ S
+      int lx = 0, ly = 0, lz = 0;  // link mix of the mapped pattern edges (Eq. 2)
       for (int t = 1; t < k; ++t) {
+        const uint32_t *rt = trow + ((phi_code >> (4 * t)) & 15u) * wpr;
         uint32_t nbm = 0;
-        for (uint32_t m = (uint32_t)(p.nbtab >> (8 * t)) & 0xFFu; m; m &= m - 1)
-          nbm |= 1u << ((phi_code >> (4 * __builtin_ctz(m))) & 15u);
-        agg += wsum_rt(trow + ((phi_code >> (4 * t)) & 15u) * wpr, wpr, nbm | (nbm << 16));
+        for (uint32_t m = (uint32_t)(p.nbtab >> (8 * t)) & 0xFFu; m; m &= m - 1) {
+          const uint32_t v = (phi_code >> (4 * __builtin_ctz(m))) & 15u;
+          nbm |= 1u << v;
+          const int w = wsum_rt(rt, wpr, (1u << v) | (1u << (v + 16)));
+          lx += w == 2;
+          ly += w == 1;
+          lz += w == 0;
+        }
+        agg += wsum_rt(rt, wpr, nbm | (nbm << 16));
       }
       pres = set_weight(trow, wpr, p.R & ~S);
-      o.key = (int32_t)(best >> 32);
       status = MAPA_RES_OK;
-      if ((int32_t)p.a * agg + (int32_t)p.b * pres != o.key) atomicAdd(self_check_failures, 1u);
+      if (p.metric == MAPA_METRIC_EFFBW) {
+        const int E = lx + ly + lz;
+        const int at = eff_off(E) + lx * (E + 1) + ly;
+        o.key = eff_key[at];
+        o.links = lx | (ly << 8) | (lz << 16);
+        if ((uint32_t)eff_rank[at] != (uint32_t)(best >> 32)) atomicAdd(self_check_failures, 1u);
+      } else {
+        o.key = (int32_t)(best >> 32);
+        if ((int32_t)p.a * agg + (int32_t)p.b * pres != o.key) atomicAdd(self_check_failures, 1u);
+      }
     }
   }
   return o;
@@ -934,7 +1039,7 @@ __device__ __forceinline__ void store_result(mapa_result *res, const Outcome &o)
   int4 *dst = reinterpret_cast<int4 *>(res);
   dst[0] = make_int4((int32_t)(uint32_t)o.count, (int32_t)(o.count >> 32), o.status, o.key);
   dst[1] = make_int4(o.agg, o.pres, (int32_t)o.S, (int32_t)o.map_lo);
-  dst[2] = make_int4((int32_t)o.map_hi, 0, (int32_t)(uint32_t)o.handle, (int32_t)(o.handle >> 32));
+  dst[2] = make_int4((int32_t)o.map_hi, o.links, (int32_t)(uint32_t)o.handle, (int32_t)(o.handle >> 32));
 }
 
 __global__ __launch_bounds__(256) void k_finalize(BatchArgs a) {
@@ -942,7 +1047,7 @@ __global__ __launch_bounds__(256) void k_finalize(BatchArgs a) {
   if (i >= a.nq) return;
   const Plan p = a.plan[i];
   Outcome o = decode_best(p, a.acc_count[i], a.acc_best[i], a.rows + (size_t)p.topo * kTopoWords * a.wpr,
-                          a.wpr, &a.ctr->self_check_failures);
+                          a.wpr, a.eff_rank, a.eff_key, &a.ctr->self_check_failures);
   a.acc_count[i] = 0;  // leave the accumulators clean for the next batch
   a.acc_best[i] = 0;
   if (p.status != kPlanInvalid && p.commit) {
@@ -980,7 +1085,7 @@ __global__ __launch_bounds__(256) void k_fused(FusedArgs f) {
   const uint32_t span = (uint32_t)f.bpq * blockDim.x;
   if (tid == 0) {
     const mapa_query q = f.q[i];
-    Plan p = make_plan(q, f.nservers, f.server_topo, f.topo_n, f.busy, f.rows, WPR);
+    Plan p = make_plan(q, f.nservers, f.server_topo, f.topo_n, f.topo_maxw, f.busy, f.rows, WPR);
     if (p.status == kPlanOk) {
       int d = 0;
       while (d < p.k - 1 && c_tab.perm[p.F][d] < (unsigned long long)span) ++d;
@@ -999,7 +1104,7 @@ __global__ __launch_bounds__(256) void k_fused(FusedArgs f) {
   for (uint32_t base = (uint32_t)j * blockDim.x; base < nitems; base += span) {
     const uint32_t x = base + (uint32_t)tid;
     unsigned long long c1, b1;
-    item_search<WPR, 0>(x < nitems ? &s_plan : nullptr, s_rows, x, c1, b1);
+    item_search<WPR, 0>(x < nitems ? &s_plan : nullptr, s_rows, x, f.eff_rank, c1, b1);
     cnt += c1;
     best = b1 > best ? b1 : best;
   }
@@ -1035,7 +1140,7 @@ __global__ __launch_bounds__(256) void k_fused(FusedArgs f) {
   __syncthreads();
   if (tid == 0 && s_last) {
     const Plan p = s_plan;
-    Outcome o = decode_best(p, cnt, best, s_rows, WPR, f.self_check_failures);
+    Outcome o = decode_best(p, cnt, best, s_rows, WPR, f.eff_rank, f.eff_key, f.self_check_failures);
     if (p.status != kPlanInvalid && p.commit && o.status == MAPA_RES_OK) {
       atomicOr(&f.busy[p.server], o.S);
       o.handle = ((int64_t)p.server << 32) | (int64_t)o.S;

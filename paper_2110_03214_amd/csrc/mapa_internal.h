@@ -17,19 +17,29 @@ constexpr int kMaxK = MAPA_MAX_K;
 constexpr int kNumSplits = 17;
 constexpr int kSplitWhole = kNumSplits - 1;
 
-// Shape buckets: (mode, pattern kind, L = positions left below the prefix,
-// F' = free vertices left below the prefix).  Every item of one bucket
-// expands a subtree of the same pattern kind, and in ALL mode of the same
-// shape, so the 64 lanes of a wave run the same code in lock step.
+// Shape buckets: (metric, mode, pattern kind, L = positions left below the
+// prefix, F' = free vertices left below the prefix).  Every item of one
+// bucket runs the same scoring code and expands a subtree of the same pattern
+// kind, and in ALL mode of the same shape, so the 64 lanes of a wave run in
+// lock step.
 constexpr int kFp = kMaxN + 1;                      // F' in 0..16
-constexpr int kNumBuckets = 2 * 3 * kMaxK * kFp;    // 816
+constexpr int kNumBuckets = 2 * 2 * 3 * kMaxK * kFp;  // 1632
 constexpr int kChunk = 64;                          // items per wave-chunk (one per lane)
 constexpr int kPadReserve = (kChunk - 1) * kNumBuckets;
 constexpr uint32_t kInvalidItem = 0xFFFFFFFFu;
 
-__host__ __device__ inline int bucket_id(int mode, int kind, int L, int Fp) {
-  return ((mode * 3 + kind) * kMaxK + (L - 1)) * kFp + Fp;
+__host__ __device__ inline int bucket_id(int metric, int mode, int kind, int L, int Fp) {
+  return (((metric * 2 + mode) * 3 + kind) * kMaxK + (L - 1)) * kFp + Fp;
 }
+
+// Eq. 2 tables, one block per pattern edge count E = 0..28: entry
+// eff_off(E) + x * (E + 1) + y holds, for the mix of x double NVLinks, y
+// single NVLinks and z = E - x - y PCIe links, the dense rank of its
+// predicted effective bandwidth among the mixes of E edges (0 = lowest) and
+// round(1000 * EffBW).  eff_off(E) = 1^2 + ... + E^2.
+constexpr int kMaxEdges = kMaxK * (kMaxK - 1) / 2;  // 28
+__host__ __device__ constexpr int eff_off(int E) { return E * (E + 1) * (2 * E + 1) / 6; }
+constexpr int kEffEntries = eff_off(kMaxEdges + 1);  // 8555
 
 // Per-query plan, written by the prepare/bucketize kernels.
 struct Plan {
@@ -45,6 +55,8 @@ struct Plan {
   uint16_t bucket;
   uint32_t nitems;     // prefix items of the chosen split
   uint32_t item_off;   // offset of the first item inside its bucket
+  uint8_t metric;      // MAPA_METRIC_*
+  uint8_t pad[3];
   uint64_t nbtab;      // byte p: pattern neighbours of position p that precede it
 };
 static_assert(sizeof(Plan) == 48, "Plan layout");
@@ -119,6 +131,9 @@ struct BatchArgs {
   const int32_t *topo_n;
   const uint8_t *topo_W;  // [T][16][16]
   const uint32_t *rows;   // [T][kTopoWords][wpr], see kTopoWords
+  const uint8_t *topo_maxw;  // [T] largest weight of each topology
+  const uint16_t *eff_rank;  // [kEffEntries], see eff_off
+  const int32_t *eff_key;    // [kEffEntries]
   int32_t ntopo;
   int32_t wpr;
   const uint8_t *split_d;  // [F][k][j], see kSplitTable
@@ -148,6 +163,9 @@ struct FusedArgs {
   const int32_t *topo_n;
   const uint32_t *rows;
   int32_t wpr;
+  const uint8_t *topo_maxw;
+  const uint16_t *eff_rank;
+  const int32_t *eff_key;
   uint32_t *self_check_failures;
   unsigned long long *acc_count, *acc_best;  // per query, zero on entry and exit
   uint32_t *done;                            // per query, zero on entry and exit

@@ -325,7 +325,7 @@ int32_t dispatch(ServeState *S, Slot &sl, bool final_release, bool *did) {
       q.commit = 1;
       q.a = r.a;
       q.b = r.b;
-      q.reserved = 0;
+      q.metric = r.metric;
     }
     // one request per server: small batches take the fused launch, which
     // reads the requests from and writes the results to the pinned buffers
@@ -540,8 +540,10 @@ int32_t mapa_serve_submit(mapa_ctx *c, const mapa_request *reqs, int32_t n) {
       return fail(MAPA_ERR_UNKNOWN_SERVER, "request %d: unknown server %d", i, r.server);
     if (r.k > kMaxK) return fail(MAPA_ERR_UNSUPPORTED, "request %d: k=%d > %d", i, r.k, kMaxK);
     if (r.k < 1 || r.kind > 2 || r.mode > 1 || r.a < 0 || r.a > MAPA_MAX_AB || r.b < 0 ||
-        r.b > MAPA_MAX_AB || r.reserved0 != 0 || r.reserved1 != 0)
+        r.b > MAPA_MAX_AB || r.metric > MAPA_METRIC_EFFBW || r.reserved1 != 0)
       return fail(MAPA_ERR_INVALID_ARG, "request %d: malformed field", i);
+    if (r.metric == MAPA_METRIC_EFFBW && c->topo_maxw[c->server_topo[r.server]] > 2)
+      return fail(MAPA_ERR_UNSUPPORTED, "request %d: effective bandwidth needs link weights 0..2", i);
     if (i > 0 && !(r.t_arrival >= reqs[i - 1].t_arrival))
       return fail(MAPA_ERR_INVALID_ARG, "request %d: arrival goes back in time", i);
     batch[i] = {r, S->opts.time_unit_us > 0 ? r.t_arrival * S->opts.time_unit_us : 0.0};

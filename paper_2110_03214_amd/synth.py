@@ -117,7 +117,7 @@ class Workload:
                         self.busy, q, dict(self.meta))
 
 
-def make_queries(server, kind, k, mode=MODE_ALL, commit=0, a=1, b=1):
+def make_queries(server, kind, k, mode=MODE_ALL, commit=0, a=1, b=1, metric=0):
     nq = len(server)
 
     def col(x, dt):
@@ -133,6 +133,7 @@ def make_queries(server, kind, k, mode=MODE_ALL, commit=0, a=1, b=1):
         "commit": col(commit, np.uint8),
         "a": col(a, np.int16),
         "b": col(b, np.int16),
+        "metric": col(metric, np.uint8),
     }
 
 

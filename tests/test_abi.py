@@ -117,10 +117,15 @@ def test_query_validation(vctx):
     assert code_of(with_field("commit", 2)) == B.ERR_INVALID_ARG
     assert code_of(with_field("a", 1025)) == B.ERR_INVALID_ARG
     assert code_of(with_field("b", -1)) == B.ERR_INVALID_ARG
-    assert code_of(with_field("reserved", 7)) == B.ERR_INVALID_ARG
+    assert code_of(with_field("metric", 7)) == B.ERR_INVALID_ARG
     assert "query 1" in B.lib().mapa_last_error().decode()
     # a valid batch passes validation and then needs a device
     assert code_of(lambda: vctx.query_batch(good)) == B.ERR_NO_DEVICE
+    # Eq. 2 needs weights 0..2; the cube-mesh here has weight 1 only: fine
+    vctx.create_topology(np.full((3, 3), 3, np.uint8) - 3 * np.eye(3, dtype=np.uint8), 1)
+    heavy = B.pack_queries([4], [0], [3], metric=[1])
+    assert code_of(lambda: vctx.query_batch(heavy)) == B.ERR_UNSUPPORTED
+    assert code_of(lambda: vctx.query_batch(B.pack_queries([0], [0], [3], metric=[1]))) == B.ERR_NO_DEVICE
 
 
 def test_release_validation(vctx):

@@ -236,6 +236,72 @@ def test_sixteen_vertex_topologies_every_pair_width(ctx):
     assert ctx.stats()["self_check_failures"] == 0
 
 
+@pytest.mark.parametrize("n_max", [8, 12])
+def test_effective_bandwidth_queries(ctx, n_max):
+    """Bandwidth-sensitive queries (Eq. 2): random topologies with weights
+    0..2 (PCIe, single, double NVLink), every kind, k, both modes; the
+    reported key round(1000 * EffBW) and link mix (x, y, z), count, mapping
+    and the AggBW / PreservedBW of the chosen match equal the oracle's, in one
+    pipeline batch (mixed with weighted queries) and as fused
+    one-query-per-server batches.  n_max 12 also runs the search variant for
+    contexts of large topologies."""
+    rng = np.random.default_rng(2 + n_max)
+    topos = [random_topology(rng, int(rng.integers(3, n_max + 1)), 2, 0.6) for _ in range(6)]
+    st, busy, cols = [], [], {key: [] for key in ("server", "kind", "k", "mode", "metric")}
+    s = 0
+    for t, W in enumerate(topos):
+        n = W.shape[0]
+        for _ in range(4):
+            st.append(t)
+            b = int(rng.integers(0, 1 << n)) & int(rng.integers(0, 1 << n))
+            busy.append(b)
+            F = n - bin(b).count("1")
+            for kind in range(3):
+                for k in range(1, 9):
+                    if k <= F and math.perm(F, k) > 3_000_000:
+                        continue
+                    for mode in (0, 1):
+                        for metric in (1, 0):
+                            for key, v in zip(cols, (s, kind, k, mode, metric)):
+                                cols[key].append(v)
+            s += 1
+    q = synth.make_queries(cols["server"], cols["kind"], cols["k"], cols["mode"], 0, 1, 1,
+                           cols["metric"])
+    wl = synth.Workload("effbw", topos, np.array(st, np.int32), np.array(busy, np.uint32), q)
+    qh, _ = B.load_workload(ctx, wl)
+    got = ctx.query_batch(qh)
+    ref = oracle.run_workload(wl, NTHREADS)
+    assert_same(got, ref, wl.queries["k"], "effbw")
+    eff = (qh["metric"] == 1) & (ref["status"] == 0)
+    assert np.array_equal(got["links"][eff], ref["links"][eff])
+    assert (got["links"][qh["metric"] == 0] == 0).all()
+    assert eff.sum() > 200
+    for sel in distinct_server_batches(qh["server"])[:12]:
+        fused = ctx.query_batch(qh[sel])
+        assert np.array_equal(fused, got[sel])
+    assert ctx.stats()["self_check_failures"] == 0
+
+
+def test_effective_bandwidth_rejections(ctx, torch):
+    """Eq. 2 has no class for weight 3: a host batch with such a query is
+    refused up front; through device pointers the query is answered
+    MAPA_RES_INVALID and the rest of the batch is unaffected."""
+    W = np.full((5, 5), 3, np.uint8)
+    np.fill_diagonal(W, 0)
+    ids = ctx.load_servers([W], np.zeros(2, np.int32))
+    q = B.pack_queries(ids, [0, 0], [3, 3], metric=[1, 0])
+    with pytest.raises(B.MapaError) as e:
+        ctx.query_batch(q)
+    assert e.value.code == B.ERR_UNSUPPORTED
+    dq = torch.from_numpy(q.view(np.uint8)).to("cuda")
+    dr = torch.zeros(2 * 48, dtype=torch.uint8, device="cuda")
+    ctx.query_batch(dq, dr, stream=torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    got = dr.cpu().numpy().view(B.RESULT_DTYPE)
+    assert got["status"][0] == B.RES_INVALID and got["status"][1] == B.RES_OK
+    assert got["count"][1] == 60
+
+
 def test_edge_cases(ctx):
     W16 = np.full((16, 16), 255, np.uint8)
     np.fill_diagonal(W16, 0)
@@ -323,7 +389,7 @@ def test_device_pointer_release_and_invalid_queries(ctx, torch):
     q, ids = B.load_workload(ctx, wl)
     q["commit"] = 1
     q["k"][7] = 0          # malformed: answered with RES_INVALID on device
-    q["reserved"][9] = 3
+    q["metric"][9] = 3    # unknown metric
     dq = torch.from_numpy(q.view(np.uint8)).to("cuda")
     dr = torch.zeros(len(q) * 48, dtype=torch.uint8, device="cuda")
     ctx.query_batch(dq, dr, stream=torch.cuda.current_stream())
