@@ -197,6 +197,8 @@ __global__ __launch_bounds__(256) void k_prepare(BatchArgs a) {
 
 // --------------------------------------------------------------- bucketize
 
+constexpr int kFatBlock = 1024;  // threads of k_bucketize and k_layout blocks
+
 // Lay the buckets out (largest items first), pad each to whole 64-item
 // chunks with invalid items, and reset the per-batch counters.  Run by the
 // one block of k_layout, once every k_bucketize block's counts are in.
@@ -205,7 +207,10 @@ __device__ void layout_buckets(const BatchArgs &a) {
   __shared__ uint32_t s_cnt[kNumBuckets];
   __shared__ uint32_t s_start[kNumBuckets];
   const int t = threadIdx.x;
-  for (int r = t; r < kNumBuckets; r += blockDim.x) {
+  // loops over the buckets have a fixed stride (one 1024-thread block), so
+  // they unroll and each thread's loads are in flight together
+#pragma unroll
+  for (int r = t; r < kNumBuckets; r += kFatBlock) {
     const int b = c_tab.rank_bucket[r];
     const uint32_t cnt = __hip_atomic_load(&a.ctr->bucket_items[b][0], __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_AGENT);
@@ -213,33 +218,52 @@ __device__ void layout_buckets(const BatchArgs &a) {
     s_pad[r] = (cnt + (kChunk - 1)) & ~(uint32_t)(kChunk - 1);
   }
   __syncthreads();
-  if (t < 64) {
-    // exclusive scan of the padded sizes in rank order by one wave: each lane
-    // owns 5 consecutive ranks (64 x 5 >= 272)
-    constexpr int kPer = (kNumBuckets + 63) / 64;
+  {
+    // exclusive scan of the padded sizes in rank order over the whole block:
+    // thread t owns kPerT consecutive ranks; wave scans, then a scan of the
+    // wave totals
+    constexpr int kPerT = (kNumBuckets + kFatBlock - 1) / kFatBlock;
+    __shared__ uint32_t s_wave[kFatBlock / 64];
+    const int lane = t & 63, wave = t >> 6;
+    uint32_t v[kPerT];
     uint32_t sum = 0;
-    for (int e = 0; e < kPer; ++e) {
-      const int r = t * kPer + e;
-      if (r < kNumBuckets) sum += s_pad[r];
+#pragma unroll
+    for (int e = 0; e < kPerT; ++e) {
+      const int r = t * kPerT + e;
+      v[e] = r < kNumBuckets ? s_pad[r] : 0u;
+      sum += v[e];
     }
     uint32_t incl = sum;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
       const uint32_t o = __shfl_up(incl, off, 64);
-      if (t >= off) incl += o;
+      if (lane >= off) incl += o;
     }
-    uint32_t run = incl - sum;
-    for (int e = 0; e < kPer; ++e) {
-      const int r = t * kPer + e;
-      if (r < kNumBuckets) {
-        s_start[r] = run;
-        run += s_pad[r];
+    if (lane == 63) s_wave[wave] = incl;
+    __syncthreads();
+    if (t < 64) {
+      const uint32_t w = t < kFatBlock / 64 ? s_wave[t] : 0u;
+      uint32_t wi = w;
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t o = __shfl_up(wi, off, 64);
+        if (lane >= off) wi += o;
       }
+      if (t < kFatBlock / 64) s_wave[t] = wi - w;  // exclusive
+      if (t == kFatBlock / 64 - 1) a.ctr->total_chunks = wi / kChunk;
     }
-    if (t == 63) a.ctr->total_chunks = incl / kChunk;
+    __syncthreads();
+    uint32_t run = s_wave[wave] + incl - sum;
+#pragma unroll
+    for (int e = 0; e < kPerT; ++e) {
+      const int r = t * kPerT + e;
+      if (r < kNumBuckets) s_start[r] = run;
+      run += v[e];
+    }
   }
   __syncthreads();
-  for (int r = t; r < kNumBuckets; r += blockDim.x) {
+#pragma unroll
+  for (int r = t; r < kNumBuckets; r += kFatBlock) {
     const int b = c_tab.rank_bucket[r];
     a.ctr->bucket_start[b] = s_start[r];
     for (uint32_t x = s_cnt[r]; x < s_pad[r]; ++x) a.items[s_start[r] + x] = make_uint2(kInvalidItem, 0u);
@@ -263,7 +287,8 @@ __global__ __launch_bounds__(1024) void k_bucketize(BatchArgs a) {
   __shared__ uint32_t s_base[kNumBuckets];
   __shared__ unsigned long long s_part[kTotCopies * (kNumSplits + 1)];
   __shared__ unsigned long long s_tot[kNumSplits + 1];
-  for (int b = threadIdx.x; b < kNumBuckets; b += blockDim.x) s_cnt[b] = 0;
+#pragma unroll
+  for (int b = threadIdx.x; b < kNumBuckets; b += kFatBlock) s_cnt[b] = 0;
   // the batch totals: every copy loaded at once (one load per thread), then summed
   if (threadIdx.x < kTotCopies * (kNumSplits + 1))
     s_part[threadIdx.x] =
@@ -330,7 +355,8 @@ __global__ __launch_bounds__(1024) void k_bucketize(BatchArgs a) {
     }
   }
   __syncthreads();
-  for (int c = threadIdx.x; c < kNumBuckets; c += blockDim.x)
+#pragma unroll
+  for (int c = threadIdx.x; c < kNumBuckets; c += kFatBlock)
     s_base[c] = s_cnt[c] ? atomicAdd(&a.ctr->bucket_items[c][0], s_cnt[c]) : 0u;
   __syncthreads();
 #pragma unroll
@@ -1003,6 +1029,7 @@ __device__ __forceinline__ Outcome decode_best(const Plan &p, unsigned long long
       }
       // AggBW (Eq. 1) from the mapping: each position against its earlier
       // pattern neighbours; PreservedBW (Eq. 3): weight left inside R \ S
+      const bool eff = p.metric == MAPA_METRIC_EFFBW;
       int lx = 0, ly = 0, lz = 0;  // link mix of the mapped pattern edges (Eq. 2)
       for (int t = 1; t < k; ++t) {
         const uint32_t *rt = trow + ((phi_code >> (4 * t)) & 15u) * wpr;
@@ -1010,16 +1037,18 @@ __device__ __forceinline__ Outcome decode_best(const Plan &p, unsigned long long
         for (uint32_t m = (uint32_t)(p.nbtab >> (8 * t)) & 0xFFu; m; m &= m - 1) {
           const uint32_t v = (phi_code >> (4 * __builtin_ctz(m))) & 15u;
           nbm |= 1u << v;
-          const int w = wsum_rt(rt, wpr, (1u << v) | (1u << (v + 16)));
-          lx += w == 2;
-          ly += w == 1;
-          lz += w == 0;
+          if (eff) {
+            const int w = wsum_rt(rt, wpr, (1u << v) | (1u << (v + 16)));
+            lx += w == 2;
+            ly += w == 1;
+            lz += w == 0;
+          }
         }
         agg += wsum_rt(rt, wpr, nbm | (nbm << 16));
       }
       pres = set_weight(trow, wpr, p.R & ~S);
       status = MAPA_RES_OK;
-      if (p.metric == MAPA_METRIC_EFFBW) {
+      if (eff) {
         const int E = lx + ly + lz;
         const int at = eff_off(E) + lx * (E + 1) + ly;
         o.key = eff_key[at];
@@ -1248,8 +1277,8 @@ hipError_t launch_batch_front(const BatchArgs &a, hipStream_t s) {
   unsigned gb = blocks_for(a.nq, 1024 * 16);
   if (gb < 64) gb = std::min<unsigned>(64, blocks_for(a.nq, 1024));
   if (gb < 1) gb = 1;
-  hipLaunchKernelGGL(k_bucketize, dim3(gb), dim3(1024), 0, s, a);
-  hipLaunchKernelGGL(k_layout, dim3(1), dim3(1024), 0, s, a);
+  hipLaunchKernelGGL(k_bucketize, dim3(gb), dim3(kFatBlock), 0, s, a);
+  hipLaunchKernelGGL(k_layout, dim3(1), dim3(kFatBlock), 0, s, a);
   // one-wave blocks of at most 64 queries, and at least ~2048 blocks
   int qpb = 64;
   if (blocks_for(a.nq, qpb) < 2048) qpb = (int)((a.nq + 2047) / 2048);
