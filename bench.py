@@ -235,6 +235,9 @@ def main():
     ap.add_argument("--steps", type=int, default=0, help="timed steps (default: per config)")
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", type=int, default=2, choices=(1, 2, 3))
+    ap.add_argument("--metric", default="weighted", choices=("weighted", "effbw"),
+                    help="key of every query: a*AggBW + b*PreservedBW, or the predicted effective "
+                         "bandwidth of Eq. 2 (bandwidth-sensitive jobs; needs weights 0..2)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="no HIP-event timing of the kernel")
     ap.add_argument("--plain", type=int, default=4096,
@@ -280,6 +283,7 @@ def main():
     ctx = B.Context(0)
     qh, ids = B.load_workload(ctx, wl)
     qh["commit"] = 1
+    qh["metric"] = B.METRIC_EFFBW if args.metric == "effbw" else B.METRIC_WEIGHTED
     dq = torch.from_numpy(qh.view(np.uint8).copy()).to(dev)
     dr = torch.zeros(wl.nq * B.RESULT_DTYPE.itemsize, dtype=torch.uint8, device=dev)
     handles = dr.view(torch.int64)[5:]  # alloc_handle: byte 40 of each 48-byte result
@@ -334,6 +338,8 @@ def main():
         "dtype": "int32",
         "data": "synthetic (seeded generator)",
         "config": {"workload": WORKLOAD_TEXT[args.config], "config_id": args.config,
+                   "key": ("a*AggBW + b*PreservedBW, (a, b) = (1, 1)" if args.metric == "weighted"
+                           else "predicted effective bandwidth (Eq. 2)"),
                    "queries": wl.nq, "embeddings_per_step": emb,
                    "topologies": len(wl.topologies), "parallelism": "single GPU"},
         "queries_per_s": wl.nq * steps / wall,
@@ -361,6 +367,8 @@ def main():
         out["serving"] = run_serving(B, args.serving_trace, args.serving)
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle")
+        if args.metric == "effbw":
+            wl.queries["metric"][:] = 1
         out["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(out), flush=True)
 

@@ -537,7 +537,7 @@ __device__ __forceinline__ void node_masks(const LaneState &s, int kind, uint32_
 // unrolled over N, so the per-candidate values stay in registers.  Leaves
 // come in lexicographic order (c_i, then c_j, ascending) as in level().
 // Rows of one word (weights up to 3): the packed weight of u is 2 bits at 2u.
-template <int M, int KIND>
+template <int M, int KIND, bool PRES>
 __device__ __forceinline__ void pair_level(LaneState &s, uint32_t rest, uint32_t code, int kp,
                                            int p, uint32_t prev) {
   constexpr int N = M + 1;
@@ -566,9 +566,10 @@ __device__ __forceinline__ void pair_level(LaneState &s, uint32_t rest, uint32_t
     r &= r - 1;
     sh2[j] = 2 * c;
     const uint32_t *row = s.trow + c;
-    P[j] = __mul24(16 * s.a, wsum<1>(row, fix2)) - __mul24(16 * s.b, wsum<1>(row, rest2)) - (int)c;
+    P[j] = __mul24(16 * s.a, wsum<1>(row, fix2)) - (int)c;
+    if constexpr (PRES) P[j] -= __mul24(16 * s.b, wsum<1>(row, rest2));
   }
-  const int gamma = (alpha ? 16 * s.a : 0) + 16 * s.b;
+  const int gamma = (alpha ? 16 * s.a : 0) + (PRES ? 16 * s.b : 0);
   s.count += (uint32_t)(N * M);
   const int sh = 4 * p;
   uint32_t ri = rest;
@@ -576,7 +577,8 @@ __device__ __forceinline__ void pair_level(LaneState &s, uint32_t rest, uint32_t
     const uint32_t ci = (uint32_t)__builtin_ctz(ri);
     ri &= ri - 1;
     const uint32_t *row = s.trow + ci;
-    const int kp2 = kp + __mul24(s.a, wsum<1>(row, nb2)) - __mul24(s.b, wsum<1>(row, rest2));
+    int kp2 = kp + __mul24(s.a, wsum<1>(row, nb2));
+    if constexpr (PRES) kp2 -= __mul24(s.b, wsum<1>(row, rest2));
     const int base = 16 * kp2 + 31;
     const uint32_t wp = prow[ci];
     const uint32_t si = 2 * ci;
@@ -595,73 +597,73 @@ __device__ __forceinline__ void pair_level(LaneState &s, uint32_t rest, uint32_t
 
 // pair_level for N = 2 .. PAIRN free vertices at the last two positions (rows
 // of one word); other shapes take the general per-level loops.
-template <int KIND, int PAIRN>
+template <int KIND, int PAIRN, bool PRES>
 __device__ __forceinline__ bool pair_dispatch(LaneState &s, uint32_t rest, uint32_t code, int kp,
                                               int p, uint32_t prev, int mu) {
   switch (mu) {
     case 2:
       if constexpr (PAIRN >= 2) {
-        pair_level<1, KIND>(s, rest, code, kp, p, prev);
+        pair_level<1, KIND, PRES>(s, rest, code, kp, p, prev);
         return true;
       }
       return false;
     case 3:
       if constexpr (PAIRN >= 3) {
-        pair_level<2, KIND>(s, rest, code, kp, p, prev);
+        pair_level<2, KIND, PRES>(s, rest, code, kp, p, prev);
         return true;
       }
       return false;
     case 4:
       if constexpr (PAIRN >= 4) {
-        pair_level<3, KIND>(s, rest, code, kp, p, prev);
+        pair_level<3, KIND, PRES>(s, rest, code, kp, p, prev);
         return true;
       }
       return false;
     case 5:
       if constexpr (PAIRN >= 5) {
-        pair_level<4, KIND>(s, rest, code, kp, p, prev);
+        pair_level<4, KIND, PRES>(s, rest, code, kp, p, prev);
         return true;
       }
       return false;
     case 6:
       if constexpr (PAIRN >= 6) {
-        pair_level<5, KIND>(s, rest, code, kp, p, prev);
+        pair_level<5, KIND, PRES>(s, rest, code, kp, p, prev);
         return true;
       }
       return false;
     case 7:
       if constexpr (PAIRN >= 7) {
-        pair_level<6, KIND>(s, rest, code, kp, p, prev);
+        pair_level<6, KIND, PRES>(s, rest, code, kp, p, prev);
         return true;
       }
       return false;
     case 8:
       if constexpr (PAIRN >= 8) {
-        pair_level<7, KIND>(s, rest, code, kp, p, prev);
+        pair_level<7, KIND, PRES>(s, rest, code, kp, p, prev);
         return true;
       }
       return false;
     case 9:
       if constexpr (PAIRN >= 9) {
-        pair_level<8, KIND>(s, rest, code, kp, p, prev);
+        pair_level<8, KIND, PRES>(s, rest, code, kp, p, prev);
         return true;
       }
       return false;
     case 10:
       if constexpr (PAIRN >= 10) {
-        pair_level<9, KIND>(s, rest, code, kp, p, prev);
+        pair_level<9, KIND, PRES>(s, rest, code, kp, p, prev);
         return true;
       }
       return false;
     case 11:
       if constexpr (PAIRN >= 11) {
-        pair_level<10, KIND>(s, rest, code, kp, p, prev);
+        pair_level<10, KIND, PRES>(s, rest, code, kp, p, prev);
         return true;
       }
       return false;
     case 12:
       if constexpr (PAIRN >= 12) {
-        pair_level<11, KIND>(s, rest, code, kp, p, prev);
+        pair_level<11, KIND, PRES>(s, rest, code, kp, p, prev);
         return true;
       }
       return false;
@@ -683,17 +685,17 @@ __device__ __forceinline__ bool pair_dispatch(LaneState &s, uint32_t rest, uint3
 // ((key + 1) << 4) | (15 - c), so one max() picks the largest key and, among
 // equal keys, the smallest vertex; the node then replaces the lane's best only
 // on a strictly larger key (leaves arrive in lexicographic order).
-template <int L, int WPR, bool LINKED, int KIND, int PAIR>
+template <int L, int WPR, bool LINKED, int KIND, int PAIR, bool PRES = true>
 __device__ __forceinline__ void level(LaneState &s, int kind, uint32_t rest, uint32_t code,
                                       int kp, int p, uint32_t prev, int mu, int Lrun) {
   if constexpr (L > 1) {
     if (Lrun < L) {
-      level<L - 1, WPR, LINKED, KIND, PAIR>(s, kind, rest, code, kp, p, prev, mu, Lrun);
+      level<L - 1, WPR, LINKED, KIND, PAIR, PRES>(s, kind, rest, code, kp, p, prev, mu, Lrun);
       return;
     }
   }
   if constexpr (PAIR > 0 && L == 2 && !LINKED && KIND >= 0 && WPR == 1) {
-    if (pair_dispatch<KIND, PAIR>(s, rest, code, kp, p, prev, mu)) return;
+    if (pair_dispatch<KIND, PAIR, PRES>(s, rest, code, kp, p, prev, mu)) return;
   }
   uint32_t nbm, cand;
   node_masks<WPR, LINKED, L == 1, KIND>(s, kind, rest, code, p, prev, nbm, cand);
@@ -711,8 +713,9 @@ __device__ __forceinline__ void level(LaneState &s, int kind, uint32_t rest, uin
       const int c = __builtin_ctz(cand);
       cand &= cand - 1;
       const uint32_t *rc = s.trow + c * WPR;
-      const uint32_t pk = (uint32_t)(base + __mul24(a16, wsum<WPR>(rc, nb2)) -
-                                     __mul24(b16, wsum<WPR>(rc, rest2)) - c);
+      int v = base + __mul24(a16, wsum<WPR>(rc, nb2)) - c;
+      if constexpr (PRES) v -= __mul24(b16, wsum<WPR>(rc, rest2));
+      const uint32_t pk = (uint32_t)v;
       pb = pk > pb ? pk : pb;
     }
     // strictly larger key <=> pb > (bpk | 15)
@@ -725,17 +728,18 @@ __device__ __forceinline__ void level(LaneState &s, int kind, uint32_t rest, uin
       const int c = __builtin_ctz(cand);
       cand &= cand - 1;
       const uint32_t *rc = s.trow + c * WPR;
-      const int kp2 = kp + __mul24(s.a, wsum<WPR>(rc, nb2)) - __mul24(s.b, wsum<WPR>(rc, rest2));
-      level<L - 1, WPR, LINKED, KIND, PAIR>(s, kind, rest & ~(1u << c), code | ((uint32_t)c << sh),
+      int kp2 = kp + __mul24(s.a, wsum<WPR>(rc, nb2));
+      if constexpr (PRES) kp2 -= __mul24(s.b, wsum<WPR>(rc, rest2));
+      level<L - 1, WPR, LINKED, KIND, PAIR, PRES>(s, kind, rest & ~(1u << c), code | ((uint32_t)c << sh),
                                             kp2, p + 1, (uint32_t)c, mu - 1, L - 1);
     }
   }
 }
 
-template <int WPR, bool LINKED, int KIND, int PAIR>
+template <int WPR, bool LINKED, int KIND, int PAIR, bool PRES = true>
 __device__ __forceinline__ void expand(LaneState &s, int kind, int L, uint32_t rest,
                                        uint32_t code, int kp, int d, uint32_t prev, int mu) {
-  if (L > 0) level<kMaxK, WPR, LINKED, KIND, PAIR>(s, kind, rest, code, kp, d, prev, mu, L);
+  if (L > 0) level<kMaxK, WPR, LINKED, KIND, PAIR, PRES>(s, kind, rest, code, kp, d, prev, mu, L);
 }
 
 // Bandwidth-sensitive queries (Eq. 2, sensitive branch of Alg. 1).  The
@@ -869,7 +873,19 @@ __device__ __forceinline__ void item_search(const Plan *pp, const uint32_t *trow
     }
   } else if (__builtin_amdgcn_readfirstlane(s.linked))
     expand<WPR, true, -1, PAIR>(s, kind_w, L, rest, code, kp, d, prev, 0);
-  else if (kind_w == MAPA_RING)
+  else if (__builtin_amdgcn_readfirstlane(L) >= fp_w - 1) {
+    // The item's remaining positions leave at most one free vertex unused, so
+    // every match below it preserves nothing (Eq. 3 over no pair): take the
+    // preserved weight of its free vertices out of the running key once and
+    // score the subtree by AggBW alone.
+    if (L > 0) kp -= __mul24(s.b, set_weight(s.trow, WPR, rest));
+    if (kind_w == MAPA_RING)
+      expand<WPR, false, MAPA_RING, PAIR, false>(s, kind_w, L, rest, code, kp, d, prev, fp_w);
+    else if (kind_w == MAPA_ALL_TO_ALL)
+      expand<WPR, false, MAPA_ALL_TO_ALL, PAIR, false>(s, kind_w, L, rest, code, kp, d, prev, fp_w);
+    else
+      expand<WPR, false, MAPA_TREE, PAIR, false>(s, kind_w, L, rest, code, kp, d, prev, fp_w);
+  } else if (kind_w == MAPA_RING)
     expand<WPR, false, MAPA_RING, PAIR>(s, kind_w, L, rest, code, kp, d, prev, fp_w);
   else if (kind_w == MAPA_ALL_TO_ALL)
     expand<WPR, false, MAPA_ALL_TO_ALL, PAIR>(s, kind_w, L, rest, code, kp, d, prev, fp_w);
