@@ -173,6 +173,19 @@ struct FusedArgs {
 };
 
 hipError_t launch_fused(const FusedArgs &f, hipStream_t s);
+
+// per translation unit: constant-table upload, enumeration launch and occupancy
+hipError_t upload_tables_front(const Tables &t);
+hipError_t upload_tables_fused(const Tables &t);
+hipError_t upload_tables_enum_pair12(const Tables &t);
+hipError_t upload_tables_enum_pair8(const Tables &t);
+hipError_t upload_tables_enum_plain(const Tables &t);
+hipError_t launch_enum_pair12(const BatchArgs &a, hipStream_t s);
+hipError_t launch_enum_pair8(const BatchArgs &a, hipStream_t s);
+hipError_t launch_enum_plain(const BatchArgs &a, hipStream_t s);
+int occ_enum_pair12(int rows_in_lds, int threads, size_t lds_bytes);
+int occ_enum_pair8(int rows_in_lds, int threads, size_t lds_bytes);
+int occ_enum_plain(int wpr, int rows_in_lds, int threads, size_t lds_bytes);
 hipError_t launch_batch_front(const BatchArgs &a, hipStream_t s);   // prepare .. expand
 hipError_t launch_enumerate(const BatchArgs &a, hipStream_t s);
 hipError_t launch_finalize(const BatchArgs &a, hipStream_t s);
