@@ -81,26 +81,44 @@ def lib():
                                ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                ctypes.c_int, ctypes.POINTER(OrResult)]
         L.or_batch.restype = ctypes.c_int
-        L.or_batch.argtypes = [ctypes.c_int] + [ctypes.c_void_p] * 11 + [ctypes.c_int]
+        L.or_query_edges.restype = ctypes.c_int
+        L.or_query_edges.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int,
+                                     ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                     ctypes.c_int, ctypes.c_int, ctypes.POINTER(OrResult)]
+        L.or_batch.argtypes = [ctypes.c_int] + [ctypes.c_void_p] * 13 + [ctypes.c_int]
         L.or_effbw.restype = ctypes.c_double
         L.or_effbw.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
         L.or_pattern_edges.restype = ctypes.c_int
         L.or_pattern_edges.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
         L.or_aut_count.restype = ctypes.c_int
         L.or_aut_count.argtypes = [ctypes.c_int, ctypes.c_int]
+        L.or_aut_count_edges.restype = ctypes.c_int
+        L.or_aut_count_edges.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
         L.or_result_size.restype = ctypes.c_int
         assert L.or_result_size() == RESULT_DTYPE.itemsize == ctypes.sizeof(OrResult)
         _lib = L
     return _lib
 
 
-def query(W, busy, kind, k, mode=MODE_ALL, a=1, b=1, metric=METRIC_WEIGHTED) -> dict:
-    """One query on an n x n weight matrix.  Returns a dict of the result."""
+def edge_array(edges):
+    """Flat int32 array of an edge list [(u, v), ...]."""
+    return np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1))
+
+
+def query(W, busy, kind, k, mode=MODE_ALL, a=1, b=1, metric=METRIC_WEIGHTED, edges=None) -> dict:
+    """One query on an n x n weight matrix.  Returns a dict of the result.
+    With ``edges`` (a list of (u, v) pairs on vertices 0..k-1) the pattern
+    is that graph and ``kind`` is ignored."""
     W = np.ascontiguousarray(np.asarray(W, dtype=np.uint8))
     n = W.shape[0]
     r = OrResult()
-    lib().or_query(n, W.ctypes.data, int(busy), int(kind), int(k), int(mode), int(a), int(b),
-                   int(metric), ctypes.byref(r))
+    if edges is None:
+        lib().or_query(n, W.ctypes.data, int(busy), int(kind), int(k), int(mode), int(a), int(b),
+                       int(metric), ctypes.byref(r))
+    else:
+        e = edge_array(edges)
+        lib().or_query_edges(n, W.ctypes.data, int(busy), int(k), len(e) // 2, e.ctypes.data,
+                             int(mode), int(a), int(b), int(metric), ctypes.byref(r))
     return {
         "count": r.count, "status": r.status, "key": r.key, "agg": r.agg, "pres": r.pres,
         "vertex_mask": r.vertex_mask, "links": r.links,
@@ -121,8 +139,11 @@ def pattern_edges(kind, k):
     return [(buf[2 * i], buf[2 * i + 1]) for i in range(ne)]
 
 
-def aut_count(kind, k) -> int:
-    return int(lib().or_aut_count(int(kind), int(k)))
+def aut_count(kind, k, edges=None) -> int:
+    if edges is None:
+        return int(lib().or_aut_count(int(kind), int(k)))
+    e = edge_array(edges)
+    return int(lib().or_aut_count_edges(int(k), len(e) // 2, e.ctypes.data))
 
 
 def pad_topologies(topologies):
@@ -136,12 +157,23 @@ def pad_topologies(topologies):
 
 
 def batch(topologies, q_topo, q_busy, kind, k, mode, a, b, nthreads: int | None = None,
-          metric=None):
-    """Evaluate queries independently.  Returns a structured numpy array."""
+          metric=None, edges=None):
+    """Evaluate queries independently.  Returns a structured numpy array.
+    ``edges``, if given, holds per query an edge list (the pattern of that
+    query, ``kind`` ignored) or None (the canonical pattern of ``kind``)."""
     tn, tw = pad_topologies(topologies)
     nq = len(q_topo)
     if metric is None:
         metric = np.zeros(nq, np.uint8)
+    q_ne = np.full(nq, -1, np.int32)
+    q_edges = np.zeros((nq, 56), np.int32)
+    if edges is not None:
+        for i, e in enumerate(edges):
+            if e is None:
+                continue
+            flat = edge_array(e)
+            q_ne[i] = len(flat) // 2
+            q_edges[i, :len(flat)] = flat[:56]
     cols = [np.ascontiguousarray(np.asarray(x, dtype=dt)) for x, dt in (
         (q_topo, np.int32), (q_busy, np.uint32), (kind, np.uint8), (k, np.uint8),
         (mode, np.uint8), (a, np.int16), (b, np.int16), (metric, np.uint8))]
@@ -149,7 +181,7 @@ def batch(topologies, q_topo, q_busy, kind, k, mode, a, b, nthreads: int | None 
     if nthreads is None:
         nthreads = os.cpu_count() or 1
     lib().or_batch(nq, tn.ctypes.data, tw.ctypes.data, *[c.ctypes.data for c in cols],
-                   out.ctypes.data, int(nthreads))
+                   q_ne.ctypes.data, q_edges.ctypes.data, out.ctypes.data, int(nthreads))
     return out
 
 

@@ -47,10 +47,12 @@ def effbw(x: int, y: int, z: int) -> float:
 
 
 def query(W, busy: int, kind: int, k: int, mode: int = 0, a: int = 1, b: int = 1,
-          metric: int = 0):
+          metric: int = 0, pattern=None):
+    """``pattern``: an explicit edge list on vertices 0..k-1 (``kind`` is then
+    ignored), e.g. a union of canonical patterns or a program-derived graph."""
     n = len(W)
     free = [v for v in range(n) if not (busy >> v) & 1]
-    E = edges(kind, k)
+    E = edges(kind, k) if pattern is None else [tuple(e) for e in pattern]
     count = 0
     best = None
     for phi in itertools.permutations(free, k):

@@ -13,7 +13,9 @@
  *     removed from G by state management (Sec. 3.6); R = the free vertices.
  *   - Pattern graph P on k vertices: ring, all-to-all or binary tree (Sec. 3.1,
  *     Fig. "Example application topology").  Canonical numbering, see
- *     or_pattern_edges().
+ *     or_pattern_edges().  Any other application graph (a union of those,
+ *     or one derived from a program, Sec. 3.1) is given as its edge list on
+ *     vertices 0..k-1 in the caller's numbering: or_query_edges().
  *   - Matches (Sec. 3.3): one-to-one maps phi from V(P) into R such that
  *     adjacent pattern vertices land on adjacent accelerators.  Because the
  *     paper assumes G fully connected (Sec. 3.2, every pair reachable through
@@ -112,12 +114,37 @@ int or_pattern_edges(int kind, int k, int *ep) {
   return ne;
 }
 
+/* A caller-supplied pattern: ne edges on vertices 0..k-1, each unordered
+ * pair at most once, no loops (a simple graph, as the canonical patterns). */
+static int check_edges(int k, int ne, const int *ep) {
+  if (k < 1 || k > OR_MAX_K || ne < 0 || ne > 28) return OR_EINVAL;
+  int seen[OR_MAX_K][OR_MAX_K];
+  memset(seen, 0, sizeof seen);
+  for (int e = 0; e < ne; ++e) {
+    int u = ep[2 * e], v = ep[2 * e + 1];
+    if (u < 0 || v < 0 || u >= k || v >= k || u == v || seen[u][v]) return OR_EINVAL;
+    seen[u][v] = seen[v][u] = 1;
+  }
+  return OR_OK;
+}
+
+static int aut_count_edges(int k, int ne, const int *ep);
+
 /* |Aut(P)| by brute force over all k! permutations sigma of V(P): sigma is an
  * automorphism iff it maps the edge set onto itself. */
 int or_aut_count(int kind, int k) {
   int ep[2 * 28];
   int ne = or_pattern_edges(kind, k, ep);
   if (ne < 0) return ne;
+  return aut_count_edges(k, ne, ep);
+}
+
+int or_aut_count_edges(int k, int ne, const int *ep) {
+  int rc = check_edges(k, ne, ep);
+  return rc ? rc : aut_count_edges(k, ne, ep);
+}
+
+static int aut_count_edges(int k, int ne, const int *ep) {
   int adj[OR_MAX_K][OR_MAX_K];
   memset(adj, 0, sizeof adj);
   for (int e = 0; e < ne; ++e) adj[ep[2 * e]][ep[2 * e + 1]] = adj[ep[2 * e + 1]][ep[2 * e]] = 1;
@@ -260,16 +287,17 @@ static int validate_topology(int n, const uint8_t *W) {
   return OR_OK;
 }
 
-/* One query against one hardware graph.  memo must hold 1<<n int32. */
-static int query_with_memo(int n, const uint8_t *W, uint32_t busy, int kind, int k, int mode,
-                           int a, int b, int metric, or_result *out, int32_t *memo) {
+/* One query of the pattern (k, ne, ep) against one hardware graph.  memo
+ * must hold 1<<n int32. */
+static int query_with_memo(int n, const uint8_t *W, uint32_t busy, int k, int ne, const int *ep,
+                           int mode, int a, int b, int metric, or_result *out, int32_t *memo) {
   memset(out, 0, sizeof *out);
   memset(out->mapping, 0xFF, sizeof out->mapping);
   out->key = INT32_MIN;
   int rc = validate_topology(n, W);
   if (rc) return out->status = rc;
   if (k > OR_MAX_K) return out->status = OR_EUNSUP;
-  if (k < 1 || kind < 0 || kind > 2 || mode < 0 || mode > 1 || a < 0 || b < 0 ||
+  if (k < 1 || check_edges(k, ne, ep) || mode < 0 || mode > 1 || a < 0 || b < 0 ||
       a > OR_MAX_AB || b > OR_MAX_AB || (n < 32 && (busy >> n) != 0) || metric < 0 || metric > 1)
     return out->status = OR_EINVAL;
   if (metric == OR_METRIC_EFFBW)
@@ -280,7 +308,8 @@ static int query_with_memo(int n, const uint8_t *W, uint32_t busy, int kind, int
   if (!s) return out->status = OR_ENOMEM;
   s->n = n; s->k = k; s->mode = mode; s->metric = metric; s->a = a; s->b = b; s->W = W;
   s->memo = memo;
-  s->ne = or_pattern_edges(kind, k, s->ep);
+  s->ne = ne;
+  memcpy(s->ep, ep, sizeof(int) * 2 * ne);
   for (int v = 0; v < n; ++v)
     if (!((busy >> v) & 1u)) { s->R[s->F++] = v; s->Rmask |= 1u << v; }
   for (uint32_t m = 0; m < (1u << n); ++m) memo[m] = -1;
@@ -305,14 +334,29 @@ static int query_with_memo(int n, const uint8_t *W, uint32_t busy, int kind, int
   return OR_OK;
 }
 
-int or_query(int n, const uint8_t *W, uint32_t busy, int kind, int k, int mode, int a, int b,
-             int metric, or_result *out) {
+/* The canonical pattern of (kind, k); ne = -1 when there is none. */
+static int kind_edges(int kind, int k, int *ep) {
+  if (k < 1 || k > OR_MAX_K) return -1;
+  int ne = or_pattern_edges(kind, k, ep);
+  return ne < 0 ? -1 : ne;
+}
+
+int or_query_edges(int n, const uint8_t *W, uint32_t busy, int k, int ne, const int *ep,
+                   int mode, int a, int b, int metric, or_result *out) {
   int nn = (n >= 1 && n <= OR_MAX_N) ? n : 1;
   int32_t *memo = (int32_t *)malloc(sizeof(int32_t) << nn);
   if (!memo) return OR_ENOMEM;
-  int rc = query_with_memo(n, W, busy, kind, k, mode, a, b, metric, out, memo);
+  int rc = query_with_memo(n, W, busy, k, ne, ep, mode, a, b, metric, out, memo);
   free(memo);
   return rc;
+}
+
+int or_query(int n, const uint8_t *W, uint32_t busy, int kind, int k, int mode, int a, int b,
+             int metric, or_result *out) {
+  int ep[2 * 28];
+  int ne = kind_edges(kind, k, ep);
+  if (k > OR_MAX_K) ne = 0; /* reported as unsupported, not invalid */
+  return or_query_edges(n, W, busy, k, ne, ep, mode, a, b, metric, out);
 }
 
 /* ---------------- batch driver: static split of queries over threads ------ */
@@ -325,6 +369,7 @@ typedef struct {
   const uint32_t *q_busy;
   const uint8_t *q_kind, *q_k, *q_mode, *q_metric;
   const int16_t *q_a, *q_b;
+  const int32_t *q_ne, *q_edges; /* optional per-query edge lists (ne < 0: use kind) */
   or_result *out;
 } or_job;
 
@@ -342,8 +387,17 @@ static void *batch_worker(void *arg) {
     }
     for (int u = 0; u < n; ++u)
       for (int v = 0; v < n; ++v) W[u * n + v] = j->topo_W[(size_t)t * 256 + u * 16 + v];
-    query_with_memo(n, W, j->q_busy[q], j->q_kind[q], j->q_k[q], j->q_mode[q], j->q_a[q],
-                    j->q_b[q], j->q_metric[q], &j->out[q], memo);
+    int ep[2 * 28];
+    int ne;
+    if (j->q_ne && j->q_ne[q] >= 0) {
+      ne = j->q_ne[q] <= 28 ? j->q_ne[q] : -1;
+      for (int i = 0; i < 2 * ne; ++i) ep[i] = j->q_edges[(size_t)q * 56 + i];
+    } else {
+      ne = kind_edges(j->q_kind[q], j->q_k[q], ep);
+      if (j->q_k[q] > OR_MAX_K) ne = 0;
+    }
+    query_with_memo(n, W, j->q_busy[q], j->q_k[q], ne, ep, j->q_mode[q], j->q_a[q], j->q_b[q],
+                    j->q_metric[q], &j->out[q], memo);
   }
   free(memo);
   return NULL;
@@ -352,14 +406,15 @@ static void *batch_worker(void *arg) {
 int or_batch(int nq, const int32_t *topo_n, const uint8_t *topo_W, const int32_t *q_topo,
              const uint32_t *q_busy, const uint8_t *q_kind, const uint8_t *q_k,
              const uint8_t *q_mode, const int16_t *q_a, const int16_t *q_b,
-             const uint8_t *q_metric, or_result *out, int nthreads) {
+             const uint8_t *q_metric, const int32_t *q_ne, const int32_t *q_edges,
+             or_result *out, int nthreads) {
   if (nthreads < 1) nthreads = 1;
   if (nthreads > 256) nthreads = 256;
   pthread_t th[256];
   or_job jobs[256];
   for (int t = 0; t < nthreads; ++t) {
-    jobs[t] = (or_job){t, nthreads, nq, topo_n, topo_W, q_topo, q_busy, q_kind, q_k, q_mode,
-                       q_metric, q_a, q_b, out};
+    jobs[t] = (or_job){t,   nthreads, nq,  topo_n, topo_W, q_topo, q_busy, q_kind, q_k,
+                       q_mode, q_metric, q_a, q_b, q_ne, q_edges, out};
     if (pthread_create(&th[t], NULL, batch_worker, &jobs[t]) != 0) {
       batch_worker(&jobs[t]);
       th[t] = 0;
