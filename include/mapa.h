@@ -65,10 +65,16 @@ extern "C" {
  * Pattern vertex i is position i of the mapping tuple.
  *   MAPA_RING:       k=1 no edge; k=2 the edge (0,1); k>=3 edges (i, i+1 mod k)
  *   MAPA_ALL_TO_ALL: every pair i<j
- *   MAPA_TREE:       binary heap, vertex i>0 joined to (i-1)/2                */
+ *   MAPA_TREE:       binary heap, vertex i>0 joined to (i-1)/2
+ *   MAPA_PATTERN_BASE + id: the application graph registered by
+ *                    mapa_create_pattern under that id (0 <= id <
+ *                    MAPA_MAX_PATTERNS); kinds 3 .. MAPA_PATTERN_BASE - 1 are
+ *                    invalid                                                  */
 #define MAPA_RING 0
 #define MAPA_ALL_TO_ALL 1
 #define MAPA_TREE 2
+#define MAPA_PATTERN_BASE 16
+#define MAPA_MAX_PATTERNS 240
 
 /* ---- match modes (Sec. 3.2 / 3.3) -------------------------------------------
  * MAPA_ALL_INJECTIVE: the hardware graph is taken as fully connected (every
@@ -108,8 +114,9 @@ typedef struct mapa_ctx mapa_ctx; /* opaque; owns all device memory it uses */
  * 16 bytes, no padding. */
 typedef struct {
   int32_t server;   /* server id from mapa_create_topology                      */
-  uint8_t kind;     /* MAPA_RING / MAPA_ALL_TO_ALL / MAPA_TREE                   */
-  uint8_t k;        /* pattern vertices, 1..8                                   */
+  uint8_t kind;     /* MAPA_RING / MAPA_ALL_TO_ALL / MAPA_TREE, or
+                       MAPA_PATTERN_BASE + id of a registered pattern            */
+  uint8_t k;        /* pattern vertices, 1..8 (a registered pattern's own k)    */
   uint8_t mode;     /* MAPA_ALL_INJECTIVE or MAPA_LINKED                        */
   uint8_t commit;   /* 1: on MAPA_RES_OK mark the chosen vertices busy          */
   int16_t a;        /* key = a*AggBW + b*PreservedBW, 0 <= a, b <= 1024.        */
@@ -158,7 +165,7 @@ const char *mapa_last_error(void);
  * context with device = -1 (argument checks run; compute calls then return
  * MAPA_ERR_NO_DEVICE).  enum_buffer_bytes sizes the prefix work-list of one
  * in-flight batch (0 = default 256 MiB); a batch of nq queries needs at least
- * 8 * (nq + 102816) bytes of it, else MAPA_ERR_ADMISSION.  *out receives the
+ * 8 * (nq + 137088) bytes of it, else MAPA_ERR_ADMISSION.  *out receives the
  * context. */
 int32_t mapa_ctx_create(int32_t device, size_t enum_buffer_bytes, mapa_ctx **out);
 
@@ -176,6 +183,26 @@ int32_t mapa_ctx_destroy(mapa_ctx *ctx);
  * first_server .. first_server + num_servers - 1. */
 int32_t mapa_create_topology(mapa_ctx *ctx, int32_t n, const uint8_t *W, int32_t num_servers,
                              int32_t *topo_id, int32_t *first_server);
+
+/* Register an application graph that is not one of the canonical shapes
+ * (Sec. 3.1: a union of them, or a graph derived from a program's
+ * communication), for use as mapa_query.kind / mapa_request.kind.
+ *   k:         1..8 pattern vertices (k > 8: MAPA_ERR_UNSUPPORTED), numbered
+ *              0..k-1; vertex i is position i of the mapping tuple, so the
+ *              tie-break is lexicographic in this numbering, and positions
+ *              are placed in this order (for MAPA_LINKED a numbering in which
+ *              every vertex after the first has an earlier neighbour prunes
+ *              soonest).
+ *   num_edges: 0 .. k(k-1)/2.
+ *   edges:     host pointer, 2 * num_edges uint8 values, pairs (u, v) with
+ *              u, v < k, u != v, each unordered pair at most once (else
+ *              MAPA_ERR_INVALID_ARG).  Copied; caller keeps it.
+ * *kind_out (host pointer, may be NULL) receives MAPA_PATTERN_BASE + id, ids
+ * counting up from 0 per context; MAPA_ERR_STATE once MAPA_MAX_PATTERNS are
+ * registered.  Registered patterns are immutable; the call may run while
+ * batches or the serving loop are in flight (earlier ids are not touched). */
+int32_t mapa_create_pattern(mapa_ctx *ctx, int32_t k, int32_t num_edges, const uint8_t *edges,
+                            int32_t *kind_out);
 
 /* Overwrite the busy masks of `count` servers (bit v set = accelerator v is
  * allocated; Sec. 3.6).  server_ids / busy_masks: host pointers (synchronous

@@ -26,6 +26,7 @@ ERRORS = {
 ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_OOM, ERR_DEVICE, ERR_NOT_BUSY = -1, -2, -3, -4, -5
 ERR_UNKNOWN_SERVER, ERR_ADMISSION, ERR_NO_DEVICE, ERR_STATE = -6, -7, -8, -9
 RING, ALL_TO_ALL, TREE = 0, 1, 2
+PATTERN_BASE, MAX_PATTERNS = 16, 240
 ALL_INJECTIVE, LINKED = 0, 1
 METRIC_WEIGHTED, METRIC_EFFBW = 0, 1
 RES_OK, RES_NOFIT, RES_CONFLICT, RES_INVALID = 0, 1, 2, 3
@@ -90,6 +91,7 @@ SIGNATURES = {
     "mapa_ctx_create": (_I32, [_I32, _SZ, ctypes.POINTER(_P)]),
     "mapa_ctx_destroy": (_I32, [_P]),
     "mapa_create_topology": (_I32, [_P, _I32, _P, _I32, _P, _P]),
+    "mapa_create_pattern": (_I32, [_P, _I32, _I32, _P, _P]),
     "mapa_set_busy": (_I32, [_P, _I32, _P, _P, _U32, _P]),
     "mapa_get_busy": (_I32, [_P, _I32, _P, _P]),
     "mapa_query_batch": (_I32, [_P, _P, _I32, _P, _U32, _P]),
@@ -192,6 +194,15 @@ class Context:
                                          ctypes.byref(tid), ctypes.byref(first)),
               "mapa_create_topology")
         return tid.value, first.value
+
+    def create_pattern(self, k: int, edges) -> int:
+        """Register an application graph given as (u, v) pairs on vertices
+        0..k-1; returns the kind value that names it in queries/requests."""
+        e = np.ascontiguousarray(np.asarray(edges, dtype=np.uint8).reshape(-1))
+        kind = ctypes.c_int32()
+        check(lib().mapa_create_pattern(self.h, int(k), len(e) // 2, e.ctypes.data if len(e) else None,
+                                        ctypes.byref(kind)), "mapa_create_pattern")
+        return kind.value
 
     def load_servers(self, topologies, server_topo) -> np.ndarray:
         """Create one server per entry of server_topo; returns the library's

@@ -84,6 +84,13 @@ struct mapa_ctx {
   uint16_t *d_eff_rank = nullptr;  // Eq. 2 tables (eff_off layout)
   int32_t *d_eff_key = nullptr;
 
+  // registered patterns (append-only; slot i = kind MAPA_PATTERN_BASE + i)
+  std::vector<unsigned long long> pat_nbtab;  // host mirror, back-neighbour tables
+  std::vector<uint8_t> pat_k;                 // host mirror, k per slot (0 = free)
+  int32_t npat = 0;
+  unsigned long long *d_pat_nbtab = nullptr;  // [MAPA_MAX_PATTERNS]
+  uint8_t *d_pat_k = nullptr;                 // [MAPA_MAX_PATTERNS], zero = free
+
   // servers
   std::vector<int32_t> server_topo;  // host mirror, immutable per server
   int32_t *d_server_topo = nullptr;

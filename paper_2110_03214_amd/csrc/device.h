@@ -84,16 +84,21 @@ __device__ __forceinline__ int set_weight(const uint32_t *trow, int wpr, uint32_
 __device__ __forceinline__ Plan make_plan(const mapa_query &q, int32_t nservers,
                                           const int32_t *server_topo, const int32_t *topo_n,
                                           const uint8_t *topo_maxw, const uint32_t *busy,
-                                          const uint32_t *rows, int wpr) {
+                                          const uint32_t *rows, int wpr,
+                                          const unsigned long long *pat_nbtab,
+                                          const uint8_t *pat_k) {
   Plan p = {};
   p.server = q.server;
-  p.kind = q.kind;
+  const bool registered = q.kind >= MAPA_PATTERN_BASE;
+  p.kind = registered ? (uint8_t)kKindPattern : q.kind;
   p.k = q.k;
   p.mode = q.mode;
   p.a = q.a;
   p.b = q.b;
   p.commit = q.commit;
-  const bool ok = q.server >= 0 && q.server < nservers && q.kind <= 2 && q.k >= 1 &&
+  // a registered pattern's slot holds its k (0 while the slot is free)
+  const bool kind_ok = q.kind <= MAPA_TREE || (registered && pat_k[q.kind - MAPA_PATTERN_BASE] == q.k);
+  const bool ok = q.server >= 0 && q.server < nservers && kind_ok && q.k >= 1 &&
                   q.k <= kMaxK && q.mode <= 1 && q.commit <= 1 && q.a >= 0 &&
                   q.a <= MAPA_MAX_AB && q.b >= 0 && q.b <= MAPA_MAX_AB &&
                   (q.metric == MAPA_METRIC_WEIGHTED || q.metric == MAPA_METRIC_EFFBW);
@@ -118,7 +123,7 @@ __device__ __forceinline__ Plan make_plan(const mapa_query &q, int32_t nservers,
   // link mix of the edges placed so far, which starts empty
   p.kp0 = q.metric == MAPA_METRIC_EFFBW ? 0
                                         : (int32_t)q.b * set_weight(rows + (size_t)t * kTopoWords * wpr, wpr, R);
-  p.nbtab = c_tab.nbtab[q.kind][q.k];
+  p.nbtab = registered ? pat_nbtab[q.kind - MAPA_PATTERN_BASE] : c_tab.nbtab[q.kind][q.k];
   p.status = q.k > F ? kPlanNofit : kPlanOk;
   return p;
 }
@@ -210,8 +215,9 @@ __device__ __forceinline__ uint32_t adjacency(const uint32_t *r) {
 // candidate set for position p.
 //   ALL mode: computed per pattern kind (wave-uniform): ring -> the previous
 //   vertex, plus vertex 0 at the closing position; tree -> the parent
-//   (heap numbering); all-to-all -> every chosen vertex.  Candidates: every
-//   free vertex not chosen yet.
+//   (heap numbering); all-to-all -> every chosen vertex; a registered pattern
+//   -> the vertices at the positions its back-neighbour table names.
+//   Candidates: every free vertex not chosen yet.
 //   LINKED mode: from the back-neighbour table; candidates must also be
 //   adjacent to each of those vertices.
 //   KIND >= 0 fixes the pattern kind at compile time (ALL mode inside the
@@ -228,8 +234,12 @@ __device__ __forceinline__ void node_masks(const LaneState &s, int kind, uint32_
     } else if (kd == MAPA_RING) {
       nbm = p > 0 ? (1u << prev) : 0u;
       if (LAST && s.k >= 3) nbm |= 1u << (code & 15u);
-    } else {
+    } else if (kd == MAPA_TREE) {
       nbm = p > 0 ? (1u << ((code >> (4 * ((p - 1) >> 1))) & 15u)) : 0u;
+    } else {  // registered pattern: its back-neighbour table
+      nbm = 0;
+      for (uint32_t m = (uint32_t)(s.nbtab >> (8 * p)) & 0xFFu; m; m &= m - 1)
+        nbm |= 1u << ((code >> (4 * __builtin_ctz(m))) & 15u);
     }
   } else {
     const uint32_t nbpos = (uint32_t)(s.nbtab >> (8 * p)) & 0xFFu;
@@ -269,10 +279,15 @@ __device__ __forceinline__ void pair_level(LaneState &s, uint32_t rest, uint32_t
     fixm = s.R & ~rest;
   } else if constexpr (KIND == MAPA_RING) {
     if (s.k >= 3) fixm = 1u << (code & 15u);
-  } else {
+  } else if constexpr (KIND == MAPA_TREE) {
     const int parent = (s.k - 2) >> 1;  // heap parent of position k-1
     alpha = parent == p;
     if (!alpha) fixm = 1u << ((code >> (4 * parent)) & 15u);
+  } else {  // registered pattern: back-neighbours of position k-1 from its table
+    const uint32_t nbl = (uint32_t)(s.nbtab >> (8 * (s.k - 1))) & 0xFFu;
+    alpha = (nbl >> p) & 1u;
+    for (uint32_t m = nbl & ~(1u << p); m; m &= m - 1)
+      fixm |= 1u << ((code >> (4 * __builtin_ctz(m))) & 15u);
   }
   const uint32_t nb2 = nbm | (nbm << 16), rest2 = rest | (rest << 16), fix2 = fixm | (fixm << 16);
   const uint32_t *prow = s.trow + 16;  // packed-weight rows
@@ -602,14 +617,18 @@ __device__ __forceinline__ void item_search(const Plan *pp, const uint32_t *trow
       expand<WPR, false, MAPA_RING, PAIR, false>(s, kind_w, L, rest, code, kp, d, prev, fp_w);
     else if (kind_w == MAPA_ALL_TO_ALL)
       expand<WPR, false, MAPA_ALL_TO_ALL, PAIR, false>(s, kind_w, L, rest, code, kp, d, prev, fp_w);
-    else
+    else if (kind_w == MAPA_TREE)
       expand<WPR, false, MAPA_TREE, PAIR, false>(s, kind_w, L, rest, code, kp, d, prev, fp_w);
+    else
+      expand<WPR, false, kKindPattern, PAIR, false>(s, kind_w, L, rest, code, kp, d, prev, fp_w);
   } else if (kind_w == MAPA_RING)
     expand<WPR, false, MAPA_RING, PAIR>(s, kind_w, L, rest, code, kp, d, prev, fp_w);
   else if (kind_w == MAPA_ALL_TO_ALL)
     expand<WPR, false, MAPA_ALL_TO_ALL, PAIR>(s, kind_w, L, rest, code, kp, d, prev, fp_w);
-  else
+  else if (kind_w == MAPA_TREE)
     expand<WPR, false, MAPA_TREE, PAIR>(s, kind_w, L, rest, code, kp, d, prev, fp_w);
+  else
+    expand<WPR, false, kKindPattern, PAIR>(s, kind_w, L, rest, code, kp, d, prev, fp_w);
 
   int bkey = -1;
   uint32_t bcode = 0;

@@ -28,7 +28,8 @@ __global__ __launch_bounds__(256) void k_fused(FusedArgs f) {
   const uint32_t span = (uint32_t)f.bpq * blockDim.x;
   if (tid == 0) {
     const mapa_query q = f.q[i];
-    Plan p = make_plan(q, f.nservers, f.server_topo, f.topo_n, f.topo_maxw, f.busy, f.rows, WPR);
+    Plan p = make_plan(q, f.nservers, f.server_topo, f.topo_n, f.topo_maxw, f.busy, f.rows, WPR,
+                       f.pat_nbtab, f.pat_k);
     if (p.status == kPlanOk) {
       int d = 0;
       while (d < p.k - 1 && c_tab.perm[p.F][d] < (unsigned long long)span) ++d;

@@ -116,6 +116,8 @@ void fill_args(mapa_ctx *c, const Workspace &w, BatchArgs &a) {
   a.ntopo = (int32_t)c->topo_n.size();
   a.wpr = c->wpr;
   a.split_d = c->d_split;
+  a.pat_nbtab = c->d_pat_nbtab;
+  a.pat_k = c->d_pat_k;
   const int threads = c->tuning.threads_per_block;
   const size_t lds_bytes = (size_t)a.ntopo * kTopoWords * c->wpr * sizeof(uint32_t);
   a.rows_in_lds = lds_bytes <= 48 * 1024 ? 1 : 0;
@@ -180,6 +182,8 @@ int32_t enqueue_fused(mapa_ctx *c, const Workspace &w, const mapa_query *q, mapa
   f.topo_maxw = c->d_topo_maxw;
   f.eff_rank = c->d_eff_rank;
   f.eff_key = c->d_eff_key;
+  f.pat_nbtab = c->d_pat_nbtab;
+  f.pat_k = c->d_pat_k;
   f.self_check_failures = &w.d_ctr->self_check_failures;
   f.acc_count = w.d_acc_count;
   f.acc_best = w.d_acc_best;
@@ -486,7 +490,15 @@ int32_t validate_query(const mapa_ctx *c, const mapa_query &q, int32_t i) {
     return fail(MAPA_ERR_UNKNOWN_SERVER, "query %d: unknown server %d", i, q.server);
   if (q.k > kMaxK) return fail(MAPA_ERR_UNSUPPORTED, "query %d: k=%d > %d", i, q.k, kMaxK);
   if (q.k < 1) return fail(MAPA_ERR_INVALID_ARG, "query %d: k=%d < 1", i, q.k);
-  if (q.kind > 2) return fail(MAPA_ERR_INVALID_ARG, "query %d: kind=%d", i, q.kind);
+  if (q.kind > MAPA_TREE) {
+    const int id = q.kind - MAPA_PATTERN_BASE;
+    if (id < 0 || id >= c->npat)
+      return fail(MAPA_ERR_INVALID_ARG, "query %d: kind=%d is neither a pattern kind nor a "
+                  "registered pattern", i, q.kind);
+    if (c->pat_k[id] != q.k)
+      return fail(MAPA_ERR_INVALID_ARG, "query %d: k=%d but registered pattern %d has %d "
+                  "vertices", i, q.k, id, c->pat_k[id]);
+  }
   if (q.mode > 1) return fail(MAPA_ERR_INVALID_ARG, "query %d: mode=%d", i, q.mode);
   if (q.commit > 1) return fail(MAPA_ERR_INVALID_ARG, "query %d: commit=%d", i, q.commit);
   if (q.a < 0 || q.a > MAPA_MAX_AB || q.b < 0 || q.b > MAPA_MAX_AB)
@@ -514,6 +526,8 @@ int32_t mapa_ctx_create(int32_t device, size_t enum_buffer_bytes, mapa_ctx **out
   *out = nullptr;
   mapa_ctx *c = new (std::nothrow) mapa_ctx();
   if (!c) return fail(MAPA_ERR_OOM, "context allocation failed");
+  c->pat_nbtab.assign(MAPA_MAX_PATTERNS, 0);
+  c->pat_k.assign(MAPA_MAX_PATTERNS, 0);
   c->enum_bytes = enum_buffer_bytes ? enum_buffer_bytes : kDefaultEnumBytes;
   if (device < 0) {  // validation-only context
     *out = c;
@@ -549,6 +563,12 @@ int32_t mapa_ctx_create(int32_t device, size_t enum_buffer_bytes, mapa_ctx **out
   rc = upload_effbw_tables(c);
   if (rc) return bail(rc);
   if (dev_alloc(&c->d_flag, 1) != hipSuccess) return bail(fail(MAPA_ERR_OOM, "flag allocation failed"));
+  if (dev_alloc(&c->d_pat_nbtab, MAPA_MAX_PATTERNS) != hipSuccess ||
+      dev_alloc(&c->d_pat_k, MAPA_MAX_PATTERNS) != hipSuccess)
+    return bail(fail(MAPA_ERR_OOM, "pattern table allocation failed"));
+  if (hipMemset(c->d_pat_nbtab, 0, MAPA_MAX_PATTERNS * sizeof(unsigned long long)) != hipSuccess ||
+      hipMemset(c->d_pat_k, 0, MAPA_MAX_PATTERNS) != hipSuccess)
+    return bail(fail(MAPA_ERR_DEVICE, "pattern table initialisation failed"));
   if (hipDeviceSynchronize() != hipSuccess) return bail(fail(MAPA_ERR_DEVICE, "device init failed"));
   *out = c;
   return MAPA_OK;
@@ -566,6 +586,8 @@ int32_t mapa_ctx_destroy(mapa_ctx *c) {
       (void)hipEventDestroy(e.stop);
     }
     for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.exec);
+    dev_free(c->d_pat_nbtab);
+    dev_free(c->d_pat_k);
     dev_free(c->d_topo_n);
     dev_free(c->d_topo_W);
     dev_free(c->d_rows);
@@ -648,6 +670,43 @@ int32_t mapa_create_topology(mapa_ctx *c, int32_t n, const uint8_t *W, int32_t n
   c->server_topo.insert(c->server_topo.end(), (size_t)num_servers, tid);
   if (topo_id) *topo_id = tid;
   if (first_server) *first_server = first;
+  return MAPA_OK;
+}
+
+int32_t mapa_create_pattern(mapa_ctx *c, int32_t k, int32_t num_edges, const uint8_t *edges,
+                            int32_t *kind_out) {
+  if (!c) return fail(MAPA_ERR_INVALID_ARG, "ctx is NULL");
+  if (k > kMaxK) return fail(MAPA_ERR_UNSUPPORTED, "pattern of %d vertices > %d", k, kMaxK);
+  if (k < 1) return fail(MAPA_ERR_INVALID_ARG, "pattern of %d vertices", k);
+  if (num_edges < 0 || num_edges > k * (k - 1) / 2)
+    return fail(MAPA_ERR_INVALID_ARG, "%d edges on %d vertices", num_edges, k);
+  if (num_edges > 0 && !edges) return fail(MAPA_ERR_INVALID_ARG, "edges is NULL");
+  if (c->npat >= MAPA_MAX_PATTERNS)
+    return fail(MAPA_ERR_STATE, "all %d pattern slots are taken", MAPA_MAX_PATTERNS);
+  // back-neighbour table: edge (u, v) with u < v makes u an earlier neighbour of v
+  uint8_t nb[kMaxK] = {};
+  for (int e = 0; e < num_edges; ++e) {
+    const int u = edges[2 * e], v = edges[2 * e + 1];
+    if (u >= k || v >= k || u == v)
+      return fail(MAPA_ERR_INVALID_ARG, "edge %d = (%d, %d) on a pattern of %d vertices", e, u, v, k);
+    const int lo = std::min(u, v), hi = std::max(u, v);
+    if (nb[hi] & (1u << lo)) return fail(MAPA_ERR_INVALID_ARG, "edge (%d, %d) given twice", lo, hi);
+    nb[hi] |= (uint8_t)(1u << lo);
+  }
+  unsigned long long tab = 0;
+  for (int p = 0; p < k; ++p) tab |= (unsigned long long)nb[p] << (8 * p);
+  const int id = c->npat;
+  if (c->has_device) {
+    if (hipSetDevice(c->device) != hipSuccess) return fail(MAPA_ERR_DEVICE, "hipSetDevice failed");
+    // the table first, then k: a slot is valid to the kernels once its k matches
+    const uint8_t kk = (uint8_t)k;
+    MAPA_HIPCHK(hipMemcpy(c->d_pat_nbtab + id, &tab, sizeof tab, hipMemcpyHostToDevice));
+    MAPA_HIPCHK(hipMemcpy(c->d_pat_k + id, &kk, 1, hipMemcpyHostToDevice));
+  }
+  c->pat_nbtab[id] = tab;
+  c->pat_k[id] = (uint8_t)k;
+  c->npat = id + 1;
+  if (kind_out) *kind_out = MAPA_PATTERN_BASE + id;
   return MAPA_OK;
 }
 

@@ -56,7 +56,7 @@ __global__ __launch_bounds__(256) void k_prepare(BatchArgs a) {
   if (i < a.nq) {
     const mapa_query q = a.q[i];
     const Plan p = make_plan(q, a.nservers, a.server_topo, a.topo_n, a.topo_maxw, a.busy, a.rows,
-                             a.wpr);
+                             a.wpr, a.pat_nbtab, a.pat_k);
     if (p.status == kPlanOk) {
       leaves = c_tab.perm[p.F][p.k];
       const uint8_t *sd = a.split_d + ((size_t)p.F * (kMaxK + 1) + p.k) * kNumSplits;
@@ -427,13 +427,15 @@ hipError_t launch_batch_front(const BatchArgs &a, hipStream_t s) {
 }
 
 hipError_t launch_enumerate(const BatchArgs &a, hipStream_t s) {
-  if (a.wpr == 1 && a.pair >= 12) return launch_enum_pair12(a, s);
+  if (a.wpr == 1 && a.pair >= 12)
+    return a.rows_in_lds ? launch_enum_pair12_lds(a, s) : launch_enum_pair12_glb(a, s);
   if (a.wpr == 1 && a.pair >= 8) return launch_enum_pair8(a, s);
   return launch_enum_plain(a, s);
 }
 
 int enumerate_occupancy(int wpr, int rows_in_lds, int pair, int threads, size_t lds_bytes) {
-  if (wpr == 1 && pair >= 12) return occ_enum_pair12(rows_in_lds, threads, lds_bytes);
+  if (wpr == 1 && pair >= 12)
+    return rows_in_lds ? occ_enum_pair12_lds(threads, lds_bytes) : occ_enum_pair12_glb(threads, lds_bytes);
   if (wpr == 1 && pair >= 8) return occ_enum_pair8(rows_in_lds, threads, lds_bytes);
   return occ_enum_plain(wpr, rows_in_lds, threads, lds_bytes);
 }
@@ -442,7 +444,8 @@ int enumerate_occupancy(int wpr, int rows_in_lds, int pair, int threads, size_t 
 hipError_t upload_tables(const Tables &t) {
   hipError_t e = upload_tables_front(t);
   if (e == hipSuccess) e = upload_tables_fused(t);
-  if (e == hipSuccess) e = upload_tables_enum_pair12(t);
+  if (e == hipSuccess) e = upload_tables_enum_pair12_lds(t);
+  if (e == hipSuccess) e = upload_tables_enum_pair12_glb(t);
   if (e == hipSuccess) e = upload_tables_enum_pair8(t);
   if (e == hipSuccess) e = upload_tables_enum_plain(t);
   return e;

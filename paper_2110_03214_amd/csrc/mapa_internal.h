@@ -23,13 +23,15 @@ constexpr int kSplitWhole = kNumSplits - 1;
 // kind, and in ALL mode of the same shape, so the 64 lanes of a wave run in
 // lock step.
 constexpr int kFp = kMaxN + 1;                      // F' in 0..16
-constexpr int kNumBuckets = 2 * 2 * 3 * kMaxK * kFp;  // 1632
+constexpr int kKinds = 4;        // ring, all-to-all, tree, registered pattern
+constexpr int kKindPattern = 3;  // bucket and template kind of every registered pattern
+constexpr int kNumBuckets = 2 * 2 * kKinds * kMaxK * kFp;  // 2176
 constexpr int kChunk = 64;                          // items per wave-chunk (one per lane)
 constexpr int kPadReserve = (kChunk - 1) * kNumBuckets;
 constexpr uint32_t kInvalidItem = 0xFFFFFFFFu;
 
 __host__ __device__ inline int bucket_id(int metric, int mode, int kind, int L, int Fp) {
-  return (((metric * 2 + mode) * 3 + kind) * kMaxK + (L - 1)) * kFp + Fp;
+  return (((metric * 2 + mode) * kKinds + kind) * kMaxK + (L - 1)) * kFp + Fp;
 }
 
 // Eq. 2 tables, one block per pattern edge count E = 0..28: entry
@@ -137,6 +139,8 @@ struct BatchArgs {
   int32_t ntopo;
   int32_t wpr;
   const uint8_t *split_d;  // [F][k][j], see kSplitTable
+  const unsigned long long *pat_nbtab;  // [MAPA_MAX_PATTERNS] registered patterns
+  const uint8_t *pat_k;                 // [MAPA_MAX_PATTERNS] their k (0: free slot)
   // tuning
   unsigned long long lanes;  // resident enumeration lanes
   uint32_t mean_leaves;      // smallest mean item size the split may take
@@ -166,6 +170,8 @@ struct FusedArgs {
   const uint8_t *topo_maxw;
   const uint16_t *eff_rank;
   const int32_t *eff_key;
+  const unsigned long long *pat_nbtab;
+  const uint8_t *pat_k;
   uint32_t *self_check_failures;
   unsigned long long *acc_count, *acc_best;  // per query, zero on entry and exit
   uint32_t *done;                            // per query, zero on entry and exit
@@ -177,13 +183,16 @@ hipError_t launch_fused(const FusedArgs &f, hipStream_t s);
 // per translation unit: constant-table upload, enumeration launch and occupancy
 hipError_t upload_tables_front(const Tables &t);
 hipError_t upload_tables_fused(const Tables &t);
-hipError_t upload_tables_enum_pair12(const Tables &t);
+hipError_t upload_tables_enum_pair12_lds(const Tables &t);
+hipError_t upload_tables_enum_pair12_glb(const Tables &t);
 hipError_t upload_tables_enum_pair8(const Tables &t);
 hipError_t upload_tables_enum_plain(const Tables &t);
-hipError_t launch_enum_pair12(const BatchArgs &a, hipStream_t s);
+hipError_t launch_enum_pair12_lds(const BatchArgs &a, hipStream_t s);
+hipError_t launch_enum_pair12_glb(const BatchArgs &a, hipStream_t s);
 hipError_t launch_enum_pair8(const BatchArgs &a, hipStream_t s);
 hipError_t launch_enum_plain(const BatchArgs &a, hipStream_t s);
-int occ_enum_pair12(int rows_in_lds, int threads, size_t lds_bytes);
+int occ_enum_pair12_lds(int threads, size_t lds_bytes);
+int occ_enum_pair12_glb(int threads, size_t lds_bytes);
 int occ_enum_pair8(int rows_in_lds, int threads, size_t lds_bytes);
 int occ_enum_plain(int wpr, int rows_in_lds, int threads, size_t lds_bytes);
 hipError_t launch_batch_front(const BatchArgs &a, hipStream_t s);   // prepare .. expand

@@ -539,7 +539,13 @@ int32_t mapa_serve_submit(mapa_ctx *c, const mapa_request *reqs, int32_t n) {
     if (r.server < 0 || (size_t)r.server >= c->server_topo.size())
       return fail(MAPA_ERR_UNKNOWN_SERVER, "request %d: unknown server %d", i, r.server);
     if (r.k > kMaxK) return fail(MAPA_ERR_UNSUPPORTED, "request %d: k=%d > %d", i, r.k, kMaxK);
-    if (r.k < 1 || r.kind > 2 || r.mode > 1 || r.a < 0 || r.a > MAPA_MAX_AB || r.b < 0 ||
+    if (r.kind > MAPA_TREE) {
+      const int id = r.kind - MAPA_PATTERN_BASE;
+      if (id < 0 || id >= c->npat || c->pat_k[id] != r.k)
+        return fail(MAPA_ERR_INVALID_ARG, "request %d: kind=%d with k=%d is neither a pattern "
+                    "kind nor a registered pattern of that size", i, r.kind, r.k);
+    }
+    if (r.k < 1 || r.mode > 1 || r.a < 0 || r.a > MAPA_MAX_AB || r.b < 0 ||
         r.b > MAPA_MAX_AB || r.metric > MAPA_METRIC_EFFBW || r.reserved1 != 0)
       return fail(MAPA_ERR_INVALID_ARG, "request %d: malformed field", i);
     if (r.metric == MAPA_METRIC_EFFBW && c->topo_maxw[c->server_topo[r.server]] > 2)

@@ -128,6 +128,30 @@ def test_query_validation(vctx):
     assert code_of(lambda: vctx.query_batch(B.pack_queries([0], [0], [3], metric=[1]))) == B.ERR_NO_DEVICE
 
 
+def test_pattern_registration_and_query_kinds(vctx):
+    vctx.create_topology(cube_mesh(), 2)
+    star = [(0, 1), (0, 2), (0, 3)]
+    kind = vctx.create_pattern(4, star)
+    assert kind == B.PATTERN_BASE
+    assert vctx.create_pattern(3, []) == B.PATTERN_BASE + 1
+    assert code_of(lambda: vctx.create_pattern(9, [])) == B.ERR_UNSUPPORTED
+    assert code_of(lambda: vctx.create_pattern(0, [])) == B.ERR_INVALID_ARG
+    assert code_of(lambda: vctx.create_pattern(3, [(0, 3)])) == B.ERR_INVALID_ARG
+    assert code_of(lambda: vctx.create_pattern(3, [(1, 1)])) == B.ERR_INVALID_ARG
+    assert code_of(lambda: vctx.create_pattern(3, [(0, 1), (1, 0)])) == B.ERR_INVALID_ARG
+    assert "twice" in B.lib().mapa_last_error().decode()
+    assert code_of(lambda: vctx.create_pattern(3, [(0, 1), (1, 2), (0, 2), (0, 1)])) == B.ERR_INVALID_ARG
+    # a registered kind with its own k passes validation, then needs a device
+    assert code_of(lambda: vctx.query_batch(B.pack_queries([0], [kind], [4]))) == B.ERR_NO_DEVICE
+    assert code_of(lambda: vctx.query_batch(B.pack_queries([0], [kind], [5]))) == B.ERR_INVALID_ARG
+    assert code_of(lambda: vctx.query_batch(B.pack_queries([0], [kind + 2], [4]))) == B.ERR_INVALID_ARG
+    assert code_of(lambda: vctx.query_batch(B.pack_queries([0], [3], [4]))) == B.ERR_INVALID_ARG
+    # the table holds MAPA_MAX_PATTERNS patterns, then refuses
+    for _ in range(B.MAX_PATTERNS - 2):
+        vctx.create_pattern(2, [(0, 1)])
+    assert code_of(lambda: vctx.create_pattern(2, [(0, 1)])) == B.ERR_STATE
+
+
 def test_release_validation(vctx):
     vctx.create_topology(cube_mesh(), 2)
     assert code_of(lambda: vctx.release([(5 << 32) | 1])) == B.ERR_UNKNOWN_SERVER
