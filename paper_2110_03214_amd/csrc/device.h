@@ -6,6 +6,7 @@
 #pragma once
 
 #include <algorithm>
+#include <climits>
 
 #include "mapa_internal.h"
 
@@ -266,6 +267,11 @@ __device__ __forceinline__ void node_masks(const LaneState &s, int kind, uint32_
 // unrolled over N, so the per-candidate values stay in registers.  Leaves
 // come in lexicographic order (c_i, then c_j, ascending) as in level().
 // Rows of one word (weights up to 3): the packed weight of u is 2 bits at 2u.
+#ifndef MAPA_PAIR_MAX_FIRST
+#define MAPA_PAIR_MAX_FIRST 9
+#endif
+constexpr int kPairMaxFirst = MAPA_PAIR_MAX_FIRST;  // N from which rows take the max first
+
 template <int M, int KIND, bool PRES>
 __device__ __forceinline__ void pair_level(LaneState &s, uint32_t rest, uint32_t code, int kp,
                                            int p, uint32_t prev) {
@@ -313,15 +319,34 @@ __device__ __forceinline__ void pair_level(LaneState &s, uint32_t rest, uint32_t
     const uint32_t *row = s.trow + ci;
     int kp2 = kp + __mul24(s.a, wsum<1>(row, nb2));
     if constexpr (PRES) kp2 -= __mul24(s.b, wsum<1>(row, rest2));
-    const int base = 16 * kp2 + 31;
     const uint32_t wp = prow[ci];
-    const uint32_t si = 2 * ci;
-    uint32_t pb = 0;
+    uint32_t pb;
+    if constexpr (N >= kPairMaxFirst) {
+      // Long rows: the leaf values are base + P[j] + gamma * w with base
+      // shared by the row, so take the max over j first and add base once
+      // (every leaf value is > 0); the i loop unrolls, which turns the
+      // j == i exclusion into nothing.
+      int tb = INT_MIN;
 #pragma unroll
-    for (int j = 0; j < N; ++j) {
-      const int w = (int)((wp >> sh2[j]) & 3u);
-      const uint32_t pk = (uint32_t)(base + P[j] + __mul24(gamma, w));
-      pb = (pk > pb && sh2[j] != si) ? pk : pb;  // c_j = c_i is no match
+      for (int j = 0; j < N; ++j) {
+        if (j == i) continue;  // c_j = c_i is no match (both loops take one order)
+        const int w = (int)((wp >> sh2[j]) & 3u);
+        const int t = P[j] + __mul24(gamma, w);
+        tb = t > tb ? t : tb;
+      }
+      pb = (uint32_t)(16 * kp2 + 31 + tb);
+    } else {
+      // Short rows keep the exclusion test per leaf: with few leaves per row
+      // the form above costs more registers than it saves (measured).
+      const int base = 16 * kp2 + 31;
+      const uint32_t si = 2 * ci;
+      pb = 0;
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        const int w = (int)((wp >> sh2[j]) & 3u);
+        const uint32_t pk = (uint32_t)(base + P[j] + __mul24(gamma, w));
+        pb = (pk > pb && sh2[j] != si) ? pk : pb;  // c_j = c_i is no match
+      }
     }
     const bool better = pb > (s.bpk | 15u);
     s.bpk = better ? pb : s.bpk;
