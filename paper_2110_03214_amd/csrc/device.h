@@ -262,8 +262,9 @@ __device__ __forceinline__ void node_masks(const LaneState &s, int kind, uint32_
 // the leaf key of (c_i, c_j) is
 //   kp + a*Y_i - b*D_i + a*(X_j + alpha*W[c_j][c_i]) - b*(D_j - W[c_j][c_i])
 // where alpha says whether position p neighbours position k-1.  Per node the
-// N values P_j = 16a*X_j - 16b*D_j - c_j are computed once; a leaf is then
-// one packed-weight field, one multiply-add and a max.  The inner loop is
+// N values P_j = 16a*X_j - 16b*D_j - c_j (and, for long rows, the row terms
+// Q_i = a*Y_i - b*D_i) are computed once; a leaf is then one packed-weight
+// field, one multiply-add and a max.  The inner loop is
 // unrolled over N, so the per-candidate values stay in registers.  Leaves
 // come in lexicographic order (c_i, then c_j, ascending) as in level().
 // Rows of one word (weights up to 3): the packed weight of u is 2 bits at 2u.
@@ -297,8 +298,21 @@ __device__ __forceinline__ void pair_level(LaneState &s, uint32_t rest, uint32_t
   }
   const uint32_t nb2 = nbm | (nbm << 16), rest2 = rest | (rest << 16), fix2 = fixm | (fixm << 16);
   const uint32_t *prow = s.trow + 16;  // packed-weight rows
-  uint32_t sh2[N];                     // 2 * c_j: bit offset of c_j's packed weight
+  // Long rows (N >= kPairMaxFirst) also take the row term a*Y_i - b*D_i from
+  // the per-candidate pass (Q_i) and unroll over i, so Q stays in registers.
+  constexpr bool kLong = N >= kPairMaxFirst;
+  // ring and tree: the neighbours of position p and the fixed neighbours of
+  // position k-1 are at most one vertex each, whose packed-weight row gives
+  // the weight to every candidate as one field
+  constexpr bool kSingle = KIND == MAPA_RING || KIND == MAPA_TREE;
+  uint32_t pnb = 0, pfix = 0;
+  if constexpr (kSingle) {
+    pnb = nbm ? prow[__builtin_ctz(nbm)] : 0u;
+    pfix = fixm ? prow[__builtin_ctz(fixm)] : 0u;
+  }
+  uint32_t sh2[N];  // 2 * c_j: bit offset of c_j's packed weight
   int P[N];
+  int Q[kLong ? N : 1];
   uint32_t r = rest;
 #pragma unroll
   for (int j = 0; j < N; ++j) {
@@ -306,26 +320,38 @@ __device__ __forceinline__ void pair_level(LaneState &s, uint32_t rest, uint32_t
     r &= r - 1;
     sh2[j] = 2 * c;
     const uint32_t *row = s.trow + c;
-    P[j] = __mul24(16 * s.a, wsum<1>(row, fix2)) - (int)c;
-    if constexpr (PRES) P[j] -= __mul24(16 * s.b, wsum<1>(row, rest2));
+    int X;
+    if constexpr (kSingle)
+      X = (int)((pfix >> (2 * c)) & 3u);
+    else
+      X = wsum<1>(row, fix2);
+    const int D = PRES ? wsum<1>(row, rest2) : 0;
+    P[j] = __mul24(16 * s.a, X) - (int)c;
+    if constexpr (PRES) P[j] -= __mul24(16 * s.b, D);
+    if constexpr (kLong) {
+      int Y;
+      if constexpr (kSingle)
+        Y = (int)((pnb >> (2 * c)) & 3u);
+      else if constexpr (KIND == MAPA_ALL_TO_ALL)
+        Y = X;  // every chosen vertex neighbours both positions
+      else
+        Y = wsum<1>(row, nb2);
+      Q[j] = __mul24(s.a, Y) - (PRES ? __mul24(s.b, D) : 0);
+    }
   }
   const int gamma = (alpha ? 16 * s.a : 0) + (PRES ? 16 * s.b : 0);
   s.count += (uint32_t)(N * M);
   const int sh = 4 * p;
   uint32_t ri = rest;
-  for (int i = 0; i < N; ++i) {
-    const uint32_t ci = (uint32_t)__builtin_ctz(ri);
-    ri &= ri - 1;
-    const uint32_t *row = s.trow + ci;
-    int kp2 = kp + __mul24(s.a, wsum<1>(row, nb2));
-    if constexpr (PRES) kp2 -= __mul24(s.b, wsum<1>(row, rest2));
-    const uint32_t wp = prow[ci];
-    uint32_t pb;
-    if constexpr (N >= kPairMaxFirst) {
-      // Long rows: the leaf values are base + P[j] + gamma * w with base
-      // shared by the row, so take the max over j first and add base once
-      // (every leaf value is > 0); the i loop unrolls, which turns the
-      // j == i exclusion into nothing.
+  if constexpr (kLong) {
+    // the leaf values are base_i + P[j] + gamma * w with base_i shared by the
+    // row: take the max over j first and add base_i once (every leaf value is
+    // > 0); with i unrolled the j == i exclusion costs nothing
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      const uint32_t ci = (uint32_t)__builtin_ctz(ri);
+      ri &= ri - 1;
+      const uint32_t wp = prow[ci];
       int tb = INT_MIN;
 #pragma unroll
       for (int j = 0; j < N; ++j) {
@@ -334,23 +360,34 @@ __device__ __forceinline__ void pair_level(LaneState &s, uint32_t rest, uint32_t
         const int t = P[j] + __mul24(gamma, w);
         tb = t > tb ? t : tb;
       }
-      pb = (uint32_t)(16 * kp2 + 31 + tb);
-    } else {
-      // Short rows keep the exclusion test per leaf: with few leaves per row
-      // the form above costs more registers than it saves (measured).
+      const uint32_t pb = (uint32_t)(16 * (kp + Q[i]) + 31 + tb);
+      const bool better = pb > (s.bpk | 15u);
+      s.bpk = better ? pb : s.bpk;
+      s.bcode = better ? (code | (ci << sh)) : s.bcode;
+    }
+  } else {
+    // short rows keep the exclusion test per leaf and the row term per row:
+    // with few leaves per row this uses fewer registers (measured faster)
+    for (int i = 0; i < N; ++i) {
+      const uint32_t ci = (uint32_t)__builtin_ctz(ri);
+      ri &= ri - 1;
+      const uint32_t *row = s.trow + ci;
+      int kp2 = kp + __mul24(s.a, wsum<1>(row, nb2));
+      if constexpr (PRES) kp2 -= __mul24(s.b, wsum<1>(row, rest2));
+      const uint32_t wp = prow[ci];
       const int base = 16 * kp2 + 31;
       const uint32_t si = 2 * ci;
-      pb = 0;
+      uint32_t pb = 0;
 #pragma unroll
       for (int j = 0; j < N; ++j) {
         const int w = (int)((wp >> sh2[j]) & 3u);
         const uint32_t pk = (uint32_t)(base + P[j] + __mul24(gamma, w));
         pb = (pk > pb && sh2[j] != si) ? pk : pb;  // c_j = c_i is no match
       }
+      const bool better = pb > (s.bpk | 15u);
+      s.bpk = better ? pb : s.bpk;
+      s.bcode = better ? (code | (ci << sh)) : s.bcode;
     }
-    const bool better = pb > (s.bpk | 15u);
-    s.bpk = better ? pb : s.bpk;
-    s.bcode = better ? (code | (ci << sh)) : s.bcode;
   }
 }
 
