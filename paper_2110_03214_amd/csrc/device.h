@@ -310,6 +310,41 @@ __device__ __forceinline__ void pair_level(LaneState &s, uint32_t rest, uint32_t
     pnb = nbm ? prow[__builtin_ctz(nbm)] : 0u;
     pfix = fixm ? prow[__builtin_ctz(fixm)] : 0u;
   }
+  if constexpr (M == 1) {
+    // Two free vertices c0 < c1, two leaves.  Both still-free weights are
+    // w01 = W[c0][c1], so the leaf keys are kp + a*(Y_i + X_j) + (a*alpha -
+    // b*PRES) * w01 and the pair placing c0 first wins unless strictly worse.
+    const uint32_t c0 = (uint32_t)__builtin_ctz(rest);
+    const uint32_t c1 = (uint32_t)__builtin_ctz(rest & (rest - 1u));
+    const int w01 = (int)((prow[c0] >> (2 * c1)) & 3u);
+    int X0, X1, Y0, Y1;
+    if constexpr (kSingle) {
+      X0 = (int)((pfix >> (2 * c0)) & 3u);
+      X1 = (int)((pfix >> (2 * c1)) & 3u);
+      Y0 = (int)((pnb >> (2 * c0)) & 3u);
+      Y1 = (int)((pnb >> (2 * c1)) & 3u);
+    } else {
+      X0 = wsum<1>(s.trow + c0, fix2);
+      X1 = wsum<1>(s.trow + c1, fix2);
+      if constexpr (KIND == MAPA_ALL_TO_ALL) {
+        Y0 = X0;
+        Y1 = X1;
+      } else {
+        Y0 = wsum<1>(s.trow + c0, nb2);
+        Y1 = wsum<1>(s.trow + c1, nb2);
+      }
+    }
+    const int kA = __mul24(s.a, Y0 + X1), kB = __mul24(s.a, Y1 + X0);
+    const bool first = kA >= kB;
+    const int key = kp + (first ? kA : kB) + __mul24((alpha ? s.a : 0) - (PRES ? s.b : 0), w01);
+    const uint32_t cf = first ? c0 : c1, cl = first ? c1 : c0;
+    const uint32_t pb = ((uint32_t)(key + 1) << 4) | (15u - cl);
+    const bool better = pb > (s.bpk | 15u);
+    s.bpk = better ? pb : s.bpk;
+    s.bcode = better ? (code | (cf << (4 * p))) : s.bcode;
+    s.count += 2u;
+    return;
+  }
   uint32_t sh2[N];  // 2 * c_j: bit offset of c_j's packed weight
   int P[N];
   int Q[kLong ? N : 1];
