@@ -31,6 +31,8 @@ LIB_PATH = os.path.join(HERE, "liboracle.so")
 SRC_PATH = os.path.join(HERE, "mapa_oracle.c")
 
 RING, A2A, TREE = 0, 1, 2
+MAX_N, MAX_K = 32, 12
+MAX_E = MAX_K * (MAX_K - 1) // 2
 MODE_ALL, MODE_LINKED = 0, 1
 METRIC_WEIGHTED, METRIC_EFFBW = 0, 1
 OK, NOFIT, CONFLICT = 0, 1, 2
@@ -45,14 +47,14 @@ class OrResult(ctypes.Structure):
         ("agg", ctypes.c_int32),
         ("pres", ctypes.c_int32),
         ("vertex_mask", ctypes.c_uint32),
-        ("mapping", ctypes.c_uint8 * 8),
+        ("mapping", ctypes.c_uint8 * 16),
         ("links", ctypes.c_int32),
     ]
 
 
 RESULT_DTYPE = np.dtype([
     ("count", np.int64), ("status", np.int32), ("key", np.int32), ("agg", np.int32),
-    ("pres", np.int32), ("vertex_mask", np.uint32), ("mapping", np.uint8, 8), ("links", np.int32),
+    ("pres", np.int32), ("vertex_mask", np.uint32), ("mapping", np.uint8, 16), ("links", np.int32),
 ], align=True)
 
 
@@ -122,7 +124,7 @@ def query(W, busy, kind, k, mode=MODE_ALL, a=1, b=1, metric=METRIC_WEIGHTED, edg
     return {
         "count": r.count, "status": r.status, "key": r.key, "agg": r.agg, "pres": r.pres,
         "vertex_mask": r.vertex_mask, "links": r.links,
-        "mapping": tuple(r.mapping[i] for i in range(k) if r.status == OK) if 1 <= k <= 8 else (),
+        "mapping": tuple(r.mapping[i] for i in range(k) if r.status == OK) if 1 <= k <= MAX_K else (),
     }
 
 
@@ -132,7 +134,7 @@ def effbw(x, y, z) -> float:
 
 
 def pattern_edges(kind, k):
-    buf = (ctypes.c_int * 56)()
+    buf = (ctypes.c_int * (2 * MAX_E))()
     ne = lib().or_pattern_edges(int(kind), int(k), buf)
     if ne < 0:
         raise ValueError("bad pattern")
@@ -149,7 +151,7 @@ def aut_count(kind, k, edges=None) -> int:
 def pad_topologies(topologies):
     T = len(topologies)
     tn = np.array([t.shape[0] for t in topologies], dtype=np.int32)
-    tw = np.zeros((T, 16, 16), dtype=np.uint8)
+    tw = np.zeros((T, MAX_N, MAX_N), dtype=np.uint8)
     for i, t in enumerate(topologies):
         n = t.shape[0]
         tw[i, :n, :n] = t
@@ -166,14 +168,14 @@ def batch(topologies, q_topo, q_busy, kind, k, mode, a, b, nthreads: int | None 
     if metric is None:
         metric = np.zeros(nq, np.uint8)
     q_ne = np.full(nq, -1, np.int32)
-    q_edges = np.zeros((nq, 56), np.int32)
+    q_edges = np.zeros((nq, 2 * MAX_E), np.int32)
     if edges is not None:
         for i, e in enumerate(edges):
             if e is None:
                 continue
             flat = edge_array(e)
             q_ne[i] = len(flat) // 2
-            q_edges[i, :len(flat)] = flat[:56]
+            q_edges[i, :len(flat)] = flat[:2 * MAX_E]
     cols = [np.ascontiguousarray(np.asarray(x, dtype=dt)) for x, dt in (
         (q_topo, np.int32), (q_busy, np.uint32), (kind, np.uint8), (k, np.uint8),
         (mode, np.uint8), (a, np.int16), (b, np.int16), (metric, np.uint8))]

@@ -43,7 +43,8 @@
  *     are reported too.  Other weights have no class in Eq. 2, so such
  *     topologies are unsupported for this metric.
  *
- * PreservedBW depends only on the chosen vertex set; its literal double loop
+ * Sizes: n <= 32 accelerators, k <= 12 pattern vertices.  PreservedBW
+ * depends only on the chosen vertex set; for n <= 20 its literal double loop
  * is memoised per vertex set (same loop, evaluated at most once per set).
  * Parity of this file is pinned by the "not gpu" test-suite: closed-form
  * counts, hand-derived counts and argmaxes, the paper's worked AggBW example,
@@ -56,8 +57,10 @@
 #include <stdlib.h>
 #include <string.h>
 
-#define OR_MAX_N 16
-#define OR_MAX_K 8
+#define OR_MAX_N 32
+#define OR_MAX_K 12
+#define OR_MAX_E (OR_MAX_K * (OR_MAX_K - 1) / 2) /* 66 */
+#define OR_MEMO_MAX_N 20 /* PreservedBW memo per vertex set up to this n */
 #define OR_MAX_AB 1024
 
 enum { OR_RING = 0, OR_A2A = 1, OR_TREE = 2 };
@@ -71,7 +74,7 @@ typedef struct {
   int32_t status;
   int32_t key, agg, pres;
   uint32_t vertex_mask;
-  uint8_t mapping[8];
+  uint8_t mapping[16]; /* entries k.. are 0xFF */
   int32_t links; /* EFFBW: x | y << 8 | z << 16 of the kept match, else 0 */
 } or_result;
 
@@ -117,7 +120,7 @@ int or_pattern_edges(int kind, int k, int *ep) {
 /* A caller-supplied pattern: ne edges on vertices 0..k-1, each unordered
  * pair at most once, no loops (a simple graph, as the canonical patterns). */
 static int check_edges(int k, int ne, const int *ep) {
-  if (k < 1 || k > OR_MAX_K || ne < 0 || ne > 28) return OR_EINVAL;
+  if (k < 1 || k > OR_MAX_K || ne < 0 || ne > k * (k - 1) / 2) return OR_EINVAL;
   int seen[OR_MAX_K][OR_MAX_K];
   memset(seen, 0, sizeof seen);
   for (int e = 0; e < ne; ++e) {
@@ -133,7 +136,7 @@ static int aut_count_edges(int k, int ne, const int *ep);
 /* |Aut(P)| by brute force over all k! permutations sigma of V(P): sigma is an
  * automorphism iff it maps the edge set onto itself. */
 int or_aut_count(int kind, int k) {
-  int ep[2 * 28];
+  int ep[2 * OR_MAX_E];
   int ne = or_pattern_edges(kind, k, ep);
   if (ne < 0) return ne;
   return aut_count_edges(k, ne, ep);
@@ -183,10 +186,10 @@ typedef struct {
   int n, k, ne, mode, metric;
   int64_t a, b;
   const uint8_t *W; /* n*n row-major */
-  int ep[2 * 28];
+  int ep[2 * OR_MAX_E];
   int R[OR_MAX_N], F;
   uint32_t Rmask;
-  int32_t *memo; /* 1<<n entries; -1 = not yet evaluated */
+  int32_t *memo; /* 1<<n entries (n <= OR_MEMO_MAX_N, else NULL); -1 = not yet evaluated */
   int phi[OR_MAX_K];
   int used[OR_MAX_N];
   int64_t count;
@@ -200,7 +203,7 @@ typedef struct {
 /* Eq. 3: PreservedBW of the vertex set S = sum of W[u][v] over pairs u<v of
  * free vertices not in S (the subgraph induced by R \ S). */
 static int64_t preserved_bw(or_state *s, uint32_t S) {
-  if (s->memo[S] >= 0) return s->memo[S];
+  if (s->memo && s->memo[S] >= 0) return s->memo[S];
   int64_t p = 0;
   for (int u = 0; u < s->n; ++u) {
     if (!((s->Rmask >> u) & 1u) || ((S >> u) & 1u)) continue;
@@ -209,7 +212,7 @@ static int64_t preserved_bw(or_state *s, uint32_t S) {
       p += s->W[u * s->n + v];
     }
   }
-  s->memo[S] = (int32_t)p;
+  if (s->memo) s->memo[S] = (int32_t)p;
   return p;
 }
 
@@ -288,7 +291,7 @@ static int validate_topology(int n, const uint8_t *W) {
 }
 
 /* One query of the pattern (k, ne, ep) against one hardware graph.  memo
- * must hold 1<<n int32. */
+ * holds 1<<n int32, or is NULL (then PreservedBW is evaluated per match). */
 static int query_with_memo(int n, const uint8_t *W, uint32_t busy, int k, int ne, const int *ep,
                            int mode, int a, int b, int metric, or_result *out, int32_t *memo) {
   memset(out, 0, sizeof *out);
@@ -312,7 +315,8 @@ static int query_with_memo(int n, const uint8_t *W, uint32_t busy, int k, int ne
   memcpy(s->ep, ep, sizeof(int) * 2 * ne);
   for (int v = 0; v < n; ++v)
     if (!((busy >> v) & 1u)) { s->R[s->F++] = v; s->Rmask |= 1u << v; }
-  for (uint32_t m = 0; m < (1u << n); ++m) memo[m] = -1;
+  if (memo)
+    for (uint32_t m = 0; m < (1u << n); ++m) memo[m] = -1;
 
   if (k <= s->F) extend(s, 0);
 
@@ -343,9 +347,11 @@ static int kind_edges(int kind, int k, int *ep) {
 
 int or_query_edges(int n, const uint8_t *W, uint32_t busy, int k, int ne, const int *ep,
                    int mode, int a, int b, int metric, or_result *out) {
-  int nn = (n >= 1 && n <= OR_MAX_N) ? n : 1;
-  int32_t *memo = (int32_t *)malloc(sizeof(int32_t) << nn);
-  if (!memo) return OR_ENOMEM;
+  int32_t *memo = NULL;
+  if (n >= 1 && n <= OR_MEMO_MAX_N) {
+    memo = (int32_t *)malloc(sizeof(int32_t) << n);
+    if (!memo) return OR_ENOMEM;
+  }
   int rc = query_with_memo(n, W, busy, k, ne, ep, mode, a, b, metric, out, memo);
   free(memo);
   return rc;
@@ -353,7 +359,7 @@ int or_query_edges(int n, const uint8_t *W, uint32_t busy, int k, int ne, const 
 
 int or_query(int n, const uint8_t *W, uint32_t busy, int kind, int k, int mode, int a, int b,
              int metric, or_result *out) {
-  int ep[2 * 28];
+  int ep[2 * OR_MAX_E];
   int ne = kind_edges(kind, k, ep);
   if (k > OR_MAX_K) ne = 0; /* reported as unsupported, not invalid */
   return or_query_edges(n, W, busy, k, ne, ep, mode, a, b, metric, out);
@@ -364,18 +370,19 @@ int or_query(int n, const uint8_t *W, uint32_t busy, int kind, int k, int mode, 
 typedef struct {
   int tid, nthreads, nq;
   const int32_t *topo_n;
-  const uint8_t *topo_W; /* per topology 16*16 row-major, row stride 16 */
+  const uint8_t *topo_W; /* per topology 32*32 row-major, row stride 32 */
   const int32_t *q_topo;
   const uint32_t *q_busy;
   const uint8_t *q_kind, *q_k, *q_mode, *q_metric;
   const int16_t *q_a, *q_b;
-  const int32_t *q_ne, *q_edges; /* optional per-query edge lists (ne < 0: use kind) */
+  const int32_t *q_ne, *q_edges; /* optional per-query edge lists, 2*OR_MAX_E ints each
+                                    (ne < 0: use kind) */
   or_result *out;
 } or_job;
 
 static void *batch_worker(void *arg) {
   or_job *j = (or_job *)arg;
-  int32_t *memo = (int32_t *)malloc(sizeof(int32_t) << OR_MAX_N);
+  int32_t *memo = (int32_t *)malloc(sizeof(int32_t) << OR_MEMO_MAX_N);
   uint8_t W[OR_MAX_N * OR_MAX_N];
   for (int q = j->tid; q < j->nq; q += j->nthreads) {
     int t = j->q_topo[q];
@@ -386,18 +393,19 @@ static void *batch_worker(void *arg) {
       continue;
     }
     for (int u = 0; u < n; ++u)
-      for (int v = 0; v < n; ++v) W[u * n + v] = j->topo_W[(size_t)t * 256 + u * 16 + v];
-    int ep[2 * 28];
+      for (int v = 0; v < n; ++v)
+        W[u * n + v] = j->topo_W[(size_t)t * OR_MAX_N * OR_MAX_N + u * OR_MAX_N + v];
+    int ep[2 * OR_MAX_E];
     int ne;
     if (j->q_ne && j->q_ne[q] >= 0) {
-      ne = j->q_ne[q] <= 28 ? j->q_ne[q] : -1;
-      for (int i = 0; i < 2 * ne; ++i) ep[i] = j->q_edges[(size_t)q * 56 + i];
+      ne = j->q_ne[q] <= OR_MAX_E ? j->q_ne[q] : -1;
+      for (int i = 0; i < 2 * ne; ++i) ep[i] = j->q_edges[(size_t)q * 2 * OR_MAX_E + i];
     } else {
       ne = kind_edges(j->q_kind[q], j->q_k[q], ep);
       if (j->q_k[q] > OR_MAX_K) ne = 0;
     }
     query_with_memo(n, W, j->q_busy[q], j->q_k[q], ne, ep, j->q_mode[q], j->q_a[q], j->q_b[q],
-                    j->q_metric[q], &j->out[q], memo);
+                    j->q_metric[q], &j->out[q], n <= OR_MEMO_MAX_N ? memo : NULL);
   }
   free(memo);
   return NULL;

@@ -427,7 +427,8 @@ def test_exhaustive_agreement_with_python_brute_force(orc):
 def test_input_validation(orc):
     W = cube_mesh()
     assert orc.query(W, 0, RING, 0)["status"] == orc.EINVAL
-    assert orc.query(W, 0, RING, 9)["status"] == orc.EUNSUP
+    assert orc.query(W, 0, RING, 9)["status"] == 1  # k = 9 > 8 free vertices: NOFIT
+    assert orc.query(W, 0, RING, 13)["status"] == orc.EUNSUP
     assert orc.query(W, 0, 3, 2)["status"] == orc.EINVAL
     assert orc.query(W, 0, RING, 2, 2)["status"] == orc.EINVAL
     assert orc.query(W, 1 << 8, RING, 2)["status"] == orc.EINVAL
@@ -438,7 +439,7 @@ def test_input_validation(orc):
     bad = W.copy()
     bad[2, 2] = 1
     assert orc.query(bad, 0, RING, 2)["status"] == orc.EINVAL
-    assert orc.query(np.zeros((17, 17), np.uint8), 0, RING, 2)["status"] == orc.EUNSUP
+    assert orc.query(np.zeros((33, 33), np.uint8), 0, RING, 2)["status"] == orc.EUNSUP
 
 
 def test_extreme_weights_and_keys_fit_int32(orc):
