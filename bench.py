@@ -12,7 +12,8 @@ timed region.
 Default workload: the batched config (65,536 server states over three 8- and
 6-vertex topologies, 0-6 busy vertices, ring / all-to-all / tree patterns with
 k in 2..8).  ``--config 3`` runs the large 16-vertex enumeration and
-``--config 1`` the tiny one.
+``--config 1`` the tiny one, ``--config 6`` the wide path (32-vertex servers,
+jobs of 9 and 10 accelerators).
 
 Prints ONE JSON line (rank 0):  value = embeddings scored per second, plus
 queries/s, per-batch p50/p99 latency, the roofline of the enumeration kernel
@@ -58,6 +59,8 @@ WORKLOAD_TEXT = {
         "weight-2, 6-vertex two-socket), 0-6 busy, ring/all-to-all/tree with k in 2..8"),
     3: ("large: 256 16-vertex hypercube+chord topologies (weights 1-3), all free, ring and "
         "all-to-all with k in 6..8 (1,536 queries, 2.98e11 embeddings)"),
+    6: ("wide: 16 32-vertex 5-cube+chord topologies (weights 1-3), 12 free accelerators each, "
+        "ring/all-to-all/tree with k in 9..10 (96 queries, 1.53e10 embeddings; host buffers)"),
 }
 
 
@@ -237,7 +240,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=0, help="timed steps (default: per config)")
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", type=int, default=2, choices=(1, 2, 3))
+    ap.add_argument("--config", type=int, default=2, choices=(1, 2, 3, 6))
     ap.add_argument("--metric", default="weighted", choices=("weighted", "effbw"),
                     help="key of every query: a*AggBW + b*PreservedBW, or the predicted effective "
                          "bandwidth of Eq. 2 (bandwidth-sensitive jobs; needs weights 0..2)")
@@ -267,8 +270,9 @@ def main():
     if not torch.cuda.is_available():
         log("no GPU visible")
         sys.exit(1)
-    steps = args.steps or {1: 200, 2: 200, 3: 3}[args.config]
-    wl = {1: synth.config1, 2: synth.config2, 3: synth.config3}[args.config]()
+    steps = args.steps or {1: 200, 2: 200, 3: 3, 6: 3}[args.config]
+    wl = {1: synth.config1, 2: synth.config2, 3: synth.config3, 6: synth.config6}[args.config]()
+    wide = args.config == 6
     emb, ops = algorithmic_ops(wl)
     log(f"[bench] config {args.config}: {wl.nq} queries, {emb:.4g} embeddings/step, "
         f"{ops:.4g} algorithmic ops/step")
@@ -291,7 +295,13 @@ def main():
     dr = torch.zeros(wl.nq * B.RESULT_DTYPE.itemsize, dtype=torch.uint8, device=dev)
     handles = dr.view(torch.int64)[5:]  # alloc_handle: byte 40 of each 48-byte result
 
+    wide_res = [None]
+
     def step():
+        if wide:  # host buffers in and out (16 B per query, 56 B per result)
+            wide_res[0] = ctx.query_batch_wide(qh)
+            ctx.release(wide_res[0]["alloc_handle"])
+            return
         ctx.query_batch(dq, dr, stream=stream)
         ctx.release(handles, stride=48, count=wl.nq, stream=stream)
 
@@ -318,7 +328,7 @@ def main():
     lat = np.array([a.elapsed_time(b) for a, b in ev])
     st = ctx.stats()
     # every step scored every embedding and handed every allocation back
-    res = dr.cpu().numpy().view(B.RESULT_DTYPE)
+    res = wide_res[0] if wide else dr.cpu().numpy().view(B.RESULT_DTYPE)
     assert int(res["count"].sum()) == emb, (int(res["count"].sum()), emb)
     assert np.array_equal(ctx.get_busy(ids), wl.busy), "release did not restore the entry state"
     assert st["self_check_failures"] == 0
@@ -358,7 +368,8 @@ def main():
         out["roofline"] = {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_PEAK / 1e12,
                            "unit": "Tops/s", "frac": achieved / ALU_PEAK, "traffic": traffic,
                            "traffic_unit": "HBM bytes per launch", "traffic_source": source,
-                           "kernel": "k_enumerate", "kernel_ms": avg_s * 1e3,
+                           "kernel": "k_wide_search" if wide else "k_enumerate",
+                           "kernel_ms": avg_s * 1e3,
                            "ops_per_launch": ops, "items_per_launch": st["last_items"],
                            "measured_peak": probe / 1e12, "frac_of_measured_peak": achieved / probe}
     if args.plain:

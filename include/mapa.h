@@ -45,14 +45,17 @@ extern "C" {
 #endif
 
 /* ---- limits -------------------------------------------------------------- */
-#define MAPA_MAX_N 16     /* accelerators per server (hardware-graph vertices)  */
-#define MAPA_MAX_K 8      /* accelerators per job (pattern vertices)            */
+#define MAPA_MAX_N 16     /* accelerators per server, mapa_query_batch          */
+#define MAPA_MAX_K 8      /* accelerators per job (pattern vertices), same      */
+#define MAPA_MAX_N_WIDE 32 /* accelerators per server, mapa_create_topology and
+                              mapa_query_batch_wide                           */
+#define MAPA_MAX_K_WIDE 12 /* pattern vertices, mapa_query_batch_wide          */
 #define MAPA_MAX_AB 1024  /* largest key weight a, b                             */
 
 /* ---- status codes -------------------------------------------------------- */
 #define MAPA_OK 0
 #define MAPA_ERR_INVALID_ARG (-1)    /* malformed argument (see each function)  */
-#define MAPA_ERR_UNSUPPORTED (-2)    /* n > 16 or k > 8                         */
+#define MAPA_ERR_UNSUPPORTED (-2)    /* a size beyond the call's limits        */
 #define MAPA_ERR_OOM (-3)            /* device or host allocation failed       */
 #define MAPA_ERR_DEVICE (-4)         /* a HIP call failed                      */
 #define MAPA_ERR_NOT_BUSY (-5)       /* release of a vertex that is not busy   */
@@ -174,7 +177,8 @@ int32_t mapa_ctx_destroy(mapa_ctx *ctx);
 
 /* Register a hardware graph (Sec. 3.2) and create num_servers servers of it,
  * all free.
- *   n:  1..16 accelerators (n > 16: MAPA_ERR_UNSUPPORTED)
+ *   n:  1..32 accelerators (n > 32: MAPA_ERR_UNSUPPORTED); servers of more
+ *       than 16 are queried with mapa_query_batch_wide only
  *   W:  host pointer, n*n uint8 row-major, W[i][j] = link weight of the pair,
  *       symmetric, W[i][i] = 0, 0 = no direct link.  Copied; caller keeps it.
  *   num_servers: >= 0.
@@ -221,8 +225,9 @@ int32_t mapa_get_busy(mapa_ctx *ctx, int32_t count, const int32_t *server_ids,
 /* Run nq allocation queries (Sec. 3.3-3.5) as one batch.
  *   q:   nq queries; res: nq results (same index).
  *   Host pointers (flags = 0): the batch is validated first (bad field ->
- *     MAPA_ERR_INVALID_ARG, k > 8 -> MAPA_ERR_UNSUPPORTED, unknown server ->
- *     MAPA_ERR_UNKNOWN_SERVER; nothing runs on error), then the call blocks
+ *     MAPA_ERR_INVALID_ARG, k > 8 or a server of more than 16 accelerators
+ *     -> MAPA_ERR_UNSUPPORTED, unknown server -> MAPA_ERR_UNKNOWN_SERVER;
+ *     nothing runs on error), then the call blocks
  *     until res is filled.  A small batch (at most 4096 queries, each on a
  *     different server, at most 2^20 embeddings per query and 2^24 in all,
  *     counted on the whole topology) runs as one fused launch that reads and
@@ -239,6 +244,34 @@ int32_t mapa_get_busy(mapa_ctx *ctx, int32_t count, const int32_t *server_ids,
  * MAPA_RES_CONFLICT.  The caller owns q and res. */
 int32_t mapa_query_batch(mapa_ctx *ctx, const mapa_query *q, int32_t nq, mapa_result *res,
                          uint32_t flags, void *hip_stream);
+
+/* Result of one wide query: as mapa_result, with room for 16 mapping
+ * entries.  56 bytes. */
+typedef struct {
+  int64_t count;
+  int32_t status, key, agg, pres;
+  uint32_t vertex_mask;
+  uint8_t mapping[16];  /* mapping[i] = accelerator of pattern vertex i; 0xFF beyond k */
+  int32_t reserved;     /* 0 */
+  int64_t alloc_handle; /* (server << 32) | vertex_mask if committed, else -1 */
+} mapa_result_wide;
+
+/* The same query semantics (Sec. 3.3-3.5, Alg. 1, reading of batches as in
+ * mapa_query_batch) for the sizes beyond the batch path, the paper's jobs
+ * of 9 accelerators and more: servers of up to 32 accelerators and patterns
+ * of up to 12 vertices (ring, all-to-all and tree of any k <= 12, or a
+ * registered pattern), key a*AggBW + b*PreservedBW (MAPA_METRIC_EFFBW ->
+ * MAPA_ERR_UNSUPPORTED).  Any server may be queried this way.
+ *   q, res: host pointers, nq entries each; the call is synchronous and
+ *     validated as mapa_query_batch's host form (k > 12 ->
+ *     MAPA_ERR_UNSUPPORTED).
+ *   A batch of more than 2^36 embeddings in all (summed over its queries, on
+ *   their free vertices at the batch's start) is refused with
+ *   MAPA_ERR_ADMISSION before anything runs.
+ * Every embedding is enumerated and scored, as on the batch path; the work
+ * of each query is split over blocks by a prefix of its first positions. */
+int32_t mapa_query_batch_wide(mapa_ctx *ctx, const mapa_query *q, int32_t nq,
+                              mapa_result_wide *res);
 
 /* Release committed allocations (Sec. 3.6: add the vertices back).
  * Handles equal to -1 are ignored.

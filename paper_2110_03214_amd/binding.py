@@ -43,6 +43,12 @@ RESULT_DTYPE = np.dtype([("count", np.int64), ("status", np.int32), ("key", np.i
                          ("alloc_handle", np.int64)])
 assert QUERY_DTYPE.itemsize == 16 and RESULT_DTYPE.itemsize == 48
 assert RESULT_DTYPE.fields["alloc_handle"][1] == 40
+RESULT_WIDE_DTYPE = np.dtype([("count", np.int64), ("status", np.int32), ("key", np.int32),
+                              ("agg", np.int32), ("pres", np.int32), ("vertex_mask", np.uint32),
+                              ("mapping", np.uint8, 16), ("reserved", np.int32),
+                              ("alloc_handle", np.int64)])
+assert RESULT_WIDE_DTYPE.itemsize == 56 and RESULT_WIDE_DTYPE.fields["alloc_handle"][1] == 48
+MAX_N_WIDE, MAX_K_WIDE = 32, 12
 
 
 class Tuning(ctypes.Structure):
@@ -95,6 +101,7 @@ SIGNATURES = {
     "mapa_set_busy": (_I32, [_P, _I32, _P, _P, _U32, _P]),
     "mapa_get_busy": (_I32, [_P, _I32, _P, _P]),
     "mapa_query_batch": (_I32, [_P, _P, _I32, _P, _U32, _P]),
+    "mapa_query_batch_wide": (_I32, [_P, _P, _I32, _P]),
     "mapa_release": (_I32, [_P, _I32, _P, _I32, _U32, _P]),
     "mapa_get_tuning": (_I32, [_P, ctypes.POINTER(Tuning)]),
     "mapa_set_tuning": (_I32, [_P, ctypes.POINTER(Tuning)]),
@@ -247,6 +254,14 @@ class Context:
         res = np.zeros(len(q), dtype=RESULT_DTYPE) if results is None else results
         check(lib().mapa_query_batch(self.h, _ptr(q), len(q), _ptr(res),
                                      PIPELINE if pipeline else 0, None), "mapa_query_batch")
+        return res
+
+    def query_batch_wide(self, queries):
+        """Host QUERY_DTYPE array -> RESULT_WIDE_DTYPE array (servers of up to
+        32 accelerators, patterns of up to 12 vertices; blocking)."""
+        q = np.ascontiguousarray(queries, dtype=QUERY_DTYPE)
+        res = np.zeros(len(q), dtype=RESULT_WIDE_DTYPE)
+        check(lib().mapa_query_batch_wide(self.h, _ptr(q), len(q), _ptr(res)), "mapa_query_batch_wide")
         return res
 
     def release(self, handles, stride: int = 8, count: int | None = None, stream=None):

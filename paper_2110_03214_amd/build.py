@@ -6,7 +6,9 @@ The library is the whole product path: the device units (kernels.hip: batch
 front end, finalize and state kernels; fused.hip: the small-batch launch;
 enum_*.hip: the enumeration kernel, one unit per pair-level variant) and the
 host units (host.cpp: C ABI, validation, memory, launches; serve.cpp: the
-serving loop), each compiled by hipcc for gfx950 only, in parallel, then
+serving loop; wide.hip / wide.cpp: servers of up to 32 accelerators and
+patterns of up to 12 vertices), each compiled by hipcc for gfx950 only, in
+parallel, then
 linked into one shared object.
 """
 from __future__ import annotations
@@ -25,7 +27,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libmapa.so")
 SOURCES = [os.path.join(CSRC, f) for f in (
     "enum_pair12_lds.hip", "enum_pair12_glb.hip", "enum_pair8.hip", "enum_plain.hip",
-    "fused.hip", "kernels.hip", "host.cpp", "serve.cpp")]
+    "fused.hip", "kernels.hip", "wide.hip", "host.cpp", "serve.cpp", "wide.cpp")]
 ARCH = "gfx950"
 
 

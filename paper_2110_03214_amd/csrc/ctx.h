@@ -73,7 +73,8 @@ struct mapa_ctx {
 
   // topologies (host copy is authoritative; device copies are derived)
   std::vector<int32_t> topo_n;
-  std::vector<std::array<uint8_t, 256>> topo_W;  // 16x16 padded
+  std::vector<std::array<uint8_t, 256>> topo_W;  // 16x16 padded (zero for n > 16)
+  std::vector<std::array<uint8_t, 1024>> wide_W;  // 32x32 padded, every topology
   int wpr = 1;
   int32_t *d_topo_n = nullptr;
   uint8_t *d_topo_W = nullptr;
@@ -83,6 +84,14 @@ struct mapa_ctx {
   size_t cap_topos = 0;
   uint16_t *d_eff_rank = nullptr;  // Eq. 2 tables (eff_off layout)
   int32_t *d_eff_key = nullptr;
+
+  // wide path (servers of up to 32 accelerators, patterns of up to 12 vertices)
+  uint32_t *d_wide_rows = nullptr;  // [T][kWidePlanes][32], see kWidePlanes
+  size_t wide_uploaded = 0, cap_wide = 0;
+  struct WideBuf {
+    void *d = nullptr;
+    size_t cap = 0;
+  } wide_buf;  // plans, block tables and per-block partials of one wide call
 
   // registered patterns (append-only; slot i = kind MAPA_PATTERN_BASE + i)
   std::vector<unsigned long long> pat_nbtab;  // host mirror, back-neighbour tables

@@ -114,6 +114,10 @@ __device__ __forceinline__ Plan make_plan(const mapa_query &q, int32_t nservers,
     return p;
   }
   const int n = topo_n[t];
+  if (n > kMaxN) {  // servers of more than 16 accelerators take the wide path
+    p.status = kPlanInvalid;
+    return p;
+  }
   const uint32_t R = ~busy[q.server] & ((1u << n) - 1u);
   const int F = __popc(R);
   p.topo = (uint16_t)t;

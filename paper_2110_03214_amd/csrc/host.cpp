@@ -359,7 +359,8 @@ int32_t upload_topologies(mapa_ctx *c, size_t first, bool all) {
   std::vector<uint32_t> rows(nt * kTopoWords * c->wpr);
   for (size_t t = t0; t < T; ++t) {
     std::memcpy(&W[(t - t0) * 256], c->topo_W[t].data(), 256);
-    build_rows(c->topo_W[t].data(), c->topo_n[t], c->wpr, &rows[(t - t0) * kTopoWords * c->wpr]);
+    build_rows(c->topo_W[t].data(), std::min(c->topo_n[t], kMaxN), c->wpr,
+               &rows[(t - t0) * kTopoWords * c->wpr]);
   }
   MAPA_HIPCHK(hipMemcpy(c->d_topo_n + t0, c->topo_n.data() + t0, nt * sizeof(int32_t),
                         hipMemcpyHostToDevice));
@@ -488,7 +489,12 @@ int32_t ensure_small(mapa_ctx *c, size_t n) {
 int32_t validate_query(const mapa_ctx *c, const mapa_query &q, int32_t i) {
   if (q.server < 0 || (size_t)q.server >= c->server_topo.size())
     return fail(MAPA_ERR_UNKNOWN_SERVER, "query %d: unknown server %d", i, q.server);
-  if (q.k > kMaxK) return fail(MAPA_ERR_UNSUPPORTED, "query %d: k=%d > %d", i, q.k, kMaxK);
+  if (q.k > kMaxK)
+    return fail(MAPA_ERR_UNSUPPORTED, "query %d: k=%d > %d (mapa_query_batch_wide takes up to %d)", i,
+                q.k, kMaxK, MAPA_MAX_K_WIDE);
+  if (c->topo_n[c->server_topo[q.server]] > kMaxN)
+    return fail(MAPA_ERR_UNSUPPORTED, "query %d: server %d has %d accelerators (> %d: use "
+                "mapa_query_batch_wide)", i, q.server, c->topo_n[c->server_topo[q.server]], kMaxN);
   if (q.k < 1) return fail(MAPA_ERR_INVALID_ARG, "query %d: k=%d < 1", i, q.k);
   if (q.kind > MAPA_TREE) {
     const int id = q.kind - MAPA_PATTERN_BASE;
@@ -588,6 +594,9 @@ int32_t mapa_ctx_destroy(mapa_ctx *c) {
     for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.exec);
     dev_free(c->d_pat_nbtab);
     dev_free(c->d_pat_k);
+    dev_free(c->d_wide_rows);
+    if (c->wide_buf.d) (void)hipFree(c->wide_buf.d);
+    c->wide_buf.d = nullptr;
     dev_free(c->d_topo_n);
     dev_free(c->d_topo_W);
     dev_free(c->d_rows);
@@ -617,7 +626,7 @@ int32_t mapa_create_topology(mapa_ctx *c, int32_t n, const uint8_t *W, int32_t n
   if (!c) return fail(MAPA_ERR_INVALID_ARG, "ctx is NULL");
   if (int32_t rc = not_while_serving(c, "mapa_create_topology")) return rc;
   if (n < 1) return fail(MAPA_ERR_INVALID_ARG, "n=%d < 1", n);
-  if (n > kMaxN) return fail(MAPA_ERR_UNSUPPORTED, "n=%d > %d", n, kMaxN);
+  if (n > MAPA_MAX_N_WIDE) return fail(MAPA_ERR_UNSUPPORTED, "n=%d > %d", n, MAPA_MAX_N_WIDE);
   if (!W) return fail(MAPA_ERR_INVALID_ARG, "W is NULL");
   if (num_servers < 0) return fail(MAPA_ERR_INVALID_ARG, "num_servers=%d < 0", num_servers);
   for (int i = 0; i < n; ++i) {
@@ -629,11 +638,15 @@ int32_t mapa_create_topology(mapa_ctx *c, int32_t n, const uint8_t *W, int32_t n
   if (c->topo_n.size() >= 65535) return fail(MAPA_ERR_UNSUPPORTED, "too many topologies");
   if (c->server_topo.size() + (size_t)num_servers > (size_t)INT32_MAX)
     return fail(MAPA_ERR_UNSUPPORTED, "too many servers");
+  // the batch path keeps 16x16 weights (zero for wider servers, which only
+  // the wide path queries); the wide path keeps every topology as 32x32
   std::array<uint8_t, 256> w16{};
+  std::array<uint8_t, 1024> w32{};
   uint8_t maxw = 0;
   for (int i = 0; i < n; ++i)
     for (int j = 0; j < n; ++j) {
-      w16[i * 16 + j] = W[i * n + j];
+      if (n <= kMaxN) w16[i * 16 + j] = W[i * n + j];
+      w32[i * 32 + j] = W[i * n + j];
       maxw = std::max(maxw, W[i * n + j]);
     }
   const int32_t tid = (int32_t)c->topo_n.size();
@@ -645,13 +658,15 @@ int32_t mapa_create_topology(mapa_ctx *c, int32_t n, const uint8_t *W, int32_t n
     const int old_wpr = c->wpr;
     c->topo_n.push_back(n);
     c->topo_W.push_back(w16);
+    c->wide_W.push_back(w32);
     c->topo_maxw.push_back(maxw);
-    c->wpr = std::max(c->wpr, weight_class(W, n));
+    if (n <= kMaxN) c->wpr = std::max(c->wpr, weight_class(W, n));
     rc = upload_topologies(c, (size_t)tid, c->wpr != old_wpr);
     if (!rc) rc = grow_servers(c, first + (size_t)num_servers);
     if (rc) {
       c->topo_n.pop_back();
       c->topo_W.pop_back();
+      c->wide_W.pop_back();
       c->topo_maxw.pop_back();
       c->wpr = old_wpr;
       return rc;
@@ -665,6 +680,7 @@ int32_t mapa_create_topology(mapa_ctx *c, int32_t n, const uint8_t *W, int32_t n
   } else {
     c->topo_n.push_back(n);
     c->topo_W.push_back(w16);
+    c->wide_W.push_back(w32);
     c->topo_maxw.push_back(maxw);
   }
   c->server_topo.insert(c->server_topo.end(), (size_t)num_servers, tid);

@@ -330,7 +330,7 @@ __global__ void k_set_busy(const int32_t *ids, const uint32_t *masks, int32_t co
   const int s = ids[i];
   if (s < 0 || s >= nservers) return;
   const int n = topo_n[server_topo[s]];
-  busy[s] = masks[i] & ((1u << n) - 1u);
+  busy[s] = masks[i] & (n >= 32 ? 0xFFFFFFFFu : (1u << n) - 1u);
 }
 
 __global__ void k_get_busy(const int32_t *ids, int32_t count, const uint32_t *busy,

@@ -539,6 +539,9 @@ int32_t mapa_serve_submit(mapa_ctx *c, const mapa_request *reqs, int32_t n) {
     if (r.server < 0 || (size_t)r.server >= c->server_topo.size())
       return fail(MAPA_ERR_UNKNOWN_SERVER, "request %d: unknown server %d", i, r.server);
     if (r.k > kMaxK) return fail(MAPA_ERR_UNSUPPORTED, "request %d: k=%d > %d", i, r.k, kMaxK);
+    if (c->topo_n[c->server_topo[r.server]] > kMaxN)
+      return fail(MAPA_ERR_UNSUPPORTED, "request %d: server %d has more than %d accelerators", i,
+                  r.server, kMaxN);
     if (r.kind > MAPA_TREE) {
       const int id = r.kind - MAPA_PATTERN_BASE;
       if (id < 0 || id >= c->npat || c->pat_k[id] != r.k)

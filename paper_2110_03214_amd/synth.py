@@ -233,6 +233,41 @@ def config3(ntopo: int = 256, ks=(6, 7, 8), kinds=(RING, ALL_TO_ALL)) -> Workloa
                     np.zeros(ntopo, np.uint32), q, {"config": 3})
 
 
+def config6_topology(rng) -> np.ndarray:
+    """32-vertex: 5-D hypercube edges with weight U{1,2,3}, plus 16 distinct
+    extra chords (uniform over the non-hypercube pairs) of weight 1."""
+    hc = hypercube_edges(5)
+    W = _sym(32, hc, rng.integers(1, 4, size=len(hc)))
+    hcs = set(hc)
+    others = [(u, v) for u, v in itertools.combinations(range(32), 2) if (u, v) not in hcs]
+    pick = rng.choice(len(others), size=16, replace=False)
+    for i in pick:
+        u, v = others[int(i)]
+        W[u, v] = W[v, u] = 1
+    return W
+
+
+def config6(nserv: int = 16, free: int = 12, ks=(9, 10), kinds=(RING, ALL_TO_ALL, TREE)) -> Workload:
+    """Wide: nserv independently seeded 32-vertex topologies, each server
+    with `free` accelerators free (a uniform subset, the rest busy); kinds x
+    ks queries per server (jobs of 9 and 10 accelerators)."""
+    rt, rb = streams(6)[S_TOPO], streams(6)[S_BUSY]
+    topos = [config6_topology(rt) for _ in range(nserv)]
+    busy = np.empty(nserv, np.uint32)
+    for t in range(nserv):
+        fr = rb.choice(32, size=free, replace=False)
+        busy[t] = np.uint32(0xFFFFFFFF & ~int(np.bitwise_or.reduce(1 << fr.astype(np.int64))))
+    srv, kd, kk = [], [], []
+    for t in range(nserv):
+        for kind in kinds:
+            for k in ks:
+                srv.append(t)
+                kd.append(kind)
+                kk.append(k)
+    q = make_queries(srv, kd, kk)
+    return Workload("C6", topos, np.arange(nserv, dtype=np.int32), busy, q, {"config": 6})
+
+
 # ---------------------------------------------------------------------------
 # serving traces
 # ---------------------------------------------------------------------------

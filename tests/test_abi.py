@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_sizes_match_header():
     text = open(HEADER).read()
-    assert "16 bytes" in text and "48 bytes" in text
+    assert "16 bytes" in text and "48 bytes" in text and "56 bytes" in text
     assert B.QUERY_DTYPE.itemsize == 16 and B.RESULT_DTYPE.itemsize == 48
 
 
@@ -76,7 +76,7 @@ def test_topology_validation(vctx):
     W = cube_mesh()
     assert vctx.create_topology(W, 3) == (0, 0)
     assert vctx.create_topology(W, 2) == (1, 3)
-    assert code_of(lambda: vctx.create_topology(np.zeros((17, 17), np.uint8), 1)) == B.ERR_UNSUPPORTED
+    assert code_of(lambda: vctx.create_topology(np.zeros((33, 33), np.uint8), 1)) == B.ERR_UNSUPPORTED
     asym = W.copy()
     asym[0, 1] = 2
     assert code_of(lambda: vctx.create_topology(asym, 1)) == B.ERR_INVALID_ARG
@@ -150,6 +150,32 @@ def test_pattern_registration_and_query_kinds(vctx):
     for _ in range(B.MAX_PATTERNS - 2):
         vctx.create_pattern(2, [(0, 1)])
     assert code_of(lambda: vctx.create_pattern(2, [(0, 1)])) == B.ERR_STATE
+
+
+def test_wide_queries_validation(vctx):
+    """Servers of 17..32 accelerators are created, answered only by the wide
+    call; the wide call takes k up to 12 and the weighted key only."""
+    W = np.ones((32, 32), np.uint8) - np.eye(32, dtype=np.uint8)
+    assert vctx.create_topology(W, 2) == (0, 0)
+    vctx.create_topology(cube_mesh(), 1)
+    # every bit of a 32-accelerator server's mask is a vertex
+    assert code_of(lambda: vctx.set_busy([0, 1], [0xFFFF0000, 3 << 30])) == B.ERR_NO_DEVICE
+    assert code_of(lambda: vctx.set_busy([2], [1 << 8])) == B.ERR_INVALID_ARG
+    # the batch path refuses the wide servers and k > 8
+    assert code_of(lambda: vctx.query_batch(B.pack_queries([0], [0], [3]))) == B.ERR_UNSUPPORTED
+    assert "wide" in B.lib().mapa_last_error().decode()
+    assert code_of(lambda: vctx.query_batch(B.pack_queries([2], [0], [9]))) == B.ERR_UNSUPPORTED
+    # the wide call
+    ok = B.pack_queries([0, 2, 1], [0, 1, 2], [12, 3, 9])
+    assert code_of(lambda: vctx.query_batch_wide(ok)) == B.ERR_NO_DEVICE
+    assert code_of(lambda: vctx.query_batch_wide(B.pack_queries([0], [0], [13]))) == B.ERR_UNSUPPORTED
+    assert code_of(lambda: vctx.query_batch_wide(B.pack_queries([0], [0], [0]))) == B.ERR_INVALID_ARG
+    assert code_of(lambda: vctx.query_batch_wide(B.pack_queries([0], [0], [3], metric=[1]))) == \
+        B.ERR_UNSUPPORTED
+    assert code_of(lambda: vctx.query_batch_wide(B.pack_queries([3], [0], [3]))) == B.ERR_UNKNOWN_SERVER
+    kind = vctx.create_pattern(5, [(0, 4), (1, 4)])
+    assert code_of(lambda: vctx.query_batch_wide(B.pack_queries([0], [kind], [5]))) == B.ERR_NO_DEVICE
+    assert code_of(lambda: vctx.query_batch_wide(B.pack_queries([0], [kind], [6]))) == B.ERR_INVALID_ARG
 
 
 def test_release_validation(vctx):

@@ -142,7 +142,7 @@ def load_stored_c3():
         out[i]["count"], out[i]["status"] = int(r[4]), int(r[5])
         out[i]["key"], out[i]["agg"], out[i]["pres"] = int(r[6]), int(r[7]), int(r[8])
         out[i]["vertex_mask"] = int(r[9])
-        m = np.full(8, 255, np.uint8)
+        m = np.full(out.dtype["mapping"].shape[0], 255, np.uint8)
         m[:k] = [int(x) for x in r[10:10 + k]]
         out[i]["mapping"] = m
     return out

@@ -1,0 +1,195 @@
+"""GPU parity for the wide path (mapa_query_batch_wide): servers of 17..32
+accelerators and patterns of 9..12 vertices against the oracle bit for bit,
+the batch path's answers on servers both paths take, the five-cube's hand
+counts, registered patterns, and the batch commit rule."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2110_03214_amd import binding as B
+from paper_2110_03214_amd import synth
+
+pytestmark = pytest.mark.gpu
+NTHREADS = min(16, os.cpu_count() or 1)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.fail("GPU test run without a visible GPU")
+    return t
+
+
+@pytest.fixture
+def ctx(torch):
+    c = B.Context(0)
+    yield c
+    c.close()
+
+
+def assert_same(gpu, ref, k, label=""):
+    k = np.asarray(k)
+    for f in ("count", "status"):
+        bad = np.nonzero(gpu[f] != ref[f])[0]
+        assert bad.size == 0, f"{label} {f} differs at {bad[:5]}: gpu {gpu[f][bad[:5]]} ref {ref[f][bad[:5]]}"
+    ok = ref["status"] == 0
+    for f in ("key", "agg", "pres", "vertex_mask"):
+        bad = np.nonzero(ok & (gpu[f] != ref[f]))[0]
+        assert bad.size == 0, f"{label} {f} differs at {bad[:5]}: gpu {gpu[f][bad[:5]]} ref {ref[f][bad[:5]]}"
+    for kk in np.unique(k):
+        sel = ok & (k == kk)
+        assert np.array_equal(gpu["mapping"][sel, :kk], ref["mapping"][sel, :kk]), f"{label} mapping k={kk}"
+        assert (gpu["mapping"][sel, kk:] == 0xFF).all()
+
+
+def random_topology(rng, n, wmax, p_edge):
+    W = np.zeros((n, n), np.uint8)
+    for u in range(n):
+        for v in range(u + 1, n):
+            if rng.random() < p_edge:
+                W[u, v] = W[v, u] = rng.integers(1, wmax + 1)
+    return W
+
+
+def busy_leaving(rng, n, F):
+    free = rng.choice(n, size=F, replace=False)
+    return int(((1 << n) - 1) & ~int(np.bitwise_or.reduce(1 << free.astype(np.int64))))
+
+
+def run_wide(ctx, topos, st, busy, cols, edges=None):
+    q = synth.make_queries(cols["server"], cols["kind"], cols["k"], cols["mode"], cols.get("commit", 0),
+                           cols["a"], cols["b"])
+    wl = synth.Workload("wide", topos, np.array(st, np.int32), np.array(busy, np.uint32), q)
+    qh, ids = B.load_workload(ctx, wl)
+    got = ctx.query_batch_wide(qh)
+    srv = wl.queries["server"]
+    ref = oracle.batch(topos, wl.server_topo[srv], wl.busy[srv], q["kind"], q["k"], q["mode"], q["a"],
+                       q["b"], NTHREADS, edges=edges)
+    return got, ref, qh
+
+
+@pytest.mark.parametrize("wmax", [3, 255])
+def test_wide_servers_against_oracle(ctx, wmax):
+    """Servers of 17..32 accelerators with 2..11 free, every kind, k = 1..12,
+    both modes, several keys; one call."""
+    rng = np.random.default_rng(900 + wmax)
+    topos = [random_topology(rng, n, wmax, 0.5) for n in (17, 20, 24, 32)]
+    st, busy, cols = [], [], {c: [] for c in ("server", "kind", "k", "mode", "a", "b")}
+    s = 0
+    for t, W in enumerate(topos):
+        n = W.shape[0]
+        for F in (2, 5, 8, 11):
+            st.append(t)
+            busy.append(busy_leaving(rng, n, F))
+            limit = 2_000_000 if n <= 20 else 20_000  # the oracle memoises PreservedBW up to n = 20
+            for kind in range(3):
+                for k in range(1, 13):
+                    if k <= F and math.perm(F, k) > limit:
+                        continue
+                    for mode in (0, 1):
+                        a, b = [(1, 1), (1, 0), (0, 1), (1024, 3)][int(rng.integers(0, 4))]
+                        for c, v in zip(cols, (s, kind, k, mode, a, b)):
+                            cols[c].append(v)
+            s += 1
+    got, ref, qh = run_wide(ctx, topos, st, busy, cols)
+    assert_same(got, ref, qh["k"], "wide")
+    assert (ref["status"] == 0).sum() > 100
+    assert ctx.stats()["self_check_failures"] == 0
+
+
+def test_wide_jobs_of_nine_to_twelve(ctx):
+    """k = 9..12 on 9..12 free accelerators of 18- and 20-vertex servers,
+    up to 12! embeddings per query."""
+    rng = np.random.default_rng(912)
+    topos = [random_topology(rng, 18, 3, 0.6), random_topology(rng, 20, 7, 0.8)]
+    st, busy, cols = [], [], {c: [] for c in ("server", "kind", "k", "mode", "a", "b")}
+    s = 0
+    for t in range(2):
+        for F in (9, 10, 11, 12):
+            st.append(t)
+            busy.append(busy_leaving(rng, topos[t].shape[0], F))
+            for kind in range(3):
+                for k in range(9, 13):
+                    if k < F and math.perm(F, k) > 4_000_000:
+                        continue  # k = F stays: the oracle takes a few seconds for 12!
+                    mode = int(rng.integers(0, 2))
+                    for c, v in zip(cols, (s, kind, k, mode, 1, 1)):
+                        cols[c].append(v)
+            s += 1
+    got, ref, qh = run_wide(ctx, topos, st, busy, cols)
+    assert_same(got, ref, qh["k"], "k9-12")
+    assert (ref["status"] == 0).sum() >= 12 and (qh["k"] >= 11).any()
+    assert ctx.stats()["self_check_failures"] == 0
+
+
+def test_wide_path_equals_batch_path_on_small_servers(ctx):
+    """On servers both paths take (n <= 16, k <= 8) the wide call answers
+    exactly as mapa_query_batch: 8,192 queries of the batched config."""
+    wl = synth.config2(8192)
+    qh, _ = B.load_workload(ctx, wl)
+    base = ctx.query_batch(qh)
+    wide = ctx.query_batch_wide(qh)
+    for f in ("count", "status", "key", "agg", "pres", "vertex_mask", "alloc_handle"):
+        assert np.array_equal(wide[f], base[f]), f
+    assert np.array_equal(wide["mapping"][:, :8], base["mapping"])
+    assert (wide["mapping"][:, 8:] == 0xFF).all()
+
+
+def test_five_cube_hand_counts(ctx):
+    """Q5 (32 vertices, degree 5, bipartite): LINKED ring k=2: 160; 4-cycles
+    80 faces x 8 = 640; heap tree k=3: 32*5*4 = 640; heap tree k=4: 2560;
+    no triangle; ALL mode ring k=3: 32*31*30."""
+    W = np.zeros((32, 32), np.uint8)
+    for u in range(32):
+        for b in range(5):
+            W[u, u ^ (1 << b)] = 1
+    ids = ctx.load_servers([W], np.zeros(1, np.int32))
+    q = B.pack_queries(ids[[0] * 6], [0, 0, 2, 2, 1, 0], [2, 4, 3, 4, 3, 3], [1, 1, 1, 1, 1, 0])
+    got = ctx.query_batch_wide(q)
+    assert list(got["count"]) == [160, 640, 640, 2560, 0, 29760]
+    assert got["status"][4] == B.RES_NOFIT
+
+
+def test_wide_registered_patterns(ctx):
+    """Registered application graphs on 24-vertex servers, both modes."""
+    rng = np.random.default_rng(24)
+    pats = [(5, [(0, 4), (1, 4), (2, 4), (3, 4)]), (6, [(0, 1), (1, 2), (2, 0), (3, 4), (4, 5)]),
+            (4, []), (8, [(i, (i + 3) % 8) for i in range(8)])]
+    kinds = [ctx.create_pattern(k, e) for k, e in pats]
+    topos = [random_topology(rng, 24, 3, 0.5)]
+    st, busy, cols, edges = [], [], {c: [] for c in ("server", "kind", "k", "mode", "a", "b")}, []
+    for s, F in enumerate((6, 8, 9)):
+        st.append(0)
+        busy.append(busy_leaving(rng, 24, F))
+        for (k, e), kind in zip(pats, kinds):
+            if math.perm(F, k) > 20_000:
+                continue
+            for mode in (0, 1):
+                for c, v in zip(cols, (s, kind, k, mode, 1, 1)):
+                    cols[c].append(v)
+                edges.append(e)
+    got, ref, qh = run_wide(ctx, topos, st, busy, cols, edges)
+    assert_same(got, ref, qh["k"], "wide patterns")
+
+
+def test_wide_commit_conflict_release(ctx):
+    """Per server only the first committing query commits; later committing
+    queries of that server get MAPA_RES_CONFLICT; handles release."""
+    rng = np.random.default_rng(5)
+    W = random_topology(rng, 28, 3, 0.6)
+    ids = ctx.load_servers([W, W], np.zeros(2, np.int32))
+    ctx.set_busy(ids, [busy_leaving(rng, 28, 10), busy_leaving(rng, 28, 10)])
+    before = ctx.get_busy(ids).copy()
+    q = B.pack_queries(ids[[0, 0, 1, 0]], [0, 1, 2, 0], [9, 3, 4, 2], commit=[1, 1, 1, 0])
+    got = ctx.query_batch_wide(q)
+    assert list(got["status"]) == [B.RES_OK, B.RES_CONFLICT, B.RES_OK, B.RES_OK]
+    after = ctx.get_busy(ids)
+    assert after[0] == before[0] | got["vertex_mask"][0]
+    assert after[1] == before[1] | got["vertex_mask"][2]
+    assert got["alloc_handle"][1] == -1 and got["alloc_handle"][3] == -1
+    ctx.release(got["alloc_handle"][[0, 2]])
+    assert np.array_equal(ctx.get_busy(ids), before)
