@@ -71,14 +71,25 @@ __device__ void wide_level(WideState &s, uint32_t rest, unsigned long long code,
   wide_masks(s, code, pos, rest, nbm, cand);
   const int sh = 5 * (kWideK - 1 - pos);
   if constexpr (L == 1) {
+    // every candidate is a leaf: scored as ((key + 1) << 5) | (31 - c), so
+    // one max picks the node's largest key and, among equal keys, the first
+    // leaf (keys stay below 2^27: weights <= 255, n <= 32, a, b <= 1024)
+    s.count += (unsigned long long)__popc(cand);
+    uint32_t best = 0;
     for (uint32_t m = cand; m; m &= m - 1) {
       const int c = __builtin_ctz(m);
-      const int key = kp + s.a * wsum_wide(s.rows, s.B, c, nbm) - s.b * wsum_wide(s.rows, s.B, c, rest);
-      s.count += 1;
-      if (key > s.bkey) {  // leaves come in lexicographic order: keep the first maximum
-        s.bkey = key;
-        s.bcode = code | ((unsigned long long)c << sh);
+      int v = kp + 1;
+      for (int t = 0; t < s.B; ++t) {
+        const uint32_t r = s.rows[t * 32 + c];
+        v += (s.a * __popc(r & nbm) - s.b * __popc(r & rest)) << t;
       }
+      const uint32_t pk = ((uint32_t)v << 5) | (31u - (uint32_t)c);
+      best = pk > best ? pk : best;
+    }
+    const int key = (int)(best >> 5) - 1;
+    if (best && key > s.bkey) {  // nodes come in lexicographic order: keep the first maximum
+      s.bkey = key;
+      s.bcode = code | ((unsigned long long)(31u - (best & 31u)) << sh);
     }
   } else {
     for (uint32_t m = cand; m; m &= m - 1) {
