@@ -49,9 +49,10 @@ ALU_PEAK = CU * LANES_PER_CLK * CLK  # 78.64e12 int32 lane-ops/s
 # while the kernel sources still hash to the value the profile was taken on.
 KERNEL_SOURCES = tuple("paper_2110_03214_amd/csrc/" + f for f in (
     "device.h", "enumerate.h", "enum_pair12_lds.hip", "enum_pair12_glb.hip", "enum_pair8.hip",
-    "enum_plain.hip",
-    "mapa_internal.h"))
-PMC_PROFILE = {2: "k_enumerate_batched_65536q_pmc.txt", 3: "k_enumerate_large_1536q_pmc.txt"}
+    "enum_plain.hip", "mapa_internal.h"))
+WIDE_SOURCES = tuple("paper_2110_03214_amd/csrc/" + f for f in ("wide.hip", "mapa_internal.h"))
+PMC_PROFILE = {2: "k_enumerate_batched_65536q_pmc.txt", 3: "k_enumerate_large_1536q_pmc.txt",
+               6: "k_wide_search_wide_96q_pmc.txt"}
 
 WORKLOAD_TEXT = {
     1: "tiny: 1,000 states of one 8-vertex cube-mesh (weights 1-2), 0-4 busy, ring k=4",
@@ -102,9 +103,10 @@ def algorithmic_ops(wl) -> tuple[int, int]:
     return emb, ops
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(cfg: int = 2) -> str:
+    """sha256 of the sources of the kernel a workload's roofline is about."""
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
+    for rel in (WIDE_SOURCES if cfg == 6 else KERNEL_SOURCES):
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
@@ -126,7 +128,7 @@ def profiled_traffic(cfg: int):
             if ":" in line and not line.startswith(" "):
                 key, _, val = line.partition(":")
                 fields[key.strip()] = val.strip()
-    if fields.get("kernel_source_sha256") != kernel_source_hash():
+    if fields.get("kernel_source_sha256") != kernel_source_hash(cfg):
         return None, f"profiles/{name} was taken on other kernel sources"
     if "traffic_bytes_per_launch" not in fields:
         return None, f"profiles/{name} holds no memory counters"
