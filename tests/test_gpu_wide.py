@@ -193,3 +193,25 @@ def test_wide_commit_conflict_release(ctx):
     assert got["alloc_handle"][1] == -1 and got["alloc_handle"][3] == -1
     ctx.release(got["alloc_handle"][[0, 2]])
     assert np.array_equal(ctx.get_busy(ids), before)
+
+
+def test_batch_path_refuses_wide_servers(ctx, torch):
+    """The batch path answers queries on servers of more than 16
+    accelerators with MAPA_RES_INVALID through device pointers (and refuses
+    them up front through host pointers); the rest of the batch is served."""
+    W = np.ones((24, 24), np.uint8) - np.eye(24, dtype=np.uint8)
+    ids = ctx.load_servers([W, np.ones((4, 4), np.uint8) - np.eye(4, dtype=np.uint8)],
+                           np.array([0, 1], np.int32))
+    q = B.pack_queries(ids, [0, 0], [3, 3])
+    with pytest.raises(B.MapaError) as e:
+        ctx.query_batch(q)
+    assert e.value.code == B.ERR_UNSUPPORTED
+    dq = torch.from_numpy(q.view(np.uint8)).to("cuda")
+    dr = torch.zeros(2 * 48, dtype=torch.uint8, device="cuda")
+    ctx.query_batch(dq, dr, stream=torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    got = dr.cpu().numpy().view(B.RESULT_DTYPE)
+    assert got["status"][0] == B.RES_INVALID
+    assert got["status"][1] == B.RES_OK and got["count"][1] == 24
+    wide = ctx.query_batch_wide(q)
+    assert list(wide["count"]) == [24 * 23 * 22, 24]
