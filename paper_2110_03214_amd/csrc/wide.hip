@@ -52,6 +52,21 @@ struct WideState {
   unsigned long long bcode;
 };
 
+// a * w(c, nbm) - b * w(c, rest): one pass over the weight planes; the
+// common cases of one and two planes (weights up to 3) unrolled
+__device__ __forceinline__ int wide_term(const WideState &s, int c, uint32_t nbm, uint32_t rest) {
+  const uint32_t r0 = s.rows[c];
+  int v = s.a * __popc(r0 & nbm) - s.b * __popc(r0 & rest);
+  if (s.B == 1) return v;
+  const uint32_t r1 = s.rows[32 + c];
+  v += (s.a * __popc(r1 & nbm) - s.b * __popc(r1 & rest)) << 1;
+  for (int t = 2; t < s.B; ++t) {
+    const uint32_t r = s.rows[t * 32 + c];
+    v += (s.a * __popc(r & nbm) - s.b * __popc(r & rest)) << t;
+  }
+  return v;
+}
+
 // vertices at the earlier pattern neighbours of position pos, and the
 // candidates for pos (in LINKED mode adjacent to each of them)
 __device__ __forceinline__ void wide_masks(const WideState &s, unsigned long long code, int pos,
@@ -78,11 +93,7 @@ __device__ void wide_level(WideState &s, uint32_t rest, unsigned long long code,
     uint32_t best = 0;
     for (uint32_t m = cand; m; m &= m - 1) {
       const int c = __builtin_ctz(m);
-      int v = kp + 1;
-      for (int t = 0; t < s.B; ++t) {
-        const uint32_t r = s.rows[t * 32 + c];
-        v += (s.a * __popc(r & nbm) - s.b * __popc(r & rest)) << t;
-      }
+      const int v = kp + 1 + wide_term(s, c, nbm, rest);
       const uint32_t pk = ((uint32_t)v << 5) | (31u - (uint32_t)c);
       best = pk > best ? pk : best;
     }
@@ -94,7 +105,7 @@ __device__ void wide_level(WideState &s, uint32_t rest, unsigned long long code,
   } else {
     for (uint32_t m = cand; m; m &= m - 1) {
       const int c = __builtin_ctz(m);
-      const int kp2 = kp + s.a * wsum_wide(s.rows, s.B, c, nbm) - s.b * wsum_wide(s.rows, s.B, c, rest);
+      const int kp2 = kp + wide_term(s, c, nbm, rest);
       wide_level<L - 1>(s, rest & ~(1u << c), code | ((unsigned long long)c << sh), kp2, pos + 1);
     }
   }
