@@ -199,7 +199,8 @@ struct WidePlan {
   uint8_t k, mode, d, B; // positions, match mode, prefix depth, weight bit-planes in use
   uint8_t F, status, commit, owner;  // owner: first committing query of its server
   int16_t a, b;
-  uint16_t topo, pad;
+  uint16_t topo;
+  uint16_t nb_all;       // 1: every earlier position neighbours each position (all-to-all)
   uint32_t items;        // F!/(F-d)! prefixes
   uint32_t block0, nblocks;
 };

@@ -145,6 +145,7 @@ extern "C" int32_t mapa_query_batch_wide(mapa_ctx *c, const mapa_query *q, int32
     p.kp0 = qq.b * WR;
     p.server = qq.server;
     wide_neighbours(c, qq.kind, qq.k, p.nb);
+    p.nb_all = qq.kind == MAPA_ALL_TO_ALL ? 1 : 0;
     p.k = qq.k;
     p.mode = qq.mode;
     p.B = (uint8_t)B;

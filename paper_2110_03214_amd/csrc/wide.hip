@@ -46,7 +46,7 @@ __device__ __forceinline__ int vertex_at(unsigned long long code, int pos) {
 struct WideState {
   const uint32_t *rows;  // LDS: [kWidePlanes][32]
   const WidePlan *p;
-  int B, a, b, k, linked;
+  int B, a, b, k, linked, nb_all;
   unsigned long long count;
   int bkey;
   unsigned long long bcode;
@@ -71,8 +71,12 @@ __device__ __forceinline__ int wide_term(const WideState &s, int c, uint32_t nbm
 // candidates for pos (in LINKED mode adjacent to each of them)
 __device__ __forceinline__ void wide_masks(const WideState &s, unsigned long long code, int pos,
                                            uint32_t rest, uint32_t &nbm, uint32_t &cand) {
-  nbm = 0;
   cand = rest;
+  if (s.nb_all && !s.linked) {  // all-to-all: every vertex chosen so far
+    nbm = s.p->R & ~rest;
+    return;
+  }
+  nbm = 0;
   for (uint32_t m = s.p->nb[pos]; m; m &= m - 1) {
     const int v = vertex_at(code, __builtin_ctz(m));
     nbm |= 1u << v;
@@ -157,6 +161,7 @@ __global__ __launch_bounds__(kWideThreads) __attribute__((amdgpu_waves_per_eu(6)
   s.b = p->b;
   s.k = p->k;
   s.linked = p->mode;
+  s.nb_all = p->nb_all;
   s.count = 0;
   s.bkey = -1;
   s.bcode = ~0ull;
