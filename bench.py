@@ -48,7 +48,7 @@ ALU_PEAK = CU * LANES_PER_CLK * CLK  # 78.64e12 int32 lane-ops/s
 # kernel, committed under profiles/; their HBM byte count is reported only
 # while the kernel sources still hash to the value the profile was taken on.
 KERNEL_SOURCES = tuple("paper_2110_03214_amd/csrc/" + f for f in (
-    "device.h", "enumerate.h", "enum_pair12_lds.hip", "enum_pair12_glb.hip", "enum_pair8.hip",
+    "device.h", "enumerate.h", "enum_pair12_lds.hip", "enum_pair12_glb.hip", "enum_pair6.hip",
     "enum_plain.hip", "mapa_internal.h"))
 WIDE_SOURCES = tuple("paper_2110_03214_amd/csrc/" + f for f in ("wide.hip", "mapa_internal.h"))
 PMC_PROFILE = {2: "k_enumerate_batched_65536q_pmc.txt", 3: "k_enumerate_large_1536q_pmc.txt",

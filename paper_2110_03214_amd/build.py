@@ -26,7 +26,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libmapa.so")
 SOURCES = [os.path.join(CSRC, f) for f in (
-    "enum_pair12_lds.hip", "enum_pair12_glb.hip", "enum_pair8.hip", "enum_plain.hip",
+    "enum_pair12_lds.hip", "enum_pair12_glb.hip", "enum_pair6.hip", "enum_plain.hip",
     "fused.hip", "kernels.hip", "wide.hip", "host.cpp", "serve.cpp", "wide.cpp")]
 ARCH = "gfx950"
 

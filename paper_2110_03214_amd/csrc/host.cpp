@@ -125,7 +125,7 @@ void fill_args(mapa_ctx *c, const Workspace &w, BatchArgs &a) {
   // registers (fewer waves per SIMD), so up to 12 free vertices only where
   // topologies have 10 or more vertices (measured: 8 is best below that)
   const int max_n = c->topo_n.empty() ? 0 : *std::max_element(c->topo_n.begin(), c->topo_n.end());
-  a.pair = c->wpr != 1 ? 0 : max_n >= 10 ? 12 : 8;
+  a.pair = c->wpr != 1 ? 0 : max_n >= 10 ? 12 : 6;
   int per_cu = c->tuning.blocks_per_cu;
   if (per_cu <= 0) {
     // the occupancy query costs microseconds: ask once per launch shape

@@ -429,14 +429,14 @@ hipError_t launch_batch_front(const BatchArgs &a, hipStream_t s) {
 hipError_t launch_enumerate(const BatchArgs &a, hipStream_t s) {
   if (a.wpr == 1 && a.pair >= 12)
     return a.rows_in_lds ? launch_enum_pair12_lds(a, s) : launch_enum_pair12_glb(a, s);
-  if (a.wpr == 1 && a.pair >= 8) return launch_enum_pair8(a, s);
+  if (a.wpr == 1 && a.pair >= 6) return launch_enum_pair6(a, s);
   return launch_enum_plain(a, s);
 }
 
 int enumerate_occupancy(int wpr, int rows_in_lds, int pair, int threads, size_t lds_bytes) {
   if (wpr == 1 && pair >= 12)
     return rows_in_lds ? occ_enum_pair12_lds(threads, lds_bytes) : occ_enum_pair12_glb(threads, lds_bytes);
-  if (wpr == 1 && pair >= 8) return occ_enum_pair8(rows_in_lds, threads, lds_bytes);
+  if (wpr == 1 && pair >= 6) return occ_enum_pair6(rows_in_lds, threads, lds_bytes);
   return occ_enum_plain(wpr, rows_in_lds, threads, lds_bytes);
 }
 
@@ -446,7 +446,7 @@ hipError_t upload_tables(const Tables &t) {
   if (e == hipSuccess) e = upload_tables_fused(t);
   if (e == hipSuccess) e = upload_tables_enum_pair12_lds(t);
   if (e == hipSuccess) e = upload_tables_enum_pair12_glb(t);
-  if (e == hipSuccess) e = upload_tables_enum_pair8(t);
+  if (e == hipSuccess) e = upload_tables_enum_pair6(t);
   if (e == hipSuccess) e = upload_tables_enum_plain(t);
   return e;
 }

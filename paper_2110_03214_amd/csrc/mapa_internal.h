@@ -231,15 +231,15 @@ hipError_t upload_tables_front(const Tables &t);
 hipError_t upload_tables_fused(const Tables &t);
 hipError_t upload_tables_enum_pair12_lds(const Tables &t);
 hipError_t upload_tables_enum_pair12_glb(const Tables &t);
-hipError_t upload_tables_enum_pair8(const Tables &t);
+hipError_t upload_tables_enum_pair6(const Tables &t);
 hipError_t upload_tables_enum_plain(const Tables &t);
 hipError_t launch_enum_pair12_lds(const BatchArgs &a, hipStream_t s);
 hipError_t launch_enum_pair12_glb(const BatchArgs &a, hipStream_t s);
-hipError_t launch_enum_pair8(const BatchArgs &a, hipStream_t s);
+hipError_t launch_enum_pair6(const BatchArgs &a, hipStream_t s);
 hipError_t launch_enum_plain(const BatchArgs &a, hipStream_t s);
 int occ_enum_pair12_lds(int threads, size_t lds_bytes);
 int occ_enum_pair12_glb(int threads, size_t lds_bytes);
-int occ_enum_pair8(int rows_in_lds, int threads, size_t lds_bytes);
+int occ_enum_pair6(int rows_in_lds, int threads, size_t lds_bytes);
 int occ_enum_plain(int wpr, int rows_in_lds, int threads, size_t lds_bytes);
 hipError_t launch_batch_front(const BatchArgs &a, hipStream_t s);   // prepare .. expand
 hipError_t launch_enumerate(const BatchArgs &a, hipStream_t s);
