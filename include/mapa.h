@@ -411,7 +411,8 @@ int32_t mapa_serve_start(mapa_ctx *ctx, const mapa_serve_opts *opts);
 
 /* Queue n requests (host array, copied).  All-or-nothing validation: unknown
  * server -> MAPA_ERR_UNKNOWN_SERVER, malformed field or an arrival earlier
- * than the previous one -> MAPA_ERR_INVALID_ARG, k > 8 -> MAPA_ERR_UNSUPPORTED. */
+ * than the previous one -> MAPA_ERR_INVALID_ARG, k > 8 or a server of more
+ * than 16 accelerators -> MAPA_ERR_UNSUPPORTED. */
 int32_t mapa_serve_submit(mapa_ctx *ctx, const mapa_request *reqs, int32_t n);
 
 /* Move up to cap finished requests into out (host array); *n_out = how many. */
