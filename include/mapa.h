@@ -257,8 +257,9 @@ typedef struct {
 } mapa_result_wide;
 
 /* The same query semantics (Sec. 3.3-3.5, Alg. 1, reading of batches as in
- * mapa_query_batch) for the sizes beyond the batch path, the paper's jobs
- * of 9 accelerators and more: servers of up to 32 accelerators and patterns
+ * mapa_query_batch) for the sizes beyond the batch path, the jobs of 9
+ * accelerators and more on larger hardware graphs whose scheduling cost
+ * Sec. 5.4 discusses: servers of up to 32 accelerators and patterns
  * of up to 12 vertices (ring, all-to-all and tree of any k <= 12, or a
  * registered pattern), key a*AggBW + b*PreservedBW (MAPA_METRIC_EFFBW ->
  * MAPA_ERR_UNSUPPORTED).  Any server may be queried this way.

@@ -1,5 +1,5 @@
 """Pins for the oracle on wide shapes: servers of 17..32 accelerators and
-patterns of 9..12 vertices (the paper's "9 GPUs and above").  Values come
+patterns of 9..12 vertices (the larger jobs of Sec. 5.4).  Values come
 from combinatorics and textbook problems, not from the oracle itself."""
 import itertools
 import math
