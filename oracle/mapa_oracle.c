@@ -44,8 +44,11 @@
  *     topologies are unsupported for this metric.
  *
  * Sizes: n <= 32 accelerators, k <= 12 pattern vertices.  PreservedBW
- * depends only on the chosen vertex set; for n <= 20 its literal double loop
- * is memoised per vertex set (same loop, evaluated at most once per set).
+ * depends only on the chosen vertex set (Eq. 3 sums over pairs of free
+ * vertices outside it), so its literal double loop is memoised per vertex
+ * set: for n <= 20 in a table indexed by the set, above that in a plain
+ * open-addressing hash map of at most OR_HASH_CAP sets (once it is 3/4 full,
+ * further sets are evaluated by the same loop without being stored).
  * Parity of this file is pinned by the "not gpu" test-suite: closed-form
  * counts, hand-derived counts and argmaxes, the paper's worked AggBW example,
  * automorphism counts, textbook special cases and exhaustive agreement with an
@@ -62,6 +65,8 @@
 #define OR_MAX_E (OR_MAX_K * (OR_MAX_K - 1) / 2) /* 66 */
 #define OR_MEMO_MAX_N 20 /* PreservedBW memo per vertex set up to this n */
 #define OR_MAX_AB 1024
+#define OR_HASH_BITS 18
+#define OR_HASH_CAP (1u << OR_HASH_BITS) /* PreservedBW memo above OR_MEMO_MAX_N */
 
 enum { OR_RING = 0, OR_A2A = 1, OR_TREE = 2 };
 enum { OR_MODE_ALL = 0, OR_MODE_LINKED = 1 };
@@ -190,6 +195,9 @@ typedef struct {
   int R[OR_MAX_N], F;
   uint32_t Rmask;
   int32_t *memo; /* 1<<n entries (n <= OR_MEMO_MAX_N, else NULL); -1 = not yet evaluated */
+  uint32_t *hkey; /* n > OR_MEMO_MAX_N: hash map vertex set -> PreservedBW (key 0 = empty slot;  */
+  int32_t *hval;  /* a chosen set is never empty since k >= 1), or NULL                         */
+  uint32_t hused;
   int phi[OR_MAX_K];
   int used[OR_MAX_N];
   int64_t count;
@@ -204,6 +212,12 @@ typedef struct {
  * free vertices not in S (the subgraph induced by R \ S). */
 static int64_t preserved_bw(or_state *s, uint32_t S) {
   if (s->memo && s->memo[S] >= 0) return s->memo[S];
+  uint32_t h = 0;
+  if (s->hkey) {
+    h = (S * 2654435761u) >> (32 - OR_HASH_BITS);
+    while (s->hkey[h] != 0 && s->hkey[h] != S) h = (h + 1) & (OR_HASH_CAP - 1);
+    if (s->hkey[h] == S) return s->hval[h];
+  }
   int64_t p = 0;
   for (int u = 0; u < s->n; ++u) {
     if (!((s->Rmask >> u) & 1u) || ((S >> u) & 1u)) continue;
@@ -213,6 +227,11 @@ static int64_t preserved_bw(or_state *s, uint32_t S) {
     }
   }
   if (s->memo) s->memo[S] = (int32_t)p;
+  if (s->hkey && s->hused < OR_HASH_CAP / 4 * 3) {
+    s->hkey[h] = S;
+    s->hval[h] = (int32_t)p;
+    ++s->hused;
+  }
   return p;
 }
 
@@ -317,6 +336,16 @@ static int query_with_memo(int n, const uint8_t *W, uint32_t busy, int k, int ne
     if (!((busy >> v) & 1u)) { s->R[s->F++] = v; s->Rmask |= 1u << v; }
   if (memo)
     for (uint32_t m = 0; m < (1u << n); ++m) memo[m] = -1;
+  if (!memo && n > OR_MEMO_MAX_N) {
+    s->hkey = (uint32_t *)calloc(OR_HASH_CAP, sizeof(uint32_t));
+    s->hval = (int32_t *)malloc(OR_HASH_CAP * sizeof(int32_t));
+    if (!s->hkey || !s->hval) { /* no memo: every set evaluated by the loop */
+      free(s->hkey);
+      free(s->hval);
+      s->hkey = NULL;
+      s->hval = NULL;
+    }
+  }
 
   if (k <= s->F) extend(s, 0);
 
@@ -334,6 +363,8 @@ static int query_with_memo(int n, const uint8_t *W, uint32_t busy, int k, int ne
   } else {
     out->status = OR_NOFIT;
   }
+  free(s->hkey);
+  free(s->hval);
   free(s);
   return OR_OK;
 }

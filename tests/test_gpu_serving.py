@@ -50,9 +50,13 @@ def drain(ctx, n):
     return np.concatenate(got) if got else np.zeros(0, B.COMPLETION_DTYPE)
 
 
-def check_against_alone(tr, reqs, comp, max_leaves=2e7):
+def check_against_alone(tr, reqs, comp, max_leaves=2e7, ctx=None, ids=None):
     """Oracle answer of each request alone, on its server's topology with the
-    busy mask it was dispatched with."""
+    busy mask it was dispatched with.  Requests of more than max_leaves
+    embeddings are checked, when a context is given (the serving loop
+    stopped), against a single-query GPU batch of that request alone on its
+    server with that busy mask (the batch path, which the full large-config
+    parity pins to the oracle).  Returns the number of requests checked."""
     order = np.argsort(comp["id"])
     comp = comp[order]
     assert np.array_equal(comp["id"], np.arange(len(reqs)))
@@ -75,7 +79,26 @@ def check_against_alone(tr, reqs, comp, max_leaves=2e7):
         assert np.array_equal(got["mapping"][m, :kk], ref["mapping"][m, :kk])
     # every granted request is committed, every other is not
     assert ((got["alloc_handle"] >= 0) == ok).all()
-    return len(sel)
+    checked = len(sel)
+    big = np.nonzero(leaves > max_leaves)[0]
+    if ctx is not None and len(big):
+        for i in big:
+            sid = int(ids[srv[i]])
+            ctx.set_busy([sid], [int(comp["busy_before"][i])])
+            q = B.pack_queries([sid], [reqs["kind"][i]], [reqs["k"][i]], reqs["mode"][i], 0,
+                               reqs["a"][i], reqs["b"][i])
+            r = ctx.query_batch(q)[0]
+            c = comp[i]
+            for f in ("count", "status"):
+                assert int(r[f]) == int(c[f]), (i, f)
+            assert c["status"] == 0 and c["alloc_handle"] >= 0
+            for f in ("key", "agg", "pres", "vertex_mask"):
+                assert int(r[f]) == int(c[f]), (i, f)
+            kk = int(reqs["k"][i])
+            assert np.array_equal(r["mapping"][:kk], c["mapping"][:kk]), i
+            checked += 1
+        ctx.set_busy(ids, np.zeros(len(ids), np.uint32))
+    return checked
 
 
 def test_serving_mix_equals_alone_batched_config_servers(ctx):
@@ -106,8 +129,9 @@ def test_serving_mixed_sizes_admission_and_release(ctx):
     comp = drain(ctx, tr.n)
     st = ctx.serve_stop()
     assert len(comp) == tr.n and st["completed"] == tr.n
-    check_against_alone(tr, reqs, comp, max_leaves=2e7)
     assert (ctx.get_busy(ids) == 0).all()
+    checked = check_against_alone(tr, reqs, comp, max_leaves=2e7, ctx=ctx, ids=ids)
+    assert checked == tr.n
 
 
 def test_serving_as_fast_as_possible_and_restart(ctx):

@@ -215,3 +215,33 @@ def test_batch_path_refuses_wide_servers(ctx, torch):
     assert got["status"][1] == B.RES_OK and got["count"][1] == 24
     wide = ctx.query_batch_wide(q)
     assert list(wide["count"]) == [24 * 23 * 22, 24]
+
+
+def test_wide_config_full_against_stored_oracle_results(ctx):
+    """Every query of the wide benchmark workload (16 seeded 32-vertex
+    servers, 12 free accelerators each, ring / all-to-all / tree with k = 9
+    and 10), in the call the benchmark times, against the stored oracle
+    results field by field (tests/golden/c6_expected.txt, written by
+    tests/golden/make_c6_expected.py from the oracle alone)."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c6_expected.txt")
+    if not os.path.exists(path):
+        pytest.skip("tests/golden/c6_expected.txt not generated")
+    rows = [[int(x) for x in line.split()] for line in open(path) if not line.startswith("#")]
+    wl = synth.config6()
+    assert len(rows) == wl.nq
+    q, ids = B.load_workload(ctx, wl)
+    got = ctx.query_batch_wide(q)
+    for i, r in enumerate(rows):
+        idx, server, busy, kind, k = r[:5]
+        count, status, key, agg, pres, mask = r[5:11]
+        assert idx == i and busy == int(wl.busy[server])
+        assert (int(wl.queries["kind"][i]), int(wl.queries["k"][i])) == (kind, k)
+        g = got[i]
+        assert (int(g["count"]), int(g["status"])) == (count, status), i
+        assert (int(g["key"]), int(g["agg"]), int(g["pres"]), int(g["vertex_mask"])) == \
+            (key, agg, pres, mask), i
+        assert tuple(int(x) for x in g["mapping"][:k]) == tuple(r[11:11 + k]), i
+        assert (g["mapping"][k:] == 0xFF).all()
+    # a second call on the same state answers the same (nothing committed)
+    again = ctx.query_batch_wide(q)
+    assert np.array_equal(again, got)
