@@ -380,11 +380,14 @@ typedef struct {           /* 40 bytes */
   int32_t reserved1;       /* must be 0                                                */
 } mapa_request;
 
-typedef struct {           /* 72 bytes */
+typedef struct {           /* 80 bytes */
   int64_t id;
   int64_t count;           /* matches scored                                           */
   int64_t alloc_handle;    /* (server << 32) | vertex_mask if granted, else -1         */
   double latency_us;       /* completion time minus scheduled arrival time             */
+  double wait_us;          /* queue wait: dispatch of its batch (or its host answer)
+                              minus scheduled arrival; latency_us - wait_us is the
+                              batch's turnaround                                       */
   int32_t status;          /* MAPA_RES_OK or MAPA_RES_NOFIT                            */
   int32_t key, agg, pres;
   uint32_t vertex_mask;
@@ -404,6 +407,11 @@ typedef struct {
   double mean_batch;       /* mean queries per device batch                            */
   double mean_batch_us;    /* mean time from a batch's dispatch to its results on the host */
   int64_t fused_batches;   /* batches run as one fused launch (small batches)    */
+  double wait_p50_us, wait_p99_us;        /* queue wait percentiles                     */
+  double turnaround_p50_us, turnaround_p99_us;  /* latency minus queue wait           */
+  double mean_dispatch_us; /* host time to build and enqueue one device batch          */
+  double mean_gpu_us;      /* device time of one batch's kernels (HIP events)          */
+  double mean_harvest_us;  /* host time to turn one batch's results into completions   */
 } mapa_serve_stats;
 
 /* Start the loop.  opts may be NULL (defaults).  MAPA_ERR_STATE if a loop is

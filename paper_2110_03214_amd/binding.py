@@ -75,7 +75,10 @@ class ServeStats(ctypes.Structure):
         "requests", "completed", "granted", "nofit", "host_nofit", "batches", "releases",
         "embeddings", "admission_waits")] + [(n, ctypes.c_double) for n in (
             "wall_s", "requests_per_s", "embeddings_per_s", "p50_us", "p99_us", "p999_us",
-            "max_us", "mean_batch", "mean_batch_us")] + [("fused_batches", ctypes.c_int64)]
+            "max_us", "mean_batch", "mean_batch_us")] + [("fused_batches", ctypes.c_int64)] + [
+                (n, ctypes.c_double) for n in (
+                    "wait_p50_us", "wait_p99_us", "turnaround_p50_us", "turnaround_p99_us",
+                    "mean_dispatch_us", "mean_gpu_us", "mean_harvest_us")]
 
 
 REQUEST_DTYPE = np.dtype([("id", np.int64), ("t_arrival", np.float64), ("hold", np.float64),
@@ -83,11 +86,12 @@ REQUEST_DTYPE = np.dtype([("id", np.int64), ("t_arrival", np.float64), ("hold", 
                           ("mode", np.uint8), ("metric", np.uint8), ("a", np.int16),
                           ("b", np.int16), ("reserved1", np.int32)])
 COMPLETION_DTYPE = np.dtype([("id", np.int64), ("count", np.int64), ("alloc_handle", np.int64),
-                             ("latency_us", np.float64), ("status", np.int32), ("key", np.int32),
+                             ("latency_us", np.float64), ("wait_us", np.float64),
+                             ("status", np.int32), ("key", np.int32),
                              ("agg", np.int32), ("pres", np.int32), ("vertex_mask", np.uint32),
                              ("busy_before", np.uint32), ("batch", np.int32),
                              ("server", np.int32), ("mapping", np.uint8, 8)])
-assert REQUEST_DTYPE.itemsize == 40 and COMPLETION_DTYPE.itemsize == 72
+assert REQUEST_DTYPE.itemsize == 40 and COMPLETION_DTYPE.itemsize == 80
 
 
 # every symbol include/mapa.h declares, with its ctypes signature
@@ -316,10 +320,14 @@ class Context:
         check(lib().mapa_serve_submit(self.h, _ptr(r), len(r)), "mapa_serve_submit")
 
     def serve_poll(self, cap: int = 65536) -> np.ndarray:
-        out = np.zeros(cap, dtype=COMPLETION_DTYPE)
+        """Completions finished since the last poll (a copy; the staging
+        buffer is kept between calls)."""
+        buf = getattr(self, "_poll_buf", None)
+        if buf is None or len(buf) < cap:
+            buf = self._poll_buf = np.zeros(cap, dtype=COMPLETION_DTYPE)
         n = ctypes.c_int32()
-        check(lib().mapa_serve_poll(self.h, _ptr(out), cap, ctypes.byref(n)), "mapa_serve_poll")
-        return out[:n.value]
+        check(lib().mapa_serve_poll(self.h, _ptr(buf), cap, ctypes.byref(n)), "mapa_serve_poll")
+        return buf[:n.value].copy()
 
     def serve_stop(self) -> dict:
         st = ServeStats()

@@ -138,7 +138,8 @@ struct mapa_ctx {
   uint64_t occ_shape = ~0ull;  // launch shape whose occupancy occ_blocks holds
   int occ_blocks = 0;
   bool profile = false;
-  std::vector<mapa::ProfEvents> prof;
+  std::vector<mapa::ProfEvents> prof;       // recorded, not yet read
+  std::vector<mapa::ProfEvents> prof_free;  // created earlier, ready for reuse
   double prof_ms = 0;
   int64_t prof_launches = 0;
   int64_t batches = 0;
@@ -168,5 +169,11 @@ int32_t enqueue_batch(mapa_ctx *c, const Workspace &w, const mapa_query *d_q,
                       mapa_result *d_res, int32_t nq, hipStream_t s);
 
 void serve_teardown(mapa_ctx *c);  // stop and free a running serving loop
+
+// Kernel timing (mapa_profile): record the start event of a timed launch on
+// stream s (events come from a pool, so timing costs no event creation once
+// warm), then its stop event, which queues the pair for mapa_get_stats.
+int32_t prof_start(mapa_ctx *c, hipStream_t s, ProfEvents &ev);
+int32_t prof_stop(mapa_ctx *c, hipStream_t s, const ProfEvents &ev);
 
 }  // namespace mapa

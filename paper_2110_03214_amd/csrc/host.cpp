@@ -195,6 +195,35 @@ int32_t enqueue_fused(mapa_ctx *c, const Workspace &w, const mapa_query *q, mapa
   return MAPA_OK;
 }
 
+int32_t prof_start(mapa_ctx *c, hipStream_t s, ProfEvents &ev) {
+  if (!c->prof_free.empty()) {
+    ev = c->prof_free.back();
+    c->prof_free.pop_back();
+  } else {
+    MAPA_HIPCHK(hipEventCreate(&ev.start));
+    if (hipEventCreate(&ev.stop) != hipSuccess) {
+      (void)hipEventDestroy(ev.start);
+      return fail(MAPA_ERR_DEVICE, "hipEventCreate failed");
+    }
+  }
+  const hipError_t e = hipEventRecord(ev.start, s);
+  if (e != hipSuccess) {
+    c->prof_free.push_back(ev);
+    return fail(MAPA_ERR_DEVICE, "hipEventRecord: %s", hipGetErrorString(e));
+  }
+  return MAPA_OK;
+}
+
+int32_t prof_stop(mapa_ctx *c, hipStream_t s, const ProfEvents &ev) {
+  const hipError_t e = hipEventRecord(ev.stop, s);
+  if (e != hipSuccess) {
+    c->prof_free.push_back(ev);
+    return fail(MAPA_ERR_DEVICE, "hipEventRecord: %s", hipGetErrorString(e));
+  }
+  c->prof.push_back(ev);
+  return MAPA_OK;
+}
+
 int32_t enqueue_batch(mapa_ctx *c, const Workspace &w, const mapa_query *d_q, mapa_result *d_res,
                       int32_t nq, hipStream_t s) {
   BatchArgs a;
@@ -587,10 +616,11 @@ int32_t mapa_ctx_destroy(mapa_ctx *c) {
     (void)hipSetDevice(c->device);
     if (c->last) (void)hipEventSynchronize(c->last);
     (void)hipDeviceSynchronize();
-    for (auto &e : c->prof) {
-      (void)hipEventDestroy(e.start);
-      (void)hipEventDestroy(e.stop);
-    }
+    for (auto *v : {&c->prof, &c->prof_free})
+      for (auto &e : *v) {
+        (void)hipEventDestroy(e.start);
+        (void)hipEventDestroy(e.stop);
+      }
     for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.exec);
     dev_free(c->d_pat_nbtab);
     dev_free(c->d_pat_k);
@@ -883,16 +913,11 @@ int32_t mapa_query_batch(mapa_ctx *c, const mapa_query *q, int32_t nq, mapa_resu
   a.res = dr;
   MAPA_HIPCHK(launch_batch_front(a, s));
   ProfEvents ev{};
-  if (c->profile) {
-    MAPA_HIPCHK(hipEventCreate(&ev.start));
-    MAPA_HIPCHK(hipEventCreate(&ev.stop));
-    MAPA_HIPCHK(hipEventRecord(ev.start, s));
-  }
+  if (c->profile)
+    if (int32_t rc2 = prof_start(c, s, ev)) return rc2;
   MAPA_HIPCHK(launch_enumerate(a, s));
-  if (c->profile) {
-    MAPA_HIPCHK(hipEventRecord(ev.stop, s));
-    c->prof.push_back(ev);
-  }
+  if (c->profile)
+    if (int32_t rc2 = prof_stop(c, s, ev)) return rc2;
   MAPA_HIPCHK(launch_finalize(a, s));
   if (!dev) MAPA_HIPCHK(hipMemcpyAsync(res, c->ws.d_res, nq * sizeof(mapa_result), hipMemcpyDeviceToHost, s));
   MAPA_HIPCHK(end_call(c, s));
@@ -1025,8 +1050,7 @@ int32_t mapa_get_stats(mapa_ctx *c, mapa_stats *out) {
       MAPA_HIPCHK(hipEventElapsedTime(&ms, e.start, e.stop));
       c->prof_ms += ms;
       ++c->prof_launches;
-      (void)hipEventDestroy(e.start);
-      (void)hipEventDestroy(e.stop);
+      c->prof_free.push_back(e);
     }
     c->prof.clear();
     Counters h;
@@ -1045,10 +1069,7 @@ int32_t mapa_reset_stats(mapa_ctx *c) {
   if (int32_t rc = not_while_serving(c, "mapa_reset_stats")) return rc;
   int32_t rc = sync_ctx(c);
   if (rc) return rc;
-  for (auto &e : c->prof) {
-    (void)hipEventDestroy(e.start);
-    (void)hipEventDestroy(e.stop);
-  }
+  for (auto &e : c->prof) c->prof_free.push_back(e);
   c->prof.clear();
   c->prof_ms = 0;
   c->prof_launches = 0;

@@ -45,6 +45,7 @@ struct Slot {
   Workspace ws;
   hipStream_t stream = nullptr;
   hipEvent_t done = nullptr;
+  hipEvent_t g0 = nullptr, g1 = nullptr;  // timing: around the batch's kernels
   mapa_query *h_q = nullptr;     // pinned
   mapa_result *h_res = nullptr;  // pinned
   int64_t *h_rel = nullptr;      // pinned, read by the release kernel in place
@@ -105,12 +106,14 @@ struct ServeState {
   std::priority_queue<Held, std::vector<Held>, HeldLater> held;
   std::vector<Held> deferred;  // due releases whose server has a request in flight
   std::vector<int64_t> held_forever;
-  std::vector<double> lat;
+  std::vector<double> lat, waits, turns;
+  std::vector<mapa_completion> out_buf;  // completions of one harvest, handed over under one lock
   mapa_serve_stats st{};
   int64_t completed = 0;
   int64_t batched_queries = 0;
   int64_t fused_batches = 0;
   double batch_us_sum = 0;
+  double dispatch_us_sum = 0, gpu_us_sum = 0, harvest_us_sum = 0;
   double last_done_us = 0;
   hipEvent_t rel_event = nullptr;
   bool rel_event_valid = false;
@@ -135,12 +138,21 @@ int32_t loop_fail(ServeState *S, int32_t code, const char *what, hipError_t e) {
     if (e_ != hipSuccess) return loop_fail(S, MAPA_ERR_DEVICE, #expr, e_);  \
   } while (0)
 
+// Record a completion; it reaches mapa_serve_poll at the next flush.
 void push_completion(ServeState *S, const mapa_completion &cpl, double now) {
   S->lat.push_back(cpl.latency_us);
+  S->waits.push_back(cpl.wait_us);
+  S->turns.push_back(cpl.latency_us - cpl.wait_us);
   S->last_done_us = now;
   ++S->completed;
+  S->out_buf.push_back(cpl);
+}
+
+void flush_completions(ServeState *S) {
+  if (S->out_buf.empty()) return;
   std::lock_guard<std::mutex> lk(S->mu);
-  S->done_q.push_back(cpl);
+  S->done_q.insert(S->done_q.end(), S->out_buf.begin(), S->out_buf.end());
+  S->out_buf.clear();
 }
 
 void make_ready(ServeState *S, int32_t s) {
@@ -158,6 +170,8 @@ int32_t harvest(ServeState *S, bool *did) {
     if (q == hipErrorNotReady) continue;
     if (q != hipSuccess) return loop_fail(S, MAPA_ERR_DEVICE, "batch", q);
     const double now = S->now_us();
+    float gms = 0;
+    if (hipEventElapsedTime(&gms, sl.g0, sl.g1) == hipSuccess) S->gpu_us_sum += 1e3 * gms;
     for (size_t i = 0; i < sl.reqs.size(); ++i) {
       const mapa_result &r = sl.h_res[i];
       const Req &rq = sl.reqs[i];
@@ -168,6 +182,7 @@ int32_t harvest(ServeState *S, bool *did) {
       cpl.count = r.count;
       cpl.alloc_handle = r.alloc_handle;
       cpl.latency_us = now - rq.due_us;
+      cpl.wait_us = sl.t_dispatch - rq.due_us;
       cpl.status = r.status;
       cpl.key = r.key;
       cpl.agg = r.agg;
@@ -195,10 +210,12 @@ int32_t harvest(ServeState *S, bool *did) {
       make_ready(S, s);
     }
     S->batch_us_sum += now - sl.t_dispatch;
+    S->harvest_us_sum += S->now_us() - now;
     sl.active = false;
     sl.reqs.clear();
     *did = true;
   }
+  flush_completions(S);
   return MAPA_OK;
 }
 
@@ -253,6 +270,7 @@ int32_t dispatch(ServeState *S, Slot &sl, bool final_release, bool *did) {
       cpl.id = rq.r.id;
       cpl.alloc_handle = -1;
       cpl.latency_us = now - rq.due_us;
+      cpl.wait_us = cpl.latency_us;
       cpl.status = MAPA_RES_NOFIT;
       cpl.key = INT32_MIN;
       cpl.busy_before = S->busy[s];
@@ -288,6 +306,7 @@ int32_t dispatch(ServeState *S, Slot &sl, bool final_release, bool *did) {
     S->in_ready[*it] = 1;
     S->ready.push_front(*it);
   }
+  flush_completions(S);  // host answers
   if (rel.empty() && sl.reqs.empty()) return MAPA_OK;
   *did = true;
 
@@ -339,6 +358,7 @@ int32_t dispatch(ServeState *S, Slot &sl, bool final_release, bool *did) {
       total += e;
     }
     int32_t rc;
+    SERVE_CHK(hipEventRecord(sl.g0, sl.stream));
     if (small && total <= kFusedMaxLeaves) {
       rc = enqueue_fused(c, sl.ws, sl.h_q, sl.h_res, nq, sl.stream);
       ++S->fused_batches;
@@ -355,8 +375,10 @@ int32_t dispatch(ServeState *S, Slot &sl, bool final_release, bool *did) {
       S->error_msg = "batch enqueue failed";
       return rc;
     }
+    SERVE_CHK(hipEventRecord(sl.g1, sl.stream));
     sl.batch_id = S->next_batch++;
     sl.t_dispatch = now;
+    S->dispatch_us_sum += S->now_us() - now;
     ++S->st.batches;
     S->batched_queries += nq;
   }
@@ -437,6 +459,8 @@ void free_state(ServeState *S) {
     if (sl.h_res) (void)hipHostFree(sl.h_res);
     if (sl.h_rel) (void)hipHostFree(sl.h_rel);
     if (sl.done) (void)hipEventDestroy(sl.done);
+    if (sl.g0) (void)hipEventDestroy(sl.g0);
+    if (sl.g1) (void)hipEventDestroy(sl.g1);
     if (sl.stream) (void)hipStreamDestroy(sl.stream);
   }
   if (S->rel_event) (void)hipEventDestroy(S->rel_event);
@@ -514,6 +538,7 @@ int32_t mapa_serve_start(mapa_ctx *c, const mapa_serve_opts *opts) {
       return bail(MAPA_ERR_ADMISSION, "max_batch exceeds the enumeration buffer");
     if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreate(&sl.g0) != hipSuccess || hipEventCreate(&sl.g1) != hipSuccess ||
         hipHostMalloc((void **)&sl.h_q, o.max_batch * sizeof(mapa_query), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void **)&sl.h_res, o.max_batch * sizeof(mapa_result), hipHostMallocDefault) != hipSuccess)
       return bail(MAPA_ERR_DEVICE, "stream, event or pinned buffers");
@@ -613,6 +638,13 @@ int32_t mapa_serve_stop(mapa_ctx *c, mapa_serve_stats *out) {
   st.mean_batch = st.batches ? (double)S->batched_queries / (double)st.batches : 0;
   st.mean_batch_us = st.batches ? S->batch_us_sum / (double)st.batches : 0;
   st.fused_batches = S->fused_batches;
+  st.wait_p50_us = percentile(S->waits, 0.50);
+  st.wait_p99_us = percentile(S->waits, 0.99);
+  st.turnaround_p50_us = percentile(S->turns, 0.50);
+  st.turnaround_p99_us = percentile(S->turns, 0.99);
+  st.mean_dispatch_us = st.batches ? S->dispatch_us_sum / (double)st.batches : 0;
+  st.mean_gpu_us = st.batches ? S->gpu_us_sum / (double)st.batches : 0;
+  st.mean_harvest_us = st.batches ? S->harvest_us_sum / (double)st.batches : 0;
   const int32_t err = S->error;
   const std::string msg = S->error_msg;
   c->serve = nullptr;

@@ -206,16 +206,11 @@ extern "C" int32_t mapa_query_batch_wide(mapa_ctx *c, const mapa_query *q, int32
     MAPA_HIPCHK(hipMemcpyAsync(const_cast<uint32_t *>(w.blk_q), blk_q.data(), blocks * sizeof(uint32_t),
                                hipMemcpyHostToDevice, s));
   ProfEvents ev{};
-  if (c->profile && blocks) {  // the search kernel's time counts as enumeration time
-    MAPA_HIPCHK(hipEventCreate(&ev.start));
-    MAPA_HIPCHK(hipEventCreate(&ev.stop));
-    MAPA_HIPCHK(hipEventRecord(ev.start, s));
-  }
+  if (c->profile && blocks)  // the search kernel's time counts as enumeration time
+    if (int32_t rc2 = prof_start(c, s, ev)) return rc2;
   MAPA_HIPCHK(launch_wide_search(w, (int32_t)blocks, s));
-  if (c->profile && blocks) {
-    MAPA_HIPCHK(hipEventRecord(ev.stop, s));
-    c->prof.push_back(ev);
-  }
+  if (c->profile && blocks)
+    if (int32_t rc2 = prof_stop(c, s, ev)) return rc2;
   MAPA_HIPCHK(launch_wide_finalize(w, s));
   MAPA_HIPCHK(hipMemcpyAsync(res, w.res, (size_t)nq * sizeof(mapa_result_wide), hipMemcpyDeviceToHost, s));
   MAPA_HIPCHK(hipEventRecord(c->last, s));

@@ -17,8 +17,6 @@
 
 namespace mapa {
 
-namespace {
-
 // sum of W[v][u] over u in X, from the B weight bit-planes of row v
 __device__ __forceinline__ int wsum_wide(const uint32_t *rows, int B, int v, uint32_t X) {
   int s = 0;
@@ -286,8 +284,6 @@ __global__ __launch_bounds__(256) void k_wide_finalize(WideArgs w) {
   }
   w.res[q] = r;
 }
-
-}  // namespace
 
 hipError_t launch_wide_search(const WideArgs &w, int32_t blocks, hipStream_t s) {
   if (blocks > 0) hipLaunchKernelGGL(k_wide_search, dim3(blocks), dim3(kWideThreads), 0, s, w);
