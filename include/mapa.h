@@ -245,6 +245,31 @@ int32_t mapa_get_busy(mapa_ctx *ctx, int32_t count, const int32_t *server_ids,
 int32_t mapa_query_batch(mapa_ctx *ctx, const mapa_query *q, int32_t nq, mapa_result *res,
                          uint32_t flags, void *hip_stream);
 
+/* ---- allocation-free batch ---------------------------------------------------
+ * For callers that cannot allocate device memory during a call: code being
+ * captured into a HIP graph, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same queries, results, semantics and kernels as
+ * mapa_query_batch with MAPA_DEVICE_PTRS; the batch's workspace (per-query
+ * plans and accumulators, counters, prefix work-list) is a fixed device
+ * array of MAPA_NOALLOC_SCRATCH_MIB MiB that each device the library runs on
+ * holds from context creation until the process ends, instead of memory the
+ * context allocates.  The call allocates and frees nothing.
+ *   q, res: device pointers (16-byte aligned), nq entries each; the call
+ *     returns once the work is queued on hip_stream (NULL = default stream).
+ *   nq > MAPA_NOALLOC_MAX_QUERIES -> MAPA_ERR_ADMISSION, nothing runs.
+ *   Malformed queries get status MAPA_RES_INVALID, as with device pointers.
+ *   A batch whose finest prefix split does not fit the array's work-list
+ *   runs with a coarser split; results are identical, only speed differs.
+ * Every call on one device shares that device's array: calls on one context
+ * are ordered (as every call on a context), but calls from different
+ * contexts on the same device that overlap in time race and give undefined
+ * results.  Self-check failures of these calls are not added to
+ * mapa_get_stats. */
+#define MAPA_NOALLOC_MAX_QUERIES 65536
+#define MAPA_NOALLOC_SCRATCH_MIB 32
+int32_t mapa_query_batch_noalloc(mapa_ctx *ctx, const mapa_query *q, int32_t nq,
+                                 mapa_result *res, void *hip_stream);
+
 /* Result of one wide query: as mapa_result, with room for 16 mapping
  * entries.  56 bytes. */
 typedef struct {

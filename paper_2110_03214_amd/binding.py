@@ -49,6 +49,7 @@ RESULT_WIDE_DTYPE = np.dtype([("count", np.int64), ("status", np.int32), ("key",
                               ("alloc_handle", np.int64)])
 assert RESULT_WIDE_DTYPE.itemsize == 56 and RESULT_WIDE_DTYPE.fields["alloc_handle"][1] == 48
 MAX_N_WIDE, MAX_K_WIDE = 32, 12
+NOALLOC_MAX_QUERIES = 65536
 
 
 class Tuning(ctypes.Structure):
@@ -106,6 +107,7 @@ SIGNATURES = {
     "mapa_get_busy": (_I32, [_P, _I32, _P, _P]),
     "mapa_query_batch": (_I32, [_P, _P, _I32, _P, _U32, _P]),
     "mapa_query_batch_wide": (_I32, [_P, _P, _I32, _P]),
+    "mapa_query_batch_noalloc": (_I32, [_P, _P, _I32, _P, _P]),
     "mapa_release": (_I32, [_P, _I32, _P, _I32, _U32, _P]),
     "mapa_get_tuning": (_I32, [_P, ctypes.POINTER(Tuning)]),
     "mapa_set_tuning": (_I32, [_P, ctypes.POINTER(Tuning)]),
@@ -259,6 +261,15 @@ class Context:
         check(lib().mapa_query_batch(self.h, _ptr(q), len(q), _ptr(res),
                                      PIPELINE if pipeline else 0, None), "mapa_query_batch")
         return res
+
+    def query_batch_noalloc(self, queries, results, stream=None):
+        """Device byte tensors (nq*16 and nq*48 bytes) -> asynchronous batch
+        whose workspace is the library's fixed device array (no allocation
+        inside the call)."""
+        nq = queries.numel() * queries.element_size() // QUERY_DTYPE.itemsize
+        check(lib().mapa_query_batch_noalloc(self.h, _ptr(queries), int(nq), _ptr(results),
+                                             _stream(stream)), "mapa_query_batch_noalloc")
+        return results
 
     def query_batch_wide(self, queries):
         """Host QUERY_DTYPE array -> RESULT_WIDE_DTYPE array (servers of up to

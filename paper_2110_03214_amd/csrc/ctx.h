@@ -176,4 +176,7 @@ void serve_teardown(mapa_ctx *c);  // stop and free a running serving loop
 int32_t prof_start(mapa_ctx *c, hipStream_t s, ProfEvents &ev);
 int32_t prof_stop(mapa_ctx *c, hipStream_t s, const ProfEvents &ev);
 
+// Resolve the allocation-free batch's scratch array on `device` (current).
+int32_t noalloc_setup(int device);
+
 }  // namespace mapa

@@ -580,6 +580,7 @@ int32_t mapa_ctx_create(int32_t device, size_t enum_buffer_bytes, mapa_ctx **out
     return rc;
   };
   if (hipSetDevice(device) != hipSuccess) return bail(fail(MAPA_ERR_DEVICE, "hipSetDevice failed"));
+  if (int32_t rc0 = noalloc_setup(device)) return bail(rc0);
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) != hipSuccess)
     return bail(fail(MAPA_ERR_DEVICE, "hipGetDeviceProperties failed"));
