@@ -9,15 +9,27 @@ allocation is released again, so each step starts from the same busy state.
 Queries, results and busy masks stay in HBM; nothing crosses PCIe inside the
 timed region.
 
-Default workload: the batched config (65,536 server states over three 8- and
-6-vertex topologies, 0-6 busy vertices, ring / all-to-all / tree patterns with
-k in 2..8).  ``--config 3`` runs the large 16-vertex enumeration and
-``--config 1`` the tiny one, ``--config 6`` the wide path (32-vertex servers,
-jobs of 9 and 10 accelerators).
+Headline workload (default): the large enumeration (256 16-vertex
+hypercube-plus-chord topologies, all free, ring and all-to-all patterns with
+k = 6, 7, 8: 1,536 queries, 2.98e11 embeddings per batch), the paper's
+overhead case of large jobs on 16-accelerator hardware graphs (Sec. 5.4).
+``--config 2`` makes the batched config the headline, ``--config 1`` the tiny
+one, ``--config 6`` the wide path (32-vertex servers, jobs of 9 and 10).
 
-Prints ONE JSON line (rank 0):  value = embeddings scored per second, plus
-queries/s, per-batch p50/p99 latency, the roofline of the enumeration kernel
-(integer ALU bound) and the CPU oracle timed on the host on a bounded sample.
+Beside the headline the default run also reports (each skippable):
+  * the batched config (65,536 server states) as a timed batch;
+  * the plain form: one query per call with host buffers, on both;
+  * the serving forms on the serving trace (1M Poisson requests over 4,096
+    servers) and the mixed-size bursty trace (1,024 cube-mesh + 1,024
+    16-vertex servers): the continuous-batching loop at 0.5 / 0.8 / 1.0 /
+    1.2 x its measured capacity, and the plain serving form (one request per
+    device batch, one batch in flight) at the same fractions of its own;
+  * the CPU oracle on the host (single thread and all cores).
+
+Prints ONE JSON line:  value = embeddings scored per second on the headline
+workload, plus queries/s, per-batch p50/p99 latency, the roofline of the
+enumeration kernel (integer ALU bound) under three operation counts, and the
+CPU oracle baseline.
 """
 from __future__ import annotations
 
@@ -26,6 +38,7 @@ import hashlib
 import json
 import math
 import os
+import platform
 import sys
 import time
 
@@ -38,15 +51,17 @@ METRIC = "pattern embeddings scored/sec + allocation queries/sec, p50/p99 latenc
 # MI355X vector-ALU ceiling for 32-bit lane operations: the published fp32
 # vector rate, 157.3 TFLOP/s, is 256 CUs x 2.4 GHz x 128 lanes x 2 flops per
 # FMA, so the vector ALUs retire at most 256 x 128 x 2.4e9 = 78.6e12 32-bit
-# lane-ops/s.  (A 4 SIMD x 16 lane model, 39.3e12, is exceeded in
-# measurement: the enumeration kernel itself sustains ~75 int32 lane-ops per
-# clock per CU.)
+# lane-ops/s.  This is an upper bound for integer work: mapa_measure_alu_peak
+# (independent chains of the leaf loop's integer instruction mix) sustains
+# about 46e12.
 CU, LANES_PER_CLK, CLK = 256, 128, 2.4e9
 ALU_PEAK = CU * LANES_PER_CLK * CLK  # 78.64e12 int32 lane-ops/s
+PEAK_NOTE = ("78.64 T = the fp32 vector FMA lane rate (157.3 TFLOP/s / 2 flops): an upper bound "
+             "for 32-bit integer lane ops; measured_peak is the integer probe's sustained rate")
 
-# Counter profiles (rocprofv3 FETCH_SIZE / WRITE_SIZE) of the enumeration
-# kernel, committed under profiles/; their HBM byte count is reported only
-# while the kernel sources still hash to the value the profile was taken on.
+# Counter profiles (rocprofv3) of the enumeration kernel, committed under
+# profiles/; their figures are reported only while the kernel sources still
+# hash to the value the profile was taken on.
 KERNEL_SOURCES = tuple("paper_2110_03214_amd/csrc/" + f for f in (
     "device.h", "enumerate.h", "enum_pair12_lds.hip", "enum_pair12_glb.hip", "enum_pair6.hip",
     "enum_plain.hip", "mapa_internal.h"))
@@ -63,47 +78,79 @@ WORKLOAD_TEXT = {
     6: ("wide: 16 32-vertex 5-cube+chord topologies (weights 1-3), 12 free accelerators each, "
         "ring/all-to-all/tree with k in 9..10 (96 queries, 1.53e10 embeddings; host buffers)"),
 }
+SERVING_TEXT = {
+    4: "serving: Poisson requests over 4,096 servers of the batched config's three topologies",
+    5: "mixed serving: bursty (two-state MMPP) requests over 1,024 cube-mesh and 1,024 16-vertex servers",
+}
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-# Integer ops charged per node of the search tree (every partial and every
-# complete embedding): with the weights of the node's candidates to the
-# vertices still free tabulated once per parent, placing one more vertex
-# needs one packed-weight read (the weight to the vertex just placed), one
-# multiply-add, one add of the tabulated term and one compare/select.  No
-# method that scores every embedding separately does less, so the fraction
-# of peak this gives is a lower bound on the kernel's ALU use.
-OPS_PER_NODE = 4
+# ---------------------------------------------------------------- op models
+
+def last_back_neighbours(kind: int, k: int) -> int:
+    """|Nb[k-1]|: pattern neighbours of the last position among the earlier
+    ones (ring: previous and first; all-to-all: all; tree: the parent)."""
+    if k <= 1:
+        return 0
+    if kind == 0:  # ring
+        return 1 if k == 2 else 2
+    if kind == 1:  # all-to-all
+        return k - 1
+    return 1  # binary tree
 
 
-def algorithmic_ops(wl) -> tuple[int, int]:
-    """(embeddings, algorithmic int ops) of one pass over the workload:
-    OPS_PER_NODE for every node at depth 1..k of each query's search tree,
-    F!/(F-p)! of them at depth p in ALL mode (the leaves are the embeddings)."""
+def weight_bits(W) -> int:
+    """B = bits of the largest weight (bit-planes a weighted popcount reads)."""
+    return max(1, int(np.max(W)).bit_length())
+
+
+def op_counts(wl) -> dict:
+    """Embeddings and three algorithmic integer-op counts of one pass:
+      ops_leaf8d : 8 + 3B + |Nb[k-1]| per embedding, plus that per leaf times
+                   1/(F-k+1) for the interior nodes (the per-leaf work of an
+                   enumerate-and-score method that scores each embedding on
+                   its own: candidate test, edge adds, B plane ANDs, popcounts
+                   and shift-adds, the preserved-weight lookup, the key and
+                   the select);
+      ops_factored : 3 per embedding + 4 per interior node at depths 1..k-1
+                   (the factored last two positions: a leaf is one weight-field
+                   extract, one multiply-add and one max over terms tabulated
+                   once per candidate of its parent);
+      ops_node4  : 4 per search-tree node at depths 1..k.
+    Counts are for ALL mode (every injective map), the headline mode."""
     q = wl.queries
     n_of = [W.shape[0] for W in wl.topologies]
-    emb = ops = 0
+    B_of = [weight_bits(W) for W in wl.topologies]
+    emb = o8d = ofac = onode = 0.0
     cache = {}
-    for s, k in zip(q["server"], q["k"]):
+    for s, kind, k in zip(q["server"], q["kind"], q["k"]):
         t = int(wl.server_topo[s])
         F = n_of[t] - bin(int(wl.busy[s])).count("1")
-        key = (F, int(k))
+        key = (F, int(k), int(kind), B_of[t])
         if key not in cache:
-            if k > F:
-                cache[key] = (0, 0)
+            k_ = int(k)
+            if k_ > F:
+                cache[key] = (0, 0, 0, 0)
             else:
-                nodes = sum(math.perm(F, p) for p in range(1, int(k) + 1))
-                cache[key] = (math.perm(F, int(k)), OPS_PER_NODE * nodes)
-        e, o = cache[key]
+                leaves = math.perm(F, k_)
+                per_leaf = 8 + 3 * B_of[t] + last_back_neighbours(int(kind), k_)
+                a = leaves * per_leaf * (1.0 + 1.0 / (F - k_ + 1))
+                interior = sum(math.perm(F, p) for p in range(1, k_))
+                cache[key] = (leaves, a, 3 * leaves + 4 * interior, 4 * (interior + leaves))
+        e, a, f, n = cache[key]
         emb += e
-        ops += o
-    return emb, ops
+        o8d += a
+        ofac += f
+        onode += n
+    return {"embeddings": int(emb), "ops_leaf8d": o8d, "ops_factored": ofac, "ops_node4": onode}
 
 
-def kernel_source_hash(cfg: int = 2) -> str:
+# ---------------------------------------------------------------- profiles
+
+def kernel_source_hash(cfg: int = 3) -> str:
     """sha256 of the sources of the kernel a workload's roofline is about."""
     h = hashlib.sha256()
     for rel in (WIDE_SOURCES if cfg == 6 else KERNEL_SOURCES):
@@ -112,10 +159,10 @@ def kernel_source_hash(cfg: int = 2) -> str:
     return h.hexdigest()
 
 
-def profiled_traffic(cfg: int):
-    """(HBM bytes per enumeration launch, profile path) from the committed
-    counter profile of this workload, or (None, reason) when there is none or
-    the kernel has changed since it was taken."""
+def profile_fields(cfg: int):
+    """Key: value header fields of the committed counter profile of a
+    workload, or (None, reason) when there is none or the kernel sources have
+    changed since it was taken."""
     name = PMC_PROFILE.get(cfg)
     if not name:
         return None, "no counter profile for this workload"
@@ -130,80 +177,208 @@ def profiled_traffic(cfg: int):
                 fields[key.strip()] = val.strip()
     if fields.get("kernel_source_sha256") != kernel_source_hash(cfg):
         return None, f"profiles/{name} was taken on other kernel sources"
+    return fields, f"profiles/{name}"
+
+
+def profiled_traffic(cfg: int):
+    """(HBM bytes per enumeration launch, source) from the committed counter
+    profile, or (None, reason)."""
+    fields, source = profile_fields(cfg)
+    if fields is None:
+        return None, source
     if "traffic_bytes_per_launch" not in fields:
-        return None, f"profiles/{name} holds no memory counters"
-    return int(fields["traffic_bytes_per_launch"]), f"profiles/{name}"
+        return None, f"{source} holds no memory counters"
+    return int(fields["traffic_bytes_per_launch"]), source
 
 
-def cpu_baseline(wl, seconds: float = 8.0):
-    """The oracle (test infrastructure) timed on the host on a bounded sample."""
+def profiled_valu_lane_ops(cfg: int):
+    """(SQ_INSTS_VALU x 64 per launch, source) from the committed profile."""
+    fields, source = profile_fields(cfg)
+    if fields is None:
+        return None, source
+    if "valu_lane_ops_per_launch" not in fields:
+        return None, f"{source} holds no instruction counters"
+    return float(fields["valu_lane_ops_per_launch"]), source
+
+
+# ---------------------------------------------------------------- CPU oracle
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def host_threads() -> int:
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    # a GPU box's share of host cores is 16, whatever the machine reports
+    return max(1, min(16, n))
+
+
+def large_sample(ntopo: int = 8):
+    """The large config's seeded 8-topology sample: 8 of its 256 topologies,
+    each with its 6 queries (ring and all-to-all, k = 6, 7, 8), 48 queries."""
+    from paper_2110_03214_amd import synth
+    wl = synth.config3()
+    rng = np.random.default_rng(np.random.SeedSequence([0x2110_0321, 3, 48]))
+    topo = np.sort(rng.choice(len(wl.topologies), size=ntopo, replace=False))
+    sel = np.nonzero(np.isin(wl.queries["server"], topo))[0]
+    return wl.subset(sel), [int(t) for t in topo]
+
+
+def cpu_baseline(wl, cfg: int, all_core_s: float = 30.0):
+    """The oracle (test infrastructure, plain C at -O2, one query per thread,
+    static split by query) timed on the host: all cores on the workload's
+    sample, one thread on a part of it."""
     import oracle
     oracle.build()
-    try:
-        cores = len(os.sched_getaffinity(0))
-    except AttributeError:
-        cores = os.cpu_count() or 1
-    cores = max(1, min(16, cores))
-    # bounded sample: whole queries, at most ~5e8 embeddings per pass
-    sel, total = [], 0
-    emb_q = []
-    q = wl.queries
-    for i in range(wl.nq):
-        t = int(wl.server_topo[q["server"][i]])
-        F = wl.topologies[t].shape[0] - bin(int(wl.busy[q["server"][i]])).count("1")
-        e = math.perm(F, int(q["k"][i])) if q["k"][i] <= F else 0
-        emb_q.append(e)
-    order = np.argsort(np.arange(wl.nq) * 2654435761 % (1 << 32), kind="stable")
-    for i in order:
-        if total + emb_q[i] > 5e8 and sel:
-            continue
-        sel.append(int(i))
-        total += emb_q[i]
-    sub = wl.subset(np.sort(np.array(sel)))
-    done = passes = 0
+    cores = host_threads()
+
+    def timed(sub, nthreads):
+        t0 = time.perf_counter()
+        res = oracle.run_workload(sub, nthreads=nthreads)
+        return int(res["count"].sum()), time.perf_counter() - t0
+
+    if cfg == 3:
+        sample, topo = large_sample()
+        n_all, dt_all = timed(sample, cores)
+        k6 = np.nonzero(sample.queries["k"] == 6)[0]
+        one = sample.subset(k6)
+        n_one, dt_one = timed(one, 1)
+        desc = (f"all cores: the large config's seeded 8-topology sample (topologies {topo}, "
+                f"48 queries, {n_all:.3g} embeddings) in {dt_all:.1f} s; one thread: its 16 "
+                f"k=6 queries ({n_one:.3g} embeddings) in {dt_one:.1f} s")
+    else:
+        # whole queries in a fixed pseudo-random order, up to ~5e8 embeddings
+        q = wl.queries
+        emb_q = []
+        for i in range(wl.nq):
+            t = int(wl.server_topo[q["server"][i]])
+            F = wl.topologies[t].shape[0] - bin(int(wl.busy[q["server"][i]])).count("1")
+            emb_q.append(math.perm(F, int(q["k"][i])) if q["k"][i] <= F else 0)
+        order = np.argsort(np.arange(wl.nq) * 2654435761 % (1 << 32), kind="stable")
+        sel, total = [], 0
+        for i in order:
+            if total + emb_q[i] > 5e8 and sel:
+                continue
+            sel.append(int(i))
+            total += emb_q[i]
+        sample = wl.subset(np.sort(np.array(sel)))
+        n_all, dt_all = timed(sample, cores)
+        one = wl.subset(np.sort(np.array(sel[: max(1, len(sel) // 16)])))
+        n_one, dt_one = timed(one, 1)
+        desc = (f"all cores: {len(sel)} of {wl.nq} queries ({n_all:.3g} embeddings) in "
+                f"{dt_all:.1f} s; one thread: {one.nq} of them ({n_one:.3g} embeddings) in "
+                f"{dt_one:.1f} s")
+    return {"value": n_all / dt_all, "unit": "embeddings/s", "cores": cores, "kind": "oracle",
+            "single_thread_value": n_one / dt_one, "cpu_model": cpu_model(),
+            "host_cpus": os.cpu_count(), "sample": desc + "; static split by query"}
+
+
+# ---------------------------------------------------------------- GPU forms
+
+def timed_batch(B, wl, steps, warmup, metric="weighted", wide=False, profile=True):
+    """The batched form: `steps` timed steps (query batch with commits, then
+    release of every handle) after `warmup` untimed ones, inputs resident in
+    HBM.  Kernel time from HIP events on the launch stream over the timed
+    region.  Validates after the timed region."""
+    import torch
+    ops = op_counts(wl)
+    emb = ops["embeddings"]
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    ctx = B.Context(0)
+    qh, ids = B.load_workload(ctx, wl)
+    qh["commit"] = 1
+    qh["metric"] = B.METRIC_EFFBW if metric == "effbw" else B.METRIC_WEIGHTED
+    dq = torch.from_numpy(qh.view(np.uint8).copy()).to(dev)
+    dr = torch.zeros(wl.nq * B.RESULT_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+    handles = dr.view(torch.int64)[5:]  # alloc_handle: byte 40 of each 48-byte result
+    wide_res = [None]
+
+    def step():
+        if wide:  # host buffers in and out (16 B per query, 56 B per result)
+            wide_res[0] = ctx.query_batch_wide(qh)
+            ctx.release(wide_res[0]["alloc_handle"])
+            return
+        ctx.query_batch(dq, dr, stream=stream)
+        ctx.release(handles, stride=48, count=wl.nq, stream=stream)
+
+    for i in range(warmup):
+        step()
+        if i == 0:
+            torch.cuda.synchronize()
+    torch.cuda.synchronize()
+    ctx.profile(profile)
+    ctx.reset_stats()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    while True:
-        res = oracle.run_workload(sub, nthreads=cores)
-        done += int(res["count"].sum())
-        passes += 1
-        if time.perf_counter() - t0 >= seconds:
-            break
-    dt = time.perf_counter() - t0
-    return {"value": done / dt, "unit": "embeddings/s", "cores": cores, "kind": "oracle",
-            "sample": f"{len(sel)} of {wl.nq} queries ({total:.3g} embeddings) x {passes} "
-                      f"passes in {dt:.1f} s, static split by query over {cores} threads"}
+    for s in range(steps):
+        ev[s][0].record(stream)
+        step()
+        ev[s][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lat = np.array([a.elapsed_time(b) for a, b in ev])
+    st = ctx.stats()
+    ctx.profile(False)
+    # every step scored every embedding and handed every allocation back
+    res = wide_res[0] if wide else dr.cpu().numpy().view(B.RESULT_DTYPE)
+    assert int(res["count"].sum()) == emb, (int(res["count"].sum()), emb)
+    assert np.array_equal(ctx.get_busy(ids), wl.busy), "release did not restore the entry state"
+    assert st["self_check_failures"] == 0
+    out = {"wall_s": wall, "steps": steps, "embeddings": emb, "ops": ops, "queries": wl.nq,
+           "lat_ms": lat, "stats": st, "qh": qh}
+    out["kernel_ms"] = (st["enum_ms"] / st["enum_launches"]) if st["enum_launches"] else None
+    out["probe"] = ctx.measure_alu_peak() if profile else None
+    return ctx, out
 
 
-def run_plain(ctx, B, qh, limit: int = 4096):
+def run_plain(ctx, qh, limit: int):
     """Plain form: one query per call, host pointers, synchronous (launch +
     copy back + sync per query).  Returns queries/s and per-query latency."""
     n = min(limit, len(qh))
     q = qh[:n].copy()
     q["commit"] = 0
     lat = np.empty(n)
-    for i in range(min(64, n)):  # warm
+    for i in range(min(16, n)):  # warm
         ctx.query_batch(q[i:i + 1])
+    emb = 0
     t0 = time.perf_counter()
     for i in range(n):
         t = time.perf_counter()
-        ctx.query_batch(q[i:i + 1])
+        r = ctx.query_batch(q[i:i + 1])
         lat[i] = time.perf_counter() - t
+        emb += int(r["count"][0])
     wall = time.perf_counter() - t0
-    return {"queries": n, "queries_per_s": n / wall, "p50_ms": float(np.percentile(lat, 50) * 1e3),
+    return {"queries": n, "queries_per_s": n / wall, "embeddings_per_s": emb / wall,
+            "p50_ms": float(np.percentile(lat, 50) * 1e3),
             "p99_ms": float(np.percentile(lat, 99) * 1e3)}
 
 
-def run_serving(B, cfg: int, nreq: int, loads=(0.5, 0.8, 1.0, 1.2)):
-    """Serving form: a request trace through the continuous-batching loop.
-    First replays it as fast as possible to measure capacity, then at offered
-    loads that are fractions of that capacity (time unit scaled)."""
+def run_serving(B, cfg: int, nreq: int, plain: bool = False, loads=(0.5, 0.8, 1.0, 1.2)):
+    """Serving form on a request trace.  Continuous batching: up to 4,096
+    requests of different servers per device batch, two batches in flight.
+    Plain: one request per device batch, one batch in flight.  First replays
+    the trace with every request due at once to measure the form's capacity,
+    then at offered loads that are fractions of it (trace time scaled)."""
     from paper_2110_03214_amd import synth
     tr = synth.config4(nreq) if cfg == 4 else synth.config5(nreq)
     rate_per_unit = nreq / tr.t_arrival[-1]
-    out = {"workload": ("serving: Poisson requests over 4,096 servers of the batched config's "
-                        "three topologies" if cfg == 4 else
-                        "mixed serving: bursty requests over 1,024 cube-mesh and 1,024 16-vertex "
-                        "servers"), "requests": nreq, "runs": []}
+    out = {"workload": SERVING_TEXT[cfg], "requests": nreq,
+           "form": ("plain: one request per device batch, one batch in flight" if plain else
+                    "continuous batching: up to 4,096 requests per device batch, two in flight"),
+           "runs": []}
     ctx = B.Context(0)
     ids = ctx.load_servers(tr.topologies, tr.server_topo)
     r = np.zeros(tr.n, dtype=B.REQUEST_DTYPE)
@@ -212,12 +387,13 @@ def run_serving(B, cfg: int, nreq: int, loads=(0.5, 0.8, 1.0, 1.2)):
     r["kind"], r["k"], r["a"], r["b"] = tr.kind, tr.k, 1, 1
 
     def one(unit_us):
-        ctx.serve_start(max_batch=4096, inflight=2, time_unit_us=unit_us)
+        ctx.serve_start(max_batch=1 if plain else 4096, inflight=1 if plain else 2,
+                        time_unit_us=unit_us)
         ctx.serve_submit(r)
         got = 0
         while got < tr.n:
             got += len(ctx.serve_poll())
-            time.sleep(0.001)
+            time.sleep(0.002)
         return ctx.serve_stop()
 
     cap = one(0.0)
@@ -226,38 +402,100 @@ def run_serving(B, cfg: int, nreq: int, loads=(0.5, 0.8, 1.0, 1.2)):
     for f in loads:
         unit = rate_per_unit / (f * capacity) * 1e6  # us per trace time unit
         st = one(unit)
-        out["runs"].append({"offered_fraction": f, "offered_requests_per_s": f * capacity,
-                            "requests_per_s": st["requests_per_s"], "p50_us": st["p50_us"],
-                            "p99_us": st["p99_us"], "p999_us": st["p999_us"],
-                            "mean_batch": st["mean_batch"], "batches": st["batches"],
-                            "mean_batch_us": st["mean_batch_us"], "fused_batches": st["fused_batches"],
-                            "granted": st["granted"], "nofit": st["nofit"],
-                            "embeddings_per_s": st["embeddings_per_s"]})
+        out["runs"].append({
+            "offered_fraction": f, "offered_requests_per_s": f * capacity,
+            "requests_per_s": st["requests_per_s"], "p50_us": st["p50_us"], "p99_us": st["p99_us"],
+            "p999_us": st["p999_us"], "wait_p50_us": st["wait_p50_us"],
+            "wait_p99_us": st["wait_p99_us"], "turnaround_p50_us": st["turnaround_p50_us"],
+            "turnaround_p99_us": st["turnaround_p99_us"], "mean_batch": st["mean_batch"],
+            "batches": st["batches"], "mean_batch_us": st["mean_batch_us"],
+            "mean_dispatch_us": st["mean_dispatch_us"], "mean_gpu_us": st["mean_gpu_us"],
+            "mean_harvest_us": st["mean_harvest_us"], "fused_batches": st["fused_batches"],
+            "granted": st["granted"], "nofit": st["nofit"], "host_nofit": st["host_nofit"],
+            "admission_waits": st["admission_waits"],
+            "embeddings_per_s": st["embeddings_per_s"]})
+        log(f"[bench]   {'plain' if plain else 'continuous'} trace {cfg} at {f}x: "
+            f"{st['requests_per_s']:.4g} req/s, p50 {st['p50_us']:.0f} us, p99 {st['p99_us']:.0f} us, "
+            f"batch {st['mean_batch']:.0f} x {st['mean_batch_us']:.0f} us")
     ctx.close()
     return out
+
+
+def roofline(cfg, tb):
+    """Roofline of the enumeration kernel from the timed region's HIP-event
+    kernel time: the per-leaf operation count (``achieved``/``frac``), the
+    factored count and the issued VALU lane-ops of the committed counter
+    profile."""
+    avg_s = tb["kernel_ms"] / 1e3
+    ops = tb["ops"]
+    probe = tb["probe"]
+    traffic, tsrc = profiled_traffic(cfg)
+    valu, vsrc = profiled_valu_lane_ops(cfg)
+    r = {"bound": "alu", "achieved": ops["ops_leaf8d"] / avg_s / 1e12, "peak": ALU_PEAK / 1e12,
+         "unit": "Tops/s", "frac": ops["ops_leaf8d"] / avg_s / ALU_PEAK, "traffic": traffic,
+         "traffic_unit": "HBM bytes per launch", "traffic_source": tsrc,
+         "kernel": "k_wide_search" if cfg == 6 else "k_enumerate", "kernel_ms": tb["kernel_ms"],
+         "op_model": ("per embedding 8 + 3B + |Nb[k-1]| int ops (B = weight bits), times "
+                      "1 + 1/(F-k+1) for the interior nodes"),
+         "ops_per_launch": ops["ops_leaf8d"], "embeddings_per_launch": ops["embeddings"],
+         "peak_note": PEAK_NOTE, "measured_peak": probe / 1e12 if probe else None,
+         "frac_of_measured_peak": ops["ops_leaf8d"] / avg_s / probe if probe else None,
+         "items_per_launch": tb["stats"]["last_items"]}
+    r["factored_model"] = {
+        "model": ("3 int ops per embedding (weight-field extract, multiply-add, max) + 4 per "
+                  "interior node at depths 1..k-1"),
+        "ops_per_launch": ops["ops_factored"], "achieved": ops["ops_factored"] / avg_s / 1e12,
+        "frac": ops["ops_factored"] / avg_s / ALU_PEAK,
+        "frac_of_measured_peak": ops["ops_factored"] / avg_s / probe if probe else None}
+    r["valu_counters"] = {"source": vsrc}
+    if valu:
+        r["valu_counters"].update({
+            "lane_ops_per_launch": valu, "lane_ops_per_embedding": valu / max(1, ops["embeddings"]),
+            "achieved": valu / avg_s / 1e12, "frac": valu / avg_s / ALU_PEAK,
+            "frac_of_measured_peak": valu / avg_s / probe if probe else None})
+    return r
+
+
+def batched_summary(tb):
+    lat = tb["lat_ms"]
+    return {"embeddings_per_s": tb["embeddings"] * tb["steps"] / tb["wall_s"],
+            "queries_per_s": tb["queries"] * tb["steps"] / tb["wall_s"],
+            "ms_per_step": tb["wall_s"] * 1e3 / tb["steps"], "steps": tb["steps"],
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "kernel_ms": tb["kernel_ms"]}
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=0, help="timed steps (default: per config)")
+    ap.add_argument("--steps", type=int, default=20, help="timed steps of the headline batch")
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", type=int, default=2, choices=(1, 2, 3, 6))
+    ap.add_argument("--config", type=int, default=3, choices=(1, 2, 3, 6),
+                    help="headline workload (3: large enumeration)")
     ap.add_argument("--metric", default="weighted", choices=("weighted", "effbw"),
                     help="key of every query: a*AggBW + b*PreservedBW, or the predicted effective "
                          "bandwidth of Eq. 2 (bandwidth-sensitive jobs; needs weights 0..2)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="no HIP-event timing of the kernel")
+    ap.add_argument("--batched", type=int, default=200,
+                    help="timed steps of the batched config beside the headline (0: skip)")
     ap.add_argument("--plain", type=int, default=4096,
-                    help="queries timed in the plain one-query-per-launch form (0: skip)")
-    ap.add_argument("--serving-trace", type=int, default=4, choices=(4, 5),
-                    help="serving trace: 4 = Poisson requests over the batched config's topologies, "
-                         "5 = bursty requests over cube-mesh and 16-vertex servers")
-    ap.add_argument("--serving", type=int, default=100000,
-                    help="requests of the serving trace timed through the serving loop (0: skip)")
+                    help="queries timed in the plain one-query-per-call form (0: skip; the "
+                         "large config times at most 16)")
+    ap.add_argument("--serving", type=int, default=1_000_000,
+                    help="requests of the serving trace through the continuous-batching loop "
+                         "(0: skip)")
+    ap.add_argument("--serving-plain", type=int, default=100_000,
+                    help="requests of the serving trace through the plain serving form (0: skip)")
+    ap.add_argument("--mixed", type=int, default=20_000,
+                    help="requests of the mixed-size trace through the continuous loop (0: skip)")
+    ap.add_argument("--mixed-plain", type=int, default=5_000,
+                    help="requests of the mixed-size trace through the plain serving form (0: skip)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device-to-device copy of this many MiB first, to scale "
                          "hardware memory counters (FETCH_SIZE / WRITE_SIZE) against known bytes")
+    ap.add_argument("--only-headline", action="store_true",
+                    help="the headline batch alone (for profiling runs)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -272,81 +510,39 @@ def main():
     if not torch.cuda.is_available():
         log("no GPU visible")
         sys.exit(1)
-    steps = args.steps or {1: 200, 2: 200, 3: 3, 6: 3}[args.config]
-    wl = {1: synth.config1, 2: synth.config2, 3: synth.config3, 6: synth.config6}[args.config]()
-    wide = args.config == 6
-    emb, ops = algorithmic_ops(wl)
-    log(f"[bench] config {args.config}: {wl.nq} queries, {emb:.4g} embeddings/step, "
-        f"{ops:.4g} algorithmic ops/step")
-
-    dev = torch.device("cuda:0")
-    stream = torch.cuda.current_stream()
+    if args.only_headline:
+        args.batched = args.plain = args.serving = args.serving_plain = 0
+        args.mixed = args.mixed_plain = 0
+        args.no_cpu_baseline = True
     if args.copy_calibration_mib:
-        src = torch.empty(args.copy_calibration_mib << 20, dtype=torch.uint8, device=dev)
+        src = torch.empty(args.copy_calibration_mib << 20, dtype=torch.uint8, device="cuda:0")
         dst = torch.empty_like(src)
         src.fill_(1)
         torch.cuda.synchronize()
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    ctx = B.Context(0)
-    qh, ids = B.load_workload(ctx, wl)
-    qh["commit"] = 1
-    qh["metric"] = B.METRIC_EFFBW if args.metric == "effbw" else B.METRIC_WEIGHTED
-    dq = torch.from_numpy(qh.view(np.uint8).copy()).to(dev)
-    dr = torch.zeros(wl.nq * B.RESULT_DTYPE.itemsize, dtype=torch.uint8, device=dev)
-    handles = dr.view(torch.int64)[5:]  # alloc_handle: byte 40 of each 48-byte result
 
-    wide_res = [None]
-
-    def step():
-        if wide:  # host buffers in and out (16 B per query, 56 B per result)
-            wide_res[0] = ctx.query_batch_wide(qh)
-            ctx.release(wide_res[0]["alloc_handle"])
-            return
-        ctx.query_batch(dq, dr, stream=stream)
-        ctx.release(handles, stride=48, count=wl.nq, stream=stream)
-
-    for i in range(args.warmup):
-        step()
-        if i == 0:
-            torch.cuda.synchronize()
-            log("[bench] first step done")
-    torch.cuda.synchronize()
-
-    if not args.no_profile:
-        ctx.profile(True)
-    ctx.reset_stats()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for s in range(steps):
-        ev[s][0].record(stream)
-        step()
-        ev[s][1].record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    lat = np.array([a.elapsed_time(b) for a, b in ev])
-    st = ctx.stats()
-    # every step scored every embedding and handed every allocation back
-    res = wide_res[0] if wide else dr.cpu().numpy().view(B.RESULT_DTYPE)
-    assert int(res["count"].sum()) == emb, (int(res["count"].sum()), emb)
-    assert np.array_equal(ctx.get_busy(ids), wl.busy), "release did not restore the entry state"
-    assert st["self_check_failures"] == 0
-    ctx.profile(False)
-    log(f"[bench] {steps} steps in {wall:.3f} s; enumerate {st['enum_ms'] / max(1, st['enum_launches']):.3f} ms avg")
-
-    ms_per_step = wall * 1e3 / steps
-    value = emb * steps / wall
+    makers = {1: synth.config1, 2: synth.config2, 3: synth.config3, 6: synth.config6}
+    wl = makers[args.config]()
+    if args.metric == "effbw":
+        wl.queries["metric"][:] = 1
+    ops = op_counts(wl)
+    log(f"[bench] headline config {args.config}: {wl.nq} queries, {ops['embeddings']:.4g} "
+        f"embeddings/step")
+    ctx, tb = timed_batch(B, wl, args.steps, args.warmup, args.metric, wide=args.config == 6,
+                          profile=not args.no_profile)
+    log(f"[bench] {args.steps} steps in {tb['wall_s']:.3f} s; kernel "
+        f"{tb['kernel_ms'] if tb['kernel_ms'] else float('nan'):.3f} ms avg")
+    lat = tb["lat_ms"]
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": tb["embeddings"] * args.steps / tb["wall_s"],
         "unit": "embeddings/s",
         "n_gpus": 1,
-        "steps": steps,
+        "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": tb["wall_s"] * 1e3 / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -355,37 +551,55 @@ def main():
         "config": {"workload": WORKLOAD_TEXT[args.config], "config_id": args.config,
                    "key": ("a*AggBW + b*PreservedBW, (a, b) = (1, 1)" if args.metric == "weighted"
                            else "predicted effective bandwidth (Eq. 2)"),
-                   "queries": wl.nq, "embeddings_per_step": emb,
+                   "queries": wl.nq, "embeddings_per_step": tb["embeddings"],
                    "topologies": len(wl.topologies), "parallelism": "single GPU"},
-        "queries_per_s": wl.nq * steps / wall,
+        "queries_per_s": wl.nq * args.steps / tb["wall_s"],
         "p50_ms": float(np.percentile(lat, 50)),
         "p99_ms": float(np.percentile(lat, 99)),
         "latency_scope": "per batch (every query of a batch completes together)",
     }
-    if not args.no_profile and st["enum_launches"]:
-        avg_s = st["enum_ms"] / st["enum_launches"] / 1e3
-        achieved = ops / avg_s
-        probe = ctx.measure_alu_peak()
-        traffic, source = profiled_traffic(args.config)
-        out["roofline"] = {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_PEAK / 1e12,
-                           "unit": "Tops/s", "frac": achieved / ALU_PEAK, "traffic": traffic,
-                           "traffic_unit": "HBM bytes per launch", "traffic_source": source,
-                           "kernel": "k_wide_search" if wide else "k_enumerate",
-                           "kernel_ms": avg_s * 1e3,
-                           "ops_per_launch": ops, "items_per_launch": st["last_items"],
-                           "measured_peak": probe / 1e12, "frac_of_measured_peak": achieved / probe}
+    if tb["kernel_ms"]:
+        out["roofline"] = roofline(args.config, tb)
+    plain = {}
     if args.plain:
-        log("[bench] plain form: one query per launch")
-        out["plain_one_query_per_launch"] = run_plain(ctx, B, qh, args.plain)
+        log("[bench] plain form: one query per call")
+        plain[f"config_{args.config}"] = run_plain(ctx, tb["qh"], 16 if args.config == 3 else args.plain)
     ctx.close()
-    if args.serving and args.config == 2:
-        log(f"[bench] serving form, trace {args.serving_trace}")
-        out["serving"] = run_serving(B, args.serving_trace, args.serving)
+    if args.batched and args.config != 2:
+        log("[bench] batched config")
+        c2 = synth.config2()
+        ctx2, tb2 = timed_batch(B, c2, args.batched, args.warmup, profile=not args.no_profile)
+        out["batched_config_2"] = batched_summary(tb2)
+        out["batched_config_2"]["workload"] = WORKLOAD_TEXT[2]
+        if tb2["kernel_ms"]:
+            rl = roofline(2, tb2)
+            out["batched_config_2"]["roofline"] = {
+                k: rl[k] for k in ("achieved", "frac", "kernel_ms", "measured_peak",
+                                   "frac_of_measured_peak", "traffic")}
+            out["batched_config_2"]["roofline"]["factored_frac"] = rl["factored_model"]["frac"]
+        if args.plain:
+            plain["config_2"] = run_plain(ctx2, tb2["qh"], args.plain)
+        ctx2.close()
+    if plain:
+        out["plain_one_query_per_call"] = plain
+    serving = {}
+    if args.serving:
+        log(f"[bench] serving trace, continuous batching, {args.serving} requests")
+        serving["trace_4_continuous"] = run_serving(B, 4, args.serving)
+    if args.serving_plain:
+        log(f"[bench] serving trace, plain form, {args.serving_plain} requests")
+        serving["trace_4_plain"] = run_serving(B, 4, args.serving_plain, plain=True)
+    if args.mixed:
+        log(f"[bench] mixed-size trace, continuous batching, {args.mixed} requests")
+        serving["trace_5_continuous"] = run_serving(B, 5, args.mixed)
+    if args.mixed_plain:
+        log(f"[bench] mixed-size trace, plain form, {args.mixed_plain} requests")
+        serving["trace_5_plain"] = run_serving(B, 5, args.mixed_plain, plain=True)
+    if serving:
+        out["serving"] = serving
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle")
-        if args.metric == "effbw":
-            wl.queries["metric"][:] = 1
-        out["cpu_baseline"] = cpu_baseline(wl)
+        out["cpu_baseline"] = cpu_baseline(wl, args.config)
     print(json.dumps(out), flush=True)
 
 
