@@ -312,6 +312,78 @@ int32_t mapa_query_batch_wide(mapa_ctx *ctx, const mapa_query *q, int32_t nq,
 int32_t mapa_release(mapa_ctx *ctx, int32_t count, const int64_t *handles, int32_t stride_bytes,
                      uint32_t flags, void *hip_stream);
 
+/* ---- job-trace simulation (Sec. 5.2) ------------------------------------------
+ * The paper's simulation framework, run on the library's allocation path.  A
+ * job file lists jobs with their arrival cycle, execution time, pattern and
+ * bandwidth sensitivity; a dispatcher puts arriving jobs into a first-in
+ * first-out queue; whenever the head of the queue fits in the free
+ * accelerators, the simulation's allocation policy places it and marks its
+ * accelerators busy; once its execution time has elapsed the Job Finished
+ * Signal frees them again.  The engine is cycle based.  Within one cycle:
+ * finished jobs free their accelerators, then arrivals join the queue, then
+ * the head is placed again and again while it fits (a blocked head blocks
+ * the queue).  Every match is an injective map into the free accelerators
+ * (MAPA_ALL_INJECTIVE); ties go to the lexicographically smallest mapping.
+ * The log records, per job, its start and finish cycles, the accelerators it
+ * got and, scored at its start cycle, AggBW (Eq. 1), PreservedBW (Eq. 3)
+ * and its predicted effective bandwidth (Eq. 2). */
+#define MAPA_POLICY_PRESERVE 0 /* Alg. 1: bandwidth-sensitive jobs take the match of
+                                  largest predicted effective bandwidth (Eq. 2), the
+                                  others the match of largest PreservedBW (Eq. 3)   */
+#define MAPA_POLICY_GREEDY 1   /* the match of largest AggBW (Eq. 1)                   */
+#define MAPA_POLICY_BASELINE 2 /* the lowest free accelerator ids, pattern vertex i on
+                                  the i-th lowest (the comparison policy of Sec. 5.1) */
+
+typedef struct {          /* 16 bytes */
+  int32_t id;             /* caller's job id, echoed in the log                       */
+  int32_t arrival;        /* cycle at which the dispatcher queues the job, >= 0,
+                             non-decreasing within one simulation                     */
+  int32_t duration;       /* execution cycles, >= 1                                   */
+  uint8_t kind;           /* pattern, as mapa_query.kind                              */
+  uint8_t k;              /* accelerators requested, 1..8                             */
+  uint8_t sensitive;      /* 1: bandwidth-sensitive                                   */
+  uint8_t reserved;       /* must be 0                                                */
+} mapa_job;
+
+typedef struct {          /* 48 bytes */
+  int32_t id;
+  int32_t status;         /* MAPA_RES_OK; MAPA_RES_NOFIT: the job needs more accelerators
+                             than the server ever has free, it is logged when it arrives
+                             and leaves the queue                                      */
+  int32_t start, finish;  /* cycles (finish = start + duration); -1 if not placed     */
+  uint32_t vertex_mask;   /* accelerators the job ran on                              */
+  uint8_t mapping[8];     /* mapping[i] = accelerator of pattern vertex i; 0xFF beyond k */
+  int32_t agg, pres;      /* AggBW and PreservedBW of the placement at its start      */
+  int32_t effbw_milli;    /* round(1000 * predicted effective bandwidth)              */
+  int32_t links;          /* x | y << 8 | z << 16: the placement's pattern edges on double
+                             NVLinks, single NVLinks and PCIe                         */
+  int32_t reserved;
+} mapa_job_log;
+
+typedef struct {
+  int64_t cycles;         /* last cycle simulated                                     */
+  int64_t event_cycles;   /* cycles with an arrival or a finish                       */
+  int64_t rounds;         /* placement rounds (one scoring launch each)               */
+  int64_t device_batches; /* allocation-query batches                                 */
+  int64_t jobs_placed;
+} mapa_sim_stats;
+
+/* Run nsim independent simulations together.  Simulation i runs the jobs
+ * jobs[job_offsets[i] .. job_offsets[i+1]) on server servers[i] under policy
+ * policies[i] and writes their logs at the same indices of logs.
+ *   servers: distinct servers of at most 16 accelerators whose topologies have
+ *     link weights 0, 1, 2 only (PCIe, single, double NVLink; Eq. 2), else
+ *     MAPA_ERR_UNSUPPORTED.  A server's accelerators that are busy when the
+ *     call starts stay reserved throughout; every other one is free at cycle 0
+ *     and free again when the call returns.
+ *   All arrays are host pointers; job_offsets has nsim + 1 entries, starting
+ *   at 0.  stats (may be NULL) receives counters of the run.  The call is
+ *   synchronous and validates everything before it starts (bad field ->
+ *   MAPA_ERR_INVALID_ARG, nothing runs). */
+int32_t mapa_simulate(mapa_ctx *ctx, int32_t nsim, const int32_t *servers, const int32_t *policies,
+                      const int32_t *job_offsets, const mapa_job *jobs, mapa_job_log *logs,
+                      mapa_sim_stats *stats);
+
 /* ---- tuning and measurement ---------------------------------------------- */
 
 typedef struct {

@@ -95,6 +95,22 @@ COMPLETION_DTYPE = np.dtype([("id", np.int64), ("count", np.int64), ("alloc_hand
 assert REQUEST_DTYPE.itemsize == 40 and COMPLETION_DTYPE.itemsize == 80
 
 
+POLICY_PRESERVE, POLICY_GREEDY, POLICY_BASELINE = 0, 1, 2
+JOB_DTYPE = np.dtype([("id", np.int32), ("arrival", np.int32), ("duration", np.int32),
+                      ("kind", np.uint8), ("k", np.uint8), ("sensitive", np.uint8),
+                      ("reserved", np.uint8)])
+JOB_LOG_DTYPE = np.dtype([("id", np.int32), ("status", np.int32), ("start", np.int32),
+                          ("finish", np.int32), ("vertex_mask", np.uint32), ("mapping", np.uint8, 8),
+                          ("agg", np.int32), ("pres", np.int32), ("effbw_milli", np.int32),
+                          ("links", np.int32), ("reserved", np.int32)])
+assert JOB_DTYPE.itemsize == 16 and JOB_LOG_DTYPE.itemsize == 48
+
+
+class SimStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in (
+        "cycles", "event_cycles", "rounds", "device_batches", "jobs_placed")]
+
+
 # every symbol include/mapa.h declares, with its ctypes signature
 _P, _I32, _U32, _SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_size_t
 SIGNATURES = {
@@ -109,6 +125,7 @@ SIGNATURES = {
     "mapa_query_batch_wide": (_I32, [_P, _P, _I32, _P]),
     "mapa_query_batch_noalloc": (_I32, [_P, _P, _I32, _P, _P]),
     "mapa_release": (_I32, [_P, _I32, _P, _I32, _U32, _P]),
+    "mapa_simulate": (_I32, [_P, _I32, _P, _P, _P, _P, _P, ctypes.POINTER(SimStats)]),
     "mapa_get_tuning": (_I32, [_P, ctypes.POINTER(Tuning)]),
     "mapa_set_tuning": (_I32, [_P, ctypes.POINTER(Tuning)]),
     "mapa_profile": (_I32, [_P, _I32]),
@@ -288,6 +305,24 @@ class Context:
         h = np.ascontiguousarray(handles, dtype=np.int64)
         check(lib().mapa_release(self.h, len(h), _ptr(h), 8, 0, None), "mapa_release")
 
+    # -- job-trace simulation ------------------------------------------------------
+    def simulate(self, servers, policies, offsets, jobs):
+        """Run len(servers) simulations (job files jobs[offsets[i]:offsets[i+1]]
+        on distinct servers under the given policies).  Returns (logs as a
+        JOB_LOG_DTYPE array aligned with jobs, stats dict)."""
+        srv = np.ascontiguousarray(servers, dtype=np.int32)
+        pol = np.ascontiguousarray(policies, dtype=np.int32)
+        off = np.ascontiguousarray(offsets, dtype=np.int32)
+        j = np.zeros(len(jobs), dtype=JOB_DTYPE)
+        for f in ("id", "arrival", "duration", "kind", "k", "sensitive"):
+            j[f] = jobs[f]
+        logs = np.zeros(len(j), dtype=JOB_LOG_DTYPE)
+        st = SimStats()
+        check(lib().mapa_simulate(self.h, len(srv), _ptr(srv), _ptr(pol), _ptr(off),
+                                  _ptr(j) if len(j) else None, _ptr(logs) if len(j) else None,
+                                  ctypes.byref(st)), "mapa_simulate")
+        return logs, {name: getattr(st, name) for name, _ in SimStats._fields_}
+
     # -- tuning / stats ----------------------------------------------------------
     def tuning(self) -> Tuning:
         t = Tuning()
@@ -344,6 +379,11 @@ class Context:
         st = ServeStats()
         check(lib().mapa_serve_stop(self.h, ctypes.byref(st)), "mapa_serve_stop")
         return {name: getattr(st, name) for name, _ in ServeStats._fields_}
+
+
+def load_jobfiles(ctx: Context, jf):
+    """Create one server per simulation of a synth.JobFiles; returns the server ids."""
+    return ctx.load_servers(jf.topologies, jf.sim_topo)
 
 
 def _stream(stream):

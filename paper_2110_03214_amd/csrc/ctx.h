@@ -176,6 +176,11 @@ void serve_teardown(mapa_ctx *c);  // stop and free a running serving loop
 int32_t prof_start(mapa_ctx *c, hipStream_t s, ProfEvents &ev);
 int32_t prof_stop(mapa_ctx *c, hipStream_t s, const ProfEvents &ev);
 
+// Back-neighbour table of a pattern kind (canonical or registered) with k positions.
+unsigned long long pattern_nbtab(const mapa_ctx *c, int kind, int k);
+// Grow the API workspace to hold nq queries (no work may be in flight).
+int32_t ensure_batch_capacity(mapa_ctx *c, size_t nq);
+
 // Resolve the allocation-free batch's scratch array on `device` (current).
 int32_t noalloc_setup(int device);
 

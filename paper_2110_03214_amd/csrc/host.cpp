@@ -490,13 +490,6 @@ int32_t upload_split_table(mapa_ctx *c) {
   return MAPA_OK;
 }
 
-int32_t ensure_batch_capacity(mapa_ctx *c, size_t nq) {
-  if (nq <= c->ws.cap_q) return MAPA_OK;
-  int32_t rc = sync_ctx(c);
-  if (rc) return rc;
-  drop_graphs(c);
-  return ws_ensure_q(c->ws, nq);
-}
 
 int32_t ensure_small(mapa_ctx *c, size_t n) {
   if (n <= c->cap_small) return MAPA_OK;
@@ -549,6 +542,24 @@ int32_t validate_query(const mapa_ctx *c, const mapa_query &q, int32_t i) {
 }
 
 }  // namespace
+
+namespace mapa {
+
+int32_t ensure_batch_capacity(mapa_ctx *c, size_t nq) {
+  if (nq <= c->ws.cap_q) return MAPA_OK;
+  int32_t rc = sync_ctx(c);
+  if (rc) return rc;
+  drop_graphs(c);
+  return ws_ensure_q(c->ws, nq);
+}
+
+unsigned long long pattern_nbtab(const mapa_ctx *c, int kind, int k) {
+  if (kind > MAPA_TREE) return c->pat_nbtab[(size_t)(kind - MAPA_PATTERN_BASE)];
+  static const Tables t = build_tables();
+  return t.nbtab[kind][k];
+}
+
+}  // namespace mapa
 
 // =================================================================== ABI
 

@@ -354,3 +354,110 @@ def config5(nreq: int = 200_000, mean_rate: float = 38.0) -> Trace:
     return Trace("C5", topos, st, times, server, kind, k, hold,
                  {"config": 5, "mean_rate": mean_rate})
 
+
+
+# ---------------------------------------------------------------------------
+# job files for the trace simulator (Sec. 5.2)
+# ---------------------------------------------------------------------------
+
+def dgx1v_topology() -> np.ndarray:
+    """DGX-1 V100 (8 GPUs, hybrid cube-mesh), NVLink counts per pair, 0 = PCIe
+    only: the cells the paper's text fixes (GPUs 1-5 double, 1-2 single, 1-6
+    and 2-5 PCIe, GPUs 1, 3, 4 one single and two doubles) and the publicly
+    documented layout for the rest (every GPU uses its six NVLink ports).
+    Vertex index = paper GPU id - 1."""
+    double = [(0, 3), (0, 4), (1, 2), (1, 5), (2, 3), (4, 7), (5, 6), (6, 7)]
+    single = [(0, 1), (0, 2), (1, 3), (2, 6), (3, 7), (4, 5), (4, 6), (5, 7)]
+    return _sym(8, double + single, [2] * len(double) + [1] * len(single))
+
+
+def torus2d_16_topology(rng) -> np.ndarray:
+    """16 GPUs on a 4 x 4 torus (each joined to its four grid neighbours,
+    wrapping around), a seeded half of the 32 links double, the rest single;
+    every other pair PCIe only."""
+    edges = sorted({tuple(sorted((4 * r + c, 4 * r + (c + 1) % 4))) for r in range(4) for c in range(4)} |
+                   {tuple(sorted((4 * r + c, 4 * ((r + 1) % 4) + c))) for r in range(4) for c in range(4)})
+    heavy = set(int(i) for i in rng.permutation(len(edges))[:len(edges) // 2])
+    return _sym(16, edges, [2 if i in heavy else 1 for i in range(len(edges))])
+
+
+def cubemesh_16_topology(rng) -> np.ndarray:
+    """16 GPUs as two 8-GPU hybrid cube-meshes (each with a seeded half of its
+    16 links double) joined by single links i--i+8; every other pair PCIe."""
+    e8 = cube_mesh_edges()
+    edges, w = [], []
+    for base in (0, 8):
+        heavy = set(int(i) for i in rng.permutation(len(e8))[:len(e8) // 2])
+        edges += [(u + base, v + base) for u, v in e8]
+        w += [2 if i in heavy else 1 for i in range(len(e8))]
+    edges += [(i, i + 8) for i in range(8)]
+    w += [1] * 8
+    return _sym(16, edges, w)
+
+
+@dataclass
+class JobFiles:
+    """Simulations for the trace simulator: simulation i runs job file
+    ``jobs[offsets[i]:offsets[i+1]]`` on a server of topology ``sim_topo[i]``
+    under policy ``policy[i]`` (0 Preserve, 1 Greedy, 2 lowest ids)."""
+    name: str
+    topologies: list
+    sim_topo: np.ndarray   # int32 per simulation
+    policy: np.ndarray     # int32 per simulation
+    offsets: np.ndarray    # int32, nsim + 1
+    jobs: np.ndarray       # structured: id, arrival, duration, kind, k, sensitive
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def nsim(self) -> int:
+        return int(self.sim_topo.shape[0])
+
+    def subset(self, idx) -> "JobFiles":
+        idx = np.asarray(idx)
+        parts = [self.jobs[self.offsets[i]:self.offsets[i + 1]] for i in idx]
+        off = np.concatenate([[0], np.cumsum([len(p) for p in parts])]).astype(np.int32)
+        return JobFiles(self.name + "[sub]", self.topologies, self.sim_topo[idx], self.policy[idx],
+                        off, np.concatenate(parts) if parts else self.jobs[:0], dict(self.meta))
+
+
+JOB_DTYPE = np.dtype([("id", np.int32), ("arrival", np.int32), ("duration", np.int32),
+                      ("kind", np.uint8), ("k", np.uint8), ("sensitive", np.uint8),
+                      ("reserved", np.uint8)])
+
+
+def job_file(rng, njobs: int = 300, kmax: int = 5, dmin: int = 100, dmax: int = 1000,
+             mean_gap: float = 0.0) -> np.ndarray:
+    """One job file: njobs jobs asking U{1..kmax} GPUs (the paper's jobs ask
+    1 to 5, uniformly), pattern U{ring, all-to-all, tree}, bandwidth-sensitive
+    with probability 1/2, execution time U{dmin..dmax} cycles; all queued at
+    cycle 0 (mean_gap = 0, the paper's FIFO job file) or Poisson arrivals
+    with that mean gap in cycles."""
+    j = np.zeros(njobs, dtype=JOB_DTYPE)
+    j["id"] = np.arange(njobs)
+    if mean_gap > 0:
+        j["arrival"] = np.floor(np.cumsum(rng.exponential(mean_gap, size=njobs))).astype(np.int32)
+    j["duration"] = rng.integers(dmin, dmax + 1, size=njobs)
+    j["kind"] = rng.integers(0, 3, size=njobs)
+    j["k"] = rng.integers(1, kmax + 1, size=njobs)
+    j["sensitive"] = rng.integers(0, 2, size=njobs)
+    return j
+
+
+def config7(files_per_topology: int = 16, njobs: int = 300) -> JobFiles:
+    """Trace simulation: three hardware graphs (DGX-1 V100; 16-GPU torus-2d;
+    16-GPU two-cube-mesh), each with ``files_per_topology`` seeded job files
+    of ``njobs`` jobs (job_file defaults), every file run under each of the
+    three policies: 3 x files x 3 simulations."""
+    rt, _, rp, _, _ = streams(7)
+    topos = [dgx1v_topology(), torus2d_16_topology(rt), cubemesh_16_topology(rt)]
+    files = [[job_file(rp, njobs) for _ in range(files_per_topology)] for _ in topos]
+    sim_topo, policy, parts = [], [], []
+    for t in range(len(topos)):
+        for f in files[t]:
+            for pol in (0, 1, 2):
+                sim_topo.append(t)
+                policy.append(pol)
+                parts.append(f)
+    off = np.concatenate([[0], np.cumsum([len(p) for p in parts])]).astype(np.int32)
+    return JobFiles("C7", topos, np.array(sim_topo, np.int32), np.array(policy, np.int32), off,
+                    np.concatenate(parts), {"config": 7})

@@ -214,3 +214,29 @@ def test_serving_api_validation(vctx):
     assert code_of(lambda: vctx.serve_start(max_batch=-1)) == B.ERR_INVALID_ARG
     assert code_of(lambda: vctx.serve_start(inflight=3)) == B.ERR_INVALID_ARG
     assert code_of(lambda: vctx.serve_start()) == B.ERR_NO_DEVICE
+
+
+def test_simulation_validation(vctx):
+    """mapa_simulate validates every argument before it needs the device."""
+    W2 = np.array([[0, 2], [2, 0]], np.uint8)
+    _, s0 = vctx.create_topology(cube_mesh(), 2)
+    _, s2 = vctx.create_topology(W2, 1)
+    _, s3 = vctx.create_topology(np.array([[0, 3], [3, 0]], np.uint8), 1)
+    jobs = np.zeros(3, dtype=B.JOB_DTYPE)
+    jobs["duration"], jobs["k"] = 5, 2
+    off = [0, 2, 3]
+    assert code_of(lambda: vctx.simulate([s0, s0], [0, 0], off, jobs)) == B.ERR_INVALID_ARG
+    assert code_of(lambda: vctx.simulate([s0, 99], [0, 0], off, jobs)) == B.ERR_UNKNOWN_SERVER
+    assert code_of(lambda: vctx.simulate([s0, s3], [0, 0], off, jobs)) == B.ERR_UNSUPPORTED
+    assert code_of(lambda: vctx.simulate([s0, s2], [0, 3], off, jobs)) == B.ERR_INVALID_ARG
+    for field, val in (("k", 0), ("k", 9), ("duration", 0), ("arrival", -1), ("sensitive", 2),
+                       ("kind", 5)):
+        bad = jobs.copy()
+        bad[field][1] = val
+        assert code_of(lambda: vctx.simulate([s0, s2], [0, 1], off, bad)) == B.ERR_INVALID_ARG, field
+    late = jobs.copy()
+    late["arrival"] = [4, 1, 0]  # goes back in time within simulation 0
+    assert code_of(lambda: vctx.simulate([s0, s2], [0, 1], off, late)) == B.ERR_INVALID_ARG
+    assert code_of(lambda: vctx.simulate([s0, s2], [0, 2], off, jobs)) == B.ERR_NO_DEVICE
+    assert B.JOB_DTYPE.itemsize == 16 and B.JOB_LOG_DTYPE.itemsize == 48
+    assert B.COMPLETION_DTYPE.itemsize == 80
