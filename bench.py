@@ -24,6 +24,8 @@ Beside the headline the default run also reports (each skippable):
     16-vertex servers): the continuous-batching loop at 0.5 / 0.8 / 1.0 /
     1.2 x its measured capacity, and the plain serving form (one request per
     device batch, one batch in flight) at the same fractions of its own;
+  * the trace simulation of Sec. 5.2 (job files on three hardware graphs under
+    the Preserve, Greedy and lowest-id policies) with the oracle's simulator;
   * the CPU oracle on the host (single thread and all cores).
 
 Prints ONE JSON line:  value = embeddings scored per second on the headline
@@ -285,7 +287,26 @@ def cpu_baseline(wl, cfg: int, all_core_s: float = 30.0):
 
 # ---------------------------------------------------------------- GPU forms
 
-def timed_batch(B, wl, steps, warmup, metric="weighted", wide=False, profile=True):
+def autotune_into(B, ctx, wl, qh, path):
+    """Run the library's autotuner on the workload (no commits) and merge the
+    chosen tuning into the JSON cache at `path` under the workload's shape
+    class."""
+    q = qh.copy()
+    q["commit"] = 0
+    best, trials = ctx.autotune(q, reps=3)
+    key = B.shape_class(wl)
+    cache = B.load_tuning_cache(path)
+    cache[key] = {"tuning": best, "ms": min(ms for _, ms in trials),
+                  "default_ms": trials[0][1], "trials": len(trials)}
+    with open(path, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    log(f"[bench] autotuned {key}: {best} ({trials[0][1]:.4f} -> {cache[key]['ms']:.4f} ms, "
+        f"{len(trials)} trials)")
+    return key, best
+
+
+def timed_batch(B, wl, steps, warmup, metric="weighted", wide=False, profile=True, tuning="cache",
+                autotune=None):
     """The batched form: `steps` timed steps (query batch with commits, then
     release of every handle) after `warmup` untimed ones, inputs resident in
     HBM.  Kernel time from HIP events on the launch stream over the timed
@@ -299,6 +320,16 @@ def timed_batch(B, wl, steps, warmup, metric="weighted", wide=False, profile=Tru
     qh, ids = B.load_workload(ctx, wl)
     qh["commit"] = 1
     qh["metric"] = B.METRIC_EFFBW if metric == "effbw" else B.METRIC_WEIGHTED
+    if autotune and not wide:
+        key, settings = autotune_into(B, ctx, wl, qh, autotune)
+        source = f"autotuned in this run, written to {autotune}"
+    elif tuning == "cache" and not wide:
+        key, settings = B.apply_cached_tuning(ctx, wl)
+        source = ("autotuner cache paper_2110_03214_amd/tuning.json" if settings else
+                  "library defaults (no cached entry for this shape class)")
+    else:
+        key, settings, source = None, None, "library defaults"
+    tuning_info = {"shape_class": key, "source": source, "settings": ctx.tuning().as_dict()}
     dq = torch.from_numpy(qh.view(np.uint8).copy()).to(dev)
     dr = torch.zeros(wl.nq * B.RESULT_DTYPE.itemsize, dtype=torch.uint8, device=dev)
     handles = dr.view(torch.int64)[5:]  # alloc_handle: byte 40 of each 48-byte result
@@ -338,7 +369,7 @@ def timed_batch(B, wl, steps, warmup, metric="weighted", wide=False, profile=Tru
     assert np.array_equal(ctx.get_busy(ids), wl.busy), "release did not restore the entry state"
     assert st["self_check_failures"] == 0
     out = {"wall_s": wall, "steps": steps, "embeddings": emb, "ops": ops, "queries": wl.nq,
-           "lat_ms": lat, "stats": st, "qh": qh}
+           "lat_ms": lat, "stats": st, "qh": qh, "tuning": tuning_info}
     out["kernel_ms"] = (st["enum_ms"] / st["enum_launches"]) if st["enum_launches"] else None
     out["probe"] = ctx.measure_alu_peak() if profile else None
     return ctx, out
@@ -421,6 +452,59 @@ def run_serving(B, cfg: int, nreq: int, plain: bool = False, loads=(0.5, 0.8, 1.
     return out
 
 
+SIM_TOPOLOGY = ("DGX-1 V100 (8 GPUs)", "torus-2d (16 GPUs)", "two cube-meshes (16 GPUs)")
+SIM_POLICY = ("preserve", "greedy", "baseline lowest ids")
+
+
+def run_simulator(B, files_per_topology: int, njobs: int = 300, cpu_sims: int = 3):
+    """Trace simulation (Sec. 5.2) of the job-file workload: every job file
+    on each hardware graph under each policy, all simulations in one
+    mapa_simulate call; plus the oracle's simulator on a few of them and the
+    predicted effective bandwidth of the bandwidth-sensitive jobs per
+    (hardware graph, policy), the paper's figure of merit."""
+    from paper_2110_03214_amd import synth
+    jf = synth.config7(files_per_topology, njobs)
+    ctx = B.Context(0)
+    ids = B.load_jobfiles(ctx, jf)
+    warm = jf.subset(np.arange(3))
+    ctx.simulate(ids[:3], warm.policy, warm.offsets, warm.jobs)
+    t0 = time.perf_counter()
+    logs, st = ctx.simulate(ids, jf.policy, jf.offsets, jf.jobs)
+    wall = time.perf_counter() - t0
+    ctx.close()
+    out = {"workload": (f"{jf.nsim} simulations: {files_per_topology} seeded job files of {njobs} "
+                        "jobs (1-5 GPUs, ring/all-to-all/tree, half bandwidth-sensitive, all "
+                        "queued at cycle 0) on each of 3 hardware graphs, each file under the "
+                        "3 policies"),
+           "jobs": int(len(jf.jobs)), "wall_s": wall, "jobs_per_s": len(jf.jobs) / wall,
+           "rounds": st["rounds"], "device_batches": st["device_batches"],
+           "jobs_placed": st["jobs_placed"]}
+    eff = {}
+    for t, tname in enumerate(SIM_TOPOLOGY):
+        eff[tname] = {}
+        for p, pname in enumerate(SIM_POLICY):
+            sel = [i for i in range(jf.nsim) if jf.sim_topo[i] == t and jf.policy[i] == p]
+            v = np.concatenate([logs["effbw_milli"][jf.offsets[i]:jf.offsets[i + 1]][
+                (jf.jobs["sensitive"][jf.offsets[i]:jf.offsets[i + 1]] == 1) &
+                (jf.jobs["k"][jf.offsets[i]:jf.offsets[i + 1]] >= 2)] for i in sel]) / 1000.0
+            eff[tname][pname] = [round(float(x), 3) for x in np.percentile(v, [0, 25, 50, 75, 100])]
+    out["effbw_sensitive_min_p25_p50_p75_max_gbps"] = eff
+    # the oracle's simulator (test infrastructure) on the first job file of
+    # each hardware graph under Preserve
+    from oracle import simulate as osim
+    pick = [int(np.nonzero((jf.sim_topo == t) & (jf.policy == 0))[0][0]) for t in range(3)][:cpu_sims]
+    t0 = time.perf_counter()
+    n = 0
+    for i in pick:
+        a, b = jf.offsets[i], jf.offsets[i + 1]
+        osim.simulate(jf.topologies[jf.sim_topo[i]], 0, jf.jobs[a:b], 0)
+        n += b - a
+    dt = time.perf_counter() - t0
+    out["cpu_baseline"] = {"value": n / dt, "unit": "jobs/s", "cores": 1, "kind": "oracle",
+                           "sample": f"{len(pick)} simulations ({n} jobs, Preserve) one after another"}
+    return out
+
+
 def roofline(cfg, tb):
     """Roofline of the enumeration kernel from the timed region's HIP-event
     kernel time: the per-leaf operation count (``achieved``/``frac``), the
@@ -462,7 +546,7 @@ def batched_summary(tb):
             "queries_per_s": tb["queries"] * tb["steps"] / tb["wall_s"],
             "ms_per_step": tb["wall_s"] * 1e3 / tb["steps"], "steps": tb["steps"],
             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-            "kernel_ms": tb["kernel_ms"]}
+            "kernel_ms": tb["kernel_ms"], "tuning": tb["tuning"]}
 
 
 def main():
@@ -491,6 +575,14 @@ def main():
                     help="requests of the mixed-size trace through the continuous loop (0: skip)")
     ap.add_argument("--mixed-plain", type=int, default=5_000,
                     help="requests of the mixed-size trace through the plain serving form (0: skip)")
+    ap.add_argument("--simulate", type=int, default=16,
+                    help="job files per hardware graph for the trace simulation (0: skip)")
+    ap.add_argument("--tuning", default="cache", choices=("cache", "default"),
+                    help="launch settings: the autotuner's cached choice for the workload's shape "
+                         "class (paper_2110_03214_amd/tuning.json), or the library defaults")
+    ap.add_argument("--autotune", default="",
+                    help="run the autotuner on each timed batch workload first and merge its "
+                         "choices into this JSON cache file")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device-to-device copy of this many MiB first, to scale "
                          "hardware memory counters (FETCH_SIZE / WRITE_SIZE) against known bytes")
@@ -512,7 +604,7 @@ def main():
         sys.exit(1)
     if args.only_headline:
         args.batched = args.plain = args.serving = args.serving_plain = 0
-        args.mixed = args.mixed_plain = 0
+        args.mixed = args.mixed_plain = args.simulate = 0
         args.no_cpu_baseline = True
     if args.copy_calibration_mib:
         src = torch.empty(args.copy_calibration_mib << 20, dtype=torch.uint8, device="cuda:0")
@@ -531,7 +623,7 @@ def main():
     log(f"[bench] headline config {args.config}: {wl.nq} queries, {ops['embeddings']:.4g} "
         f"embeddings/step")
     ctx, tb = timed_batch(B, wl, args.steps, args.warmup, args.metric, wide=args.config == 6,
-                          profile=not args.no_profile)
+                          profile=not args.no_profile, tuning=args.tuning, autotune=args.autotune)
     log(f"[bench] {args.steps} steps in {tb['wall_s']:.3f} s; kernel "
         f"{tb['kernel_ms'] if tb['kernel_ms'] else float('nan'):.3f} ms avg")
     lat = tb["lat_ms"]
@@ -557,6 +649,7 @@ def main():
         "p50_ms": float(np.percentile(lat, 50)),
         "p99_ms": float(np.percentile(lat, 99)),
         "latency_scope": "per batch (every query of a batch completes together)",
+        "tuning": tb["tuning"],
     }
     if tb["kernel_ms"]:
         out["roofline"] = roofline(args.config, tb)
@@ -568,7 +661,8 @@ def main():
     if args.batched and args.config != 2:
         log("[bench] batched config")
         c2 = synth.config2()
-        ctx2, tb2 = timed_batch(B, c2, args.batched, args.warmup, profile=not args.no_profile)
+        ctx2, tb2 = timed_batch(B, c2, args.batched, args.warmup, profile=not args.no_profile,
+                                tuning=args.tuning, autotune=args.autotune)
         out["batched_config_2"] = batched_summary(tb2)
         out["batched_config_2"]["workload"] = WORKLOAD_TEXT[2]
         if tb2["kernel_ms"]:
@@ -597,6 +691,9 @@ def main():
         serving["trace_5_plain"] = run_serving(B, 5, args.mixed_plain, plain=True)
     if serving:
         out["serving"] = serving
+    if args.simulate:
+        log(f"[bench] trace simulation, {args.simulate} job files per hardware graph")
+        out["simulation"] = run_simulator(B, args.simulate)
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(wl, args.config)

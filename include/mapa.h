@@ -396,13 +396,41 @@ typedef struct {
                                    (128); a batch too small to fill the lanes
                                    takes the finest split that fits          */
   int32_t blocks_per_cu;        /* persistent enumeration blocks per CU (0=auto) */
-  int32_t threads_per_block;    /* 64..1024, multiple of 64 (256)                */
+  int32_t threads_per_block;    /* 64..256, multiple of 64 (256)                 */
+  int32_t pair_width;           /* widest number of free vertices whose last two
+                                   positions are scored from per-candidate
+                                   tables: 6 or 12; -1 none; 0 auto (12 when the
+                                   context has a topology of 10 or more
+                                   vertices, else 6)                          */
 } mapa_tuning;
 
 /* Read or replace the context's tuning knobs (NULL out/in allowed).  Results
  * never depend on tuning; only speed does. */
 int32_t mapa_get_tuning(mapa_ctx *ctx, mapa_tuning *out);
 int32_t mapa_set_tuning(mapa_ctx *ctx, const mapa_tuning *in);
+
+typedef struct {
+  mapa_tuning tuning;
+  double ms;              /* mean time of one batch with this tuning (HIP events) */
+} mapa_tune_trial;
+
+/* Autotuner: time candidate tunings on a representative batch and keep the
+ * fastest.  q: nq host queries, validated as by mapa_query_batch; they run
+ * without commits, so no server state changes.  Starting from the current
+ * tuning, the knobs are searched one at a time (coordinate descent, at most
+ * two passes): min_leaves_per_item in {16, 64, 256, 1024, 4096},
+ * mean_item_leaves in {32, 128, 512, 2048, 8192}, threads_per_block in
+ * {64, 128, 192, 256}, blocks_per_cu in {0, 1, 2, 4, 8} and, for contexts
+ * whose weights fit 2 bits, pair_width in {0, -1, 6, 12}; a candidate runs
+ * one warm-up batch and `reps` (1..100) timed ones, and its results must
+ * equal the first candidate's byte for byte (else MAPA_ERR_DEVICE and the
+ * starting tuning is restored).  A change is kept only if it is at least 1 %
+ * faster.  On success the context keeps the fastest tuning, *best (may be
+ * NULL) receives it, trials[0 .. min(cap, *ntrials)) the candidates in the
+ * order timed (trials may be NULL with cap = 0) and *ntrials (may be NULL)
+ * their number.  Synchronous. */
+int32_t mapa_autotune(mapa_ctx *ctx, const mapa_query *q, int32_t nq, int32_t reps,
+                      mapa_tuning *best, mapa_tune_trial *trials, int32_t cap, int32_t *ntrials);
 
 typedef struct {
   int64_t batches;         /* query batches run                                */

@@ -54,7 +54,15 @@ NOALLOC_MAX_QUERIES = 65536
 
 class Tuning(ctypes.Structure):
     _fields_ = [("min_leaves_per_item", ctypes.c_int32), ("mean_item_leaves", ctypes.c_int32),
-                ("blocks_per_cu", ctypes.c_int32), ("threads_per_block", ctypes.c_int32)]
+                ("blocks_per_cu", ctypes.c_int32), ("threads_per_block", ctypes.c_int32),
+                ("pair_width", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class TuneTrial(ctypes.Structure):
+    _fields_ = [("tuning", Tuning), ("ms", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -128,6 +136,8 @@ SIGNATURES = {
     "mapa_simulate": (_I32, [_P, _I32, _P, _P, _P, _P, _P, ctypes.POINTER(SimStats)]),
     "mapa_get_tuning": (_I32, [_P, ctypes.POINTER(Tuning)]),
     "mapa_set_tuning": (_I32, [_P, ctypes.POINTER(Tuning)]),
+    "mapa_autotune": (_I32, [_P, _P, _I32, _I32, ctypes.POINTER(Tuning), _P, _I32,
+                             ctypes.POINTER(_I32)]),
     "mapa_profile": (_I32, [_P, _I32]),
     "mapa_get_stats": (_I32, [_P, ctypes.POINTER(Stats)]),
     "mapa_reset_stats": (_I32, [_P]),
@@ -335,6 +345,19 @@ class Context:
             setattr(t, key, int(v))
         check(lib().mapa_set_tuning(self.h, ctypes.byref(t)), "mapa_set_tuning")
 
+    def autotune(self, queries, reps: int = 3):
+        """Run the library's autotuner on host queries; the context keeps the
+        fastest tuning.  Returns (best tuning dict, list of (tuning dict, ms))."""
+        q = np.ascontiguousarray(queries, dtype=QUERY_DTYPE)
+        cap = 256
+        trials = (TuneTrial * cap)()
+        best, n = Tuning(), ctypes.c_int32()
+        check(lib().mapa_autotune(self.h, _ptr(q), len(q), int(reps), ctypes.byref(best),
+                                  ctypes.cast(trials, ctypes.c_void_p), cap, ctypes.byref(n)),
+              "mapa_autotune")
+        return best.as_dict(), [(trials[i].tuning.as_dict(), trials[i].ms)
+                                for i in range(min(cap, n.value))]
+
     def profile(self, on: bool = True):
         check(lib().mapa_profile(self.h, 1 if on else 0), "mapa_profile")
 
@@ -379,6 +402,45 @@ class Context:
         st = ServeStats()
         check(lib().mapa_serve_stop(self.h, ctypes.byref(st)), "mapa_serve_stop")
         return {name: getattr(st, name) for name, _ in ServeStats._fields_}
+
+
+# Autotuned settings per batch shape class, as written by a bench run with
+# --autotune: {class key: {"tuning": {...}, "ms": ..., "default_ms": ...}}.
+TUNING_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json")
+
+
+def shape_class(wl) -> str:
+    """Key of a synth.Workload's batch shape: accelerators per server, pattern
+    sizes, kinds, modes, key metric, widest weight class and the batch size
+    (power of two)."""
+    q = wl.queries
+    topo = wl.server_topo[q["server"]]
+    n = [wl.topologies[t].shape[0] for t in np.unique(topo)]
+    wmax = max(int(np.max(wl.topologies[t])) for t in np.unique(topo))
+    wcls = 3 if wmax <= 3 else 15 if wmax <= 15 else 255
+    metric = sorted(set(int(x) for x in q.get("metric", np.zeros(1, np.int32))))
+    return (f"n{min(n)}-{max(n)}|k{int(q['k'].min())}-{int(q['k'].max())}|"
+            f"kinds{','.join(str(int(k)) for k in np.unique(q['kind']))}|"
+            f"mode{','.join(str(int(m)) for m in np.unique(q['mode']))}|"
+            f"metric{','.join(map(str, metric))}|w{wcls}|q2^{max(0, int(wl.nq - 1).bit_length())}")
+
+
+def load_tuning_cache(path: str = TUNING_CACHE) -> dict:
+    import json
+    if not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        return json.load(f)
+
+
+def apply_cached_tuning(ctx: Context, wl, path: str = TUNING_CACHE):
+    """Set the autotuned tuning cached for the workload's shape class, if any.
+    Returns (key, tuning dict or None)."""
+    key = shape_class(wl)
+    entry = load_tuning_cache(path).get(key)
+    if entry:
+        ctx.set_tuning(**entry["tuning"])
+    return key, (entry or {}).get("tuning")
 
 
 def load_jobfiles(ctx: Context, jf):

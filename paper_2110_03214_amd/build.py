@@ -8,7 +8,7 @@ enum_*.hip: the enumeration kernel, one unit per pair-level variant) and the
 host units (host.cpp: C ABI, validation, memory, launches; serve.cpp: the
 serving loop; wide.hip / wide.cpp: servers of up to 32 accelerators and
 patterns of up to 12 vertices; noalloc.hip: the allocation-free batch; simulate.hip /
-simulate.cpp: the job-trace simulation), each compiled by hipcc for gfx950 only, in
+simulate.cpp: the job-trace simulation; autotune.cpp: the autotuner), each compiled by hipcc for gfx950 only, in
 parallel, then
 linked into one shared object.
 """
@@ -28,7 +28,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libmapa.so")
 SOURCES = [os.path.join(CSRC, f) for f in (
     "enum_pair12_lds.hip", "enum_pair12_glb.hip", "enum_pair6.hip", "enum_plain.hip",
-    "fused.hip", "kernels.hip", "wide.hip", "noalloc.hip", "simulate.hip", "host.cpp", "serve.cpp", "wide.cpp", "simulate.cpp")]
+    "fused.hip", "kernels.hip", "wide.hip", "noalloc.hip", "simulate.hip", "host.cpp", "serve.cpp", "wide.cpp", "simulate.cpp",
+    "autotune.cpp")]
 ARCH = "gfx950"
 
 

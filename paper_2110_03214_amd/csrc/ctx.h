@@ -134,7 +134,7 @@ struct mapa_ctx {
   std::vector<Graph> graphs;
   uint64_t version = 1;  // bumped whenever a value baked into a launch changes
 
-  mapa_tuning tuning{64, 128, 0, 256};
+  mapa_tuning tuning{64, 128, 0, 256, 0};
   uint64_t occ_shape = ~0ull;  // launch shape whose occupancy occ_blocks holds
   int occ_blocks = 0;
   bool profile = false;
@@ -178,6 +178,8 @@ int32_t prof_stop(mapa_ctx *c, hipStream_t s, const ProfEvents &ev);
 
 // Back-neighbour table of a pattern kind (canonical or registered) with k positions.
 unsigned long long pattern_nbtab(const mapa_ctx *c, int kind, int k);
+// Validate nq host queries as mapa_query_batch does.
+int32_t validate_queries(const mapa_ctx *c, const mapa_query *q, int32_t nq);
 // Grow the API workspace to hold nq queries (no work may be in flight).
 int32_t ensure_batch_capacity(mapa_ctx *c, size_t nq);
 

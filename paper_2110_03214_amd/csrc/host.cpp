@@ -126,6 +126,7 @@ void fill_args(mapa_ctx *c, const Workspace &w, BatchArgs &a) {
   // topologies have 10 or more vertices (measured: 8 is best below that)
   const int max_n = c->topo_n.empty() ? 0 : *std::max_element(c->topo_n.begin(), c->topo_n.end());
   a.pair = c->wpr != 1 ? 0 : max_n >= 10 ? 12 : 6;
+  if (c->wpr == 1 && c->tuning.pair_width != 0) a.pair = c->tuning.pair_width < 0 ? 0 : c->tuning.pair_width;
   int per_cu = c->tuning.blocks_per_cu;
   if (per_cu <= 0) {
     // the occupancy query costs microseconds: ask once per launch shape
@@ -551,6 +552,12 @@ int32_t ensure_batch_capacity(mapa_ctx *c, size_t nq) {
   if (rc) return rc;
   drop_graphs(c);
   return ws_ensure_q(c->ws, nq);
+}
+
+int32_t validate_queries(const mapa_ctx *c, const mapa_query *q, int32_t nq) {
+  for (int32_t i = 0; i < nq; ++i)
+    if (int32_t rc = validate_query(c, q[i], i)) return rc;
+  return MAPA_OK;
 }
 
 unsigned long long pattern_nbtab(const mapa_ctx *c, int kind, int k) {
@@ -1028,6 +1035,8 @@ int32_t mapa_set_tuning(mapa_ctx *c, const mapa_tuning *in) {
     return fail(MAPA_ERR_INVALID_ARG, "blocks_per_cu outside 0..64");
   if (in->threads_per_block < 64 || in->threads_per_block > 256 || in->threads_per_block % 64)
     return fail(MAPA_ERR_INVALID_ARG, "threads_per_block must be 64, 128, 192 or 256");
+  if (in->pair_width != 0 && in->pair_width != -1 && in->pair_width != 6 && in->pair_width != 12)
+    return fail(MAPA_ERR_INVALID_ARG, "pair_width must be 0, -1, 6 or 12");
   c->tuning = *in;
   if (c->has_device) {
     int32_t rc = sync_ctx(c);

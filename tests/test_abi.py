@@ -240,3 +240,13 @@ def test_simulation_validation(vctx):
     assert code_of(lambda: vctx.simulate([s0, s2], [0, 2], off, jobs)) == B.ERR_NO_DEVICE
     assert B.JOB_DTYPE.itemsize == 16 and B.JOB_LOG_DTYPE.itemsize == 48
     assert B.COMPLETION_DTYPE.itemsize == 80
+
+
+def test_tuning_knobs_and_cached_tunings_validate(vctx):
+    assert code_of(lambda: vctx.set_tuning(pair_width=7)) == B.ERR_INVALID_ARG
+    for pw in (0, -1, 6, 12):
+        vctx.set_tuning(pair_width=pw)
+    for key, entry in B.load_tuning_cache().items():
+        assert key.count("|") == 6
+        vctx.set_tuning(**entry["tuning"])
+        assert vctx.tuning().as_dict() == entry["tuning"]
