@@ -31,6 +31,7 @@ using Clock = std::chrono::steady_clock;
 struct Req {
   mapa_request r;
   double due_us;  // wall-clock time (since the loop started) at which it is due
+  Req *next;      // next request of the same server's queue
 };
 
 struct Held {
@@ -53,7 +54,7 @@ struct Slot {
   bool active = false;
   int32_t batch_id = -1;
   double t_dispatch = 0;
-  std::vector<Req> reqs;
+  std::vector<const Req *> reqs;
   std::vector<uint32_t> busy_before;
 };
 
@@ -63,6 +64,20 @@ unsigned long long estimate_items(int F, int k, int leaves) {
   while (d < k - 1 && perm_leaves(F - d, k - d) > (unsigned long long)leaves) ++d;
   return perm_leaves(F, d);
 }
+
+// Per (free accelerators, k): prefix items admission counts and embeddings
+// (the fused-launch test), tabulated once per loop.
+struct WorkTables {
+  unsigned long long items[kMaxN + 1][kMaxK + 1];
+  unsigned long long leaves[kMaxN + 1][kMaxK + 1];
+  void build(int item_leaves) {
+    for (int F = 0; F <= kMaxN; ++F)
+      for (int k = 0; k <= kMaxK; ++k) {
+        items[F][k] = k >= 1 && k <= F ? estimate_items(F, k, item_leaves) : 0;
+        leaves[F][k] = perm_leaves(F, k);
+      }
+  }
+};
 
 }  // namespace
 
@@ -87,22 +102,40 @@ struct ServeState {
   std::vector<uint32_t> busy;  // host mirror of the device busy masks
   std::vector<int32_t> nvert;
   std::vector<uint8_t> in_flight, in_ready;
-  std::vector<std::deque<Req>> fifo;
+  // per server, the requests due and not yet answered, oldest first: a
+  // singly linked list through Req::next (requests never move: they stay in
+  // their submission's vector until the loop ends)
+  std::vector<Req *> fhead, ftail;
+  WorkTables work;
   std::deque<int32_t> ready;
-  // submitted, not yet due: whole submissions in arrival order, consumed
-  // from the front (pend_pos indexes the front one), so taking over a large
-  // submission costs nothing per request
-  std::deque<std::vector<Req>> pending;
-  size_t pend_pos = 0;
+  // every submission in arrival order (kept until the loop ends, so queued
+  // requests can be referred to by address); (pend_sub, pend_pos) is the
+  // first request not yet due
+  std::deque<std::vector<Req>> subs;
+  size_t pend_sub = 0, pend_pos = 0;
 
   bool pending_empty() {
-    while (!pending.empty() && pend_pos >= pending.front().size()) {
-      pending.pop_front();
+    while (pend_sub < subs.size() && pend_pos >= subs[pend_sub].size()) {
+      ++pend_sub;
       pend_pos = 0;
     }
-    return pending.empty();
+    return pend_sub >= subs.size();
   }
-  const Req &pending_front() const { return pending.front()[pend_pos]; }
+  Req &pending_front() { return subs[pend_sub][pend_pos]; }
+
+  bool fifo_empty(int32_t s) const { return fhead[s] == nullptr; }
+  void fifo_push(int32_t s, Req *r) {
+    r->next = nullptr;
+    if (ftail[s])
+      ftail[s]->next = r;
+    else
+      fhead[s] = r;
+    ftail[s] = r;
+  }
+  void fifo_pop(int32_t s) {
+    fhead[s] = fhead[s]->next;
+    if (!fhead[s]) ftail[s] = nullptr;
+  }
   std::priority_queue<Held, std::vector<Held>, HeldLater> held;
   std::vector<Held> deferred;  // due releases whose server has a request in flight
   std::vector<int64_t> held_forever;
@@ -156,7 +189,7 @@ void flush_completions(ServeState *S) {
 }
 
 void make_ready(ServeState *S, int32_t s) {
-  if (!S->in_flight[s] && !S->in_ready[s] && !S->fifo[s].empty()) {
+  if (!S->in_flight[s] && !S->in_ready[s] && !S->fifo_empty(s)) {
     S->in_ready[s] = 1;
     S->ready.push_back(s);
   }
@@ -174,7 +207,7 @@ int32_t harvest(ServeState *S, bool *did) {
     if (hipEventElapsedTime(&gms, sl.g0, sl.g1) == hipSuccess) S->gpu_us_sum += 1e3 * gms;
     for (size_t i = 0; i < sl.reqs.size(); ++i) {
       const mapa_result &r = sl.h_res[i];
-      const Req &rq = sl.reqs[i];
+      const Req &rq = *sl.reqs[i];
       const int32_t s = rq.r.server;
       mapa_completion cpl;
       std::memset(&cpl, 0, sizeof cpl);
@@ -259,10 +292,9 @@ int32_t dispatch(ServeState *S, Slot &sl, bool final_release, bool *did) {
     S->ready.pop_front();
     S->in_ready[s] = 0;
     if (S->in_flight[s]) continue;
-    auto &f = S->fifo[s];
     // requests that cannot fit are answered here, in order
-    while (!f.empty()) {
-      const Req &rq = f.front();
+    while (!S->fifo_empty(s)) {
+      const Req &rq = *S->fhead[s];
       const int F = S->nvert[s] - __builtin_popcount(S->busy[s]);
       if ((int)rq.r.k <= F) break;
       mapa_completion cpl;
@@ -280,13 +312,13 @@ int32_t dispatch(ServeState *S, Slot &sl, bool final_release, bool *did) {
       ++S->st.nofit;
       ++S->st.host_nofit;
       push_completion(S, cpl, now);
-      f.pop_front();
+      S->fifo_pop(s);
       *did = true;
     }
-    if (f.empty()) continue;
-    const Req &rq = f.front();
+    if (S->fifo_empty(s)) continue;
+    const Req *rq = S->fhead[s];
     const int F = S->nvert[s] - __builtin_popcount(S->busy[s]);
-    const unsigned long long est = estimate_items(F, rq.r.k, S->opts.item_leaves);
+    const unsigned long long est = S->work.items[F][rq->r.k];
     if ((int32_t)sl.reqs.size() >= S->opts.max_batch) {
       keep.push_back(s);
       continue;
@@ -300,7 +332,7 @@ int32_t dispatch(ServeState *S, Slot &sl, bool final_release, bool *did) {
     sl.reqs.push_back(rq);
     sl.busy_before.push_back(S->busy[s]);
     S->in_flight[s] = 1;
-    f.pop_front();
+    S->fifo_pop(s);
   }
   for (auto it = keep.rbegin(); it != keep.rend(); ++it) {
     S->in_ready[*it] = 1;
@@ -335,7 +367,7 @@ int32_t dispatch(ServeState *S, Slot &sl, bool final_release, bool *did) {
   if (!sl.reqs.empty()) {
     const int32_t nq = (int32_t)sl.reqs.size();
     for (int32_t i = 0; i < nq; ++i) {
-      const mapa_request &r = sl.reqs[i].r;
+      const mapa_request &r = sl.reqs[i]->r;
       mapa_query &q = sl.h_q[i];
       q.server = r.server;
       q.kind = r.kind;
@@ -351,9 +383,9 @@ int32_t dispatch(ServeState *S, Slot &sl, bool final_release, bool *did) {
     unsigned long long total = 0;
     bool small = nq <= kFusedMaxQueries;
     for (int32_t i = 0; i < nq && small; ++i) {
-      const int32_t s = sl.reqs[i].r.server;
+      const int32_t s = sl.reqs[i]->r.server;
       const unsigned long long e =
-          perm_leaves(S->nvert[s] - __builtin_popcount(sl.busy_before[i]), sl.reqs[i].r.k);
+          S->work.leaves[S->nvert[s] - __builtin_popcount(sl.busy_before[i])][sl.reqs[i]->r.k];
       small = e <= kFusedMaxQueryLeaves;
       total += e;
     }
@@ -399,7 +431,7 @@ void loop_main(ServeState *S) {
     bool stopping;
     {
       std::lock_guard<std::mutex> lk(S->mu);
-      for (auto &v : S->incoming) S->pending.push_back(std::move(v));
+      for (auto &v : S->incoming) S->subs.push_back(std::move(v));
       S->incoming.clear();
       stopping = S->stopping;
     }
@@ -407,10 +439,10 @@ void loop_main(ServeState *S) {
     // due arrivals join their server's queue
     const double now = S->now_us();
     while (!S->pending_empty() && S->pending_front().due_us <= now) {
-      const Req r = S->pending_front();
+      Req *r = &S->pending_front();
       ++S->pend_pos;
-      S->fifo[r.r.server].push_back(r);
-      make_ready(S, r.r.server);
+      S->fifo_push(r->r.server, r);
+      make_ready(S, r->r.server);
       did = true;
     }
     bool outstanding;
@@ -521,7 +553,9 @@ int32_t mapa_serve_start(mapa_ctx *c, const mapa_serve_opts *opts) {
   for (size_t s = 0; s < ns; ++s) S->nvert[s] = c->topo_n[c->server_topo[s]];
   S->in_flight.assign(ns, 0);
   S->in_ready.assign(ns, 0);
-  S->fifo.resize(ns);
+  S->fhead.assign(ns, nullptr);
+  S->ftail.assign(ns, nullptr);
+  S->work.build(o.item_leaves);
   auto bail = [&](int32_t code, const char *what) {
     free_state(S);
     return fail(code, "mapa_serve_start: %s", what);
@@ -580,7 +614,7 @@ int32_t mapa_serve_submit(mapa_ctx *c, const mapa_request *reqs, int32_t n) {
       return fail(MAPA_ERR_UNSUPPORTED, "request %d: effective bandwidth needs link weights 0..2", i);
     if (i > 0 && !(r.t_arrival >= reqs[i - 1].t_arrival))
       return fail(MAPA_ERR_INVALID_ARG, "request %d: arrival goes back in time", i);
-    batch[i] = {r, S->opts.time_unit_us > 0 ? r.t_arrival * S->opts.time_unit_us : 0.0};
+    batch[i] = {r, S->opts.time_unit_us > 0 ? r.t_arrival * S->opts.time_unit_us : 0.0, nullptr};
   }
   std::lock_guard<std::mutex> lk(S->mu);
   if (S->stopping) return fail(MAPA_ERR_STATE, "the serving loop is stopping");

@@ -9,8 +9,16 @@
 // k_wide_search: a block works on one query; its threads take the query's
 // prefixes of depth d (F!/(F-d)! of them, in lexicographic order of their
 // index) in a block-strided loop and expand each depth-first, keeping a count
-// and their best (key, mapping).  Weighted sums are popcounts over 32-bit
-// weight bit-planes staged in LDS.  The block reduces to one partial.
+// and their best (key, mapping).  The search is iterative: each thread keeps
+// the candidates left, the running key and the neighbour mask of every open
+// position in an LDS stack, so nothing spills and no call frames are built.
+// The last two positions are one step: in ALL mode every ordered pair of the
+// N free vertices left is a match, and its key is a sum of per-candidate
+// terms tabulated once per node plus one pair weight (see pair_table).
+// Weighted sums are popcounts over 32-bit weight bit-planes staged in LDS.
+// The lanes of a wave hold prefixes of one query, so in ALL mode they open
+// the same number of candidates at every position and run in lock step.
+// The block reduces to one partial.
 // k_wide_finalize: per query, the partials of its blocks, the mapping, a
 // recomputation of AggBW and PreservedBW from it (self-check) and the commit.
 #include "mapa_internal.h"
@@ -41,94 +49,263 @@ __device__ __forceinline__ int vertex_at(unsigned long long code, int pos) {
   return (int)((code >> (5 * (kWideK - 1 - pos))) & 31ull);
 }
 
-struct WideState {
-  const uint32_t *rows;  // LDS: [kWidePlanes][32]
-  const WidePlan *p;
-  int B, a, b, k, linked, nb_all;
-  unsigned long long count;
-  int bkey;
-  unsigned long long bcode;
-};
 
-// a * w(c, nbm) - b * w(c, rest): one pass over the weight planes; the
-// common cases of one and two planes (weights up to 3) unrolled
-__device__ __forceinline__ int wide_term(const WideState &s, int c, uint32_t nbm, uint32_t rest) {
-  const uint32_t r0 = s.rows[c];
-  int v = s.a * __popc(r0 & nbm) - s.b * __popc(r0 & rest);
-  if (s.B == 1) return v;
-  const uint32_t r1 = s.rows[32 + c];
-  v += (s.a * __popc(r1 & nbm) - s.b * __popc(r1 & rest)) << 1;
-  for (int t = 2; t < s.B; ++t) {
-    const uint32_t r = s.rows[t * 32 + c];
-    v += (s.a * __popc(r & nbm) - s.b * __popc(r & rest)) << t;
-  }
-  return v;
+// key of a leaf, packed so one unsigned max picks the largest key and, among
+// equal keys, the smallest last vertex: ((key + 1) << 5) | (31 - c).  Keys
+// stay below 2^27 (weights <= 255, n <= 32, a, b <= 1024: at most 465 pairs
+// of one of the two sums), so the packed value fits 32 bits.
+__device__ __forceinline__ uint32_t pack_leaf(int key, int c) {
+  return ((uint32_t)(key + 1) << 5) | (31u - (uint32_t)c);
 }
 
-// vertices at the earlier pattern neighbours of position pos, and the
-// candidates for pos (in LINKED mode adjacent to each of them)
-__device__ __forceinline__ void wide_masks(const WideState &s, unsigned long long code, int pos,
-                                           uint32_t rest, uint32_t &nbm, uint32_t &cand) {
+// sum of W[v][u] over u in X from B (1, 2, or any up to 8) bit-planes
+template <int B>
+__device__ __forceinline__ int wsum_b(const uint32_t *rows, int Bn, int v, uint32_t X) {
+  if constexpr (B == 1) {
+    return __popc(rows[v] & X);
+  } else if constexpr (B == 2) {
+    return __popc(rows[v] & X) + 2 * __popc(rows[32 + v] & X);
+  } else {
+    int s = 0;
+    for (int t = 0; t < Bn; ++t) s += __popc(rows[t * 32 + v] & X) << t;
+    return s;
+  }
+}
+
+// W[u][v] from the bit-planes
+template <int B>
+__device__ __forceinline__ int wpair_b(const uint32_t *rows, int Bn, int u, int v) {
+  if constexpr (B == 1) {
+    return (int)((rows[u] >> v) & 1u);
+  } else if constexpr (B == 2) {
+    return (int)((rows[u] >> v) & 1u) + 2 * (int)((rows[32 + u] >> v) & 1u);
+  } else {
+    int s = 0;
+    for (int t = 0; t < Bn; ++t) s += (int)((rows[t * 32 + u] >> v) & 1u) << t;
+    return s;
+  }
+}
+
+struct WideCtx {
+  const uint32_t *rows;  // LDS: [kWidePlanes][32]
+  const uint32_t *pw;    // LDS: [32][2] packed 2-bit weights (weights <= 3): W[v][u] at
+                         // bit 2 * (u % 16) of word 2 * v + u / 16
+  const uint16_t *nb;    // LDS: back-neighbour position masks of the pattern
+  uint32_t R;
+  int Bn, a, b, k, linked, nb_all;
+};
+
+// vertices at the earlier pattern neighbours of position pos (except the
+// positions in `skip`), and the candidates for pos (in LINKED mode adjacent
+// to each of them)
+__device__ __forceinline__ void wide_masks(const WideCtx &s, unsigned long long code, int pos,
+                                           uint32_t rest, uint32_t skip, uint32_t &nbm,
+                                           uint32_t &cand) {
   cand = rest;
-  if (s.nb_all && !s.linked) {  // all-to-all: every vertex chosen so far
-    nbm = s.p->R & ~rest;
+  if (s.nb_all && !s.linked && !skip) {  // all-to-all: every vertex chosen so far
+    nbm = s.R & ~rest;
     return;
   }
   nbm = 0;
-  for (uint32_t m = s.p->nb[pos]; m; m &= m - 1) {
+  for (uint32_t m = (uint32_t)s.nb[pos] & ~skip; m; m &= m - 1) {
     const int v = vertex_at(code, __builtin_ctz(m));
     nbm |= 1u << v;
     if (s.linked) cand &= s.rows[(kWidePlanes - 1) * 32 + v];
   }
 }
 
-template <int L>
-__device__ void wide_level(WideState &s, uint32_t rest, unsigned long long code, int kp, int pos) {
-  uint32_t nbm, cand;
-  wide_masks(s, code, pos, rest, nbm, cand);
-  const int sh = 5 * (kWideK - 1 - pos);
-  if constexpr (L == 1) {
-    // every candidate is a leaf: scored as ((key + 1) << 5) | (31 - c), so
-    // one max picks the node's largest key and, among equal keys, the first
-    // leaf (keys stay below 2^27: weights <= 255, n <= 32, a, b <= 1024)
-    s.count += (unsigned long long)__popc(cand);
-    uint32_t best = 0;
-    for (uint32_t m = cand; m; m &= m - 1) {
-      const int c = __builtin_ctz(m);
-      const int v = kp + 1 + wide_term(s, c, nbm, rest);
-      const uint32_t pk = ((uint32_t)v << 5) | (31u - (uint32_t)c);
-      best = pk > best ? pk : best;
-    }
-    const int key = (int)(best >> 5) - 1;
-    if (best && key > s.bkey) {  // nodes come in lexicographic order: keep the first maximum
-      s.bkey = key;
-      s.bcode = code | ((unsigned long long)(31u - (best & 31u)) << sh);
-    }
-  } else {
-    for (uint32_t m = cand; m; m &= m - 1) {
-      const int c = __builtin_ctz(m);
-      const int kp2 = kp + wide_term(s, c, nbm, rest);
-      wide_level<L - 1>(s, rest & ~(1u << c), code | ((unsigned long long)c << sh), kp2, pos + 1);
-    }
+// Lane state of the search
+struct WideLane {
+  unsigned long long count;
+  uint32_t bpk;            // best packed leaf of the best node (0: none)
+  unsigned long long bcode;  // that node's mapping of the positions before the leaf
+  int bsh;                 // shift of the leaf position in the code
+};
+
+__device__ __forceinline__ void keep_best(WideLane &L, uint32_t pk, unsigned long long code, int sh) {
+  // nodes come in lexicographic order: a node replaces the best only with a
+  // strictly larger key
+  if (pk > (L.bpk | 31u)) {
+    L.bpk = pk;
+    L.bcode = code;
+    L.bsh = sh;
   }
 }
 
-__device__ void wide_expand(WideState &s, int L, uint32_t rest, unsigned long long code, int kp,
-                            int pos) {
-  switch (L) {
-    case 1: wide_level<1>(s, rest, code, kp, pos); break;
-    case 2: wide_level<2>(s, rest, code, kp, pos); break;
-    case 3: wide_level<3>(s, rest, code, kp, pos); break;
-    case 4: wide_level<4>(s, rest, code, kp, pos); break;
-    case 5: wide_level<5>(s, rest, code, kp, pos); break;
-    case 6: wide_level<6>(s, rest, code, kp, pos); break;
-    case 7: wide_level<7>(s, rest, code, kp, pos); break;
-    case 8: wide_level<8>(s, rest, code, kp, pos); break;
-    case 9: wide_level<9>(s, rest, code, kp, pos); break;
-    case 10: wide_level<10>(s, rest, code, kp, pos); break;
-    case 11: wide_level<11>(s, rest, code, kp, pos); break;
-    case 12: wide_level<12>(s, rest, code, kp, pos); break;
-    default: break;
+// One position left (pos = k - 1): every candidate is a leaf.
+template <int B>
+__device__ __forceinline__ void leaf_level(const WideCtx &s, WideLane &L, uint32_t rest,
+                                           unsigned long long code, int kp, int pos) {
+  uint32_t nbm, cand;
+  wide_masks(s, code, pos, rest, 0u, nbm, cand);
+  L.count += (unsigned long long)__popc(cand);
+  uint32_t best = 0;
+  for (uint32_t m = cand; m; m &= m - 1) {
+    const int c = __builtin_ctz(m);
+    const int v = kp + s.a * wsum_b<B>(s.rows, s.Bn, c, nbm) - s.b * wsum_b<B>(s.rows, s.Bn, c, rest);
+    const uint32_t pk = pack_leaf(v, c);
+    best = pk > best ? pk : best;
+  }
+  if (best) keep_best(L, best, code, 5 * (kWideK - 1 - pos));
+}
+
+// The last two positions p = k - 2 and k - 1 in ALL mode with N free
+// vertices c_0 < ... < c_{N-1} (N wave-uniform): every ordered pair
+// (c_i at p, c_j at k - 1), i != j, is a leaf, with key
+//   kp + [a Y_i - b D_i] + [a X_j - b D_j] + (a alpha + b) W[c_i][c_j]
+// where D = weight to every free vertex, Y = weight to the vertices at the
+// earlier neighbours of p, X = weight to those of k - 1 other than p, and
+// alpha = whether p neighbours k - 1 (placing c_i first takes W[c_i][c_j]
+// out of c_j's preserved weight and, if alpha, adds it to its AggBW).  The
+// per-candidate terms are tabulated once, so a leaf is one pair weight, one
+// multiply-add and a max.  Rows come in ascending c_i and each row's max
+// takes the smallest c_j among equal keys: lexicographic order.
+template <int N, int B>
+__device__ __forceinline__ void pair_table(const WideCtx &s, WideLane &L, uint32_t rest,
+                                           unsigned long long code, int kp, int p) {
+  uint32_t nbm, cand, fixm, unused;
+  wide_masks(s, code, p, rest, 0u, nbm, cand);
+  const uint32_t nbq = (uint32_t)s.nb[p + 1];
+  const int alpha = (int)((nbq >> p) & 1u);
+  if (s.nb_all)
+    fixm = s.R & ~rest;  // all-to-all: the chosen vertices neighbour both positions
+  else
+    wide_masks(s, code, p + 1, rest, 1u << p, fixm, unused);
+  int c[N], P[N], Q[N];
+  uint32_t sh2[N];  // bit offset of c_j's field in its packed-weight word
+  bool hi[N];       // c_j's field is in the second word
+  uint32_t r = rest;
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    c[j] = __builtin_ctz(r);
+    r &= r - 1;
+    sh2[j] = 2u * ((uint32_t)c[j] & 15u);
+    hi[j] = c[j] >= 16;
+    const int D = wsum_b<B>(s.rows, s.Bn, c[j], rest);
+    const int X = wsum_b<B>(s.rows, s.Bn, c[j], fixm);
+    const int Y = s.nb_all ? X : wsum_b<B>(s.rows, s.Bn, c[j], nbm);
+    P[j] = 32 * (s.a * X - s.b * D) - c[j];
+    Q[j] = s.a * Y - s.b * D;
+  }
+  const int g32 = 32 * (s.a * alpha + s.b);
+  const uint32_t base = (uint32_t)(32 * kp + 63);
+  L.count += (unsigned long long)(N * (N - 1));
+  const int sh = 5 * (kWideK - 1 - p);
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    int tb = INT_MIN;
+    if constexpr (B == 1 || B == 2) {
+      // weights <= 3: one 2-bit field of c_i's packed row per leaf
+      const uint32_t w0 = s.pw[2 * c[i]], w1 = s.pw[2 * c[i] + 1];
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        if (j == i) continue;
+        const int w = (int)(((hi[j] ? w1 : w0) >> sh2[j]) & 3u);
+        const int t = P[j] + g32 * w;
+        tb = t > tb ? t : tb;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        if (j == i) continue;
+        const int t = P[j] + g32 * wpair_b<B>(s.rows, s.Bn, c[i], c[j]);
+        tb = t > tb ? t : tb;
+      }
+    }
+    const uint32_t pk = base + (uint32_t)(32 * Q[i]) + (uint32_t)tb;
+    keep_best(L, pk, code | ((unsigned long long)c[i] << sh), sh - 5);
+  }
+}
+
+// The last two positions without the table (LINKED mode, or more free
+// vertices than the table is built for): position p, then a leaf level.
+template <int B>
+__device__ __forceinline__ void pair_plain(const WideCtx &s, WideLane &L, uint32_t rest,
+                                           unsigned long long code, int kp, int p) {
+  uint32_t nbm, cand;
+  wide_masks(s, code, p, rest, 0u, nbm, cand);
+  const int sh = 5 * (kWideK - 1 - p);
+  for (uint32_t m = cand; m; m &= m - 1) {
+    const int c = __builtin_ctz(m);
+    const int kp2 = kp + s.a * wsum_b<B>(s.rows, s.Bn, c, nbm) - s.b * wsum_b<B>(s.rows, s.Bn, c, rest);
+    leaf_level<B>(s, L, rest & ~(1u << c), code | ((unsigned long long)c << sh), kp2, p + 1);
+  }
+}
+
+template <int B>
+__device__ __forceinline__ void last_two(const WideCtx &s, WideLane &L, uint32_t rest,
+                                         unsigned long long code, int kp, int p, int nfree) {
+  if (!s.linked) {
+    switch (nfree) {
+      case 2: pair_table<2, B>(s, L, rest, code, kp, p); return;
+      case 3: pair_table<3, B>(s, L, rest, code, kp, p); return;
+      case 4: pair_table<4, B>(s, L, rest, code, kp, p); return;
+      case 5: pair_table<5, B>(s, L, rest, code, kp, p); return;
+      case 6: pair_table<6, B>(s, L, rest, code, kp, p); return;
+      case 7: pair_table<7, B>(s, L, rest, code, kp, p); return;
+      case 8: pair_table<8, B>(s, L, rest, code, kp, p); return;
+      default: break;
+    }
+  }
+  pair_plain<B>(s, L, rest, code, kp, p);
+}
+
+// Expand one prefix: positions d .. k - 3 by an iterative depth-first search
+// whose open positions live in the LDS stack (column `tid`), then the last
+// two positions in one step.
+template <int B>
+__device__ __forceinline__ void expand_prefix(const WideCtx &s, WideLane &L, uint32_t *stk_cand,
+                                              int *stk_kp, uint32_t *stk_nbm, int tid,
+                                              uint32_t rest, unsigned long long code, int kp,
+                                              int d, int F) {
+  const int k = s.k;
+  if (k - d == 1) {
+    leaf_level<B>(s, L, rest, code, kp, d);
+    return;
+  }
+  const int top = k - 2;  // position of the two-position step
+  if (d == top) {
+    last_two<B>(s, L, rest, code, kp, top, F - top);
+    return;
+  }
+  // open position d
+  {
+    uint32_t nbm, cand;
+    wide_masks(s, code, d, rest, 0u, nbm, cand);
+    stk_cand[d * kWideThreads + tid] = cand;
+    stk_kp[d * kWideThreads + tid] = kp;
+    stk_nbm[d * kWideThreads + tid] = nbm;
+  }
+  int pos = d;
+  for (;;) {
+    const uint32_t cand = stk_cand[pos * kWideThreads + tid];
+    if (cand == 0) {  // position exhausted: back to the previous one
+      if (pos == d) break;
+      --pos;
+      const int v = vertex_at(code, pos);
+      rest |= 1u << v;
+      code &= ~(31ull << (5 * (kWideK - 1 - pos)));
+      continue;
+    }
+    const int c = __builtin_ctz(cand);
+    stk_cand[pos * kWideThreads + tid] = cand & (cand - 1);
+    const uint32_t nbm = stk_nbm[pos * kWideThreads + tid];
+    const int kpc = stk_kp[pos * kWideThreads + tid] + s.a * wsum_b<B>(s.rows, s.Bn, c, nbm) -
+                    s.b * wsum_b<B>(s.rows, s.Bn, c, rest);
+    rest &= ~(1u << c);
+    code |= (unsigned long long)c << (5 * (kWideK - 1 - pos));
+    if (pos + 1 == top) {
+      last_two<B>(s, L, rest, code, kpc, top, F - top);
+      rest |= 1u << c;  // undo the choice, stay at pos
+      code &= ~(31ull << (5 * (kWideK - 1 - pos)));
+      continue;
+    }
+    ++pos;
+    uint32_t nbm2, cand2;
+    wide_masks(s, code, pos, rest, 0u, nbm2, cand2);
+    stk_cand[pos * kWideThreads + tid] = cand2;
+    stk_kp[pos * kWideThreads + tid] = kpc;
+    stk_nbm[pos * kWideThreads + tid] = nbm2;
   }
 }
 
@@ -138,41 +315,21 @@ __device__ __forceinline__ bool wide_better(int k1, unsigned long long c1, int k
   return k1 > k2 || (k1 == k2 && c1 < c2);
 }
 
-// 8 waves per SIMD (at most 64 VGPRs): on the wide workload 14.4 ms per
-// call against 14.7 at 6 and 18.5 at 4 (the compiler's own choice)
-__global__ __launch_bounds__(kWideThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_wide_search(
-    WideArgs w) {
-  __shared__ uint32_t s_rows[kWidePlanes * 32];
-  __shared__ unsigned long long s_cnt[kWideThreads / 64], s_code[kWideThreads / 64];
-  __shared__ int s_key[kWideThreads / 64];
-  const uint32_t q = w.blk_q[blockIdx.x];
-  const WidePlan *p = w.plan + q;
-  const int tid = threadIdx.x;
-  for (int i = tid; i < kWidePlanes * 32; i += blockDim.x)
-    s_rows[i] = w.rows[(size_t)p->topo * kWidePlanes * 32 + i];
-  __syncthreads();
-  WideState s;
-  s.rows = s_rows;
-  s.p = p;
-  s.B = p->B;
-  s.a = p->a;
-  s.b = p->b;
-  s.k = p->k;
-  s.linked = p->mode;
-  s.nb_all = p->nb_all;
-  s.count = 0;
-  s.bkey = -1;
-  s.bcode = ~0ull;
+template <int B>
+__device__ __forceinline__ void wide_search_items(const WidePlan *p, const WideCtx &s, WideLane &L,
+                                                  uint32_t *stk_cand, int *stk_kp, uint32_t *stk_nbm,
+                                                  int tid, uint32_t bi) {
   const int d = p->d, F = p->F;
-  const uint32_t bi = blockIdx.x - p->block0;
-  const uint32_t stride = p->nblocks * (uint32_t)blockDim.x;
-  for (uint32_t x0 = bi * blockDim.x + tid; x0 < p->items; x0 += stride) {
+  const uint32_t stride = p->nblocks * (uint32_t)kWideThreads;
+  for (uint32_t x0 = bi * kWideThreads + tid; x0 < p->items; x0 += stride) {
     // prefix x0: mixed-radix digits (radix F - t at position t, position 0
-    // most significant), each picking among the vertices still free
-    uint32_t x = x0, digits[kWideK];
+    // most significant), each picking among the vertices still free; the
+    // digits are unpacked least significant first into 5-bit fields
+    uint32_t x = x0;
+    unsigned long long digits = 0;
     for (int t = d - 1; t >= 0; --t) {
       const uint32_t m = (uint32_t)(F - t);
-      digits[t] = x % m;
+      digits |= (unsigned long long)(x % m) << (5 * t);
       x /= m;
     }
     uint32_t rest = p->R;
@@ -180,19 +337,75 @@ __global__ __launch_bounds__(kWideThreads) __attribute__((amdgpu_waves_per_eu(8)
     int kp = p->kp0;
     bool ok = true;
     for (int t = 0; t < d; ++t) {
-      const int v = select_bit32(rest, digits[t]);
+      const int v = select_bit32(rest, (uint32_t)((digits >> (5 * t)) & 31ull));
       uint32_t nbm, cand;
-      wide_masks(s, code, t, rest, nbm, cand);
+      wide_masks(s, code, t, rest, 0u, nbm, cand);
       ok = ok && ((cand >> v) & 1u);
-      kp += s.a * wsum_wide(s_rows, s.B, v, nbm) - s.b * wsum_wide(s_rows, s.B, v, rest);
+      kp += s.a * wsum_b<B>(s.rows, s.Bn, v, nbm) - s.b * wsum_b<B>(s.rows, s.Bn, v, rest);
       rest &= ~(1u << v);
       code |= (unsigned long long)v << (5 * (kWideK - 1 - t));
     }
-    if (ok) wide_expand(s, s.k - d, rest, code, kp, d);
+    if (ok) expand_prefix<B>(s, L, stk_cand, stk_kp, stk_nbm, tid, rest, code, kp, d, F);
+  }
+}
+
+// 4 waves per SIMD (at most 128 VGPRs): the LDS stack allows 4 blocks per CU
+__global__ __launch_bounds__(kWideThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_wide_search(
+    WideArgs w) {
+  __shared__ uint32_t s_rows[kWidePlanes * 32];
+  __shared__ uint32_t s_pw[64];
+  __shared__ uint16_t s_nb[kWideK];
+  __shared__ uint32_t s_cand[kWideK * kWideThreads];
+  __shared__ int s_kp[kWideK * kWideThreads];
+  __shared__ uint32_t s_nbm[kWideK * kWideThreads];
+  __shared__ unsigned long long s_cnt[kWideThreads / 64], s_code[kWideThreads / 64];
+  __shared__ int s_key[kWideThreads / 64];
+  const uint32_t q = w.blk_q[blockIdx.x];
+  const WidePlan *p = w.plan + q;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < kWidePlanes * 32; i += blockDim.x)
+    s_rows[i] = w.rows[(size_t)p->topo * kWidePlanes * 32 + i];
+  if (tid < kWideK) s_nb[tid] = p->nb[tid];
+  __syncthreads();
+  if (tid < 64) {  // packed 2-bit weights from the two low planes
+    const int v = tid >> 1, h = tid & 1;
+    const uint32_t lo = s_rows[v] >> (16 * h), hb = s_rows[32 + v] >> (16 * h);
+    uint32_t word = 0;
+    for (int u = 0; u < 16; ++u) word |= (((lo >> u) & 1u) | (((hb >> u) & 1u) << 1)) << (2 * u);
+    s_pw[tid] = word;
+  }
+  __syncthreads();
+  WideCtx s;
+  s.rows = s_rows;
+  s.pw = s_pw;
+  s.nb = s_nb;
+  s.R = p->R;
+  s.Bn = p->B;
+  s.a = p->a;
+  s.b = p->b;
+  s.k = p->k;
+  s.linked = p->mode;
+  s.nb_all = p->nb_all;
+  WideLane L;
+  L.count = 0;
+  L.bpk = 0;
+  L.bcode = 0;
+  L.bsh = 0;
+  const uint32_t bi = blockIdx.x - p->block0;
+  if (s.Bn == 1)
+    wide_search_items<1>(p, s, L, s_cand, s_kp, s_nbm, tid, bi);
+  else if (s.Bn == 2)
+    wide_search_items<2>(p, s, L, s_cand, s_kp, s_nbm, tid, bi);
+  else
+    wide_search_items<0>(p, s, L, s_cand, s_kp, s_nbm, tid, bi);
+  // this lane's best: the node's code plus its leaf vertex
+  unsigned long long cnt = L.count, code = ~0ull;
+  int key = -1;
+  if (L.bpk) {
+    key = (int)(L.bpk >> 5) - 1;
+    code = L.bcode | ((unsigned long long)(31u - (L.bpk & 31u)) << L.bsh);
   }
   // block reduction: count sum; best = largest key, then smallest mapping
-  unsigned long long cnt = s.count, code = s.bcode;
-  int key = s.bkey;
   for (int off = 32; off >= 1; off >>= 1) {
     cnt += __shfl_xor(cnt, off, 64);
     const int ok2 = __shfl_xor(key, off, 64);
