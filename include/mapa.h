@@ -535,7 +535,7 @@ typedef struct {
   double wait_p50_us, wait_p99_us;        /* queue wait percentiles                     */
   double turnaround_p50_us, turnaround_p99_us;  /* latency minus queue wait           */
   double mean_dispatch_us; /* host time to build and enqueue one device batch          */
-  double mean_gpu_us;      /* device time of one batch's kernels (HIP events)          */
+  double mean_gpu_us;      /* device time of one batch's kernels (HIP events on one batch in 8) */
   double mean_harvest_us;  /* host time to turn one batch's results into completions   */
 } mapa_serve_stats;
 

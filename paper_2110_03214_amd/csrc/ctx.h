@@ -99,6 +99,10 @@ struct mapa_ctx {
   int32_t npat = 0;
   unsigned long long *d_pat_nbtab = nullptr;  // [MAPA_MAX_PATTERNS]
   uint8_t *d_pat_k = nullptr;                 // [MAPA_MAX_PATTERNS], zero = free
+  // matching order of each registered pattern (LINKED search) and its
+  // back-neighbour table in that order
+  unsigned long long *d_pat_nbtab_ord = nullptr;  // [MAPA_MAX_PATTERNS]
+  uint32_t *d_pat_order = nullptr;                // [MAPA_MAX_PATTERNS]
 
   // servers
   std::vector<int32_t> server_topo;  // host mirror, immutable per server

@@ -87,7 +87,9 @@ __device__ __forceinline__ Plan make_plan(const mapa_query &q, int32_t nservers,
                                           const uint8_t *topo_maxw, const uint32_t *busy,
                                           const uint32_t *rows, int wpr,
                                           const unsigned long long *pat_nbtab,
-                                          const uint8_t *pat_k) {
+                                          const uint8_t *pat_k,
+                                          const unsigned long long *pat_nbtab_ord,
+                                          const uint32_t *pat_order) {
   Plan p = {};
   p.server = q.server;
   const bool registered = q.kind >= MAPA_PATTERN_BASE;
@@ -129,6 +131,19 @@ __device__ __forceinline__ Plan make_plan(const mapa_query &q, int32_t nservers,
   p.kp0 = q.metric == MAPA_METRIC_EFFBW ? 0
                                         : (int32_t)q.b * set_weight(rows + (size_t)t * kTopoWords * wpr, wpr, R);
   p.nbtab = registered ? pat_nbtab[q.kind - MAPA_PATTERN_BASE] : c_tab.nbtab[q.kind][q.k];
+  if (registered) {
+    // LINKED search of a registered pattern places its vertices in the
+    // pattern's matching order (weighted key; the tie-break stays
+    // lexicographic in the pattern's own numbering)
+    const int id = q.kind - MAPA_PATTERN_BASE;
+    p.pat = (uint8_t)id;
+    const uint32_t digits = q.k >= 8 ? 0xFFFFFFFFu : ((1u << (4 * q.k)) - 1u);
+    if (q.mode == MAPA_LINKED && q.metric == MAPA_METRIC_WEIGHTED &&
+        ((pat_order[id] ^ kIdentityOrder) & digits) != 0) {
+      p.ord = 1;
+      p.nbtab = pat_nbtab_ord[id];
+    }
+  }
   p.status = q.k > F ? kPlanNofit : kPlanOk;
   return p;
 }
@@ -192,7 +207,12 @@ struct LaneState {
   // leaf-parent node (0: none), bcode = that node's mapping of positions < k-1
   uint32_t bpk;
   uint32_t bcode;
-  // Eq. 2 (bandwidth-sensitive queries): rank table and this pattern's block
+  // Eq. 2 (bandwidth-sensitive queries): rank table and this pattern's block.
+  // LINKED search of a registered pattern in its matching order (weighted key
+  // only) reuses these words: e1 = 0 marks it and eoff holds the order word
+  // (digit p = pattern vertex at position p); the lane's best is then the
+  // u64 (bpk, bcode) = (key, inverted lexicographic code in the pattern's
+  // numbering), so equal keys are decided by that code.
   const uint16_t *erank;
   int eoff, e1;
 };
@@ -520,12 +540,12 @@ __device__ __forceinline__ bool pair_dispatch(LaneState &s, uint32_t rest, uint3
 // ((key + 1) << 4) | (15 - c), so one max() picks the largest key and, among
 // equal keys, the smallest vertex; the node then replaces the lane's best only
 // on a strictly larger key (leaves arrive in lexicographic order).
-template <int L, int WPR, bool LINKED, int KIND, int PAIR, bool PRES = true>
+template <int L, int WPR, bool LINKED, int KIND, int PAIR, bool PRES = true, bool ORD = false>
 __device__ __forceinline__ void level(LaneState &s, int kind, uint32_t rest, uint32_t code,
                                       int kp, int p, uint32_t prev, int mu, int Lrun) {
   if constexpr (L > 1) {
     if (Lrun < L) {
-      level<L - 1, WPR, LINKED, KIND, PAIR, PRES>(s, kind, rest, code, kp, p, prev, mu, Lrun);
+      level<L - 1, WPR, LINKED, KIND, PAIR, PRES, ORD>(s, kind, rest, code, kp, p, prev, mu, Lrun);
       return;
     }
   }
@@ -537,6 +557,32 @@ __device__ __forceinline__ void level(LaneState &s, int kind, uint32_t rest, uin
   const uint32_t nb2 = nbm | (nbm << 16);
   const uint32_t rest2 = rest | (rest << 16);
   const int m = LINKED ? __popc(cand) : mu;
+  if constexpr (L == 1 && LINKED && ORD) {
+    {
+      // code digit t is the vertex at position t; in the pattern's numbering
+      // it is vertex ordw[t], lexicographic digit k - 1 - ordw[t]
+      const uint32_t ordw = (uint32_t)s.eoff;
+      uint32_t lexn = 0;
+      for (int t = 0; t < p; ++t)
+        lexn |= ((code >> (4 * t)) & 15u) << (4 * (s.k - 1 - (int)((ordw >> (4 * t)) & 15u)));
+      const int shl = 4 * (s.k - 1 - (int)((ordw >> (4 * p)) & 15u));
+      s.count += (uint32_t)m;
+      unsigned long long b64 = ((unsigned long long)s.bpk << 32) | s.bcode;
+      for (int t = 0; t < m; ++t) {
+        const int c = __builtin_ctz(cand);
+        cand &= cand - 1;
+        const uint32_t *rc = s.trow + c * WPR;
+        int key = kp + __mul24(s.a, wsum<WPR>(rc, nb2));
+        if constexpr (PRES) key -= __mul24(s.b, wsum<WPR>(rc, rest2));
+        const uint32_t lex = lexn | ((uint32_t)c << shl);
+        const unsigned long long v = ((unsigned long long)(uint32_t)key << 32) | (0xFFFFFFFFu - lex);
+        b64 = v > b64 ? v : b64;
+      }
+      s.bpk = (uint32_t)(b64 >> 32);
+      s.bcode = (uint32_t)b64;
+      return;
+    }
+  }
   if constexpr (L == 1) {
     s.count += (uint32_t)m;
     // ((key + 1) << 4) | (15 - c)  ==  16*(kp + 1) + 15 + 16a*nb - 16b*dr - c
@@ -565,16 +611,17 @@ __device__ __forceinline__ void level(LaneState &s, int kind, uint32_t rest, uin
       const uint32_t *rc = s.trow + c * WPR;
       int kp2 = kp + __mul24(s.a, wsum<WPR>(rc, nb2));
       if constexpr (PRES) kp2 -= __mul24(s.b, wsum<WPR>(rc, rest2));
-      level<L - 1, WPR, LINKED, KIND, PAIR, PRES>(s, kind, rest & ~(1u << c), code | ((uint32_t)c << sh),
-                                            kp2, p + 1, (uint32_t)c, mu - 1, L - 1);
+      level<L - 1, WPR, LINKED, KIND, PAIR, PRES, ORD>(s, kind, rest & ~(1u << c),
+                                                 code | ((uint32_t)c << sh), kp2, p + 1, (uint32_t)c,
+                                                 mu - 1, L - 1);
     }
   }
 }
 
-template <int WPR, bool LINKED, int KIND, int PAIR, bool PRES = true>
+template <int WPR, bool LINKED, int KIND, int PAIR, bool PRES = true, bool ORD = false>
 __device__ __forceinline__ void expand(LaneState &s, int kind, int L, uint32_t rest,
                                        uint32_t code, int kp, int d, uint32_t prev, int mu) {
-  if (L > 0) level<kMaxK, WPR, LINKED, KIND, PAIR, PRES>(s, kind, rest, code, kp, d, prev, mu, L);
+  if (L > 0) level<kMaxK, WPR, LINKED, KIND, PAIR, PRES, ORD>(s, kind, rest, code, kp, d, prev, mu, L);
 }
 
 // Bandwidth-sensitive queries (Eq. 2, sensitive branch of Alg. 1).  The
@@ -636,7 +683,8 @@ __device__ __forceinline__ void level_eff(LaneState &s, int kind, uint32_t rest,
 // the smallest mapping; 0: no match).  trow: the topology's rows.
 template <int WPR, int PAIR>
 __device__ __forceinline__ void item_search(const Plan *pp, const uint32_t *trow, uint32_t x,
-                                            const uint16_t *erank, unsigned long long &cnt_out,
+                                            const uint16_t *erank, const uint32_t *pat_order,
+                                            unsigned long long &cnt_out,
                                             unsigned long long &best_out) {
   const bool valid = pp != nullptr;
   LaneState s;
@@ -659,6 +707,12 @@ __device__ __forceinline__ void item_search(const Plan *pp, const uint32_t *trow
     s.k = p.k;
     s.linked = p.mode;
     s.nbtab = p.nbtab;
+    // LINKED weighted search of a registered pattern: matching order (the
+    // identity when the pattern's numbering is kept) and the u64 best
+    if (p.mode == MAPA_LINKED && p.kind == kKindPattern && p.metric == MAPA_METRIC_WEIGHTED) {
+      s.e1 = 0;
+      s.eoff = (int)(p.ord ? pat_order[p.pat] : kIdentityOrder);
+    }
     metric = p.metric;
     if (metric) {
       const int E = __popcll(p.nbtab);  // pattern edges: one back-neighbour bit each
@@ -706,8 +760,14 @@ __device__ __forceinline__ void item_search(const Plan *pp, const uint32_t *trow
       else
         level_eff<kMaxK, WPR, false>(s, kind_w, rest, code, (uint32_t)kp, d, prev, fp_w, L);
     }
-  } else if (__builtin_amdgcn_readfirstlane(s.linked))
-    expand<WPR, true, -1, PAIR>(s, kind_w, L, rest, code, kp, d, prev, 0);
+  } else if (__builtin_amdgcn_readfirstlane(s.linked)) {
+    // registered patterns (bucket kind) in matching order, with the best
+    // compared by (key, lexicographic code in the pattern's numbering)
+    if (kind_w == kKindPattern)
+      expand<WPR, true, -1, PAIR, true, true>(s, kind_w, L, rest, code, kp, d, prev, 0);
+    else
+      expand<WPR, true, -1, PAIR>(s, kind_w, L, rest, code, kp, d, prev, 0);
+  }
   else if (__builtin_amdgcn_readfirstlane(L) >= fp_w - 1) {
     // The item's remaining positions leave at most one free vertex unused, so
     // every match below it preserves nothing (Eq. 3 over no pair): take the
@@ -738,7 +798,9 @@ __device__ __forceinline__ void item_search(const Plan *pp, const uint32_t *trow
     bcode = s.bcode | ((15u - (s.bpk & 15u)) << (4 * (s.k - 1)));
   }
   unsigned long long best = 0;
-  if (bkey >= 0) {
+  if (s.e1 == 0) {
+    best = ((unsigned long long)s.bpk << 32) | s.bcode;
+  } else if (bkey >= 0) {
     uint32_t lex = 0;
     for (int i = 0; i < s.k; ++i) lex = (lex << 4) | ((bcode >> (4 * i)) & 15u);
     best = ((unsigned long long)(uint32_t)bkey << 32) | (0xFFFFFFFFu - lex);
@@ -761,7 +823,7 @@ struct Outcome {
 __device__ __forceinline__ Outcome decode_best(const Plan &p, unsigned long long cnt,
                                                unsigned long long best, const uint32_t *trow,
                                                int wpr, const uint16_t *eff_rank,
-                                               const int32_t *eff_key,
+                                               const int32_t *eff_key, const uint32_t *pat_order,
                                                uint32_t *self_check_failures) {
   Outcome o;
   o.count = 0;
@@ -788,6 +850,15 @@ __device__ __forceinline__ Outcome decode_best(const Plan &p, unsigned long long
         S |= 1u << v;
         if (t < 4) map_lo = (map_lo & ~(0xFFu << (8 * t))) | (v << (8 * t));
         else map_hi = (map_hi & ~(0xFFu << (8 * (t - 4)))) | (v << (8 * (t - 4)));
+      }
+      // a plan in matching order lists back-neighbours by search position:
+      // the vertex at search position t is the mapping's entry ordw[t]
+      if (p.ord) {
+        const uint32_t ordw = pat_order[p.pat];
+        uint32_t placed = 0;
+        for (int t = 0; t < k; ++t)
+          placed |= ((phi_code >> (4 * ((ordw >> (4 * t)) & 15u))) & 15u) << (4 * t);
+        phi_code = placed;
       }
       // AggBW (Eq. 1) from the mapping: each position against its earlier
       // pattern neighbours; PreservedBW (Eq. 3): weight left inside R \ S

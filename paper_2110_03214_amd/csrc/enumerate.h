@@ -13,7 +13,7 @@ __device__ __forceinline__ void run_item(const BatchArgs &a, const uint32_t *row
   const Plan *pp = valid ? &a.plan[it.x] : nullptr;
   const uint32_t *trow = valid ? rows + (uint32_t)pp->topo * (kTopoWords * WPR) : rows;
   unsigned long long cnt, best;
-  item_search<WPR, PAIR>(pp, trow, it.y, a.eff_rank, cnt, best);
+  item_search<WPR, PAIR>(pp, trow, it.y, a.eff_rank, a.pat_order, cnt, best);
   const int qi = valid ? (int)it.x : -1;
   const int q0 = __builtin_amdgcn_readfirstlane(qi);
   const bool same = __ballot(valid && qi != q0) == 0ull;

@@ -29,7 +29,7 @@ __global__ __launch_bounds__(256) void k_fused(FusedArgs f) {
   if (tid == 0) {
     const mapa_query q = f.q[i];
     Plan p = make_plan(q, f.nservers, f.server_topo, f.topo_n, f.topo_maxw, f.busy, f.rows, WPR,
-                       f.pat_nbtab, f.pat_k);
+                       f.pat_nbtab, f.pat_k, f.pat_nbtab_ord, f.pat_order);
     if (p.status == kPlanOk) {
       int d = 0;
       while (d < p.k - 1 && c_tab.perm[p.F][d] < (unsigned long long)span) ++d;
@@ -48,7 +48,7 @@ __global__ __launch_bounds__(256) void k_fused(FusedArgs f) {
   for (uint32_t base = (uint32_t)j * blockDim.x; base < nitems; base += span) {
     const uint32_t x = base + (uint32_t)tid;
     unsigned long long c1, b1;
-    item_search<WPR, 0>(x < nitems ? &s_plan : nullptr, s_rows, x, f.eff_rank, c1, b1);
+    item_search<WPR, 0>(x < nitems ? &s_plan : nullptr, s_rows, x, f.eff_rank, f.pat_order, c1, b1);
     cnt += c1;
     best = b1 > best ? b1 : best;
   }
@@ -84,7 +84,8 @@ __global__ __launch_bounds__(256) void k_fused(FusedArgs f) {
   __syncthreads();
   if (tid == 0 && s_last) {
     const Plan p = s_plan;
-    Outcome o = decode_best(p, cnt, best, s_rows, WPR, f.eff_rank, f.eff_key, f.self_check_failures);
+    Outcome o = decode_best(p, cnt, best, s_rows, WPR, f.eff_rank, f.eff_key, f.pat_order,
+                            f.self_check_failures);
     if (p.status != kPlanInvalid && p.commit && o.status == MAPA_RES_OK) {
       atomicOr(&f.busy[p.server], o.S);
       o.handle = ((int64_t)p.server << 32) | (int64_t)o.S;

@@ -118,6 +118,8 @@ void fill_args(mapa_ctx *c, const Workspace &w, BatchArgs &a) {
   a.split_d = c->d_split;
   a.pat_nbtab = c->d_pat_nbtab;
   a.pat_k = c->d_pat_k;
+  a.pat_nbtab_ord = c->d_pat_nbtab_ord;
+  a.pat_order = c->d_pat_order;
   const int threads = c->tuning.threads_per_block;
   const size_t lds_bytes = (size_t)a.ntopo * kTopoWords * c->wpr * sizeof(uint32_t);
   a.rows_in_lds = lds_bytes <= 48 * 1024 ? 1 : 0;
@@ -185,6 +187,8 @@ int32_t enqueue_fused(mapa_ctx *c, const Workspace &w, const mapa_query *q, mapa
   f.eff_key = c->d_eff_key;
   f.pat_nbtab = c->d_pat_nbtab;
   f.pat_k = c->d_pat_k;
+  f.pat_nbtab_ord = c->d_pat_nbtab_ord;
+  f.pat_order = c->d_pat_order;
   f.self_check_failures = &w.d_ctr->self_check_failures;
   f.acc_count = w.d_acc_count;
   f.acc_best = w.d_acc_best;
@@ -618,7 +622,9 @@ int32_t mapa_ctx_create(int32_t device, size_t enum_buffer_bytes, mapa_ctx **out
   if (rc) return bail(rc);
   if (dev_alloc(&c->d_flag, 1) != hipSuccess) return bail(fail(MAPA_ERR_OOM, "flag allocation failed"));
   if (dev_alloc(&c->d_pat_nbtab, MAPA_MAX_PATTERNS) != hipSuccess ||
-      dev_alloc(&c->d_pat_k, MAPA_MAX_PATTERNS) != hipSuccess)
+      dev_alloc(&c->d_pat_k, MAPA_MAX_PATTERNS) != hipSuccess ||
+      dev_alloc(&c->d_pat_nbtab_ord, MAPA_MAX_PATTERNS) != hipSuccess ||
+      dev_alloc(&c->d_pat_order, MAPA_MAX_PATTERNS) != hipSuccess)
     return bail(fail(MAPA_ERR_OOM, "pattern table allocation failed"));
   if (hipMemset(c->d_pat_nbtab, 0, MAPA_MAX_PATTERNS * sizeof(unsigned long long)) != hipSuccess ||
       hipMemset(c->d_pat_k, 0, MAPA_MAX_PATTERNS) != hipSuccess)
@@ -643,6 +649,8 @@ int32_t mapa_ctx_destroy(mapa_ctx *c) {
     for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.exec);
     dev_free(c->d_pat_nbtab);
     dev_free(c->d_pat_k);
+    dev_free(c->d_pat_nbtab_ord);
+    dev_free(c->d_pat_order);
     dev_free(c->d_wide_rows);
     if (c->wide_buf.d) (void)hipFree(c->wide_buf.d);
     c->wide_buf.d = nullptr;
@@ -760,12 +768,53 @@ int32_t mapa_create_pattern(mapa_ctx *c, int32_t k, int32_t num_edges, const uin
   }
   unsigned long long tab = 0;
   for (int p = 0; p < k; ++p) tab |= (unsigned long long)nb[p] << (8 * p);
+  // matching order for LINKED search (Sec. 3.3: a match must keep pattern
+  // adjacency, so a candidate is pruned as soon as it misses an edge to an
+  // already placed neighbour): the vertex of largest degree first, then
+  // repeatedly the unplaced vertex with the most placed neighbours (ties:
+  // larger degree, then smaller number), so every placed vertex after the
+  // first of its connected component has an earlier neighbour
+  uint8_t adj[kMaxK] = {};
+  for (int v = 0; v < k; ++v)
+    for (int u = 0; u < v; ++u)
+      if ((nb[v] >> u) & 1u) {
+        adj[v] |= (uint8_t)(1u << u);
+        adj[u] |= (uint8_t)(1u << v);
+      }
+  uint32_t placed = 0, order = 0;
+  int pos_of[kMaxK] = {};
+  for (int p = 0; p < k; ++p) {
+    int best = -1, best_links = -1, best_deg = -1;
+    for (int v = 0; v < k; ++v) {
+      if ((placed >> v) & 1u) continue;
+      const int links = __builtin_popcount(adj[v] & placed), deg = __builtin_popcount(adj[v]);
+      if (links > best_links || (links == best_links && deg > best_deg)) {
+        best = v;
+        best_links = links;
+        best_deg = deg;
+      }
+    }
+    placed |= 1u << best;
+    order |= (uint32_t)best << (4 * p);
+    pos_of[best] = p;
+  }
+  for (int p = k; p < 8; ++p) order |= (uint32_t)p << (4 * p);  // unused digits: identity
+  unsigned long long tab_ord = 0;
+  for (int p = 0; p < k; ++p) {
+    const int v = (order >> (4 * p)) & 15;
+    uint32_t m = 0;
+    for (int u = 0; u < k; ++u)
+      if (((adj[v] >> u) & 1u) && pos_of[u] < p) m |= 1u << pos_of[u];
+    tab_ord |= (unsigned long long)m << (8 * p);
+  }
   const int id = c->npat;
   if (c->has_device) {
     if (hipSetDevice(c->device) != hipSuccess) return fail(MAPA_ERR_DEVICE, "hipSetDevice failed");
-    // the table first, then k: a slot is valid to the kernels once its k matches
+    // the tables first, then k: a slot is valid to the kernels once its k matches
     const uint8_t kk = (uint8_t)k;
     MAPA_HIPCHK(hipMemcpy(c->d_pat_nbtab + id, &tab, sizeof tab, hipMemcpyHostToDevice));
+    MAPA_HIPCHK(hipMemcpy(c->d_pat_nbtab_ord + id, &tab_ord, sizeof tab_ord, hipMemcpyHostToDevice));
+    MAPA_HIPCHK(hipMemcpy(c->d_pat_order + id, &order, sizeof order, hipMemcpyHostToDevice));
     MAPA_HIPCHK(hipMemcpy(c->d_pat_k + id, &kk, 1, hipMemcpyHostToDevice));
   }
   c->pat_nbtab[id] = tab;

@@ -56,7 +56,7 @@ __global__ __launch_bounds__(256) void k_prepare(BatchArgs a) {
   if (i < a.nq) {
     const mapa_query q = a.q[i];
     const Plan p = make_plan(q, a.nservers, a.server_topo, a.topo_n, a.topo_maxw, a.busy, a.rows,
-                             a.wpr, a.pat_nbtab, a.pat_k);
+                             a.wpr, a.pat_nbtab, a.pat_k, a.pat_nbtab_ord, a.pat_order);
     if (p.status == kPlanOk) {
       leaves = c_tab.perm[p.F][p.k];
       const uint8_t *sd = a.split_d + ((size_t)p.F * (kMaxK + 1) + p.k) * kNumSplits;
@@ -303,7 +303,7 @@ __global__ __launch_bounds__(256) void k_finalize(BatchArgs a) {
   if (i >= a.nq) return;
   const Plan p = a.plan[i];
   Outcome o = decode_best(p, a.acc_count[i], a.acc_best[i], a.rows + (size_t)p.topo * kTopoWords * a.wpr,
-                          a.wpr, a.eff_rank, a.eff_key, &a.ctr->self_check_failures);
+                          a.wpr, a.eff_rank, a.eff_key, a.pat_order, &a.ctr->self_check_failures);
   a.acc_count[i] = 0;  // leave the accumulators clean for the next batch
   a.acc_best[i] = 0;
   if (p.status != kPlanInvalid && p.commit) {

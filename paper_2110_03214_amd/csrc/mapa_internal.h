@@ -58,12 +58,19 @@ struct Plan {
   uint32_t nitems;     // prefix items of the chosen split
   uint32_t item_off;   // offset of the first item inside its bucket
   uint8_t metric;      // MAPA_METRIC_*
-  uint8_t pad[3];
+  uint8_t pat;         // registered pattern id (kind kKindPattern)
+  uint8_t ord;         // 1: positions are placed in the pattern's matching order
+  uint8_t pad;
   uint64_t nbtab;      // byte p: pattern neighbours of position p that precede it
 };
 static_assert(sizeof(Plan) == 48, "Plan layout");
 
 constexpr uint8_t kPlanOk = 0, kPlanNofit = 1, kPlanInvalid = 3;
+
+// Matching order of a registered pattern for LINKED search: the pattern
+// vertex placed at search position p is digit p (bits 4p..4p+3) of the order
+// word.  The pattern's own numbering is the identity word.
+constexpr uint32_t kIdentityOrder = 0x76543210u;
 
 // Per-batch counters (device).  Zeroed at allocation; k_layout re-zeroes what
 // the batch consumed so the next batch starts clean.
@@ -141,6 +148,8 @@ struct BatchArgs {
   const uint8_t *split_d;  // [F][k][j], see kSplitTable
   const unsigned long long *pat_nbtab;  // [MAPA_MAX_PATTERNS] registered patterns
   const uint8_t *pat_k;                 // [MAPA_MAX_PATTERNS] their k (0: free slot)
+  const unsigned long long *pat_nbtab_ord;  // [MAPA_MAX_PATTERNS] the same in matching order
+  const uint32_t *pat_order;            // [MAPA_MAX_PATTERNS] matching order, see kIdentityOrder
   // tuning
   unsigned long long lanes;  // resident enumeration lanes
   uint32_t mean_leaves;      // smallest mean item size the split may take
@@ -172,6 +181,8 @@ struct FusedArgs {
   const int32_t *eff_key;
   const unsigned long long *pat_nbtab;
   const uint8_t *pat_k;
+  const unsigned long long *pat_nbtab_ord;
+  const uint32_t *pat_order;
   uint32_t *self_check_failures;
   unsigned long long *acc_count, *acc_best;  // per query, zero on entry and exit
   uint32_t *done;                            // per query, zero on entry and exit

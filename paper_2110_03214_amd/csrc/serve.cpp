@@ -47,6 +47,9 @@ struct Slot {
   hipStream_t stream = nullptr;
   hipEvent_t done = nullptr;
   hipEvent_t g0 = nullptr, g1 = nullptr;  // timing: around the batch's kernels
+  bool timed = false;         // this batch records g0 / g1 (one batch in kGpuSample)
+  bool stream_busy = false;   // work not yet seen complete may still read the pinned buffers
+  uint64_t rel_seen = 0;      // release generation this stream is already ordered after
   mapa_query *h_q = nullptr;     // pinned
   mapa_result *h_res = nullptr;  // pinned
   int64_t *h_rel = nullptr;      // pinned, read by the release kernel in place
@@ -57,6 +60,9 @@ struct Slot {
   std::vector<const Req *> reqs;
   std::vector<uint32_t> busy_before;
 };
+
+// one device batch in kGpuSample records timing events (mean_gpu_us)
+constexpr int64_t kGpuSample = 8;
 
 // prefix items a request would need with items of at most `leaves` embeddings
 unsigned long long estimate_items(int F, int k, int leaves) {
@@ -149,7 +155,9 @@ struct ServeState {
   double dispatch_us_sum = 0, gpu_us_sum = 0, harvest_us_sum = 0;
   double last_done_us = 0;
   hipEvent_t rel_event = nullptr;
-  bool rel_event_valid = false;
+  uint64_t rel_gen = 0;        // releases enqueued so far (generation of rel_event)
+  int rel_slot = -1;           // slot whose stream recorded rel_event
+  int64_t gpu_samples = 0;
   int32_t next_batch = 0;
 
   double now_us() const {
@@ -204,7 +212,11 @@ int32_t harvest(ServeState *S, bool *did) {
     if (q != hipSuccess) return loop_fail(S, MAPA_ERR_DEVICE, "batch", q);
     const double now = S->now_us();
     float gms = 0;
-    if (hipEventElapsedTime(&gms, sl.g0, sl.g1) == hipSuccess) S->gpu_us_sum += 1e3 * gms;
+    if (sl.timed && hipEventElapsedTime(&gms, sl.g0, sl.g1) == hipSuccess) {
+      S->gpu_us_sum += 1e3 * gms;
+      ++S->gpu_samples;
+    }
+    sl.stream_busy = false;
     for (size_t i = 0; i < sl.reqs.size(); ++i) {
       const mapa_result &r = sl.h_res[i];
       const Req &rq = *sl.reqs[i];
@@ -345,8 +357,15 @@ int32_t dispatch(ServeState *S, Slot &sl, bool final_release, bool *did) {
   // 3. enqueue: releases first (ordered before this batch and, through
   //    rel_event, before every later batch on the other stream).  The slot's
   //    pinned buffers may still feed copies of a release-only dispatch.
-  SERVE_CHK(hipEventSynchronize(sl.done));
-  if (S->rel_event_valid) SERVE_CHK(hipStreamWaitEvent(sl.stream, S->rel_event, 0));
+  // Only what is needed is waited for (each HIP call costs the loop time):
+  // the slot's own earlier release-only work, and releases enqueued on the
+  // other stream since this stream last ordered itself after them.
+  if (sl.stream_busy) SERVE_CHK(hipEventSynchronize(sl.done));
+  const int self = (int)(&sl - S->slots.data());
+  if (sl.rel_seen < S->rel_gen) {
+    if (S->rel_slot != self) SERVE_CHK(hipStreamWaitEvent(sl.stream, S->rel_event, 0));
+    sl.rel_seen = S->rel_gen;
+  }
   if (!rel.empty()) {
     if (rel.size() > sl.cap_rel) {
       SERVE_CHK(hipStreamSynchronize(sl.stream));
@@ -361,7 +380,9 @@ int32_t dispatch(ServeState *S, Slot &sl, bool final_release, bool *did) {
     SERVE_CHK(launch_release_apply(sl.h_rel, 8, (int32_t)rel.size(), (int32_t)c->server_topo.size(),
                                    c->d_busy, sl.stream));
     SERVE_CHK(hipEventRecord(S->rel_event, sl.stream));
-    S->rel_event_valid = true;
+    ++S->rel_gen;
+    S->rel_slot = self;
+    sl.rel_seen = S->rel_gen;
     S->st.releases += (int64_t)rel.size();
   }
   if (!sl.reqs.empty()) {
@@ -390,7 +411,8 @@ int32_t dispatch(ServeState *S, Slot &sl, bool final_release, bool *did) {
       total += e;
     }
     int32_t rc;
-    SERVE_CHK(hipEventRecord(sl.g0, sl.stream));
+    sl.timed = S->st.batches % kGpuSample == 0;
+    if (sl.timed) SERVE_CHK(hipEventRecord(sl.g0, sl.stream));
     if (small && total <= kFusedMaxLeaves) {
       rc = enqueue_fused(c, sl.ws, sl.h_q, sl.h_res, nq, sl.stream);
       ++S->fused_batches;
@@ -407,7 +429,7 @@ int32_t dispatch(ServeState *S, Slot &sl, bool final_release, bool *did) {
       S->error_msg = "batch enqueue failed";
       return rc;
     }
-    SERVE_CHK(hipEventRecord(sl.g1, sl.stream));
+    if (sl.timed) SERVE_CHK(hipEventRecord(sl.g1, sl.stream));
     sl.batch_id = S->next_batch++;
     sl.t_dispatch = now;
     S->dispatch_us_sum += S->now_us() - now;
@@ -416,6 +438,7 @@ int32_t dispatch(ServeState *S, Slot &sl, bool final_release, bool *did) {
   }
   SERVE_CHK(hipEventRecord(sl.done, sl.stream));
   sl.active = !sl.reqs.empty();
+  sl.stream_busy = true;
   return MAPA_OK;
 }
 
@@ -677,7 +700,7 @@ int32_t mapa_serve_stop(mapa_ctx *c, mapa_serve_stats *out) {
   st.turnaround_p50_us = percentile(S->turns, 0.50);
   st.turnaround_p99_us = percentile(S->turns, 0.99);
   st.mean_dispatch_us = st.batches ? S->dispatch_us_sum / (double)st.batches : 0;
-  st.mean_gpu_us = st.batches ? S->gpu_us_sum / (double)st.batches : 0;
+  st.mean_gpu_us = S->gpu_samples ? S->gpu_us_sum / (double)S->gpu_samples : 0;
   st.mean_harvest_us = st.batches ? S->harvest_us_sum / (double)st.batches : 0;
   const int32_t err = S->error;
   const std::string msg = S->error_msg;

@@ -226,3 +226,41 @@ def test_registered_pattern_invalid_on_device(ctx, torch):
     got = dr.cpu().numpy().view(B.RESULT_DTYPE)
     assert got["status"][0] == B.RES_OK and got["count"][0] == 120
     assert got["status"][1] == B.RES_INVALID and got["status"][2] == B.RES_INVALID
+
+
+def test_linked_search_order_keeps_the_numbering_tie_break(ctx):
+    """LINKED search places a registered pattern's vertices in a matching
+    order (most constrained first, each next to a placed neighbour); the
+    selection must still be the lexicographically first maximum in the
+    caller's numbering.  Random renumberings of connected patterns on dense
+    topologies with weights 1 (many equal keys) and 1..3, against the oracle
+    on the same numbering, through the pipeline and the fused launch."""
+    rng = np.random.default_rng(77)
+    base = [(4, [(0, 1), (1, 2), (2, 3)]), (5, [(0, 4), (1, 4), (2, 4), (3, 4)]),
+            (6, [(0, 1), (1, 2), (2, 0), (3, 4), (4, 5), (5, 3), (0, 3)]),
+            (7, [(i, 6) for i in range(6)] + [(0, 1)]), (8, [(i, i + 1) for i in range(7)]),
+            (6, [(0, 1), (2, 3), (4, 5)])]  # a disconnected one: order per component
+    for _ in range(6):  # random connected graphs
+        k = int(rng.integers(4, 9))
+        perm = rng.permutation(k)
+        e = {tuple(sorted((int(perm[i]), int(perm[int(rng.integers(0, i))])))) for i in range(1, k)}
+        e |= {tuple(sorted(map(int, rng.choice(k, 2, replace=False)))) for _ in range(int(rng.integers(0, k)))}
+        base.append((k, sorted(e)))
+    pats = []
+    for k, e in base:
+        for _ in range(3):
+            sigma = rng.permutation(k)
+            pats.append((k, [(int(sigma[u]), int(sigma[v])) for u, v in e]))
+    kinds = [ctx.create_pattern(k, e) for k, e in pats]
+    topos = [random_topology(rng, 10, 1, 0.8), random_topology(rng, 11, 3, 0.7),
+             random_topology(rng, 9, 1, 1.0)]
+    wl, edges = build_queries(rng, topos, pats, kinds, 2, modes=(1,), max_leaves=3_000_000)
+    qh, _ = B.load_workload(ctx, wl)
+    print(f"[patterns] {len(qh)} LINKED queries of {len(pats)} renumbered patterns", flush=True)
+    got = ctx.query_batch(qh)
+    ref = oracle_answers(wl, edges)
+    assert_same(got, ref, qh["k"], "renumbered LINKED")
+    assert (ref["status"] == 0).sum() > 100
+    for sel in distinct_server_batches(qh["server"])[:10]:
+        assert np.array_equal(ctx.query_batch(qh[sel]), got[sel])
+    assert ctx.stats()["self_check_failures"] == 0
