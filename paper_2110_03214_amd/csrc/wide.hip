@@ -253,6 +253,112 @@ __device__ __forceinline__ void last_two(const WideCtx &s, WideLane &L, uint32_t
 // Expand one prefix: positions d .. k - 3 by an iterative depth-first search
 // whose open positions live in the LDS stack (column `tid`), then the last
 // two positions in one step.
+// The last three positions a = k - 3, p = k - 2, q = k - 1 in ALL mode
+// with N3 free vertices (weights <= 3; N3 wave-uniform).  For every choice
+// c_a at a, the last two positions are the step of pair_table on the other
+// N = N3 - 1 vertices, and its per-candidate terms differ from terms
+// tabulated once for all N3 vertices only by the weight to c_a:
+//   D_j = D3_j - W[c_j][c_a]                 (c_a is no longer free)
+//   Y_j = Yb_j + [a neighbours p] W[c_j][c_a]
+//   X_j = Xb_j + [a neighbours q] W[c_j][c_a]
+// where D3 is the weight to every free vertex, Yb the weight to p's earlier
+// neighbours before a and Xb to q's earlier neighbours before a; c_a itself
+// adds a * (weight to a's earlier neighbours) - b * D3_a.  A child's tables
+// then cost one packed-weight field and a few adds per candidate.  Choices
+// of c_a, rows and columns all come in ascending order: lexicographic.
+template <int N3>
+__device__ __forceinline__ void triple_table(const WideCtx &s, WideLane &L, uint32_t rest3,
+                                             unsigned long long code, int kp, int a) {
+  constexpr int N = N3 - 1;
+  const int p = a + 1, q = a + 2;
+  uint32_t nbm_a, nbm_pb, fix_b, unused;
+  wide_masks(s, code, a, rest3, 0u, nbm_a, unused);
+  if (s.nb_all) {
+    nbm_pb = fix_b = s.R & ~rest3;  // all-to-all: the vertices chosen before a
+  } else {
+    wide_masks(s, code, p, rest3, 1u << a, nbm_pb, unused);
+    wide_masks(s, code, q, rest3, (1u << a) | (1u << p), fix_b, unused);
+  }
+  const int by = (int)((s.nb[p] >> a) & 1u), bx = (int)((s.nb[q] >> a) & 1u);
+  const int alpha = (int)((s.nb[q] >> p) & 1u);
+  int c3[N3], D3[N3], Yb[N3], Xb[N3], KA[N3];
+  uint32_t sh3[N3];
+  bool hi3[N3];
+  uint32_t r = rest3;
+#pragma unroll
+  for (int j = 0; j < N3; ++j) {
+    c3[j] = __builtin_ctz(r);
+    r &= r - 1;
+    sh3[j] = 2u * ((uint32_t)c3[j] & 15u);
+    hi3[j] = c3[j] >= 16;
+    D3[j] = wsum_b<2>(s.rows, 2, c3[j], rest3);
+    Xb[j] = wsum_b<2>(s.rows, 2, c3[j], fix_b);
+    Yb[j] = s.nb_all ? Xb[j] : wsum_b<2>(s.rows, 2, c3[j], nbm_pb);
+    KA[j] = kp + s.a * wsum_b<2>(s.rows, 2, c3[j], nbm_a) - s.b * D3[j];
+  }
+  const int g32 = 32 * (s.a * alpha + s.b);
+  L.count += (unsigned long long)(N3 * N * (N - 1));
+  const int sha = 5 * (kWideK - 1 - a), shp = sha - 5;
+#pragma unroll
+  for (int ia = 0; ia < N3; ++ia) {
+    const int ca = c3[ia];
+    const uint32_t wa0 = s.pw[2 * ca], wa1 = s.pw[2 * ca + 1];
+    int c[N], P[N], Q[N];
+    uint32_t sh2[N];
+    bool hi[N];
+#pragma unroll
+    for (int j = 0, jj = 0; j < N3; ++j) {
+      if (j == ia) continue;
+      const int w = (int)(((hi3[j] ? wa1 : wa0) >> sh3[j]) & 3u);
+      const int D = D3[j] - w;
+      const int X = Xb[j] + bx * w;
+      const int Y = Yb[j] + by * w;
+      c[jj] = c3[j];
+      sh2[jj] = sh3[j];
+      hi[jj] = hi3[j];
+      P[jj] = 32 * (s.a * X - s.b * D) - c3[j];
+      Q[jj] = s.a * Y - s.b * D;
+      ++jj;
+    }
+    const uint32_t base = (uint32_t)(32 * KA[ia] + 63);
+    const unsigned long long code_a = code | ((unsigned long long)ca << sha);
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      const uint32_t w0 = s.pw[2 * c[i]], w1 = s.pw[2 * c[i] + 1];
+      int tb = INT_MIN;
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        if (j == i) continue;
+        const int t = P[j] + g32 * (int)(((hi[j] ? w1 : w0) >> sh2[j]) & 3u);
+        tb = t > tb ? t : tb;
+      }
+      const uint32_t pk = base + (uint32_t)(32 * Q[i]) + (uint32_t)tb;
+      keep_best(L, pk, code_a | ((unsigned long long)c[i] << shp), shp - 5);
+    }
+  }
+}
+
+// The step that finishes a prefix from position `at`: the three-position
+// table (ALL mode, weights <= 3, 3..6 free vertices; with 7 the tables
+// spilled 200 bytes per lane at the same speed) or the last two.
+template <int B>
+__device__ __forceinline__ void final_step(const WideCtx &s, WideLane &L, uint32_t rest,
+                                           unsigned long long code, int kp, int at, int nfree,
+                                           bool triple) {
+  if constexpr (B == 1 || B == 2) {
+    if (triple) {
+      switch (nfree) {
+        case 3: triple_table<3>(s, L, rest, code, kp, at); return;
+        case 4: triple_table<4>(s, L, rest, code, kp, at); return;
+        case 5: triple_table<5>(s, L, rest, code, kp, at); return;
+        case 6: triple_table<6>(s, L, rest, code, kp, at); return;
+        default: break;
+      }
+    }
+  }
+  last_two<B>(s, L, rest, code, kp, at, nfree);
+}
+
 template <int B>
 __device__ __forceinline__ void expand_prefix(const WideCtx &s, WideLane &L, uint32_t *stk_cand,
                                               int *stk_kp, uint32_t *stk_nbm, int tid,
@@ -263,9 +369,13 @@ __device__ __forceinline__ void expand_prefix(const WideCtx &s, WideLane &L, uin
     leaf_level<B>(s, L, rest, code, kp, d);
     return;
   }
-  const int top = k - 2;  // position of the two-position step
+  // position at which the finishing step takes over: k - 3 for the
+  // three-position table, else k - 2
+  const int nf3 = F - (k - 3);
+  const bool triple = (B == 1 || B == 2) && !s.linked && d <= k - 3 && nf3 >= 3 && nf3 <= 6;
+  const int top = triple ? k - 3 : k - 2;
   if (d == top) {
-    last_two<B>(s, L, rest, code, kp, top, F - top);
+    final_step<B>(s, L, rest, code, kp, top, F - top, triple);
     return;
   }
   // open position d
@@ -295,7 +405,7 @@ __device__ __forceinline__ void expand_prefix(const WideCtx &s, WideLane &L, uin
     rest &= ~(1u << c);
     code |= (unsigned long long)c << (5 * (kWideK - 1 - pos));
     if (pos + 1 == top) {
-      last_two<B>(s, L, rest, code, kpc, top, F - top);
+      final_step<B>(s, L, rest, code, kpc, top, F - top, triple);
       rest |= 1u << c;  // undo the choice, stay at pos
       code &= ~(31ull << (5 * (kWideK - 1 - pos)));
       continue;
@@ -349,9 +459,11 @@ __device__ __forceinline__ void wide_search_items(const WidePlan *p, const WideC
   }
 }
 
-// 4 waves per SIMD (at most 128 VGPRs): the LDS stack allows 4 blocks per CU
-__global__ __launch_bounds__(kWideThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_wide_search(
-    WideArgs w) {
+// Register use is left to the compiler (143 VGPRs, 3 waves per SIMD, no
+// scratch): capped at 128 VGPRs (4 waves, which the 38 KB LDS stack would
+// allow) it spilled 52 bytes per lane, 14 MB of scratch writes per call on
+// the wide workload, for 4 % less time.
+__global__ __launch_bounds__(kWideThreads) void k_wide_search(WideArgs w) {
   __shared__ uint32_t s_rows[kWidePlanes * 32];
   __shared__ uint32_t s_pw[64];
   __shared__ uint16_t s_nb[kWideK];
