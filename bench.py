@@ -67,7 +67,7 @@ PEAK_NOTE = ("78.64 T = the fp32 vector FMA lane rate (157.3 TFLOP/s / 2 flops):
 KERNEL_SOURCES = tuple("paper_2110_03214_amd/csrc/" + f for f in (
     "device.h", "enumerate.h", "enum_pair12_lds.hip", "enum_pair12_glb.hip", "enum_pair6.hip",
     "enum_plain.hip", "mapa_internal.h"))
-WIDE_SOURCES = tuple("paper_2110_03214_amd/csrc/" + f for f in ("wide.hip", "mapa_internal.h"))
+WIDE_SOURCES = tuple("paper_2110_03214_amd/csrc/" + f for f in ("wide.hip", "wide.h", "mapa_internal.h"))
 PMC_PROFILE = {2: "k_enumerate_batched_65536q_pmc.txt", 3: "k_enumerate_large_1536q_pmc.txt",
                6: "k_wide_search_wide_96q_pmc.txt"}
 

@@ -97,6 +97,8 @@ extern "C" {
                                 fields are valid, nothing was committed           */
 #define MAPA_RES_INVALID 3   /* malformed query (device-pointer batches only;
                                 host-pointer batches are rejected up front)       */
+#define MAPA_RES_REFUSED 4   /* device-pointer wide batch beyond its embedding
+                                limit: nothing was evaluated or committed         */
 
 /* ---- flags ------------------------------------------------------------------ */
 #define MAPA_DEVICE_PTRS 1u  /* array arguments are device pointers; the call is
@@ -287,17 +289,26 @@ typedef struct {
  * Sec. 5.4 discusses: servers of up to 32 accelerators and patterns
  * of up to 12 vertices (ring, all-to-all and tree of any k <= 12, or a
  * registered pattern), key a*AggBW + b*PreservedBW (MAPA_METRIC_EFFBW ->
- * MAPA_ERR_UNSUPPORTED).  Any server may be queried this way.
- *   q, res: host pointers, nq entries each; the call is synchronous and
+ * MAPA_ERR_UNSUPPORTED / MAPA_RES_INVALID).  Any server may be queried this
+ * way.
+ *   nq: 0 .. MAPA_MAX_WIDE_QUERIES (more -> MAPA_ERR_ADMISSION, nothing runs).
+ *   Host pointers (flags = 0): q, res hold nq entries each; the call is
  *     validated as mapa_query_batch's host form (k > 12 ->
- *     MAPA_ERR_UNSUPPORTED).
- *   A batch of more than 2^36 embeddings in all (summed over its queries, on
- *   their free vertices at the batch's start) is refused with
- *   MAPA_ERR_ADMISSION before anything runs.
+ *     MAPA_ERR_UNSUPPORTED) and blocks until res is filled.  A batch of more
+ *     than 2^36 embeddings in all (summed over its queries, on their free
+ *     vertices at the batch's start) is refused with MAPA_ERR_ADMISSION
+ *     before anything runs.
+ *   MAPA_DEVICE_PTRS: q and res are device pointers (16-byte aligned); the
+ *     call returns once the work is queued on hip_stream (NULL = the default
+ *     stream).  Queries are validated and planned on the device: malformed
+ *     ones get MAPA_RES_INVALID; a batch beyond the same 2^36 embeddings
+ *     gets MAPA_RES_REFUSED in every well-formed query, and nothing of it
+ *     is committed.
  * Every embedding is enumerated and scored, as on the batch path; the work
  * of each query is split over blocks by a prefix of its first positions. */
+#define MAPA_MAX_WIDE_QUERIES 16384
 int32_t mapa_query_batch_wide(mapa_ctx *ctx, const mapa_query *q, int32_t nq,
-                              mapa_result_wide *res);
+                              mapa_result_wide *res, uint32_t flags, void *hip_stream);
 
 /* Release committed allocations (Sec. 3.6: add the vertices back).
  * Handles equal to -1 are ignored.

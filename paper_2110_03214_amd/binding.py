@@ -29,7 +29,7 @@ RING, ALL_TO_ALL, TREE = 0, 1, 2
 PATTERN_BASE, MAX_PATTERNS = 16, 240
 ALL_INJECTIVE, LINKED = 0, 1
 METRIC_WEIGHTED, METRIC_EFFBW = 0, 1
-RES_OK, RES_NOFIT, RES_CONFLICT, RES_INVALID = 0, 1, 2, 3
+RES_OK, RES_NOFIT, RES_CONFLICT, RES_INVALID, RES_REFUSED = 0, 1, 2, 3, 4
 DEVICE_PTRS = 1
 USE_GRAPH = 2
 PIPELINE = 4
@@ -49,6 +49,7 @@ RESULT_WIDE_DTYPE = np.dtype([("count", np.int64), ("status", np.int32), ("key",
                               ("alloc_handle", np.int64)])
 assert RESULT_WIDE_DTYPE.itemsize == 56 and RESULT_WIDE_DTYPE.fields["alloc_handle"][1] == 48
 MAX_N_WIDE, MAX_K_WIDE = 32, 12
+MAX_WIDE_QUERIES = 16384
 NOALLOC_MAX_QUERIES = 65536
 
 
@@ -130,7 +131,7 @@ SIGNATURES = {
     "mapa_set_busy": (_I32, [_P, _I32, _P, _P, _U32, _P]),
     "mapa_get_busy": (_I32, [_P, _I32, _P, _P]),
     "mapa_query_batch": (_I32, [_P, _P, _I32, _P, _U32, _P]),
-    "mapa_query_batch_wide": (_I32, [_P, _P, _I32, _P]),
+    "mapa_query_batch_wide": (_I32, [_P, _P, _I32, _P, _U32, _P]),
     "mapa_query_batch_noalloc": (_I32, [_P, _P, _I32, _P, _P]),
     "mapa_release": (_I32, [_P, _I32, _P, _I32, _U32, _P]),
     "mapa_simulate": (_I32, [_P, _I32, _P, _P, _P, _P, _P, ctypes.POINTER(SimStats)]),
@@ -298,12 +299,19 @@ class Context:
                                              _stream(stream)), "mapa_query_batch_noalloc")
         return results
 
-    def query_batch_wide(self, queries):
+    def query_batch_wide(self, queries, results=None, stream=None):
         """Host QUERY_DTYPE array -> RESULT_WIDE_DTYPE array (servers of up to
-        32 accelerators, patterns of up to 12 vertices; blocking)."""
+        32 accelerators, patterns of up to 12 vertices; blocking), or device
+        byte tensors (nq*16 and nq*56 bytes) -> asynchronous."""
+        if hasattr(queries, "data_ptr"):
+            nq = queries.numel() * queries.element_size() // QUERY_DTYPE.itemsize
+            check(lib().mapa_query_batch_wide(self.h, _ptr(queries), int(nq), _ptr(results),
+                                              DEVICE_PTRS, _stream(stream)), "mapa_query_batch_wide")
+            return results
         q = np.ascontiguousarray(queries, dtype=QUERY_DTYPE)
-        res = np.zeros(len(q), dtype=RESULT_WIDE_DTYPE)
-        check(lib().mapa_query_batch_wide(self.h, _ptr(q), len(q), _ptr(res)), "mapa_query_batch_wide")
+        res = np.zeros(len(q), dtype=RESULT_WIDE_DTYPE) if results is None else results
+        check(lib().mapa_query_batch_wide(self.h, _ptr(q), len(q), _ptr(res), 0, None),
+              "mapa_query_batch_wide")
         return res
 
     def release(self, handles, stride: int = 8, count: int | None = None, stream=None):

@@ -86,12 +86,12 @@ struct mapa_ctx {
   int32_t *d_eff_key = nullptr;
 
   // wide path (servers of up to 32 accelerators, patterns of up to 12 vertices)
-  uint32_t *d_wide_rows = nullptr;  // [T][kWidePlanes][32], see kWidePlanes
+  uint32_t *d_wide_rows = nullptr;  // [T][9][32]: weight bit-planes 0..7 and adjacency, one row per vertex
   size_t wide_uploaded = 0, cap_wide = 0;
   struct WideBuf {
     void *d = nullptr;
     size_t cap = 0;
-  } wide_buf;  // plans, block tables and per-block partials of one wide call
+  } wide_buf;  // embedding total, plans, per-block partials (and host queries, results) of one wide call
 
   // registered patterns (append-only; slot i = kind MAPA_PATTERN_BASE + i)
   std::vector<unsigned long long> pat_nbtab;  // host mirror, back-neighbour tables

@@ -191,52 +191,6 @@ struct FusedArgs {
 
 hipError_t launch_fused(const FusedArgs &f, hipStream_t s);
 
-// ---- wide path: servers of up to 32 accelerators, patterns of up to 12
-// vertices (mapa_query_batch_wide).  Plans are built on the host; the work of
-// a query is split over blocks by a prefix of its first d positions.
-constexpr int kWideN = MAPA_MAX_N_WIDE;
-constexpr int kWideK = MAPA_MAX_K_WIDE;
-constexpr int kWidePlanes = 9;  // rows per topology: weight bit-planes 0..7, then adjacency
-constexpr int kWideThreads = 256;
-constexpr int kWideMaxBlocksPerQuery = 128;
-constexpr uint32_t kWideMinItems = 16384;             // prefix items a query is split into, at least
-constexpr unsigned long long kWideMaxLeaves = 1ull << 36;  // embeddings per call
-
-struct WidePlan {
-  uint32_t R;            // free vertex mask at the call's start
-  int32_t kp0;           // b * W(R)
-  int32_t server;
-  uint16_t nb[kWideK];   // positions j < p that neighbour position p in the pattern
-  uint8_t k, mode, d, B; // positions, match mode, prefix depth, weight bit-planes in use
-  uint8_t F, status, commit, owner;  // owner: first committing query of its server
-  int16_t a, b;
-  uint16_t topo;
-  uint16_t nb_all;       // 1: every earlier position neighbours each position (all-to-all)
-  uint32_t items;        // F!/(F-d)! prefixes
-  uint32_t block0, nblocks;
-};
-
-struct WidePartial {     // one block's share of a query
-  unsigned long long count;
-  unsigned long long code;  // best mapping, position p in bits 5*(11-p) .. +4
-  int32_t key;              // best key, -1: none
-  int32_t pad;
-};
-
-struct WideArgs {
-  const WidePlan *plan;
-  int32_t nq;
-  const uint32_t *blk_q;  // [blocks] query of each block
-  WidePartial *part;      // [blocks]
-  const uint32_t *rows;   // [T][kWidePlanes][32]: bit u of row (t, v) = bit t of W[v][u]
-  uint32_t *busy;
-  mapa_result_wide *res;
-  uint32_t *self_check_failures;
-};
-
-hipError_t launch_wide_search(const WideArgs &w, int32_t blocks, hipStream_t s);
-hipError_t launch_wide_finalize(const WideArgs &w, hipStream_t s);
-
 // per translation unit: constant-table upload, enumeration launch and occupancy
 hipError_t upload_tables_front(const Tables &t);
 hipError_t upload_tables_fused(const Tables &t);

@@ -1,14 +1,14 @@
-// Host side of mapa_query_batch_wide: validation, weight bit-planes of every
-// topology as 32-bit rows, per-query plans (free set, b*W(R), pattern
-// neighbour masks, prefix depth, block share), the launches and the copy back.
+// Host side of mapa_query_batch_wide: validation and admission of host
+// batches, weight bit-planes of every topology as 32-bit rows, the call's
+// device buffer, the launches (plan, search, finalize) and the copies.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cstring>
-#include <unordered_map>
 #include <vector>
 
 #include "ctx.h"
+#include "wide.h"
 
 namespace mapa {
 
@@ -76,26 +76,6 @@ int32_t validate_wide(const mapa_ctx *c, const mapa_query &q, int32_t i) {
   return MAPA_OK;
 }
 
-// earlier pattern neighbours of each position (bit j of nb[p]: j < p neighbours p)
-void wide_neighbours(const mapa_ctx *c, int kind, int k, uint16_t *nb) {
-  for (int p = 0; p < kWideK; ++p) nb[p] = 0;
-  if (kind >= MAPA_PATTERN_BASE) {
-    const unsigned long long tab = c->pat_nbtab[kind - MAPA_PATTERN_BASE];
-    for (int p = 0; p < k; ++p) nb[p] = (uint16_t)((tab >> (8 * p)) & 0xFFu);
-    return;
-  }
-  for (int p = 1; p < k; ++p) {
-    if (kind == MAPA_RING) {
-      nb[p] = (uint16_t)(1u << (p - 1));
-      if (p == k - 1 && k >= 3) nb[p] |= 1u;
-    } else if (kind == MAPA_ALL_TO_ALL) {
-      nb[p] = (uint16_t)((1u << p) - 1u);
-    } else {
-      nb[p] = (uint16_t)(1u << ((p - 1) / 2));
-    }
-  }
-}
-
 }  // namespace
 
 }  // namespace mapa
@@ -103,85 +83,48 @@ void wide_neighbours(const mapa_ctx *c, int kind, int k, uint16_t *nb) {
 using namespace mapa;
 
 extern "C" int32_t mapa_query_batch_wide(mapa_ctx *c, const mapa_query *q, int32_t nq,
-                                         mapa_result_wide *res) {
+                                         mapa_result_wide *res, uint32_t flags, void *stream) {
   if (!c) return fail(MAPA_ERR_INVALID_ARG, "ctx is NULL");
   if (c->serve) return fail(MAPA_ERR_STATE, "mapa_query_batch_wide: the serving loop owns the context");
   if (nq < 0) return fail(MAPA_ERR_INVALID_ARG, "nq=%d < 0", nq);
+  if (nq > kWideMaxQueries)
+    return fail(MAPA_ERR_ADMISSION, "wide batch of %d queries exceeds %d", nq, kWideMaxQueries);
   if (nq > 0 && (!q || !res)) return fail(MAPA_ERR_INVALID_ARG, "queries or results NULL");
-  for (int32_t i = 0; i < nq; ++i)
-    if (int32_t rc = validate_wide(c, q[i], i)) return rc;
+  const bool dev = flags & MAPA_DEVICE_PTRS;
+  if (!dev)
+    for (int32_t i = 0; i < nq; ++i)
+      if (int32_t rc = validate_wide(c, q[i], i)) return rc;
   if (!c->has_device) return fail(MAPA_ERR_NO_DEVICE, "context has no device");
   if (nq == 0) return MAPA_OK;
+  if (c->server_topo.empty()) return fail(MAPA_ERR_UNKNOWN_SERVER, "no servers created");
   if (hipSetDevice(c->device) != hipSuccess) return fail(MAPA_ERR_DEVICE, "hipSetDevice failed");
-  if (int32_t rc = sync_ctx(c)) return rc;
-  if (int32_t rc = upload_wide_rows(c)) return rc;
-
-  // busy masks at the call's start
-  std::vector<uint32_t> busy(c->server_topo.size());
-  if (!busy.empty())
-    MAPA_HIPCHK(hipMemcpy(busy.data(), c->d_busy, busy.size() * sizeof(uint32_t), hipMemcpyDeviceToHost));
-
-  std::vector<WidePlan> plans((size_t)nq);
-  std::vector<uint32_t> blk_q;
-  std::unordered_map<int32_t, int32_t> first_commit;  // server -> first committing query
-  unsigned long long leaves = 0;
-  for (int32_t i = 0; i < nq; ++i) {
-    const mapa_query &qq = q[i];
-    WidePlan &p = plans[(size_t)i];
-    std::memset(&p, 0, sizeof p);
-    const int t = c->server_topo[qq.server];
-    const int n = c->topo_n[t];
-    const uint32_t all = n >= 32 ? 0xFFFFFFFFu : (1u << n) - 1u;
-    const uint32_t R = ~busy[qq.server] & all;
-    const int F = __builtin_popcount(R);
-    const uint8_t *W = c->wide_W[t].data();
-    int WR = 0;
-    for (int u = 0; u < n; ++u)
-      for (int v = u + 1; v < n; ++v)
-        if (((R >> u) & 1u) && ((R >> v) & 1u)) WR += W[u * kWideN + v];
-    int B = 1;
-    while (B < 8 && (c->topo_maxw[t] >> B)) ++B;
-    p.R = R;
-    p.kp0 = qq.b * WR;
-    p.server = qq.server;
-    wide_neighbours(c, qq.kind, qq.k, p.nb);
-    p.nb_all = qq.kind == MAPA_ALL_TO_ALL ? 1 : 0;
-    p.k = qq.k;
-    p.mode = qq.mode;
-    p.B = (uint8_t)B;
-    p.F = (uint8_t)F;
-    p.a = qq.a;
-    p.b = qq.b;
-    p.topo = (uint16_t)t;
-    p.commit = qq.commit;
-    if (qq.commit && first_commit.emplace(qq.server, i).second) p.owner = 1;
-    if (qq.k > F) {
-      p.status = kPlanNofit;
-      continue;
-    }
-    p.status = kPlanOk;
-    leaves += perm_wide(F, qq.k);
-    if (leaves > kWideMaxLeaves)
-      return fail(MAPA_ERR_ADMISSION, "wide batch exceeds %llu embeddings at query %d", kWideMaxLeaves, i);
-    int d = 0;
-    while (d < qq.k - 1 && perm_wide(F, d) < kWideMinItems) ++d;
-    p.d = (uint8_t)d;
-    p.items = (uint32_t)perm_wide(F, d);
-    const unsigned long long want = (p.items + kWideThreads - 1) / kWideThreads;
-    p.nblocks = (uint32_t)std::min<unsigned long long>(std::max<unsigned long long>(want, 1),
-                                                       kWideMaxBlocksPerQuery);
-    p.block0 = (uint32_t)blk_q.size();
-    blk_q.insert(blk_q.end(), p.nblocks, (uint32_t)i);
+  if (!dev || c->wide_uploaded != c->wide_W.size()) {
+    if (int32_t rc = sync_ctx(c)) return rc;
+    if (int32_t rc = upload_wide_rows(c)) return rc;
   }
-  const size_t blocks = blk_q.size();
+  if (!dev) {
+    // admission: the embeddings of the whole call, on the free sets at its start
+    std::vector<uint32_t> busy(c->server_topo.size());
+    MAPA_HIPCHK(hipMemcpy(busy.data(), c->d_busy, busy.size() * sizeof(uint32_t), hipMemcpyDeviceToHost));
+    unsigned long long leaves = 0;
+    for (int32_t i = 0; i < nq; ++i) {
+      const int n = c->topo_n[c->server_topo[q[i].server]];
+      const uint32_t all = n >= 32 ? 0xFFFFFFFFu : (1u << n) - 1u;
+      leaves += perm_wide(__builtin_popcount(~busy[q[i].server] & all), q[i].k);
+      if (leaves > kWideMaxLeaves)
+        return fail(MAPA_ERR_ADMISSION, "wide batch exceeds %llu embeddings at query %d", kWideMaxLeaves, i);
+    }
+  }
 
-  // one device buffer: plans | block table | partials | results
+  // one device buffer: embedding total | plans | partials | (host form) queries | results
   auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
-  const size_t o_plan = 0, o_blk = align(o_plan + plans.size() * sizeof(WidePlan));
-  const size_t o_part = align(o_blk + blocks * sizeof(uint32_t));
-  const size_t o_res = align(o_part + blocks * sizeof(WidePartial));
-  const size_t bytes = align(o_res + (size_t)nq * sizeof(mapa_result_wide));
+  const size_t o_plan = 256;
+  const size_t o_part = align(o_plan + (size_t)nq * sizeof(WidePlan));
+  const size_t o_q = align(o_part + (size_t)nq * kWideMaxBlocksPerQuery * sizeof(WidePartial));
+  const size_t o_res = align(o_q + (dev ? 0 : (size_t)nq * sizeof(mapa_query)));
+  const size_t bytes = align(o_res + (dev ? 0 : (size_t)nq * sizeof(mapa_result_wide)));
   if (bytes > c->wide_buf.cap) {
+    if (int32_t rc = sync_ctx(c)) return rc;  // earlier calls may still use the old buffer
     if (c->wide_buf.d) (void)hipFree(c->wide_buf.d);
     c->wide_buf.d = nullptr;
     c->wide_buf.cap = 0;
@@ -191,30 +134,40 @@ extern "C" int32_t mapa_query_batch_wide(mapa_ctx *c, const mapa_query *q, int32
   }
   char *base = static_cast<char *>(c->wide_buf.d);
   WideArgs w;
-  w.plan = reinterpret_cast<WidePlan *>(base + o_plan);
+  w.q = dev ? q : reinterpret_cast<const mapa_query *>(base + o_q);
   w.nq = nq;
-  w.blk_q = reinterpret_cast<uint32_t *>(base + o_blk);
+  w.plan = reinterpret_cast<WidePlan *>(base + o_plan);
   w.part = reinterpret_cast<WidePartial *>(base + o_part);
   w.rows = c->d_wide_rows;
+  w.server_topo = c->d_server_topo;
+  w.topo_n = c->d_topo_n;
+  w.topo_maxw = c->d_topo_maxw;
+  w.nservers = (int32_t)c->server_topo.size();
+  w.ntopo_wide = (int32_t)c->wide_uploaded;
+  w.pat_nbtab = c->d_pat_nbtab;
+  w.pat_k = c->d_pat_k;
   w.busy = c->d_busy;
-  w.res = reinterpret_cast<mapa_result_wide *>(base + o_res);
+  w.commit_slot = c->d_commit_slot;
+  w.res = dev ? res : reinterpret_cast<mapa_result_wide *>(base + o_res);
   w.self_check_failures = &c->ws.d_ctr->self_check_failures;
-  hipStream_t s = c->internal;
-  MAPA_HIPCHK(hipMemcpyAsync(const_cast<WidePlan *>(w.plan), plans.data(), plans.size() * sizeof(WidePlan),
-                             hipMemcpyHostToDevice, s));
-  if (blocks)
-    MAPA_HIPCHK(hipMemcpyAsync(const_cast<uint32_t *>(w.blk_q), blk_q.data(), blocks * sizeof(uint32_t),
+  w.total = reinterpret_cast<unsigned long long *>(base);
+  hipStream_t s = dev ? reinterpret_cast<hipStream_t>(stream) : c->internal;
+  MAPA_HIPCHK(hipStreamWaitEvent(s, c->last, 0));
+  if (!dev)
+    MAPA_HIPCHK(hipMemcpyAsync(const_cast<mapa_query *>(w.q), q, (size_t)nq * sizeof(mapa_query),
                                hipMemcpyHostToDevice, s));
+  MAPA_HIPCHK(launch_wide_plan(w, s));
   ProfEvents ev{};
-  if (c->profile && blocks)  // the search kernel's time counts as enumeration time
+  if (c->profile)  // the search kernel's time counts as enumeration time
     if (int32_t rc2 = prof_start(c, s, ev)) return rc2;
-  MAPA_HIPCHK(launch_wide_search(w, (int32_t)blocks, s));
-  if (c->profile && blocks)
+  MAPA_HIPCHK(launch_wide_search(w, s));
+  if (c->profile)
     if (int32_t rc2 = prof_stop(c, s, ev)) return rc2;
   MAPA_HIPCHK(launch_wide_finalize(w, s));
-  MAPA_HIPCHK(hipMemcpyAsync(res, w.res, (size_t)nq * sizeof(mapa_result_wide), hipMemcpyDeviceToHost, s));
+  if (!dev)
+    MAPA_HIPCHK(hipMemcpyAsync(res, w.res, (size_t)nq * sizeof(mapa_result_wide), hipMemcpyDeviceToHost, s));
   MAPA_HIPCHK(hipEventRecord(c->last, s));
-  MAPA_HIPCHK(hipStreamSynchronize(s));
+  if (!dev) MAPA_HIPCHK(hipStreamSynchronize(s));
   c->batches += 1;
   return MAPA_OK;
 }

@@ -6,9 +6,14 @@
 //   key = b*W(R) + sum_p [ a*w(phi_p, earlier neighbours) - b*w(phi_p, still free) ],
 // the first maximum in lexicographic order (Alg. 1 with strict improvement).
 //
-// k_wide_search: a block works on one query; its threads take the query's
+// k_wide_plan: per query, on the device (so the call also takes device
+// pointers): validation, the free set R from the busy mask at the call's
+// start, b*W(R), the pattern's neighbour masks, the prefix depth and block
+// share, the server's commit claim, and the call's embedding total.
+// k_wide_search: every query owns kWideMaxBlocksPerQuery consecutive blocks
+// of the grid, of which its plan's share search; its threads take the query's
 // prefixes of depth d (F!/(F-d)! of them, in lexicographic order of their
-// index) in a block-strided loop and expand each depth-first, keeping a count
+// index) in a loop strided over the share and expand each depth-first, keeping a count
 // and their best (key, mapping).  The search is iterative: each thread keeps
 // the candidates left, the running key and the neighbour mask of every open
 // position in an LDS stack, so nothing spills and no call frames are built.
@@ -21,7 +26,7 @@
 // The block reduces to one partial.
 // k_wide_finalize: per query, the partials of its blocks, the mapping, a
 // recomputation of AggBW and PreservedBW from it (self-check) and the commit.
-#include "mapa_internal.h"
+#include "wide.h"
 
 namespace mapa {
 
@@ -459,6 +464,100 @@ __device__ __forceinline__ void wide_search_items(const WidePlan *p, const WideC
   }
 }
 
+// Plan of one query from the busy mask in memory (the call's start): the
+// checks of the host form (malformed -> kPlanInvalid), free set R,
+// b * W(R), the pattern's earlier-neighbour masks, weight bit-planes in use,
+// prefix depth (the smallest with at least kWideMinItems prefixes), the
+// blocks that have items, and the claim of the server's commit (the first
+// committing query of the batch, array order).
+__global__ void k_wide_clear(unsigned long long *total) {
+  if (threadIdx.x == 0) *total = 0;
+}
+
+__global__ __launch_bounds__(256) void k_wide_plan(WideArgs w) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= w.nq) return;
+  const mapa_query q = w.q[i];
+  WidePlan p;
+  p.R = 0;
+  p.kp0 = 0;
+  p.server = q.server;
+  for (int t = 0; t < kWideK; ++t) p.nb[t] = 0;
+  p.k = q.k;
+  p.mode = q.mode;
+  p.d = 0;
+  p.B = 1;
+  p.F = 0;
+  p.commit = q.commit;
+  p.nb_all = q.kind == MAPA_ALL_TO_ALL;
+  p.a = q.a;
+  p.b = q.b;
+  p.topo = 0;
+  p.pad = 0;
+  p.items = 0;
+  p.nblocks = 0;
+  const int pid = (int)q.kind - MAPA_PATTERN_BASE;  // registered pattern id
+  const bool registered = pid >= 0 && pid < MAPA_MAX_PATTERNS;
+  const bool ok = q.server >= 0 && q.server < w.nservers && q.k >= 1 && q.k <= kWideK &&
+                  (q.kind <= MAPA_TREE || (registered && w.pat_k[pid] == q.k)) &&
+                  q.mode <= 1 && q.commit <= 1 && q.a >= 0 && q.a <= MAPA_MAX_AB && q.b >= 0 &&
+                  q.b <= MAPA_MAX_AB && q.metric == MAPA_METRIC_WEIGHTED &&
+                  w.server_topo[q.server] < w.ntopo_wide;
+  if (!ok) {
+    p.status = kPlanInvalid;
+    w.plan[i] = p;
+    return;
+  }
+  const int t = w.server_topo[q.server];
+  const int n = w.topo_n[t];
+  const uint32_t R = ~w.busy[q.server] & (n >= 32 ? 0xFFFFFFFFu : ((1u << n) - 1u));
+  const int F = __popc(R);
+  int B = 1;
+  while (B < 8 && (w.topo_maxw[t] >> B)) ++B;
+  const uint32_t *rows = w.rows + (size_t)t * kWidePlanes * 32;
+  int wr2 = 0;  // twice W(R): every pair counted from both ends
+  for (uint32_t m = R; m; m &= m - 1) wr2 += wsum_b<0>(rows, B, __builtin_ctz(m), R);
+  p.topo = (uint16_t)t;
+  p.R = R;
+  p.F = (uint8_t)F;
+  p.B = (uint8_t)B;
+  p.kp0 = q.b * (wr2 / 2);
+  if (registered) {
+    const unsigned long long tab = w.pat_nbtab[pid];
+    for (int j = 0; j < q.k; ++j) p.nb[j] = (uint16_t)((tab >> (8 * j)) & 0xFFu);
+  } else {
+    for (int j = 1; j < q.k; ++j) {
+      if (q.kind == MAPA_RING)
+        p.nb[j] = (uint16_t)((1u << (j - 1)) | (j == q.k - 1 && q.k >= 3 ? 1u : 0u));
+      else if (q.kind == MAPA_ALL_TO_ALL)
+        p.nb[j] = (uint16_t)((1u << j) - 1u);
+      else
+        p.nb[j] = (uint16_t)(1u << ((j - 1) / 2));
+    }
+  }
+  if (q.commit) atomicMin(&w.commit_slot[q.server], (unsigned long long)i);
+  if (q.k > F) {
+    p.status = kPlanNofit;
+    w.plan[i] = p;
+    return;
+  }
+  p.status = kPlanOk;
+  unsigned long long leaves = 1;  // F!/(F-k)! <= 32!/20! < 2^54
+  for (int j = 0; j < q.k; ++j) leaves *= (unsigned long long)(F - j);
+  atomicAdd(w.total, leaves < 2 * kWideMaxLeaves ? leaves : 2 * kWideMaxLeaves);
+  int d = 0;
+  unsigned long long items = 1;  // F!/(F-d)!
+  while (d < q.k - 1 && items < kWideMinItems) {
+    items *= (unsigned long long)(F - d);
+    ++d;
+  }
+  p.d = (uint8_t)d;
+  p.items = (uint32_t)items;
+  const unsigned long long want = (items + kWideThreads - 1) / kWideThreads;
+  p.nblocks = (uint32_t)(want < 1 ? 1 : want > kWideMaxBlocksPerQuery ? kWideMaxBlocksPerQuery : want);
+  w.plan[i] = p;
+}
+
 // Register use is left to the compiler (143 VGPRs, 3 waves per SIMD, no
 // scratch): capped at 128 VGPRs (4 waves, which the 38 KB LDS stack would
 // allow) it spilled 52 bytes per lane, 14 MB of scratch writes per call on
@@ -472,9 +571,23 @@ __global__ __launch_bounds__(kWideThreads) void k_wide_search(WideArgs w) {
   __shared__ uint32_t s_nbm[kWideK * kWideThreads];
   __shared__ unsigned long long s_cnt[kWideThreads / 64], s_code[kWideThreads / 64];
   __shared__ int s_key[kWideThreads / 64];
-  const uint32_t q = w.blk_q[blockIdx.x];
+  // block b of query q's share: b = blockIdx.x % kWideMaxBlocksPerQuery
+  const uint32_t q = blockIdx.x / kWideMaxBlocksPerQuery;
+  const uint32_t bi = blockIdx.x % kWideMaxBlocksPerQuery;
   const WidePlan *p = w.plan + q;
   const int tid = threadIdx.x;
+  // nothing to search (or the call is over its embedding limit): an empty partial
+  if (p->status != kPlanOk || bi >= p->nblocks || *w.total > kWideMaxLeaves) {
+    if (tid == 0) {
+      WidePartial r;
+      r.count = 0;
+      r.code = ~0ull;
+      r.key = -1;
+      r.pad = 0;
+      w.part[blockIdx.x] = r;
+    }
+    return;
+  }
   for (int i = tid; i < kWidePlanes * 32; i += blockDim.x)
     s_rows[i] = w.rows[(size_t)p->topo * kWidePlanes * 32 + i];
   if (tid < kWideK) s_nb[tid] = p->nb[tid];
@@ -503,7 +616,6 @@ __global__ __launch_bounds__(kWideThreads) void k_wide_search(WideArgs w) {
   L.bpk = 0;
   L.bcode = 0;
   L.bsh = 0;
-  const uint32_t bi = blockIdx.x - p->block0;
   if (s.Bn == 1)
     wide_search_items<1>(p, s, L, s_cand, s_kp, s_nbm, tid, bi);
   else if (s.Bn == 2)
@@ -565,11 +677,12 @@ __global__ __launch_bounds__(256) void k_wide_finalize(WideArgs w) {
   for (int i = 0; i < 16; ++i) r.mapping[i] = 0xFF;
   r.reserved = 0;
   r.alloc_handle = -1;
-  if (p.status == kPlanOk) {
+  const bool refused = *w.total > kWideMaxLeaves;
+  if (p.status == kPlanOk && !refused) {
     unsigned long long cnt = 0, code = ~0ull;
     int key = -1;
     for (uint32_t b = 0; b < p.nblocks; ++b) {
-      const WidePartial &pt = w.part[p.block0 + b];
+      const WidePartial &pt = w.part[(size_t)q * kWideMaxBlocksPerQuery + b];
       cnt += pt.count;
       if (wide_better(pt.key, pt.code, key, code)) {
         key = pt.key;
@@ -597,21 +710,40 @@ __global__ __launch_bounds__(256) void k_wide_finalize(WideArgs w) {
       r.pres = pres2 / 2;
       r.vertex_mask = S;
       if ((int)p.a * agg + (int)p.b * r.pres != key) atomicAdd(w.self_check_failures, 1u);
-      if (p.commit) {
-        if (p.owner) {
-          w.busy[p.server] |= S;
-          r.alloc_handle = ((int64_t)p.server << 32) | (int64_t)S;
-        } else {
-          r.status = MAPA_RES_CONFLICT;
-        }
+    }
+  }
+  if (p.status == kPlanInvalid) {
+    r.status = MAPA_RES_INVALID;
+  } else if (refused) {  // nothing evaluated; a claim is only given back
+    r.status = MAPA_RES_REFUSED;
+    if (p.commit && w.commit_slot[p.server] == (unsigned long long)q) w.commit_slot[p.server] = ~0ull;
+  } else if (p.commit) {
+    // the server's first committing query commits (if it found a match) and
+    // frees the claim; later committing queries of the server conflict
+    if (w.commit_slot[p.server] == (unsigned long long)q) {
+      if (r.status == MAPA_RES_OK) {
+        atomicOr(&w.busy[p.server], r.vertex_mask);
+        r.alloc_handle = ((int64_t)p.server << 32) | (int64_t)r.vertex_mask;
       }
+      w.commit_slot[p.server] = ~0ull;
+    } else if (r.status == MAPA_RES_OK) {
+      r.status = MAPA_RES_CONFLICT;
     }
   }
   w.res[q] = r;
 }
 
-hipError_t launch_wide_search(const WideArgs &w, int32_t blocks, hipStream_t s) {
-  if (blocks > 0) hipLaunchKernelGGL(k_wide_search, dim3(blocks), dim3(kWideThreads), 0, s, w);
+hipError_t launch_wide_plan(const WideArgs &w, hipStream_t s) {
+  if (w.nq <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_wide_clear, dim3(1), dim3(64), 0, s, w.total);
+  hipLaunchKernelGGL(k_wide_plan, dim3((w.nq + 255) / 256), dim3(256), 0, s, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_wide_search(const WideArgs &w, hipStream_t s) {
+  if (w.nq > 0)
+    hipLaunchKernelGGL(k_wide_search, dim3((unsigned)w.nq * kWideMaxBlocksPerQuery), dim3(kWideThreads), 0,
+                       s, w);
   return hipGetLastError();
 }
 

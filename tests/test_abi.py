@@ -176,6 +176,9 @@ def test_wide_queries_validation(vctx):
     kind = vctx.create_pattern(5, [(0, 4), (1, 4)])
     assert code_of(lambda: vctx.query_batch_wide(B.pack_queries([0], [kind], [5]))) == B.ERR_NO_DEVICE
     assert code_of(lambda: vctx.query_batch_wide(B.pack_queries([0], [kind], [6]))) == B.ERR_INVALID_ARG
+    # more than MAPA_MAX_WIDE_QUERIES queries: refused before validation
+    many = B.pack_queries(np.zeros(B.MAX_WIDE_QUERIES + 1, np.int32), 0, 0)
+    assert code_of(lambda: vctx.query_batch_wide(many)) == B.ERR_ADMISSION
 
 
 def test_release_validation(vctx):

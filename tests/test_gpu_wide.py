@@ -1,7 +1,8 @@
 """GPU parity for the wide path (mapa_query_batch_wide): servers of 17..32
 accelerators and patterns of 9..12 vertices against the oracle bit for bit,
 the batch path's answers on servers both paths take, the five-cube's hand
-counts, registered patterns, and the batch commit rule."""
+counts, registered patterns, the batch commit rule, the device-pointer form
+against the host form, and the embedding limit."""
 import math
 import os
 
@@ -245,3 +246,108 @@ def test_wide_config_full_against_stored_oracle_results(ctx):
     # a second call on the same state answers the same (nothing committed)
     again = ctx.query_batch_wide(q)
     assert np.array_equal(again, got)
+
+
+def wide_on_device(ctx, torch, q):
+    """The device-pointer form on torch's current stream, results copied back."""
+    dq = torch.from_numpy(np.ascontiguousarray(q).view(np.uint8).copy()).to("cuda")
+    dr = torch.full((len(q) * B.RESULT_WIDE_DTYPE.itemsize,), 0xAB, dtype=torch.uint8, device="cuda")
+    ctx.query_batch_wide(dq, dr, stream=torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    return dr.cpu().numpy().view(B.RESULT_WIDE_DTYPE), dr
+
+
+def test_wide_device_pointers_equal_host_form(ctx, torch):
+    """Queries and results in device memory, planned on the device: every
+    byte of every result equals the host form's, on the wide benchmark
+    workload and on mixed 17..32-vertex servers with every kind and k."""
+    wl = synth.config6()
+    q, _ = B.load_workload(ctx, wl)
+    host = ctx.query_batch_wide(q)
+    dev, _ = wide_on_device(ctx, torch, q)
+    assert dev.tobytes() == host.tobytes()
+    rng = np.random.default_rng(77)
+    topos = [random_topology(rng, n, w, 0.5) for n, w in ((17, 1), (24, 2), (32, 255))]
+    busy = [busy_leaving(rng, W.shape[0], F) for W, F in zip(topos, (9, 7, 6))]
+    ids = ctx.load_servers(topos, np.arange(3, dtype=np.int32))
+    ctx.set_busy(ids, busy)
+    cols = [(s, kind, k, mode) for s in range(3) for kind in range(3) for k in range(1, 10)
+            for mode in (0, 1)]
+    srv, kind, k, mode = (np.array(c) for c in zip(*cols))
+    q2 = B.pack_queries(ids[srv], kind, k, mode, a=rng.integers(0, 5, len(cols)), b=1)
+    host2 = ctx.query_batch_wide(q2)
+    dev2, _ = wide_on_device(ctx, torch, q2)
+    assert dev2.tobytes() == host2.tobytes()
+    assert (host2["status"] == B.RES_OK).sum() > 50
+
+
+def test_wide_device_pointers_malformed_queries(ctx, torch):
+    """Malformed queries are answered with MAPA_RES_INVALID on the device
+    (no mapping, no handle); the well-formed rest of the batch answers as
+    the host form does without them."""
+    rng = np.random.default_rng(13)
+    W = random_topology(rng, 24, 3, 0.6)
+    ids = ctx.load_servers([W], np.zeros(1, np.int32))
+    ctx.set_busy(ids, [busy_leaving(rng, 24, 8)])
+    q = B.pack_queries(ids[[0] * 14], [0, 1, 2] * 4 + [0, 1], [3, 4, 5, 6] * 3 + [2, 7])
+    bad = {1: ("k", 0), 2: ("k", 13), 4: ("server", -1), 5: ("server", 99), 6: ("metric", 1),
+           7: ("metric", 3), 8: ("kind", 5), 9: ("kind", B.PATTERN_BASE + 7), 10: ("mode", 2),
+           11: ("commit", 2), 12: ("a", -1), 13: ("b", 1025)}
+    for i, (f, v) in bad.items():
+        q[f][i] = v
+    dev, _ = wide_on_device(ctx, torch, q)
+    idx = np.array(sorted(bad))
+    assert (dev["status"][idx] == B.RES_INVALID).all()
+    assert (dev["alloc_handle"][idx] == -1).all() and (dev["mapping"][idx] == 0xFF).all()
+    good = np.array([i for i in range(len(q)) if i not in bad])
+    host = ctx.query_batch_wide(q[good])
+    assert dev[good].tobytes() == host.tobytes()
+
+
+def test_wide_device_pointers_commit_and_release(ctx, torch):
+    """The batch commit rule through device pointers, handles released from
+    the device result array in place (alloc_handle at byte 48 of 56)."""
+    rng = np.random.default_rng(6)
+    W = random_topology(rng, 30, 3, 0.6)
+    ids = ctx.load_servers([W, W], np.zeros(2, np.int32))
+    ctx.set_busy(ids, [busy_leaving(rng, 30, 10), busy_leaving(rng, 30, 9)])
+    before = ctx.get_busy(ids).copy()
+    q = B.pack_queries(ids[[0, 1, 0, 1, 0]], [0, 1, 2, 0, 1], [9, 3, 4, 2, 2], commit=[1, 1, 1, 0, 1])
+    expect = ctx.query_batch_wide(q)  # host form: commits, then given back
+    ctx.release(expect["alloc_handle"][expect["alloc_handle"] >= 0])
+    assert np.array_equal(ctx.get_busy(ids), before)
+    dev, dr = wide_on_device(ctx, torch, q)
+    assert dev.tobytes() == expect.tobytes()
+    assert list(dev["status"]) == [B.RES_OK, B.RES_OK, B.RES_CONFLICT, B.RES_OK, B.RES_CONFLICT]
+    after = ctx.get_busy(ids)
+    assert after[0] == before[0] | dev["vertex_mask"][0] and after[1] == before[1] | dev["vertex_mask"][1]
+    ctx.release(dr.view(torch.int64)[6:], stride=56, count=len(q), stream=torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    assert np.array_equal(ctx.get_busy(ids), before)
+
+
+def test_wide_embedding_limit(ctx, torch):
+    """A batch beyond 2^36 embeddings: the host form refuses it with
+    MAPA_ERR_ADMISSION before anything runs; the device form answers every
+    well-formed query with MAPA_RES_REFUSED, commits nothing and leaves the
+    servers' commit claims free for the next call.  More than
+    MAPA_MAX_WIDE_QUERIES queries are refused up front in both forms."""
+    W = np.ones((32, 32), np.uint8) - np.eye(32, dtype=np.uint8)
+    ids = ctx.load_servers([W, W], np.zeros(2, np.int32))
+    q = B.pack_queries(ids[[0, 1, 1]], [0, 1, 0], [12, 3, 0], commit=[1, 1, 0])  # 32!/20! > 2^36
+    with pytest.raises(B.MapaError) as e:
+        ctx.query_batch_wide(q[:2])
+    assert e.value.code == B.ERR_ADMISSION
+    dev, _ = wide_on_device(ctx, torch, q)
+    assert list(dev["status"]) == [B.RES_REFUSED, B.RES_REFUSED, B.RES_INVALID]
+    assert (dev["count"] == 0).all() and (dev["alloc_handle"] == -1).all()
+    assert (ctx.get_busy(ids) == 0).all()
+    small = B.pack_queries(ids[[0, 1]], [0, 1], [2, 3], commit=[1, 1])
+    dev2, _ = wide_on_device(ctx, torch, small)
+    assert list(dev2["status"]) == [B.RES_OK, B.RES_OK]
+    assert list(dev2["count"]) == [32 * 31, 32 * 31 * 30]
+    assert list(ctx.get_busy(ids)) == [int(dev2["vertex_mask"][0]), int(dev2["vertex_mask"][1])]
+    many = B.pack_queries(np.full(B.MAX_WIDE_QUERIES + 1, ids[0]), 0, 2)
+    with pytest.raises(B.MapaError) as e:
+        ctx.query_batch_wide(many)
+    assert e.value.code == B.ERR_ADMISSION
