@@ -279,7 +279,8 @@ typedef struct {
   int32_t status, key, agg, pres;
   uint32_t vertex_mask;
   uint8_t mapping[16];  /* mapping[i] = accelerator of pattern vertex i; 0xFF beyond k */
-  int32_t reserved;     /* 0 */
+  int32_t links;        /* MAPA_METRIC_EFFBW: x | y << 8 | z << 16, as in
+                           mapa_result; else 0                                  */
   int64_t alloc_handle; /* (server << 32) | vertex_mask if committed, else -1 */
 } mapa_result_wide;
 
@@ -288,9 +289,10 @@ typedef struct {
  * accelerators and more on larger hardware graphs whose scheduling cost
  * Sec. 5.4 discusses: servers of up to 32 accelerators and patterns
  * of up to 12 vertices (ring, all-to-all and tree of any k <= 12, or a
- * registered pattern), key a*AggBW + b*PreservedBW (MAPA_METRIC_EFFBW ->
- * MAPA_ERR_UNSUPPORTED / MAPA_RES_INVALID).  Any server may be queried this
- * way.
+ * registered pattern), key a*AggBW + b*PreservedBW or, with
+ * MAPA_METRIC_EFFBW, the predicted effective bandwidth of Eq. 2 on the link
+ * mix of the mapped pattern edges (up to 66 of them; topologies of weights
+ * 0, 1, 2 only, as on the batch path).  Any server may be queried this way.
  *   nq: 0 .. MAPA_MAX_WIDE_QUERIES (more -> MAPA_ERR_ADMISSION, nothing runs).
  *   Host pointers (flags = 0): q, res hold nq entries each; the call is
  *     validated as mapa_query_batch's host form (k > 12 ->

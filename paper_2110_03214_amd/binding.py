@@ -45,7 +45,7 @@ assert QUERY_DTYPE.itemsize == 16 and RESULT_DTYPE.itemsize == 48
 assert RESULT_DTYPE.fields["alloc_handle"][1] == 40
 RESULT_WIDE_DTYPE = np.dtype([("count", np.int64), ("status", np.int32), ("key", np.int32),
                               ("agg", np.int32), ("pres", np.int32), ("vertex_mask", np.uint32),
-                              ("mapping", np.uint8, 16), ("reserved", np.int32),
+                              ("mapping", np.uint8, 16), ("links", np.int32),
                               ("alloc_handle", np.int64)])
 assert RESULT_WIDE_DTYPE.itemsize == 56 and RESULT_WIDE_DTYPE.fields["alloc_handle"][1] == 48
 MAX_N_WIDE, MAX_K_WIDE = 32, 12

@@ -12,6 +12,7 @@
 #include <utility>
 
 #include "ctx.h"
+#include "wide.h"
 
 using namespace mapa;
 
@@ -420,13 +421,14 @@ double effbw_eq2(int x, int y, int z) {
   return v;
 }
 
-// The device's Eq. 2 tables: per edge count E, each mix's dense rank (equal
-// values share a rank, so maximising the rank maximises EffBW and keeps its
-// ties) and its reported key round(1000 * EffBW).
+// The device's Eq. 2 tables: per edge count E (up to 66, the wide path's
+// 12-vertex all-to-all), each mix's dense rank (equal values share a rank,
+// so maximising the rank maximises EffBW and keeps its ties) and its
+// reported key round(1000 * EffBW).
 int32_t upload_effbw_tables(mapa_ctx *c) {
-  std::vector<uint16_t> rank(kEffEntries, 0);
-  std::vector<int32_t> key(kEffEntries, 0);
-  for (int E = 0; E <= kMaxEdges; ++E) {
+  std::vector<uint16_t> rank(kEffEntriesWide, 0);
+  std::vector<int32_t> key(kEffEntriesWide, 0);
+  for (int E = 0; E <= kWideMaxEdges; ++E) {
     std::vector<double> vals;
     for (int x = 0; x <= E; ++x)
       for (int y = 0; x + y <= E; ++y) vals.push_back(effbw_eq2(x, y, E - x - y));
@@ -440,8 +442,8 @@ int32_t upload_effbw_tables(mapa_ctx *c) {
         key[at] = (int32_t)std::llround(1000.0 * v);
       }
   }
-  if (dev_alloc(&c->d_eff_rank, kEffEntries) != hipSuccess ||
-      dev_alloc(&c->d_eff_key, kEffEntries) != hipSuccess)
+  if (dev_alloc(&c->d_eff_rank, kEffEntriesWide) != hipSuccess ||
+      dev_alloc(&c->d_eff_key, kEffEntriesWide) != hipSuccess)
     return fail(MAPA_ERR_OOM, "effective-bandwidth tables: device allocation failed");
   MAPA_HIPCHK(hipMemcpy(c->d_eff_rank, rank.data(), rank.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
   MAPA_HIPCHK(hipMemcpy(c->d_eff_key, key.data(), key.size() * sizeof(int32_t), hipMemcpyHostToDevice));

@@ -70,9 +70,11 @@ int32_t validate_wide(const mapa_ctx *c, const mapa_query &q, int32_t i) {
   if (q.a < 0 || q.a > MAPA_MAX_AB || q.b < 0 || q.b > MAPA_MAX_AB)
     return fail(MAPA_ERR_INVALID_ARG, "query %d: key weights (%d,%d) outside 0..%d", i, q.a, q.b,
                 MAPA_MAX_AB);
-  if (q.metric == MAPA_METRIC_EFFBW)
-    return fail(MAPA_ERR_UNSUPPORTED, "query %d: the wide path scores a*AggBW + b*PreservedBW only", i);
-  if (q.metric != MAPA_METRIC_WEIGHTED) return fail(MAPA_ERR_INVALID_ARG, "query %d: metric=%d", i, q.metric);
+  if (q.metric != MAPA_METRIC_WEIGHTED && q.metric != MAPA_METRIC_EFFBW)
+    return fail(MAPA_ERR_INVALID_ARG, "query %d: metric=%d", i, q.metric);
+  if (q.metric == MAPA_METRIC_EFFBW && c->topo_maxw[c->server_topo[q.server]] > 2)
+    return fail(MAPA_ERR_UNSUPPORTED,
+                "query %d: effective bandwidth needs link weights 0, 1, 2 (PCIe, single, double NVLink)", i);
   return MAPA_OK;
 }
 
@@ -146,6 +148,8 @@ extern "C" int32_t mapa_query_batch_wide(mapa_ctx *c, const mapa_query *q, int32
   w.ntopo_wide = (int32_t)c->wide_uploaded;
   w.pat_nbtab = c->d_pat_nbtab;
   w.pat_k = c->d_pat_k;
+  w.eff_rank = c->d_eff_rank;
+  w.eff_key = c->d_eff_key;
   w.busy = c->d_busy;
   w.commit_slot = c->d_commit_slot;
   w.res = dev ? res : reinterpret_cast<mapa_result_wide *>(base + o_res);

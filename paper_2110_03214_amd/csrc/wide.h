@@ -17,6 +17,11 @@ constexpr int kWideMaxBlocksPerQuery = 128;
 constexpr uint32_t kWideMinItems = 16384;             // prefix items a query is split into, at least
 constexpr unsigned long long kWideMaxLeaves = 1ull << 36;  // embeddings per call
 constexpr int kWideMaxQueries = MAPA_MAX_WIDE_QUERIES;
+// Eq. 2 tables (layout of eff_off) are built up to this many pattern edges,
+// a 12-vertex all-to-all; the batch path reads the first kEffEntries.
+constexpr int kWideMaxEdges = kWideK * (kWideK - 1) / 2;  // 66
+constexpr int kEffEntriesWide = eff_off(kWideMaxEdges + 1);
+constexpr int kWideEffTab = (kWideMaxEdges + 1) * (kWideMaxEdges + 1);  // one edge count's block, at most
 
 // Per-query plan, written by k_wide_plan from the query and the busy mask at
 // the call's start.
@@ -29,7 +34,8 @@ struct WidePlan {
   uint8_t F, status, commit, nb_all;  // nb_all: every earlier position neighbours each one
   int16_t a, b;
   uint16_t topo;
-  uint16_t pad;
+  uint8_t metric;        // MAPA_METRIC_WEIGHTED or MAPA_METRIC_EFFBW
+  uint8_t E;             // pattern edges (Eq. 2 table block)
   uint32_t items;        // F!/(F-d)! prefixes
   uint32_t nblocks;      // blocks of the query's share that have items
 };
@@ -54,6 +60,8 @@ struct WideArgs {
   int32_t ntopo_wide;     // topologies whose rows are uploaded
   const unsigned long long *pat_nbtab;  // registered patterns
   const uint8_t *pat_k;
+  const uint16_t *eff_rank;  // [kEffEntriesWide] Eq. 2 dense ranks, layout of eff_off
+  const int32_t *eff_key;    // [kEffEntriesWide] round(1000 * EffBW)
   uint32_t *busy;
   unsigned long long *commit_slot;  // first committing query per server, all ones when free
   mapa_result_wide *res;  // [nq] device or pinned memory

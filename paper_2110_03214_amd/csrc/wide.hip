@@ -93,12 +93,42 @@ __device__ __forceinline__ int wpair_b(const uint32_t *rows, int Bn, int u, int 
 
 struct WideCtx {
   const uint32_t *rows;  // LDS: [kWidePlanes][32]
+  const uint16_t *erank; // LDS: Eq. 2 dense ranks of the query's edge count, [x * e1 + y]
   const uint32_t *pw;    // LDS: [32][2] packed 2-bit weights (weights <= 3): W[v][u] at
                          // bit 2 * (u % 16) of word 2 * v + u / 16
   const uint16_t *nb;    // LDS: back-neighbour position masks of the pattern
   uint32_t R;
-  int Bn, a, b, k, linked, nb_all;
+  int Bn, a, b, k, linked, nb_all, e1;
 };
+
+// The score a search carries, fixed per query by the template argument B:
+// B = kEffB scores by Eq. 2 (the running value is the link mix of the
+// pattern edges placed so far, x << 8 | y with x double and y single
+// NVLinks, and a leaf's key is the mix's dense rank among the mixes of the
+// query's edge count); any other B by a*AggBW + b*PreservedBW through the
+// identity above, from B weight bit-planes (0: as many as the topology has).
+constexpr int kEffB = -1;
+
+// running value after placing c at a position whose earlier pattern
+// neighbours sit on nbm, with `rest` free before c is placed
+template <int B>
+__device__ __forceinline__ int step_key(const WideCtx &s, int kp, int c, uint32_t nbm, uint32_t rest) {
+  if constexpr (B == kEffB) {
+    // weights 0, 1, 2 only: plane 1 marks the double NVLinks, plane 0 the single ones
+    return kp + (__popc(s.rows[32 + c] & nbm) << 8) + __popc(s.rows[c] & nbm);
+  } else {
+    return kp + s.a * wsum_b<B>(s.rows, s.Bn, c, nbm) - s.b * wsum_b<B>(s.rows, s.Bn, c, rest);
+  }
+}
+
+// key of a leaf whose running value is v
+template <int B>
+__device__ __forceinline__ int leaf_key(const WideCtx &s, int v) {
+  if constexpr (B == kEffB)
+    return (int)s.erank[(v >> 8) * s.e1 + (v & 255)];
+  else
+    return v;
+}
 
 // vertices at the earlier pattern neighbours of position pos (except the
 // positions in `skip`), and the candidates for pos (in LINKED mode adjacent
@@ -147,8 +177,7 @@ __device__ __forceinline__ void leaf_level(const WideCtx &s, WideLane &L, uint32
   uint32_t best = 0;
   for (uint32_t m = cand; m; m &= m - 1) {
     const int c = __builtin_ctz(m);
-    const int v = kp + s.a * wsum_b<B>(s.rows, s.Bn, c, nbm) - s.b * wsum_b<B>(s.rows, s.Bn, c, rest);
-    const uint32_t pk = pack_leaf(v, c);
+    const uint32_t pk = pack_leaf(leaf_key<B>(s, step_key<B>(s, kp, c, nbm, rest)), c);
     best = pk > best ? pk : best;
   }
   if (best) keep_best(L, best, code, 5 * (kWideK - 1 - pos));
@@ -232,7 +261,7 @@ __device__ __forceinline__ void pair_plain(const WideCtx &s, WideLane &L, uint32
   const int sh = 5 * (kWideK - 1 - p);
   for (uint32_t m = cand; m; m &= m - 1) {
     const int c = __builtin_ctz(m);
-    const int kp2 = kp + s.a * wsum_b<B>(s.rows, s.Bn, c, nbm) - s.b * wsum_b<B>(s.rows, s.Bn, c, rest);
+    const int kp2 = step_key<B>(s, kp, c, nbm, rest);
     leaf_level<B>(s, L, rest & ~(1u << c), code | ((unsigned long long)c << sh), kp2, p + 1);
   }
 }
@@ -240,16 +269,18 @@ __device__ __forceinline__ void pair_plain(const WideCtx &s, WideLane &L, uint32
 template <int B>
 __device__ __forceinline__ void last_two(const WideCtx &s, WideLane &L, uint32_t rest,
                                          unsigned long long code, int kp, int p, int nfree) {
-  if (!s.linked) {
-    switch (nfree) {
-      case 2: pair_table<2, B>(s, L, rest, code, kp, p); return;
-      case 3: pair_table<3, B>(s, L, rest, code, kp, p); return;
-      case 4: pair_table<4, B>(s, L, rest, code, kp, p); return;
-      case 5: pair_table<5, B>(s, L, rest, code, kp, p); return;
-      case 6: pair_table<6, B>(s, L, rest, code, kp, p); return;
-      case 7: pair_table<7, B>(s, L, rest, code, kp, p); return;
-      case 8: pair_table<8, B>(s, L, rest, code, kp, p); return;
-      default: break;
+  if constexpr (B != kEffB) {  // Eq. 2 keys are not sums of per-candidate terms
+    if (!s.linked) {
+      switch (nfree) {
+        case 2: pair_table<2, B>(s, L, rest, code, kp, p); return;
+        case 3: pair_table<3, B>(s, L, rest, code, kp, p); return;
+        case 4: pair_table<4, B>(s, L, rest, code, kp, p); return;
+        case 5: pair_table<5, B>(s, L, rest, code, kp, p); return;
+        case 6: pair_table<6, B>(s, L, rest, code, kp, p); return;
+        case 7: pair_table<7, B>(s, L, rest, code, kp, p); return;
+        case 8: pair_table<8, B>(s, L, rest, code, kp, p); return;
+        default: break;
+      }
     }
   }
   pair_plain<B>(s, L, rest, code, kp, p);
@@ -405,8 +436,7 @@ __device__ __forceinline__ void expand_prefix(const WideCtx &s, WideLane &L, uin
     const int c = __builtin_ctz(cand);
     stk_cand[pos * kWideThreads + tid] = cand & (cand - 1);
     const uint32_t nbm = stk_nbm[pos * kWideThreads + tid];
-    const int kpc = stk_kp[pos * kWideThreads + tid] + s.a * wsum_b<B>(s.rows, s.Bn, c, nbm) -
-                    s.b * wsum_b<B>(s.rows, s.Bn, c, rest);
+    const int kpc = step_key<B>(s, stk_kp[pos * kWideThreads + tid], c, nbm, rest);
     rest &= ~(1u << c);
     code |= (unsigned long long)c << (5 * (kWideK - 1 - pos));
     if (pos + 1 == top) {
@@ -456,7 +486,7 @@ __device__ __forceinline__ void wide_search_items(const WidePlan *p, const WideC
       uint32_t nbm, cand;
       wide_masks(s, code, t, rest, 0u, nbm, cand);
       ok = ok && ((cand >> v) & 1u);
-      kp += s.a * wsum_b<B>(s.rows, s.Bn, v, nbm) - s.b * wsum_b<B>(s.rows, s.Bn, v, rest);
+      kp = step_key<B>(s, kp, v, nbm, rest);
       rest &= ~(1u << v);
       code |= (unsigned long long)v << (5 * (kWideK - 1 - t));
     }
@@ -464,16 +494,19 @@ __device__ __forceinline__ void wide_search_items(const WidePlan *p, const WideC
   }
 }
 
-// Plan of one query from the busy mask in memory (the call's start): the
-// checks of the host form (malformed -> kPlanInvalid), free set R,
-// b * W(R), the pattern's earlier-neighbour masks, weight bit-planes in use,
-// prefix depth (the smallest with at least kWideMinItems prefixes), the
-// blocks that have items, and the claim of the server's commit (the first
-// committing query of the batch, array order).
+// The call's embedding total starts from zero (a kernel, not a memset, so
+// the launch sequence may be captured into a graph).
 __global__ void k_wide_clear(unsigned long long *total) {
   if (threadIdx.x == 0) *total = 0;
 }
 
+// Plan of one query from the busy mask in memory (the call's start): the
+// checks of the host form (malformed -> kPlanInvalid), free set R,
+// b * W(R) (0 for Eq. 2), the pattern's earlier-neighbour masks and edge
+// count, weight bit-planes in use, prefix depth (the smallest with at least
+// kWideMinItems prefixes), the blocks that have items, the claim of the
+// server's commit (the first committing query of the batch, array order)
+// and the query's embeddings added to the call's total.
 __global__ __launch_bounds__(256) void k_wide_plan(WideArgs w) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= w.nq) return;
@@ -493,7 +526,8 @@ __global__ __launch_bounds__(256) void k_wide_plan(WideArgs w) {
   p.a = q.a;
   p.b = q.b;
   p.topo = 0;
-  p.pad = 0;
+  p.metric = q.metric;
+  p.E = 0;
   p.items = 0;
   p.nblocks = 0;
   const int pid = (int)q.kind - MAPA_PATTERN_BASE;  // registered pattern id
@@ -501,8 +535,10 @@ __global__ __launch_bounds__(256) void k_wide_plan(WideArgs w) {
   const bool ok = q.server >= 0 && q.server < w.nservers && q.k >= 1 && q.k <= kWideK &&
                   (q.kind <= MAPA_TREE || (registered && w.pat_k[pid] == q.k)) &&
                   q.mode <= 1 && q.commit <= 1 && q.a >= 0 && q.a <= MAPA_MAX_AB && q.b >= 0 &&
-                  q.b <= MAPA_MAX_AB && q.metric == MAPA_METRIC_WEIGHTED &&
-                  w.server_topo[q.server] < w.ntopo_wide;
+                  q.b <= MAPA_MAX_AB &&
+                  (q.metric == MAPA_METRIC_WEIGHTED || q.metric == MAPA_METRIC_EFFBW) &&
+                  w.server_topo[q.server] < w.ntopo_wide &&
+                  (q.metric == MAPA_METRIC_WEIGHTED || w.topo_maxw[w.server_topo[q.server]] <= 2);
   if (!ok) {
     p.status = kPlanInvalid;
     w.plan[i] = p;
@@ -521,7 +557,7 @@ __global__ __launch_bounds__(256) void k_wide_plan(WideArgs w) {
   p.R = R;
   p.F = (uint8_t)F;
   p.B = (uint8_t)B;
-  p.kp0 = q.b * (wr2 / 2);
+  p.kp0 = q.metric == MAPA_METRIC_EFFBW ? 0 : q.b * (wr2 / 2);  // Eq. 2 starts from no edges
   if (registered) {
     const unsigned long long tab = w.pat_nbtab[pid];
     for (int j = 0; j < q.k; ++j) p.nb[j] = (uint16_t)((tab >> (8 * j)) & 0xFFu);
@@ -535,6 +571,9 @@ __global__ __launch_bounds__(256) void k_wide_plan(WideArgs w) {
         p.nb[j] = (uint16_t)(1u << ((j - 1) / 2));
     }
   }
+  int E = 0;
+  for (int j = 0; j < q.k; ++j) E += __popc(p.nb[j]);
+  p.E = (uint8_t)E;
   if (q.commit) atomicMin(&w.commit_slot[q.server], (unsigned long long)i);
   if (q.k > F) {
     p.status = kPlanNofit;
@@ -571,6 +610,7 @@ __global__ __launch_bounds__(kWideThreads) void k_wide_search(WideArgs w) {
   __shared__ uint32_t s_nbm[kWideK * kWideThreads];
   __shared__ unsigned long long s_cnt[kWideThreads / 64], s_code[kWideThreads / 64];
   __shared__ int s_key[kWideThreads / 64];
+  __shared__ uint16_t s_erank[kWideEffTab];
   // block b of query q's share: b = blockIdx.x % kWideMaxBlocksPerQuery
   const uint32_t q = blockIdx.x / kWideMaxBlocksPerQuery;
   const uint32_t bi = blockIdx.x % kWideMaxBlocksPerQuery;
@@ -591,6 +631,9 @@ __global__ __launch_bounds__(kWideThreads) void k_wide_search(WideArgs w) {
   for (int i = tid; i < kWidePlanes * 32; i += blockDim.x)
     s_rows[i] = w.rows[(size_t)p->topo * kWidePlanes * 32 + i];
   if (tid < kWideK) s_nb[tid] = p->nb[tid];
+  const int e1 = p->E + 1;
+  if (p->metric == MAPA_METRIC_EFFBW)  // the ranks of the query's edge count
+    for (int i = tid; i < e1 * e1; i += blockDim.x) s_erank[i] = w.eff_rank[eff_off(p->E) + i];
   __syncthreads();
   if (tid < 64) {  // packed 2-bit weights from the two low planes
     const int v = tid >> 1, h = tid & 1;
@@ -602,6 +645,8 @@ __global__ __launch_bounds__(kWideThreads) void k_wide_search(WideArgs w) {
   __syncthreads();
   WideCtx s;
   s.rows = s_rows;
+  s.erank = s_erank;
+  s.e1 = e1;
   s.pw = s_pw;
   s.nb = s_nb;
   s.R = p->R;
@@ -616,7 +661,9 @@ __global__ __launch_bounds__(kWideThreads) void k_wide_search(WideArgs w) {
   L.bpk = 0;
   L.bcode = 0;
   L.bsh = 0;
-  if (s.Bn == 1)
+  if (p->metric == MAPA_METRIC_EFFBW)
+    wide_search_items<kEffB>(p, s, L, s_cand, s_kp, s_nbm, tid, bi);
+  else if (s.Bn == 1)
     wide_search_items<1>(p, s, L, s_cand, s_kp, s_nbm, tid, bi);
   else if (s.Bn == 2)
     wide_search_items<2>(p, s, L, s_cand, s_kp, s_nbm, tid, bi);
@@ -663,25 +710,18 @@ __global__ __launch_bounds__(kWideThreads) void k_wide_search(WideArgs w) {
   }
 }
 
+// One wave per query: the lanes combine the query's block partials, then
+// lane 0 builds the result.
 __global__ __launch_bounds__(256) void k_wide_finalize(WideArgs w) {
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  const int q = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   if (q >= w.nq) return;
   const WidePlan &p = w.plan[q];
-  mapa_result_wide r;
-  r.count = 0;
-  r.status = MAPA_RES_NOFIT;
-  r.key = INT32_MIN;
-  r.agg = 0;
-  r.pres = 0;
-  r.vertex_mask = 0;
-  for (int i = 0; i < 16; ++i) r.mapping[i] = 0xFF;
-  r.reserved = 0;
-  r.alloc_handle = -1;
   const bool refused = *w.total > kWideMaxLeaves;
+  unsigned long long cnt = 0, code = ~0ull;
+  int key = -1;
   if (p.status == kPlanOk && !refused) {
-    unsigned long long cnt = 0, code = ~0ull;
-    int key = -1;
-    for (uint32_t b = 0; b < p.nblocks; ++b) {
+    for (uint32_t b = lane; b < p.nblocks; b += 64) {
       const WidePartial &pt = w.part[(size_t)q * kWideMaxBlocksPerQuery + b];
       cnt += pt.count;
       if (wide_better(pt.key, pt.code, key, code)) {
@@ -689,26 +729,57 @@ __global__ __launch_bounds__(256) void k_wide_finalize(WideArgs w) {
         code = pt.code;
       }
     }
-    r.count = (int64_t)cnt;
-    if (cnt > 0 && key >= 0) {
-      const uint32_t *rows = w.rows + (size_t)p.topo * kWidePlanes * 32;
-      uint32_t S = 0;
-      int agg = 0;
-      for (int i = 0; i < p.k; ++i) {
-        const int v = vertex_at(code, i);
-        r.mapping[i] = (uint8_t)v;
-        S |= 1u << v;
-        for (uint32_t m = p.nb[i]; m; m &= m - 1)  // Eq. 1 over the pattern edges
-          agg += wsum_wide(rows, p.B, v, 1u << vertex_at(code, __builtin_ctz(m)));
+    for (int off = 32; off >= 1; off >>= 1) {
+      cnt += __shfl_xor(cnt, off, 64);
+      const int k2 = __shfl_xor(key, off, 64);
+      const unsigned long long c2 = __shfl_xor(code, off, 64);
+      if (wide_better(k2, c2, key, code)) {
+        key = k2;
+        code = c2;
       }
-      const uint32_t left = p.R & ~S;  // Eq. 3 over the free vertices left
-      int pres2 = 0;
-      for (uint32_t m = left; m; m &= m - 1) pres2 += wsum_wide(rows, p.B, __builtin_ctz(m), left);
-      r.status = MAPA_RES_OK;
+    }
+  }
+  if (lane != 0) return;
+  mapa_result_wide r;
+  r.count = (int64_t)cnt;
+  r.status = MAPA_RES_NOFIT;
+  r.key = INT32_MIN;
+  r.agg = 0;
+  r.pres = 0;
+  r.vertex_mask = 0;
+  for (int i = 0; i < 16; ++i) r.mapping[i] = 0xFF;
+  r.links = 0;
+  r.alloc_handle = -1;
+  if (p.status == kPlanOk && !refused && cnt > 0 && key >= 0) {
+    const uint32_t *rows = w.rows + (size_t)p.topo * kWidePlanes * 32;
+    uint32_t S = 0;
+    int agg = 0, lx = 0, ly = 0, lz = 0;
+    for (int i = 0; i < p.k; ++i) {
+      const int v = vertex_at(code, i);
+      r.mapping[i] = (uint8_t)v;
+      S |= 1u << v;
+      for (uint32_t m = p.nb[i]; m; m &= m - 1) {  // Eq. 1 over the pattern edges
+        const int wv = wsum_wide(rows, p.B, v, 1u << vertex_at(code, __builtin_ctz(m)));
+        agg += wv;
+        lx += wv == 2;  // Eq. 2's link classes
+        ly += wv == 1;
+        lz += wv == 0;
+      }
+    }
+    const uint32_t left = p.R & ~S;  // Eq. 3 over the free vertices left
+    int pres2 = 0;
+    for (uint32_t m = left; m; m &= m - 1) pres2 += wsum_wide(rows, p.B, __builtin_ctz(m), left);
+    r.status = MAPA_RES_OK;
+    r.agg = agg;
+    r.pres = pres2 / 2;
+    r.vertex_mask = S;
+    if (p.metric == MAPA_METRIC_EFFBW) {
+      const int at = eff_off(p.E) + lx * (p.E + 1) + ly;
+      r.key = w.eff_key[at];
+      r.links = lx | (ly << 8) | (lz << 16);
+      if ((int)w.eff_rank[at] != key || lx + ly + lz != p.E) atomicAdd(w.self_check_failures, 1u);
+    } else {
       r.key = key;
-      r.agg = agg;
-      r.pres = pres2 / 2;
-      r.vertex_mask = S;
       if ((int)p.a * agg + (int)p.b * r.pres != key) atomicAdd(w.self_check_failures, 1u);
     }
   }
@@ -748,7 +819,7 @@ hipError_t launch_wide_search(const WideArgs &w, hipStream_t s) {
 }
 
 hipError_t launch_wide_finalize(const WideArgs &w, hipStream_t s) {
-  if (w.nq > 0) hipLaunchKernelGGL(k_wide_finalize, dim3((w.nq + 255) / 256), dim3(256), 0, s, w);
+  if (w.nq > 0) hipLaunchKernelGGL(k_wide_finalize, dim3((w.nq + 3) / 4), dim3(256), 0, s, w);
   return hipGetLastError();
 }
 

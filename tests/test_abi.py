@@ -154,7 +154,8 @@ def test_pattern_registration_and_query_kinds(vctx):
 
 def test_wide_queries_validation(vctx):
     """Servers of 17..32 accelerators are created, answered only by the wide
-    call; the wide call takes k up to 12 and the weighted key only."""
+    call; the wide call takes k up to 12, the weighted key and Eq. 2 (on
+    weights 0..2)."""
     W = np.ones((32, 32), np.uint8) - np.eye(32, dtype=np.uint8)
     assert vctx.create_topology(W, 2) == (0, 0)
     vctx.create_topology(cube_mesh(), 1)
@@ -170,9 +171,16 @@ def test_wide_queries_validation(vctx):
     assert code_of(lambda: vctx.query_batch_wide(ok)) == B.ERR_NO_DEVICE
     assert code_of(lambda: vctx.query_batch_wide(B.pack_queries([0], [0], [13]))) == B.ERR_UNSUPPORTED
     assert code_of(lambda: vctx.query_batch_wide(B.pack_queries([0], [0], [0]))) == B.ERR_INVALID_ARG
+    # Eq. 2 on a server of weights 0..2 passes validation, on weights > 2 it is refused
     assert code_of(lambda: vctx.query_batch_wide(B.pack_queries([0], [0], [3], metric=[1]))) == \
-        B.ERR_UNSUPPORTED
+        B.ERR_NO_DEVICE
     assert code_of(lambda: vctx.query_batch_wide(B.pack_queries([3], [0], [3]))) == B.ERR_UNKNOWN_SERVER
+    W3 = np.full((20, 20), 3, np.uint8) - 3 * np.eye(20, dtype=np.uint8)
+    assert vctx.create_topology(W3, 1) == (2, 3)
+    assert code_of(lambda: vctx.query_batch_wide(B.pack_queries([3], [0], [3], metric=[1]))) == \
+        B.ERR_UNSUPPORTED
+    assert code_of(lambda: vctx.query_batch_wide(B.pack_queries([3], [0], [3], metric=[2]))) == \
+        B.ERR_INVALID_ARG
     kind = vctx.create_pattern(5, [(0, 4), (1, 4)])
     assert code_of(lambda: vctx.query_batch_wide(B.pack_queries([0], [kind], [5]))) == B.ERR_NO_DEVICE
     assert code_of(lambda: vctx.query_batch_wide(B.pack_queries([0], [kind], [6]))) == B.ERR_INVALID_ARG

@@ -38,7 +38,7 @@ def assert_same(gpu, ref, k, label=""):
         bad = np.nonzero(gpu[f] != ref[f])[0]
         assert bad.size == 0, f"{label} {f} differs at {bad[:5]}: gpu {gpu[f][bad[:5]]} ref {ref[f][bad[:5]]}"
     ok = ref["status"] == 0
-    for f in ("key", "agg", "pres", "vertex_mask"):
+    for f in ("key", "agg", "pres", "vertex_mask", "links"):
         bad = np.nonzero(ok & (gpu[f] != ref[f]))[0]
         assert bad.size == 0, f"{label} {f} differs at {bad[:5]}: gpu {gpu[f][bad[:5]]} ref {ref[f][bad[:5]]}"
     for kk in np.unique(k):
@@ -61,15 +61,15 @@ def busy_leaving(rng, n, F):
     return int(((1 << n) - 1) & ~int(np.bitwise_or.reduce(1 << free.astype(np.int64))))
 
 
-def run_wide(ctx, topos, st, busy, cols, edges=None):
+def run_wide(ctx, topos, st, busy, cols, edges=None, metric=0):
     q = synth.make_queries(cols["server"], cols["kind"], cols["k"], cols["mode"], cols.get("commit", 0),
-                           cols["a"], cols["b"])
+                           cols["a"], cols["b"], metric)
     wl = synth.Workload("wide", topos, np.array(st, np.int32), np.array(busy, np.uint32), q)
     qh, ids = B.load_workload(ctx, wl)
     got = ctx.query_batch_wide(qh)
     srv = wl.queries["server"]
     ref = oracle.batch(topos, wl.server_topo[srv], wl.busy[srv], q["kind"], q["k"], q["mode"], q["a"],
-                       q["b"], NTHREADS, edges=edges)
+                       q["b"], NTHREADS, metric=q["metric"], edges=edges)
     return got, ref, qh
 
 
@@ -100,6 +100,55 @@ def test_wide_servers_against_oracle(ctx, wmax):
     assert_same(got, ref, qh["k"], "wide")
     assert (ref["status"] == 0).sum() > 100
     assert ctx.stats()["self_check_failures"] == 0
+
+
+def test_wide_effbw_against_oracle(ctx):
+    """Eq. 2 on the wide path: servers of 17..32 accelerators whose links
+    are PCIe (0), single (1) or double NVLinks (2), every kind, k = 1..12
+    (up to 66 pattern edges), both modes; key round(1000 * EffBW), the link
+    mix and the mapping of the first best placement, as the oracle."""
+    rng = np.random.default_rng(2)
+    topos = [random_topology(rng, n, 2, p) for n, p in ((17, 0.6), (24, 0.9), (32, 0.5))]
+    st, busy, cols = [], [], {c: [] for c in ("server", "kind", "k", "mode", "a", "b")}
+    s = 0
+    for t, W in enumerate(topos):
+        n = W.shape[0]
+        for F in (4, 10, 12):
+            st.append(t)
+            busy.append(busy_leaving(rng, n, F))
+            limit = 2_000_000 if n <= 20 else 50_000
+            for kind in range(3):
+                for k in range(1, 13):
+                    # k = F = 10 stays on the 17-vertex server (10! embeddings)
+                    if k <= F and math.perm(F, k) > limit and not (k == F == 10 and n <= 20):
+                        continue
+                    for mode in (0, 1):
+                        for c, v in zip(cols, (s, kind, k, mode, 1, 1)):
+                            cols[c].append(v)
+            s += 1
+    got, ref, qh = run_wide(ctx, topos, st, busy, cols, metric=1)
+    assert_same(got, ref, qh["k"], "wide effbw")
+    ok = ref["status"] == 0
+    assert ok.sum() > 80 and (qh["k"][ok] >= 9).any()
+    assert ctx.stats()["self_check_failures"] == 0
+
+
+def test_wide_effbw_equals_batch_path(ctx):
+    """Eq. 2 queries on servers both paths take (cube-mesh 8-GPU graphs of
+    weights 0..2, k <= 8) answer identically on the wide and batch calls."""
+    rng = np.random.default_rng(3)
+    topos = [random_topology(rng, n, 2, 0.7) for n in (8, 12, 16)]
+    ids = ctx.load_servers(topos, np.arange(3, dtype=np.int32))
+    ctx.set_busy(ids, [busy_leaving(rng, 8, 7), busy_leaving(rng, 12, 9), busy_leaving(rng, 16, 8)])
+    cols = [(s, kind, k, mode) for s in range(3) for kind in range(3) for k in range(1, 9) for mode in (0, 1)]
+    srv, kind, k, mode = (np.array(c) for c in zip(*cols))
+    q = B.pack_queries(ids[srv], kind, k, mode, metric=1)
+    base = ctx.query_batch(q)
+    wide = ctx.query_batch_wide(q)
+    for f in ("count", "status", "key", "agg", "pres", "vertex_mask", "links", "alloc_handle"):
+        assert np.array_equal(wide[f], base[f]), f
+    assert np.array_equal(wide["mapping"][:, :8], base["mapping"])
+    assert (base["status"] == B.RES_OK).sum() > 40
 
 
 def test_wide_jobs_of_nine_to_twelve(ctx):
