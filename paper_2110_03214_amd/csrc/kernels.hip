@@ -5,11 +5,12 @@
 //   k_prepare    per query: validate, free set R, constant key term b*W(R),
 //                per-split prefix depths and item totals, commit claim.
 //   k_bucketize  choose one split for the batch; per query: prefix depth d,
-//                shape bucket, offset inside the bucket.
-//   k_layout     one block: lays the buckets out (largest items first), pads
-//                each to whole 64-item chunks, resets the per-batch counters.
-//   k_expand     fills every query's work-list slots with (query, item index);
-//                k_enumerate turns the index into the prefix tuple.
+//                shape bucket, offset inside the bucket.  Its last block to
+//                finish lays the buckets out (largest items first) and
+//                resets the per-batch counters.
+//   k_expand     fills every query's work-list slots with (query, item index)
+//                and pads each bucket to whole 64-item chunks; k_enumerate
+//                turns the index into the prefix tuple.
 //   k_enumerate  persistent: each wave takes a 64-item chunk; each lane
 //                expands its prefix depth-first over the remaining pattern
 //                positions, scoring every match incrementally, and keeps a
@@ -47,67 +48,64 @@ hipError_t upload_tables_front(const Tables &t) {
 // ----------------------------------------------------------------- prepare
 
 __global__ __launch_bounds__(256) void k_prepare(BatchArgs a) {
+  // queries that fit, by (F, k): one LDS atomic per query, then one global
+  // atomic per block and nonzero bin (the split totals need nothing else)
+  __shared__ uint32_t s_hist[kFkBins];
+  for (int e = threadIdx.x; e < kFkBins; e += blockDim.x) s_hist[e] = 0;
+  __syncthreads();
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  unsigned long long leaves = 0;
-  unsigned long long items[kNumSplits];
-#pragma unroll
-  for (int j = 0; j < kNumSplits; ++j) items[j] = 0;
-
   if (i < a.nq) {
     const mapa_query q = a.q[i];
     const Plan p = make_plan(q, a.nservers, a.server_topo, a.topo_n, a.topo_maxw, a.busy, a.rows,
                              a.wpr, a.pat_nbtab, a.pat_k, a.pat_nbtab_ord, a.pat_order);
-    if (p.status == kPlanOk) {
-      leaves = c_tab.perm[p.F][p.k];
-      const uint8_t *sd = a.split_d + ((size_t)p.F * (kMaxK + 1) + p.k) * kNumSplits;
-#pragma unroll
-      for (int j = 0; j < kNumSplits; ++j) items[j] = c_tab.perm[p.F][sd[j]];
-    }
+    if (p.status == kPlanOk) atomicAdd(&s_hist[p.F * (kMaxK + 1) + p.k], 1u);
     if (p.status != kPlanInvalid && p.commit)
       atomicMin(&a.commit_slot[p.server], (unsigned long long)i);
     a.plan[i] = p;
     a.acc_count[i] = 0;
     a.acc_best[i] = 0;
   }
-  // wave sums -> block sums in LDS -> one global atomic per block and counter
-  __shared__ unsigned long long s_tot[kNumSplits + 1];
-  if (threadIdx.x <= kNumSplits) s_tot[threadIdx.x] = 0;
   __syncthreads();
-  leaves = wave_sum_u64(leaves);
-#pragma unroll
-  for (int j = 0; j < kNumSplits; ++j) items[j] = wave_sum_u64(items[j]);
-  if ((threadIdx.x & 63) == 0) {
-    if (leaves) atomicAdd(&s_tot[kNumSplits], leaves);
-#pragma unroll
-    for (int j = 0; j < kNumSplits; ++j)
-      if (items[j]) atomicAdd(&s_tot[j], items[j]);
-  }
-  __syncthreads();
-  if (threadIdx.x <= kNumSplits && s_tot[threadIdx.x])
-    atomicAdd(&a.ctr->totals[blockIdx.x % kTotCopies][threadIdx.x][0], s_tot[threadIdx.x]);
+  for (int e = threadIdx.x; e < kFkBins; e += blockDim.x)
+    if (s_hist[e]) atomicAdd(&a.ctr->fk_hist[blockIdx.x % kTotCopies][e], s_hist[e]);
 }
 
 // --------------------------------------------------------------- bucketize
 
 constexpr int kFatBlock = 1024;  // threads of k_bucketize and k_layout blocks
 
-// Lay the buckets out (largest items first), pad each to whole 64-item
-// chunks with invalid items, and reset the per-batch counters.  Run by the
-// one block of k_layout, once every k_bucketize block's counts are in.
+// Lay the buckets out (largest items first, each rounded up to whole 64-item
+// chunks) and reset the per-batch counters.  Run by the last k_bucketize
+// block to finish, once every block's counts are in.
 __device__ void layout_buckets(const BatchArgs &a) {
   __shared__ uint32_t s_pad[kNumBuckets];
   __shared__ uint32_t s_cnt[kNumBuckets];
   __shared__ uint32_t s_start[kNumBuckets];
   const int t = threadIdx.x;
   // loops over the buckets have a fixed stride (one 1024-thread block), so
-  // they unroll and each thread's loads are in flight together
+  // they unroll and each thread's loads are in flight together.  The counts
+  // are loaded in bucket order (into s_start, free until the scan) beside
+  // the rank table, then gathered into rank order through LDS.
+  constexpr int kPer = (kNumBuckets + kFatBlock - 1) / kFatBlock;
+  int rank_b[kPer];
 #pragma unroll
-  for (int r = t; r < kNumBuckets; r += kFatBlock) {
-    const int b = c_tab.rank_bucket[r];
-    const uint32_t cnt = __hip_atomic_load(&a.ctr->bucket_items[b][0], __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-    s_cnt[r] = cnt;
-    s_pad[r] = (cnt + (kChunk - 1)) & ~(uint32_t)(kChunk - 1);
+  for (int e = 0; e < kPer; ++e) {
+    const int i = t + e * kFatBlock;
+    if (i < kNumBuckets) {
+      rank_b[e] = c_tab.rank_bucket[i];
+      s_start[i] = __hip_atomic_load(&a.ctr->bucket_items[i][0], __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < kPer; ++e) {
+    const int r = t + e * kFatBlock;
+    if (r < kNumBuckets) {
+      const uint32_t cnt = s_start[rank_b[e]];
+      s_cnt[r] = cnt;
+      s_pad[r] = (cnt + (kChunk - 1)) & ~(uint32_t)(kChunk - 1);
+    }
   }
   __syncthreads();
   {
@@ -158,38 +156,48 @@ __device__ void layout_buckets(const BatchArgs &a) {
   for (int r = t; r < kNumBuckets; r += kFatBlock) {
     const int b = c_tab.rank_bucket[r];
     a.ctr->bucket_start[b] = s_start[r];
-    for (uint32_t x = s_cnt[r]; x < s_pad[r]; ++x) a.items[s_start[r] + x] = make_uint2(kInvalidItem, 0u);
+    a.ctr->bucket_count[b] = s_cnt[r];
     a.ctr->bucket_items[b][0] = 0;
   }
   if (t < kQueues) a.ctr->queue_ctr[t][0] = 0;
-  for (int e = t; e < kTotCopies * (kNumSplits + 1); e += blockDim.x)
-    a.ctr->totals[e / (kNumSplits + 1)][e % (kNumSplits + 1)][0] = 0;
+  for (int e = t; e < kTotCopies * kFkBins; e += blockDim.x) a.ctr->fk_hist[e / kFkBins][e % kFkBins] = 0;
 }
-
-// One block, after k_bucketize: the bucket layout (the counts it needs are
-// final only once every k_bucketize block has added its own).
-__global__ __launch_bounds__(1024) void k_layout(BatchArgs a) { layout_buckets(a); }
 
 // Few, fat blocks: each block histograms many queries in LDS and then adds
 // one total per bucket to the global counters, so every global counter sees
-// only a handful of atomics.
+// only a handful of atomics.  The last block to finish (by a counter taken
+// after its atomics are done) then lays the buckets out, which needs every
+// block's counts; no block waits for another.
 __global__ __launch_bounds__(1024) void k_bucketize(BatchArgs a) {
   __shared__ int s_split;
   __shared__ uint32_t s_cnt[kNumBuckets];
   __shared__ uint32_t s_base[kNumBuckets];
-  __shared__ unsigned long long s_part[kTotCopies * (kNumSplits + 1)];
+  __shared__ uint32_t s_h[kFkBins];
   __shared__ unsigned long long s_tot[kNumSplits + 1];
 #pragma unroll
   for (int b = threadIdx.x; b < kNumBuckets; b += kFatBlock) s_cnt[b] = 0;
-  // the batch totals: every copy loaded at once (one load per thread), then summed
-  if (threadIdx.x < kTotCopies * (kNumSplits + 1))
-    s_part[threadIdx.x] =
-        a.ctr->totals[threadIdx.x / (kNumSplits + 1)][threadIdx.x % (kNumSplits + 1)][0];
+  if (threadIdx.x < kFkBins) s_h[threadIdx.x] = 0;
+  if (threadIdx.x <= kNumSplits) s_tot[threadIdx.x] = 0;
   __syncthreads();
-  if (threadIdx.x <= kNumSplits) {
-    unsigned long long v = 0;
-    for (int c = 0; c < kTotCopies; ++c) v += s_part[c * (kNumSplits + 1) + threadIdx.x];
-    s_tot[threadIdx.x] = v;
+  // The batch totals from the (F, k) histogram: its copies summed, then for
+  // each (bin, split) pair h * (items per query of that split), and at
+  // j = kNumSplits h * F!/(F-k)!.  Fixed strides, so each thread's loads are
+  // in flight together.
+#pragma unroll
+  for (int e = threadIdx.x; e < kTotCopies * kFkBins; e += kFatBlock) {
+    const uint32_t v = a.ctr->fk_hist[e / kFkBins][e % kFkBins];
+    if (v) atomicAdd(&s_h[e % kFkBins], v);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int e = threadIdx.x; e < kFkBins * (kNumSplits + 1); e += kFatBlock) {
+    const int bin = e / (kNumSplits + 1), j = e % (kNumSplits + 1);
+    const uint32_t h = s_h[bin];
+    if (h) {
+      const int F = bin / (kMaxK + 1), kk = bin % (kMaxK + 1);
+      const int d = j < kNumSplits ? (int)a.split_d[(size_t)bin * kNumSplits + j] : kk;
+      atomicAdd(&s_tot[j], (unsigned long long)h * c_tab.perm[F][d]);
+    }
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -256,43 +264,80 @@ __global__ __launch_bounds__(1024) void k_bucketize(BatchArgs a) {
     const int i = q0 + threadIdx.x + r * (int)blockDim.x;
     if (bk[r] >= 0) a.plan[i].item_off = s_base[bk[r]] + local[r];
   }
+  // Every count this block added came back from its atomic (s_base) before
+  // the barrier, so it is in place before the block takes its turn; the
+  // last block reads the counts with device-scope atomic loads.  No fence:
+  // a device-scope fence writes back the whole L2, which cost more than a
+  // separate launch.
+  __shared__ bool s_last;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    s_last = atomicAdd(&a.ctr->bucketize_done, 1u) == gridDim.x - 1u;
+  __syncthreads();
+  if (s_last) {
+    layout_buckets(a);
+    if (threadIdx.x == 0) a.ctr->bucketize_done = 0;
+  }
 }
 
 // ------------------------------------------------------------------ expand
 
 // Prefix item x of a query (0 <= x < F!/(F-d)!) is the x-th injective
-// d-tuple of free vertices in lexicographic order: digit t of x in the mixed
-// radix (F, F-1, ..., F-d+1) picks the digit-th smallest still-unused vertex.
-// Returns the tuple with the vertex of position t at bits 4t..4t+3.
-constexpr uint32_t kExpandSmall = 16;  // a lane writes up to this many items itself
-
-// Work-list fill: item slot base+x of a query holds (query, x).  One-wave
-// blocks own a range of queries; a lane fills a small query's items, the
-// whole wave a large one's.
-__global__ __launch_bounds__(64) void k_expand(BatchArgs a, int qpb) {
-  __shared__ int s_big[64];
-  __shared__ int s_nbig;
+// d-tuple of free vertices in lexicographic order (k_enumerate unranks it).
+//
+// Work-list fill: slot bucket_start + item_off + x of a query holds
+// (query, x).  A block owns qpb <= 256 consecutive queries: a scan of their
+// item counts lays their items end to end and the block's threads write that
+// sequence in order, so consecutive threads fill consecutive slots of one
+// query; each finds its slot's query by binary search over the scan.  The
+// query whose items end its bucket also writes the bucket's padding (invalid
+// items up to a whole chunk).
+constexpr int kExpandThreads = 256;
+__global__ __launch_bounds__(kExpandThreads) void k_expand(BatchArgs a, int qpb) {
+  __shared__ uint32_t s_end[kExpandThreads];  // inclusive scan of the item counts
+  __shared__ uint32_t s_dst[kExpandThreads];  // each query's first slot
+  __shared__ uint32_t s_wave[kExpandThreads / 64];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int q0 = blockIdx.x * qpb;
-  const int q1 = min(a.nq, q0 + qpb);
-  if (threadIdx.x == 0) s_nbig = 0;
-  __syncthreads();
-  for (int i = q0 + threadIdx.x; i < q1; i += blockDim.x) {
-    const Plan &p = a.plan[i];
-    if (p.status != kPlanOk) continue;
-    if (p.nitems > kExpandSmall) {
-      s_big[atomicAdd(&s_nbig, 1)] = i;
-      continue;
+  const int nloc = min(qpb, a.nq - q0);
+  uint32_t n = 0, dst = 0;
+  if (t < nloc) {
+    const Plan &p = a.plan[q0 + t];
+    if (p.status == kPlanOk) {
+      const uint32_t start = a.ctr->bucket_start[p.bucket];
+      const uint32_t cnt = a.ctr->bucket_count[p.bucket];
+      n = p.nitems;
+      dst = start + p.item_off;
+      if (p.item_off + n == cnt) {
+        const uint32_t pad = (cnt + (kChunk - 1)) & ~(uint32_t)(kChunk - 1);
+        for (uint32_t x = cnt; x < pad; ++x) a.items[start + x] = make_uint2(kInvalidItem, 0u);
+      }
     }
-    uint2 *dst = a.items + a.ctr->bucket_start[p.bucket] + p.item_off;
-    for (uint32_t x = 0; x < p.nitems; ++x) dst[x] = make_uint2((uint32_t)i, x);
   }
+  uint32_t incl = n;  // scan: within each wave, then the wave totals
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t o = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += o;
+  }
+  if (lane == 63) s_wave[wave] = incl;
   __syncthreads();
-  const int nbig = s_nbig;
-  for (int bi = 0; bi < nbig; ++bi) {
-    const int i = s_big[bi];
-    const Plan &p = a.plan[i];
-    uint2 *dst = a.items + a.ctr->bucket_start[p.bucket] + p.item_off;
-    for (uint32_t x = threadIdx.x; x < p.nitems; x += blockDim.x) dst[x] = make_uint2((uint32_t)i, x);
+  for (int w = 0; w < wave; ++w) incl += s_wave[w];
+  s_end[t] = incl;
+  s_dst[t] = dst;
+  __syncthreads();
+  const uint32_t total = s_end[nloc - 1];
+  for (uint32_t r = t; r < total; r += kExpandThreads) {
+    int lo = 0, hi = nloc - 1;  // the first query whose items end after slot r
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (s_end[mid] > r)
+        hi = mid;
+      else
+        lo = mid + 1;
+    }
+    const uint32_t x = r - (lo ? s_end[lo - 1] : 0u);
+    a.items[s_dst[lo] + x] = make_uint2((uint32_t)(q0 + lo), x);
   }
 }
 
@@ -417,12 +462,10 @@ hipError_t launch_batch_front(const BatchArgs &a, hipStream_t s) {
   if (gb < 64) gb = std::min<unsigned>(64, blocks_for(a.nq, 1024));
   if (gb < 1) gb = 1;
   hipLaunchKernelGGL(k_bucketize, dim3(gb), dim3(kFatBlock), 0, s, a);
-  hipLaunchKernelGGL(k_layout, dim3(1), dim3(kFatBlock), 0, s, a);
-  // one-wave blocks of at most 64 queries, and at least ~2048 blocks
-  int qpb = 64;
-  if (blocks_for(a.nq, qpb) < 2048) qpb = (int)((a.nq + 2047) / 2048);
-  if (qpb < 1) qpb = 1;
-  hipLaunchKernelGGL(k_expand, dim3(blocks_for(a.nq, qpb)), dim3(64), 0, s, a, qpb);
+  // about 2048 blocks of up to 256 queries each
+  int qpb = (int)((a.nq + 2047) / 2048);
+  qpb = std::max(1, std::min(qpb, kExpandThreads));
+  hipLaunchKernelGGL(k_expand, dim3(blocks_for(a.nq, qpb)), dim3(kExpandThreads), 0, s, a, qpb);
   return hipGetLastError();
 }
 
