@@ -97,8 +97,9 @@ extern "C" {
                                 fields are valid, nothing was committed           */
 #define MAPA_RES_INVALID 3   /* malformed query (device-pointer batches only;
                                 host-pointer batches are rejected up front)       */
-#define MAPA_RES_REFUSED 4   /* device-pointer wide batch beyond its embedding
-                                limit: nothing was evaluated or committed         */
+#define MAPA_RES_REFUSED 4   /* beyond the wide kernels' embedding limit (a
+                                device-pointer wide batch, or a served request):
+                                nothing was evaluated or committed                */
 
 /* ---- flags ------------------------------------------------------------------ */
 #define MAPA_DEVICE_PTRS 1u  /* array arguments are device pointers; the call is
@@ -492,8 +493,13 @@ int32_t mapa_measure_alu_peak(mapa_ctx *ctx, double *ops_per_s);
  * a batch only while the batch's prefix work-list estimate fits the admission
  * budget; otherwise it waits for the next batch (at the head of the line).  A
  * request asking for more accelerators than its server has free is answered
- * MAPA_RES_NOFIT on the host at once.  Every completion reports the busy mask
- * it was evaluated against, so each answer can be reproduced alone. */
+ * MAPA_RES_NOFIT on the host at once.  Requests the batch path does not take
+ * (a server of more than 16 accelerators, or k > 8) run in the same dispatch
+ * as a second device batch on the kernels of mapa_query_batch_wide, up to 256
+ * of them and 2^34 embeddings per dispatch (a single larger one runs alone);
+ * one of more than 2^36 embeddings on its free accelerators is answered
+ * MAPA_RES_REFUSED on the host.  Every completion reports the busy mask it
+ * was evaluated against, so each answer can be reproduced alone. */
 
 typedef struct {
   int32_t max_batch;       /* queries per device batch, 1..65536 (0: 4096)            */
@@ -518,7 +524,7 @@ typedef struct {           /* 40 bytes */
   int32_t reserved1;       /* must be 0                                                */
 } mapa_request;
 
-typedef struct {           /* 80 bytes */
+typedef struct {           /* 88 bytes */
   int64_t id;
   int64_t count;           /* matches scored                                           */
   int64_t alloc_handle;    /* (server << 32) | vertex_mask if granted, else -1         */
@@ -526,13 +532,13 @@ typedef struct {           /* 80 bytes */
   double wait_us;          /* queue wait: dispatch of its batch (or its host answer)
                               minus scheduled arrival; latency_us - wait_us is the
                               batch's turnaround                                       */
-  int32_t status;          /* MAPA_RES_OK or MAPA_RES_NOFIT                            */
+  int32_t status;          /* MAPA_RES_OK, MAPA_RES_NOFIT or MAPA_RES_REFUSED          */
   int32_t key, agg, pres;
   uint32_t vertex_mask;
   uint32_t busy_before;    /* the server's busy mask this request was answered against */
   int32_t batch;           /* device batch index; -1 if answered on the host           */
   int32_t server;
-  uint8_t mapping[8];
+  uint8_t mapping[16];     /* accelerator of each pattern vertex; 0xFF beyond k       */
 } mapa_completion;
 
 typedef struct {
@@ -558,8 +564,7 @@ int32_t mapa_serve_start(mapa_ctx *ctx, const mapa_serve_opts *opts);
 
 /* Queue n requests (host array, copied).  All-or-nothing validation: unknown
  * server -> MAPA_ERR_UNKNOWN_SERVER, malformed field or an arrival earlier
- * than the previous one -> MAPA_ERR_INVALID_ARG, k > 8 or a server of more
- * than 16 accelerators -> MAPA_ERR_UNSUPPORTED. */
+ * than the previous one -> MAPA_ERR_INVALID_ARG, k > 12 -> MAPA_ERR_UNSUPPORTED. */
 int32_t mapa_serve_submit(mapa_ctx *ctx, const mapa_request *reqs, int32_t n);
 
 /* Move up to cap finished requests into out (host array); *n_out = how many. */

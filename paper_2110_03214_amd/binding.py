@@ -100,8 +100,8 @@ COMPLETION_DTYPE = np.dtype([("id", np.int64), ("count", np.int64), ("alloc_hand
                              ("status", np.int32), ("key", np.int32),
                              ("agg", np.int32), ("pres", np.int32), ("vertex_mask", np.uint32),
                              ("busy_before", np.uint32), ("batch", np.int32),
-                             ("server", np.int32), ("mapping", np.uint8, 8)])
-assert REQUEST_DTYPE.itemsize == 40 and COMPLETION_DTYPE.itemsize == 80
+                             ("server", np.int32), ("mapping", np.uint8, 16)])
+assert REQUEST_DTYPE.itemsize == 40 and COMPLETION_DTYPE.itemsize == 88
 
 
 POLICY_PRESERVE, POLICY_GREEDY, POLICY_BASELINE = 0, 1, 2

@@ -9,7 +9,10 @@
 // The loop keeps a host mirror of every server's busy mask, updated from the
 // results of its own batches and the releases it issues, which lets it answer
 // requests that cannot fit (k > free accelerators) without a device batch
-// and estimate each request's prefix work-list for admission.
+// and estimate each request's prefix work-list for admission.  Requests the
+// batch path does not take (servers of more than 16 accelerators, or k > 8)
+// join the same dispatch as a second, wide batch on the same stream
+// (wide.hip's kernels on the slot's own buffers), admitted by embeddings.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -21,6 +24,7 @@
 #include <thread>
 
 #include "ctx.h"
+#include "wide.h"
 
 namespace mapa {
 
@@ -59,7 +63,24 @@ struct Slot {
   double t_dispatch = 0;
   std::vector<const Req *> reqs;
   std::vector<uint32_t> busy_before;
+  // the dispatch's wide batch
+  std::vector<const Req *> wreqs;
+  std::vector<uint32_t> wbusy_before;
+  mapa_query *h_wq = nullptr;          // pinned [kServeWideMax]
+  mapa_result_wide *h_wres = nullptr;  // pinned [kServeWideMax]
+  void *d_wide = nullptr;              // device: queries | results | wide scratch
 };
+
+// wide requests per dispatch, and the embeddings a wide batch is admitted up
+// to (a single request beyond it still runs alone; one beyond the wide
+// kernels' limit is answered MAPA_RES_REFUSED on the host)
+constexpr int32_t kServeWideMax = 256;
+constexpr unsigned long long kServeWideLeaves = 1ull << 34;
+constexpr size_t kServeWideResOff = ((size_t)kServeWideMax * sizeof(mapa_query) + 255) / 256 * 256;
+constexpr size_t kServeWideScratchOff =
+    kServeWideResOff + ((size_t)kServeWideMax * sizeof(mapa_result_wide) + 255) / 256 * 256;
+
+bool is_wide(int nvert, int k) { return nvert > kMaxN || k > kMaxK; }
 
 // one device batch in kGpuSample records timing events (mean_gpu_us)
 constexpr int64_t kGpuSample = 8;
@@ -237,6 +258,44 @@ int32_t harvest(ServeState *S, bool *did) {
       cpl.batch = sl.batch_id;
       cpl.server = s;
       std::memcpy(cpl.mapping, r.mapping, 8);
+      std::memset(cpl.mapping + 8, 0xFF, 8);
+      S->st.embeddings += r.count;
+      if (r.status == MAPA_RES_OK && r.alloc_handle >= 0) {
+        ++S->st.granted;
+        S->busy[s] |= r.vertex_mask;
+        if (rq.r.hold >= 0) {
+          const double unit = S->opts.time_unit_us > 0 ? S->opts.time_unit_us : 1.0;
+          S->held.push({now + rq.r.hold * unit, r.alloc_handle});
+        } else {
+          S->held_forever.push_back(r.alloc_handle);
+        }
+      } else {
+        ++S->st.nofit;
+      }
+      S->in_flight[s] = 0;
+      push_completion(S, cpl, now);
+      make_ready(S, s);
+    }
+    for (size_t i = 0; i < sl.wreqs.size(); ++i) {
+      const mapa_result_wide &r = sl.h_wres[i];
+      const Req &rq = *sl.wreqs[i];
+      const int32_t s = rq.r.server;
+      mapa_completion cpl;
+      std::memset(&cpl, 0, sizeof cpl);
+      cpl.id = rq.r.id;
+      cpl.count = r.count;
+      cpl.alloc_handle = r.alloc_handle;
+      cpl.latency_us = now - rq.due_us;
+      cpl.wait_us = sl.t_dispatch - rq.due_us;
+      cpl.status = r.status;
+      cpl.key = r.key;
+      cpl.agg = r.agg;
+      cpl.pres = r.pres;
+      cpl.vertex_mask = r.vertex_mask;
+      cpl.busy_before = sl.wbusy_before[i];
+      cpl.batch = sl.batch_id;
+      cpl.server = s;
+      std::memcpy(cpl.mapping, r.mapping, 16);
       S->st.embeddings += r.count;
       if (r.status == MAPA_RES_OK && r.alloc_handle >= 0) {
         ++S->st.granted;
@@ -258,6 +317,7 @@ int32_t harvest(ServeState *S, bool *did) {
     S->harvest_us_sum += S->now_us() - now;
     sl.active = false;
     sl.reqs.clear();
+    sl.wreqs.clear();
     *did = true;
   }
   flush_completions(S);
@@ -294,9 +354,11 @@ int32_t dispatch(ServeState *S, Slot &sl, bool final_release, bool *did) {
   const unsigned long long budget =
       S->opts.admission_items > 0 ? (unsigned long long)S->opts.admission_items
                                   : sl.ws.cap_items - (unsigned long long)kPadReserve - S->opts.max_batch;
-  unsigned long long items = 0;
+  unsigned long long items = 0, wleaves = 0;
   sl.reqs.clear();
   sl.busy_before.clear();
+  sl.wreqs.clear();
+  sl.wbusy_before.clear();
   std::vector<int32_t> keep;
   const size_t nready = S->ready.size();
   for (size_t it = 0; it < nready; ++it) {
@@ -304,23 +366,26 @@ int32_t dispatch(ServeState *S, Slot &sl, bool final_release, bool *did) {
     S->ready.pop_front();
     S->in_ready[s] = 0;
     if (S->in_flight[s]) continue;
-    // requests that cannot fit are answered here, in order
+    // requests that cannot fit, or that would exceed the wide kernels'
+    // embedding limit, are answered here, in order
     while (!S->fifo_empty(s)) {
       const Req &rq = *S->fhead[s];
       const int F = S->nvert[s] - __builtin_popcount(S->busy[s]);
-      if ((int)rq.r.k <= F) break;
+      const bool refuse = (int)rq.r.k <= F && is_wide(S->nvert[s], rq.r.k) &&
+                          wide_embeddings(F, rq.r.k) > kWideMaxLeaves;
+      if ((int)rq.r.k <= F && !refuse) break;
       mapa_completion cpl;
       std::memset(&cpl, 0, sizeof cpl);
       cpl.id = rq.r.id;
       cpl.alloc_handle = -1;
       cpl.latency_us = now - rq.due_us;
       cpl.wait_us = cpl.latency_us;
-      cpl.status = MAPA_RES_NOFIT;
+      cpl.status = refuse ? MAPA_RES_REFUSED : MAPA_RES_NOFIT;
       cpl.key = INT32_MIN;
       cpl.busy_before = S->busy[s];
       cpl.batch = -1;
       cpl.server = s;
-      std::memset(cpl.mapping, 0xFF, 8);
+      std::memset(cpl.mapping, 0xFF, sizeof cpl.mapping);
       ++S->st.nofit;
       ++S->st.host_nofit;
       push_completion(S, cpl, now);
@@ -330,6 +395,24 @@ int32_t dispatch(ServeState *S, Slot &sl, bool final_release, bool *did) {
     if (S->fifo_empty(s)) continue;
     const Req *rq = S->fhead[s];
     const int F = S->nvert[s] - __builtin_popcount(S->busy[s]);
+    if (is_wide(S->nvert[s], rq->r.k)) {  // the dispatch's wide batch, admitted by embeddings
+      const unsigned long long e = wide_embeddings(F, rq->r.k);
+      if ((int32_t)sl.wreqs.size() >= kServeWideMax) {
+        keep.push_back(s);
+        continue;
+      }
+      if (!sl.wreqs.empty() && wleaves + e > kServeWideLeaves) {
+        ++S->st.admission_waits;
+        keep.push_back(s);
+        continue;
+      }
+      wleaves += e;
+      sl.wreqs.push_back(rq);
+      sl.wbusy_before.push_back(S->busy[s]);
+      S->in_flight[s] = 1;
+      S->fifo_pop(s);
+      continue;
+    }
     const unsigned long long est = S->work.items[F][rq->r.k];
     if ((int32_t)sl.reqs.size() >= S->opts.max_batch) {
       keep.push_back(s);
@@ -351,7 +434,7 @@ int32_t dispatch(ServeState *S, Slot &sl, bool final_release, bool *did) {
     S->ready.push_front(*it);
   }
   flush_completions(S);  // host answers
-  if (rel.empty() && sl.reqs.empty()) return MAPA_OK;
+  if (rel.empty() && sl.reqs.empty() && sl.wreqs.empty()) return MAPA_OK;
   *did = true;
 
   // 3. enqueue: releases first (ordered before this batch and, through
@@ -429,15 +512,51 @@ int32_t dispatch(ServeState *S, Slot &sl, bool final_release, bool *did) {
       S->error_msg = "batch enqueue failed";
       return rc;
     }
+    if (sl.timed && sl.wreqs.empty()) SERVE_CHK(hipEventRecord(sl.g1, sl.stream));
+  }
+  if (!sl.wreqs.empty()) {
+    const int32_t nw = (int32_t)sl.wreqs.size();
+    for (int32_t i = 0; i < nw; ++i) {
+      const mapa_request &r = sl.wreqs[i]->r;
+      mapa_query &q = sl.h_wq[i];
+      q.server = r.server;
+      q.kind = r.kind;
+      q.k = r.k;
+      q.mode = r.mode;
+      q.commit = 1;
+      q.a = r.a;
+      q.b = r.b;
+      q.metric = r.metric;
+    }
+    if (sl.reqs.empty()) {
+      sl.timed = S->st.batches % kGpuSample == 0;
+      if (sl.timed) SERVE_CHK(hipEventRecord(sl.g0, sl.stream));
+    }
+    char *dw = static_cast<char *>(sl.d_wide);
+    WideArgs w;
+    wide_ctx_args(c, w);
+    wide_scratch_args(dw + kServeWideScratchOff, nw, w);
+    w.q = reinterpret_cast<const mapa_query *>(dw);
+    w.nq = nw;
+    w.res = reinterpret_cast<mapa_result_wide *>(dw + kServeWideResOff);
+    w.self_check_failures = &sl.ws.d_ctr->self_check_failures;
+    SERVE_CHK(hipMemcpyAsync(dw, sl.h_wq, nw * sizeof(mapa_query), hipMemcpyHostToDevice, sl.stream));
+    SERVE_CHK(launch_wide_plan(w, sl.stream));
+    SERVE_CHK(launch_wide_search(w, sl.stream));
+    SERVE_CHK(launch_wide_finalize(w, sl.stream));
+    SERVE_CHK(hipMemcpyAsync(sl.h_wres, w.res, nw * sizeof(mapa_result_wide), hipMemcpyDeviceToHost,
+                             sl.stream));
     if (sl.timed) SERVE_CHK(hipEventRecord(sl.g1, sl.stream));
+  }
+  if (!sl.reqs.empty() || !sl.wreqs.empty()) {
     sl.batch_id = S->next_batch++;
     sl.t_dispatch = now;
     S->dispatch_us_sum += S->now_us() - now;
     ++S->st.batches;
-    S->batched_queries += nq;
+    S->batched_queries += (int64_t)sl.reqs.size() + (int64_t)sl.wreqs.size();
   }
   SERVE_CHK(hipEventRecord(sl.done, sl.stream));
-  sl.active = !sl.reqs.empty();
+  sl.active = !sl.reqs.empty() || !sl.wreqs.empty();
   sl.stream_busy = true;
   return MAPA_OK;
 }
@@ -513,6 +632,9 @@ void free_state(ServeState *S) {
     if (sl.h_q) (void)hipHostFree(sl.h_q);
     if (sl.h_res) (void)hipHostFree(sl.h_res);
     if (sl.h_rel) (void)hipHostFree(sl.h_rel);
+    if (sl.h_wq) (void)hipHostFree(sl.h_wq);
+    if (sl.h_wres) (void)hipHostFree(sl.h_wres);
+    if (sl.d_wide) (void)hipFree(sl.d_wide);
     if (sl.done) (void)hipEventDestroy(sl.done);
     if (sl.g0) (void)hipEventDestroy(sl.g0);
     if (sl.g1) (void)hipEventDestroy(sl.g1);
@@ -567,6 +689,8 @@ int32_t mapa_serve_start(mapa_ctx *c, const mapa_serve_opts *opts) {
   if (c->server_topo.empty()) return fail(MAPA_ERR_UNKNOWN_SERVER, "no servers created");
   int32_t rc = sync_ctx(c);
   if (rc) return rc;
+  rc = wide_upload(c);  // the wide batches read every topology's rows
+  if (rc) return rc;
   ServeState *S = new ServeState();
   S->c = c;
   S->opts = o;
@@ -597,7 +721,10 @@ int32_t mapa_serve_start(mapa_ctx *c, const mapa_serve_opts *opts) {
         hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess ||
         hipEventCreate(&sl.g0) != hipSuccess || hipEventCreate(&sl.g1) != hipSuccess ||
         hipHostMalloc((void **)&sl.h_q, o.max_batch * sizeof(mapa_query), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void **)&sl.h_res, o.max_batch * sizeof(mapa_result), hipHostMallocDefault) != hipSuccess)
+        hipHostMalloc((void **)&sl.h_res, o.max_batch * sizeof(mapa_result), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&sl.h_wq, kServeWideMax * sizeof(mapa_query), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&sl.h_wres, kServeWideMax * sizeof(mapa_result_wide), hipHostMallocDefault) != hipSuccess ||
+        hipMalloc(&sl.d_wide, kServeWideScratchOff + wide_scratch_bytes(kServeWideMax)) != hipSuccess)
       return bail(MAPA_ERR_DEVICE, "stream, event or pinned buffers");
   }
   if (hipDeviceSynchronize() != hipSuccess) return bail(MAPA_ERR_DEVICE, "device sync");
@@ -620,10 +747,7 @@ int32_t mapa_serve_submit(mapa_ctx *c, const mapa_request *reqs, int32_t n) {
     const mapa_request &r = reqs[i];
     if (r.server < 0 || (size_t)r.server >= c->server_topo.size())
       return fail(MAPA_ERR_UNKNOWN_SERVER, "request %d: unknown server %d", i, r.server);
-    if (r.k > kMaxK) return fail(MAPA_ERR_UNSUPPORTED, "request %d: k=%d > %d", i, r.k, kMaxK);
-    if (c->topo_n[c->server_topo[r.server]] > kMaxN)
-      return fail(MAPA_ERR_UNSUPPORTED, "request %d: server %d has more than %d accelerators", i,
-                  r.server, kMaxN);
+    if (r.k > kWideK) return fail(MAPA_ERR_UNSUPPORTED, "request %d: k=%d > %d", i, r.k, kWideK);
     if (r.kind > MAPA_TREE) {
       const int id = r.kind - MAPA_PATTERN_BASE;
       if (id < 0 || id >= c->npat || c->pat_k[id] != r.k)

@@ -14,13 +14,6 @@ namespace mapa {
 
 namespace {
 
-unsigned long long perm_wide(int F, int d) {  // F!/(F-d)!, 0 if d > F
-  if (d > F) return 0;
-  unsigned long long v = 1;
-  for (int i = 0; i < d; ++i) v *= (unsigned long long)(F - i);
-  return v;
-}
-
 // Upload the planes of topologies added since the last wide call.
 int32_t upload_wide_rows(mapa_ctx *c) {
   const size_t T = c->wide_W.size();
@@ -80,6 +73,50 @@ int32_t validate_wide(const mapa_ctx *c, const mapa_query &q, int32_t i) {
 
 }  // namespace
 
+unsigned long long wide_embeddings(int F, int k) {
+  if (k > F) return 0;
+  unsigned long long v = 1;
+  for (int i = 0; i < k; ++i) v *= (unsigned long long)(F - i);
+  return v;
+}
+
+int32_t wide_upload(mapa_ctx *c) {
+  if (c->wide_uploaded == c->wide_W.size()) return MAPA_OK;
+  if (int32_t rc = sync_ctx(c)) return rc;
+  return upload_wide_rows(c);
+}
+
+void wide_ctx_args(const mapa_ctx *c, WideArgs &w) {
+  w.rows = c->d_wide_rows;
+  w.server_topo = c->d_server_topo;
+  w.topo_n = c->d_topo_n;
+  w.topo_maxw = c->d_topo_maxw;
+  w.nservers = (int32_t)c->server_topo.size();
+  w.ntopo_wide = (int32_t)c->wide_uploaded;
+  w.pat_nbtab = c->d_pat_nbtab;
+  w.pat_k = c->d_pat_k;
+  w.eff_rank = c->d_eff_rank;
+  w.eff_key = c->d_eff_key;
+  w.busy = c->d_busy;
+  w.commit_slot = c->d_commit_slot;
+}
+
+namespace {
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+}  // namespace
+
+size_t wide_scratch_bytes(int32_t nq) {
+  return align256(256 + align256((size_t)nq * sizeof(WidePlan)) +
+                  (size_t)nq * kWideMaxBlocksPerQuery * sizeof(WidePartial));
+}
+
+void wide_scratch_args(void *base, int32_t nq, WideArgs &w) {
+  char *b = static_cast<char *>(base);
+  w.total = reinterpret_cast<unsigned long long *>(b);
+  w.plan = reinterpret_cast<WidePlan *>(b + 256);
+  w.part = reinterpret_cast<WidePartial *>(b + 256 + align256((size_t)nq * sizeof(WidePlan)));
+}
+
 }  // namespace mapa
 
 using namespace mapa;
@@ -100,10 +137,10 @@ extern "C" int32_t mapa_query_batch_wide(mapa_ctx *c, const mapa_query *q, int32
   if (nq == 0) return MAPA_OK;
   if (c->server_topo.empty()) return fail(MAPA_ERR_UNKNOWN_SERVER, "no servers created");
   if (hipSetDevice(c->device) != hipSuccess) return fail(MAPA_ERR_DEVICE, "hipSetDevice failed");
-  if (!dev || c->wide_uploaded != c->wide_W.size()) {
+  if (!dev) {
     if (int32_t rc = sync_ctx(c)) return rc;
-    if (int32_t rc = upload_wide_rows(c)) return rc;
   }
+  if (int32_t rc = wide_upload(c)) return rc;
   if (!dev) {
     // admission: the embeddings of the whole call, on the free sets at its start
     std::vector<uint32_t> busy(c->server_topo.size());
@@ -112,19 +149,16 @@ extern "C" int32_t mapa_query_batch_wide(mapa_ctx *c, const mapa_query *q, int32
     for (int32_t i = 0; i < nq; ++i) {
       const int n = c->topo_n[c->server_topo[q[i].server]];
       const uint32_t all = n >= 32 ? 0xFFFFFFFFu : (1u << n) - 1u;
-      leaves += perm_wide(__builtin_popcount(~busy[q[i].server] & all), q[i].k);
+      leaves += wide_embeddings(__builtin_popcount(~busy[q[i].server] & all), q[i].k);
       if (leaves > kWideMaxLeaves)
         return fail(MAPA_ERR_ADMISSION, "wide batch exceeds %llu embeddings at query %d", kWideMaxLeaves, i);
     }
   }
 
-  // one device buffer: embedding total | plans | partials | (host form) queries | results
-  auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
-  const size_t o_plan = 256;
-  const size_t o_part = align(o_plan + (size_t)nq * sizeof(WidePlan));
-  const size_t o_q = align(o_part + (size_t)nq * kWideMaxBlocksPerQuery * sizeof(WidePartial));
-  const size_t o_res = align(o_q + (dev ? 0 : (size_t)nq * sizeof(mapa_query)));
-  const size_t bytes = align(o_res + (dev ? 0 : (size_t)nq * sizeof(mapa_result_wide)));
+  // one device buffer: scratch (embedding total, plans, partials) | (host form) queries | results
+  const size_t o_q = wide_scratch_bytes(nq);
+  const size_t o_res = o_q + (dev ? 0 : ((size_t)nq * sizeof(mapa_query) + 255) / 256 * 256);
+  const size_t bytes = o_res + (dev ? 0 : (size_t)nq * sizeof(mapa_result_wide));
   if (bytes > c->wide_buf.cap) {
     if (int32_t rc = sync_ctx(c)) return rc;  // earlier calls may still use the old buffer
     if (c->wide_buf.d) (void)hipFree(c->wide_buf.d);
@@ -136,25 +170,12 @@ extern "C" int32_t mapa_query_batch_wide(mapa_ctx *c, const mapa_query *q, int32
   }
   char *base = static_cast<char *>(c->wide_buf.d);
   WideArgs w;
+  wide_ctx_args(c, w);
+  wide_scratch_args(base, nq, w);
   w.q = dev ? q : reinterpret_cast<const mapa_query *>(base + o_q);
   w.nq = nq;
-  w.plan = reinterpret_cast<WidePlan *>(base + o_plan);
-  w.part = reinterpret_cast<WidePartial *>(base + o_part);
-  w.rows = c->d_wide_rows;
-  w.server_topo = c->d_server_topo;
-  w.topo_n = c->d_topo_n;
-  w.topo_maxw = c->d_topo_maxw;
-  w.nservers = (int32_t)c->server_topo.size();
-  w.ntopo_wide = (int32_t)c->wide_uploaded;
-  w.pat_nbtab = c->d_pat_nbtab;
-  w.pat_k = c->d_pat_k;
-  w.eff_rank = c->d_eff_rank;
-  w.eff_key = c->d_eff_key;
-  w.busy = c->d_busy;
-  w.commit_slot = c->d_commit_slot;
   w.res = dev ? res : reinterpret_cast<mapa_result_wide *>(base + o_res);
   w.self_check_failures = &c->ws.d_ctr->self_check_failures;
-  w.total = reinterpret_cast<unsigned long long *>(base);
   hipStream_t s = dev ? reinterpret_cast<hipStream_t>(stream) : c->internal;
   MAPA_HIPCHK(hipStreamWaitEvent(s, c->last, 0));
   if (!dev)

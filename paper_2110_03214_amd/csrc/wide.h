@@ -69,6 +69,17 @@ struct WideArgs {
   unsigned long long *total;  // embeddings of the call (each query's share capped at 2^37)
 };
 
+// Host side (wide.cpp), for mapa_query_batch_wide and the serving loop:
+// upload the rows of topologies added since the last upload (waits for the
+// context's work first); the context's part of the arguments (rows,
+// topologies, patterns, Eq. 2 tables, busy masks, commit claims); and the
+// call's device scratch: embedding total | plans | partials of nq queries.
+int32_t wide_upload(mapa_ctx *c);
+void wide_ctx_args(const mapa_ctx *c, WideArgs &w);
+size_t wide_scratch_bytes(int32_t nq);
+void wide_scratch_args(void *base, int32_t nq, WideArgs &w);
+unsigned long long wide_embeddings(int F, int k);  // F!/(F-k)!, 0 if k > F
+
 hipError_t launch_wide_plan(const WideArgs &w, hipStream_t s);  // clears total, then plans
 hipError_t launch_wide_search(const WideArgs &w, hipStream_t s);  // nq * kWideMaxBlocksPerQuery blocks
 hipError_t launch_wide_finalize(const WideArgs &w, hipStream_t s);

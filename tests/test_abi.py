@@ -250,7 +250,7 @@ def test_simulation_validation(vctx):
     assert code_of(lambda: vctx.simulate([s0, s2], [0, 1], off, late)) == B.ERR_INVALID_ARG
     assert code_of(lambda: vctx.simulate([s0, s2], [0, 2], off, jobs)) == B.ERR_NO_DEVICE
     assert B.JOB_DTYPE.itemsize == 16 and B.JOB_LOG_DTYPE.itemsize == 48
-    assert B.COMPLETION_DTYPE.itemsize == 80
+    assert B.COMPLETION_DTYPE.itemsize == 88
 
 
 def test_tuning_knobs_and_cached_tunings_validate(vctx):
