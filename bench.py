@@ -306,14 +306,14 @@ def autotune_into(B, ctx, wl, qh, path):
 
 
 def timed_batch(B, wl, steps, warmup, metric="weighted", wide=False, profile=True, tuning="cache",
-                autotune=None, step_pass=False):
+                autotune=None, step_pass=True):
     """The batched form: `steps` timed steps (query batch with commits, then
     release of every handle) after `warmup` untimed ones, inputs resident in
     HBM.  Kernel time from HIP events on the launch stream over the timed
-    region.  Validates after the timed region.  With `step_pass` (steps of
-    ~0.1 ms, where an event record between kernels shows in the step time),
-    the step time comes from a first pass of `steps` steps with nothing
-    recorded between them, and per-step latency and kernel time from a
+    region.  Validates after the timed region.  With `step_pass` (the
+    default) the step time comes from a first pass of `steps` steps with
+    nothing recorded between them (an event record between kernels adds
+    ~15 us to a ~0.15 ms step), and per-step latency and kernel time from a
     second pass of `steps` steps with the events."""
     import torch
     ops = op_counts(wl)
@@ -640,7 +640,7 @@ def main():
         f"embeddings/step")
     ctx, tb = timed_batch(B, wl, args.steps, args.warmup, args.metric, wide=args.config == 6,
                           profile=not args.no_profile, tuning=args.tuning, autotune=args.autotune,
-                          step_pass=args.config == 2)
+                          step_pass=True)
     log(f"[bench] {args.steps} steps in {tb['wall_s']:.3f} s; kernel "
         f"{tb['kernel_ms'] if tb['kernel_ms'] else float('nan'):.3f} ms avg")
     lat = tb["lat_ms"]
