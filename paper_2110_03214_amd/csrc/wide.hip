@@ -332,44 +332,54 @@ __device__ __forceinline__ void triple_table(const WideCtx &s, WideLane &L, uint
     Yb[j] = s.nb_all ? Xb[j] : wsum_b<2>(s.rows, 2, c3[j], nbm_pb);
     KA[j] = kp + s.a * wsum_b<2>(s.rows, 2, c3[j], nbm_a) - s.b * D3[j];
   }
+  // The weights among the N3 candidates as one word per candidate: field m
+  // (bits 2m, 2m+1) of lw[j] = W[c_j][c_m].  Each pair is read once from the
+  // packed rows and entered in both words; every later read is a field at a
+  // fixed offset.
+  uint32_t lw[N3];
+#pragma unroll
+  for (int j = 0; j < N3; ++j) lw[j] = 0;
+#pragma unroll
+  for (int j = 0; j < N3; ++j) {
+    const uint32_t w0 = s.pw[2 * c3[j]], w1 = s.pw[2 * c3[j] + 1];
+#pragma unroll
+    for (int m = j + 1; m < N3; ++m) {
+      const uint32_t f = ((hi3[m] ? w1 : w0) >> sh3[m]) & 3u;
+      lw[j] |= f << (2 * m);
+      lw[m] |= f << (2 * j);
+    }
+  }
   const int g32 = 32 * (s.a * alpha + s.b);
   L.count += (unsigned long long)(N3 * N * (N - 1));
   const int sha = 5 * (kWideK - 1 - a), shp = sha - 5;
 #pragma unroll
   for (int ia = 0; ia < N3; ++ia) {
-    const int ca = c3[ia];
-    const uint32_t wa0 = s.pw[2 * ca], wa1 = s.pw[2 * ca + 1];
-    int c[N], P[N], Q[N];
-    uint32_t sh2[N];
-    bool hi[N];
+    // tables of the last two positions over the candidates other than c_a
+    int P[N3], Q[N3];
 #pragma unroll
-    for (int j = 0, jj = 0; j < N3; ++j) {
+    for (int j = 0; j < N3; ++j) {
       if (j == ia) continue;
-      const int w = (int)(((hi3[j] ? wa1 : wa0) >> sh3[j]) & 3u);
+      const int w = (int)((lw[ia] >> (2 * j)) & 3u);  // W[c_a][c_j]
       const int D = D3[j] - w;
       const int X = Xb[j] + bx * w;
       const int Y = Yb[j] + by * w;
-      c[jj] = c3[j];
-      sh2[jj] = sh3[j];
-      hi[jj] = hi3[j];
-      P[jj] = 32 * (s.a * X - s.b * D) - c3[j];
-      Q[jj] = s.a * Y - s.b * D;
-      ++jj;
+      P[j] = 32 * (s.a * X - s.b * D) - c3[j];
+      Q[j] = s.a * Y - s.b * D;
     }
     const uint32_t base = (uint32_t)(32 * KA[ia] + 63);
-    const unsigned long long code_a = code | ((unsigned long long)ca << sha);
+    const unsigned long long code_a = code | ((unsigned long long)c3[ia] << sha);
 #pragma unroll
-    for (int i = 0; i < N; ++i) {
-      const uint32_t w0 = s.pw[2 * c[i]], w1 = s.pw[2 * c[i] + 1];
+    for (int i = 0; i < N3; ++i) {
+      if (i == ia) continue;
       int tb = INT_MIN;
 #pragma unroll
-      for (int j = 0; j < N; ++j) {
-        if (j == i) continue;
-        const int t = P[j] + g32 * (int)(((hi[j] ? w1 : w0) >> sh2[j]) & 3u);
+      for (int j = 0; j < N3; ++j) {
+        if (j == i || j == ia) continue;
+        const int t = P[j] + g32 * (int)((lw[i] >> (2 * j)) & 3u);
         tb = t > tb ? t : tb;
       }
       const uint32_t pk = base + (uint32_t)(32 * Q[i]) + (uint32_t)tb;
-      keep_best(L, pk, code_a | ((unsigned long long)c[i] << shp), shp - 5);
+      keep_best(L, pk, code_a | ((unsigned long long)c3[i] << shp), shp - 5);
     }
   }
 }
