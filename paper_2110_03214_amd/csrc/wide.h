@@ -11,6 +11,11 @@ constexpr int kWideN = MAPA_MAX_N_WIDE;
 constexpr int kWideK = MAPA_MAX_K_WIDE;
 constexpr int kWidePlanes = 9;  // rows per topology: weight bit-planes 0..7, then adjacency
 constexpr int kWideThreads = 256;
+// Open positions on a thread's LDS stack: the search keeps positions d .. top-1
+// there, where the prefix depth d >= 1 whenever k >= 2 (the plan extends the
+// prefix while it has fewer than kWideMinItems items, and one item never
+// does) and top <= k - 2 <= 10, so position p sits at entry p - 1 < 9.
+constexpr int kWideStack = kWideK - 3;
 // Every query owns this many consecutive blocks of the search grid; a query
 // that needs fewer leaves the rest idle (they write an empty partial).
 constexpr int kWideMaxBlocksPerQuery = 128;

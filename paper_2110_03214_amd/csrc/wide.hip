@@ -225,6 +225,8 @@ __device__ __forceinline__ void pair_table(const WideCtx &s, WideLane &L, uint32
   const uint32_t base = (uint32_t)(32 * kp + 63);
   L.count += (unsigned long long)(N * (N - 1));
   const int sh = 5 * (kWideK - 1 - p);
+  uint32_t sbest = 0;  // the step's best leaf and its row, as in triple_table
+  int sci = 0;
 #pragma unroll
   for (int i = 0; i < N; ++i) {
     int tb = INT_MIN;
@@ -247,8 +249,11 @@ __device__ __forceinline__ void pair_table(const WideCtx &s, WideLane &L, uint32
       }
     }
     const uint32_t pk = base + (uint32_t)(32 * Q[i]) + (uint32_t)tb;
-    keep_best(L, pk, code | ((unsigned long long)c[i] << sh), sh - 5);
+    const bool up = pk > (sbest | 31u);
+    sbest = up ? pk : sbest;
+    sci = up ? c[i] : sci;
   }
+  keep_best(L, sbest, code | ((unsigned long long)sci << sh), sh - 5);
 }
 
 // The last two positions without the table (LINKED mode, or more free
@@ -352,6 +357,21 @@ __device__ __forceinline__ void triple_table(const WideCtx &s, WideLane &L, uint
   const int g32 = 32 * (s.a * alpha + s.b);
   L.count += (unsigned long long)(N3 * N * (N - 1));
   const int sha = 5 * (kWideK - 1 - a), shp = sha - 5;
+  // The two-position terms before c_a is chosen, and what one unit of
+  // W[c_j][c_a] adds to them: D loses it, X and Y gain it where a
+  // neighbours q or p, so P gains 32 (a bx + b) and Q gains a by + b per unit.
+  int P3[N3], Q3[N3];
+#pragma unroll
+  for (int j = 0; j < N3; ++j) {
+    P3[j] = 32 * (s.a * Xb[j] - s.b * D3[j]) - c3[j];
+    Q3[j] = s.a * Yb[j] - s.b * D3[j];
+  }
+  const int dP = 32 * (s.a * bx + s.b), dQ = s.a * by + s.b;
+  // the step's best leaf and its first two vertices; rows come in
+  // lexicographic order, so a row replaces it only with a strictly larger
+  // key (as keep_best), and the lane's best is updated once at the end
+  uint32_t sbest = 0;
+  int sca = 0, sci = 0;
 #pragma unroll
   for (int ia = 0; ia < N3; ++ia) {
     // tables of the last two positions over the candidates other than c_a
@@ -360,14 +380,10 @@ __device__ __forceinline__ void triple_table(const WideCtx &s, WideLane &L, uint
     for (int j = 0; j < N3; ++j) {
       if (j == ia) continue;
       const int w = (int)((lw[ia] >> (2 * j)) & 3u);  // W[c_a][c_j]
-      const int D = D3[j] - w;
-      const int X = Xb[j] + bx * w;
-      const int Y = Yb[j] + by * w;
-      P[j] = 32 * (s.a * X - s.b * D) - c3[j];
-      Q[j] = s.a * Y - s.b * D;
+      P[j] = P3[j] + dP * w;
+      Q[j] = Q3[j] + dQ * w;
     }
     const uint32_t base = (uint32_t)(32 * KA[ia] + 63);
-    const unsigned long long code_a = code | ((unsigned long long)c3[ia] << sha);
 #pragma unroll
     for (int i = 0; i < N3; ++i) {
       if (i == ia) continue;
@@ -379,9 +395,13 @@ __device__ __forceinline__ void triple_table(const WideCtx &s, WideLane &L, uint
         tb = t > tb ? t : tb;
       }
       const uint32_t pk = base + (uint32_t)(32 * Q[i]) + (uint32_t)tb;
-      keep_best(L, pk, code_a | ((unsigned long long)c3[i] << shp), shp - 5);
+      const bool up = pk > (sbest | 31u);
+      sbest = up ? pk : sbest;
+      sca = up ? c3[ia] : sca;
+      sci = up ? c3[i] : sci;
     }
   }
+  keep_best(L, sbest, code | ((unsigned long long)sca << sha) | ((unsigned long long)sci << shp), shp - 5);
 }
 
 // The step that finishes a prefix from position `at`: the three-position
@@ -428,13 +448,13 @@ __device__ __forceinline__ void expand_prefix(const WideCtx &s, WideLane &L, uin
   {
     uint32_t nbm, cand;
     wide_masks(s, code, d, rest, 0u, nbm, cand);
-    stk_cand[d * kWideThreads + tid] = cand;
-    stk_kp[d * kWideThreads + tid] = kp;
-    stk_nbm[d * kWideThreads + tid] = nbm;
+    stk_cand[(d - 1) * kWideThreads + tid] = cand;
+    stk_kp[(d - 1) * kWideThreads + tid] = kp;
+    stk_nbm[(d - 1) * kWideThreads + tid] = nbm;
   }
   int pos = d;
   for (;;) {
-    const uint32_t cand = stk_cand[pos * kWideThreads + tid];
+    const uint32_t cand = stk_cand[(pos - 1) * kWideThreads + tid];
     if (cand == 0) {  // position exhausted: back to the previous one
       if (pos == d) break;
       --pos;
@@ -444,9 +464,9 @@ __device__ __forceinline__ void expand_prefix(const WideCtx &s, WideLane &L, uin
       continue;
     }
     const int c = __builtin_ctz(cand);
-    stk_cand[pos * kWideThreads + tid] = cand & (cand - 1);
-    const uint32_t nbm = stk_nbm[pos * kWideThreads + tid];
-    const int kpc = step_key<B>(s, stk_kp[pos * kWideThreads + tid], c, nbm, rest);
+    stk_cand[(pos - 1) * kWideThreads + tid] = cand & (cand - 1);
+    const uint32_t nbm = stk_nbm[(pos - 1) * kWideThreads + tid];
+    const int kpc = step_key<B>(s, stk_kp[(pos - 1) * kWideThreads + tid], c, nbm, rest);
     rest &= ~(1u << c);
     code |= (unsigned long long)c << (5 * (kWideK - 1 - pos));
     if (pos + 1 == top) {
@@ -458,9 +478,9 @@ __device__ __forceinline__ void expand_prefix(const WideCtx &s, WideLane &L, uin
     ++pos;
     uint32_t nbm2, cand2;
     wide_masks(s, code, pos, rest, 0u, nbm2, cand2);
-    stk_cand[pos * kWideThreads + tid] = cand2;
-    stk_kp[pos * kWideThreads + tid] = kpc;
-    stk_nbm[pos * kWideThreads + tid] = nbm2;
+    stk_cand[(pos - 1) * kWideThreads + tid] = cand2;
+    stk_kp[(pos - 1) * kWideThreads + tid] = kpc;
+    stk_nbm[(pos - 1) * kWideThreads + tid] = nbm2;
   }
 }
 
@@ -607,17 +627,18 @@ __global__ __launch_bounds__(256) void k_wide_plan(WideArgs w) {
   w.plan[i] = p;
 }
 
-// Register use is left to the compiler (143 VGPRs, 3 waves per SIMD, no
-// scratch): capped at 128 VGPRs (4 waves, which the 38 KB LDS stack would
-// allow) it spilled 52 bytes per lane, 14 MB of scratch writes per call on
-// the wide workload, for 4 % less time.
-__global__ __launch_bounds__(kWideThreads) void k_wide_search(WideArgs w) {
+// Four waves per SIMD: 128 VGPRs (135 uncapped), 37 KB of LDS per block
+// (the nine-entry stack and the Eq. 2 ranks).  The cap leaves a few
+// bytes per lane in scratch that stay in cache: the wide workload's HBM
+// writes are the same 0.59 MB per call with and without it, and the call
+// takes 3.37 instead of 3.53 ms.
+__global__ __launch_bounds__(kWideThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_wide_search(WideArgs w) {
   __shared__ uint32_t s_rows[kWidePlanes * 32];
   __shared__ uint32_t s_pw[64];
   __shared__ uint16_t s_nb[kWideK];
-  __shared__ uint32_t s_cand[kWideK * kWideThreads];
-  __shared__ int s_kp[kWideK * kWideThreads];
-  __shared__ uint32_t s_nbm[kWideK * kWideThreads];
+  __shared__ uint32_t s_cand[kWideStack * kWideThreads];
+  __shared__ int s_kp[kWideStack * kWideThreads];
+  __shared__ uint32_t s_nbm[kWideStack * kWideThreads];
   __shared__ unsigned long long s_cnt[kWideThreads / 64], s_code[kWideThreads / 64];
   __shared__ int s_key[kWideThreads / 64];
   __shared__ uint16_t s_erank[kWideEffTab];
