@@ -286,19 +286,22 @@ __global__ __launch_bounds__(1024) void k_bucketize(BatchArgs a) {
 // d-tuple of free vertices in lexicographic order (k_enumerate unranks it).
 //
 // Work-list fill: slot bucket_start + item_off + x of a query holds
-// (query, x).  A block owns qpb <= 256 consecutive queries: a scan of their
-// item counts lays their items end to end and the block's threads write that
-// sequence in order, so consecutive threads fill consecutive slots of one
-// query; each finds its slot's query by binary search over the scan.  The
+// (query, x).  A group of bpg blocks owns qpb <= 256 consecutive queries: a
+// scan of their item counts lays their items end to end and the group's
+// threads write that sequence in order (block g of the group takes every
+// bpg-th run of 256 slots), so consecutive threads fill consecutive slots of
+// one query; each finds its slot's query by binary search over the scan.
+// Small batches take one query per group and several blocks per query.  The
 // query whose items end its bucket also writes the bucket's padding (invalid
-// items up to a whole chunk).
+// items up to a whole chunk), from the group's first block.
 constexpr int kExpandThreads = 256;
-__global__ __launch_bounds__(kExpandThreads) void k_expand(BatchArgs a, int qpb) {
+__global__ __launch_bounds__(kExpandThreads) void k_expand(BatchArgs a, int qpb, int bpg) {
   __shared__ uint32_t s_end[kExpandThreads];  // inclusive scan of the item counts
   __shared__ uint32_t s_dst[kExpandThreads];  // each query's first slot
   __shared__ uint32_t s_wave[kExpandThreads / 64];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int q0 = blockIdx.x * qpb;
+  const int g = (int)blockIdx.x % bpg;
+  const int q0 = ((int)blockIdx.x / bpg) * qpb;
   const int nloc = min(qpb, a.nq - q0);
   uint32_t n = 0, dst = 0;
   if (t < nloc) {
@@ -308,7 +311,7 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(BatchArgs a, int qpb)
       const uint32_t cnt = a.ctr->bucket_count[p.bucket];
       n = p.nitems;
       dst = start + p.item_off;
-      if (p.item_off + n == cnt) {
+      if (g == 0 && p.item_off + n == cnt) {
         const uint32_t pad = (cnt + (kChunk - 1)) & ~(uint32_t)(kChunk - 1);
         for (uint32_t x = cnt; x < pad; ++x) a.items[start + x] = make_uint2(kInvalidItem, 0u);
       }
@@ -327,7 +330,7 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(BatchArgs a, int qpb)
   s_dst[t] = dst;
   __syncthreads();
   const uint32_t total = s_end[nloc - 1];
-  for (uint32_t r = t; r < total; r += kExpandThreads) {
+  for (uint32_t r = (uint32_t)(g * kExpandThreads + t); r < total; r += (uint32_t)(bpg * kExpandThreads)) {
     int lo = 0, hi = nloc - 1;  // the first query whose items end after slot r
     while (lo < hi) {
       const int mid = (lo + hi) >> 1;
@@ -462,10 +465,13 @@ hipError_t launch_batch_front(const BatchArgs &a, hipStream_t s) {
   if (gb < 64) gb = std::min<unsigned>(64, blocks_for(a.nq, 1024));
   if (gb < 1) gb = 1;
   hipLaunchKernelGGL(k_bucketize, dim3(gb), dim3(kFatBlock), 0, s, a);
-  // about 2048 blocks of up to 256 queries each
+  // about 2048 blocks: groups of up to 256 queries, or for a batch of fewer
+  // than 2048 queries up to 64 blocks per query
   int qpb = (int)((a.nq + 2047) / 2048);
   qpb = std::max(1, std::min(qpb, kExpandThreads));
-  hipLaunchKernelGGL(k_expand, dim3(blocks_for(a.nq, qpb)), dim3(kExpandThreads), 0, s, a, qpb);
+  const int bpg = qpb == 1 ? std::max(1, std::min(64, 2048 / std::max(1, a.nq))) : 1;
+  hipLaunchKernelGGL(k_expand, dim3(blocks_for(a.nq, qpb) * bpg), dim3(kExpandThreads), 0, s, a, qpb,
+                     bpg);
   return hipGetLastError();
 }
 

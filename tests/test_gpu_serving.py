@@ -154,8 +154,9 @@ def test_serving_wide_requests_mix_equals_alone(ctx):
     ones: every completion equals that request alone against its busy mask
     (the oracle up to 2e6 embeddings, above that a wide call of the request
     alone, which the wide parity tests pin to the oracle); a request beyond
-    the wide kernels' embedding limit is refused on the host; the loop hands
-    back everything it granted."""
+    the wide kernels' embedding limit is refused on the host; Eq. 2 requests
+    ride along on the servers of weights 0..2; the loop hands back
+    everything it granted."""
     rng = np.random.default_rng(41)
 
     def rand_topo(n, wmax, p):
@@ -190,6 +191,8 @@ def test_serving_wide_requests_mix_equals_alone(ctx):
     r["k"][:nreq] = k
     r["mode"][:nreq] = rng.random(nreq) < 0.3
     r["a"], r["b"] = 1, 1
+    # Eq. 2 on the servers whose links weigh 0..2 (8- and 32-vertex)
+    r["metric"][:nreq] = np.isin(st[srv], (0, 3)) & (rng.random(nreq) < 0.4)
     # 12 of the 32 free accelerators: 32!/20! embeddings, past the wide limit
     r["server"][nreq], r["kind"][nreq], r["k"][nreq], r["hold"][nreq] = ids[8], 1, 12, 1.0
     ctx.serve_start(max_batch=64, inflight=2, time_unit_us=300.0)
@@ -208,7 +211,7 @@ def test_serving_wide_requests_mix_equals_alone(ctx):
     small = leaves <= 2e6
     sel = np.nonzero(small)[0]
     ref = oracle.batch(topos, tsel[sel], comp["busy_before"][sel], r["kind"][sel], r["k"][sel],
-                       r["mode"][sel], r["a"][sel], r["b"][sel], NTHREADS)
+                       r["mode"][sel], r["a"][sel], r["b"][sel], NTHREADS, metric=r["metric"][sel])
     got = comp[sel]
     for f in ("count", "status"):
         assert np.array_equal(got[f], ref[f]), f
@@ -224,7 +227,7 @@ def test_serving_wide_requests_mix_equals_alone(ctx):
     for i in big:
         sid = int(r["server"][i])
         ctx.set_busy([sid], [int(comp["busy_before"][i])])
-        q = B.pack_queries([sid], [r["kind"][i]], [r["k"][i]], r["mode"][i], 0, 1, 1)
+        q = B.pack_queries([sid], [r["kind"][i]], [r["k"][i]], r["mode"][i], 0, 1, 1, r["metric"][i])
         alone = ctx.query_batch_wide(q)[0]
         c = comp[i]
         for f in ("count", "status", "key", "agg", "pres", "vertex_mask"):
@@ -234,3 +237,4 @@ def test_serving_wide_requests_mix_equals_alone(ctx):
     wide = (tsel > 0) | (k > 8)
     assert (wide & (comp["status"] == B.RES_OK)).sum() > 100
     assert (k[comp["status"] == B.RES_OK] >= 9).any()
+    assert (wide & (r["metric"] == 1) & (comp["status"] == B.RES_OK)).sum() > 20
