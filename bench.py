@@ -306,7 +306,7 @@ def autotune_into(B, ctx, wl, qh, path):
 
 
 def timed_batch(B, wl, steps, warmup, metric="weighted", wide=False, profile=True, tuning="cache",
-                autotune=None, step_pass=True):
+                autotune=None, step_pass=True, graph_pass=False):
     """The batched form: `steps` timed steps (query batch with commits, then
     release of every handle) after `warmup` untimed ones, inputs resident in
     HBM.  Kernel time from HIP events on the launch stream over the timed
@@ -314,7 +314,9 @@ def timed_batch(B, wl, steps, warmup, metric="weighted", wide=False, profile=Tru
     default) the step time comes from a first pass of `steps` steps with
     nothing recorded between them (an event record between kernels adds
     ~15 us to a ~0.15 ms step), and per-step latency and kernel time from a
-    second pass of `steps` steps with the events."""
+    second pass of `steps` steps with the events.  With `graph_pass`, a third
+    pass replays the query batch as a captured HIP graph (MAPA_USE_GRAPH)
+    and reports its step time beside the stream-launched one."""
     import torch
     ops = op_counts(wl)
     emb = ops["embeddings"]
@@ -374,6 +376,20 @@ def timed_batch(B, wl, steps, warmup, metric="weighted", wide=False, profile=Tru
     lat = np.array([a.elapsed_time(b) for a, b in ev])
     st = ctx.stats()
     ctx.profile(False)
+    graph_ms = None
+    if graph_pass and not wide:
+        def gstep():
+            ctx.query_batch(dq, dr, stream=stream, graph=True)
+            ctx.release(handles, stride=48, count=wl.nq, stream=stream)
+
+        for _ in range(3):  # the first call captures the graph
+            gstep()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(steps):
+            gstep()
+        torch.cuda.synchronize()
+        graph_ms = (time.perf_counter() - t0) * 1e3 / steps
     # every step scored every embedding and handed every allocation back
     res = wide_res[0] if wide else dr.cpu().numpy().view(B.RESULT_DTYPE)
     assert int(res["count"].sum()) == emb, (int(res["count"].sum()), emb)
@@ -381,6 +397,7 @@ def timed_batch(B, wl, steps, warmup, metric="weighted", wide=False, profile=Tru
     assert st["self_check_failures"] == 0
     out = {"wall_s": wall_plain if step_pass else wall, "steps": steps, "embeddings": emb, "ops": ops,
            "queries": wl.nq, "lat_ms": lat, "stats": st, "qh": qh, "tuning": tuning_info,
+           "graph_ms_per_step": graph_ms,
            "timing": ("step time from a pass of the steps with nothing recorded between them; "
                       "per-step latency and kernel time from a second pass with HIP events "
                       f"({wall * 1e3 / steps:.4f} ms per step with the events)") if step_pass else
@@ -562,7 +579,10 @@ def batched_summary(tb):
             "queries_per_s": tb["queries"] * tb["steps"] / tb["wall_s"],
             "ms_per_step": tb["wall_s"] * 1e3 / tb["steps"], "steps": tb["steps"],
             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-            "kernel_ms": tb["kernel_ms"], "tuning": tb["tuning"], "timing": tb["timing"]}
+            "kernel_ms": tb["kernel_ms"], "tuning": tb["tuning"], "timing": tb["timing"],
+            "hip_graph_ms_per_step": tb["graph_ms_per_step"],
+            "launch": "stream launches; hip_graph_ms_per_step replays the same batch as a captured "
+                      "HIP graph (MAPA_USE_GRAPH), which the step time does not use"}
 
 
 def main():
@@ -640,7 +660,7 @@ def main():
         f"embeddings/step")
     ctx, tb = timed_batch(B, wl, args.steps, args.warmup, args.metric, wide=args.config == 6,
                           profile=not args.no_profile, tuning=args.tuning, autotune=args.autotune,
-                          step_pass=True)
+                          step_pass=True, graph_pass=args.config == 2)
     log(f"[bench] {args.steps} steps in {tb['wall_s']:.3f} s; kernel "
         f"{tb['kernel_ms'] if tb['kernel_ms'] else float('nan'):.3f} ms avg")
     lat = tb["lat_ms"]
@@ -669,6 +689,8 @@ def main():
         "tuning": tb["tuning"],
         "timing": tb["timing"],
     }
+    if tb["graph_ms_per_step"] is not None:
+        out["hip_graph_ms_per_step"] = tb["graph_ms_per_step"]
     if tb["kernel_ms"]:
         out["roofline"] = roofline(args.config, tb)
     plain = {}
@@ -680,7 +702,8 @@ def main():
         log("[bench] batched config")
         c2 = synth.config2()
         ctx2, tb2 = timed_batch(B, c2, args.batched, args.warmup, profile=not args.no_profile,
-                                tuning=args.tuning, autotune=args.autotune, step_pass=True)
+                                tuning=args.tuning, autotune=args.autotune, step_pass=True,
+                                graph_pass=True)
         out["batched_config_2"] = batched_summary(tb2)
         out["batched_config_2"]["workload"] = WORKLOAD_TEXT[2]
         if tb2["kernel_ms"]:
