@@ -221,7 +221,7 @@ def host_threads() -> int:
         n = len(os.sched_getaffinity(0))
     except AttributeError:
         n = os.cpu_count() or 1
-    # a GPU machine's share of host cores is 16, whatever the machine reports
+    # at most 16 threads: the host cores one GPU is given, whatever the machine reports
     return max(1, min(16, n))
 
 
