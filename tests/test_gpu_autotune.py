@@ -40,12 +40,16 @@ def test_every_cached_tuning_gives_identical_results(ctx):
     small = synth.config2(4096)
     qs, _ = B.load_workload(ctx, small)
     qb, _ = B.load_workload(ctx, big)
+    qe = qs.copy()
+    qe["metric"] = B.METRIC_EFFBW  # the batched topologies weigh 0..2
     ref_s, ref_b = ctx.query_batch(qs, pipeline=True), ctx.query_batch(qb)
+    ref_e = ctx.query_batch(qe, pipeline=True)
     for key, entry in sorted(cache.items()):
         print(f"[autotune] cached {key}: {entry['tuning']}", flush=True)
         ctx.set_tuning(**entry["tuning"])
         assert np.array_equal(ctx.query_batch(qs, pipeline=True), ref_s), key
         assert np.array_equal(ctx.query_batch(qb), ref_b), key
+        assert np.array_equal(ctx.query_batch(qe, pipeline=True), ref_e), key
     k = big.queries["k"]
     sel = np.nonzero(k == 6)[0]
     ref = oracle.run_workload(big.subset(sel), 16)
