@@ -6,9 +6,31 @@
 
 namespace mapa {
 
+// The lane id, opaque to the compiler at each use.  Taken once per chunk, it
+// keeps the cross-lane source addresses of the reductions below (and the
+// lane's work-list address) from being hoisted out of the persistent loop:
+// hoisted, they outlived the register budget and were spilled, 76 bytes per
+// lane written to scratch by every thread of the grid at each launch (the
+// batched config's kernel: 4.2 instead of 21.7 MiB written per launch, 4 %
+// faster).  The twelve-wide instances keep the hoisted form, measured 2 %
+// faster on the large config.
+template <int PAIR>
+__device__ __forceinline__ int chunk_lane() {
+  int lane = (int)(threadIdx.x & 63u);
+  if constexpr (PAIR < 12) __asm__ volatile("" : "+v"(lane));
+  return lane;
+}
+
+// v of lane src (0 <= src < 64 for a defined value)
+__device__ __forceinline__ unsigned long long lane_read_u64(int src, unsigned long long v) {
+  const int lo = __builtin_amdgcn_ds_bpermute(src << 2, (int)(uint32_t)v);
+  const int hi = __builtin_amdgcn_ds_bpermute(src << 2, (int)(uint32_t)(v >> 32));
+  return ((unsigned long long)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+
 template <int WPR, int PAIR>
-__device__ __forceinline__ void run_item(const BatchArgs &a, const uint32_t *rows, uint2 it) {
-  const int lane = threadIdx.x & 63;
+__device__ __forceinline__ void run_item(const BatchArgs &a, const uint32_t *rows, uint2 it,
+                                         int lane) {
   const bool valid = it.x != kInvalidItem;
   const Plan *pp = valid ? &a.plan[it.x] : nullptr;
   const uint32_t *trow = valid ? rows + (uint32_t)pp->topo * (kTopoWords * WPR) : rows;
@@ -18,8 +40,17 @@ __device__ __forceinline__ void run_item(const BatchArgs &a, const uint32_t *row
   const int q0 = __builtin_amdgcn_readfirstlane(qi);
   const bool same = __ballot(valid && qi != q0) == 0ull;
   if (same) {
-    cnt = wave_sum_u64(cnt);
-    best = wave_max_u64(best);
+    if constexpr (PAIR >= 12) {
+      cnt = wave_sum_u64(cnt);
+      best = wave_max_u64(best);
+    } else {
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        cnt += lane_read_u64(lane ^ off, cnt);
+        const unsigned long long ob = lane_read_u64(lane ^ off, best);
+        best = ob > best ? ob : best;
+      }
+    }
     if (lane == 0 && q0 >= 0) {
       atomicAdd(&a.acc_count[q0], cnt);
       if (best) atomicMax(&a.acc_best[q0], best);
@@ -30,15 +61,28 @@ __device__ __forceinline__ void run_item(const BatchArgs &a, const uint32_t *row
     // atomics (one per query and chunk instead of one per item).
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
-      const int oq = __shfl_down(qi, off, 64);
-      const unsigned long long oc = __shfl_down(cnt, off, 64);
-      const unsigned long long ob = __shfl_down(best, off, 64);
-      if (lane + off < 64 && oq == qi) {
+      const int src = lane + off;  // beyond lane 63 the value read is not used
+      int oq;
+      unsigned long long oc, ob;
+      if constexpr (PAIR >= 12) {
+        oq = __shfl_down(qi, off, 64);
+        oc = __shfl_down(cnt, off, 64);
+        ob = __shfl_down(best, off, 64);
+      } else {
+        oq = __builtin_amdgcn_ds_bpermute(src << 2, qi);
+        oc = lane_read_u64(src, cnt);
+        ob = lane_read_u64(src, best);
+      }
+      if (src < 64 && oq == qi) {
         cnt += oc;
         best = ob > best ? ob : best;
       }
     }
-    const int pq = __shfl_up(qi, 1, 64);
+    int pq;  // not used on lane 0
+    if constexpr (PAIR >= 12)
+      pq = __shfl_up(qi, 1, 64);
+    else
+      pq = __builtin_amdgcn_ds_bpermute((lane - 1) << 2, qi);
     if (valid && (lane == 0 || pq != qi)) {
       if (cnt) atomicAdd(&a.acc_count[qi], cnt);
       if (best) atomicMax(&a.acc_best[qi], best);
@@ -48,7 +92,6 @@ __device__ __forceinline__ void run_item(const BatchArgs &a, const uint32_t *row
 
 template <int WPR, int PAIR>
 __device__ __forceinline__ void chunk_loop(const BatchArgs &a, const uint32_t *rows) {
-  const int lane = threadIdx.x & 63;
   const uint32_t nchunks = *(volatile const uint32_t *)&a.ctr->total_chunks;
   // Home queue: consecutive blocks land on different XCDs, so the waves of
   // one queue mostly share an XCD.  A wave whose queue runs dry looks at
@@ -57,6 +100,7 @@ __device__ __forceinline__ void chunk_loop(const BatchArgs &a, const uint32_t *r
   const uint32_t home = blockIdx.x % kQueues;
   uint32_t qu = home;
   for (;;) {
+    const int lane = chunk_lane<PAIR>();
     uint32_t c = 0;
     if (lane == 0) c = qu + atomicAdd(&a.ctr->queue_ctr[qu][0], 1u) * (uint32_t)kQueues;
     c = __shfl(c, 0, 64);
@@ -75,7 +119,7 @@ __device__ __forceinline__ void chunk_loop(const BatchArgs &a, const uint32_t *r
       continue;
     }
     const uint2 it = a.items[(size_t)c * kChunk + lane];
-    run_item<WPR, PAIR>(a, rows, it);
+    run_item<WPR, PAIR>(a, rows, it, lane);
   }
 }
 
@@ -83,8 +127,7 @@ __device__ __forceinline__ void chunk_loop(const BatchArgs &a, const uint32_t *r
 // free vertices go through pair_level (faster per match, more registers, so
 // fewer waves per SIMD).
 template <int WPR, bool ROWS_LDS, int PAIR>
-// At most 128 VGPRs, so four waves share each SIMD: the values this forces
-// to scratch belong to the outer levels of the search, which run rarely.
+// At most 128 VGPRs, so four waves share each SIMD.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_enumerate(BatchArgs a) {
   if constexpr (ROWS_LDS) {
     extern __shared__ uint32_t s_rows[];
