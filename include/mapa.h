@@ -451,7 +451,7 @@ typedef struct {
   int64_t enum_launches;   /* enumeration-kernel launches timed                */
   double enum_ms;          /* summed enumeration-kernel time (HIP events)      */
   int64_t last_items;      /* prefix items of the last batch (0 if unknown)    */
-  int32_t last_split;      /* index of the split size chosen for the last batch */
+  int32_t last_split;      /* split size chosen by the last batch's first block */
   int64_t self_check_failures; /* results whose key disagreed with the AggBW and
                                   PreservedBW recomputed from the chosen mapping
                                   (always 0 unless something is broken)        */

@@ -2,12 +2,13 @@
 // wave64).  Integer-only: every match is enumerated and scored exactly.
 //
 // Batch pipeline (one launch each, all on the caller's stream):
-//   k_prepare    per query: validate, free set R, constant key term b*W(R),
-//                per-split prefix depths and item totals, commit claim.
-//   k_bucketize  choose one split for the batch; per query: prefix depth d,
-//                shape bucket, offset inside the bucket.  Its last block to
-//                finish lays the buckets out (largest items first) and
-//                resets the per-batch counters.
+//   k_front      few fat blocks, each over a share of the queries: per query
+//                validate, free set R, constant key term b*W(R), commit
+//                claim; the block's own prefix split from its share's item
+//                totals; per query prefix depth d, shape bucket, offset
+//                inside the bucket.  The last block to finish lays the
+//                buckets out (largest items first) and resets the per-batch
+//                counters.
 //   k_expand     fills every query's work-list slots with (query, item index)
 //                and pads each bucket to whole 64-item chunks; k_enumerate
 //                turns the index into the prefix tuple.
@@ -45,43 +46,20 @@ hipError_t upload_tables_front(const Tables &t) {
   return hipMemcpyToSymbol(HIP_SYMBOL(c_tab), &t, sizeof(Tables));
 }
 
-// ----------------------------------------------------------------- prepare
+// ------------------------------------------------------------------- front
 
-__global__ __launch_bounds__(256) void k_prepare(BatchArgs a) {
-  // queries that fit, by (F, k): one LDS atomic per query, then one global
-  // atomic per block and nonzero bin (the split totals need nothing else)
-  __shared__ uint32_t s_hist[kFkBins];
-  for (int e = threadIdx.x; e < kFkBins; e += blockDim.x) s_hist[e] = 0;
-  __syncthreads();
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < a.nq) {
-    const mapa_query q = a.q[i];
-    const Plan p = make_plan(q, a.nservers, a.server_topo, a.topo_n, a.topo_maxw, a.busy, a.rows,
-                             a.wpr, a.pat_nbtab, a.pat_k, a.pat_nbtab_ord, a.pat_order);
-    if (p.status == kPlanOk) atomicAdd(&s_hist[p.F * (kMaxK + 1) + p.k], 1u);
-    if (p.status != kPlanInvalid && p.commit)
-      atomicMin(&a.commit_slot[p.server], (unsigned long long)i);
-    a.plan[i] = p;
-    a.acc_count[i] = 0;
-    a.acc_best[i] = 0;
-  }
-  __syncthreads();
-  for (int e = threadIdx.x; e < kFkBins; e += blockDim.x)
-    if (s_hist[e]) atomicAdd(&a.ctr->fk_hist[blockIdx.x % kTotCopies][e], s_hist[e]);
-}
-
-// --------------------------------------------------------------- bucketize
-
-constexpr int kFatBlock = 1024;  // threads of k_bucketize and k_layout blocks
+constexpr int kFatBlock = 1024;  // threads of a k_front block
 
 // Lay the buckets out (largest items first, each rounded up to whole 64-item
-// chunks) and reset the per-batch counters.  Run by the last k_bucketize
-// block to finish, once every block's counts are in.
+// chunks) and reset the per-batch counters.  Run by the last k_front block
+// to finish, once every block's counts are in.
 __device__ void layout_buckets(const BatchArgs &a) {
   __shared__ uint32_t s_pad[kNumBuckets];
   __shared__ uint32_t s_cnt[kNumBuckets];
   __shared__ uint32_t s_start[kNumBuckets];
+  __shared__ unsigned long long s_items;  // items of the batch (before padding)
   const int t = threadIdx.x;
+  if (t == 0) s_items = 0;
   // loops over the buckets have a fixed stride (one 1024-thread block), so
   // they unroll and each thread's loads are in flight together.  The counts
   // are loaded in bucket order (into s_start, free until the scan) beside
@@ -103,6 +81,7 @@ __device__ void layout_buckets(const BatchArgs &a) {
     const int r = t + e * kFatBlock;
     if (r < kNumBuckets) {
       const uint32_t cnt = s_start[rank_b[e]];
+      if (cnt) atomicAdd(&s_items, (unsigned long long)cnt);
       s_cnt[r] = cnt;
       s_pad[r] = (cnt + (kChunk - 1)) & ~(uint32_t)(kChunk - 1);
     }
@@ -160,15 +139,23 @@ __device__ void layout_buckets(const BatchArgs &a) {
     a.ctr->bucket_items[b][0] = 0;
   }
   if (t < kQueues) a.ctr->queue_ctr[t][0] = 0;
-  for (int e = t; e < kTotCopies * kFkBins; e += blockDim.x) a.ctr->fk_hist[e / kFkBins][e % kFkBins] = 0;
+  if (t == 0) a.ctr->last_total_items = s_items;
 }
 
-// Few, fat blocks: each block histograms many queries in LDS and then adds
-// one total per bucket to the global counters, so every global counter sees
-// only a handful of atomics.  The last block to finish (by a counter taken
-// after its atomics are done) then lays the buckets out, which needs every
-// block's counts; no block waits for another.
-__global__ __launch_bounds__(1024) void k_bucketize(BatchArgs a) {
+// Few, fat blocks, each over a share of the queries.  A block plans its
+// queries (validation, free set R, b*W(R), the commit claim), counts those
+// that fit by (F, k), and from those counts picks its own prefix split: the
+// item totals of every candidate split follow from the (F, k) counts, and
+// the rule below is applied to the block's share of the work-list and of the
+// resident lanes.  A split changes how a query's work is cut, never its
+// result, so blocks need not agree, and each block's items fit its share of
+// the work-list, so the batch's fit.  Then per query the prefix depth, the
+// shape bucket and the offset inside it: an LDS histogram, then one global
+// atomic per bucket per block, so every global counter sees only a handful
+// of atomics.  The last block to finish (by a counter taken after its
+// atomics are done) lays the buckets out, which needs every block's counts;
+// no block waits for another.
+__global__ __launch_bounds__(1024) void k_front(BatchArgs a) {
   __shared__ int s_split;
   __shared__ uint32_t s_cnt[kNumBuckets];
   __shared__ uint32_t s_base[kNumBuckets];
@@ -179,16 +166,29 @@ __global__ __launch_bounds__(1024) void k_bucketize(BatchArgs a) {
   if (threadIdx.x < kFkBins) s_h[threadIdx.x] = 0;
   if (threadIdx.x <= kNumSplits) s_tot[threadIdx.x] = 0;
   __syncthreads();
-  // The batch totals from the (F, k) histogram: its copies summed, then for
-  // each (bin, split) pair h * (items per query of that split), and at
-  // j = kNumSplits h * F!/(F-k)!.  Fixed strides, so each thread's loads are
-  // in flight together.
+  const int per_block = (a.nq + gridDim.x - 1) / gridDim.x;
+  const int q0 = blockIdx.x * per_block;
+  const int q1 = min(a.nq, q0 + per_block);
+  constexpr int kMaxPerThread = 16;
 #pragma unroll
-  for (int e = threadIdx.x; e < kTotCopies * kFkBins; e += kFatBlock) {
-    const uint32_t v = a.ctr->fk_hist[e / kFkBins][e % kFkBins];
-    if (v) atomicAdd(&s_h[e % kFkBins], v);
+  for (int r = 0; r < kMaxPerThread; ++r) {
+    const int i = q0 + threadIdx.x + r * (int)blockDim.x;
+    if (i < q1) {
+      const mapa_query q = a.q[i];
+      const Plan p = make_plan(q, a.nservers, a.server_topo, a.topo_n, a.topo_maxw, a.busy, a.rows,
+                               a.wpr, a.pat_nbtab, a.pat_k, a.pat_nbtab_ord, a.pat_order);
+      if (p.status == kPlanOk) atomicAdd(&s_h[p.F * (kMaxK + 1) + p.k], 1u);
+      if (p.status != kPlanInvalid && p.commit)
+        atomicMin(&a.commit_slot[p.server], (unsigned long long)i);
+      a.plan[i] = p;
+      a.acc_count[i] = 0;
+      a.acc_best[i] = 0;
+    }
   }
   __syncthreads();
+  // The share's totals: for each (bin, split) pair h * (items per query of
+  // that split), and at j = kNumSplits h * F!/(F-k)!.  Fixed strides, so each
+  // thread's loads are in flight together.
 #pragma unroll
   for (int e = threadIdx.x; e < kFkBins * (kNumSplits + 1); e += kFatBlock) {
     const int bin = e / (kNumSplits + 1), j = e % (kNumSplits + 1);
@@ -201,38 +201,34 @@ __global__ __launch_bounds__(1024) void k_bucketize(BatchArgs a) {
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    // The split is a pure function of batch totals, so every block picks the
-    // same one.  Items get finer (more, smaller) as j falls.  Finer items
-    // balance the lanes better but each costs a fixed setup, so take the
-    // finest split that fits the work-list, gives every resident lane an
-    // item and keeps the mean item at mean_leaves embeddings or more.
-    // Failing that: the coarsest split that still gives every lane an item;
-    // for a batch too small for that, the finest split that fits.  Whole
-    // queries (one item each) always fit.
+    // Items get finer (more, smaller) as j falls.  Finer items balance the
+    // lanes better but each costs a fixed setup, so take the finest split
+    // that fits the share of the work-list, gives every resident lane of the
+    // share an item and keeps the mean item at mean_leaves embeddings or
+    // more.  Failing that: the coarsest split that still gives every such
+    // lane an item; for a share too small for that, the finest split that
+    // fits.  Whole queries (one item each) always fit: the batch's queries
+    // fit the work-list beside its padding.
+    const unsigned long long nb = (unsigned long long)max(q1 - q0, 0);
+    const unsigned long long cap = (a.cap_items - kPadReserve) * nb / (unsigned long long)a.nq;
+    const unsigned long long lanes = ((unsigned long long)a.lanes * nb + a.nq - 1) / (unsigned long long)a.nq;
     const unsigned long long leaves = s_tot[kNumSplits];
     int best = -1, busy = -1, finest = kSplitWhole;
     for (int c = kSplitWhole; c >= 0; --c) {
       const unsigned long long n = s_tot[c];
-      if (n + kPadReserve > a.cap_items) break;
+      if (n > cap) break;
       finest = c;
-      if (n >= a.lanes) {
+      if (n >= lanes) {
         if (busy < 0) busy = c;
         if (leaves >= n * (unsigned long long)a.mean_leaves) best = c;
       }
     }
     const int j = best >= 0 ? best : busy >= 0 ? busy : finest;
     s_split = j;
-    if (blockIdx.x == 0) {
-      a.ctr->chosen_split = (uint32_t)j;
-      a.ctr->last_total_items = s_tot[j];
-    }
+    if (blockIdx.x == 0) a.ctr->chosen_split = (uint32_t)j;
   }
   __syncthreads();
   const int j = s_split;
-  const int per_block = (a.nq + gridDim.x - 1) / gridDim.x;
-  const int q0 = blockIdx.x * per_block;
-  const int q1 = min(a.nq, q0 + per_block);
-  constexpr int kMaxPerThread = 16;
   uint32_t local[kMaxPerThread];
   int bk[kMaxPerThread];
 #pragma unroll
@@ -241,7 +237,7 @@ __global__ __launch_bounds__(1024) void k_bucketize(BatchArgs a) {
     bk[r] = -1;
     local[r] = 0;
     if (i < q1) {
-      const Plan &p = a.plan[i];
+      const Plan &p = a.plan[i];  // this thread's own write above
       if (p.status == kPlanOk) {
         const int d = a.split_d[((size_t)p.F * (kMaxK + 1) + p.k) * kNumSplits + j];
         const uint32_t nitems = (uint32_t)c_tab.perm[p.F][d];
@@ -458,13 +454,11 @@ int valu_probe_ops_per_iter() { return kProbeOpsPerIter; }
 
 
 hipError_t launch_batch_front(const BatchArgs &a, hipStream_t s) {
-  const unsigned g = blocks_for(a.nq, 256);
-  hipLaunchKernelGGL(k_prepare, dim3(g), dim3(256), 0, s, a);
   // 1024-thread blocks, up to 16 queries per thread, at most 64 blocks
   unsigned gb = blocks_for(a.nq, 1024 * 16);
   if (gb < 64) gb = std::min<unsigned>(64, blocks_for(a.nq, 1024));
   if (gb < 1) gb = 1;
-  hipLaunchKernelGGL(k_bucketize, dim3(gb), dim3(kFatBlock), 0, s, a);
+  hipLaunchKernelGGL(k_front, dim3(gb), dim3(kFatBlock), 0, s, a);
   // about 2048 blocks: groups of up to 256 queries, or for a batch of fewer
   // than 2048 queries up to 64 blocks per query
   int qpb = (int)((a.nq + 2047) / 2048);

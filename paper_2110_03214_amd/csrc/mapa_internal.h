@@ -73,7 +73,7 @@ constexpr uint8_t kPlanOk = 0, kPlanNofit = 1, kPlanInvalid = 3;
 constexpr uint32_t kIdentityOrder = 0x76543210u;
 
 // Per-batch counters (device).  Zeroed at allocation; the block of
-// k_bucketize that lays the buckets out re-zeroes what the batch consumed so
+// k_front that lays the buckets out re-zeroes what the batch consumed so
 // the next batch starts clean.
 // Counters hit by atomics from many blocks each own a 128-byte line, so their
 // atomics spread over L2 channels instead of queueing on one.
@@ -89,19 +89,14 @@ constexpr int kTopoWords = 32;
 // queue c % kQueues), each with its own claim counter, so the claims of the
 // persistent waves spread over many addresses instead of serializing on one.
 constexpr int kQueues = 32;
-constexpr int kTotCopies = 16;
+// bins of a (free vertices F, pattern size k) histogram, bin F * (kMaxK + 1) + k
 constexpr int kFkBins = (kMaxN + 1) * (kMaxK + 1);
 struct Counters {
-  // queries that fit, by (free vertices F, pattern size k) at F * (kMaxK + 1)
-  // + k, spread over kTotCopies copies: block b of k_prepare adds to copy
-  // b % kTotCopies, so no counter queues more than a few atomics.  Every
-  // split's item total and the embedding total follow from it.
-  uint32_t fk_hist[kTotCopies][kFkBins];
   uint32_t bucket_items[kNumBuckets][kLine];              // [b][0] used
   uint32_t queue_ctr[kQueues][kLine];                     // next chunk of each queue
   uint32_t bucket_start[kNumBuckets];
   uint32_t bucket_count[kNumBuckets];  // items of each bucket (before padding)
-  uint32_t bucketize_done;             // k_bucketize blocks finished (the last one lays out)
+  uint32_t bucketize_done;             // k_front blocks finished (the last one lays out)
   uint32_t total_chunks;
   uint32_t chosen_split;
   uint32_t self_check_failures;
