@@ -80,8 +80,17 @@ __device__ __forceinline__ int set_weight(const uint32_t *trow, int wpr, uint32_
   return s >> 1;
 }
 
+// The key's constant term of a plan, b*W(R) (0 for Eq. 2, whose running
+// score is the link mix of the edges placed so far and starts empty).
+__device__ __forceinline__ int32_t plan_kp0(const Plan &p, const uint32_t *rows, int wpr) {
+  return p.metric == MAPA_METRIC_EFFBW
+             ? 0
+             : (int32_t)p.b * set_weight(rows + (size_t)p.topo * kTopoWords * wpr, wpr, p.R);
+}
+
 // Plan of one query against the busy mask now in memory: validation, free
-// set R, the key's constant term b*W(R), the pattern's back-neighbour table.
+// set R, the pattern's back-neighbour table and, with with_kp0, the key's
+// constant term b*W(R) (else 0, to be set with plan_kp0 before the search).
 __device__ __forceinline__ Plan make_plan(const mapa_query &q, int32_t nservers,
                                           const int32_t *server_topo, const int32_t *topo_n,
                                           const uint8_t *topo_maxw, const uint32_t *busy,
@@ -89,7 +98,7 @@ __device__ __forceinline__ Plan make_plan(const mapa_query &q, int32_t nservers,
                                           const unsigned long long *pat_nbtab,
                                           const uint8_t *pat_k,
                                           const unsigned long long *pat_nbtab_ord,
-                                          const uint32_t *pat_order) {
+                                          const uint32_t *pat_order, bool with_kp0 = true) {
   Plan p = {};
   p.server = q.server;
   const bool registered = q.kind >= MAPA_PATTERN_BASE;
@@ -126,10 +135,7 @@ __device__ __forceinline__ Plan make_plan(const mapa_query &q, int32_t nservers,
   p.n = (uint8_t)n;
   p.R = R;
   p.F = (uint8_t)F;
-  // the search's running score starts from b * W(R); for Eq. 2 it is the
-  // link mix of the edges placed so far, which starts empty
-  p.kp0 = q.metric == MAPA_METRIC_EFFBW ? 0
-                                        : (int32_t)q.b * set_weight(rows + (size_t)t * kTopoWords * wpr, wpr, R);
+  if (with_kp0) p.kp0 = plan_kp0(p, rows, wpr);
   p.nbtab = registered ? pat_nbtab[q.kind - MAPA_PATTERN_BASE] : c_tab.nbtab[q.kind][q.k];
   if (registered) {
     // LINKED search of a registered pattern places its vertices in the

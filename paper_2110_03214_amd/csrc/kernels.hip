@@ -132,8 +132,10 @@ __device__ void layout_buckets(const BatchArgs &a) {
   }
   __syncthreads();
 #pragma unroll
-  for (int r = t; r < kNumBuckets; r += kFatBlock) {
-    const int b = c_tab.rank_bucket[r];
+  for (int e = 0; e < kPer; ++e) {
+    const int r = t + e * kFatBlock;
+    if (r >= kNumBuckets) break;
+    const int b = rank_b[e];  // loaded above for the same r
     a.ctr->bucket_start[b] = s_start[r];
     a.ctr->bucket_count[b] = s_cnt[r];
     a.ctr->bucket_items[b][0] = 0;
@@ -143,7 +145,8 @@ __device__ void layout_buckets(const BatchArgs &a) {
 }
 
 // Few, fat blocks, each over a share of the queries.  A block plans its
-// queries (validation, free set R, b*W(R), the commit claim), counts those
+// queries (validation, free set R, the commit claim; the key's constant term
+// b*W(R) is left to k_expand, whose loads it then overlaps), counts those
 // that fit by (F, k), and from those counts picks its own prefix split: the
 // item totals of every candidate split follow from the (F, k) counts, and
 // the rule below is applied to the block's share of the work-list and of the
@@ -160,24 +163,40 @@ __global__ __launch_bounds__(1024) void k_front(BatchArgs a) {
   __shared__ uint32_t s_cnt[kNumBuckets];
   __shared__ uint32_t s_base[kNumBuckets];
   __shared__ uint32_t s_h[kFkBins];
+  __shared__ unsigned long long s_perm[kFkBins];  // F!/(F-d)! at F * (kMaxK + 1) + d
+  __shared__ uint8_t s_sd[kSplitTable];           // the split table, see kSplitTable
   __shared__ unsigned long long s_tot[kNumSplits + 1];
+  const int t = threadIdx.x;
 #pragma unroll
-  for (int b = threadIdx.x; b < kNumBuckets; b += kFatBlock) s_cnt[b] = 0;
-  if (threadIdx.x < kFkBins) s_h[threadIdx.x] = 0;
-  if (threadIdx.x <= kNumSplits) s_tot[threadIdx.x] = 0;
-  __syncthreads();
+  for (int b = t; b < kNumBuckets; b += kFatBlock) s_cnt[b] = 0;
+  if (t < kFkBins) s_h[t] = 0;
+  if (t <= kNumSplits) s_tot[t] = 0;
+  // the tables are loaded before the planning and stored to LDS after it,
+  // so their loads overlap the planning's
+  constexpr int kSdPer = (kSplitTable + kFatBlock - 1) / kFatBlock;
+  uint8_t sd[kSdPer];
+#pragma unroll
+  for (int e = 0; e < kSdPer; ++e)
+    sd[e] = t + e * kFatBlock < kSplitTable ? a.split_d[t + e * kFatBlock] : 0;
+  const unsigned long long perm = t < kFkBins ? c_tab.perm[t / (kMaxK + 1)][t % (kMaxK + 1)] : 0ull;
   const int per_block = (a.nq + gridDim.x - 1) / gridDim.x;
   const int q0 = blockIdx.x * per_block;
   const int q1 = min(a.nq, q0 + per_block);
   constexpr int kMaxPerThread = 16;
+  // per query of this thread: F | k << 8 | bucket fields << 16, or ~0u when
+  // the query does not fit (the plan itself goes to memory once)
+  uint32_t shape[kMaxPerThread];
 #pragma unroll
   for (int r = 0; r < kMaxPerThread; ++r) {
-    const int i = q0 + threadIdx.x + r * (int)blockDim.x;
+    const int i = q0 + t + r * kFatBlock;
+    shape[r] = ~0u;
     if (i < q1) {
       const mapa_query q = a.q[i];
       const Plan p = make_plan(q, a.nservers, a.server_topo, a.topo_n, a.topo_maxw, a.busy, a.rows,
-                               a.wpr, a.pat_nbtab, a.pat_k, a.pat_nbtab_ord, a.pat_order);
-      if (p.status == kPlanOk) atomicAdd(&s_h[p.F * (kMaxK + 1) + p.k], 1u);
+                               a.wpr, a.pat_nbtab, a.pat_k, a.pat_nbtab_ord, a.pat_order, false);
+      if (p.status == kPlanOk)
+        shape[r] = (uint32_t)p.F | (uint32_t)p.k << 8 | (uint32_t)p.kind << 16 |
+                   (uint32_t)p.mode << 20 | (uint32_t)p.metric << 24;
       if (p.status != kPlanInvalid && p.commit)
         atomicMin(&a.commit_slot[p.server], (unsigned long long)i);
       a.plan[i] = p;
@@ -185,47 +204,63 @@ __global__ __launch_bounds__(1024) void k_front(BatchArgs a) {
       a.acc_best[i] = 0;
     }
   }
+#pragma unroll
+  for (int e = 0; e < kSdPer; ++e)
+    if (t + e * kFatBlock < kSplitTable) s_sd[t + e * kFatBlock] = sd[e];
+  if (t < kFkBins) s_perm[t] = perm;
+  __syncthreads();
+  // the share's queries that fit, by (F, k)
+#pragma unroll
+  for (int r = 0; r < kMaxPerThread; ++r)
+    if (shape[r] != ~0u) atomicAdd(&s_h[(shape[r] & 0xFF) * (kMaxK + 1) + ((shape[r] >> 8) & 0xFF)], 1u);
   __syncthreads();
   // The share's totals: for each (bin, split) pair h * (items per query of
-  // that split), and at j = kNumSplits h * F!/(F-k)!.  Fixed strides, so each
-  // thread's loads are in flight together.
+  // that split), and at j = kNumSplits h * F!/(F-k)!.
 #pragma unroll
-  for (int e = threadIdx.x; e < kFkBins * (kNumSplits + 1); e += kFatBlock) {
+  for (int e = t; e < kFkBins * (kNumSplits + 1); e += kFatBlock) {
     const int bin = e / (kNumSplits + 1), j = e % (kNumSplits + 1);
     const uint32_t h = s_h[bin];
     if (h) {
       const int F = bin / (kMaxK + 1), kk = bin % (kMaxK + 1);
-      const int d = j < kNumSplits ? (int)a.split_d[(size_t)bin * kNumSplits + j] : kk;
-      atomicAdd(&s_tot[j], (unsigned long long)h * c_tab.perm[F][d]);
+      const int d = j < kNumSplits ? (int)s_sd[bin * kNumSplits + j] : kk;
+      atomicAdd(&s_tot[j], (unsigned long long)h * s_perm[F * (kMaxK + 1) + d]);
     }
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (t < 64) {
     // Items get finer (more, smaller) as j falls.  Finer items balance the
     // lanes better but each costs a fixed setup, so take the finest split
     // that fits the share of the work-list, gives every resident lane of the
     // share an item and keeps the mean item at mean_leaves embeddings or
     // more.  Failing that: the coarsest split that still gives every such
     // lane an item; for a share too small for that, the finest split that
-    // fits.  Whole queries (one item each) always fit: the batch's queries
-    // fit the work-list beside its padding.
-    const unsigned long long nb = (unsigned long long)max(q1 - q0, 0);
-    const unsigned long long cap = (a.cap_items - kPadReserve) * nb / (unsigned long long)a.nq;
-    const unsigned long long lanes = ((unsigned long long)a.lanes * nb + a.nq - 1) / (unsigned long long)a.nq;
+    // fits.  Only the splits above the coarsest one that does not fit count
+    // as fitting.  Whole queries (one item each) always fit: the batch's
+    // queries fit the work-list beside its padding, and the share is at
+    // least whole queries' worth of it.  One lane per split, then ballots.
+    const uint32_t nb = (uint32_t)max(q1 - q0, 0);
+    const unsigned long long room = a.cap_items - kPadReserve;
+    const uint32_t room32 = room > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)room;
+    const unsigned long long cap = (unsigned long long)(room32 / (uint32_t)a.nq) * nb;
+    const unsigned long long lanes =
+        (unsigned long long)ceil((double)a.lanes * (double)nb / (double)a.nq);
     const unsigned long long leaves = s_tot[kNumSplits];
-    int best = -1, busy = -1, finest = kSplitWhole;
-    for (int c = kSplitWhole; c >= 0; --c) {
-      const unsigned long long n = s_tot[c];
-      if (n > cap) break;
-      finest = c;
-      if (n >= lanes) {
-        if (busy < 0) busy = c;
-        if (leaves >= n * (unsigned long long)a.mean_leaves) best = c;
-      }
+    const bool in = t <= kSplitWhole;
+    const unsigned long long n = in ? s_tot[t] : 0ull;
+    const unsigned long long nofit = __ballot(in && n > cap);
+    const unsigned long long fill = __ballot(in && n >= lanes);
+    const unsigned long long big = __ballot(in && leaves >= n * (unsigned long long)a.mean_leaves);
+    constexpr unsigned long long kAll = (1ull << (kSplitWhole + 1)) - 1ull;
+    const unsigned long long fits = nofit ? kAll & ~((2ull << (63 - __builtin_clzll(nofit))) - 1ull) : kAll;
+    const unsigned long long best = fits & fill & big, busy = fits & fill;
+    const int j = best   ? __builtin_ctzll(best)
+                  : busy ? 63 - __builtin_clzll(busy)
+                  : fits ? __builtin_ctzll(fits)
+                         : kSplitWhole;
+    if (t == 0) {
+      s_split = j;
+      if (blockIdx.x == 0) a.ctr->chosen_split = (uint32_t)j;
     }
-    const int j = best >= 0 ? best : busy >= 0 ? busy : finest;
-    s_split = j;
-    if (blockIdx.x == 0) a.ctr->chosen_split = (uint32_t)j;
   }
   __syncthreads();
   const int j = s_split;
@@ -233,31 +268,31 @@ __global__ __launch_bounds__(1024) void k_front(BatchArgs a) {
   int bk[kMaxPerThread];
 #pragma unroll
   for (int r = 0; r < kMaxPerThread; ++r) {
-    const int i = q0 + threadIdx.x + r * (int)blockDim.x;
+    const int i = q0 + t + r * kFatBlock;
     bk[r] = -1;
     local[r] = 0;
-    if (i < q1) {
-      const Plan &p = a.plan[i];  // this thread's own write above
-      if (p.status == kPlanOk) {
-        const int d = a.split_d[((size_t)p.F * (kMaxK + 1) + p.k) * kNumSplits + j];
-        const uint32_t nitems = (uint32_t)c_tab.perm[p.F][d];
-        const int b = bucket_id(p.metric, p.mode, p.kind, p.k - d, p.F - d);
-        a.plan[i].d = (uint8_t)d;
-        a.plan[i].bucket = (uint16_t)b;
-        a.plan[i].nitems = nitems;
-        bk[r] = b;
-        local[r] = atomicAdd(&s_cnt[b], nitems);
-      }
+    if (shape[r] != ~0u) {
+      const int F = shape[r] & 0xFF, kk = (shape[r] >> 8) & 0xFF;
+      const int kind = (shape[r] >> 16) & 0xF, mode = (shape[r] >> 20) & 0xF;
+      const int metric = shape[r] >> 24;
+      const int d = s_sd[(F * (kMaxK + 1) + kk) * kNumSplits + j];
+      const uint32_t nitems = (uint32_t)s_perm[F * (kMaxK + 1) + d];
+      const int b = bucket_id(metric, mode, kind, kk - d, F - d);
+      a.plan[i].d = (uint8_t)d;
+      a.plan[i].bucket = (uint16_t)b;
+      a.plan[i].nitems = nitems;
+      bk[r] = b;
+      local[r] = atomicAdd(&s_cnt[b], nitems);
     }
   }
   __syncthreads();
 #pragma unroll
-  for (int c = threadIdx.x; c < kNumBuckets; c += kFatBlock)
+  for (int c = t; c < kNumBuckets; c += kFatBlock)
     s_base[c] = s_cnt[c] ? atomicAdd(&a.ctr->bucket_items[c][0], s_cnt[c]) : 0u;
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < kMaxPerThread; ++r) {
-    const int i = q0 + threadIdx.x + r * (int)blockDim.x;
+    const int i = q0 + t + r * kFatBlock;
     if (bk[r] >= 0) a.plan[i].item_off = s_base[bk[r]] + local[r];
   }
   // Every count this block added came back from its atomic (s_base) before
@@ -267,12 +302,11 @@ __global__ __launch_bounds__(1024) void k_front(BatchArgs a) {
   // separate launch.
   __shared__ bool s_last;
   __syncthreads();
-  if (threadIdx.x == 0)
-    s_last = atomicAdd(&a.ctr->bucketize_done, 1u) == gridDim.x - 1u;
+  if (t == 0) s_last = atomicAdd(&a.ctr->bucketize_done, 1u) == gridDim.x - 1u;
   __syncthreads();
   if (s_last) {
     layout_buckets(a);
-    if (threadIdx.x == 0) a.ctr->bucketize_done = 0;
+    if (t == 0) a.ctr->bucketize_done = 0;
   }
 }
 
@@ -280,6 +314,8 @@ __global__ __launch_bounds__(1024) void k_front(BatchArgs a) {
 
 // Prefix item x of a query (0 <= x < F!/(F-d)!) is the x-th injective
 // d-tuple of free vertices in lexicographic order (k_enumerate unranks it).
+//
+// Each query's plan also gets its key's constant term b*W(R) here.
 //
 // Work-list fill: slot bucket_start + item_off + x of a query holds
 // (query, x).  A group of bpg blocks owns qpb <= 256 consecutive queries: a
@@ -305,6 +341,9 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(BatchArgs a, int qpb,
     if (p.status == kPlanOk) {
       const uint32_t start = a.ctr->bucket_start[p.bucket];
       const uint32_t cnt = a.ctr->bucket_count[p.bucket];
+      // the key's constant term (k_front leaves it out): its row loads
+      // overlap the bucket loads above
+      if (g == 0) a.plan[q0 + t].kp0 = plan_kp0(p, a.rows, a.wpr);
       n = p.nitems;
       dst = start + p.item_off;
       if (g == 0 && p.item_off + n == cnt) {

@@ -43,7 +43,7 @@ constexpr int kMaxEdges = kMaxK * (kMaxK - 1) / 2;  // 28
 __host__ __device__ constexpr int eff_off(int E) { return E * (E + 1) * (2 * E + 1) / 6; }
 constexpr int kEffEntries = eff_off(kMaxEdges + 1);  // 8555
 
-// Per-query plan, written by the prepare/bucketize kernels.
+// Per-query plan, written by k_front (the key's constant term by k_expand).
 struct Plan {
   uint32_t R;          // free vertex mask at batch start
   int32_t kp0;         // b * W(R): the key's constant term
