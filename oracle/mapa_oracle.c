@@ -53,6 +53,12 @@
  * counts, hand-derived counts and argmaxes, the paper's worked AggBW example,
  * automorphism counts, textbook special cases and exhaustive agreement with an
  * independent Python brute force.
+ *
+ * or_effbw (Eq. 2): parity unpinned for mixes with PCIe links (z > 0).  The
+ * EffBW values the paper prints all have z = 0, so they fix the x and y
+ * terms and the sum of the constant terms, while theta_3, theta_8, theta_9
+ * and theta_13 (each multiplied by z) rest only on the table as transcribed
+ * here and, independently, in the Python brute force.
  */
 #include <math.h>
 #include <pthread.h>
