@@ -451,3 +451,39 @@ def test_graph_replay_matches_eager(ctx, torch):
         release(d_eager)
         torch.cuda.synchronize()
         assert np.array_equal(ctx.get_busy(ids), wl.busy)
+
+
+def test_uneven_shares_split_independently(ctx):
+    """The front end's blocks each pick the prefix split for their own share
+    of the batch.  A batch whose first half is heavy (12 free of 16, k = 6)
+    and second half light (8-vertex servers, k <= 4) gives the blocks very
+    different shares; run forward and reversed, so every query lands in a
+    block of the other kind, the results must be identical, and they must
+    match the oracle on every light query and a sample of the heavy ones."""
+    rng = np.random.default_rng(2110)
+    topos = [random_topology(rng, 16, 3, 0.7), random_topology(rng, 8, 3, 0.8)]
+    st, busy, cols = [], [], {key: [] for key in ("server", "kind", "k", "mode", "a", "b")}
+    nheavy = nlight = 2048
+    for i in range(nheavy + nlight):
+        heavy = i < nheavy
+        n = 16 if heavy else 8
+        F = 12 if heavy else int(rng.integers(2, 7))
+        free = rng.choice(n, size=F, replace=False)
+        st.append(0 if heavy else 1)
+        busy.append(int(((1 << n) - 1) & ~int(np.bitwise_or.reduce(1 << free))))
+        k = 6 if heavy else int(rng.integers(2, min(F, 4) + 1))
+        a, b = [(1, 1), (1, 0), (0, 1)][int(rng.integers(0, 3))]
+        for key, v in zip(cols, (i, int(rng.integers(0, 2)), k, int(rng.integers(0, 2)), a, b)):
+            cols[key].append(v)
+    q = synth.make_queries(cols["server"], cols["kind"], cols["k"], cols["mode"], 0, cols["a"], cols["b"])
+    wl = synth.Workload("uneven", topos, np.array(st, np.int32), np.array(busy, np.uint32), q)
+    qd, _ = B.load_workload(ctx, wl)
+    fwd = ctx.query_batch(qd)
+    rev = ctx.query_batch(qd[::-1].copy())[::-1]
+    assert np.array_equal(fwd, rev)
+    pick = np.concatenate([rng.choice(nheavy, size=48, replace=False), np.arange(nheavy, nheavy + nlight)])
+    sub = synth.Workload("uneven-sample", topos, wl.server_topo, wl.busy,
+                         {key: col[pick] for key, col in q.items()})
+    ref = oracle.run_workload(sub, NTHREADS)
+    assert_same(fwd[pick], ref, q["k"][pick], "uneven")
+    assert ctx.stats()["self_check_failures"] == 0
