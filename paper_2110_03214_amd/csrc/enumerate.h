@@ -99,27 +99,66 @@ __device__ __forceinline__ void chunk_loop(const BatchArgs &a, const uint32_t *r
   // counting from its home, that still holds chunks.
   const uint32_t home = blockIdx.x % kQueues;
   uint32_t qu = home;
-  for (;;) {
-    const int lane = chunk_lane<PAIR>();
-    uint32_t c = 0;
-    if (lane == 0) c = qu + atomicAdd(&a.ctr->queue_ctr[qu][0], 1u) * (uint32_t)kQueues;
-    c = __shfl(c, 0, 64);
-    if (c >= nchunks) {
-      bool left = false;
-      if (lane < kQueues) {
-        const uint32_t pos = __hip_atomic_load(&a.ctr->queue_ctr[lane][0], __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-        left = (unsigned long long)lane + (unsigned long long)pos * kQueues < nchunks;
+  if constexpr (PAIR >= 12) {
+    // the twelve-wide instances claim every chunk (their first chunks by
+    // wave id, below, measured 5 % slower on the large config: a different
+    // register allocation of the whole loop)
+    for (;;) {
+      const int lane = chunk_lane<PAIR>();
+      uint32_t c = 0;
+      if (lane == 0) c = qu + atomicAdd(&a.ctr->queue_ctr[qu][0], 1u) * (uint32_t)kQueues;
+      c = __shfl(c, 0, 64);
+      if (c >= nchunks) {
+        bool left = false;
+        if (lane < kQueues) {
+          const uint32_t pos = __hip_atomic_load(&a.ctr->queue_ctr[lane][0], __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+          left = (unsigned long long)lane + (unsigned long long)pos * kQueues < nchunks;
+        }
+        const unsigned long long m = __ballot(left);
+        if (!m) break;
+        // first queue with chunks left at or after home, cyclically
+        const unsigned long long hi = m & (~0ull << home);
+        qu = (uint32_t)__builtin_ctzll(hi ? hi : m);
+        continue;
       }
-      const unsigned long long m = __ballot(left);
-      if (!m) break;
-      // first queue with chunks left at or after home, cyclically
-      const unsigned long long hi = m & (~0ull << home);
-      qu = (uint32_t)__builtin_ctzll(hi ? hi : m);
-      continue;
+      const uint2 it = a.items[(size_t)c * kChunk + lane];
+      run_item<WPR, PAIR>(a, rows, it, lane);
     }
-    const uint2 it = a.items[(size_t)c * kChunk + lane];
-    run_item<WPR, PAIR>(a, rows, it, lane);
+  } else {
+    // First chunks by wave id: with S the grid's waves rounded down to whole
+    // rounds of the queues, wave w < S starts on chunk w without a claim (the
+    // front end starts every queue's counter past those S chunks), so no wave
+    // waits on an atomic before its first loads.
+    const uint32_t waves = gridDim.x * (blockDim.x / 64u);
+    const uint32_t w = blockIdx.x * (blockDim.x / 64u) + threadIdx.x / 64u;
+    constexpr uint32_t kClaim = ~0u;
+    uint32_t c = w < waves / kQueues * kQueues ? w : kClaim;
+    for (;;) {
+      const int lane = chunk_lane<PAIR>();
+      if (c == kClaim) {
+        if (lane == 0) c = qu + atomicAdd(&a.ctr->queue_ctr[qu][0], 1u) * (uint32_t)kQueues;
+        c = __shfl(c, 0, 64);
+      }
+      if (c >= nchunks) {
+        bool left = false;
+        if (lane < kQueues) {
+          const uint32_t pos = __hip_atomic_load(&a.ctr->queue_ctr[lane][0], __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+          left = (unsigned long long)lane + (unsigned long long)pos * kQueues < nchunks;
+        }
+        const unsigned long long m = __ballot(left);
+        if (!m) break;
+        // first queue with chunks left at or after home, cyclically
+        const unsigned long long hi = m & (~0ull << home);
+        qu = (uint32_t)__builtin_ctzll(hi ? hi : m);
+        c = kClaim;
+        continue;
+      }
+      const uint2 it = a.items[(size_t)c * kChunk + lane];
+      run_item<WPR, PAIR>(a, rows, it, lane);
+      c = kClaim;
+    }
   }
 }
 

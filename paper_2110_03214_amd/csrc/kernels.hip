@@ -140,7 +140,13 @@ __device__ void layout_buckets(const BatchArgs &a) {
     a.ctr->bucket_count[b] = s_cnt[r];
     a.ctr->bucket_items[b][0] = 0;
   }
-  if (t < kQueues) a.ctr->queue_ctr[t][0] = 0;
+  // the enumeration's waves take their first chunks by wave id, except in
+  // the twelve-wide instances (see chunk_loop): every queue's claims start
+  // past them
+  if (t < kQueues)
+    a.ctr->queue_ctr[t][0] = enum_twelve_wide(a)
+                                 ? 0u
+                                 : (uint32_t)(a.enum_blocks * (a.enum_threads / 64)) / (uint32_t)kQueues;
   if (t == 0) a.ctr->last_total_items = s_items;
 }
 
@@ -509,7 +515,7 @@ hipError_t launch_batch_front(const BatchArgs &a, hipStream_t s) {
 }
 
 hipError_t launch_enumerate(const BatchArgs &a, hipStream_t s) {
-  if (a.wpr == 1 && a.pair >= 12)
+  if (enum_twelve_wide(a))
     return a.rows_in_lds ? launch_enum_pair12_lds(a, s) : launch_enum_pair12_glb(a, s);
   if (a.wpr == 1 && a.pair >= 6) return launch_enum_pair6(a, s);
   return launch_enum_plain(a, s);

@@ -158,6 +158,13 @@ struct BatchArgs {
   int32_t pair;  // k_enumerate variant: widest pair_level (0: none)
 };
 
+// Whether a batch runs the twelve-wide k_enumerate instance (one-word rows,
+// pair level up to 12 free vertices); the others take their first chunks by
+// wave id, and the front end sets the chunk queues up for that.
+__host__ __device__ inline bool enum_twelve_wide(const BatchArgs &a) {
+  return a.wpr == 1 && a.pair >= 12;
+}
+
 // Fused path for small batches with one query per server (k_fused).
 constexpr int kFusedThreads = 256;
 constexpr int kFusedMaxBlocksPerQuery = 16;
